@@ -1,0 +1,260 @@
+"""Pins of the oracle's boundary pieces.
+
+* IBB formulas (Eq. 10, Eq. 11 and the linear variant): at q = 1/2 every
+  scheme reduces bit-exactly to halfway bounce-back; each scheme is Lagrange
+  interpolation, so it reproduces polynomials of its degree exactly;
+* Peskin's 4-point delta (Eq. 6): partition of unity, zero first moment (the
+  property App. B relies on), sum of squares 3/8, continuity, phi(0) = 1/2;
+* interpolation (Eq. 5) and spreading (Eq. 8): exact for constant and linear
+  fields, conservation of total force and torque, adjointness;
+* node classification, the boundary-link set and q (Fig. 1, Sec. 2.2) checked
+  by exact rational arithmetic on tiny grids, q against a 50-digit evaluation.
+"""
+import math
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from paper_1906_05445_amd import workloads as W
+
+
+# ----------------------------------------------------------------------------
+# IBB formulas
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["BB", "LINEAR", "QUADRATIC"])
+def test_half_way_link_reduces_to_bounce_back_bit_exact(method):
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        v = rng.uniform(0.01, 0.4, size=5)
+        B = rng.uniform(-1e-3, 1e-3)
+        got = oracle.ibb_value(method, 0.5, 1, 1, v[0], v[1], v[2], v[3], v[3], v[4], B)
+        assert got == v[0] + B
+
+
+@pytest.mark.parametrize("k", range(1, 17))
+def test_quadratic_bouzidi_is_quadratic_lagrange(k):
+    q = k / 16.0
+    rng = np.random.default_rng(100 + k)
+    for _ in range(20):
+        a, b, c = rng.standard_normal(3)
+        p = lambda s: a + b * s + c * s * s
+        if q < 0.5:
+            # virtual start point at s = 1 - 2q between x_f (s=0), x_ff (1), x_fff (2)
+            got = oracle.ibb_value("QUADRATIC", q, 1, 1, p(0), p(1), p(2), 0.0, 0.0, 0.0, 0.0)
+            want = p(1.0 - 2.0 * q)
+        else:
+            # bounced value at s = 1 - 2q, streamed values at s = 1, 2; wanted at s = 0
+            got = oracle.ibb_value("QUADRATIC", q, 1, 1, p(1.0 - 2.0 * q), 0.0, 0.0, 0.0, p(1), p(2), 0.0)
+            want = p(0)
+        assert abs(got - want) < 1e-13 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("k", range(1, 17))
+def test_linear_bouzidi_is_linear_lagrange(k):
+    q = k / 16.0
+    rng = np.random.default_rng(200 + k)
+    for _ in range(20):
+        a, b = rng.standard_normal(2)
+        p = lambda s: a + b * s
+        if q < 0.5:
+            got = oracle.ibb_value("LINEAR", q, 1, 1, p(0), p(1), 0.0, 0.0, 0.0, 0.0, 0.0)
+            want = p(1.0 - 2.0 * q)
+        else:
+            got = oracle.ibb_value("LINEAR", q, 1, 1, p(1.0 - 2.0 * q), 0.0, 0.0, p(1), 0.0, 0.0, 0.0)
+            want = p(0)
+        assert abs(got - want) < 1e-13 * max(1.0, abs(want))
+
+
+def test_narrow_gap_fallbacks():
+    q = 0.3
+    vals = (0.11, 0.13, 0.17, 0.19, 0.23, 0.29)
+    bb = vals[0] + 1e-4
+    lin = oracle.ibb_value("LINEAR", q, 1, 0, *vals[:3], vals[3], vals[4], vals[5], 1e-4)
+    assert lin == oracle.ibb_value("QUADRATIC", q, 1, 0, *vals[:3], vals[3], vals[4], vals[5], 1e-4)
+    assert oracle.ibb_value("LINEAR", q, 0, 0, *vals[:3], vals[3], vals[4], vals[5], 1e-4) == bb
+    assert oracle.ibb_value("QUADRATIC", q, 0, 1, *vals[:3], vals[3], vals[4], vals[5], 1e-4) == bb
+    # q >= 1/2: linear needs only x_f
+    q = 0.8
+    a = oracle.ibb_value("LINEAR", q, 0, 0, *vals[:3], vals[3], vals[4], vals[5], 1e-4)
+    assert abs(a - ((vals[0] + 1e-4) / (2 * q) + (2 * q - 1) / (2 * q) * vals[3])) < 1e-16
+
+
+# ----------------------------------------------------------------------------
+# Peskin delta, Eq. 6
+# ----------------------------------------------------------------------------
+def test_delta_function_moments():
+    rng = np.random.default_rng(32)
+    rs = rng.uniform(0.0, 1.0, size=20000)
+    for r in rs:
+        js = np.arange(-3, 5)
+        ph = np.array([oracle.phi(r - j) for j in js])
+        assert abs(ph.sum() - 1.0) < 1e-15
+        assert abs(np.sum((r - js) * ph)) < 1e-15
+        assert abs(np.sum(ph * ph) - 3.0 / 8.0) < 1e-15
+    assert oracle.phi(0.0) == 0.5
+    for r0 in (1.0, 2.0):
+        assert abs(oracle.phi(r0 - 1e-12) - oracle.phi(r0 + 1e-12)) < 1e-11
+    assert oracle.phi(2.0) == 0.0 and oracle.phi(-2.5) == 0.0
+
+
+# ----------------------------------------------------------------------------
+# Interpolation and spreading, Eq. 5 and Eq. 8
+# ----------------------------------------------------------------------------
+def _ibm_oracle(shape=(24, 22, 20), R=5.3, centre=(11.3, 10.7, 9.2)):
+    o = Oracle("D3Q19", "MRT", shape, 0.8)
+    s = W.solid("sphere", centre, R)
+    o.set_solids([s], "IBM")
+    X, dV = W.icosphere(centre, R)
+    o.set_lagrangian(0, X, dV)
+    return o, X, dV
+
+
+def test_interpolation_exact_for_linear_fields():
+    o, X, dV = _ibm_oracle()
+    nx, ny, nz = o.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a = np.array([0.3, -0.2, 0.1])
+    B = np.array([[1e-3, 2e-3, -1e-3], [0.5e-3, -1e-3, 3e-3], [2e-3, 1e-3, 1e-3]])
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()])
+    u = a[:, None] + B @ pos
+    Ut = o.interpolate(u)
+    want = a[None, :] + X @ B.T
+    assert np.max(np.abs(Ut - want)) < 1e-14
+
+
+def test_spreading_conserves_force_torque_and_is_adjoint():
+    o, X, dV = _ibm_oracle()
+    rng = np.random.default_rng(33)
+    F = rng.standard_normal((X.shape[0], 3))
+    f = o.spread(F)
+    assert np.max(np.abs(f.sum(axis=1) - F.sum(axis=0) * dV)) < 1e-12
+    nx, ny, nz = o.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    Y = np.array([11.3, 10.7, 9.2])
+    r = np.stack([x.ravel(), y.ravel(), z.ravel()]) - Y[:, None]
+    T_grid = np.cross(r.T, f.T).sum(axis=0)
+    T_lag = np.cross(X - Y, F).sum(axis=0) * dV
+    assert np.max(np.abs(T_grid - T_lag)) < 1e-11
+    u = rng.standard_normal((3, o.N))
+    Ut = o.interpolate(u)
+    assert abs(np.sum(u * f) - np.sum(Ut * F) * dV) < 1e-10 * np.sum(np.abs(Ut * F) * dV)
+
+
+# ----------------------------------------------------------------------------
+# Node classification, boundary links and q by exact arithmetic
+# ----------------------------------------------------------------------------
+def _brute_links(lat, shape, solids):
+    nx, ny, nz = shape
+    D = 2 if lat == "D2Q9" else 3
+    o = Oracle(lat, "MRT", shape, 0.8)
+    e, w, _ = o.lattice_tables()
+    dims = (nx, ny, nz)
+
+    def mi(d, L):
+        if d > Fraction(L, 2):
+            return d - L
+        if d < -Fraction(L, 2):
+            return d + L
+        return d
+
+    def inside(k, p):
+        s = solids[k]
+        c = [Fraction(v) for v in s["centre"]]
+        ax = int(np.argmax(np.abs(s["axis"])))
+        if s["kind"] == "plane":
+            sg = 1 if s["axis"][ax] > 0 else -1
+            res = sg * (p[ax] - c[ax]) <= 0
+        else:
+            d = [mi(p[a] - c[a], dims[a]) for a in range(D)] + [Fraction(0)] * (3 - D)
+            if s["kind"] == "cylinder":
+                d[ax] = Fraction(0)
+            res = sum(v * v for v in d) <= Fraction(s["radius"]) ** 2
+        return (not res) if s["inverted"] else res
+
+    owner = {}
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for k in range(len(solids)):
+                    if inside(k, (x, y, z)):
+                        owner[(x, y, z)] = k
+                        break
+    links = []
+    getcontext().prec = 50
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if (x, y, z) in owner:
+                    continue
+                for i in range(1, len(w)):
+                    b = ((x - e[i][0]) % nx, (y - e[i][1]) % ny, (z - e[i][2]) % nz)
+                    if b not in owner:
+                        continue
+                    k = owner[b]
+                    s = solids[k]
+                    ev = [Fraction(-int(e[i][a])) for a in range(3)]
+                    ax = int(np.argmax(np.abs(s["axis"])))
+                    c = [Fraction(v) for v in s["centre"]]
+                    if s["kind"] == "plane":
+                        sg = 1 if s["axis"][ax] > 0 else -1
+                        tf = sg * ((x, y, z)[ax] - c[ax]) / (-sg * ev[ax])
+                        t = Decimal(tf.numerator) / Decimal(tf.denominator)
+                    else:
+                        d = [mi((x, y, z)[a] - c[a], dims[a]) for a in range(D)] + [Fraction(0)] * (3 - D)
+                        if D == 2:
+                            ev[2] = Fraction(0)
+                        if s["kind"] == "cylinder":
+                            d[ax] = Fraction(0)
+                            ev[ax] = Fraction(0)
+                        A = sum(v * v for v in ev)
+                        Bq = sum(d[a] * ev[a] for a in range(3))
+                        C = sum(v * v for v in d) - Fraction(s["radius"]) ** 2
+                        disc = Bq * Bq - A * C
+                        dec = lambda f: Decimal(f.numerator) / Decimal(f.denominator)
+                        sq = dec(disc).sqrt()
+                        t = (-dec(Bq) - sq) / dec(A) if not s["inverted"] else (-dec(Bq) + sq) / dec(A)
+                    links.append(((x + nx * (y + ny * z)), i, k, t))
+    return o, owner, links
+
+
+CASES = [
+    ("D3Q19", (12, 11, 10), [W.solid("sphere", (5.375, 4.8125, 5.25), 3.1875)]),
+    ("D3Q19", (12, 11, 10), [W.solid("sphere", (0.5, 10.25, 9.75), 3.0)]),  # wraps around the box
+    ("D3Q19", (12, 12, 3), [W.solid("cylinder", (5.75, 6.125, 0.0), 4.5, inverted=True)]),
+    ("D3Q19", (12, 12, 6), [W.solid("cylinder", (5.75, 2.0, 2.625), 2.25, axis=(0, 1, 0)),
+                            W.solid("sphere", (5.5, 8.5, 3.0), 2.0)]),
+    ("D2Q9", (16, 15, 1), [W.solid("cylinder", (7.375, 6.625, 0.0), 4.125)]),
+    ("D2Q9", (6, 13, 1), [W.solid("plane", (0, 2.375, 0), axis=(0, 1, 0)),
+                          W.solid("plane", (0, 10.8125, 0), axis=(0, -1, 0))]),
+]
+
+
+@pytest.mark.parametrize("lat,shape,solids", CASES)
+def test_links_and_q_exact(lat, shape, solids):
+    o, owner, ref = _brute_links(lat, shape, solids)
+    o.set_solids(solids, "QUADRATIC")
+    ex, ins, own = o.node_flags()
+    nx, ny, nz = shape
+    for n in range(o.N):
+        x, y, z = n % nx, (n // nx) % ny, n // (nx * ny)
+        assert ex[n] == int((x, y, z) in owner)
+        assert own[n] == owner.get((x, y, z), -1)
+    L = o.links()
+    assert len(L["cell"]) == len(ref)
+    for l, (cell, i, k, t) in enumerate(ref):
+        assert (L["cell"][l], L["dir"][l], L["sid"][l]) == (cell, i, k)
+        qt = float(min(max(t, Decimal(2) ** -52), Decimal(1)))
+        assert abs(L["q"][l] - qt) <= 2 * math.ulp(qt), (l, L["q"][l], qt)
+
+
+def test_link_count_matches_surface_estimate():
+    R = 9.3
+    o = Oracle("D3Q19", "MRT", (26, 26, 26), 0.8)
+    o.set_solids([W.solid("sphere", (13.21, 12.87, 13.02), R)], "QUADRATIC")
+    n = len(o.links()["q"])
+    # expected links per unit area: sum over directions of |e_i . n| averaged over n = 72.2 R^2 / (4 pi R^2)
+    assert abs(n / (72.2 * R * R) - 1.0) < 0.05

@@ -1,0 +1,241 @@
+"""Pins of the oracle against closed-form flows and conservation laws.
+
+* conservation: mass and momentum of a periodic box; with boundary links the
+  fluid momentum changes by exactly (body force - momentum-exchange force,
+  Eq. 17 with u_w = 0) every step, for any bounce-back scheme; with the IBM by
+  (body force + spread boundary force);
+* Taylor-Green decay, second order;
+* plane Poiseuille: exact for the default MRT rates with halfway bounce-back
+  (and for BGK at tau = 1/2 + sqrt(3/16)); first order for halfway
+  bounce-back and second order for linear/quadratic Bouzidi at off-grid walls
+  (Sec. 3.1: IBB is second order);
+* circular Couette flow, steady profile Eq. 31 (App. A) and the torque on the
+  inner cylinder derived from it;
+* pipe flow, Eq. 28: steady profile and the transient series; IBB second
+  order, IBM first order (Sec. 3.3).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import Oracle
+from paper_1906_05445_amd import workloads as W
+
+
+def _momentum(o, e, excl):
+    """Fluid momentum and mass, summed exactly (math.fsum) over deviations f - w."""
+    _, w, _ = o.lattice_tables()
+    h = (o.get_f() - w[:, None])[:, excl == 0]
+    P = np.array([math.fsum((h * e[:, a][:, None]).ravel()) for a in range(3)])
+    return P, math.fsum(h.ravel())  # mass relative to the rest state
+
+
+@pytest.mark.parametrize("lat,coll", [("D2Q9", "BGK"), ("D3Q19", "MRT")])
+def test_periodic_conservation(lat, coll):
+    shape = (9, 8, 1) if lat == "D2Q9" else (7, 6, 5)
+    g = np.array([2e-5, -1e-5, 0.0 if lat == "D2Q9" else 5e-6])
+    o = Oracle(lat, coll, shape, 0.7, g=g)
+    e, w, _ = o.lattice_tables()
+    rng = np.random.default_rng(21)
+    o.set_f(w[:, None] * (1.0 + 0.02 * rng.standard_normal((len(w), o.N))))
+    excl = np.zeros(o.N, dtype=np.uint8)
+    P0, m0 = _momentum(o, e, excl)
+    for _ in range(200):
+        o.step(1)
+        P1, m1 = _momentum(o, e, excl)
+        assert np.max(np.abs(P1 - P0 - o.N * g)) < 1e-13
+        P0 = P1
+    assert abs(m1 - m0) / o.N < 1e-13  # relative to the total mass (rho = 1 per cell)
+
+
+@pytest.mark.parametrize("method", ["BB", "LINEAR", "QUADRATIC"])
+def test_momentum_exchange_balances_fluid_momentum(method):
+    """Fluid momentum change = body force - Eq. 17 force, every step (u_w = 0)."""
+    shape = (20, 18, 16)
+    g = np.array([1e-5, 2e-6, -1e-6])
+    o = Oracle("D3Q19", "MRT", shape, 0.8, g=g)
+    o.set_solids([W.solid("sphere", (9.3, 8.6, 7.9), 4.7)], method)
+    e, w, _ = o.lattice_tables()
+    excl, _, _ = o.node_flags()
+    nfluid = int((excl == 0).sum())
+    P0, m0 = _momentum(o, e, excl)
+    for _ in range(30):
+        o.step(1)
+        P1, m1 = _momentum(o, e, excl)
+        F = o.force_torque()[0, :3]
+        assert np.max(np.abs((P1 - P0) - (nfluid * g - F))) < 2e-13  # rounding of ~1e3 link terms of size 0.05
+        if method == "BB":
+            assert abs(m1 - m0) < 1e-15 * nfluid  # a few ulp of rounding per cell per step
+        P0, m0 = P1, m1
+
+
+def test_ibm_force_balances_fluid_momentum():
+    shape = (20, 18, 16)
+    g = np.array([1e-5, 0.0, 0.0])
+    o = Oracle("D3Q19", "MRT", shape, 0.8, g=g)
+    s = W.solid("sphere", (9.3, 8.6, 7.9), 4.2)
+    o.set_solids([s], "IBM")
+    X, dV = W.icosphere(s["centre"], s["radius"])
+    o.set_lagrangian(0, X, dV)
+    e, w, _ = o.lattice_tables()
+    excl, inside, _ = o.node_flags()
+    nforced = int((inside == 0).sum())
+    P0, _ = _momentum(o, e, excl)
+    for _ in range(10):
+        o.step(1)
+        P1, _ = _momentum(o, e, excl)
+        F = o.force_torque()[0, :3]
+        assert np.max(np.abs((P1 - P0) - (nforced * g - F))) < 2e-13  # rounding over ~6e3 collisions
+        # total spread force equals the Lagrangian force times dV (delta sums to one)
+        assert np.max(np.abs(o.ibm_force_field().sum(axis=1) + F)) < 1e-14
+        P0 = P1
+
+
+def _taylor_green_error(N, tau=0.8, U=1e-4):
+    nu = (tau - 0.5) / 3.0
+    k = 2.0 * math.pi / N
+    o = Oracle("D2Q9", "BGK", (N, N, 1), tau)
+    x, y = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    ux = -U * np.cos(k * x) * np.sin(k * y)
+    uy = U * np.sin(k * x) * np.cos(k * y)
+    f = np.stack([o.feq(1.0, (a, b, 0.0)) for a, b in zip(ux.ravel(), uy.ravel())], axis=1)
+    o.set_f(f)
+    steps = int(round(N * N / (8.0 * math.pi ** 2 * nu)))
+    o.step(steps)
+    _, u, _ = o.macros()
+    # macros are those of the last collision, at time steps - 1
+    decay = math.exp(-2.0 * nu * k * k * (steps - 1))
+    ex, ey = ux.ravel() * decay, uy.ravel() * decay
+    num = np.sqrt(np.sum((u[0] - ex) ** 2 + (u[1] - ey) ** 2))
+    return num / np.sqrt(np.sum(ex ** 2 + ey ** 2))
+
+
+def test_taylor_green_second_order():
+    errs = [_taylor_green_error(N) for N in (16, 32, 64)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 <= p <= 2.2 for p in orders), (errs, orders)
+
+
+def _poiseuille(method, coll, tau, H, q_lo, q_hi, U=1e-3, steps=None):
+    ny = H + 2
+    y0 = 1.0 - q_lo
+    y1 = float(H) + q_hi
+    Wd = y1 - y0
+    nu = (tau - 0.5) / 3.0
+    g = 8.0 * nu * U / Wd ** 2
+    o = Oracle("D2Q9", coll, (1, ny, 1), tau, g=(g, 0.0))
+    o.set_solids([W.solid("plane", (0, y0, 0), axis=(0, 1, 0)),
+                  W.solid("plane", (0, y1, 0), axis=(0, -1, 0))], method)
+    if steps is None:
+        steps = int(40 * Wd ** 2 / (math.pi ** 2 * nu))
+    o.step(steps)
+    _, u, t = o.macros()
+    y = np.arange(ny, dtype=np.float64)
+    ua = g / (2.0 * nu) * (y - y0) * (y1 - y)
+    fl = t == 0
+    return np.sqrt(np.sum((u[0][fl] - ua[fl]) ** 2) / np.sum(ua[fl] ** 2)), o
+
+
+@pytest.mark.parametrize("coll,tau", [("MRT", 0.8), ("MRT", 1.3), ("BGK", 0.5 + math.sqrt(3.0 / 16.0))])
+def test_poiseuille_exact_for_halfway_walls(coll, tau):
+    err, o = _poiseuille("BB", coll, tau, 12, 0.5, 0.5)
+    assert err < 1e-10
+    assert np.all(o.links()["q"] == 0.5)
+
+
+@pytest.mark.parametrize("method,lo,hi", [("BB", 0.6, 1.4), ("LINEAR", 1.7, 2.3), ("QUADRATIC", 1.7, 2.3)])
+def test_poiseuille_convergence_order(method, lo, hi):
+    errs = [_poiseuille(method, "MRT", 0.8, H, 0.27, 0.81)[0] for H in (8, 16, 32)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(lo <= p <= hi for p in orders), (errs, orders)
+
+
+def _couette(R1, method="QUADRATIC", tau=1.0, Om2R2=0.01):
+    R2 = 2.0 * R1
+    n = int(2 * R2 + 6)
+    c = (n / 2.0 + 0.31, n / 2.0 - 0.17, 0.0)
+    Om2 = Om2R2 / R2
+    nu = (tau - 0.5) / 3.0
+    o = Oracle("D2Q9", "MRT", (n, n, 1), tau, rates=np.full(9, 1.0 / tau))
+    o.set_solids([W.solid("cylinder", c, R1), W.solid("cylinder", c, R2, inverted=True, omega=(0, 0, Om2))],
+                 method)
+    lam1 = math.pi / (R2 - R1)
+    steps = int(22.0 / (nu * lam1 * lam1))
+    o.step(steps)
+    _, u, t = o.macros()
+    x, y = np.meshgrid(np.arange(n) - c[0], np.arange(n) - c[1], indexing="xy")
+    r = np.sqrt(x * x + y * y).ravel()
+    fl = t == 0
+    # Eq. 31 with Omega_1 = 0
+    A = -Om2 / (R1 ** -2 - R2 ** -2)
+    Bc = Om2 * R2 ** 2 / (R2 ** 2 - R1 ** 2)
+    ut = A / r + Bc * r
+    uth = (-u[0] * y.ravel() + u[1] * x.ravel()) / r
+    ur = (u[0] * x.ravel() + u[1] * y.ravel()) / r
+    err = math.sqrt(np.sum((uth[fl] - ut[fl]) ** 2 + ur[fl] ** 2) / np.sum(ut[fl] ** 2))
+    T1 = 4.0 * math.pi * nu * Om2 * R1 ** 2 * R2 ** 2 / (R2 ** 2 - R1 ** 2)
+    FT = o.force_torque()
+    return err, FT[0, 5], FT[1, 5], T1
+
+
+def test_couette_steady_profile_and_torque():
+    e8, t8, to8, T8 = _couette(8.0)
+    e16, t16, to16, T16 = _couette(16.0)
+    order = math.log2(e8 / e16)
+    assert e16 < 5e-3
+    assert 1.5 <= order <= 2.6, (e8, e16, order)
+    # inner torque converges to the analytic value; outer carries the opposite
+    assert abs(t16 / T16 - 1.0) < 0.02
+    assert abs(t16 / T16 - 1.0) < abs(t8 / T8 - 1.0) or abs(t8 / T8 - 1.0) < 0.005
+    assert abs(to16 / T16 + 1.0) < 0.02
+
+
+def _pipe(R, method, steps_factor=12.0, tau=0.8, Re=10.0, t_eval=None, retraction=0.0):
+    n = int(2 * R + 6)
+    c = (n / 2.0 + 0.23, n / 2.0 - 0.36, 0.0)
+    nu = (tau - 0.5) / 3.0
+    u0 = Re * nu / (2.0 * R)
+    g = 4.0 * nu * u0 / R ** 2
+    o = Oracle("D3Q19", "MRT", (n, n, 1), tau, g=(0.0, 0.0, g))
+    s = W.solid("cylinder", c, R, inverted=True, axis=(0, 0, 1))
+    o.set_solids([s], method)
+    if method == "IBM":
+        X, dV = W.cylinder_surface(c, R + retraction, 1)
+        o.set_lagrangian(0, X, dV)
+    steps = int(steps_factor * R * R / (nu * 5.783)) if t_eval is None else t_eval
+    o.step(steps)
+    _, u, t = o.macros()
+    x, y = np.meshgrid(np.arange(n) - c[0], np.arange(n) - c[1], indexing="xy")
+    r = np.sqrt(x * x + y * y).ravel()
+    fl = r < R
+    if t_eval is None:
+        ua = u0 * (1.0 - r ** 2 / R ** 2)
+    else:
+        lam = special.jn_zeros(0, 60)
+        tt = float(t_eval - 1)
+        series = sum(8.0 * special.j0(l * r / R) / (l ** 3 * special.j1(l)) * math.exp(-l * l * nu * tt / R ** 2)
+                     for l in lam)
+        ua = u0 * ((1.0 - r ** 2 / R ** 2) - series)
+    err = math.sqrt(np.sum((u[2][fl] - ua[fl]) ** 2) / np.sum(ua[fl] ** 2))
+    return err
+
+
+def test_pipe_flow_ibb_second_order():
+    e1, e2 = _pipe(6.0, "QUADRATIC"), _pipe(12.0, "QUADRATIC")
+    p = math.log2(e1 / e2)
+    assert e2 < 5e-3 and 1.5 <= p <= 2.7, (e1, e2, p)
+
+
+def test_pipe_flow_transient_series():
+    R, nu = 12.0, 0.1
+    t_eval = int(0.1 * R * R / nu)
+    e = _pipe(R, "QUADRATIC", t_eval=t_eval)
+    assert e < 1e-2, e
+
+
+def test_pipe_flow_ibm_first_order():
+    e1, e2 = _pipe(6.0, "IBM"), _pipe(12.0, "IBM")
+    p = math.log2(e1 / e2)
+    assert 0.6 <= p <= 1.5, (e1, e2, p)
