@@ -1,0 +1,206 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice Boltzmann library (liblbm.so).
+ *
+ * The library advances a periodic lattice Boltzmann fluid on one gfx950 GPU
+ * with no-slip solids treated either by interpolated bounce-back (IBB) on
+ * fluid-solid links with momentum-exchange force and torque, or by the
+ * direct-forcing immersed boundary method (IBM).  The method is the one
+ * compared in Peng, Ayala & Wang, arXiv 1906.05445:
+ *   - evolution: lattice BGK (Eq. 1, viscosity Eq. 2) or MRT (Eq. 3) with a
+ *     second-order mesoscopic body-force term (Sec. 2.1);
+ *   - IBB: halfway bounce-back (Eq. 10), quadratic Bouzidi (Eq. 11), linear
+ *     Bouzidi (named in Sec. 3.3), with the link fraction q of Sec. 2.2;
+ *     force and torque by the Galilean-invariant momentum exchange (Eq. 17);
+ *   - IBM: Uhlmann's direct forcing (Eq. 5-9) with Peskin's 4-point delta
+ *     (Eq. 6), iterated n_iter times (Sec. 3.1), force and torque from the
+ *     Lagrangian forces (Sec. 3.1, App. B).
+ *
+ * Conventions (lattice units: dx = dt = 1, reference density rho0 = 1):
+ *   - cell index n = x + nx*(y + ny*z); D2Q9 lattices have nz == 1;
+ *   - velocity sets: rest first, then +/- pairs, axis pairs before diagonal
+ *     pairs; D2Q9: (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,-1) (1,-1) (-1,1);
+ *     D3Q19: the 6 axis directions (+x -x +y -y +z -z) then (1,1,0)
+ *     (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+ *     (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1);
+ *   - population arrays crossing the ABI are [Q][N] (direction-major);
+ *     velocity arrays are [3][N];
+ *   - MRT moment order (the rows of M): D2Q9: 1, |e|^2, |e|^4, ex,
+ *     ex|e|^2, ey, ey|e|^2, ex^2-ey^2, ex ey; D3Q19: 1, |e|^2, |e|^4, ex,
+ *     ex|e|^2, ey, ey|e|^2, ez, ez|e|^2, 3ex^2-|e|^2, (3ex^2-|e|^2)|e|^2,
+ *     ey^2-ez^2, (ey^2-ez^2)|e|^2, ex ey, ey ez, ex ez, (ey^2-ez^2)ex,
+ *     (ez^2-ex^2)ey, (ex^2-ey^2)ez (orthogonalised in that order);
+ *   - forces are the hydrodynamic force ON the solid; torques are about the
+ *     solid centre.
+ *
+ * Ownership: every pointer argument is borrowed for the duration of the call.
+ * Device memory is caller-owned: the context lives inside a device workspace
+ * the caller allocates (size from lbm_workspace_bytes); the library never
+ * allocates device memory.  All GPU work is ordered on the caller's HIP
+ * stream; the readout calls (lbm_force_torque, lbm_force_history,
+ * lbm_macros, lbm_get_f, lbm_get_state, lbm_link_list) synchronise that
+ * stream.  One context must not be used by two host threads at once.
+ *
+ * Errors: no exception crosses the ABI.  Every call returns lbm_status;
+ * lbm_status_string names it and lbm_last_error(ctx) gives detail.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_EINVAL (-1)       /* invalid argument (tau <= 1/2, bad sizes, overlapping solids, ...) */
+#define LBM_ENOMEM (-2)       /* workspace too small, or a link / point capacity exceeded */
+#define LBM_EDEVICE (-3)      /* HIP runtime error; text in lbm_last_error */
+#define LBM_EDIVERGED (-4)    /* non-finite value found by the watchdog */
+#define LBM_EUNSUPPORTED (-5) /* combination not implemented */
+#define LBM_ESTATE (-6)       /* call out of order */
+#define LBM_EAGAIN (-7)       /* batch admission deferred: not enough free pool memory */
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
+typedef enum { LBM_BGK = 0, LBM_MRT = 1 } lbm_collision;
+/* Storage of the populations.  All formats hold the deviation f_i - w_i from
+ * the rest state; F64 computes in FP64, F32_DEV and F16_DEV decode to FP32
+ * and compute in FP32 (force and torque are always accumulated in FP64). */
+typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2 } lbm_storage;
+typedef enum { LBM_BB = 0, LBM_IBB_LINEAR = 1, LBM_IBB_QUADRATIC = 2, LBM_IBM = 3 } lbm_boundary;
+typedef enum { LBM_SPHERE = 0, LBM_CYLINDER = 1, LBM_PLANE = 2 } lbm_solid_kind;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+/* Lattice, grid and relaxation (Eq. 1-3).
+ *   tau   : BGK relaxation time, nu = (tau - 1/2)/3 (Eq. 2); must be > 1/2.
+ *   rates : MRT only; NULL selects the default diagonal S: every even
+ *           non-conserved moment relaxes with 1/tau, the odd non-conserved
+ *           moments with s_odd from (tau - 1/2)(1/s_odd - 1/2) = 3/16; or Q
+ *           caller rates in the moment order above (rates of the conserved
+ *           moments have no effect).
+ *   body_force        : force density g added on the fluid region.
+ *   body_force_fluid_only : 1 = g acts only on nodes outside every solid's
+ *           volume (the setting Sec. 3.3 finds more accurate for IBM);
+ *           0 = everywhere (IBB solid nodes never carry fluid). */
+typedef struct {
+  int32_t lattice;    /* lbm_lattice */
+  int32_t collision;  /* lbm_collision */
+  int32_t storage;    /* lbm_storage */
+  int32_t nx, ny, nz; /* all axes periodic; nz == 1 for D2Q9 */
+  double tau;
+  const double *rates;
+  double body_force[3];
+  int32_t body_force_fluid_only;
+} lbm_params;
+
+/* A rigid solid.  Sphere: centre, radius (in 2D a circle).  Cylinder: axis
+ * along a coordinate direction (unit vector), infinite and periodic along
+ * it.  Plane (a half-space, for tests): `axis` is the unit normal pointing
+ * into the fluid, `centre` a point of the plane.  inverted = 1 makes the
+ * solid the OUTSIDE of the sphere/cylinder (an outer Couette wall, a pipe).
+ * Wall velocity u_w(x) = velocity + omega x (x - centre).  A solid with
+ * nonzero velocity translates (centre(t) = centre + t*velocity, IBB only). */
+typedef struct {
+  int32_t kind;       /* lbm_solid_kind */
+  int32_t inverted;
+  double centre[3];   /* 0 <= centre < box size (per non-axial axis) */
+  double radius;
+  double axis[3];
+  double velocity[3];
+  double omega[3];
+} lbm_solid;
+
+/* IBM options: n_iter direct-forcing iterations per step (Sec. 3.1 uses 5),
+ * retraction R_d of the Lagrangian points towards the solid (Breugem,
+ * Sec. 3.1; 0 = Uhlmann). */
+typedef struct {
+  int32_t n_iter;
+  double retraction;
+} lbm_ibm_opts;
+
+/* Bytes of device workspace for one context.  max_links bounds the number of
+ * IBB boundary links, max_lagrangian the number of IBM points; 0 selects a
+ * bound computed from the lattice size. */
+size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_links,
+                           int64_t max_lagrangian);
+
+/* Create a context inside dev_workspace (device memory, >= ws_bytes, caller
+ * owned, 256-byte aligned) for work on hip_stream (a hipStream_t, may be
+ * NULL for the default stream).  The populations start at rest (f = w).
+ * Errors: LBM_EINVAL, LBM_ENOMEM (ws_bytes too small), LBM_EDEVICE. */
+lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
+
+/* Set the solids and the no-slip method (replaces any previous set).
+ * IBB: classifies nodes (inside iff squared distance <= R^2, shortest
+ * periodic image), builds the boundary links, computes q.  IBM: generates
+ * the Lagrangian mesh of each solid (geodesic sphere of about one point per
+ * unit area; circles / rings of spacing about 1), unless points are given
+ * afterwards with lbm_set_lagrangian.  opts may be NULL (5 iterations, no
+ * retraction).  Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EUNSUPPORTED. */
+lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts);
+
+/* IBM only: replace the Lagrangian points of one solid with X [n][3]
+ * (FP64, lattice units), each with control volume dV. */
+lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_t n, double dV);
+
+/* Advance nsteps time steps (no host synchronisation inside). */
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
+
+/* Force and torque on every solid in the most recent step, [n][3] each. */
+lbm_status lbm_force_torque(lbm_ctx *c, double *force, double *torque);
+
+/* Per-step force and torque, ft [count][nsolid][6] = (Fx Fy Fz Tx Ty Tz),
+ * for steps first .. first+count-1 (step k is the update k -> k+1).  The
+ * library keeps the last lbm_history_capacity() steps; older ones give
+ * LBM_EINVAL. */
+lbm_status lbm_force_history(lbm_ctx *c, int64_t first, int64_t count, double *ft);
+int64_t lbm_history_capacity(void);
+
+/* Macroscopic fields of the most recent collision: rho [N], u [3][N] with
+ * u = (j + F/2)/rho; IBB solid nodes report rho = 0 and the wall velocity.
+ * node_type [N] (may be NULL), in the geometry of that collision: 0 fluid,
+ * 1 IBB solid node, 2 fluid inside an IBM solid.  Before the first step (or
+ * after lbm_set_f / lbm_set_state): the fields of the current populations,
+ * u = j/rho. */
+lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type);
+
+/* Populations f_i(x, t) before the next collision, [Q][N] FP64 (solid nodes
+ * give 0); lbm_set_f replaces them (time and history are kept). */
+lbm_status lbm_get_f(lbm_ctx *c, double *f);
+lbm_status lbm_set_f(lbm_ctx *c, const double *f);
+
+/* Raw deviations f_i - w_i before the next collision, [Q][N] in the storage
+ * format (double, float or IEEE half), bit for bit. */
+lbm_status lbm_get_state(lbm_ctx *c, void *host);
+lbm_status lbm_set_state(lbm_ctx *c, const void *host);
+
+/* Boundary links in canonical order (by cell, then direction): cell, dir,
+ * solid, q.  Pass NULL arrays to get the count only. */
+lbm_status lbm_link_list(lbm_ctx *c, int64_t *count, uint32_t *cell, uint8_t *dir, int32_t *solid, double *q);
+
+/* Node classification [N]: 0 fluid, 1 IBB solid node, 2 inside an IBM solid. */
+lbm_status lbm_node_types(lbm_ctx *c, uint8_t *node_type);
+
+/* Completed time steps. */
+int64_t lbm_time(const lbm_ctx *c);
+
+/* Scan the current populations for NaN/Inf: LBM_OK or LBM_EDIVERGED. */
+lbm_status lbm_check(lbm_ctx *c);
+
+lbm_status lbm_destroy(lbm_ctx *c);
+const char *lbm_status_string(lbm_status st);
+const char *lbm_last_error(const lbm_ctx *c);
+
+/* Copy `bytes` from src to dst (device pointers) with the library's
+ * streaming copy kernel, the bandwidth yardstick for the sweep. */
+lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -72,6 +72,8 @@ def lib():
         L.orc_time.restype = ctypes.c_long
         L.orc_get_f.argtypes = [ctypes.c_void_p, _d]
         L.orc_set_f.argtypes = [ctypes.c_void_p, _d]
+        L.orc_get_h.argtypes = [ctypes.c_void_p, _d]
+        L.orc_set_h.argtypes = [ctypes.c_void_p, _d]
         L.orc_get_rates.argtypes = [ctypes.c_void_p, _d]
         L.orc_get_mrt.argtypes = [ctypes.c_void_p, _d, _d]
         L.orc_lattice.argtypes = [ctypes.c_void_p, _i, _d, _i]
@@ -196,6 +198,16 @@ class Oracle:
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.N)
         lib().orc_set_f(self._h, _p(f))
+
+    def get_h(self):
+        """Stored deviations h = f - w (exact, no conversion)."""
+        out = np.empty((self.Q, self.N), dtype=np.float64)
+        lib().orc_get_h(self._h, _p(out))
+        return out
+
+    def set_h(self, h):
+        h = np.ascontiguousarray(h, dtype=np.float64).reshape(self.Q, self.N)
+        lib().orc_set_h(self._h, _p(h))
 
     def macros(self):
         rho = np.empty(self.N)

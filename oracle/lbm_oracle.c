@@ -27,6 +27,12 @@
  *   7. moving IBB solids only: advance the solid, reclassify, refill the
  *      newly uncovered nodes and rebuild the boundary links (Sec. 3.2).
  *
+ * Populations are stored as deviations h_i = f_i - w_i from the rest state
+ * (rho = 1, u = 0).  Every relation used is linear in f apart from f_eq, and
+ * all bounce-back weights sum to one, so the step is the same computation
+ * written for h (f - f_eq = h - h_eq); it only keeps the stored numbers
+ * small, which lowers the oracle's own rounding by about three decades.
+ *
  * The paper does not print the velocity sets, the equilibrium, the MRT
  * matrix, the relaxation rates, the forcing term, the linear Bouzidi formula
  * or the refill rule ("not repeated here", Sec. 2).  The readings used are the
@@ -142,6 +148,20 @@ typedef struct orc {
 
 static void solid_node_output(struct orc *o);
 
+/* Compensated (Neumaier) summation: the momentum-exchange sum adds O(0.1)
+ * rest-state terms that cancel to a small force, so a plain running sum
+ * would carry an error of ~1e-12; this keeps it at the last bit. */
+typedef struct {
+  double s, c;
+} acc_t;
+static void acc_add(acc_t *a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+  else a->c += (v - t) + a->s;
+  a->s = t;
+}
+static double acc_get(const acc_t *a) { return a->s + a->c; }
+
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                             */
 /* ------------------------------------------------------------------------ */
@@ -176,6 +196,16 @@ static void feq_all(const orc *o, double rho, const double u[3], double *feq) {
   for (int i = 0; i < o->Q; i++) {
     double eu = o->e[i][0] * u[0] + o->e[i][1] * u[1] + o->e[i][2] * u[2];
     feq[i] = o->w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+  }
+}
+/* The same equilibrium written as a deviation from the rest state:
+ * f_eq_i - w_i = w_i [ (rho - 1) + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u) ]. */
+static void heq_all(const orc *o, double drho, const double u[3], double *heq) {
+  double rho = 1.0 + drho;
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < o->Q; i++) {
+    double eu = o->e[i][0] * u[0] + o->e[i][1] * u[1] + o->e[i][2] * u[2];
+    heq[i] = o->w[i] * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
   }
 }
 static void guo_all(const orc *o, const double u[3], const double F[3], double *Fi) {
@@ -574,21 +604,22 @@ static void ibm_force(orc *o, const double *rho, const double *j, const double *
     }
     for (long l = 0; l < 3 * o->nlag; l++) o->Flag[l] += Fk[l];
   }
-  for (int k = 0; k < o->nsolid; k++)
-    for (int a = 0; a < 6; a++) o->FT[6 * k + a] = 0.0;
+  acc_t *acc = (acc_t *)calloc(6 * (o->nsolid > 0 ? o->nsolid : 1), sizeof(acc_t));
   for (long l = 0; l < o->nlag; l++) {
     int k = o->lag_sid[l];
     const solid_t *s = &o->sol[k];
     double r[3], F[3];
     lever(o, s, o->X[3 * l], o->X[3 * l + 1], o->X[3 * l + 2], r);
     for (int a = 0; a < 3; a++) F[a] = -o->Flag[3 * l + a] * o->dV[l];
-    o->FT[6 * k + 0] += F[0];
-    o->FT[6 * k + 1] += F[1];
-    o->FT[6 * k + 2] += F[2];
-    o->FT[6 * k + 3] += r[1] * F[2] - r[2] * F[1];
-    o->FT[6 * k + 4] += r[2] * F[0] - r[0] * F[2];
-    o->FT[6 * k + 5] += r[0] * F[1] - r[1] * F[0];
+    acc_add(&acc[6 * k + 0], F[0]);
+    acc_add(&acc[6 * k + 1], F[1]);
+    acc_add(&acc[6 * k + 2], F[2]);
+    acc_add(&acc[6 * k + 3], r[1] * F[2] - r[2] * F[1]);
+    acc_add(&acc[6 * k + 4], r[2] * F[0] - r[0] * F[2]);
+    acc_add(&acc[6 * k + 5], r[0] * F[1] - r[1] * F[0]);
   }
+  for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = acc_get(&acc[k]);
+  free(acc);
   free(u);
   free(fk);
   free(Ut);
@@ -639,7 +670,7 @@ orc *orc_create(int lattice, int collision, int nx, int ny, int nz, double tau, 
   for (long n = 0; n < o->N; n++) {
     o->owner[n] = -1;
     o->rho_out[n] = 1.0;
-    for (int i = 0; i < o->Q; i++) o->f[(long)i * o->N + n] = o->w[i]; /* rest, rho = 1 */
+    for (int i = 0; i < o->Q; i++) o->f[(long)i * o->N + n] = 0.0; /* rest: f = w, rho = 1 */
   }
   o->n_iter = 5;
   o->method = M_BB;
@@ -731,29 +762,32 @@ void orc_set_ibm_iters(orc *o, int n_iter) { o->n_iter = n_iter; }
 /* ------------------------------------------------------------------------ */
 /* one time step                                                             */
 /* ------------------------------------------------------------------------ */
-static void collide(orc *o, const double *rho, const double *j, const double *Ftot) {
+/* Collision of every fluid node.  h holds f - w; with rho = 1 + drho and
+ * f - f_eq = h - h_eq the formulas below are Eq. 1 and Eq. 3 as written. */
+static void collide(orc *o, const double *drho, const double *j, const double *Ftot) {
   int Q = o->Q;
   long N = o->N;
   for (long n = 0; n < N; n++) {
     if (o->excl[n]) continue;
-    double fi[QMAX], feq[QMAX], Fi[QMAX], u[3], F[3];
-    for (int i = 0; i < Q; i++) fi[i] = o->f[(long)i * N + n];
+    double hi[QMAX], heq[QMAX], Fi[QMAX], u[3], F[3];
+    double rho = 1.0 + drho[n];
+    for (int i = 0; i < Q; i++) hi[i] = o->f[(long)i * N + n];
     for (int a = 0; a < 3; a++) F[a] = Ftot[a * N + n];
-    for (int a = 0; a < 3; a++) u[a] = (j[a * N + n] + 0.5 * F[a]) / rho[n];
-    feq_all(o, rho[n], u, feq);
+    for (int a = 0; a < 3; a++) u[a] = (j[a * N + n] + 0.5 * F[a]) / rho;
+    heq_all(o, drho[n], u, heq);
     guo_all(o, u, F, Fi);
     if (o->collision == 0) {
       /* Eq. 1 with F_i = (1 - 1/(2 tau)) F_hat_i */
       for (int i = 0; i < Q; i++)
-        o->fpost[(long)i * N + n] = fi[i] - (fi[i] - feq[i]) / o->tau + (1.0 - 0.5 / o->tau) * Fi[i];
+        o->fpost[(long)i * N + n] = hi[i] - (hi[i] - heq[i]) / o->tau + (1.0 - 0.5 / o->tau) * Fi[i];
     } else {
       /* Eq. 3: f + [-M^-1 S (m - m_eq) + M^-1 Psi], Psi = (I - S/2) M F_hat */
       double m[QMAX], meq[QMAX], mF[QMAX], dm[QMAX];
       for (int k = 0; k < Q; k++) {
         double a = 0.0, b = 0.0, c = 0.0;
         for (int i = 0; i < Q; i++) {
-          a += o->M[k][i] * fi[i];
-          b += o->M[k][i] * feq[i];
+          a += o->M[k][i] * hi[i];
+          b += o->M[k][i] * heq[i];
           c += o->M[k][i] * Fi[i];
         }
         m[k] = a;
@@ -764,10 +798,10 @@ static void collide(orc *o, const double *rho, const double *j, const double *Ft
       for (int i = 0; i < Q; i++) {
         double s = 0.0;
         for (int k = 0; k < Q; k++) s += o->Minv[i][k] * dm[k];
-        o->fpost[(long)i * N + n] = fi[i] + s;
+        o->fpost[(long)i * N + n] = hi[i] + s;
       }
     }
-    o->rho_out[n] = rho[n];
+    o->rho_out[n] = rho;
     for (int a = 0; a < 3; a++) o->u_out[a * N + n] = u[a];
   }
 }
@@ -839,7 +873,7 @@ static void move_solids(orc *o) {
       rs += r;
       cnt++;
     }
-    double rb = cnt ? rs / cnt : 1.0;
+    double drb = cnt ? rs / cnt : 0.0; /* mean density minus 1 */
     /* the solid that covered the node at t; its wall velocity at t+1 */
     int sid = old_owner[n];
     double uw[3] = {0.0, 0.0, 0.0}, feq[QMAX];
@@ -848,7 +882,7 @@ static void move_solids(orc *o) {
       lever(o, &o->sol[sid], (double)x, (double)y, (double)z, r);
       wall_velocity(&o->sol[sid], r, uw);
     }
-    feq_all(o, rb, uw, feq);
+    heq_all(o, drb, uw, feq);
     for (int i = 0; i < o->Q; i++) o->f[(long)i * N + n] = feq[i];
   }
   free(old);
@@ -859,6 +893,7 @@ static void move_solids(orc *o) {
 static void one_step(orc *o) {
   int Q = o->Q;
   long N = o->N;
+  double *drho = (double *)malloc(sizeof(double) * N);
   double *rho = (double *)malloc(sizeof(double) * N);
   double *j = (double *)calloc(3 * N, sizeof(double));
   double *Ft = (double *)calloc(3 * N, sizeof(double));
@@ -872,7 +907,8 @@ static void one_step(orc *o) {
         jy += v * o->e[i][1];
         jz += v * o->e[i][2];
       }
-    rho[n] = o->excl[n] ? 1.0 : r;
+    drho[n] = r;
+    rho[n] = 1.0 + r;
     j[n] = jx;
     j[N + n] = jy;
     j[2 * N + n] = jz;
@@ -884,7 +920,7 @@ static void one_step(orc *o) {
     ibm_force(o, rho, j, Ft);
     for (long n = 0; n < 3 * N; n++) Ft[n] += o->fibm[n];
   }
-  collide(o, rho, j, Ft);
+  collide(o, drho, j, Ft);
   solid_node_output(o);
   /* streaming (push) */
   for (long n = 0; n < N; n++) {
@@ -897,6 +933,7 @@ static void one_step(orc *o) {
     }
   }
   /* interpolated bounce-back and momentum exchange (Eq. 10, 11, 17) */
+  acc_t *lacc = (acc_t *)calloc(6 * (o->nsolid > 0 ? o->nsolid : 1), sizeof(acc_t));
   for (long l = 0; l < o->nlink; l++) {
     const link_t *lk = &o->links[l];
     int i = lk->dir, ib = o->opp[i];
@@ -924,18 +961,24 @@ static void one_step(orc *o) {
     double fnew = orc_ibb_value(o->method, lk->q, lk->ff_ok, lk->fff_ok, fb_f, fb_ff, fb_fff, fs_f,
                                 fs_f, fs_ff, B);
     o->fnew[(long)i * N + n] = fnew;
-    /* Eq. 17: F dt = sum [f*_ibar (e_ibar - u_w) - f_i(t+1) (e_i - u_w)] */
+    /* Eq. 17: F dt = sum [f*_ibar (e_ibar - u_w) - f_i(t+1) (e_i - u_w)].  With
+     * f = w + h and w_ibar = w_i the rest-state part is w_i (e_ibar - e_i)
+     * = -2 w_i e_i, the wall velocity cancelling out of it. */
     double dF[3];
     for (int a = 0; a < 3; a++)
-      dF[a] = fb_f * ((double)o->e[ib][a] - uw[a]) - fnew * ((double)o->e[i][a] - uw[a]);
-    double *FT = &o->FT[6 * lk->sid];
-    FT[0] += dF[0];
-    FT[1] += dF[1];
-    FT[2] += dF[2];
-    FT[3] += r[1] * dF[2] - r[2] * dF[1];
-    FT[4] += r[2] * dF[0] - r[0] * dF[2];
-    FT[5] += r[0] * dF[1] - r[1] * dF[0];
+      dF[a] = fb_f * ((double)o->e[ib][a] - uw[a]) - fnew * ((double)o->e[i][a] - uw[a]) -
+              2.0 * o->w[i] * (double)o->e[i][a];
+    acc_t *A = &lacc[6 * lk->sid];
+    acc_add(&A[0], dF[0]);
+    acc_add(&A[1], dF[1]);
+    acc_add(&A[2], dF[2]);
+    acc_add(&A[3], r[1] * dF[2] - r[2] * dF[1]);
+    acc_add(&A[4], r[2] * dF[0] - r[0] * dF[2]);
+    acc_add(&A[5], r[0] * dF[1] - r[1] * dF[0]);
   }
+  if (o->nlink > 0)
+    for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = acc_get(&lacc[k]);
+  free(lacc);
   for (long n = 0; n < N; n++)
     if (!o->excl[n])
       for (int i = 0; i < Q; i++) o->f[(long)i * N + n] = o->fnew[(long)i * N + n];
@@ -943,6 +986,7 @@ static void one_step(orc *o) {
   move_solids(o);
   o->t++;
   o->stepped = 1;
+  free(drho);
   free(rho);
   free(j);
   free(Ft);
@@ -959,8 +1003,17 @@ int orc_step(orc *o, long nsteps) {
 long orc_cells(const orc *o) { return o->N; }
 int orc_q(const orc *o) { return o->Q; }
 long orc_time(const orc *o) { return o->t; }
-void orc_get_f(const orc *o, double *f) { memcpy(f, o->f, sizeof(double) * o->Q * o->N); }
-void orc_set_f(orc *o, const double *f) { memcpy(o->f, f, sizeof(double) * o->Q * o->N); }
+void orc_get_f(const orc *o, double *f) {
+  for (int i = 0; i < o->Q; i++)
+    for (long n = 0; n < o->N; n++) f[(long)i * o->N + n] = o->w[i] + o->f[(long)i * o->N + n];
+}
+void orc_set_f(orc *o, const double *f) {
+  for (int i = 0; i < o->Q; i++)
+    for (long n = 0; n < o->N; n++) o->f[(long)i * o->N + n] = f[(long)i * o->N + n] - o->w[i];
+}
+/* the stored deviations h = f - w */
+void orc_get_h(const orc *o, double *h) { memcpy(h, o->f, sizeof(double) * o->Q * o->N); }
+void orc_set_h(orc *o, const double *h) { memcpy(o->f, h, sizeof(double) * o->Q * o->N); }
 void orc_get_rates(const orc *o, double *S) { memcpy(S, o->S, sizeof(double) * o->Q); }
 void orc_get_mrt(const orc *o, double *M, double *Minv) {
   for (int r = 0; r < o->Q; r++)
@@ -981,25 +1034,25 @@ void orc_forcing(const orc *o, const double *u, const double *F, double *Fi) { g
 
 /* Post-collision populations of one node (for the collision pins). */
 void orc_collide_node(const orc *o, const double *fin, const double *F, double *fout) {
-  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  double hin[QMAX], drho = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < o->Q; i++) {
-    rho += fin[i];
-    for (int a = 0; a < 3; a++) j[a] += fin[i] * o->e[i][a];
+    hin[i] = fin[i] - o->w[i];
+    drho += hin[i];
+    for (int a = 0; a < 3; a++) j[a] += hin[i] * o->e[i][a];
   }
   orc tmp = *o;
-  long N1 = 1;
-  tmp.N = N1;
-  double fpost[QMAX];
+  tmp.N = 1;
+  double hpost[QMAX];
   unsigned char ex = 0;
   double rho_o, u_o[3];
-  tmp.f = (double *)fin;
-  tmp.fpost = fpost;
+  tmp.f = hin;
+  tmp.fpost = hpost;
   tmp.excl = &ex;
   tmp.rho_out = &rho_o;
   tmp.u_out = u_o;
   double Ft[3] = {F[0], F[1], F[2]};
-  collide(&tmp, &rho, j, Ft);
-  for (int i = 0; i < o->Q; i++) fout[i] = fpost[i];
+  collide(&tmp, &drho, j, Ft);
+  for (int i = 0; i < o->Q; i++) fout[i] = o->w[i] + hpost[i];
 }
 
 void orc_macros(const orc *o, double *rho, double *u, unsigned char *type) {
@@ -1011,9 +1064,9 @@ void orc_macros(const orc *o, double *rho, double *u, unsigned char *type) {
         r += v;
         for (int a = 0; a < 3; a++) jj[a] += v * o->e[i][a];
       }
-      if (rho) rho[n] = o->excl[n] ? o->rho_out[n] : r;
+      if (rho) rho[n] = o->excl[n] ? o->rho_out[n] : 1.0 + r;
       if (u)
-        for (int a = 0; a < 3; a++) u[a * o->N + n] = o->excl[n] ? o->u_out[a * o->N + n] : jj[a] / r;
+        for (int a = 0; a < 3; a++) u[a * o->N + n] = o->excl[n] ? o->u_out[a * o->N + n] : jj[a] / (1.0 + r);
     }
   } else {
     if (rho) memcpy(rho, o->rho_out, sizeof(double) * o->N);

@@ -1,0 +1,537 @@
+// kernels_boundary.hip -- node classification, boundary-link builder,
+// interpolated bounce-back with momentum-exchange force/torque, refill of
+// uncovered nodes (Sec. 2.2, Eq. 10, Eq. 11, Eq. 17, Sec. 3.2).
+//
+// Links are built per solid over the solid's bounding box (all cells within
+// R + 2 of its centre), so each solid's links are contiguous; the box is
+// walked in a fixed order, which makes the link list, and every reduction
+// over it, deterministic.  A link (x_f, i) joins a fluid node x_f to the
+// solid node x_b = x_f - e_i; the bounce-back kernel writes the unknown
+// f_i(x_f, t+1) into slot i of x_b, exactly where the next pull sweep at x_f
+// looks for population i.
+#include "lbm_geom.hpp"
+
+namespace lbm {
+
+struct GeoArgs {
+  Box3 b;
+  uint32_t N;
+  FastDiv fx, fy;
+  uint64_t stride;
+  const DevSolid *solids;
+  int nsolid;
+  int ibb;         // 1 = solids remove nodes from the fluid (IBB), 0 = IBM
+  int fluid_only;  // body force only outside solids
+  int64_t t;       // geometry time
+};
+
+__device__ inline void xyz_of(uint32_t n, const GeoArgs &a, int &x, int &y, int &z) {
+  const uint32_t yz = fdiv(n, a.fx);
+  x = (int)(n - yz * (uint32_t)a.b.nx);
+  z = (int)fdiv(yz, a.fy);
+  y = (int)(yz - (uint32_t)z * (uint32_t)a.b.ny);
+}
+__device__ inline uint32_t id_of(int x, int y, int z, const GeoArgs &a) {
+  return (uint32_t)wrapi(x, a.b.nx) +
+         (uint32_t)a.b.nx * ((uint32_t)wrapi(y, a.b.ny) + (uint32_t)a.b.ny * (uint32_t)wrapi(z, a.b.nz));
+}
+
+// Box of solid s at time t: cell (lx, ly, lz) of the box -> lattice cell.
+__device__ inline void box_origin(const DevSolid &s, const GeoArgs &a, int o[3]) {
+  if (!s.moving) {
+    o[0] = s.box0[0];
+    o[1] = s.box0[1];
+    o[2] = s.box0[2];
+    return;
+  }
+  double c[3];
+  solid_centre(s, a.t, a.b, c);
+  for (int k = 0; k < 3; k++) o[k] = s.full[k] ? 0 : (int)floor(c[k] - s.R) - 2;
+}
+__device__ inline bool box_cell(const DevSolid &s, const int o[3], uint32_t bi, const GeoArgs &a, int &x, int &y,
+                                int &z) {
+  if (bi >= s.box_cells) return false;
+  const uint32_t ex = (uint32_t)s.ext[0], ey = (uint32_t)s.ext[1];
+  const uint32_t lx = bi % ex, r = bi / ex;
+  const uint32_t ly = r % ey, lz = r / ey;
+  x = wrapi(o[0] + (int)lx, a.b.nx);
+  y = wrapi(o[1] + (int)ly, a.b.ny);
+  z = wrapi(o[2] + (int)lz, a.b.nz);
+  return true;
+}
+
+// classification of one cell against all solids (first match wins)
+__device__ inline int classify_cell(const GeoArgs &a, int x, int y, int z) {
+  for (int k = 0; k < a.nsolid; k++) {
+    const DevSolid &s = a.solids[k];
+    double c[3];
+    solid_centre(s, a.t, a.b, c);
+    if (inside_solid(s, c, x, y, z, a.b)) return k;
+  }
+  return -1;
+}
+__device__ inline uint8_t flags_for(const GeoArgs &a, int k, uint8_t old_ibm) {
+  uint8_t f = old_ibm;
+  if (k >= 0) {
+    if (a.ibb) f |= F_SOLID;
+    if (a.fluid_only) f |= F_NOBODY;
+  }
+  return f;
+}
+
+// Full classification (setup): previous geometry := current.
+__global__ void k_classify_full(uint8_t *flags, uint16_t *owner, uint16_t *owner_prev, GeoArgs a) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  xyz_of(n, a, x, y, z);
+  const int k = classify_cell(a, x, y, z);
+  uint8_t f = flags_for(a, k, flags[n] & F_IBM);
+  if (f & F_SOLID) f |= F_WAS_SOLID;
+  flags[n] = f;
+  owner[n] = k < 0 ? 0xFFFF : (uint16_t)k;
+  owner_prev[n] = owner[n];
+}
+
+// Moving solids, phase 1 over their boxes: remember the current geometry.
+__global__ void k_classify_keep(uint8_t *flags, const uint16_t *owner, uint16_t *owner_prev, GeoArgs a) {
+  const DevSolid &s = a.solids[blockIdx.y];
+  if (!s.moving) return;
+  int o[3], x, y, z;
+  box_origin(s, a, o);
+  if (!box_cell(s, o, blockIdx.x * blockDim.x + threadIdx.x, a, x, y, z)) return;
+  const uint32_t n = id_of(x, y, z, a);
+  const uint8_t f = flags[n];
+  flags[n] = (f & F_SOLID) ? (f | F_WAS_SOLID) : (uint8_t)(f & ~F_WAS_SOLID);
+  owner_prev[n] = owner[n];
+}
+// Moving solids, phase 2 over their boxes: classify at the new time.
+__global__ void k_classify_box(uint8_t *flags, uint16_t *owner, GeoArgs a) {
+  const DevSolid &s = a.solids[blockIdx.y];
+  if (!s.moving) return;
+  int o[3], x, y, z;
+  box_origin(s, a, o);
+  if (!box_cell(s, o, blockIdx.x * blockDim.x + threadIdx.x, a, x, y, z)) return;
+  const uint32_t n = id_of(x, y, z, a);
+  const int k = classify_cell(a, x, y, z);
+  const uint8_t old = flags[n];
+  flags[n] = (uint8_t)(flags_for(a, k, old & F_IBM) | (old & F_WAS_SOLID));
+  owner[n] = k < 0 ? 0xFFFF : (uint16_t)k;
+}
+
+void launch_classify(lbm_ctx *c, int64_t t, bool full);
+
+// ----------------------------------------------------------------------------
+// link builder
+// ----------------------------------------------------------------------------
+struct LinkArgs {
+  GeoArgs g;
+  const uint8_t *flags;
+  const uint16_t *owner, *owner_prev;
+  uint32_t *box_counts;    // [nsolid][max_box_chunks]
+  uint32_t *box_offsets;   // exclusive scan of box_counts
+  uint32_t max_box_chunks;
+  uint32_t *link_cell, *link_meta;
+  double *link_q;
+  uint64_t max_links;
+  SolidLinks *sl;
+  uint32_t *misc;          // [0] total links, [1] overflow flag
+  void *post;              // refill: post-collision array of step t-1 -> t
+  int refill;
+};
+
+// Links of cell n whose solid node belongs to solid s; bit i of the result.
+template <int Q>
+__device__ inline uint32_t link_mask(const LinkArgs &a, int s, int x, int y, int z) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    const uint32_t nb = id_of(x - Lat<Q>::ex(i), y - Lat<Q>::ey(i), z - Lat<Q>::ez(i), a.g);
+    if ((a.flags[nb] & F_SOLID) && a.owner[nb] == (uint16_t)s) m |= 1u << i;
+  }
+  return m;
+}
+
+// Refill of a node uncovered this step (Sec. 3.2): f = f_eq(rho_bar, u_w)
+// with rho_bar the mean density at t of the neighbours that are fluid
+// before and after the move (1 if none); written into the slots the node
+// pulls from, P_i(x - e_i).
+template <int Q, typename S>
+__device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
+  using L = Lat<Q>;
+  S *P = static_cast<S *>(a.post);
+  double sum = 0.0;  // of the density deviations rho - 1
+  int cnt = 0;
+  for (int i = 1; i < Q; i++) {
+    const int yx = x + L::ex(i), yy = y + L::ey(i), yzz = z + L::ez(i);
+    const uint32_t m = id_of(yx, yy, yzz, a.g);
+    if (a.flags[m] & (F_SOLID | F_WAS_SOLID)) continue;
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; j++)
+      r += (double)Store<S>::ld(P + (uint64_t)j * a.g.stride +
+                                id_of(yx - L::ex(j), yy - L::ey(j), yzz - L::ez(j), a.g));
+    sum += r;
+    cnt++;
+  }
+  const double drb = cnt ? sum / cnt : 0.0, rb = 1.0 + drb;
+  const DevSolid &sd = a.g.solids[s];
+  double c[3], r[3], uw[3];
+  solid_centre(sd, a.g.t, a.g.b, c);
+  lever_arm(sd, c, (double)x, (double)y, (double)z, a.g.b, r);
+  wall_vel(sd, r, uw);
+  const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const double eu = L::ex(i) * uw[0] + L::ey(i) * uw[1] + L::ez(i) * uw[2];
+    const double heq = wgt<Q>(i) * (drb + rb * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    Store<S>::st(P + (uint64_t)i * a.g.stride + id_of(x - L::ex(i), y - L::ey(i), z - L::ez(i), a.g),
+                 (typename Store<S>::C)heq);
+  }
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
+  __shared__ double lds[16];
+  const int s = blockIdx.y;
+  const DevSolid &sd = a.g.solids[s];
+  int o[3], x, y, z;
+  box_origin(sd, a.g, o);
+  uint32_t cnt = 0;
+  if (box_cell(sd, o, blockIdx.x * kBlock + threadIdx.x, a.g, x, y, z)) {
+    const uint32_t n = id_of(x, y, z, a.g);
+    const uint8_t f = a.flags[n];
+    if (!(f & F_SOLID)) {
+      if (a.refill && (f & F_WAS_SOLID) && a.owner_prev[n] == (uint16_t)s) refill_node<Q, S>(a, s, x, y, z);
+      cnt = __popc(link_mask<Q>(a, s, x, y, z));
+    }
+  }
+  const double tot = block_sum((double)cnt, lds);
+  if (threadIdx.x == 0 && blockIdx.x < a.max_box_chunks)
+    a.box_counts[(uint64_t)s * a.max_box_chunks + blockIdx.x] = (uint32_t)tot;
+}
+
+// One block: exclusive scan of the per-(solid, box chunk) counts, then the
+// per-solid link ranges and chunk bases of the bounce-back kernel.
+__global__ void k_link_scan(LinkArgs a, int nsolid) {
+  __shared__ uint32_t part[1024];
+  const uint32_t total = (uint32_t)nsolid * a.max_box_chunks;
+  const uint32_t per = (total + blockDim.x - 1) / blockDim.x;
+  const uint32_t b0 = threadIdx.x * per, b1 = min(total, b0 + per);
+  uint32_t s = 0;
+  for (uint32_t k = b0; k < b1; k++) s += a.box_counts[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < blockDim.x; k++) {
+      const uint32_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    a.misc[0] = run;
+    a.misc[1] = run > a.max_links ? 1u : 0u;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (uint32_t k = b0; k < b1; k++) {
+    const uint32_t v = a.box_counts[k];
+    a.box_offsets[k] = run;
+    run += v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t cb = 0;
+    for (int sd = 0; sd < nsolid; sd++) {
+      const uint32_t first = a.box_offsets[(uint64_t)sd * a.max_box_chunks];
+      const uint32_t last = sd + 1 < nsolid ? a.box_offsets[(uint64_t)(sd + 1) * a.max_box_chunks] : a.misc[0];
+      SolidLinks L;
+      L.start = first;
+      L.count = last - first;
+      L.chunk_base = cb;
+      L.nchunks = (L.count + kBlock - 1) / kBlock;
+      cb += L.nchunks;
+      a.sl[sd] = L;
+    }
+  }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
+  __shared__ uint32_t pre[kBlock];
+  const int s = blockIdx.y;
+  const DevSolid &sd = a.g.solids[s];
+  int o[3], x = 0, y = 0, z = 0;
+  box_origin(sd, a.g, o);
+  uint32_t m = 0;
+  if (box_cell(sd, o, blockIdx.x * kBlock + threadIdx.x, a.g, x, y, z)) {
+    const uint32_t n = id_of(x, y, z, a.g);
+    if (!(a.flags[n] & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
+  }
+  // block exclusive scan of the per-thread link counts (fixed order)
+  pre[threadIdx.x] = __popc(m);
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t v = threadIdx.x >= (uint32_t)off ? pre[threadIdx.x - off] : 0u;
+    __syncthreads();
+    pre[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (!m || blockIdx.x >= a.max_box_chunks) return;
+  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + blockIdx.x] + pre[threadIdx.x] - __popc(m);
+  const uint32_t n = id_of(x, y, z, a.g);
+  double c[3];
+  solid_centre(sd, a.g.t, a.g.b, c);
+  for (int i = 1; i < Q; i++) {
+    if (!(m & (1u << i))) continue;
+    if (pos < a.max_links) {
+      const int ex = Lat<Q>::ex(i), ey = Lat<Q>::ey(i), ez = Lat<Q>::ez(i);
+      const uint32_t ff = id_of(x + ex, y + ey, z + ez, a.g);
+      const uint32_t fff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
+      const uint32_t ffok = (a.flags[ff] & F_SOLID) ? 0u : 1u;
+      const uint32_t fffok = (a.flags[fff] & F_SOLID) ? 0u : 1u;
+      a.link_cell[pos] = n;
+      a.link_meta[pos] = (uint32_t)i | (ffok << 5) | (fffok << 6);
+      a.link_q[pos] = link_fraction(sd, c, x, y, z, ex, ey, ez, a.g.b);
+    }
+    pos++;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// interpolated bounce-back + momentum exchange (one thread per link)
+// ----------------------------------------------------------------------------
+struct IbbArgs {
+  GeoArgs g;
+  const uint32_t *link_cell, *link_meta;
+  const double *link_q;
+  const SolidLinks *sl;
+  double *partials;  // [chunk][6]
+  uint64_t max_links, max_partials;
+  int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC
+};
+
+// Unknown deviation h_i(x_f, t+1) of one link.  hb_*: post-collision h_ibar at
+// x_f, x_ff, x_fff; hs_*: post-collision h_i at x_f, x_ff (= h_i at x_ff,
+// x_fff after streaming).  B: wall term 2 rho0 w_i e_i.u_w / c_s^2.  The
+// coefficients of every scheme sum to one, so the formula holds for the
+// deviations as written for f.
+template <typename C>
+__device__ inline C ibb_value(int method, double q, bool ffok, bool fffok, C hb_f, C hb_ff, C hb_fff, C hs_f,
+                              C hs_ff, C B) {
+  if (method == LBM_IBB_QUADRATIC && ffok && fffok) {
+    if (q < 0.5) {  // Eq. 11a
+      const C c1 = (C)(q * (2.0 * q + 1.0)), c2 = (C)((1.0 + 2.0 * q) * (1.0 - 2.0 * q)),
+              c3 = (C)(q * (1.0 - 2.0 * q));
+      return c1 * hb_f + c2 * hb_ff - c3 * hb_fff + B;
+    }
+    // Eq. 11b
+    const C c1 = (C)(1.0 / (q * (2.0 * q + 1.0))), c2 = (C)((2.0 * q - 1.0) / q),
+            c3 = (C)((2.0 * q - 1.0) / (1.0 + 2.0 * q));
+    return c1 * (hb_f + B) + c2 * hs_f - c3 * hs_ff;
+  }
+  if (method == LBM_IBB_QUADRATIC || method == LBM_IBB_LINEAR) {
+    if (q < 0.5) {
+      if (ffok) return (C)(2.0 * q) * hb_f + (C)(1.0 - 2.0 * q) * hb_ff + B;
+      return hb_f + B;
+    }
+    return (hb_f + B) / (C)(2.0 * q) + (C)((2.0 * q - 1.0) / (2.0 * q)) * hs_f;
+  }
+  return hb_f + B;  // Eq. 10
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_ibb(S *__restrict__ P, IbbArgs a) {
+  using C = typename Store<S>::C;
+  using L = Lat<Q>;
+  __shared__ double lds[16];
+  const int s = blockIdx.y;
+  const SolidLinks sl = a.sl[s];
+  // capacity overflow (reported by the host after the step) must not read or write out of bounds
+  if (blockIdx.x >= sl.nchunks || (uint64_t)sl.chunk_base + blockIdx.x >= a.max_partials) return;
+  const uint32_t li = blockIdx.x * kBlock + threadIdx.x;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (li < sl.count && (uint64_t)sl.start + li < a.max_links) {
+    const uint64_t l = (uint64_t)sl.start + li;
+    const uint32_t n = a.link_cell[l], meta = a.link_meta[l];
+    const double q = a.link_q[l];
+    const int i = (int)(meta & 31u), ib = opp(i);
+    const bool ffok = (meta >> 5) & 1u, fffok = (meta >> 6) & 1u;
+    int x, y, z;
+    xyz_of(n, a.g, x, y, z);
+    int ex = 0, ey = 0, ez = 0;
+    double w = 0.0;
+#pragma unroll
+    for (int k = 1; k < Q; k++)
+      if (k == i) {
+        ex = L::ex(k);
+        ey = L::ey(k);
+        ez = L::ez(k);
+        w = wgt<Q>(k);
+      }
+    const DevSolid &sd = a.g.solids[s];
+    double c[3], r[3], uw[3];
+    solid_centre(sd, a.g.t, a.g.b, c);
+    lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
+    wall_vel(sd, r, uw);
+    const double Bw = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
+    const uint32_t nff = id_of(x + ex, y + ey, z + ez, a.g);
+    const uint32_t nfff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
+    const uint32_t nb = id_of(x - ex, y - ey, z - ez, a.g);
+    const S *Pi = P + (uint64_t)i * a.g.stride;
+    const S *Pb = P + (uint64_t)ib * a.g.stride;
+    const C hb_f = Store<S>::ld(Pb + n);
+    const C hb_ff = ffok ? Store<S>::ld(Pb + nff) : C(0);
+    const C hb_fff = fffok ? Store<S>::ld(Pb + nfff) : C(0);
+    const C hs_f = Store<S>::ld(Pi + n);
+    const C hs_ff = ffok ? Store<S>::ld(Pi + nff) : C(0);
+    const C v = ibb_value<C>(a.method, q, ffok, fffok, hb_f, hb_ff, hb_fff, hs_f, hs_ff, (C)Bw);
+    S *dst = P + (uint64_t)i * a.g.stride + nb;
+    Store<S>::st(dst, v);
+    // Eq. 17 in FP64 on the stored values.  With f = w + h the rest-state part
+    // w (e_ibar - u_w) - w (e_i - u_w) is -2 w e_i (u_w cancels).
+    const double hin = (double)Store<S>::ld(dst);
+    const double hout = (double)hb_f;
+    const double e[3] = {(double)ex, (double)ey, (double)ez};
+    double dF[3];
+    for (int k = 0; k < 3; k++) dF[k] = hout * (-e[k] - uw[k]) - hin * (e[k] - uw[k]) - 2.0 * w * e[k];
+    acc[0] = dF[0];
+    acc[1] = dF[1];
+    acc[2] = dF[2];
+    acc[3] = r[1] * dF[2] - r[2] * dF[1];
+    acc[4] = r[2] * dF[0] - r[0] * dF[2];
+    acc[5] = r[0] * dF[1] - r[1] * dF[0];
+  }
+  for (int k = 0; k < 6; k++) {
+    const double tot = block_sum(acc[k], lds);
+    if (threadIdx.x == 0) a.partials[(uint64_t)(sl.chunk_base + blockIdx.x) * 6 + k] = tot;
+  }
+}
+
+// Per-solid sum of the chunk partials in a fixed order -> history slot.
+__global__ void k_ft_reduce(const double *partials, const SolidLinks *sl, double *hist, uint64_t max_partials) {
+  __shared__ double lds[16];
+  const int s = blockIdx.x;
+  const SolidLinks L = sl[s];
+  for (int k = 0; k < 6; k++) {
+    double v = 0.0;
+    for (uint32_t c = threadIdx.x; c < L.nchunks; c += blockDim.x)
+      if ((uint64_t)L.chunk_base + c < max_partials) v += partials[(uint64_t)(L.chunk_base + c) * 6 + k];
+    const double tot = block_sum(v, lds);
+    if (threadIdx.x == 0) hist[(uint64_t)s * 6 + k] = tot;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host launchers
+// ----------------------------------------------------------------------------
+static GeoArgs geo_args(const lbm_ctx *c, int64_t t) {
+  GeoArgs g{};
+  g.b = Box3{c->p.nx, c->p.ny, c->p.nz, c->D};
+  g.N = (uint32_t)c->N;
+  g.fx = c->fx;
+  g.fy = c->fy;
+  g.stride = c->L.stride;
+  g.solids = c->at<DevSolid>(c->L.solids);
+  g.nsolid = c->nsolid;
+  g.ibb = c->method != LBM_IBM;
+  g.fluid_only = c->p.body_force_fluid_only;
+  g.t = t;
+  return g;
+}
+
+static LinkArgs link_args(const lbm_ctx *c, int64_t t) {
+  LinkArgs a{};
+  a.g = geo_args(c, t);
+  a.flags = c->at<uint8_t>(c->L.flags);
+  a.owner = c->at<uint16_t>(c->L.owner0);
+  a.owner_prev = c->at<uint16_t>(c->L.owner1);
+  a.box_counts = c->at<uint32_t>(c->L.box_counts);
+  a.box_offsets = c->at<uint32_t>(c->L.box_offsets);
+  a.max_box_chunks = (uint32_t)c->max_box_chunks;
+  a.link_cell = c->at<uint32_t>(c->L.link_cell);
+  a.link_meta = c->at<uint32_t>(c->L.link_meta);
+  a.link_q = c->at<double>(c->L.link_q);
+  a.max_links = (uint64_t)c->L.max_links;
+  a.sl = c->at<SolidLinks>(c->L.solid_links);
+  a.misc = c->at<uint32_t>(c->L.misc);
+  return a;
+}
+
+void launch_classify(lbm_ctx *c, int64_t t, bool full) {
+  GeoArgs g = geo_args(c, t);
+  uint8_t *flags = c->at<uint8_t>(c->L.flags);
+  uint16_t *own = c->at<uint16_t>(c->L.owner0), *prev = c->at<uint16_t>(c->L.owner1);
+  if (full) {
+    hipLaunchKernelGGL(k_classify_full, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream, flags, own,
+                       prev, g);
+    return;
+  }
+  const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
+  hipLaunchKernelGGL(k_classify_keep, grid, dim3(kBlock), 0, c->stream, flags, own, prev, g);
+  hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, flags, own, g);
+}
+
+void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *post) {
+  LinkArgs a = link_args(c, t);
+  a.refill = refill ? 1 : 0;
+  a.post = const_cast<void *>(post);
+  const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
+#define LBM_LC(QQ, SS) hipLaunchKernelGGL((k_link_count<QQ, SS>), grid, dim3(kBlock), 0, c->stream, a)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_LC(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_LC(9, float);
+    else LBM_LC(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_LC(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_LC(19, float);
+    else LBM_LC(19, _Float16);
+  }
+#undef LBM_LC
+}
+
+void launch_link_scan(lbm_ctx *c) {
+  LinkArgs a = link_args(c, 0);
+  hipLaunchKernelGGL(k_link_scan, dim3(1), dim3(1024), 0, c->stream, a, c->nsolid);
+}
+
+void launch_link_emit(lbm_ctx *c, int64_t t) {
+  LinkArgs a = link_args(c, t);
+  const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
+  if (c->Q == 9) hipLaunchKernelGGL(k_link_emit<9>, grid, dim3(kBlock), 0, c->stream, a);
+  else hipLaunchKernelGGL(k_link_emit<19>, grid, dim3(kBlock), 0, c->stream, a);
+}
+
+void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
+  if (c->k5_chunks <= 0) return;
+  IbbArgs a{};
+  a.g = geo_args(c, t);
+  a.link_cell = c->at<uint32_t>(c->L.link_cell);
+  a.link_meta = c->at<uint32_t>(c->L.link_meta);
+  a.link_q = c->at<double>(c->L.link_q);
+  a.sl = c->at<SolidLinks>(c->L.solid_links);
+  a.partials = c->at<double>(c->L.partials);
+  a.method = c->method;
+  a.max_links = (uint64_t)c->L.max_links;
+  a.max_partials = (uint64_t)c->L.max_partials;
+  const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
+#define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(kBlock), 0, c->stream, static_cast<SS *>(P), a)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_IBB(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_IBB(9, float);
+    else LBM_IBB(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_IBB(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_IBB(19, float);
+    else LBM_IBB(19, _Float16);
+  }
+#undef LBM_IBB
+}
+
+void launch_ft_reduce(lbm_ctx *c, int64_t t) {
+  double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
+  hipLaunchKernelGGL(k_ft_reduce, dim3((uint32_t)c->nsolid), dim3(256), 0, c->stream, c->at<double>(c->L.partials),
+                     c->at<SolidLinks>(c->L.solid_links), hist, (uint64_t)c->L.max_partials);
+}
+
+}  // namespace lbm

@@ -1,0 +1,248 @@
+// kernels_ibm.hip -- direct-forcing immersed boundary method (Sec. 2.1,
+// Eq. 5-9) with Peskin's 4-point delta (Eq. 6), iterated n_iter times
+// (Sec. 3.1), and the force/torque on each solid from its Lagrangian forces.
+//
+// Data: the Lagrangian points (FP64 positions, per-axis delta weights, the
+// shell index of each of their 4^D stencil cells), the shell (the sorted
+// union of all stencil cells) with, per shell cell, the list of (point,
+// stencil slot) that cover it sorted by point.  Interpolation is a gather
+// per point; spreading is a gather per shell cell over that list, so no
+// atomics are used and every sum has a fixed order.
+#include "lbm_geom.hpp"
+
+namespace lbm {
+
+// Eq. 6, one factor.
+__device__ inline double phi4(double r) {
+  r = fabs(r);
+  if (r >= 2.0) return 0.0;
+  if (r >= 1.0) return 0.125 * (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r));
+  return 0.125 * (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r));
+}
+
+struct IbmArgs {
+  Box3 b;
+  uint32_t N;
+  FastDiv fx, fy;
+  uint64_t stride;
+  int64_t nlag, nshell;
+  const double *X, *dV;
+  const int32_t *sid;
+  double *Ud;            // [nlag][3]
+  const int32_t *base;   // [nlag][3] floor(X) - 1
+  double *wts;           // [nlag][12] per-axis weights
+  const uint32_t *idx;   // [nlag][64] shell index of each stencil slot
+  double *Fsum;          // [nlag][3] FP64 total boundary force of the step
+  void *Fk;              // [nlag][3] compute type, force of the current iteration
+  const uint32_t *shell_cell, *rowptr, *ent;
+  void *ushell, *fshell; // [3][nshell] compute type
+  void *fibm;            // [3][stride] compute type
+  uint8_t *flags;
+  const DevSolid *solids;
+  double g[3];
+  int64_t t;
+};
+
+// setup: delta weights and desired velocity U^d = U + Omega x (X - Y)
+__global__ void k_ibm_weights(IbmArgs a) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= a.nlag) return;
+  for (int ax = 0; ax < 3; ax++)
+    for (int k = 0; k < 4; k++)
+      a.wts[l * 12 + ax * 4 + k] = (ax == 2 && a.b.D == 2) ? (k == 0 ? 1.0 : 0.0)
+                                                           : phi4((double)(a.base[l * 3 + ax] + k) - a.X[l * 3 + ax]);
+  const DevSolid &s = a.solids[a.sid[l]];
+  double c[3], r[3], ud[3];
+  solid_centre(s, a.t, a.b, c);
+  lever_arm(s, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
+  wall_vel(s, r, ud);
+  if (a.b.D == 2) ud[2] = 0.0;
+  for (int k = 0; k < 3; k++) a.Ud[l * 3 + k] = ud[k];
+}
+__global__ void k_ibm_mark(IbmArgs a) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.nshell) return;
+  const uint32_t n = a.shell_cell[s];
+  a.flags[n] = (uint8_t)(a.flags[n] | F_IBM);
+}
+
+// u0 = (j + g/2)/rho at every shell cell from the populations f(t), gathered
+// from the shifted state (A_i(x - e_i)); clears the spread force.
+template <int Q, typename S>
+__global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
+  using C = typename Store<S>::C;
+  using L = Lat<Q>;
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.nshell) return;
+  const uint32_t n = a.shell_cell[s];
+  const uint32_t yz = fdiv(n, a.fx);
+  const int x = (int)(n - yz * (uint32_t)a.b.nx);
+  const int z = (int)fdiv(yz, a.fy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)a.b.ny);
+  C drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const uint32_t src = (uint32_t)wrapi(x - L::ex(i), a.b.nx) +
+                         (uint32_t)a.b.nx * ((uint32_t)wrapi(y - L::ey(i), a.b.ny) +
+                                             (uint32_t)a.b.ny * (uint32_t)wrapi(z - L::ez(i), a.b.nz));
+    const C h = Store<S>::ld(A + (uint64_t)i * a.stride + src);
+    drho += h;
+    j[0] += C(L::ex(i)) * h;
+    j[1] += C(L::ey(i)) * h;
+    j[2] += C(L::ez(i)) * h;
+  }
+  const C rho = C(1) + drho;
+  const bool body = !(a.flags[n] & F_NOBODY);
+  C *u = static_cast<C *>(a.ushell);
+  C *f = static_cast<C *>(a.fshell);
+  for (int k = 0; k < 3; k++) {
+    u[k * a.nshell + s] = (j[k] + C(0.5) * (body ? (C)a.g[k] : C(0))) / rho;
+    f[k * a.nshell + s] = C(0);
+  }
+}
+
+// Eq. 5 and Eq. 7: interpolate u to the point, F = rho0 (U^d - U~)/dt.
+template <typename C>
+__global__ void k_ibm_interp(IbmArgs a, int first) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= a.nlag) return;
+  const C *u = static_cast<const C *>(a.ushell);
+  const double *w = a.wts + l * 12;
+  const uint32_t *ix = a.idx + l * 64;
+  const int nz = a.b.D == 2 ? 1 : 4;
+  C s[3] = {0, 0, 0};
+  for (int kz = 0; kz < nz; kz++)
+    for (int ky = 0; ky < 4; ky++)
+      for (int kx = 0; kx < 4; kx++) {
+        const int slot = kz * 16 + ky * 4 + kx;
+        const C wt = (C)((w[kx] * w[4 + ky]) * w[8 + kz]);
+        const uint32_t si = ix[slot];
+        s[0] += u[si] * wt;
+        s[1] += u[a.nshell + si] * wt;
+        s[2] += u[2 * a.nshell + si] * wt;
+      }
+  C *Fk = static_cast<C *>(a.Fk);
+  for (int k = 0; k < 3; k++) {
+    const C F = (C)a.Ud[l * 3 + k] - s[k];
+    Fk[l * 3 + k] = F;
+    a.Fsum[l * 3 + k] = (first ? 0.0 : a.Fsum[l * 3 + k]) + (double)F;
+  }
+}
+
+// Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.
+template <typename C>
+__global__ void k_ibm_spread(IbmArgs a, int last) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.nshell) return;
+  const C *Fk = static_cast<const C *>(a.Fk);
+  C f[3] = {0, 0, 0};
+  for (uint32_t e = a.rowptr[s]; e < a.rowptr[s + 1]; e++) {
+    const uint32_t v = a.ent[e];
+    const uint32_t l = v >> 6, slot = v & 63u;
+    const double *w = a.wts + (uint64_t)l * 12;
+    const C wt = (C)((w[slot & 3u] * w[4 + ((slot >> 2) & 3u)]) * w[8 + (slot >> 4)]);
+    const C dv = (C)a.dV[l];
+    for (int k = 0; k < 3; k++) f[k] += Fk[(uint64_t)l * 3 + k] * wt * dv;
+  }
+  C *u = static_cast<C *>(a.ushell);
+  C *fs = static_cast<C *>(a.fshell);
+  for (int k = 0; k < 3; k++) {
+    u[k * a.nshell + s] += f[k];
+    fs[k * a.nshell + s] += f[k];
+  }
+  if (last) {
+    C *fb = static_cast<C *>(a.fibm);
+    const uint32_t n = a.shell_cell[s];
+    for (int k = 0; k < 3; k++) fb[k * a.stride + n] = fs[k * a.nshell + s];
+  }
+}
+
+// Force -sum F_l dV_l and torque -sum (X_l - Y) x F_l dV_l on each solid.
+__global__ void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
+  __shared__ double lds[16];
+  const int s = blockIdx.x;
+  const DevSolid &sd = a.solids[s];
+  double c[3];
+  solid_centre(sd, a.t, a.b, c);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t l = start[s] + threadIdx.x; l < start[s] + count[s]; l += blockDim.x) {
+    double r[3], F[3];
+    lever_arm(sd, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
+    for (int k = 0; k < 3; k++) F[k] = -a.Fsum[l * 3 + k] * a.dV[l];
+    acc[0] += F[0];
+    acc[1] += F[1];
+    acc[2] += F[2];
+    acc[3] += r[1] * F[2] - r[2] * F[1];
+    acc[4] += r[2] * F[0] - r[0] * F[2];
+    acc[5] += r[0] * F[1] - r[1] * F[0];
+  }
+  for (int k = 0; k < 6; k++) {
+    const double tot = block_sum(acc[k], lds);
+    if (threadIdx.x == 0) hist[(uint64_t)s * 6 + k] = tot;
+  }
+}
+
+static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
+  IbmArgs a{};
+  a.b = Box3{c->p.nx, c->p.ny, c->p.nz, c->D};
+  a.N = (uint32_t)c->N;
+  a.fx = c->fx;
+  a.fy = c->fy;
+  a.stride = c->L.stride;
+  a.nlag = c->nlag;
+  a.nshell = c->nshell;
+  a.X = c->at<double>(c->L.lag_X);
+  a.dV = c->at<double>(c->L.lag_dV);
+  a.sid = c->at<int32_t>(c->L.lag_sid);
+  a.Ud = c->at<double>(c->L.lag_Ud);
+  a.base = c->at<int32_t>(c->L.lag_base);
+  a.wts = c->at<double>(c->L.lag_w);
+  a.idx = c->at<uint32_t>(c->L.lag_idx);
+  a.Fsum = c->at<double>(c->L.lag_Fsum);
+  a.Fk = c->ws + c->L.lag_Fk;
+  a.shell_cell = c->at<uint32_t>(c->L.shell_cell);
+  a.rowptr = c->at<uint32_t>(c->L.shell_rowptr);
+  a.ent = c->at<uint32_t>(c->L.shell_ent);
+  a.ushell = c->ws + c->L.shell_u;
+  a.fshell = c->ws + c->L.shell_f;
+  a.fibm = c->ws + c->L.fibm;
+  a.flags = c->at<uint8_t>(c->L.flags);
+  a.solids = c->at<DevSolid>(c->L.solids);
+  for (int k = 0; k < 3; k++) a.g[k] = c->p.body_force[k];
+  a.t = t;
+  return a;
+}
+
+void launch_ibm_setup(lbm_ctx *c) {
+  if (c->nlag <= 0) return;
+  IbmArgs a = ibm_args(c, c->t);
+  hipLaunchKernelGGL(k_ibm_weights, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+  hipLaunchKernelGGL(k_ibm_mark, dim3((uint32_t)((c->nshell + 255) / 256)), dim3(256), 0, c->stream, a);
+}
+
+template <typename S>
+static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t) {
+  using C = typename Store<S>::C;
+  IbmArgs a = ibm_args(c, t);
+  const dim3 gs((uint32_t)((c->nshell + 127) / 128)), gl((uint32_t)((c->nlag + 127) / 128));
+  if (c->Q == 9)
+    hipLaunchKernelGGL((k_ibm_u0<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
+  else
+    hipLaunchKernelGGL((k_ibm_u0<19, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
+  for (int it = 0; it < c->n_iter; it++) {
+    hipLaunchKernelGGL(k_ibm_interp<C>, gl, dim3(128), 0, c->stream, a, it == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_ibm_spread<C>, gs, dim3(128), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
+  }
+  double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
+  hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(256), 0, c->stream, a,
+                     c->at<int64_t>(c->L.misc + 64), c->at<int64_t>(c->L.misc + 64 + 8 * c->L.max_solids), hist);
+}
+
+void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t) {
+  if (c->nlag <= 0 || c->n_iter <= 0) return;
+  if (c->p.storage == LBM_F64) ibm_step_t<double>(c, A, t);
+  else if (c->p.storage == LBM_F32_DEV) ibm_step_t<float>(c, A, t);
+  else ibm_step_t<_Float16>(c, A, t);
+}
+
+}  // namespace lbm

@@ -1,0 +1,506 @@
+// kernels_sweep.hip -- the fused pull stream-collide sweep and the per-cell
+// helper kernels (state encode/decode, macroscopic fields, watchdog, copy).
+//
+// One thread owns one cell.  It gathers f_i(x, t+1) = f*_i(x - e_i, t) from
+// the source array (pull streaming; the slots of solid nodes that fluid
+// nodes pull from hold the bounce-back values written beforehand), relaxes
+// them (Eq. 1 or Eq. 3 with the second-order body-force term of Sec. 2.1)
+// and writes the post-collision values of its own cell to the destination
+// array.  Storage is the deviation h_i = f_i - w_i (FP64, FP32 or FP16),
+// arithmetic is FP64 for FP64 storage and FP32 otherwise.  Arrays are SoA,
+// [Q][stride], x fastest, so each of the 2Q streams is coalesced.
+#include "lbm_geom.hpp"
+
+namespace lbm {
+
+enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
+
+struct SweepArgs {
+  uint32_t N, nx, ny, nz;
+  FastDiv fx, fy;
+  uint64_t stride;
+  const uint8_t *flags;
+  const void *fibm;  // [3][stride] compute type, read where F_IBM is set
+  double g[3];
+  double omega;          // BGK
+  double sp, sm;         // two-rate MRT: even and odd non-conserved rates
+  double sA[kMaxQ];      // general MRT: -s_k / |M_k|^2
+  double sB[kMaxQ];      //              (1 - s_k/2) / |M_k|^2
+};
+
+template <int Q, int COLL, typename S, int FLAGS>
+__global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
+  using C = typename Store<S>::C;
+  using L = Lat<Q>;
+  const uint32_t n = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (n >= a.N) return;
+  uint8_t fl = 0;
+  if (FLAGS) {
+    fl = a.flags[n];
+    if (fl & F_SOLID) return;
+  }
+  const uint32_t yz = fdiv(n, a.fx);
+  const uint32_t x = n - yz * a.nx;
+  const uint32_t z = (Q == 9) ? 0u : fdiv(yz, a.fy);
+  const uint32_t y = yz - z * a.ny;
+  const uint32_t xm = x == 0 ? a.nx - 1 : x - 1, xp = x + 1 == a.nx ? 0 : x + 1;
+  const uint32_t ym = y == 0 ? a.ny - 1 : y - 1, yp = y + 1 == a.ny ? 0 : y + 1;
+  const uint32_t zm = z == 0 ? a.nz - 1 : z - 1, zp = z + 1 == a.nz ? 0 : z + 1;
+
+  // pull: population i arrives from x - e_i
+  C h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const uint32_t sx = L::ex(i) > 0 ? xm : (L::ex(i) < 0 ? xp : x);
+    const uint32_t sy = L::ey(i) > 0 ? ym : (L::ey(i) < 0 ? yp : y);
+    const uint32_t sz = L::ez(i) > 0 ? zm : (L::ez(i) < 0 ? zp : z);
+    const uint32_t src = sx + a.nx * (sy + a.ny * sz);
+    h[i] = Store<S>::ld(A + (uint64_t)i * a.stride + src);
+  }
+
+  // moments of the deviation: rho = 1 + drho, j = sum h e (sum w e = 0)
+  C drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    drho += h[i];
+    if (L::ex(i)) jx += L::ex(i) > 0 ? h[i] : -h[i];
+    if (L::ey(i)) jy += L::ey(i) > 0 ? h[i] : -h[i];
+    if (L::ez(i)) jz += L::ez(i) > 0 ? h[i] : -h[i];
+  }
+  const C rho = C(1) + drho;
+  C Fx = 0, Fy = 0, Fz = 0;
+  if (!FLAGS || !(fl & F_NOBODY)) {
+    Fx = (C)a.g[0];
+    Fy = (C)a.g[1];
+    Fz = (C)a.g[2];
+  }
+  if (FLAGS && (fl & F_IBM)) {
+    const C *fb = reinterpret_cast<const C *>(a.fibm);
+    Fx += fb[n];
+    Fy += fb[a.stride + n];
+    if (Q == 19) Fz += fb[2 * a.stride + n];
+  }
+  const C inv = C(1) / rho;
+  const C ux = (jx + C(0.5) * Fx) * inv, uy = (jy + C(0.5) * Fy) * inv, uz = (jz + C(0.5) * Fz) * inv;
+  const C uu = ux * ux + uy * uy + uz * uz;
+  const C uF = ux * Fx + uy * Fy + uz * Fz;
+
+  // non-equilibrium part and Guo's forcing term per direction
+  C fneq[Q], Fh[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+    const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
+    const C w = (C)wgt<Q>(i);
+    const C heq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+    fneq[i] = h[i] - heq;
+    Fh[i] = w * (C(3) * (eF - uF) + C(9) * eu * eF);
+  }
+
+  if (COLL == COLL_BGK) {
+    const C om = (C)a.omega, kf = C(1) - C(0.5) * om;
+#pragma unroll
+    for (int i = 0; i < Q; i++) h[i] += -om * fneq[i] + kf * Fh[i];
+  } else if (COLL == COLL_TRT) {
+    // Eq. 3 with one rate on every even and one on every odd moment: M^-1 S M
+    // acts as sp on the symmetric and sm on the antisymmetric part.
+    const C sp = (C)a.sp, sm = (C)a.sm, kp = C(1) - C(0.5) * sp, km = C(1) - C(0.5) * sm;
+    h[0] += -sp * fneq[0] + kp * Fh[0];
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const C p = C(0.5) * (fneq[i] + fneq[i + 1]), m = C(0.5) * (fneq[i] - fneq[i + 1]);
+      const C Fp = C(0.5) * (Fh[i] + Fh[i + 1]), Fm = C(0.5) * (Fh[i] - Fh[i + 1]);
+      const C dp = -sp * p + kp * Fp, dm = -sm * m + km * Fm;
+      h[i] += dp + dm;
+      h[i + 1] += dp - dm;
+    }
+  } else {
+    // general diagonal S: dm_k = -s_k (m - m_eq)_k + (1 - s_k/2) (M F)_k,
+    // conserved rows: density 0, momentum F; then h += M^-1 dm.
+    C dmn[Q];
+#pragma unroll
+    for (int k = 0; k < Q; k++) {
+      if (conserved<Q>(k)) {
+        const C invn = C(1.0 / mnorm<Q>(k));
+        dmn[k] = k == 0 ? C(0) : (k == 3 ? Fx : (k == 5 ? Fy : Fz)) * invn;
+      } else {
+        C mn = 0, mf = 0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          if (mrow<Q>(k, i) != 0) {
+            mn += C(mrow<Q>(k, i)) * fneq[i];
+            mf += C(mrow<Q>(k, i)) * Fh[i];
+          }
+        }
+        dmn[k] = (C)a.sA[k] * mn + (C)a.sB[k] * mf;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      C s = 0;
+#pragma unroll
+      for (int k = 0; k < Q; k++)
+        if (mrow<Q>(k, i) != 0) s += C(mrow<Q>(k, i)) * dmn[k];
+      h[i] += s;
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < Q; i++) Store<S>::st(B + (uint64_t)i * a.stride + n, h[i]);
+}
+
+template <typename S>
+static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags) {
+  const uint32_t grid = (uint32_t)((c->N + kBlock - 1) / kBlock);
+  const S *As = static_cast<const S *>(A);
+  S *Bs = static_cast<S *>(B);
+#define LBM_SWEEP(QQ, CC, FF) \
+  hipLaunchKernelGGL((k_sweep<QQ, CC, S, FF>), dim3(grid), dim3(kBlock), 0, c->stream, As, Bs, a)
+#define LBM_SWEEP2(QQ, CC) \
+  do {                     \
+    if (flags)             \
+      LBM_SWEEP(QQ, CC, 1); \
+    else                   \
+      LBM_SWEEP(QQ, CC, 0); \
+  } while (0)
+  if (c->Q == 9) {
+    if (coll == COLL_BGK) LBM_SWEEP2(9, COLL_BGK);
+    else if (coll == COLL_TRT) LBM_SWEEP2(9, COLL_TRT);
+    else LBM_SWEEP2(9, COLL_MRT);
+  } else {
+    if (coll == COLL_BGK) LBM_SWEEP2(19, COLL_BGK);
+    else if (coll == COLL_TRT) LBM_SWEEP2(19, COLL_TRT);
+    else LBM_SWEEP2(19, COLL_MRT);
+  }
+#undef LBM_SWEEP2
+#undef LBM_SWEEP
+}
+
+// Two-rate test: every even non-conserved row shares one rate, every odd
+// non-conserved row another.
+static bool two_rate(const lbm_ctx *c, double *sp, double *sm) {
+  int se = -1, so = -1;
+  for (int k = 0; k < c->Q; k++) {
+    const bool cons = c->Q == 9 ? conserved<9>(k) : conserved<19>(k);
+    if (cons) continue;
+    const bool odd = c->Q == 9 ? odd_row<9>(k) : odd_row<19>(k);
+    int &ref = odd ? so : se;
+    if (ref < 0) ref = k;
+    else if (c->rates[ref] != c->rates[k]) return false;
+  }
+  *sp = c->rates[se];
+  *sm = c->rates[so];
+  return true;
+}
+
+template <int Q>
+static void mrt_coeffs(const lbm_ctx *c, SweepArgs &a) {
+  for (int k = 0; k < Q; k++) {
+    const double n = (double)mnorm<Q>(k);
+    a.sA[k] = -c->rates[k] / n;
+    a.sB[k] = (1.0 - 0.5 * c->rates[k]) / n;
+  }
+}
+
+void launch_sweep(lbm_ctx *c, const void *A, void *B) {
+  SweepArgs a{};
+  a.N = (uint32_t)c->N;
+  a.nx = (uint32_t)c->p.nx;
+  a.ny = (uint32_t)c->p.ny;
+  a.nz = (uint32_t)c->p.nz;
+  a.fx = c->fx;
+  a.fy = c->fy;
+  a.stride = c->L.stride;
+  a.flags = c->at<uint8_t>(c->L.flags);
+  a.fibm = c->ws + c->L.fibm;
+  for (int k = 0; k < 3; k++) a.g[k] = c->p.body_force[k];
+  int coll;
+  if (c->p.collision == LBM_BGK) {
+    coll = COLL_BGK;
+    a.omega = 1.0 / c->p.tau;
+  } else if (two_rate(c, &a.sp, &a.sm)) {
+    coll = COLL_TRT;
+  } else {
+    coll = COLL_MRT;
+    if (c->Q == 9) mrt_coeffs<9>(c, a);
+    else mrt_coeffs<19>(c, a);
+  }
+  const bool flags = c->nsolid > 0;
+  if (c->p.storage == LBM_F64) sweep_dispatch<double>(c, A, B, a, coll, flags);
+  else if (c->p.storage == LBM_F32_DEV) sweep_dispatch<float>(c, A, B, a, coll, flags);
+  else sweep_dispatch<_Float16>(c, A, B, a, coll, flags);
+}
+
+// ----------------------------------------------------------------------------
+// state encode / decode (host-visible populations are f_i(x) before the next
+// collision; the device keeps them shifted by e_i, A_i(y) = h_i(y + e_i))
+// ----------------------------------------------------------------------------
+struct CellArgs {
+  uint32_t N, nx, ny, nz;
+  FastDiv fx, fy;
+  uint64_t stride;
+};
+
+__device__ inline void cell_xyz(uint32_t n, const CellArgs &a, int &x, int &y, int &z) {
+  const uint32_t yz = fdiv(n, a.fx);
+  x = (int)(n - yz * a.nx);
+  z = (int)fdiv(yz, a.fy);
+  y = (int)(yz - (uint32_t)z * a.ny);
+}
+__device__ inline uint32_t cell_id(int x, int y, int z, const CellArgs &a) {
+  return (uint32_t)wrapi(x, a.nx) + a.nx * ((uint32_t)wrapi(y, a.ny) + a.ny * (uint32_t)wrapi(z, a.nz));
+}
+
+template <typename S>
+__global__ void k_encode(const double *__restrict__ f, S *__restrict__ Ai, int ex, int ey, int ez, double w,
+                         CellArgs a) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  cell_xyz(n, a, x, y, z);
+  Store<S>::st(Ai + n, (typename Store<S>::C)(f[cell_id(x + ex, y + ey, z + ez, a)] - w));
+}
+template <typename S>
+__global__ void k_shift_raw(const S *__restrict__ src, S *__restrict__ Ai, int ex, int ey, int ez, CellArgs a) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  cell_xyz(n, a, x, y, z);
+  Ai[n] = src[cell_id(x + ex, y + ey, z + ez, a)];
+}
+template <typename S>
+__global__ void k_decode(const S *__restrict__ Ai, double *__restrict__ f, int ex, int ey, int ez, double w,
+                         const uint8_t *flags, CellArgs a) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  cell_xyz(n, a, x, y, z);
+  const bool solid = flags && (flags[n] & F_SOLID);
+  f[n] = solid ? 0.0 : w + (double)Store<S>::ld(Ai + cell_id(x - ex, y - ey, z - ez, a));
+}
+template <typename S>
+__global__ void k_gather_raw(const S *__restrict__ Ai, S *__restrict__ dst, int ex, int ey, int ez, CellArgs a) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  cell_xyz(n, a, x, y, z);
+  dst[n] = Ai[cell_id(x - ex, y - ey, z - ez, a)];
+}
+
+static CellArgs cell_args(const lbm_ctx *c) {
+  CellArgs a{};
+  a.N = (uint32_t)c->N;
+  a.nx = (uint32_t)c->p.nx;
+  a.ny = (uint32_t)c->p.ny;
+  a.nz = (uint32_t)c->p.nz;
+  a.fx = c->fx;
+  a.fy = c->fy;
+  a.stride = c->L.stride;
+  return a;
+}
+
+static void dir_vec(int Q, int i, int &ex, int &ey, int &ez, double &w) {
+  if (Q == 9) {
+    ex = Lat<9>::ex(i);
+    ey = Lat<9>::ey(i);
+    ez = 0;
+    w = wgt<9>(i);
+  } else {
+    ex = Lat<19>::ex(i);
+    ey = Lat<19>::ey(i);
+    ez = Lat<19>::ez(i);
+    w = wgt<19>(i);
+  }
+}
+
+template <typename S>
+static void encode_t(lbm_ctx *c, int dir, const double *src, void *A, bool raw) {
+  CellArgs a = cell_args(c);
+  int ex, ey, ez;
+  double w;
+  dir_vec(c->Q, dir, ex, ey, ez, w);
+  S *Ai = static_cast<S *>(A) + (uint64_t)dir * c->L.stride;
+  const uint32_t grid = (uint32_t)((c->N + 255) / 256);
+  if (raw)
+    hipLaunchKernelGGL(k_shift_raw<S>, dim3(grid), dim3(256), 0, c->stream, reinterpret_cast<const S *>(src), Ai,
+                       ex, ey, ez, a);
+  else
+    hipLaunchKernelGGL(k_encode<S>, dim3(grid), dim3(256), 0, c->stream, src, Ai, ex, ey, ez, w, a);
+}
+template <typename S>
+static void decode_t(lbm_ctx *c, int dir, const void *A, double *dst, bool raw) {
+  CellArgs a = cell_args(c);
+  int ex, ey, ez;
+  double w;
+  dir_vec(c->Q, dir, ex, ey, ez, w);
+  const S *Ai = static_cast<const S *>(A) + (uint64_t)dir * c->L.stride;
+  const uint32_t grid = (uint32_t)((c->N + 255) / 256);
+  const uint8_t *fl = c->nsolid > 0 ? c->at<uint8_t>(c->L.flags) : nullptr;
+  if (raw)
+    hipLaunchKernelGGL(k_gather_raw<S>, dim3(grid), dim3(256), 0, c->stream, Ai, reinterpret_cast<S *>(dst), ex,
+                       ey, ez, a);
+  else
+    hipLaunchKernelGGL(k_decode<S>, dim3(grid), dim3(256), 0, c->stream, Ai, dst, ex, ey, ez, w, fl, a);
+}
+
+void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw) {
+  if (c->p.storage == LBM_F64) encode_t<double>(c, dir, src, A, raw);
+  else if (c->p.storage == LBM_F32_DEV) encode_t<float>(c, dir, src, A, raw);
+  else encode_t<_Float16>(c, dir, src, A, raw);
+}
+void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw) {
+  if (c->p.storage == LBM_F64) decode_t<double>(c, dir, A, dst, raw);
+  else if (c->p.storage == LBM_F32_DEV) decode_t<float>(c, dir, A, dst, raw);
+  else decode_t<_Float16>(c, dir, A, dst, raw);
+}
+
+// ----------------------------------------------------------------------------
+// macroscopic fields
+// ----------------------------------------------------------------------------
+struct MacroArgs {
+  CellArgs ca;
+  const uint8_t *flags;
+  const uint16_t *owner;
+  const DevSolid *solids;
+  const void *fibm;
+  double g[3];
+  int64_t t_geom;
+  int D;
+  int initial;
+  int nsolid;
+  uint8_t solid_bit;
+};
+
+// initial: src holds the shifted pre-collision state, u = j / rho.
+// otherwise: src holds post-collision values of the last collision, whose
+// momentum is j + F, so u = (j + F/2)/rho = (j* - F/2)/rho.
+template <int Q, typename S>
+__global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, MacroArgs m) {
+  using L = Lat<Q>;
+  const CellArgs &a = m.ca;
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  int x, y, z;
+  cell_xyz(n, a, x, y, z);
+  const uint8_t fl = m.flags ? m.flags[n] : 0;
+  const bool solid = fl & m.solid_bit;
+  if (solid && m.owner[n] < m.nsolid) {
+    const DevSolid &s = m.solids[m.owner[n]];
+    Box3 b{(int)a.nx, (int)a.ny, (int)a.nz, m.D};
+    double c[3], r[3], uw[3];
+    solid_centre(s, m.t_geom, b, c);
+    lever_arm(s, c, (double)x, (double)y, (double)z, b, r);
+    wall_vel(s, r, uw);
+    out[n] = 0.0;
+    out[a.N + n] = uw[0];
+    out[2ull * a.N + n] = uw[1];
+    out[3ull * a.N + n] = uw[2];
+    return;
+  }
+  double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const uint32_t sn = m.initial ? cell_id(x - L::ex(i), y - L::ey(i), z - L::ez(i), a) : n;
+    const double h = (double)Store<S>::ld(src + (uint64_t)i * a.stride + sn);
+    drho += h;
+    jx += L::ex(i) * h;
+    jy += L::ey(i) * h;
+    jz += L::ez(i) * h;
+  }
+  const double rho = 1.0 + drho;
+  double F[3] = {0.0, 0.0, 0.0};
+  if (!m.initial) {
+    if (!(fl & F_NOBODY))
+      for (int k = 0; k < 3; k++) F[k] = m.g[k];
+    if (fl & F_IBM) {
+      using C = typename Store<S>::C;
+      const C *fb = reinterpret_cast<const C *>(m.fibm);
+      for (int k = 0; k < m.D; k++) F[k] += (double)fb[k * a.stride + n];
+    }
+  }
+  out[n] = rho;
+  out[a.N + n] = (jx - 0.5 * F[0]) / rho;
+  out[2ull * a.N + n] = (jy - 0.5 * F[1]) / rho;
+  out[3ull * a.N + n] = (jz - 0.5 * F[2]) / rho;
+}
+
+// mode 0: before any step (src = shifted pre-collision state); mode 1: after
+// a step, geometry of that step's collision; mode 2: inside a step, right after
+// the collision and before solids move (current geometry).
+void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
+  MacroArgs m{};
+  m.ca = cell_args(c);
+  m.flags = c->nsolid > 0 ? c->at<uint8_t>(c->L.flags) : nullptr;
+  const bool prev = mode == 1 && c->any_moving;
+  m.owner = c->at<uint16_t>(prev ? c->L.owner1 : c->L.owner0);
+  m.solid_bit = prev ? F_WAS_SOLID : F_SOLID;
+  m.solids = c->at<DevSolid>(c->L.solids);
+  m.fibm = c->ws + c->L.fibm;
+  for (int k = 0; k < 3; k++) m.g[k] = c->p.body_force[k];
+  m.t_geom = mode == 1 ? c->t - 1 : c->t;
+  m.D = c->D;
+  m.initial = mode == 0 ? 1 : 0;
+  m.nsolid = c->nsolid;
+  const uint32_t grid = (uint32_t)((c->N + 255) / 256);
+#define LBM_MAC(QQ, SS) \
+  hipLaunchKernelGGL((k_macros<QQ, SS>), dim3(grid), dim3(256), 0, c->stream, static_cast<const SS *>(src), out, m)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_MAC(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_MAC(9, float);
+    else LBM_MAC(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_MAC(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_MAC(19, float);
+    else LBM_MAC(19, _Float16);
+  }
+#undef LBM_MAC
+}
+
+// ----------------------------------------------------------------------------
+// zero fill, finiteness watchdog, copy probe
+// ----------------------------------------------------------------------------
+__global__ void k_zero(uint4 *p, uint64_t n16) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+void launch_fill_zero(lbm_ctx *c, void *A) {
+  const uint64_t bytes = (uint64_t)c->Q * c->L.stride * c->store_bytes;
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, c->stream, static_cast<uint4 *>(A), bytes / 16);
+}
+
+template <typename S>
+__global__ void k_finite(const S *__restrict__ A, uint64_t count, uint32_t *flag) {
+  using C = typename Store<S>::C;
+  bool bad = false;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x) {
+    const C v = (C)A[i];
+    bad |= !(v - v == C(0));
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+int launch_check_finite(lbm_ctx *c, const void *A, uint32_t *flag) {
+  (void)hipMemsetAsync(flag, 0, sizeof(uint32_t), c->stream);
+  const uint64_t count = (uint64_t)c->Q * c->L.stride;
+  if (c->p.storage == LBM_F64)
+    hipLaunchKernelGGL(k_finite<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double *>(A), count,
+                       flag);
+  else if (c->p.storage == LBM_F32_DEV)
+    hipLaunchKernelGGL(k_finite<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float *>(A), count,
+                       flag);
+  else
+    hipLaunchKernelGGL(k_finite<_Float16>, dim3(1024), dim3(256), 0, c->stream, static_cast<const _Float16 *>(A),
+                       count, flag);
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ s, uint4 *__restrict__ d, uint64_t n16) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n16) d[i] = s[i];
+}
+void launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const uint64_t n16 = bytes / 16;
+  hipLaunchKernelGGL(k_copy, dim3((uint32_t)((n16 + 255) / 256)), dim3(256), 0, s, static_cast<const uint4 *>(src),
+                     static_cast<uint4 *>(dst), n16);
+}
+
+}  // namespace lbm

@@ -1,0 +1,117 @@
+// lbm_internal.hpp -- context layout and kernel launchers shared by the
+// library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int kMaxQ = 19;
+constexpr int kHistCap = 8192;  // steps of force/torque history kept on the device
+constexpr int kBlock = 256;     // threads per block for per-cell / per-link kernels
+
+// Solid as the kernels see it.
+struct DevSolid {
+  int32_t kind, inverted, ax, sgn, moving;
+  int32_t full[3];   // box spans the whole axis
+  int32_t ext[3];    // box extent per axis
+  int32_t box0[3];   // box origin of a fixed solid
+  uint32_t box_cells;
+  double c0[3], R, U[3], W[3];
+};
+
+// Where one solid's links sit in the link arrays, and its chunk partials.
+struct SolidLinks {
+  uint32_t start, count, chunk_base, nchunks;
+};
+
+// Regions carved out of the caller's workspace (byte offsets).
+struct Layout {
+  size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
+      partials, solids, hist, staging, macro, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
+      lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, misc, total;
+  size_t stride;  // elements per direction (N rounded up to a multiple of 64)
+  int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials;
+  int32_t max_solids;
+};
+
+bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lag, Layout *L);
+
+}  // namespace lbm
+
+// The opaque context.
+struct lbm_ctx {
+  lbm_params p;
+  double rates[lbm::kMaxQ];
+  bool default_rates;
+  int Q, D;
+  int64_t N;
+  int store_bytes;
+  hipStream_t stream;
+  char *ws;
+  size_t ws_bytes;
+  lbm::Layout L;
+  lbm::FastDiv fx, fy;
+  // state
+  int cur;  // which of A/B holds the current state (0 = A)
+  int64_t t;
+  bool fresh;  // no step since create / set_f / set_state
+  // solids
+  int method;
+  int nsolid;
+  bool any_moving;
+  std::vector<lbm_solid> solids;
+  std::vector<lbm::DevSolid> dsolids;
+  int32_t max_box_chunks;  // per solid, for the link-builder grid
+  int32_t k5_chunks;       // grid.x of the bounce-back kernel
+  int64_t nlinks;
+  // IBM
+  int n_iter;
+  double retraction;
+  int64_t nlag;
+  int64_t nshell;
+  std::vector<int64_t> lag_start, lag_count;
+  std::vector<double> lag_X, lag_dV;
+  bool lag_user;
+  std::string err;
+  // helpers
+  void *state() const { return ws + (cur == 0 ? L.A : L.B); }
+  void *other() const { return ws + (cur == 0 ? L.B : L.A); }
+  template <typename T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+};
+
+namespace lbm {
+
+// kernels_sweep.hip
+void launch_sweep(lbm_ctx *c, const void *A, void *B);
+void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
+void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
+void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
+void launch_fill_zero(lbm_ctx *c, void *A);
+int launch_check_finite(lbm_ctx *c, const void *A, uint32_t *flag);
+void launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// kernels_boundary.hip
+void launch_classify(lbm_ctx *c, int64_t t, bool full);
+void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *Bpost);
+void launch_link_scan(lbm_ctx *c);
+void launch_link_emit(lbm_ctx *c, int64_t t);
+void launch_ibb(lbm_ctx *c, void *Bpost, int64_t t);
+void launch_ft_reduce(lbm_ctx *c, int64_t t);
+
+// kernels_ibm.hip
+void launch_ibm_setup(lbm_ctx *c);
+void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t);
+
+}  // namespace lbm

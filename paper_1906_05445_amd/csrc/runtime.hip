@@ -1,0 +1,824 @@
+// runtime.hip -- host side of liblbm.so: the C ABI of include/lbm.h.
+//
+// The context lives in a caller-owned device workspace carved into fixed
+// regions (populations A/B, node flags, solid ownership, boundary links,
+// Lagrangian data, force history, staging); the library itself never
+// allocates device memory.  Every call enqueues work on the caller's stream;
+// only the readout calls synchronise it.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int csize_of(int storage) { return storage == LBM_F64 ? 8 : 4; }
+int ssize_of(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32_DEV ? 4 : 2); }
+
+FastDiv make_div(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) s++;
+  f.s = s;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+  return f;
+}
+
+bool set_err(lbm_ctx *c, const char *msg) {
+  if (c) c->err = msg;
+  return false;
+}
+
+lbm_status hip_check(lbm_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBM_OK;
+  if (c) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return LBM_EDEVICE;
+}
+
+#define HIPCALL(expr)                                    \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_check(c, _e, #expr); \
+  } while (0)
+
+int qof(int lattice) { return lattice == LBM_D2Q9 ? 9 : 19; }
+
+bool valid_params(const lbm_params *p) {
+  if (!p) return false;
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return false;
+  if (p->collision != LBM_BGK && p->collision != LBM_MRT) return false;
+  if (p->storage < LBM_F64 || p->storage > LBM_F16_DEV) return false;
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return false;
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return false;
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N * qof(p->lattice) >= 2147483647.0) return false;  // 32-bit in-lattice offsets
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
+  for (int k = 0; k < 3; k++)
+    if (!std::isfinite(p->body_force[k])) return false;
+  return true;
+}
+
+// Default relaxation rates of the MRT collision (the paper does not print
+// S): 1/tau on every even non-conserved moment, s_odd on the odd ones with
+// (tau - 1/2)(1/s_odd - 1/2) = 3/16; conserved rows 1 (no effect).
+void default_rates(int Q, double tau, double *r) {
+  const double snu = 1.0 / tau;
+  const double sodd = 1.0 / (0.5 + (3.0 / 16.0) / (tau - 0.5));
+  for (int k = 0; k < Q; k++) {
+    const bool cons = Q == 9 ? conserved<9>(k) : conserved<19>(k);
+    const bool odd = Q == 9 ? odd_row<9>(k) : odd_row<19>(k);
+    r[k] = cons ? 1.0 : (odd ? sodd : snu);
+  }
+}
+
+}  // namespace
+
+namespace lbm {
+
+bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lag, Layout *L) {
+  if (!valid_params(p)) return false;
+  const int Q = qof(p->lattice);
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const int s = ssize_of(p->storage), cs = csize_of(p->storage);
+  if (max_solids <= 0) max_solids = 1;
+  if (max_solids > 65534) return false;
+  if (max_links <= 0) max_links = std::max<int64_t>(65536, N / 2);
+  if (max_lag < 0) return false;
+  if (max_lag == 0) max_lag = std::max<int64_t>(1024, N / 64);
+  if (max_links >= (1ll << 32) || max_lag >= (1ll << 26)) return false;
+  Layout l{};
+  l.stride = (size_t)((N + 63) / 64 * 64);
+  l.max_links = max_links;
+  l.max_lag = max_lag;
+  l.max_shell = std::min<int64_t>(N, 64 * max_lag);
+  l.max_box_chunks = (N + kBlock - 1) / kBlock;
+  l.max_partials = (max_links + kBlock - 1) / kBlock + max_solids;
+  l.max_solids = max_solids;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  l.A = take((size_t)Q * l.stride * s);
+  l.B = take((size_t)Q * l.stride * s);
+  l.flags = take((size_t)N);
+  l.owner0 = take((size_t)N * 2);
+  l.owner1 = take((size_t)N * 2);
+  l.link_cell = take((size_t)max_links * 4);
+  l.link_meta = take((size_t)max_links * 4);
+  l.link_q = take((size_t)max_links * 8);
+  l.box_counts = take((size_t)max_solids * l.max_box_chunks * 4);
+  l.box_offsets = take((size_t)max_solids * l.max_box_chunks * 4);
+  l.solid_links = take((size_t)max_solids * sizeof(SolidLinks));
+  l.partials = take((size_t)l.max_partials * 6 * 8);
+  l.solids = take((size_t)max_solids * sizeof(DevSolid));
+  l.hist = take((size_t)kHistCap * max_solids * 6 * 8);
+  l.staging = take((size_t)4 * N * 8);
+  l.macro = take((size_t)4 * N * 8);
+  l.fibm = take((size_t)3 * l.stride * cs);
+  l.lag_X = take((size_t)max_lag * 24);
+  l.lag_dV = take((size_t)max_lag * 8);
+  l.lag_sid = take((size_t)max_lag * 4);
+  l.lag_Ud = take((size_t)max_lag * 24);
+  l.lag_base = take((size_t)max_lag * 12);
+  l.lag_w = take((size_t)max_lag * 96);
+  l.lag_idx = take((size_t)max_lag * 256);
+  l.lag_Fsum = take((size_t)max_lag * 24);
+  l.lag_Fk = take((size_t)max_lag * 3 * cs);
+  l.shell_cell = take((size_t)l.max_shell * 4);
+  l.shell_rowptr = take((size_t)(l.max_shell + 1) * 4);
+  l.shell_ent = take((size_t)max_lag * 64 * 4);
+  l.shell_u = take((size_t)3 * l.max_shell * cs);
+  l.shell_f = take((size_t)3 * l.max_shell * cs);
+  l.misc = take((size_t)64 + 16 * (size_t)max_solids + 64);
+  l.total = o;
+  *L = l;
+  return true;
+}
+
+}  // namespace lbm
+
+// ----------------------------------------------------------------------------
+// Lagrangian meshes (Sec. 2.1): geodesic sphere with about one point per unit
+// area, circles and rings with spacing about 1.
+// ----------------------------------------------------------------------------
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+
+void icosphere(const double c[3], double R, std::vector<double> &X, double &dV) {
+  const double ph = (1.0 + std::sqrt(5.0)) / 2.0;
+  std::vector<V3> v;
+  for (double a : {-1.0, 1.0})
+    for (double b : {-ph, ph}) {
+      v.push_back({0.0, a, b});
+      v.push_back({a, b, 0.0});
+      v.push_back({b, 0.0, a});
+    }
+  std::sort(v.begin(), v.end(), [](const V3 &p, const V3 &q) {
+    if (p.x != q.x) return p.x < q.x;
+    if (p.y != q.y) return p.y < q.y;
+    return p.z < q.z;
+  });
+  const int nv = (int)v.size();
+  auto d2 = [&](int i, int j) {
+    const double dx = v[i].x - v[j].x, dy = v[i].y - v[j].y, dz = v[i].z - v[j].z;
+    return dx * dx + dy * dy + dz * dz;
+  };
+  std::vector<std::pair<int, int>> edges;
+  for (int i = 0; i < nv; i++)
+    for (int j = i + 1; j < nv; j++)
+      if (std::fabs(d2(i, j) - 4.0) < 1e-9) edges.push_back({i, j});
+  auto adj = [&](int i, int j) { return std::fabs(d2(i, j) - 4.0) < 1e-9; };
+  std::vector<std::array<int, 3>> faces;
+  for (auto &e : edges)
+    for (int k = e.second + 1; k < nv; k++)
+      if (adj(e.first, k) && adj(e.second, k)) faces.push_back({e.first, e.second, k});
+  const int n = std::max(1, (int)std::nearbyint(R * std::sqrt(4.0 * M_PI / 10.0)));
+  std::vector<V3> P(v.begin(), v.end());
+  for (auto &e : edges)
+    for (int k = 1; k < n; k++) {
+      const V3 &a = v[e.first], &b = v[e.second];
+      P.push_back({((n - k) * a.x + k * b.x) / n, ((n - k) * a.y + k * b.y) / n, ((n - k) * a.z + k * b.z) / n});
+    }
+  for (auto &f : faces)
+    for (int i = 1; i < n; i++)
+      for (int j = 1; j < n - i; j++) {
+        const int k = n - i - j;
+        const V3 &a = v[f[0]], &b = v[f[1]], &cc = v[f[2]];
+        P.push_back({(i * a.x + j * b.x + k * cc.x) / n, (i * a.y + j * b.y + k * cc.y) / n,
+                     (i * a.z + j * b.z + k * cc.z) / n});
+      }
+  X.clear();
+  for (auto &p : P) {
+    const double nr = std::sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+    X.push_back(c[0] + R * (p.x / nr));
+    X.push_back(c[1] + R * (p.y / nr));
+    X.push_back(c[2] + R * (p.z / nr));
+  }
+  dV = 4.0 * M_PI * R * R / (double)P.size();
+}
+
+void circle(const double c[3], double R, double z, std::vector<double> &X, double &dV) {
+  const int n = std::max(3, (int)std::nearbyint(2.0 * M_PI * R));
+  for (int l = 0; l < n; l++) {
+    const double a = 2.0 * M_PI * l / n;
+    X.push_back(c[0] + R * std::cos(a));
+    X.push_back(c[1] + R * std::sin(a));
+    X.push_back(z);
+  }
+  dV = 2.0 * M_PI * R / n;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+const char *lbm_status_string(lbm_status st) {
+  switch (st) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace or capacity too small";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_EDIVERGED: return "non-finite populations";
+    case LBM_EUNSUPPORTED: return "unsupported combination";
+    case LBM_ESTATE: return "call out of order";
+    case LBM_EAGAIN: return "admission deferred";
+    default: return "unknown status";
+  }
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t lbm_history_capacity(void) { return kHistCap; }
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian) {
+  Layout L;
+  if (!make_layout(p, max_solids, max_links, max_lagrangian, &L)) return 0;
+  return L.total;
+}
+
+lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  Layout L;
+  if (!make_layout(p, max_solids, max_links, max_lagrangian, &L)) return LBM_EINVAL;
+  if (p->collision == LBM_MRT && p->rates)
+    for (int k = 0; k < qof(p->lattice); k++)
+      if (!std::isfinite(p->rates[k]) || p->rates[k] < 0.0 || p->rates[k] >= 2.0) return LBM_EINVAL;
+  if (!dev_workspace || ws_bytes < L.total) return LBM_ENOMEM;
+  if (((uintptr_t)dev_workspace & 255) != 0) return LBM_EINVAL;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->p = *p;
+  c->p.rates = nullptr;
+  c->Q = qof(p->lattice);
+  c->D = p->lattice == LBM_D2Q9 ? 2 : 3;
+  c->N = (int64_t)p->nx * p->ny * p->nz;
+  c->store_bytes = ssize_of(p->storage);
+  c->default_rates = !(p->collision == LBM_MRT && p->rates);
+  if (c->default_rates) default_rates(c->Q, p->tau, c->rates);
+  else
+    for (int k = 0; k < c->Q; k++) c->rates[k] = p->rates[k];
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char *>(dev_workspace);
+  c->ws_bytes = ws_bytes;
+  c->L = L;
+  c->fx = make_div((uint32_t)p->nx);
+  c->fy = make_div((uint32_t)p->ny);
+  c->cur = 0;
+  c->t = 0;
+  c->method = LBM_BB;
+  c->nsolid = 0;
+  c->any_moving = false;
+  c->max_box_chunks = 0;
+  c->k5_chunks = 0;
+  c->nlinks = 0;
+  c->n_iter = 5;
+  c->retraction = 0.0;
+  c->nlag = 0;
+  c->nshell = 0;
+  c->lag_user = false;
+  c->fresh = true;
+  // rest state, cleared flags and ownership
+  hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner0, 0xFF, (size_t)c->N * 2, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner1, 0xFF, (size_t)c->N * 2, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx *c) {
+  if (!c) return LBM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return LBM_OK;
+}
+
+static lbm_status build_ibm(lbm_ctx *c);
+
+static bool coord_axis(const double a[3], int *ax, int *sg) {
+  int k = -1, cnt = 0;
+  for (int i = 0; i < 3; i++)
+    if (a[i] != 0.0) {
+      k = i;
+      cnt++;
+    }
+  if (cnt != 1 || std::fabs(a[k]) != 1.0) return false;
+  *ax = k;
+  *sg = a[k] > 0 ? 1 : -1;
+  return true;
+}
+
+static int dim_of(const lbm_ctx *c, int a) { return a == 0 ? c->p.nx : (a == 1 ? c->p.ny : c->p.nz); }
+
+lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0 || n > c->L.max_solids || (n > 0 && !s)) return set_err(c, "solid count"), LBM_EINVAL;
+  if (method < LBM_BB || method > LBM_IBM) return set_err(c, "method"), LBM_EINVAL;
+  std::vector<DevSolid> ds((size_t)std::max(n, 1));
+  bool moving = false;
+  int32_t mbc = 0;
+  for (int k = 0; k < n; k++) {
+    const lbm_solid &q = s[k];
+    DevSolid &d = ds[k];
+    std::memset(&d, 0, sizeof(d));
+    d.kind = q.kind;
+    d.inverted = q.inverted ? 1 : 0;
+    d.R = q.radius;
+    for (int a = 0; a < 3; a++) {
+      d.c0[a] = q.centre[a];
+      d.U[a] = q.velocity[a];
+      d.W[a] = q.omega[a];
+      if (!std::isfinite(q.centre[a]) || !std::isfinite(q.velocity[a]) || !std::isfinite(q.omega[a]))
+        return set_err(c, "non-finite solid data"), LBM_EINVAL;
+    }
+    if (c->D == 2) d.U[2] = 0.0;
+    if (q.kind < LBM_SPHERE || q.kind > LBM_PLANE) return set_err(c, "solid kind"), LBM_EINVAL;
+    int ax = 2, sg = 1;
+    if (q.kind != LBM_SPHERE && !coord_axis(q.axis, &ax, &sg))
+      return set_err(c, "axis must be a coordinate unit vector"), LBM_EINVAL;
+    if (c->D == 2 && q.kind == LBM_CYLINDER && ax != 2) return set_err(c, "2D cylinders lie along z"), LBM_EINVAL;
+    if (c->D == 2 && q.kind == LBM_PLANE && ax == 2) return set_err(c, "2D plane normal in the xy plane"), LBM_EINVAL;
+    d.ax = ax;
+    d.sgn = sg;
+    d.moving = (d.U[0] != 0.0 || d.U[1] != 0.0 || d.U[2] != 0.0) ? 1 : 0;
+    if (d.moving && (method == LBM_IBM || q.kind == LBM_PLANE))
+      return set_err(c, "translating solids need IBB and a sphere or cylinder"), LBM_EUNSUPPORTED;
+    if (d.moving) {
+      for (int a = 0; a < 3; a++)
+        if (std::fabs(d.U[a]) >= 1.0) return set_err(c, "solid speed must be below one cell per step"), LBM_EINVAL;
+    }
+    moving |= d.moving != 0;
+    if (q.kind != LBM_PLANE) {
+      if (!(q.radius > 0.0)) return set_err(c, "radius must be positive"), LBM_EINVAL;
+      for (int a = 0; a < c->D; a++) {
+        if (q.kind == LBM_CYLINDER && a == ax) continue;
+        if (!(q.centre[a] >= 0.0 && q.centre[a] < (double)dim_of(c, a)))
+          return set_err(c, "centre must lie inside the box"), LBM_EINVAL;
+        if (!(2.0 * q.radius < (double)dim_of(c, a))) return set_err(c, "solid wider than the box"), LBM_EINVAL;
+      }
+    }
+    // bounding box: every cell within R + 2 of the centre (planes: 2 cells each side)
+    uint64_t cells = 1;
+    for (int a = 0; a < 3; a++) {
+      const int La = dim_of(c, a);
+      int ext;
+      if (a >= c->D) ext = La;
+      else if (q.kind == LBM_PLANE) ext = (a == ax) ? 6 : La;
+      else if (q.kind == LBM_CYLINDER && a == ax) ext = La;
+      else ext = (int)std::ceil(2.0 * q.radius) + 6;
+      if (ext >= La) {
+        d.full[a] = 1;
+        d.ext[a] = La;
+        d.box0[a] = 0;
+      } else {
+        d.full[a] = 0;
+        d.ext[a] = ext;
+        const double lo = q.kind == LBM_PLANE ? q.centre[a] : q.centre[a] - q.radius;
+        d.box0[a] = (int)std::floor(lo) - 2;
+      }
+      cells *= (uint64_t)d.ext[a];
+    }
+    d.box_cells = (uint32_t)cells;
+    mbc = std::max<int32_t>(mbc, (int32_t)((cells + kBlock - 1) / kBlock));
+  }
+  // ordinary spheres / cylinders must not overlap
+  for (int a = 0; a < n; a++)
+    for (int b = a + 1; b < n; b++) {
+      if (s[a].kind == LBM_PLANE || s[b].kind == LBM_PLANE || s[a].inverted || s[b].inverted) continue;
+      if (ds[a].moving || ds[b].moving) continue;
+      double d2 = 0.0;
+      for (int k = 0; k < c->D; k++) {
+        if ((s[a].kind == LBM_CYLINDER && k == ds[a].ax) || (s[b].kind == LBM_CYLINDER && k == ds[b].ax)) continue;
+        double d = s[a].centre[k] - s[b].centre[k];
+        const double L = dim_of(c, k);
+        d -= L * std::nearbyint(d / L);
+        d2 += d * d;
+      }
+      if (std::sqrt(d2) < s[a].radius + s[b].radius) return set_err(c, "solids overlap"), LBM_EINVAL;
+    }
+  if (method == LBM_IBM)
+    for (int k = 0; k < n; k++) {
+      if (s[k].kind == LBM_PLANE) return set_err(c, "IBM needs spheres or cylinders"), LBM_EUNSUPPORTED;
+      if (c->D == 3 && s[k].kind == LBM_CYLINDER && ds[k].ax != 2)
+        return set_err(c, "IBM cylinders lie along z"), LBM_EUNSUPPORTED;
+    }
+  c->solids.assign(s, s + n);
+  c->dsolids = ds;
+  c->nsolid = n;
+  c->method = method;
+  c->any_moving = moving;
+  c->max_box_chunks = mbc;
+  c->n_iter = opts ? opts->n_iter : 5;
+  c->retraction = opts ? opts->retraction : 0.0;
+  if (c->n_iter < 0 || !std::isfinite(c->retraction)) return set_err(c, "IBM options"), LBM_EINVAL;
+  c->nlinks = 0;
+  c->k5_chunks = 0;
+  c->nlag = 0;
+  c->nshell = 0;
+  c->lag_user = false;
+  HIPCALL(hipMemcpyAsync(c->ws + c->L.solids, ds.data(), sizeof(DevSolid) * ds.size(), hipMemcpyHostToDevice,
+                         c->stream));
+  HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));
+  if (n == 0) {
+    HIPCALL(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+  }
+  launch_classify(c, c->t, true);
+  if (method != LBM_IBM) {
+    launch_link_count(c, c->t, false, nullptr);
+    launch_link_scan(c);
+    launch_link_emit(c, c->t);
+    std::vector<SolidLinks> sl((size_t)n);
+    uint32_t misc[2];
+    HIPCALL(hipMemcpyAsync(sl.data(), c->ws + c->L.solid_links, sizeof(SolidLinks) * n, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIPCALL(hipMemcpyAsync(misc, c->ws + c->L.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipStreamSynchronize(c->stream));
+    if (misc[1]) return set_err(c, "more boundary links than max_links"), LBM_ENOMEM;
+    c->nlinks = misc[0];
+    int32_t mx = 0;
+    for (auto &q : sl) mx = std::max<int32_t>(mx, (int32_t)q.nchunks);
+    // translating solids gain and lose links: leave headroom, checked after each lbm_step
+    c->k5_chunks = moving ? 2 * mx + 2 : mx;
+    return LBM_OK;
+  }
+  const lbm_status st = build_ibm(c);
+  HIPCALL(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+// Lagrangian points of every solid (generated unless given by the caller),
+// their stencils, the shell of stencil cells and its transpose.
+static lbm_status build_ibm(lbm_ctx *c) {
+  if (!c->lag_user) {
+    c->lag_X.clear();
+    c->lag_dV.clear();
+    c->lag_start.assign(c->nsolid, 0);
+    c->lag_count.assign(c->nsolid, 0);
+    std::vector<double> X;
+    for (int k = 0; k < c->nsolid; k++) {
+      const lbm_solid &q = c->solids[k];
+      const double R = q.inverted ? q.radius + c->retraction : q.radius - c->retraction;
+      if (!(R > 0.0)) return set_err(c, "retraction larger than the radius"), LBM_EINVAL;
+      X.clear();
+      double dV = 0.0;
+      if (c->D == 2) circle(q.centre, R, 0.0, X, dV);
+      else if (q.kind == LBM_CYLINDER)
+        for (int z = 0; z < c->p.nz; z++) circle(q.centre, R, (double)z, X, dV);
+      else icosphere(q.centre, R, X, dV);
+      c->lag_start[k] = (int64_t)(c->lag_X.size() / 3);
+      c->lag_count[k] = (int64_t)(X.size() / 3);
+      c->lag_X.insert(c->lag_X.end(), X.begin(), X.end());
+      c->lag_dV.insert(c->lag_dV.end(), X.size() / 3, dV);
+    }
+  }
+  const int64_t nl = (int64_t)(c->lag_X.size() / 3);
+  if (nl > c->L.max_lag) return set_err(c, "more Lagrangian points than max_lagrangian"), LBM_ENOMEM;
+  std::vector<int32_t> sid((size_t)std::max<int64_t>(nl, 1)), base((size_t)std::max<int64_t>(3 * nl, 3));
+  for (int k = 0; k < c->nsolid; k++)
+    for (int64_t l = c->lag_start[k]; l < c->lag_start[k] + c->lag_count[k]; l++) sid[l] = k;
+  const int nzs = c->D == 2 ? 1 : 4;
+  std::vector<uint32_t> cellof((size_t)std::max<int64_t>(nl * 64, 1), 0);
+  std::vector<uint32_t> all;
+  all.reserve((size_t)nl * 64);
+  for (int64_t l = 0; l < nl; l++) {
+    int b[3];
+    for (int a = 0; a < 3; a++) b[a] = (a < c->D) ? (int)std::floor(c->lag_X[3 * l + a]) - 1 : 0;
+    for (int a = 0; a < 3; a++) base[3 * l + a] = b[a];
+    for (int kz = 0; kz < nzs; kz++)
+      for (int ky = 0; ky < 4; ky++)
+        for (int kx = 0; kx < 4; kx++) {
+          auto w = [](int v, int L) { return ((v % L) + L) % L; };
+          const uint32_t cell = (uint32_t)w(b[0] + kx, c->p.nx) +
+                                (uint32_t)c->p.nx * ((uint32_t)w(b[1] + ky, c->p.ny) +
+                                                     (uint32_t)c->p.ny * (uint32_t)w(b[2] + kz, c->p.nz));
+          cellof[(size_t)l * 64 + kz * 16 + ky * 4 + kx] = cell;
+          all.push_back(cell);
+        }
+  }
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  const int64_t ns = (int64_t)all.size();
+  if (ns > c->L.max_shell) return set_err(c, "IBM shell larger than its capacity"), LBM_ENOMEM;
+  std::vector<uint32_t> idx((size_t)std::max<int64_t>(nl * 64, 1), 0), rowcnt((size_t)ns + 1, 0);
+  for (int64_t l = 0; l < nl; l++)
+    for (int slot = 0; slot < 64; slot++) {
+      const int kz = slot >> 4;
+      if (kz >= nzs) continue;
+      const uint32_t cell = cellof[(size_t)l * 64 + slot];
+      const uint32_t si = (uint32_t)(std::lower_bound(all.begin(), all.end(), cell) - all.begin());
+      idx[(size_t)l * 64 + slot] = si;
+      rowcnt[si + 1]++;
+    }
+  std::vector<uint32_t> rowptr((size_t)ns + 1, 0);
+  for (int64_t s = 0; s < ns; s++) rowptr[s + 1] = rowptr[s] + rowcnt[s + 1];
+  std::vector<uint32_t> ent((size_t)std::max<uint32_t>(rowptr[ns], 1)), fill(rowptr.begin(), rowptr.end() - 1);
+  for (int64_t l = 0; l < nl; l++)  // points in order, so each row is sorted by point
+    for (int slot = 0; slot < 64; slot++) {
+      if ((slot >> 4) >= nzs) continue;
+      const uint32_t si = idx[(size_t)l * 64 + slot];
+      ent[fill[si]++] = (uint32_t)(l << 6) | (uint32_t)slot;
+    }
+  c->nlag = nl;
+  c->nshell = ns;
+  auto up = [&](size_t off, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+  };
+  HIPCALL(up(c->L.lag_X, c->lag_X.data(), sizeof(double) * 3 * nl));
+  HIPCALL(up(c->L.lag_dV, c->lag_dV.data(), sizeof(double) * nl));
+  HIPCALL(up(c->L.lag_sid, sid.data(), sizeof(int32_t) * nl));
+  HIPCALL(up(c->L.lag_base, base.data(), sizeof(int32_t) * 3 * nl));
+  HIPCALL(up(c->L.lag_idx, idx.data(), sizeof(uint32_t) * 64 * nl));
+  HIPCALL(up(c->L.shell_cell, all.data(), sizeof(uint32_t) * ns));
+  HIPCALL(up(c->L.shell_rowptr, rowptr.data(), sizeof(uint32_t) * (ns + 1)));
+  HIPCALL(up(c->L.shell_ent, ent.data(), sizeof(uint32_t) * rowptr[ns]));
+  HIPCALL(up(c->L.misc + 64, c->lag_start.data(), sizeof(int64_t) * c->nsolid));
+  HIPCALL(up(c->L.misc + 64 + 8 * (size_t)c->L.max_solids, c->lag_count.data(), sizeof(int64_t) * c->nsolid));
+  HIPCALL(hipMemsetAsync(c->ws + c->L.fibm, 0, (size_t)3 * c->L.stride * csize_of(c->p.storage), c->stream));
+  launch_ibm_setup(c);
+  // the host vectors must outlive the copies
+  HIPCALL(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_t n, double dV) {
+  if (!c) return LBM_EINVAL;
+  if (c->method != LBM_IBM || solid < 0 || solid >= c->nsolid || n < 0 || (n > 0 && !X) || !(dV >= 0.0))
+    return set_err(c, "lbm_set_lagrangian needs an IBM solid"), LBM_EINVAL;
+  // rebuild the per-solid point lists with this solid replaced
+  std::vector<double> NX, NdV;
+  std::vector<int64_t> st(c->nsolid), ct(c->nsolid);
+  for (int k = 0; k < c->nsolid; k++) {
+    st[k] = (int64_t)(NX.size() / 3);
+    if (k == solid) {
+      for (int64_t l = 0; l < n; l++) {
+        for (int a = 0; a < 3; a++) NX.push_back(a < c->D ? X[3 * l + a] : 0.0);
+        NdV.push_back(dV);
+      }
+      ct[k] = n;
+    } else {
+      for (int64_t l = c->lag_start[k]; l < c->lag_start[k] + c->lag_count[k]; l++) {
+        for (int a = 0; a < 3; a++) NX.push_back(c->lag_X[3 * l + a]);
+        NdV.push_back(c->lag_dV[l]);
+      }
+      ct[k] = c->lag_count[k];
+    }
+  }
+  for (double v : NX)
+    if (!std::isfinite(v)) return set_err(c, "non-finite Lagrangian point"), LBM_EINVAL;
+  c->lag_X = NX;
+  c->lag_dV = NdV;
+  c->lag_start = st;
+  c->lag_count = ct;
+  c->lag_user = true;
+  HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));
+  launch_classify(c, c->t, true);
+  return build_ibm(c);
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
+  for (int64_t k = 0; k < nsteps; k++) {
+    void *A = c->state(), *B = c->other();
+    if (c->method == LBM_IBM && c->nsolid > 0) launch_ibm_step(c, A, c->t);
+    launch_sweep(c, A, B);
+    if (ibb) {
+      launch_ibb(c, B, c->t);
+      launch_ft_reduce(c, c->t);
+      if (c->any_moving) {
+        // the refill below writes into neighbours' post-collision slots: keep
+        // the macroscopic fields of this collision first (last step of the call)
+        if (k == nsteps - 1) launch_macros(c, B, c->at<double>(c->L.macro), 2);
+        launch_classify(c, c->t + 1, false);
+        launch_link_count(c, c->t + 1, true, B);
+        launch_link_scan(c);
+        launch_link_emit(c, c->t + 1);
+      }
+    }
+    c->cur ^= 1;
+    c->t++;
+    c->fresh = false;
+  }
+  HIPCALL(hipGetLastError());
+  if (ibb && c->any_moving && nsteps > 0) {
+    uint32_t misc[2];
+    std::vector<SolidLinks> sl((size_t)c->nsolid);
+    HIPCALL(hipMemcpyAsync(misc, c->ws + c->L.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipMemcpyAsync(sl.data(), c->ws + c->L.solid_links, sizeof(SolidLinks) * c->nsolid,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipStreamSynchronize(c->stream));
+    c->nlinks = misc[0];
+    if (misc[1]) return set_err(c, "more boundary links than max_links"), LBM_ENOMEM;
+    for (auto &q : sl)
+      if ((int32_t)q.nchunks > c->k5_chunks)
+        return set_err(c, "a translating solid outgrew its link headroom"), LBM_ENOMEM;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_force_history(lbm_ctx *c, int64_t first, int64_t count, double *ft) {
+  if (!c || count < 0 || (count > 0 && !ft)) return LBM_EINVAL;
+  if (first < 0 || first + count > c->t || first < c->t - kHistCap)
+    return set_err(c, "requested steps are not in the history"), LBM_EINVAL;
+  const size_t per = (size_t)c->L.max_solids * 6;
+  std::vector<double> buf(per);
+  for (int64_t k = 0; k < count; k++) {
+    const int64_t slot = (first + k) % kHistCap;
+    HIPCALL(hipMemcpyAsync(buf.data(), c->ws + c->L.hist + (size_t)slot * per * 8, per * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIPCALL(hipStreamSynchronize(c->stream));
+    std::memcpy(ft + (size_t)k * c->nsolid * 6, buf.data(), sizeof(double) * 6 * c->nsolid);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_force_torque(lbm_ctx *c, double *force, double *torque) {
+  if (!c) return LBM_EINVAL;
+  if (c->t == 0) return set_err(c, "no step taken yet"), LBM_ESTATE;
+  std::vector<double> ft((size_t)std::max(c->nsolid, 1) * 6);
+  const lbm_status st = lbm_force_history(c, c->t - 1, 1, ft.data());
+  if (st != LBM_OK) return st;
+  for (int k = 0; k < c->nsolid; k++)
+    for (int a = 0; a < 3; a++) {
+      if (force) force[3 * k + a] = ft[6 * k + a];
+      if (torque) torque[3 * k + a] = ft[6 * k + 3 + a];
+    }
+  return LBM_OK;
+}
+
+static lbm_status node_types_at(lbm_ctx *c, uint8_t *node_type, bool last_collision);
+
+lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type) {
+  if (!c) return LBM_EINVAL;
+  double *stg = c->at<double>(c->L.staging);
+  const bool ibb_moving = c->any_moving && c->method != LBM_IBM && c->nsolid > 0;
+  if (!c->fresh && ibb_moving) stg = c->at<double>(c->L.macro);  // captured inside lbm_step
+  else launch_macros(c, c->state(), stg, c->fresh ? 0 : 1);
+  HIPCALL(hipGetLastError());
+  const size_t N = (size_t)c->N;
+  if (rho) HIPCALL(hipMemcpyAsync(rho, stg, N * 8, hipMemcpyDeviceToHost, c->stream));
+  if (u) HIPCALL(hipMemcpyAsync(u, stg + N, 3 * N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  if (node_type) return node_types_at(c, node_type, !c->fresh && c->any_moving);
+  return LBM_OK;
+}
+
+// Node types of the current geometry, or of the geometry of the last
+// collision (translating solids move after the collision of each step).
+static lbm_status node_types_at(lbm_ctx *c, uint8_t *node_type, bool last_collision) {
+  const size_t N = (size_t)c->N;
+  std::vector<uint8_t> fl(N);
+  std::vector<uint16_t> own(N);
+  HIPCALL(hipMemcpyAsync(fl.data(), c->ws + c->L.flags, N, hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipMemcpyAsync(own.data(), c->ws + (last_collision ? c->L.owner1 : c->L.owner0), N * 2,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  const uint8_t bit = last_collision ? F_WAS_SOLID : F_SOLID;
+  for (size_t n = 0; n < N; n++) node_type[n] = (fl[n] & bit) ? 1 : (own[n] != 0xFFFF ? 2 : 0);
+  return LBM_OK;
+}
+
+lbm_status lbm_node_types(lbm_ctx *c, uint8_t *node_type) {
+  if (!c || !node_type) return LBM_EINVAL;
+  return node_types_at(c, node_type, false);
+}
+
+lbm_status lbm_get_f(lbm_ctx *c, double *f) {
+  if (!c || !f) return LBM_EINVAL;
+  double *stg = c->at<double>(c->L.staging);
+  for (int i = 0; i < c->Q; i++) {
+    launch_decode_gather(c, i, c->state(), stg, false);
+    HIPCALL(hipMemcpyAsync(f + (size_t)i * c->N, stg, (size_t)c->N * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCALL(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_f(lbm_ctx *c, const double *f) {
+  if (!c || !f) return LBM_EINVAL;
+  double *stg = c->at<double>(c->L.staging);
+  for (int i = 0; i < c->Q; i++) {
+    HIPCALL(hipMemcpyAsync(stg, f + (size_t)i * c->N, (size_t)c->N * 8, hipMemcpyHostToDevice, c->stream));
+    launch_encode_shift(c, i, stg, c->state(), false);
+  }
+  HIPCALL(hipStreamSynchronize(c->stream));
+  c->fresh = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, void *host) {
+  if (!c || !host) return LBM_EINVAL;
+  double *stg = c->at<double>(c->L.staging);
+  const size_t bytes = (size_t)c->N * c->store_bytes;
+  for (int i = 0; i < c->Q; i++) {
+    launch_decode_gather(c, i, c->state(), stg, true);
+    HIPCALL(hipMemcpyAsync(static_cast<char *>(host) + (size_t)i * bytes, stg, bytes, hipMemcpyDeviceToHost,
+                           c->stream));
+  }
+  HIPCALL(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const void *host) {
+  if (!c || !host) return LBM_EINVAL;
+  double *stg = c->at<double>(c->L.staging);
+  const size_t bytes = (size_t)c->N * c->store_bytes;
+  for (int i = 0; i < c->Q; i++) {
+    HIPCALL(hipMemcpyAsync(stg, static_cast<const char *>(host) + (size_t)i * bytes, bytes, hipMemcpyHostToDevice,
+                           c->stream));
+    launch_encode_shift(c, i, stg, c->state(), true);
+  }
+  HIPCALL(hipStreamSynchronize(c->stream));
+  c->fresh = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_link_list(lbm_ctx *c, int64_t *count, uint32_t *cell, uint8_t *dir, int32_t *solid, double *q) {
+  if (!c || !count) return LBM_EINVAL;
+  const int64_t nl = c->nlinks;
+  if (!cell && !dir && !solid && !q) {
+    *count = nl;
+    return LBM_OK;
+  }
+  if (*count < nl) {
+    *count = nl;
+    return set_err(c, "output arrays too short"), LBM_EINVAL;
+  }
+  std::vector<uint32_t> lc((size_t)std::max<int64_t>(nl, 1)), lm((size_t)std::max<int64_t>(nl, 1));
+  std::vector<double> lq((size_t)std::max<int64_t>(nl, 1));
+  std::vector<SolidLinks> sl((size_t)std::max(c->nsolid, 1));
+  if (nl > 0) {
+    HIPCALL(hipMemcpyAsync(lc.data(), c->ws + c->L.link_cell, nl * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipMemcpyAsync(lm.data(), c->ws + c->L.link_meta, nl * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipMemcpyAsync(lq.data(), c->ws + c->L.link_q, nl * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (c->nsolid > 0)
+    HIPCALL(hipMemcpyAsync(sl.data(), c->ws + c->L.solid_links, sizeof(SolidLinks) * c->nsolid,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  std::vector<int32_t> ls((size_t)std::max<int64_t>(nl, 1));
+  for (int k = 0; k < c->nsolid; k++)
+    for (uint32_t l = sl[k].start; l < sl[k].start + sl[k].count && l < (uint32_t)nl; l++) ls[l] = k;
+  std::vector<int64_t> ord((size_t)nl);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    if (lc[a] != lc[b]) return lc[a] < lc[b];
+    return (lm[a] & 31u) < (lm[b] & 31u);
+  });
+  for (int64_t k = 0; k < nl; k++) {
+    const int64_t l = ord[k];
+    if (cell) cell[k] = lc[l];
+    if (dir) dir[k] = (uint8_t)(lm[l] & 31u);
+    if (solid) solid[k] = ls[l];
+    if (q) q[k] = lq[l];
+  }
+  *count = nl;
+  return LBM_OK;
+}
+
+lbm_status lbm_check(lbm_ctx *c) {
+  if (!c) return LBM_EINVAL;
+  uint32_t *flag = c->at<uint32_t>(c->L.misc + 8);
+  launch_check_finite(c, c->state(), flag);
+  uint32_t h = 0;
+  HIPCALL(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  if (h) return set_err(c, "non-finite value in the populations"), LBM_EDIVERGED;
+  return LBM_OK;
+}
+
+lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream) {
+  if (!src || !dst || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return LBM_EINVAL;
+  launch_copy_probe(src, dst, bytes, static_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+}  // extern "C"

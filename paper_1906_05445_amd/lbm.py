@@ -1,0 +1,273 @@
+"""ctypes binding of liblbm.so (include/lbm.h), argument marshalling only.
+
+Every function named ``lbm_*`` here calls the C entry point of the same name;
+all computation happens in the HIP library.  PyTorch provides the device
+workspace and the stream.  If the library is missing this module raises at
+import: there is no fallback path.
+
+``Lattice`` is a small owner object: it allocates the workspace tensor,
+creates the context and exposes numpy views of the readouts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1906_05445_amd/build.py (no fallback exists)")
+
+# torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+# first makes liblbm.so bind to that same runtime instead of pulling in a
+# second copy (with a second HSA runtime) from /opt/rocm.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_EUNSUPPORTED, LBM_ESTATE, LBM_EAGAIN = \
+    0, -1, -2, -3, -4, -5, -6, -7
+LATTICES = {"D2Q9": 0, "D3Q19": 1}
+COLLISIONS = {"BGK": 0, "MRT": 1}
+STORAGES = {"F64": 0, "F32": 1, "F16": 2}
+METHODS = {"BB": 0, "LINEAR": 1, "QUADRATIC": 2, "IBM": 3}
+KINDS = {"sphere": 0, "cylinder": 1, "plane": 2}
+STORAGE_DTYPES = {0: np.float64, 1: np.float32, 2: np.float16}
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("collision", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("rates", ctypes.POINTER(ctypes.c_double)),
+                ("body_force", ctypes.c_double * 3), ("body_force_fluid_only", ctypes.c_int32)]
+
+
+class lbm_solid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("inverted", ctypes.c_int32), ("centre", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("axis", ctypes.c_double * 3), ("velocity", ctypes.c_double * 3),
+                ("omega", ctypes.c_double * 3)]
+
+
+class lbm_ibm_opts(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int32), ("retraction", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+_st = ctypes.c_int32
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("lbm_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64])
+_sig("lbm_create", _st, [ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64, _vp, ctypes.c_size_t, _vp,
+                         ctypes.POINTER(_vp)])
+_sig("lbm_set_solids", _st, [_vp, ctypes.POINTER(lbm_solid), ctypes.c_int32, ctypes.c_int32,
+                             ctypes.POINTER(lbm_ibm_opts)])
+_sig("lbm_set_lagrangian", _st, [_vp, ctypes.c_int32, _d, _i64, ctypes.c_double])
+_sig("lbm_step", _st, [_vp, _i64])
+_sig("lbm_force_torque", _st, [_vp, _d, _d])
+_sig("lbm_force_history", _st, [_vp, _i64, _i64, _d])
+_sig("lbm_history_capacity", _i64, [])
+_sig("lbm_macros", _st, [_vp, _d, _d, ctypes.POINTER(ctypes.c_uint8)])
+_sig("lbm_get_f", _st, [_vp, _d])
+_sig("lbm_set_f", _st, [_vp, _d])
+_sig("lbm_get_state", _st, [_vp, _vp])
+_sig("lbm_set_state", _st, [_vp, _vp])
+_sig("lbm_link_list", _st, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32), _d])
+_sig("lbm_node_types", _st, [_vp, ctypes.POINTER(ctypes.c_uint8)])
+_sig("lbm_time", _i64, [_vp])
+_sig("lbm_check", _st, [_vp])
+_sig("lbm_destroy", _st, [_vp])
+_sig("lbm_status_string", ctypes.c_char_p, [_st])
+_sig("lbm_last_error", ctypes.c_char_p, [_vp])
+_sig("lbm_copy_probe", _st, [_vp, _vp, ctypes.c_size_t, _vp])
+
+EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
+            "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
+            "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
+            "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe"]
+globals().update({n: getattr(_lib, n) for n in EXPORTED})
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        msg = _lib.lbm_status_string(status).decode()
+        super().__init__(f"{msg} ({status})" + (f": {detail}" if detail else ""))
+
+
+def _ptr(a, t=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def make_params(lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
+                g=(0.0, 0.0, 0.0), g_fluid_only=True):
+    p = lbm_params()
+    p.lattice = LATTICES[lattice]
+    p.collision = COLLISIONS[collision]
+    p.storage = STORAGES[storage]
+    nx, ny, nz = (tuple(shape) + (1,))[:3]
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.tau = float(tau)
+    keep = None
+    if rates is not None:
+        keep = np.ascontiguousarray(rates, dtype=np.float64)
+        p.rates = _ptr(keep)
+    gg = list(g) + [0.0] * (3 - len(g))
+    for k in range(3):
+        p.body_force[k] = float(gg[k])
+    p.body_force_fluid_only = int(bool(g_fluid_only))
+    return p, keep
+
+
+def make_solids(solids):
+    arr = (lbm_solid * max(1, len(solids)))()
+    for k, s in enumerate(solids):
+        arr[k].kind = KINDS[s["kind"]]
+        arr[k].inverted = int(bool(s.get("inverted", False)))
+        c = list(s.get("centre", (0, 0, 0))) + [0.0] * 3
+        ax = list(s.get("axis", (0, 0, 1))) + [0.0] * 3
+        v = list(s.get("velocity", (0, 0, 0))) + [0.0] * 3
+        w = list(s.get("omega", (0, 0, 0))) + [0.0] * 3
+        for a in range(3):
+            arr[k].centre[a] = float(c[a])
+            arr[k].axis[a] = float(ax[a])
+            arr[k].velocity[a] = float(v[a])
+            arr[k].omega[a] = float(w[a])
+        arr[k].radius = float(s.get("radius", 0.0))
+    return arr
+
+
+class Lattice:
+    """One lattice on the current CUDA/HIP device, owning its workspace."""
+
+    def __init__(self, lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
+                 g=(0.0, 0.0, 0.0), g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0,
+                 stream=None, device="cuda"):
+        import torch
+        self._torch = torch
+        self.params, self._rates = make_params(lattice, collision, storage, shape, tau, rates, g, g_fluid_only)
+        self.shape = (self.params.nx, self.params.ny, self.params.nz)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        self.Q = 9 if lattice == "D2Q9" else 19
+        self.storage = self.params.storage
+        nbytes = _lib.lbm_workspace_bytes(ctypes.byref(self.params), max_solids, max_links, max_lagrangian)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, "lattice parameters rejected")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = _vp()
+        st = _lib.lbm_create(ctypes.byref(self.params), max_solids, max_links, max_lagrangian, _vp(aligned),
+                             nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, "lbm_create")
+        self.handle = h
+        self.nsolid = 0
+
+    def _check(self, st):
+        if st != LBM_OK:
+            raise LBMError(st, _lib.lbm_last_error(self.handle).decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_solids(self, solids, method="QUADRATIC", n_iter=5, retraction=0.0):
+        arr = make_solids(solids)
+        opts = lbm_ibm_opts(int(n_iter), float(retraction))
+        self._check(_lib.lbm_set_solids(self.handle, arr, len(solids), METHODS[method], ctypes.byref(opts)))
+        self.nsolid = len(solids)
+
+    def set_lagrangian(self, sid, X, dV):
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
+        self._check(_lib.lbm_set_lagrangian(self.handle, int(sid), _ptr(X), X.shape[0], float(dV)))
+
+    def step(self, n=1):
+        self._check(_lib.lbm_step(self.handle, int(n)))
+
+    @property
+    def time(self):
+        return _lib.lbm_time(self.handle)
+
+    def force_torque(self):
+        F = np.zeros((max(self.nsolid, 1), 3))
+        T = np.zeros((max(self.nsolid, 1), 3))
+        self._check(_lib.lbm_force_torque(self.handle, _ptr(F), _ptr(T)))
+        return np.concatenate([F, T], axis=1)[: self.nsolid]
+
+    def history(self, first=0, count=None):
+        if count is None:
+            count = self.time - first
+        out = np.zeros((max(count, 1), max(self.nsolid, 1), 6))
+        self._check(_lib.lbm_force_history(self.handle, int(first), int(count), _ptr(out)))
+        return out[:count, : self.nsolid]
+
+    def macros(self):
+        rho = np.empty(self.N)
+        u = np.empty((3, self.N))
+        t = np.empty(self.N, dtype=np.uint8)
+        self._check(_lib.lbm_macros(self.handle, _ptr(rho), _ptr(u), _ptr(t, ctypes.c_uint8)))
+        return rho, u, t
+
+    def get_f(self):
+        f = np.empty((self.Q, self.N))
+        self._check(_lib.lbm_get_f(self.handle, _ptr(f)))
+        return f
+
+    def set_f(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.N)
+        self._check(_lib.lbm_set_f(self.handle, _ptr(f)))
+
+    def get_state(self):
+        out = np.empty((self.Q, self.N), dtype=STORAGE_DTYPES[self.storage])
+        self._check(_lib.lbm_get_state(self.handle, out.ctypes.data_as(_vp)))
+        return out
+
+    def set_state(self, h):
+        h = np.ascontiguousarray(h, dtype=STORAGE_DTYPES[self.storage]).reshape(self.Q, self.N)
+        self._check(_lib.lbm_set_state(self.handle, h.ctypes.data_as(_vp)))
+
+    def links(self):
+        n = _i64(0)
+        self._check(_lib.lbm_link_list(self.handle, ctypes.byref(n), None, None, None, None))
+        m = max(n.value, 1)
+        cell = np.zeros(m, dtype=np.uint32)
+        d = np.zeros(m, dtype=np.uint8)
+        sid = np.zeros(m, dtype=np.int32)
+        q = np.zeros(m)
+        cnt = _i64(m)
+        self._check(_lib.lbm_link_list(self.handle, ctypes.byref(cnt), _ptr(cell, ctypes.c_uint32),
+                                       _ptr(d, ctypes.c_uint8), _ptr(sid, ctypes.c_int32), _ptr(q)))
+        k = cnt.value
+        return {"cell": cell[:k].astype(np.int64), "dir": d[:k].astype(np.int32), "sid": sid[:k], "q": q[:k]}
+
+    def node_types(self):
+        t = np.empty(self.N, dtype=np.uint8)
+        self._check(_lib.lbm_node_types(self.handle, _ptr(t, ctypes.c_uint8)))
+        return t
+
+    def check(self):
+        st = _lib.lbm_check(self.handle)
+        if st not in (LBM_OK, LBM_EDIVERGED):
+            self._check(st)
+        return st == LBM_OK

@@ -25,9 +25,8 @@ from paper_1906_05445_amd import workloads as W
 
 
 def _momentum(o, e, excl):
-    """Fluid momentum and mass, summed exactly (math.fsum) over deviations f - w."""
-    _, w, _ = o.lattice_tables()
-    h = (o.get_f() - w[:, None])[:, excl == 0]
+    """Fluid momentum and mass, summed exactly (math.fsum) over the deviations f - w."""
+    h = o.get_h()[:, excl == 0]
     P = np.array([math.fsum((h * e[:, a][:, None]).ravel()) for a in range(3)])
     return P, math.fsum(h.ravel())  # mass relative to the rest state
 

@@ -165,14 +165,14 @@ def test_no_relaxation_step_is_exact_streaming(lat):
     o = Oracle(lat, "MRT", shape, 0.8, rates=np.zeros(Q))
     e, w, _ = o.lattice_tables()
     rng = np.random.default_rng(15)
-    f0 = w[:, None] * (1.0 + 0.1 * rng.uniform(-1, 1, size=(Q, o.N)))
-    o.set_f(f0)
+    h0 = w[:, None] * 0.1 * rng.uniform(-1, 1, size=(Q, o.N))
+    o.set_h(h0)
     o.step(3)
     nx, ny, nz = shape
-    ref = f0.reshape(Q, nz, ny, nx).copy()
+    ref = h0.reshape(Q, nz, ny, nx).copy()
     for i in range(Q):
         ref[i] = np.roll(ref[i], shift=(3 * e[i][2], 3 * e[i][1], 3 * e[i][0]), axis=(0, 1, 2))
-    assert np.array_equal(o.get_f(), ref.reshape(Q, -1))
+    assert np.array_equal(o.get_h(), ref.reshape(Q, -1))
 
 
 def test_no_relaxation_with_halfway_walls_is_a_permutation():
@@ -184,8 +184,8 @@ def test_no_relaxation_with_halfway_walls_is_a_permutation():
                   {"kind": "plane", "centre": (0, ny - 1.5, 0), "axis": (0, -1, 0)}], "QUADRATIC")
     e, w, opp = o.lattice_tables()
     rng = np.random.default_rng(16)
-    f0 = w[:, None] * (1.0 + 0.1 * rng.uniform(-1, 1, size=(Q, o.N)))
-    o.set_f(f0)
+    f0 = w[:, None] * 0.1 * rng.uniform(-1, 1, size=(Q, o.N))  # deviations h = f - w
+    o.set_h(f0)
     o.step(1)
     fluid = lambda y: 1 <= y <= ny - 2
     ref = np.zeros_like(f0)
@@ -200,6 +200,6 @@ def test_no_relaxation_with_halfway_walls_is_a_permutation():
                     ref[i, n] = f0[i, sx + nx * sy]
                 else:
                     ref[i, n] = f0[opp[i], n]
-    got = o.get_f()
+    got = o.get_h()
     mask = np.array([fluid(n // nx) for n in range(o.N)])
     assert np.array_equal(got[:, mask], ref[:, mask])
