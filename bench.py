@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Benchmark of the lattice Boltzmann hot path on one MI355X.
+
+Workload (the value line): D3Q19 MRT, FP32 deviation storage, 128^3 periodic
+box, one fixed sphere of radius 16.2 at a seed-drawn sub-grid offset, body
+force for Re = 20, quadratic interpolated bounce-back with momentum-exchange
+force and torque every step.  A step is the whole per-step path: the fused
+stream-collide sweep, the bounce-back/force kernel and the per-solid force
+reduction.  MLUPS counts every lattice cell.
+
+Also reported (same JSON line): the FP64 and FP16 forms of that workload,
+the direct-forcing IBM form (5 forcing iterations per step), the 256^3 box
+with 64 spheres (working set far beyond the 256 MB Infinity Cache), the
+achievable HBM copy bandwidth, and the FP64 CPU oracle timed on a bounded
+sample of the value workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline (D3Q19 FP32 vs FP64); served solves/s with p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"F64": 8, "F32": 4, "F16": 2}
+
+
+def sweep_source_hash():
+    src = os.path.join(ROOT, "paper_1906_05445_amd", "csrc", "kernels_sweep.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(key, cells):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if they
+    were taken on the current sweep source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    if data.get("sweep_source_sha256_16") != sweep_source_hash():
+        return None
+    ent = data.get("workloads", {}).get(key)
+    if not ent or ent.get("cells") != cells:
+        return None
+    return ent["bytes_per_launch"]
+
+
+def run_case(case, steps, warmup, key, torch, lbm):
+    Q = 19 if case.lattice == "D3Q19" else 9
+    gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g,
+                      max_solids=max(1, len(case.solids)))
+    gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction)
+    N = gpu.N
+    gpu.step(warmup)
+    torch.cuda.synchronize()
+    gpu.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpu.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms, launches = gpu.profile_read()
+    gpu.profile(False)
+    if not gpu.check():
+        raise RuntimeError(f"{key}: populations diverged")
+    F = gpu.force_torque()
+    wall = t1 - t0
+    per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
+    avg_s = sweep_ms / 1e3 / max(launches, 1)
+    achieved = N * per_cell / avg_s / 1e9
+    traffic = traffic_for(key, N)
+    out = {
+        "mlups": N * steps / wall / 1e6,
+        "ms_per_step": wall / steps * 1e3,
+        "cells": N,
+        "solids": len(case.solids),
+        "method": case.method,
+        "storage": case.storage,
+        "sweep_avg_us": avg_s * 1e6,
+        "sweep_launches": launches,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "drag_x": float(F[0, 0]),
+    }
+    gpu.close()
+    del gpu
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_probe(torch, lbm, nbytes=4 << 30, reps=20):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def cpu_baseline(case, steps):
+    """The FP64 oracle (single-threaded C) on a bounded sample of the value workload."""
+    from oracle import Oracle
+
+    o = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g)
+    o.set_solids(case.solids, case.method)
+    t0 = time.perf_counter()
+    o.step(steps)
+    wall = time.perf_counter() - t0
+    N = case.shape[0] * case.shape[1] * case.shape[2]
+    return {"value": N * steps / wall / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the 128^3 one-sphere workload (quadratic IBB), FP64, one host thread",
+            "seconds": wall}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1906_05445_amd import lbm
+    from paper_1906_05445_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+    primary_case = W.sphere_box(storage="F32", method="QUADRATIC")
+    primary = run_case(primary_case, K, Wm, "sphere128_f32_quadratic", torch, lbm)
+    print(f"# sphere128 F32 IBB: {primary['mlups']:.0f} MLUPS, sweep {primary['sweep_avg_us']:.1f} us, "
+          f"{primary['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
+    extras = {}
+    if not args.primary_only:
+        k2 = max(K // 2, 100)
+        for key, case in [("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
+                          ("sphere128_f16_quadratic", W.sphere_box(storage="F16", method="QUADRATIC")),
+                          ("sphere128_f32_ibm", W.sphere_box(storage="F32", method="IBM")),
+                          ("pack256_f32_quadratic", W.sphere_pack(storage="F32")),
+                          ("pack256_f64_quadratic", W.sphere_pack(storage="F64"))]:
+            k = k2 if "256" not in key else max(K // 8, 50)
+            extras[key] = run_case(case, k, max(Wm // 4, 20), key, torch, lbm)
+            extras[key]["steps"] = k
+            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+        extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
+    cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps)
+    line = {
+        "metric": METRIC,
+        "value": primary["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": primary["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere128: D3Q19 MRT, 128^3 periodic, one sphere R=16.2 (seed 2), Re=20 "
+                               "body force, quadratic IBB + momentum-exchange force, FP32 deviation storage",
+                   "cells": primary["cells"], "parallelism": "single GPU"},
+        "roofline": primary["roofline"],
+        "cpu_baseline": cpu,
+        "sweep_avg_us": primary["sweep_avg_us"],
+        "extras": extras,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,13 @@ lbm_status lbm_destroy(lbm_ctx *c);
 const char *lbm_status_string(lbm_status st);
 const char *lbm_last_error(const lbm_ctx *c);
 
+/* Profiling: with enable = 1, lbm_step records a pair of HIP events on the
+ * context's stream around every stream-collide launch; lbm_profile_read
+ * synchronises the stream, returns the summed duration (ms) and the number
+ * of launches recorded since the last read, and clears them. */
+lbm_status lbm_profile(lbm_ctx *c, int32_t enable);
+lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches);
+
 /* Copy `bytes` from src to dst (device pointers) with the library's
  * streaming copy kernel, the bandwidth yardstick for the sweep. */
 lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);

@@ -81,6 +81,8 @@ struct lbm_ctx {
   std::vector<int64_t> lag_start, lag_count;
   std::vector<double> lag_X, lag_dV;
   bool lag_user;
+  bool profiling;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::string err;
   // helpers
   void *state() const { return ws + (cur == 0 ? L.A : L.B); }

@@ -299,6 +299,7 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->nlag = 0;
   c->nshell = 0;
   c->lag_user = false;
+  c->profiling = false;
   c->fresh = true;
   // rest state, cleared flags and ownership
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
@@ -316,7 +317,34 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
 lbm_status lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  for (auto &e : c->prof_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   delete c;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile(lbm_ctx *c, int32_t enable) {
+  if (!c) return LBM_EINVAL;
+  c->profiling = enable != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches) {
+  if (!c) return LBM_EINVAL;
+  HIPCALL(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (auto &e : c->prof_events) {
+    float ms = 0.0f;
+    HIPCALL(hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (sweep_ms) *sweep_ms = tot;
+  if (launches) *launches = (int64_t)c->prof_events.size();
+  c->prof_events.clear();
   return LBM_OK;
 }
 
@@ -609,7 +637,17 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
     if (c->method == LBM_IBM && c->nsolid > 0) launch_ibm_step(c, A, c->t);
-    launch_sweep(c, A, B);
+    if (c->profiling) {
+      hipEvent_t e0, e1;
+      HIPCALL(hipEventCreate(&e0));
+      HIPCALL(hipEventCreate(&e1));
+      HIPCALL(hipEventRecord(e0, c->stream));
+      launch_sweep(c, A, B);
+      HIPCALL(hipEventRecord(e1, c->stream));
+      c->prof_events.push_back({e0, e1});
+    } else {
+      launch_sweep(c, A, B);
+    }
     if (ibb) {
       launch_ibb(c, B, c->t);
       launch_ft_reduce(c, c->t);

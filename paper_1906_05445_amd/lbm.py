@@ -92,11 +92,14 @@ _sig("lbm_destroy", _st, [_vp])
 _sig("lbm_status_string", ctypes.c_char_p, [_st])
 _sig("lbm_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_copy_probe", _st, [_vp, _vp, ctypes.c_size_t, _vp])
+_sig("lbm_profile", _st, [_vp, ctypes.c_int32])
+_sig("lbm_profile_read", _st, [_vp, _d, ctypes.POINTER(_i64)])
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
-            "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe"]
+            "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
+            "lbm_profile", "lbm_profile_read"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
 
@@ -265,6 +268,16 @@ class Lattice:
         t = np.empty(self.N, dtype=np.uint8)
         self._check(_lib.lbm_node_types(self.handle, _ptr(t, ctypes.c_uint8)))
         return t
+
+    def profile(self, enable=True):
+        self._check(_lib.lbm_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        """(summed stream-collide milliseconds, launches) since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = _i64(0)
+        self._check(_lib.lbm_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def check(self):
         st = _lib.lbm_check(self.handle)
