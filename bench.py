@@ -72,6 +72,7 @@ def run_case(case, steps, warmup, key, torch, lbm):
     if not gpu.check():
         raise RuntimeError(f"{key}: populations diverged")
     F = gpu.force_torque()
+    tune = gpu.autotune_info()
     wall = t1 - t0
     per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
     avg_s = sweep_ms / 1e3 / max(launches, 1)
@@ -89,6 +90,7 @@ def run_case(case, steps, warmup, key, torch, lbm):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "drag_x": float(F[0, 0]),
+        "autotune": tune,
     }
     gpu.close()
     del gpu

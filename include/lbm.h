@@ -203,6 +203,12 @@ const char *lbm_last_error(const lbm_ctx *c);
 lbm_status lbm_profile(lbm_ctx *c, int32_t enable);
 lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches);
 
+/* Result of the sweep autotuner, which runs on the first lbm_step of a
+ * context (or reuses a choice made for an identical lattice in this process):
+ * nontemporal = 1 if the sweep writes with non-temporal stores (-1 before
+ * tuning), and the measured sweep times of both store policies (us). */
+lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain, double *us_nontemporal);
+
 /* Copy `bytes` from src to dst (device pointers) with the library's
  * streaming copy kernel, the bandwidth yardstick for the sweep. */
 lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);

@@ -169,8 +169,7 @@ __device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
     double r = 0.0;
 #pragma unroll
     for (int j = 0; j < Q; j++)
-      r += (double)Store<S>::ld(P + (uint64_t)j * a.g.stride +
-                                id_of(yx - L::ex(j), yy - L::ey(j), yzz - L::ez(j), a.g));
+      r += (double)Store<S>::ld(P + pidx<Q>(j, id_of(yx - L::ex(j), yy - L::ey(j), yzz - L::ez(j), a.g)));
     sum += r;
     cnt++;
   }
@@ -185,8 +184,7 @@ __device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
   for (int i = 0; i < Q; i++) {
     const double eu = L::ex(i) * uw[0] + L::ey(i) * uw[1] + L::ez(i) * uw[2];
     const double heq = wgt<Q>(i) * (drb + rb * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
-    Store<S>::st(P + (uint64_t)i * a.g.stride + id_of(x - L::ex(i), y - L::ey(i), z - L::ez(i), a.g),
-                 (typename Store<S>::C)heq);
+    Store<S>::st(P + pidx<Q>(i, id_of(x - L::ex(i), y - L::ey(i), z - L::ez(i), a.g)), (typename Store<S>::C)heq);
   }
 }
 
@@ -249,7 +247,7 @@ __global__ void k_link_scan(LinkArgs a, int nsolid) {
       L.start = first;
       L.count = last - first;
       L.chunk_base = cb;
-      L.nchunks = (L.count + kBlock - 1) / kBlock;
+      L.nchunks = (L.count + kLinkChunk - 1) / kLinkChunk;
       cb += L.nchunks;
       a.sl[sd] = L;
     }
@@ -340,86 +338,81 @@ __device__ inline C ibb_value(int method, double q, bool ffok, bool fffok, C hb_
   return hb_f + B;  // Eq. 10
 }
 
+// One wavefront per chunk of kLinkChunk links of one solid; each wave writes
+// the chunk's force/torque partial (summed per solid in chunk order later).
 template <int Q, typename S>
-__global__ __launch_bounds__(kBlock) void k_ibb(S *__restrict__ P, IbbArgs a) {
+__global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  __shared__ double lds[16];
   const int s = blockIdx.y;
   const SolidLinks sl = a.sl[s];
-  // capacity overflow (reported by the host after the step) must not read or write out of bounds
-  if (blockIdx.x >= sl.nchunks || (uint64_t)sl.chunk_base + blockIdx.x >= a.max_partials) return;
-  const uint32_t li = blockIdx.x * kBlock + threadIdx.x;
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (li < sl.count && (uint64_t)sl.start + li < a.max_links) {
-    const uint64_t l = (uint64_t)sl.start + li;
-    const uint32_t n = a.link_cell[l], meta = a.link_meta[l];
-    const double q = a.link_q[l];
-    const int i = (int)(meta & 31u), ib = opp(i);
-    const bool ffok = (meta >> 5) & 1u, fffok = (meta >> 6) & 1u;
-    int x, y, z;
-    xyz_of(n, a.g, x, y, z);
-    int ex = 0, ey = 0, ez = 0;
-    double w = 0.0;
+  const int lane = threadIdx.x;
+  const bool active = blockIdx.x < sl.nchunks && (uint64_t)sl.chunk_base + blockIdx.x < a.max_partials;
+  if (active) {
+    const uint32_t li = blockIdx.x * kLinkChunk + lane;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // capacity overflow (reported by the host after the step) must not read out of bounds
+    if (li < sl.count && (uint64_t)sl.start + li < a.max_links) {
+      const uint64_t l = (uint64_t)sl.start + li;
+      const uint32_t n = a.link_cell[l], meta = a.link_meta[l];
+      const double q = a.link_q[l];
+      const int i = (int)(meta & 31u), ib = opp(i);
+      const bool ffok = (meta >> 5) & 1u, fffok = (meta >> 6) & 1u;
+      int x, y, z;
+      xyz_of(n, a.g, x, y, z);
+      int ex = 0, ey = 0, ez = 0;
+      double w = 0.0;
 #pragma unroll
-    for (int k = 1; k < Q; k++)
-      if (k == i) {
-        ex = L::ex(k);
-        ey = L::ey(k);
-        ez = L::ez(k);
-        w = wgt<Q>(k);
-      }
-    const DevSolid &sd = a.g.solids[s];
-    double c[3], r[3], uw[3];
-    solid_centre(sd, a.g.t, a.g.b, c);
-    lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
-    wall_vel(sd, r, uw);
-    const double Bw = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
-    const uint32_t nff = id_of(x + ex, y + ey, z + ez, a.g);
-    const uint32_t nfff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
-    const uint32_t nb = id_of(x - ex, y - ey, z - ez, a.g);
-    const S *Pi = P + (uint64_t)i * a.g.stride;
-    const S *Pb = P + (uint64_t)ib * a.g.stride;
-    const C hb_f = Store<S>::ld(Pb + n);
-    const C hb_ff = ffok ? Store<S>::ld(Pb + nff) : C(0);
-    const C hb_fff = fffok ? Store<S>::ld(Pb + nfff) : C(0);
-    const C hs_f = Store<S>::ld(Pi + n);
-    const C hs_ff = ffok ? Store<S>::ld(Pi + nff) : C(0);
-    const C v = ibb_value<C>(a.method, q, ffok, fffok, hb_f, hb_ff, hb_fff, hs_f, hs_ff, (C)Bw);
-    S *dst = P + (uint64_t)i * a.g.stride + nb;
-    Store<S>::st(dst, v);
-    // Eq. 17 in FP64 on the stored values.  With f = w + h the rest-state part
-    // w (e_ibar - u_w) - w (e_i - u_w) is -2 w e_i (u_w cancels).
-    const double hin = (double)Store<S>::ld(dst);
-    const double hout = (double)hb_f;
-    const double e[3] = {(double)ex, (double)ey, (double)ez};
-    double dF[3];
-    for (int k = 0; k < 3; k++) dF[k] = hout * (-e[k] - uw[k]) - hin * (e[k] - uw[k]) - 2.0 * w * e[k];
-    acc[0] = dF[0];
-    acc[1] = dF[1];
-    acc[2] = dF[2];
-    acc[3] = r[1] * dF[2] - r[2] * dF[1];
-    acc[4] = r[2] * dF[0] - r[0] * dF[2];
-    acc[5] = r[0] * dF[1] - r[1] * dF[0];
-  }
-  for (int k = 0; k < 6; k++) {
-    const double tot = block_sum(acc[k], lds);
-    if (threadIdx.x == 0) a.partials[(uint64_t)(sl.chunk_base + blockIdx.x) * 6 + k] = tot;
+      for (int k = 1; k < Q; k++)
+        if (k == i) {
+          ex = L::ex(k);
+          ey = L::ey(k);
+          ez = L::ez(k);
+          w = wgt<Q>(k);
+        }
+      const DevSolid &sd = a.g.solids[s];
+      double c[3], r[3], uw[3];
+      solid_centre(sd, a.g.t, a.g.b, c);
+      lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
+      wall_vel(sd, r, uw);
+      const double Bw = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
+      const uint32_t nff = id_of(x + ex, y + ey, z + ez, a.g);
+      const uint32_t nfff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
+      const uint32_t nb = id_of(x - ex, y - ey, z - ez, a.g);
+      const C hb_f = Store<S>::ld(P + pidx<Q>(ib, n));
+      const C hb_ff = ffok ? Store<S>::ld(P + pidx<Q>(ib, nff)) : C(0);
+      const C hb_fff = fffok ? Store<S>::ld(P + pidx<Q>(ib, nfff)) : C(0);
+      const C hs_f = Store<S>::ld(P + pidx<Q>(i, n));
+      const C hs_ff = ffok ? Store<S>::ld(P + pidx<Q>(i, nff)) : C(0);
+      const C v = ibb_value<C>(a.method, q, ffok, fffok, hb_f, hb_ff, hb_fff, hs_f, hs_ff, (C)Bw);
+      S *dst = P + pidx<Q>(i, nb);
+      Store<S>::st(dst, v);
+      // Eq. 17 in FP64 on the stored values.  With f = w + h the rest-state part
+      // w (e_ibar - u_w) - w (e_i - u_w) is -2 w e_i (u_w cancels).
+      const double hin = (double)Store<S>::ld(dst);
+      const double hout = (double)hb_f;
+      const double e[3] = {(double)ex, (double)ey, (double)ez};
+      double dF[3];
+      for (int k = 0; k < 3; k++) dF[k] = hout * (-e[k] - uw[k]) - hin * (e[k] - uw[k]) - 2.0 * w * e[k];
+      acc[0] = dF[0];
+      acc[1] = dF[1];
+      acc[2] = dF[2];
+      acc[3] = r[1] * dF[2] - r[2] * dF[1];
+      acc[4] = r[2] * dF[0] - r[0] * dF[2];
+      acc[5] = r[0] * dF[1] - r[1] * dF[0];
+    }
+    for (int k = 0; k < 6; k++) {
+      const double tot = wave_sum(acc[k]);
+      if (lane == 0) a.partials[(uint64_t)(sl.chunk_base + blockIdx.x) * 6 + k] = tot;
+    }
   }
 }
 
-// Per-solid sum of the chunk partials in a fixed order -> history slot.
-__global__ void k_ft_reduce(const double *partials, const SolidLinks *sl, double *hist, uint64_t max_partials) {
-  __shared__ double lds[16];
-  const int s = blockIdx.x;
-  const SolidLinks L = sl[s];
-  for (int k = 0; k < 6; k++) {
-    double v = 0.0;
-    for (uint32_t c = threadIdx.x; c < L.nchunks; c += blockDim.x)
-      if ((uint64_t)L.chunk_base + c < max_partials) v += partials[(uint64_t)(L.chunk_base + c) * 6 + k];
-    const double tot = block_sum(v, lds);
-    if (threadIdx.x == 0) hist[(uint64_t)s * 6 + k] = tot;
-  }
+// Per-solid force/torque: one wavefront per solid sums that solid's chunk
+// partials in chunk order into the history slot (used for the last step of an
+// lbm_step call; earlier steps are reduced inside the next sweep launch).
+__global__ __launch_bounds__(256) void k_ft_reduce(FtReduceArgs r) {
+  ft_reduce_waves(r, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -515,7 +508,7 @@ void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
   a.max_links = (uint64_t)c->L.max_links;
   a.max_partials = (uint64_t)c->L.max_partials;
   const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
-#define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(kBlock), 0, c->stream, static_cast<SS *>(P), a)
+#define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(64), 0, c->stream, static_cast<SS *>(P), a)
   if (c->Q == 9) {
     if (c->p.storage == LBM_F64) LBM_IBB(9, double);
     else if (c->p.storage == LBM_F32_DEV) LBM_IBB(9, float);
@@ -528,10 +521,20 @@ void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
 #undef LBM_IBB
 }
 
+FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t) {
+  FtReduceArgs r{};
+  r.partials = c->at<double>(c->L.partials);
+  r.sl = c->at<SolidLinks>(c->L.solid_links);
+  r.hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
+  r.nsolid = c->nsolid;
+  r.max_partials = (uint64_t)c->L.max_partials;
+  return r;
+}
+
 void launch_ft_reduce(lbm_ctx *c, int64_t t) {
-  double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
-  hipLaunchKernelGGL(k_ft_reduce, dim3((uint32_t)c->nsolid), dim3(256), 0, c->stream, c->at<double>(c->L.partials),
-                     c->at<SolidLinks>(c->L.solid_links), hist, (uint64_t)c->L.max_partials);
+  if (c->k5_chunks <= 0) return;
+  FtReduceArgs r = ft_reduce_args(c, t);
+  hipLaunchKernelGGL(k_ft_reduce, dim3((uint32_t)((c->nsolid + 3) / 4)), dim3(256), 0, c->stream, r);
 }
 
 }  // namespace lbm

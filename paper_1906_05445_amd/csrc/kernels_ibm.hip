@@ -85,7 +85,7 @@ __global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
     const uint32_t src = (uint32_t)wrapi(x - L::ex(i), a.b.nx) +
                          (uint32_t)a.b.nx * ((uint32_t)wrapi(y - L::ey(i), a.b.ny) +
                                              (uint32_t)a.b.ny * (uint32_t)wrapi(z - L::ez(i), a.b.nz));
-    const C h = Store<S>::ld(A + (uint64_t)i * a.stride + src);
+    const C h = Store<S>::ld(A + pidx<Q>(i, src));
     drho += h;
     j[0] += C(L::ex(i)) * h;
     j[1] += C(L::ey(i)) * h;

@@ -9,6 +9,8 @@
 // array.  Storage is the deviation h_i = f_i - w_i (FP64, FP32 or FP16),
 // arithmetic is FP64 for FP64 storage and FP32 otherwise.  Arrays are SoA,
 // [Q][stride], x fastest, so each of the 2Q streams is coalesced.
+#include <hip/hip_ext.h>
+
 #include "lbm_geom.hpp"
 
 namespace lbm {
@@ -26,13 +28,19 @@ struct SweepArgs {
   double sp, sm;         // two-rate MRT: even and odd non-conserved rates
   double sA[kMaxQ];      // general MRT: -s_k / |M_k|^2
   double sB[kMaxQ];      //              (1 - s_k/2) / |M_k|^2
+  uint32_t rblocks;      // leading blocks that reduce the previous step's force partials
+  FtReduceArgs ft;
 };
 
-template <int Q, int COLL, typename S, int FLAGS>
+template <int Q, int COLL, typename S, int FLAGS, int NT>
 __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  const uint32_t n = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (blockIdx.x < a.rblocks) {  // dispatched first, finished long before the sweep's tail
+    ft_reduce_waves(a.ft, blockIdx.x);
+    return;
+  }
+  const uint32_t n = (blockIdx.x - a.rblocks) * kBlock + threadIdx.x;
   if (n >= a.N) return;
   uint8_t fl = 0;
   if (FLAGS) {
@@ -55,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__
     const uint32_t sy = L::ey(i) > 0 ? ym : (L::ey(i) < 0 ? yp : y);
     const uint32_t sz = L::ez(i) > 0 ? zm : (L::ez(i) < 0 ? zp : z);
     const uint32_t src = sx + a.nx * (sy + a.ny * sz);
-    h[i] = Store<S>::ld(A + (uint64_t)i * a.stride + src);
+    h[i] = Store<S>::ld(A + pidx<Q>(i, src));
   }
 
   // moments of the deviation: rho = 1 + drho, j = sum h e (sum w e = 0)
@@ -145,23 +153,33 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__
     }
   }
 
+  // one tile per block: the block writes Q contiguous runs of kTile values
+  const uint64_t base = pidx<Q>(0, n);
 #pragma unroll
-  for (int i = 0; i < Q; i++) Store<S>::st(B + (uint64_t)i * a.stride + n, h[i]);
+  for (int i = 0; i < Q; i++) {
+    if (NT) Store<S>::st_nt(B + base + (uint64_t)i * kTile, h[i]);
+    else Store<S>::st(B + base + (uint64_t)i * kTile, h[i]);
+  }
 }
 
 template <typename S>
-static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags) {
-  const uint32_t grid = (uint32_t)((c->N + kBlock - 1) / kBlock);
+static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags, bool nt,
+                           hipEvent_t e0, hipEvent_t e1) {
+  const uint32_t grid = (uint32_t)((c->N + kBlock - 1) / kBlock) + a.rblocks;
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
-#define LBM_SWEEP(QQ, CC, FF) \
-  hipLaunchKernelGGL((k_sweep<QQ, CC, S, FF>), dim3(grid), dim3(kBlock), 0, c->stream, As, Bs, a)
-#define LBM_SWEEP2(QQ, CC) \
-  do {                     \
-    if (flags)             \
-      LBM_SWEEP(QQ, CC, 1); \
-    else                   \
-      LBM_SWEEP(QQ, CC, 0); \
+  // the events (when given) are attached to the dispatch itself and time the kernel alone
+#define LBM_SWEEP(QQ, CC, FF, NN) \
+  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, As, Bs, a)
+#define LBM_SWEEP2(QQ, CC)                    \
+  do {                                        \
+    if (flags) {                              \
+      if (nt) LBM_SWEEP(QQ, CC, 1, 1);        \
+      else LBM_SWEEP(QQ, CC, 1, 0);           \
+    } else {                                  \
+      if (nt) LBM_SWEEP(QQ, CC, 0, 1);        \
+      else LBM_SWEEP(QQ, CC, 0, 0);           \
+    }                                         \
   } while (0)
   if (c->Q == 9) {
     if (coll == COLL_BGK) LBM_SWEEP2(9, COLL_BGK);
@@ -202,7 +220,7 @@ static void mrt_coeffs(const lbm_ctx *c, SweepArgs &a) {
   }
 }
 
-void launch_sweep(lbm_ctx *c, const void *A, void *B) {
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t) {
   SweepArgs a{};
   a.N = (uint32_t)c->N;
   a.nx = (uint32_t)c->p.nx;
@@ -214,6 +232,10 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B) {
   a.flags = c->at<uint8_t>(c->L.flags);
   a.fibm = c->ws + c->L.fibm;
   for (int k = 0; k < 3; k++) a.g[k] = c->p.body_force[k];
+  if (reduce_t >= 0 && c->k5_chunks > 0) {
+    a.ft = ft_reduce_args(c, reduce_t);
+    a.rblocks = (uint32_t)((c->nsolid + 3) / 4);
+  }
   int coll;
   if (c->p.collision == LBM_BGK) {
     coll = COLL_BGK;
@@ -226,9 +248,10 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B) {
     else mrt_coeffs<19>(c, a);
   }
   const bool flags = c->nsolid > 0;
-  if (c->p.storage == LBM_F64) sweep_dispatch<double>(c, A, B, a, coll, flags);
-  else if (c->p.storage == LBM_F32_DEV) sweep_dispatch<float>(c, A, B, a, coll, flags);
-  else sweep_dispatch<_Float16>(c, A, B, a, coll, flags);
+  const bool ntb = nt != 0;
+  if (c->p.storage == LBM_F64) sweep_dispatch<double>(c, A, B, a, coll, flags, ntb, e0, e1);
+  else if (c->p.storage == LBM_F32_DEV) sweep_dispatch<float>(c, A, B, a, coll, flags, ntb, e0, e1);
+  else sweep_dispatch<_Float16>(c, A, B, a, coll, flags, ntb, e0, e1);
 }
 
 // ----------------------------------------------------------------------------
@@ -252,39 +275,41 @@ __device__ inline uint32_t cell_id(int x, int y, int z, const CellArgs &a) {
 }
 
 template <typename S>
-__global__ void k_encode(const double *__restrict__ f, S *__restrict__ Ai, int ex, int ey, int ez, double w,
-                         CellArgs a) {
+__global__ void k_encode(const double *__restrict__ f, S *__restrict__ A, int Q, int dir, int ex, int ey, int ez,
+                         double w, CellArgs a) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= a.N) return;
   int x, y, z;
   cell_xyz(n, a, x, y, z);
-  Store<S>::st(Ai + n, (typename Store<S>::C)(f[cell_id(x + ex, y + ey, z + ez, a)] - w));
+  Store<S>::st(A + pidx_rt(Q, dir, n), (typename Store<S>::C)(f[cell_id(x + ex, y + ey, z + ez, a)] - w));
 }
 template <typename S>
-__global__ void k_shift_raw(const S *__restrict__ src, S *__restrict__ Ai, int ex, int ey, int ez, CellArgs a) {
+__global__ void k_shift_raw(const S *__restrict__ src, S *__restrict__ A, int Q, int dir, int ex, int ey, int ez,
+                            CellArgs a) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= a.N) return;
   int x, y, z;
   cell_xyz(n, a, x, y, z);
-  Ai[n] = src[cell_id(x + ex, y + ey, z + ez, a)];
+  A[pidx_rt(Q, dir, n)] = src[cell_id(x + ex, y + ey, z + ez, a)];
 }
 template <typename S>
-__global__ void k_decode(const S *__restrict__ Ai, double *__restrict__ f, int ex, int ey, int ez, double w,
-                         const uint8_t *flags, CellArgs a) {
+__global__ void k_decode(const S *__restrict__ A, double *__restrict__ f, int Q, int dir, int ex, int ey, int ez,
+                         double w, const uint8_t *flags, CellArgs a) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= a.N) return;
   int x, y, z;
   cell_xyz(n, a, x, y, z);
   const bool solid = flags && (flags[n] & F_SOLID);
-  f[n] = solid ? 0.0 : w + (double)Store<S>::ld(Ai + cell_id(x - ex, y - ey, z - ez, a));
+  f[n] = solid ? 0.0 : w + (double)Store<S>::ld(A + pidx_rt(Q, dir, cell_id(x - ex, y - ey, z - ez, a)));
 }
 template <typename S>
-__global__ void k_gather_raw(const S *__restrict__ Ai, S *__restrict__ dst, int ex, int ey, int ez, CellArgs a) {
+__global__ void k_gather_raw(const S *__restrict__ A, S *__restrict__ dst, int Q, int dir, int ex, int ey, int ez,
+                             CellArgs a) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= a.N) return;
   int x, y, z;
   cell_xyz(n, a, x, y, z);
-  dst[n] = Ai[cell_id(x - ex, y - ey, z - ez, a)];
+  dst[n] = A[pidx_rt(Q, dir, cell_id(x - ex, y - ey, z - ez, a))];
 }
 
 static CellArgs cell_args(const lbm_ctx *c) {
@@ -319,13 +344,13 @@ static void encode_t(lbm_ctx *c, int dir, const double *src, void *A, bool raw) 
   int ex, ey, ez;
   double w;
   dir_vec(c->Q, dir, ex, ey, ez, w);
-  S *Ai = static_cast<S *>(A) + (uint64_t)dir * c->L.stride;
+  S *As = static_cast<S *>(A);
   const uint32_t grid = (uint32_t)((c->N + 255) / 256);
   if (raw)
-    hipLaunchKernelGGL(k_shift_raw<S>, dim3(grid), dim3(256), 0, c->stream, reinterpret_cast<const S *>(src), Ai,
-                       ex, ey, ez, a);
+    hipLaunchKernelGGL(k_shift_raw<S>, dim3(grid), dim3(256), 0, c->stream, reinterpret_cast<const S *>(src), As,
+                       c->Q, dir, ex, ey, ez, a);
   else
-    hipLaunchKernelGGL(k_encode<S>, dim3(grid), dim3(256), 0, c->stream, src, Ai, ex, ey, ez, w, a);
+    hipLaunchKernelGGL(k_encode<S>, dim3(grid), dim3(256), 0, c->stream, src, As, c->Q, dir, ex, ey, ez, w, a);
 }
 template <typename S>
 static void decode_t(lbm_ctx *c, int dir, const void *A, double *dst, bool raw) {
@@ -333,14 +358,14 @@ static void decode_t(lbm_ctx *c, int dir, const void *A, double *dst, bool raw) 
   int ex, ey, ez;
   double w;
   dir_vec(c->Q, dir, ex, ey, ez, w);
-  const S *Ai = static_cast<const S *>(A) + (uint64_t)dir * c->L.stride;
+  const S *As = static_cast<const S *>(A);
   const uint32_t grid = (uint32_t)((c->N + 255) / 256);
   const uint8_t *fl = c->nsolid > 0 ? c->at<uint8_t>(c->L.flags) : nullptr;
   if (raw)
-    hipLaunchKernelGGL(k_gather_raw<S>, dim3(grid), dim3(256), 0, c->stream, Ai, reinterpret_cast<S *>(dst), ex,
-                       ey, ez, a);
+    hipLaunchKernelGGL(k_gather_raw<S>, dim3(grid), dim3(256), 0, c->stream, As, reinterpret_cast<S *>(dst), c->Q,
+                       dir, ex, ey, ez, a);
   else
-    hipLaunchKernelGGL(k_decode<S>, dim3(grid), dim3(256), 0, c->stream, Ai, dst, ex, ey, ez, w, fl, a);
+    hipLaunchKernelGGL(k_decode<S>, dim3(grid), dim3(256), 0, c->stream, As, dst, c->Q, dir, ex, ey, ez, w, fl, a);
 }
 
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw) {
@@ -401,7 +426,7 @@ __global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, Ma
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const uint32_t sn = m.initial ? cell_id(x - L::ex(i), y - L::ey(i), z - L::ez(i), a) : n;
-    const double h = (double)Store<S>::ld(src + (uint64_t)i * a.stride + sn);
+    const double h = (double)Store<S>::ld(src + pidx<Q>(i, sn));
     drho += h;
     jx += L::ex(i) * h;
     jy += L::ey(i) * h;

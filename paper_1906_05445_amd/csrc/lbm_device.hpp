@@ -126,6 +126,21 @@ __host__ __device__ constexpr bool odd_row(int k) {
 }
 
 // ----------------------------------------------------------------------------
+// population layout: tiles of kTile consecutive cells; inside a tile the Q
+// directions are stored one after the other (kTile values each).  A sweep
+// then streams two contiguous Q*kTile blocks per tile instead of 2Q arrays
+// that are far apart, which keeps the HBM access pattern dense.
+// ----------------------------------------------------------------------------
+constexpr uint32_t kTile = 256;
+template <int Q>
+__host__ __device__ inline uint64_t pidx(int i, uint32_t n) {
+  return (uint64_t)(n / kTile) * (Q * kTile) + (uint64_t)i * kTile + (n % kTile);
+}
+__host__ __device__ inline uint64_t pidx_rt(int Q, int i, uint32_t n) {
+  return (uint64_t)(n / kTile) * ((uint64_t)Q * kTile) + (uint64_t)i * kTile + (n % kTile);
+}
+
+// ----------------------------------------------------------------------------
 // node flags
 // ----------------------------------------------------------------------------
 enum : uint8_t {

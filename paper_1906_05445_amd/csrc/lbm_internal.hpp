@@ -16,7 +16,8 @@ namespace lbm {
 
 constexpr int kMaxQ = 19;
 constexpr int kHistCap = 8192;  // steps of force/torque history kept on the device
-constexpr int kBlock = 256;     // threads per block for per-cell / per-link kernels
+constexpr int kBlock = 256;     // threads per block for per-cell kernels
+constexpr int kLinkChunk = 64;  // links per wavefront of the bounce-back kernel
 
 // Solid as the kernels see it.
 struct DevSolid {
@@ -38,12 +39,46 @@ struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
       partials, solids, hist, staging, macro, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
       lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, misc, total;
-  size_t stride;  // elements per direction (N rounded up to a multiple of 64)
+  size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials;
   int32_t max_solids;
 };
 
 bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lag, Layout *L);
+
+// Per-solid reduction of the bounce-back chunk partials into a history slot.
+struct FtReduceArgs {
+  const double *partials;
+  const SolidLinks *sl;
+  double *hist;
+  int nsolid;
+  uint64_t max_partials;
+};
+
+// Wave-wide sum of a double (64 lanes, fixed order); lane 0 holds the result.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block `blk` (256 threads) reduces solids 4*blk .. 4*blk+3, one per wavefront.
+__device__ inline void ft_reduce_waves(const FtReduceArgs &r, uint32_t blk) {
+  const int lane = threadIdx.x & 63;
+  const int s = (int)(blk * 4 + (threadIdx.x >> 6));
+  if (s >= r.nsolid) return;
+  const SolidLinks L = r.sl[s];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (uint32_t c = lane; c < L.nchunks; c += 64) {
+    const uint64_t at = (uint64_t)L.chunk_base + c;
+    if (at >= r.max_partials) break;
+    for (int k = 0; k < 6; k++) v[k] += r.partials[at * 6 + k];
+  }
+  for (int k = 0; k < 6; k++) {
+    const double tot = wave_sum(v[k]);
+    if (lane == 0) r.hist[(uint64_t)s * 6 + k] = tot;
+  }
+}
 
 }  // namespace lbm
 
@@ -82,6 +117,14 @@ struct lbm_ctx {
   std::vector<double> lag_X, lag_dV;
   bool lag_user;
   bool profiling;
+  int sweep_nt;            // autotuned store policy of the sweep (-1: not tuned yet)
+  struct TuneEvent {
+    int policy;
+    hipEvent_t e0, e1;
+  };
+  std::vector<TuneEvent> tune_events;
+  uint64_t tuned_key;
+  double tune_us[2];       // measured sweep time of the two store policies
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::string err;
   // helpers
@@ -96,7 +139,9 @@ struct lbm_ctx {
 namespace lbm {
 
 // kernels_sweep.hip
-void launch_sweep(lbm_ctx *c, const void *A, void *B);
+// reduce_t >= 0: the launch also reduces the force partials of step reduce_t
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                  int64_t reduce_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
@@ -110,6 +155,7 @@ void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *Bpost);
 void launch_link_scan(lbm_ctx *c);
 void launch_link_emit(lbm_ctx *c, int64_t t);
 void launch_ibb(lbm_ctx *c, void *Bpost, int64_t t);
+FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t);
 void launch_ft_reduce(lbm_ctx *c, int64_t t);
 
 // kernels_ibm.hip

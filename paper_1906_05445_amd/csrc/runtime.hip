@@ -6,7 +6,10 @@
 // allocates device memory.  Every call enqueues work on the caller's stream;
 // only the readout calls synchronise it.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -98,12 +101,12 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   if (max_lag == 0) max_lag = std::max<int64_t>(1024, N / 64);
   if (max_links >= (1ll << 32) || max_lag >= (1ll << 26)) return false;
   Layout l{};
-  l.stride = (size_t)((N + 63) / 64 * 64);
+  l.stride = (size_t)((N + kTile - 1) / kTile * kTile);  // whole tiles
   l.max_links = max_links;
   l.max_lag = max_lag;
   l.max_shell = std::min<int64_t>(N, 64 * max_lag);
   l.max_box_chunks = (N + kBlock - 1) / kBlock;
-  l.max_partials = (max_links + kBlock - 1) / kBlock + max_solids;
+  l.max_partials = (max_links + kLinkChunk - 1) / kLinkChunk + max_solids;
   l.max_solids = max_solids;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -300,6 +303,9 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->nshell = 0;
   c->lag_user = false;
   c->profiling = false;
+  c->sweep_nt = -1;
+  c->tuned_key = 0;
+  c->tune_us[0] = c->tune_us[1] = 0.0;
   c->fresh = true;
   // rest state, cleared flags and ownership
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
@@ -320,6 +326,10 @@ lbm_status lbm_destroy(lbm_ctx *c) {
   for (auto &e : c->prof_events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
+  }
+  for (auto &t : c->tune_events) {
+    (void)hipEventDestroy(t.e0);
+    (void)hipEventDestroy(t.e1);
   }
   delete c;
   return LBM_OK;
@@ -631,26 +641,100 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
   return build_ibm(c);
 }
 
+// ----------------------------------------------------------------------------
+// Sweep autotuner.  The sweep's only free choice is how its stores treat the
+// caches: plain stores keep the freshly written tile in L2 / Infinity Cache
+// (wins when the two population arrays nearly fit the 256 MB cache),
+// non-temporal stores stream past them (wins beyond it).  The first 2R real
+// sweeps of a context run R with each policy, timed by events attached to
+// the dispatches; the faster policy is used from the end of that lbm_step
+// call on and remembered per (lattice, collision, storage, flags, size) for
+// later contexts of this process.  Both policies compute identical values.
+// ----------------------------------------------------------------------------
+static std::map<uint64_t, std::array<double, 3>> g_tune_cache;
+static std::mutex g_tune_mutex;
+static constexpr int kTuneReps = 4;
+
+static uint64_t tune_key(const lbm_ctx *c) {
+  uint64_t k = (uint64_t)c->N;
+  k = k * 31 + (uint64_t)c->Q;
+  k = k * 31 + (uint64_t)c->p.collision * 7 + (c->default_rates ? 1 : 0);
+  k = k * 31 + (uint64_t)c->p.storage;
+  k = k * 31 + (c->nsolid > 0 ? 1 : 0);
+  return k;
+}
+
+// policy for the next sweep; records tuning events when still tuning
+static int tune_policy(lbm_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
+  const uint64_t key = tune_key(c);
+  if (c->tuned_key != key) {
+    for (auto &t : c->tune_events) {
+      (void)hipEventDestroy(t.e0);
+      (void)hipEventDestroy(t.e1);
+    }
+    c->tune_events.clear();
+    c->sweep_nt = -1;
+    c->tuned_key = key;
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->sweep_nt = (int)it->second[0];
+      c->tune_us[0] = it->second[1];
+      c->tune_us[1] = it->second[2];
+    }
+  }
+  if (c->sweep_nt >= 0) return c->sweep_nt;
+  const int k = (int)c->tune_events.size();
+  if (k >= 2 * kTuneReps) return 1;  // decided at the end of this call
+  const int policy = k < kTuneReps ? 0 : 1;
+  if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) return policy;
+  c->tune_events.push_back({policy, *e0, *e1});
+  return policy;
+}
+
+static lbm_status tune_finish(lbm_ctx *c) {
+  if (c->sweep_nt >= 0 || (int)c->tune_events.size() < 2 * kTuneReps) return LBM_OK;
+  HIPCALL(hipStreamSynchronize(c->stream));
+  double sum[2] = {0.0, 0.0};
+  int cnt[2] = {0, 0};
+  for (auto &t : c->tune_events) {
+    float ms = 0.0f;
+    HIPCALL(hipEventElapsedTime(&ms, t.e0, t.e1));
+    sum[t.policy] += ms;
+    cnt[t.policy]++;
+    (void)hipEventDestroy(t.e0);
+    (void)hipEventDestroy(t.e1);
+  }
+  c->tune_events.clear();
+  c->tune_us[0] = 1e3 * sum[0] / std::max(cnt[0], 1);
+  c->tune_us[1] = 1e3 * sum[1] / std::max(cnt[1], 1);
+  c->sweep_nt = c->tune_us[1] < c->tune_us[0] ? 1 : 0;
+  std::lock_guard<std::mutex> g(g_tune_mutex);
+  g_tune_cache[c->tuned_key] = {(double)c->sweep_nt, c->tune_us[0], c->tune_us[1]};
+  return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
+
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
     if (c->method == LBM_IBM && c->nsolid > 0) launch_ibm_step(c, A, c->t);
-    if (c->profiling) {
-      hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int policy = tune_policy(c, &e0, &e1);
+    if (!e0 && c->profiling) {
       HIPCALL(hipEventCreate(&e0));
       HIPCALL(hipEventCreate(&e1));
-      HIPCALL(hipEventRecord(e0, c->stream));
-      launch_sweep(c, A, B);
-      HIPCALL(hipEventRecord(e1, c->stream));
       c->prof_events.push_back({e0, e1});
-    } else {
-      launch_sweep(c, A, B);
     }
+    // the forces of the previous step of this call are reduced inside this sweep
+    // launch (translating solids rebuild the link table first, so they reduce at once)
+    const bool fused_reduce = ibb && k > 0 && !c->any_moving;
+    launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1);
     if (ibb) {
       launch_ibb(c, B, c->t);
-      launch_ft_reduce(c, c->t);
+      if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
         // the refill below writes into neighbours' post-collision slots: keep
         // the macroscopic fields of this collision first (last step of the call)
@@ -666,6 +750,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     c->fresh = false;
   }
   HIPCALL(hipGetLastError());
+  {
+    const lbm_status st = tune_finish(c);
+    if (st != LBM_OK) return st;
+  }
   if (ibb && c->any_moving && nsteps > 0) {
     uint32_t misc[2];
     std::vector<SolidLinks> sl((size_t)c->nsolid);
@@ -850,6 +938,14 @@ lbm_status lbm_check(lbm_ctx *c) {
   HIPCALL(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCALL(hipStreamSynchronize(c->stream));
   if (h) return set_err(c, "non-finite value in the populations"), LBM_EDIVERGED;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain, double *us_nontemporal) {
+  if (!c) return LBM_EINVAL;
+  if (nontemporal) *nontemporal = c->sweep_nt;
+  if (us_plain) *us_plain = c->tune_us[0];
+  if (us_nontemporal) *us_nontemporal = c->tune_us[1];
   return LBM_OK;
 }
 

@@ -94,12 +94,13 @@ _sig("lbm_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_copy_probe", _st, [_vp, _vp, ctypes.c_size_t, _vp])
 _sig("lbm_profile", _st, [_vp, ctypes.c_int32])
 _sig("lbm_profile_read", _st, [_vp, _d, ctypes.POINTER(_i64)])
+_sig("lbm_autotune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d, _d])
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
-            "lbm_profile", "lbm_profile_read"]
+            "lbm_profile", "lbm_profile_read", "lbm_autotune_info"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
 
@@ -278,6 +279,12 @@ class Lattice:
         n = _i64(0)
         self._check(_lib.lbm_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def autotune_info(self):
+        nt = ctypes.c_int32(-1)
+        a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(_lib.lbm_autotune_info(self.handle, ctypes.byref(nt), ctypes.byref(a), ctypes.byref(b)))
+        return {"nontemporal_stores": nt.value, "sweep_us_plain": a.value, "sweep_us_nontemporal": b.value}
 
     def check(self):
         st = _lib.lbm_check(self.handle)
