@@ -39,8 +39,10 @@ def sweep_source_hash():
 
 
 def traffic_for(key, cells):
-    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if they
-    were taken on the current sweep source; otherwise None."""
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (calibrated on a copy kernel), if they were taken on the
+    current sweep source; otherwise None.  The roofline's "traffic" is these
+    bytes over the same average launch duration as "achieved"."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
@@ -77,7 +79,8 @@ def run_case(case, steps, warmup, key, torch, lbm):
     per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
     avg_s = sweep_ms / 1e3 / max(launches, 1)
     achieved = N * per_cell / avg_s / 1e9
-    traffic = traffic_for(key, N)
+    traffic_bytes = traffic_for(key, N)
+    traffic = None if traffic_bytes is None else traffic_bytes / avg_s / 1e9
     out = {
         "mlups": N * steps / wall / 1e6,
         "ms_per_step": wall / steps * 1e3,
@@ -88,7 +91,8 @@ def run_case(case, steps, warmup, key, torch, lbm):
         "sweep_avg_us": avg_s * 1e6,
         "sweep_launches": launches,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": N * per_cell, "traffic_bytes_per_launch": traffic_bytes},
         "drag_x": float(F[0, 0]),
         "autotune": tune,
     }
@@ -98,11 +102,11 @@ def run_case(case, steps, warmup, key, torch, lbm):
     return out
 
 
-def copy_probe(torch, lbm, nbytes=4 << 30, reps=20):
+def copy_probe(torch, lbm, nbytes=4 << 30, reps=20, warm=3):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     s = torch.cuda.current_stream()
-    for _ in range(3):
+    for _ in range(warm if reps > 1 else 0):
         lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
@@ -138,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run the copy kernel once over this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
@@ -168,7 +174,9 @@ def main():
             print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
                   file=sys.stderr, flush=True)
         extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
-    cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps)
+    if args.copy_calibration > 0:
+        copy_probe(torch, lbm, nbytes=args.copy_calibration << 20, reps=1)
+    cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps) if args.cpu_steps > 0 else None
     line = {
         "metric": METRIC,
         "value": primary["mlups"],
