@@ -213,6 +213,79 @@ lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain,
  * streaming copy kernel, the bandwidth yardstick for the sweep. */
 lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent lattices (uneven sizes, own solids, own
+ * relaxation rates and body force) advanced together.  Not in the paper,
+ * which treats one lattice at a time; every member follows exactly the
+ * single-context definition of a step above, so a member's results are bit
+ * for bit those of the same context stepped alone.
+ *
+ * A batch owns a device pool (caller-owned memory, 256-byte aligned, kept
+ * until lbm_batch_destroy).  The first lbm_batch_table_bytes(max_slots)
+ * bytes hold the batch's tables; members are contexts whose workspaces are
+ * carved from the rest.  All members share one lattice and one storage
+ * format, and all batch work runs on a stream the batch creates
+ * (lbm_batch_stream).  Each step is one launch per stage over the units of
+ * all members, replayed from a captured HIP graph; the first steps of a new
+ * total size tune the sweep's launch shape and store policy.
+ * A batch and its members must not be used by two host threads at once.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes at the head of the pool taken by the tables of max_slots members. */
+size_t lbm_batch_table_bytes(int32_t max_slots);
+
+/* Create a batch of up to max_slots members in dev_pool.  lattice is an
+ * lbm_lattice and storage an lbm_storage shared by every member.
+ * Errors: LBM_EINVAL, LBM_ENOMEM (pool smaller than the tables), LBM_EDEVICE. */
+lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots, void *dev_pool, size_t pool_bytes,
+                            lbm_batch **out);
+
+/* Admit a member: a context as from lbm_create (same parameters) whose
+ * workspace of lbm_workspace_bytes(p, ...) bytes is taken from the pool.
+ * It is configured and read with the ordinary context calls (lbm_set_solids,
+ * lbm_force_torque, lbm_macros, ...) and may even be stepped alone with
+ * lbm_step; lbm_destroy refuses it.  LBM_EAGAIN: no free slot, or no
+ * contiguous free range of that size (retry after a release). */
+lbm_status lbm_batch_admit(lbm_batch *b, const lbm_params *p, int32_t max_solids, int64_t max_links,
+                           int64_t max_lagrangian, lbm_ctx **out);
+
+/* Release a member: its context is destroyed and its pool range returned. */
+lbm_status lbm_batch_release(lbm_batch *b, lbm_ctx *c);
+
+/* Advance every member by nsteps steps.  Returns after enqueueing, except
+ * when a member has translating solids: then the stream is synchronised and
+ * the members' link capacities are checked (LBM_ENOMEM when exceeded, with
+ * the member's lbm_last_error naming the capacity). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Wait for the batch's stream. */
+lbm_status lbm_batch_sync(lbm_batch *b);
+
+/* Members, free pool bytes, largest contiguous free range, total cells. */
+lbm_status lbm_batch_info(lbm_batch *b, int32_t *members, size_t *bytes_free, size_t *largest_free,
+                          int64_t *total_cells);
+
+/* Sweep launch shape chosen by the tuner: non-temporal stores (0/1), unit
+ * order (0 contiguous share per block, 1 round-robin), persistent blocks,
+ * and its measured time per step (us, all members).  LBM_ESTATE before the
+ * tuner has finished. */
+lbm_status lbm_batch_tune_info(lbm_batch *b, int32_t *nontemporal, int32_t *order, int32_t *blocks,
+                               double *sweep_us);
+
+/* Advance nsteps steps launched one by one (not from the graph) with events
+ * on the sweep dispatches; returns the mean sweep time per step (us).  For
+ * measurement; needs a tuned batch whose members have not changed since its
+ * last lbm_batch_step (LBM_ESTATE otherwise). */
+lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us);
+
+/* The batch's HIP stream (a hipStream_t). */
+void *lbm_batch_stream(lbm_batch *b);
+
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+/* Destroy the batch and every member left in it (the pool is not freed). */
+lbm_status lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,21 +9,12 @@
 // solid node x_b = x_f - e_i; the bounce-back kernel writes the unknown
 // f_i(x_f, t+1) into slot i of x_b, exactly where the next pull sweep at x_f
 // looks for population i.
-#include "lbm_geom.hpp"
+#include <algorithm>
+
+#include "lbm_args.hpp"
 
 namespace lbm {
 
-struct GeoArgs {
-  Box3 b;
-  uint32_t N;
-  FastDiv fx, fy;
-  uint64_t stride;
-  const DevSolid *solids;
-  int nsolid;
-  int ibb;         // 1 = solids remove nodes from the fluid (IBB), 0 = IBM
-  int fluid_only;  // body force only outside solids
-  int64_t t;       // geometry time
-};
 
 __device__ inline void xyz_of(uint32_t n, const GeoArgs &a, int &x, int &y, int &z) {
   const uint32_t yz = fdiv(n, a.fx);
@@ -94,51 +85,38 @@ __global__ void k_classify_full(uint8_t *flags, uint16_t *owner, uint16_t *owner
 }
 
 // Moving solids, phase 1 over their boxes: remember the current geometry.
-__global__ void k_classify_keep(uint8_t *flags, const uint16_t *owner, uint16_t *owner_prev, GeoArgs a) {
-  const DevSolid &s = a.solids[blockIdx.y];
-  if (!s.moving) return;
+__device__ inline void classify_keep_body(const LinkArgs &a, uint32_t bx, int s) {
+  const DevSolid &sd = a.g.solids[s];
+  if (!sd.moving) return;
   int o[3], x, y, z;
-  box_origin(s, a, o);
-  if (!box_cell(s, o, blockIdx.x * blockDim.x + threadIdx.x, a, x, y, z)) return;
-  const uint32_t n = id_of(x, y, z, a);
-  const uint8_t f = flags[n];
-  flags[n] = (f & F_SOLID) ? (f | F_WAS_SOLID) : (uint8_t)(f & ~F_WAS_SOLID);
-  owner_prev[n] = owner[n];
+  box_origin(sd, a.g, o);
+  if (!box_cell(sd, o, bx * blockDim.x + threadIdx.x, a.g, x, y, z)) return;
+  const uint32_t n = id_of(x, y, z, a.g);
+  const uint8_t f = a.flags[n];
+  a.flags[n] = (f & F_SOLID) ? (f | F_WAS_SOLID) : (uint8_t)(f & ~F_WAS_SOLID);
+  a.owner_prev[n] = a.owner[n];
 }
 // Moving solids, phase 2 over their boxes: classify at the new time.
-__global__ void k_classify_box(uint8_t *flags, uint16_t *owner, GeoArgs a) {
-  const DevSolid &s = a.solids[blockIdx.y];
-  if (!s.moving) return;
+__device__ inline void classify_box_body(const LinkArgs &a, uint32_t bx, int s) {
+  const DevSolid &sd = a.g.solids[s];
+  if (!sd.moving) return;
   int o[3], x, y, z;
-  box_origin(s, a, o);
-  if (!box_cell(s, o, blockIdx.x * blockDim.x + threadIdx.x, a, x, y, z)) return;
-  const uint32_t n = id_of(x, y, z, a);
-  const int k = classify_cell(a, x, y, z);
-  const uint8_t old = flags[n];
-  flags[n] = (uint8_t)(flags_for(a, k, old & F_IBM) | (old & F_WAS_SOLID));
-  owner[n] = k < 0 ? 0xFFFF : (uint16_t)k;
+  box_origin(sd, a.g, o);
+  if (!box_cell(sd, o, bx * blockDim.x + threadIdx.x, a.g, x, y, z)) return;
+  const uint32_t n = id_of(x, y, z, a.g);
+  const int k = classify_cell(a.g, x, y, z);
+  const uint8_t old = a.flags[n];
+  a.flags[n] = (uint8_t)(flags_for(a.g, k, old & F_IBM) | (old & F_WAS_SOLID));
+  a.owner[n] = k < 0 ? 0xFFFF : (uint16_t)k;
 }
+__global__ void k_classify_keep(LinkArgs a) { classify_keep_body(a, blockIdx.x, blockIdx.y); }
+__global__ void k_classify_box(LinkArgs a) { classify_box_body(a, blockIdx.x, blockIdx.y); }
 
 void launch_classify(lbm_ctx *c, int64_t t, bool full);
 
 // ----------------------------------------------------------------------------
 // link builder
 // ----------------------------------------------------------------------------
-struct LinkArgs {
-  GeoArgs g;
-  const uint8_t *flags;
-  const uint16_t *owner, *owner_prev;
-  uint32_t *box_counts;    // [nsolid][max_box_chunks]
-  uint32_t *box_offsets;   // exclusive scan of box_counts
-  uint32_t max_box_chunks;
-  uint32_t *link_cell, *link_meta;
-  double *link_q;
-  uint64_t max_links;
-  SolidLinks *sl;
-  uint32_t *misc;          // [0] total links, [1] overflow flag
-  void *post;              // refill: post-collision array of step t-1 -> t
-  int refill;
-};
 
 // Links of cell n whose solid node belongs to solid s; bit i of the result.
 template <int Q>
@@ -189,14 +167,13 @@ __device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
 }
 
 template <int Q, typename S>
-__global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
+__device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ double lds[16];
-  const int s = blockIdx.y;
   const DevSolid &sd = a.g.solids[s];
   int o[3], x, y, z;
   box_origin(sd, a.g, o);
   uint32_t cnt = 0;
-  if (box_cell(sd, o, blockIdx.x * kBlock + threadIdx.x, a.g, x, y, z)) {
+  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z)) {
     const uint32_t n = id_of(x, y, z, a.g);
     const uint8_t f = a.flags[n];
     if (!(f & F_SOLID)) {
@@ -205,13 +182,16 @@ __global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
     }
   }
   const double tot = block_sum((double)cnt, lds);
-  if (threadIdx.x == 0 && blockIdx.x < a.max_box_chunks)
-    a.box_counts[(uint64_t)s * a.max_box_chunks + blockIdx.x] = (uint32_t)tot;
+  if (threadIdx.x == 0 && bx < a.max_box_chunks) a.box_counts[(uint64_t)s * a.max_box_chunks + bx] = (uint32_t)tot;
+}
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
+  link_count_body<Q, S>(a, blockIdx.x, blockIdx.y);
 }
 
 // One block: exclusive scan of the per-(solid, box chunk) counts, then the
 // per-solid link ranges and chunk bases of the bounce-back kernel.
-__global__ void k_link_scan(LinkArgs a, int nsolid) {
+__device__ inline void link_scan_body(const LinkArgs &a, int nsolid) {
   __shared__ uint32_t part[1024];
   const uint32_t total = (uint32_t)nsolid * a.max_box_chunks;
   const uint32_t per = (total + blockDim.x - 1) / blockDim.x;
@@ -253,16 +233,16 @@ __global__ void k_link_scan(LinkArgs a, int nsolid) {
     }
   }
 }
+__global__ void k_link_scan(LinkArgs a, int nsolid) { link_scan_body(a, nsolid); }
 
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
+__device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ uint32_t pre[kBlock];
-  const int s = blockIdx.y;
   const DevSolid &sd = a.g.solids[s];
   int o[3], x = 0, y = 0, z = 0;
   box_origin(sd, a.g, o);
   uint32_t m = 0;
-  if (box_cell(sd, o, blockIdx.x * kBlock + threadIdx.x, a.g, x, y, z)) {
+  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z)) {
     const uint32_t n = id_of(x, y, z, a.g);
     if (!(a.flags[n] & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
   }
@@ -275,8 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
     pre[threadIdx.x] += v;
     __syncthreads();
   }
-  if (!m || blockIdx.x >= a.max_box_chunks) return;
-  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + blockIdx.x] + pre[threadIdx.x] - __popc(m);
+  if (!m || bx >= a.max_box_chunks) return;
+  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx] + pre[threadIdx.x] - __popc(m);
   const uint32_t n = id_of(x, y, z, a.g);
   double c[3];
   solid_centre(sd, a.g.t, a.g.b, c);
@@ -295,19 +275,14 @@ __global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
     pos++;
   }
 }
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
+  link_emit_body<Q>(a, blockIdx.x, blockIdx.y);
+}
 
 // ----------------------------------------------------------------------------
 // interpolated bounce-back + momentum exchange (one thread per link)
 // ----------------------------------------------------------------------------
-struct IbbArgs {
-  GeoArgs g;
-  const uint32_t *link_cell, *link_meta;
-  const double *link_q;
-  const SolidLinks *sl;
-  double *partials;  // [chunk][6]
-  uint64_t max_links, max_partials;
-  int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC
-};
 
 // Unknown deviation h_i(x_f, t+1) of one link.  hb_*: post-collision h_ibar at
 // x_f, x_ff, x_fff; hs_*: post-collision h_i at x_f, x_ff (= h_i at x_ff,
@@ -341,15 +316,14 @@ __device__ inline C ibb_value(int method, double q, bool ffok, bool fffok, C hb_
 // One wavefront per chunk of kLinkChunk links of one solid; each wave writes
 // the chunk's force/torque partial (summed per solid in chunk order later).
 template <int Q, typename S>
-__global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
+__device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, uint32_t bx, int s) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  const int s = blockIdx.y;
   const SolidLinks sl = a.sl[s];
   const int lane = threadIdx.x;
-  const bool active = blockIdx.x < sl.nchunks && (uint64_t)sl.chunk_base + blockIdx.x < a.max_partials;
+  const bool active = bx < sl.nchunks && (uint64_t)sl.chunk_base + bx < a.max_partials;
   if (active) {
-    const uint32_t li = blockIdx.x * kLinkChunk + lane;
+    const uint32_t li = bx * kLinkChunk + lane;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     // capacity overflow (reported by the host after the step) must not read out of bounds
     if (li < sl.count && (uint64_t)sl.start + li < a.max_links) {
@@ -372,7 +346,7 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
         }
       const DevSolid &sd = a.g.solids[s];
       double c[3], r[3], uw[3];
-      solid_centre(sd, a.g.t, a.g.b, c);
+      solid_centre(sd, t, a.g.b, c);
       lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
       wall_vel(sd, r, uw);
       const double Bw = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
@@ -403,9 +377,13 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
     }
     for (int k = 0; k < 6; k++) {
       const double tot = wave_sum(acc[k]);
-      if (lane == 0) a.partials[(uint64_t)(sl.chunk_base + blockIdx.x) * 6 + k] = tot;
+      if (lane == 0) a.partials[(uint64_t)(sl.chunk_base + bx) * 6 + k] = tot;
     }
   }
+}
+template <int Q, typename S>
+__global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
+  ibb_body<Q, S>(P, a, a.g.t, blockIdx.x, blockIdx.y);
 }
 
 // Per-solid force/torque: one wavefront per solid sums that solid's chunk
@@ -413,6 +391,144 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
 // lbm_step call; earlier steps are reduced inside the next sweep launch).
 __global__ __launch_bounds__(256) void k_ft_reduce(FtReduceArgs r) {
   ft_reduce_waves(r, blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------
+// batched forms: the same bodies over the members of a work list, each at its
+// own time t = t0 + k and state parity (k: the batch step counter)
+// ----------------------------------------------------------------------------
+__device__ inline int64_t slot_time(const BatchSlot &sl, int64_t k) { return sl.t0 + k; }
+__device__ inline void *slot_post(const BatchSlot &sl, int64_t k) { return sl.P[(sl.cur0 ^ (int)(k & 1)) ^ 1]; }
+
+// bounce-back on the post-collision array of this step; unit = (solid, chunk)
+template <int Q, typename S>
+__global__ __launch_bounds__(64) void k_ibb_batch(const BatchSlot *__restrict__ slots, const WorkList *__restrict__ wl,
+                                                   const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 1, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    const uint32_t per = (uint32_t)sl.k5_chunks;
+    const int s = (int)(u / per);
+    ibb_body<Q, S>(static_cast<S *>(slot_post(sl, k)), sl.ib, slot_time(sl, k), u - (uint32_t)s * per, s);
+  });
+}
+
+// per-solid force/torque of this step into the lattice's history ring
+__global__ __launch_bounds__(256) void k_ft_batch(const BatchSlot *__restrict__ slots, const WorkList *__restrict__ wl,
+                                                  const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    FtReduceArgs r = sl.ft;
+    r.hist = sl.hist + (uint64_t)(slot_time(sl, k) % kHistCap) * (uint64_t)sl.max_solids * 6;
+    ft_reduce_waves(r, u);
+  });
+}
+
+// translating solids move to t + 1: keep, classify, count (with refill),
+// scan, emit -- each over the (solid, box chunk) units of the moving members
+__device__ inline LinkArgs move_args(const BatchSlot &sl, int64_t k) {
+  LinkArgs a = sl.lk;
+  a.g.t = slot_time(sl, k) + 1;
+  a.post = slot_post(sl, k);
+  a.refill = 1;
+  return a;
+}
+__global__ __launch_bounds__(kBlock) void k_classify_keep_batch(const BatchSlot *__restrict__ slots,
+                                                                const WorkList *__restrict__ wl,
+                                                                const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const LinkArgs a = move_args(slots[m], k);
+    const int s = (int)(u / a.max_box_chunks);
+    classify_keep_body(a, u - (uint32_t)s * a.max_box_chunks, s);
+  });
+}
+__global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *__restrict__ slots,
+                                                               const WorkList *__restrict__ wl,
+                                                               const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const LinkArgs a = move_args(slots[m], k);
+    const int s = (int)(u / a.max_box_chunks);
+    classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
+  });
+}
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__restrict__ slots,
+                                                             const WorkList *__restrict__ wl,
+                                                             const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const LinkArgs a = move_args(slots[m], k);
+    const int s = (int)(u / a.max_box_chunks);
+    link_count_body<Q, S>(a, u - (uint32_t)s * a.max_box_chunks, s);
+  });
+}
+// one unit per member; also folds the capacity checks into its status words
+__global__ __launch_bounds__(1024) void k_link_scan_batch(const BatchSlot *__restrict__ slots,
+                                                          const WorkList *__restrict__ wl) {
+  batch_units(wl, 0, [&](int m, uint32_t) {
+    const BatchSlot &sl = slots[m];
+    link_scan_body(sl.lk, sl.nsolid);
+    if (threadIdx.x == 0) {
+      uint32_t bad = sl.lk.misc[1] ? (uint32_t)BS_LINKS_OVERFLOW : 0u;
+      for (int s = 0; s < sl.nsolid; s++)
+        if (sl.lk.sl[s].nchunks > (uint32_t)sl.k5_chunks) bad |= BS_CHUNKS_OVERFLOW;
+      sl.status[0] |= bad;
+      sl.status[1] = sl.lk.misc[0];
+    }
+    __syncthreads();
+  });
+}
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_link_emit_batch(const BatchSlot *__restrict__ slots,
+                                                            const WorkList *__restrict__ wl,
+                                                            const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const LinkArgs a = move_args(slots[m], k);
+    const int s = (int)(u / a.max_box_chunks);
+    link_emit_body<Q>(a, u - (uint32_t)s * a.max_box_chunks, s);
+  });
+}
+
+void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
+#define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb_batch<QQ, SS>), dim3(grid), dim3(64), 0, b.stream, b.slots, wl, b.step)
+  if (b.Q == 9) {
+    if (b.storage == LBM_F64) LBM_IBB(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_IBB(9, float);
+    else LBM_IBB(9, _Float16);
+  } else {
+    if (b.storage == LBM_F64) LBM_IBB(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_IBB(19, float);
+    else LBM_IBB(19, _Float16);
+  }
+#undef LBM_IBB
+}
+
+void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
+  hipLaunchKernelGGL(k_ft_batch, dim3(grid), dim3(256), 0, b.stream, b.slots, wl, b.step);
+}
+
+void launch_move_batch(const BatchLaunch &b, const WorkList *box, const WorkList *one, uint32_t grid) {
+  const dim3 g(grid), blk(kBlock);
+  hipLaunchKernelGGL(k_classify_keep_batch, g, blk, 0, b.stream, b.slots, box, b.step);
+  hipLaunchKernelGGL(k_classify_box_batch, g, blk, 0, b.stream, b.slots, box, b.step);
+#define LBM_LC(QQ, SS) hipLaunchKernelGGL((k_link_count_batch<QQ, SS>), g, blk, 0, b.stream, b.slots, box, b.step)
+  if (b.Q == 9) {
+    if (b.storage == LBM_F64) LBM_LC(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_LC(9, float);
+    else LBM_LC(9, _Float16);
+  } else {
+    if (b.storage == LBM_F64) LBM_LC(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_LC(19, float);
+    else LBM_LC(19, _Float16);
+  }
+#undef LBM_LC
+  hipLaunchKernelGGL(k_link_scan_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, one);
+  if (b.Q == 9) hipLaunchKernelGGL(k_link_emit_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
+  else hipLaunchKernelGGL(k_link_emit_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
 }
 
 // ----------------------------------------------------------------------------
@@ -451,18 +567,33 @@ static LinkArgs link_args(const lbm_ctx *c, int64_t t) {
   return a;
 }
 
+void fill_link_args(lbm_ctx *c, LinkArgs *a) { *a = link_args(c, c->t); }
+
+void fill_ibb_args(lbm_ctx *c, IbbArgs *ap) {
+  IbbArgs &a = *ap;
+  a = IbbArgs{};
+  a.g = geo_args(c, c->t);
+  a.link_cell = c->at<uint32_t>(c->L.link_cell);
+  a.link_meta = c->at<uint32_t>(c->L.link_meta);
+  a.link_q = c->at<double>(c->L.link_q);
+  a.sl = c->at<SolidLinks>(c->L.solid_links);
+  a.partials = c->at<double>(c->L.partials);
+  a.method = c->method;
+  a.max_links = (uint64_t)c->L.max_links;
+  a.max_partials = (uint64_t)c->L.max_partials;
+}
+
 void launch_classify(lbm_ctx *c, int64_t t, bool full) {
-  GeoArgs g = geo_args(c, t);
-  uint8_t *flags = c->at<uint8_t>(c->L.flags);
-  uint16_t *own = c->at<uint16_t>(c->L.owner0), *prev = c->at<uint16_t>(c->L.owner1);
   if (full) {
-    hipLaunchKernelGGL(k_classify_full, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream, flags, own,
-                       prev, g);
+    GeoArgs g = geo_args(c, t);
+    hipLaunchKernelGGL(k_classify_full, dim3((uint32_t)((c->N + 255) / 256)), dim3(256), 0, c->stream,
+                       c->at<uint8_t>(c->L.flags), c->at<uint16_t>(c->L.owner0), c->at<uint16_t>(c->L.owner1), g);
     return;
   }
+  LinkArgs a = link_args(c, t);
   const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
-  hipLaunchKernelGGL(k_classify_keep, grid, dim3(kBlock), 0, c->stream, flags, own, prev, g);
-  hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, flags, own, g);
+  hipLaunchKernelGGL(k_classify_keep, grid, dim3(kBlock), 0, c->stream, a);
+  hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, a);
 }
 
 void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *post) {
@@ -497,16 +628,9 @@ void launch_link_emit(lbm_ctx *c, int64_t t) {
 
 void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
   if (c->k5_chunks <= 0) return;
-  IbbArgs a{};
-  a.g = geo_args(c, t);
-  a.link_cell = c->at<uint32_t>(c->L.link_cell);
-  a.link_meta = c->at<uint32_t>(c->L.link_meta);
-  a.link_q = c->at<double>(c->L.link_q);
-  a.sl = c->at<SolidLinks>(c->L.solid_links);
-  a.partials = c->at<double>(c->L.partials);
-  a.method = c->method;
-  a.max_links = (uint64_t)c->L.max_links;
-  a.max_partials = (uint64_t)c->L.max_partials;
+  IbbArgs a;
+  fill_ibb_args(c, &a);
+  a.g.t = t;
   const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
 #define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(64), 0, c->stream, static_cast<SS *>(P), a)
   if (c->Q == 9) {

@@ -8,7 +8,9 @@
 // stencil slot) that cover it sorted by point.  Interpolation is a gather
 // per point; spreading is a gather per shell cell over that list, so no
 // atomics are used and every sum has a fixed order.
-#include "lbm_geom.hpp"
+#include <algorithm>
+
+#include "lbm_args.hpp"
 
 namespace lbm {
 
@@ -20,28 +22,6 @@ __device__ inline double phi4(double r) {
   return 0.125 * (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r));
 }
 
-struct IbmArgs {
-  Box3 b;
-  uint32_t N;
-  FastDiv fx, fy;
-  uint64_t stride;
-  int64_t nlag, nshell;
-  const double *X, *dV;
-  const int32_t *sid;
-  double *Ud;            // [nlag][3]
-  const int32_t *base;   // [nlag][3] floor(X) - 1
-  double *wts;           // [nlag][12] per-axis weights
-  const uint32_t *idx;   // [nlag][64] shell index of each stencil slot
-  double *Fsum;          // [nlag][3] FP64 total boundary force of the step
-  void *Fk;              // [nlag][3] compute type, force of the current iteration
-  const uint32_t *shell_cell, *rowptr, *ent;
-  void *ushell, *fshell; // [3][nshell] compute type
-  void *fibm;            // [3][stride] compute type
-  uint8_t *flags;
-  const DevSolid *solids;
-  double g[3];
-  int64_t t;
-};
 
 // setup: delta weights and desired velocity U^d = U + Omega x (X - Y)
 __global__ void k_ibm_weights(IbmArgs a) {
@@ -69,10 +49,9 @@ __global__ void k_ibm_mark(IbmArgs a) {
 // u0 = (j + g/2)/rho at every shell cell from the populations f(t), gathered
 // from the shifted state (A_i(x - e_i)); clears the spread force.
 template <int Q, typename S>
-__global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
+__device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, int64_t s) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= a.nshell) return;
   const uint32_t n = a.shell_cell[s];
   const uint32_t yz = fdiv(n, a.fx);
@@ -103,8 +82,7 @@ __global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
 
 // Eq. 5 and Eq. 7: interpolate u to the point, F = rho0 (U^d - U~)/dt.
 template <typename C>
-__global__ void k_ibm_interp(IbmArgs a, int first) {
-  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ inline void ibm_interp_body(const IbmArgs &a, int first, int64_t l) {
   if (l >= a.nlag) return;
   const C *u = static_cast<const C *>(a.ushell);
   const double *w = a.wts + l * 12;
@@ -131,8 +109,7 @@ __global__ void k_ibm_interp(IbmArgs a, int first) {
 
 // Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.
 template <typename C>
-__global__ void k_ibm_spread(IbmArgs a, int last) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
   if (s >= a.nshell) return;
   const C *Fk = static_cast<const C *>(a.Fk);
   C f[3] = {0, 0, 0};
@@ -158,9 +135,8 @@ __global__ void k_ibm_spread(IbmArgs a, int last) {
 }
 
 // Force -sum F_l dV_l and torque -sum (X_l - Y) x F_l dV_l on each solid.
-__global__ void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
+__device__ inline void ibm_ft_body(const IbmArgs &a, const int64_t *start, const int64_t *count, double *hist, int s) {
   __shared__ double lds[16];
-  const int s = blockIdx.x;
   const DevSolid &sd = a.solids[s];
   double c[3];
   solid_centre(sd, a.t, a.b, c);
@@ -180,6 +156,66 @@ __global__ void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, 
     const double tot = block_sum(acc[k], lds);
     if (threadIdx.x == 0) hist[(uint64_t)s * 6 + k] = tot;
   }
+}
+
+template <int Q, typename S>
+__global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
+  ibm_u0_body<Q, S>(A, a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+template <typename C>
+__global__ void k_ibm_interp(IbmArgs a, int first) {
+  ibm_interp_body<C>(a, first, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+template <typename C>
+__global__ void k_ibm_spread(IbmArgs a, int last) {
+  ibm_spread_body<C>(a, last, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+__global__ void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
+  ibm_ft_body(a, start, count, hist, blockIdx.x);
+}
+
+// Batched forms over the IBM members of a batch (state P[cur0 ^ (k & 1)] at
+// t = t0 + k); a member takes part in forcing iteration `it` while
+// it < n_iter.  Units: 128 shell cells or points; one solid for the force.
+template <int Q, typename S>
+__global__ __launch_bounds__(128) void k_ibm_u0_batch(const BatchSlot *__restrict__ slots,
+                                                      const WorkList *__restrict__ wl,
+                                                      const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    IbmArgs a = sl.im;
+    a.t = sl.t0 + k;
+    ibm_u0_body<Q, S>(static_cast<const S *>(sl.P[sl.cur0 ^ (int)(k & 1)]), a, (int64_t)u * 128 + threadIdx.x);
+  });
+}
+template <typename C>
+__global__ __launch_bounds__(128) void k_ibm_interp_batch(const BatchSlot *__restrict__ slots,
+                                                          const WorkList *__restrict__ wl, int it) {
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    if (it < sl.n_iter) ibm_interp_body<C>(sl.im, it == 0 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+  });
+}
+template <typename C>
+__global__ __launch_bounds__(128) void k_ibm_spread_batch(const BatchSlot *__restrict__ slots,
+                                                          const WorkList *__restrict__ wl, int it) {
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    if (it < sl.n_iter) ibm_spread_body<C>(sl.im, it == sl.n_iter - 1 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+  });
+}
+__global__ __launch_bounds__(256) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
+                                                      const WorkList *__restrict__ wl,
+                                                      const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const BatchSlot &sl = slots[m];
+    IbmArgs a = sl.im;
+    a.t = sl.t0 + k;
+    double *hist = sl.hist + (uint64_t)(a.t % kHistCap) * (uint64_t)sl.max_solids * 6;
+    ibm_ft_body(a, sl.lag_start, sl.lag_count, hist, (int)u);
+  });
 }
 
 static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
@@ -236,6 +272,31 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t) {
   double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
   hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(256), 0, c->stream, a,
                      c->at<int64_t>(c->L.misc + 64), c->at<int64_t>(c->L.misc + 64 + 8 * c->L.max_solids), hist);
+}
+
+void fill_ibm_args(lbm_ctx *c, IbmArgs *a) { *a = ibm_args(c, c->t); }
+
+template <typename S>
+static void ibm_batch_t(const BatchLaunch &b, const WorkList *shell, const WorkList *lag, const WorkList *ft,
+                        int max_iter, uint32_t grid) {
+  using C = typename Store<S>::C;
+  if (b.Q == 9)
+    hipLaunchKernelGGL((k_ibm_u0_batch<9, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
+  else
+    hipLaunchKernelGGL((k_ibm_u0_batch<19, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
+  for (int it = 0; it < max_iter; it++) {
+    hipLaunchKernelGGL(k_ibm_interp_batch<C>, dim3(grid), dim3(128), 0, b.stream, b.slots, lag, it);
+    hipLaunchKernelGGL(k_ibm_spread_batch<C>, dim3(grid), dim3(128), 0, b.stream, b.slots, shell, it);
+  }
+  hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(256), 0, b.stream, b.slots, ft,
+                     b.step);
+}
+
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *shell, const WorkList *lag, const WorkList *ft,
+                      int max_iter, uint32_t grid) {
+  if (b.storage == LBM_F64) ibm_batch_t<double>(b, shell, lag, ft, max_iter, grid);
+  else if (b.storage == LBM_F32_DEV) ibm_batch_t<float>(b, shell, lag, ft, max_iter, grid);
+  else ibm_batch_t<_Float16>(b, shell, lag, ft, max_iter, grid);
 }
 
 void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t) {

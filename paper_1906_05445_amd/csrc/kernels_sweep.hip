@@ -11,36 +11,19 @@
 // [Q][stride], x fastest, so each of the 2Q streams is coalesced.
 #include <hip/hip_ext.h>
 
-#include "lbm_geom.hpp"
+#include "lbm_args.hpp"
 
 namespace lbm {
 
 enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
 
-struct SweepArgs {
-  uint32_t N, nx, ny, nz;
-  FastDiv fx, fy;
-  uint64_t stride;
-  const uint8_t *flags;
-  const void *fibm;  // [3][stride] compute type, read where F_IBM is set
-  double g[3];
-  double omega;          // BGK
-  double sp, sm;         // two-rate MRT: even and odd non-conserved rates
-  double sA[kMaxQ];      // general MRT: -s_k / |M_k|^2
-  double sB[kMaxQ];      //              (1 - s_k/2) / |M_k|^2
-  uint32_t rblocks;      // leading blocks that reduce the previous step's force partials
-  FtReduceArgs ft;
-};
 
 template <int Q, int COLL, typename S, int FLAGS, int NT>
-__global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
+                                           uint32_t blk) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  if (blockIdx.x < a.rblocks) {  // dispatched first, finished long before the sweep's tail
-    ft_reduce_waves(a.ft, blockIdx.x);
-    return;
-  }
-  const uint32_t n = (blockIdx.x - a.rblocks) * kBlock + threadIdx.x;
+  const uint32_t n = blk * kBlock + threadIdx.x;
   if (n >= a.N) return;
   uint8_t fl = 0;
   if (FLAGS) {
@@ -162,6 +145,74 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__
   }
 }
 
+template <int Q, int COLL, typename S, int FLAGS, int NT>
+__global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
+  if (blockIdx.x < a.rblocks) {  // dispatched first, finished long before the sweep's tail
+    ft_reduce_waves(a.ft, blockIdx.x);
+    return;
+  }
+  sweep_body<Q, COLL, S, FLAGS, NT>(A, B, a, blockIdx.x - a.rblocks);
+}
+
+// Batched sweep: the tiles of every lattice of a work list in one persistent
+// launch; each lattice keeps its own arguments, size and state parity.
+template <int Q, int COLL, typename S, int NT>
+__global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchSlot *__restrict__ slots,
+                                                         const WorkList *__restrict__ wl,
+                                                         const int64_t *__restrict__ step, int order) {
+  const int par = (int)(*step & 1);
+  batch_units(wl, order, [&](int m, uint32_t blk) {
+    const BatchSlot &sl = slots[m];
+    const int cur = sl.cur0 ^ par;
+    sweep_body<Q, COLL, S, 1, NT>(static_cast<const S *>(sl.P[cur]), static_cast<S *>(sl.P[cur ^ 1]), sl.sw, blk);
+  });
+}
+
+template <int Q, typename S>
+static void sweep_batch_t(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,
+                          hipEvent_t e0, hipEvent_t e1) {
+  // events (tuning, timing) are attached to the dispatch; graph capture takes plain launches
+#define LBM_SB(CC, NN)                                                                                          \
+  do {                                                                                                          \
+    if (e0 || e1)                                                                                               \
+      hipExtLaunchKernelGGL((k_sweep_batch<Q, CC, S, NN>), dim3(grid), dim3(kBlock), 0, b.stream, e0, e1, 0,    \
+                            b.slots, wl, b.step, order);                                                        \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_sweep_batch<Q, CC, S, NN>), dim3(grid), dim3(kBlock), 0, b.stream, b.slots, wl,     \
+                         b.step, order);                                                                        \
+  } while (0)
+  if (coll == COLL_BGK) {
+    if (nt) LBM_SB(COLL_BGK, 1);
+    else LBM_SB(COLL_BGK, 0);
+  } else if (coll == COLL_TRT) {
+    if (nt) LBM_SB(COLL_TRT, 1);
+    else LBM_SB(COLL_TRT, 0);
+  } else {
+    if (nt) LBM_SB(COLL_MRT, 1);
+    else LBM_SB(COLL_MRT, 0);
+  }
+#undef LBM_SB
+}
+
+void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,
+                        hipEvent_t e0, hipEvent_t e1) {
+  if (b.Q == 9) {
+    if (b.storage == LBM_F64) sweep_batch_t<9, double>(b, wl, coll, nt, order, grid, e0, e1);
+    else if (b.storage == LBM_F32_DEV) sweep_batch_t<9, float>(b, wl, coll, nt, order, grid, e0, e1);
+    else sweep_batch_t<9, _Float16>(b, wl, coll, nt, order, grid, e0, e1);
+  } else {
+    if (b.storage == LBM_F64) sweep_batch_t<19, double>(b, wl, coll, nt, order, grid, e0, e1);
+    else if (b.storage == LBM_F32_DEV) sweep_batch_t<19, float>(b, wl, coll, nt, order, grid, e0, e1);
+    else sweep_batch_t<19, _Float16>(b, wl, coll, nt, order, grid, e0, e1);
+  }
+}
+
+// Batch step counter: advanced once at the end of every batched step.
+__global__ void k_tick(int64_t *step) {
+  if (threadIdx.x == 0) step[0] = step[0] + 1;
+}
+void launch_tick(hipStream_t s, int64_t *step) { hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, step); }
+
 template <typename S>
 static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags, bool nt,
                            hipEvent_t e0, hipEvent_t e1) {
@@ -220,8 +271,9 @@ static void mrt_coeffs(const lbm_ctx *c, SweepArgs &a) {
   }
 }
 
-void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t) {
-  SweepArgs a{};
+// Sweep arguments of a context; returns the collision kind.
+static int make_sweep_args(lbm_ctx *c, SweepArgs &a) {
+  a = SweepArgs{};
   a.N = (uint32_t)c->N;
   a.nx = (uint32_t)c->p.nx;
   a.ny = (uint32_t)c->p.ny;
@@ -232,10 +284,6 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hip
   a.flags = c->at<uint8_t>(c->L.flags);
   a.fibm = c->ws + c->L.fibm;
   for (int k = 0; k < 3; k++) a.g[k] = c->p.body_force[k];
-  if (reduce_t >= 0 && c->k5_chunks > 0) {
-    a.ft = ft_reduce_args(c, reduce_t);
-    a.rblocks = (uint32_t)((c->nsolid + 3) / 4);
-  }
   int coll;
   if (c->p.collision == LBM_BGK) {
     coll = COLL_BGK;
@@ -246,6 +294,25 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hip
     coll = COLL_MRT;
     if (c->Q == 9) mrt_coeffs<9>(c, a);
     else mrt_coeffs<19>(c, a);
+  }
+  return coll;
+}
+
+int collision_kind(const lbm_ctx *c, double *sp, double *sm) {
+  double a, b;
+  if (c->p.collision == LBM_BGK) return COLL_BGK;
+  if (two_rate(c, sp ? sp : &a, sm ? sm : &b)) return COLL_TRT;
+  return COLL_MRT;
+}
+
+void fill_sweep_args(lbm_ctx *c, SweepArgs *a) { make_sweep_args(c, *a); }
+
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t) {
+  SweepArgs a;
+  const int coll = make_sweep_args(c, a);
+  if (reduce_t >= 0 && c->k5_chunks > 0) {
+    a.ft = ft_reduce_args(c, reduce_t);
+    a.rblocks = (uint32_t)((c->nsolid + 3) / 4);
   }
   const bool flags = c->nsolid > 0;
   const bool ntb = nt != 0;
@@ -258,12 +325,6 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hip
 // state encode / decode (host-visible populations are f_i(x) before the next
 // collision; the device keeps them shifted by e_i, A_i(y) = h_i(y + e_i))
 // ----------------------------------------------------------------------------
-struct CellArgs {
-  uint32_t N, nx, ny, nz;
-  FastDiv fx, fy;
-  uint64_t stride;
-};
-
 __device__ inline void cell_xyz(uint32_t n, const CellArgs &a, int &x, int &y, int &z) {
   const uint32_t yz = fdiv(n, a.fx);
   x = (int)(n - yz * a.nx);
@@ -382,28 +443,14 @@ void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool 
 // ----------------------------------------------------------------------------
 // macroscopic fields
 // ----------------------------------------------------------------------------
-struct MacroArgs {
-  CellArgs ca;
-  const uint8_t *flags;
-  const uint16_t *owner;
-  const DevSolid *solids;
-  const void *fibm;
-  double g[3];
-  int64_t t_geom;
-  int D;
-  int initial;
-  int nsolid;
-  uint8_t solid_bit;
-};
-
 // initial: src holds the shifted pre-collision state, u = j / rho.
 // otherwise: src holds post-collision values of the last collision, whose
 // momentum is j + F, so u = (j + F/2)/rho = (j* - F/2)/rho.
 template <int Q, typename S>
-__global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, MacroArgs m) {
+__device__ inline void macros_body(const S *__restrict__ src, double *__restrict__ out, const MacroArgs &m,
+                                   uint32_t n) {
   using L = Lat<Q>;
   const CellArgs &a = m.ca;
-  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= a.N) return;
   int x, y, z;
   cell_xyz(n, a, x, y, z);
@@ -448,12 +495,32 @@ __global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, Ma
   out[2ull * a.N + n] = (jy - 0.5 * F[1]) / rho;
   out[3ull * a.N + n] = (jz - 0.5 * F[2]) / rho;
 }
+template <int Q, typename S>
+__global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, MacroArgs m) {
+  macros_body<Q, S>(src, out, m, blockIdx.x * blockDim.x + threadIdx.x);
+}
+// Batched capture of the fields of the collision just done (translating
+// solids, last step of a call): post-collision state P[cur ^ 1].
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_macros_batch(const BatchSlot *__restrict__ slots,
+                                                       const WorkList *__restrict__ wl,
+                                                       const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int s, uint32_t blk) {
+    const BatchSlot &sl = slots[s];
+    MacroArgs m = sl.mac;
+    m.t_geom = sl.t0 + k;
+    const int cur = sl.cur0 ^ (int)(k & 1);
+    macros_body<Q, S>(static_cast<const S *>(sl.P[cur ^ 1]), sl.macro, m, blk * 256 + threadIdx.x);
+  });
+}
 
 // mode 0: before any step (src = shifted pre-collision state); mode 1: after
 // a step, geometry of that step's collision; mode 2: inside a step, right after
 // the collision and before solids move (current geometry).
-void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
-  MacroArgs m{};
+void fill_macro_args(lbm_ctx *c, MacroArgs *mp, int mode) {
+  MacroArgs &m = *mp;
+  m = MacroArgs{};
   m.ca = cell_args(c);
   m.flags = c->nsolid > 0 ? c->at<uint8_t>(c->L.flags) : nullptr;
   const bool prev = mode == 1 && c->any_moving;
@@ -466,6 +533,11 @@ void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
   m.D = c->D;
   m.initial = mode == 0 ? 1 : 0;
   m.nsolid = c->nsolid;
+}
+
+void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
+  MacroArgs m;
+  fill_macro_args(c, &m, mode);
   const uint32_t grid = (uint32_t)((c->N + 255) / 256);
 #define LBM_MAC(QQ, SS) \
   hipLaunchKernelGGL((k_macros<QQ, SS>), dim3(grid), dim3(256), 0, c->stream, static_cast<const SS *>(src), out, m)
@@ -476,6 +548,21 @@ void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
   } else {
     if (c->p.storage == LBM_F64) LBM_MAC(19, double);
     else if (c->p.storage == LBM_F32_DEV) LBM_MAC(19, float);
+    else LBM_MAC(19, _Float16);
+  }
+#undef LBM_MAC
+}
+
+void launch_macros_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
+#define LBM_MAC(QQ, SS) \
+  hipLaunchKernelGGL((k_macros_batch<QQ, SS>), dim3(grid), dim3(256), 0, b.stream, b.slots, wl, b.step)
+  if (b.Q == 9) {
+    if (b.storage == LBM_F64) LBM_MAC(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_MAC(9, float);
+    else LBM_MAC(9, _Float16);
+  } else {
+    if (b.storage == LBM_F64) LBM_MAC(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_MAC(19, float);
     else LBM_MAC(19, _Float16);
   }
 #undef LBM_MAC

@@ -1,0 +1,215 @@
+// lbm_args.hpp -- per-lattice argument blocks of the kernels.  The same
+// blocks are passed by value to the single-lattice kernels and stored in
+// device memory, one per lattice, for the batched kernels.
+#pragma once
+
+#include "lbm_geom.hpp"
+
+namespace lbm {
+
+struct GeoArgs {
+  Box3 b;
+  uint32_t N;
+  FastDiv fx, fy;
+  uint64_t stride;
+  const DevSolid *solids;
+  int nsolid;
+  int ibb;         // 1 = solids remove nodes from the fluid (IBB), 0 = IBM
+  int fluid_only;  // body force only outside solids
+  int64_t t;       // geometry time
+};
+
+struct LinkArgs {
+  GeoArgs g;
+  uint8_t *flags;
+  uint16_t *owner, *owner_prev;
+  uint32_t *box_counts;    // [nsolid][max_box_chunks]
+  uint32_t *box_offsets;   // exclusive scan of box_counts
+  uint32_t max_box_chunks;
+  uint32_t *link_cell, *link_meta;
+  double *link_q;
+  uint64_t max_links;
+  SolidLinks *sl;
+  uint32_t *misc;          // [0] total links, [1] overflow flag
+  void *post;              // refill: post-collision array of step t-1 -> t
+  int refill;
+};
+
+struct IbbArgs {
+  GeoArgs g;
+  const uint32_t *link_cell, *link_meta;
+  const double *link_q;
+  const SolidLinks *sl;
+  double *partials;  // [chunk][6]
+  uint64_t max_links, max_partials;
+  int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC
+};
+
+struct SweepArgs {
+  uint32_t N, nx, ny, nz;
+  FastDiv fx, fy;
+  uint64_t stride;
+  const uint8_t *flags;
+  const void *fibm;  // [3][stride] compute type, read where F_IBM is set
+  double g[3];
+  double omega;          // BGK
+  double sp, sm;         // two-rate MRT: even and odd non-conserved rates
+  double sA[kMaxQ];      // general MRT: -s_k / |M_k|^2
+  double sB[kMaxQ];      //              (1 - s_k/2) / |M_k|^2
+  uint32_t rblocks;      // leading blocks that reduce the previous step's force partials
+  FtReduceArgs ft;
+};
+
+struct IbmArgs {
+  Box3 b;
+  uint32_t N;
+  FastDiv fx, fy;
+  uint64_t stride;
+  int64_t nlag, nshell;
+  const double *X, *dV;
+  const int32_t *sid;
+  double *Ud;            // [nlag][3]
+  const int32_t *base;   // [nlag][3] floor(X) - 1
+  double *wts;           // [nlag][12] per-axis weights
+  const uint32_t *idx;   // [nlag][64] shell index of each stencil slot
+  double *Fsum;          // [nlag][3] FP64 total boundary force of the step
+  void *Fk;              // [nlag][3] compute type, force of the current iteration
+  const uint32_t *shell_cell, *rowptr, *ent;
+  void *ushell, *fshell; // [3][nshell] compute type
+  void *fibm;            // [3][stride] compute type
+  uint8_t *flags;
+  const DevSolid *solids;
+  double g[3];
+  int64_t t;
+};
+
+// Cell indexing of the per-cell helper kernels.
+struct CellArgs {
+  uint32_t N, nx, ny, nz;
+  FastDiv fx, fy;
+  uint64_t stride;
+};
+
+// Macroscopic-field kernel arguments.
+struct MacroArgs {
+  CellArgs ca;
+  const uint8_t *flags;
+  const uint16_t *owner;
+  const DevSolid *solids;
+  const void *fibm;
+  double g[3];
+  int64_t t_geom;
+  int D;
+  int initial;
+  int nsolid;
+  uint8_t solid_bit;
+};
+
+// One lattice of a batch as the batched kernels see it.  Its time and state
+// parity advance with the batch step counter: at counter value k the lattice
+// is at t = t0 + k and its current state is P[cur0 ^ (k & 1)].
+struct BatchSlot {
+  void *P[2];
+  int32_t cur0;
+  int32_t method;
+  int32_t nsolid;
+  int32_t n_iter;
+  int32_t k5_chunks;
+  int32_t max_box_chunks;
+  int32_t max_solids;
+  int32_t tiles;
+  int64_t t0;
+  double *hist;      // force/torque history ring of the lattice
+  double *macro;     // macroscopic fields captured before translating solids move
+  uint32_t *status;  // [0] sticky capacity-overflow flags, [1] link count
+  const int64_t *lag_start, *lag_count;
+  SweepArgs sw;
+  IbbArgs ib;
+  LinkArgs lk;
+  IbmArgs im;
+  FtReduceArgs ft;
+  MacroArgs mac;
+};
+
+// Status bits of a batched lattice.
+enum { BS_LINKS_OVERFLOW = 1, BS_CHUNKS_OVERFLOW = 2 };
+
+// The units (tiles, link chunks, ...) of one batched launch: member k owns
+// units start[k] .. start[k+1]-1 and is lattice slot[k] of the batch.  Kept
+// in device memory, so a captured launch follows changes of the batch.
+struct WorkList {
+  uint32_t total;
+  int32_t n;
+  const uint32_t *start;
+  const int32_t *slot;
+};
+
+// Member that owns unit `u`: the last k with start[k] <= u.
+__device__ inline int batch_member_of(const uint32_t *start, int n, uint32_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent walk over the units of a work list: order 0 gives each block a
+// contiguous share, order 1 deals the units out round-robin.  f(slot, local
+// unit) is called with the same trip count by every thread of the block.
+template <typename F>
+__device__ inline void batch_units(const WorkList *wl, int order, F f) {
+  const uint32_t total = wl->total;
+  const int n = wl->n;
+  uint32_t u, end, inc;
+  if (order == 0) {
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    u = blockIdx.x * per;
+    end = min(total, u + per);
+    inc = 1;
+  } else {
+    u = blockIdx.x;
+    end = total;
+    inc = gridDim.x;
+  }
+  if (u >= end) return;
+  int k = batch_member_of(wl->start, n, u);
+  uint32_t lo = wl->start[k], hi = wl->start[k + 1];
+  for (; u < end; u += inc) {
+    while (u >= hi) {
+      k++;
+      lo = hi;
+      hi = wl->start[k + 1];
+    }
+    f(wl->slot[k], u - lo);
+  }
+}
+
+// Host side of a batched launch.
+struct BatchLaunch {
+  const BatchSlot *slots;
+  const int64_t *step;
+  hipStream_t stream;
+  int Q, storage;
+};
+
+// argument blocks of a context (host)
+void fill_sweep_args(lbm_ctx *c, SweepArgs *a);
+void fill_macro_args(lbm_ctx *c, MacroArgs *m, int mode);
+void fill_ibb_args(lbm_ctx *c, IbbArgs *a);
+void fill_link_args(lbm_ctx *c, LinkArgs *a);
+void fill_ibm_args(lbm_ctx *c, IbmArgs *a);
+
+// batched launches (grid = persistent blocks)
+void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,
+                        hipEvent_t e0, hipEvent_t e1);
+void launch_macros_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
+void launch_tick(hipStream_t s, int64_t *step);
+void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
+void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
+void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_one, uint32_t grid);
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_shell, const WorkList *wl_lag, const WorkList *wl_ft,
+                      int max_iter, uint32_t grid);
+
+}  // namespace lbm

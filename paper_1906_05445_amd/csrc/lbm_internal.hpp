@@ -127,6 +127,9 @@ struct lbm_ctx {
   double tune_us[2];       // measured sweep time of the two store policies
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::string err;
+  // batches
+  struct lbm_batch *batch;  // owning batch, or null
+  uint64_t version;         // bumped by every call that changes the state or the geometry
   // helpers
   void *state() const { return ws + (cur == 0 ? L.A : L.B); }
   void *other() const { return ws + (cur == 0 ? L.B : L.A); }
@@ -137,6 +140,9 @@ struct lbm_ctx {
 };
 
 namespace lbm {
+
+int collision_kind(const lbm_ctx *c, double *sp = nullptr, double *sm = nullptr);
+lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 
 // kernels_sweep.hip
 // reduce_t >= 0: the launch also reduces the force partials of step reduce_t

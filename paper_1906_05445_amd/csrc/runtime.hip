@@ -232,6 +232,20 @@ void circle(const double c[3], double R, double z, std::vector<double> &X, doubl
 // ----------------------------------------------------------------------------
 // C ABI
 // ----------------------------------------------------------------------------
+lbm_status lbm::destroy_ctx(lbm_ctx *c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &e : c->prof_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto &t : c->tune_events) {
+    (void)hipEventDestroy(t.e0);
+    (void)hipEventDestroy(t.e1);
+  }
+  delete c;
+  return LBM_OK;
+}
+
 extern "C" {
 
 const char *lbm_status_string(lbm_status st) {
@@ -307,6 +321,8 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->tuned_key = 0;
   c->tune_us[0] = c->tune_us[1] = 0.0;
   c->fresh = true;
+  c->batch = nullptr;
+  c->version = 0;
   // rest state, cleared flags and ownership
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner0, 0xFF, (size_t)c->N * 2, c->stream);
@@ -322,17 +338,8 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
 
 lbm_status lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_EINVAL;
-  (void)hipStreamSynchronize(c->stream);
-  for (auto &e : c->prof_events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  for (auto &t : c->tune_events) {
-    (void)hipEventDestroy(t.e0);
-    (void)hipEventDestroy(t.e1);
-  }
-  delete c;
-  return LBM_OK;
+  if (c->batch) return set_err(c, "a batch member is released through its batch"), LBM_ESTATE;
+  return lbm::destroy_ctx(c);
 }
 
 lbm_status lbm_profile(lbm_ctx *c, int32_t enable) {
@@ -376,6 +383,7 @@ static bool coord_axis(const double a[3], int *ax, int *sg) {
 static int dim_of(const lbm_ctx *c, int a) { return a == 0 ? c->p.nx : (a == 1 ? c->p.ny : c->p.nz); }
 
 lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts) {
+  if (c) c->version++;
   if (!c) return LBM_EINVAL;
   if (n < 0 || n > c->L.max_solids || (n > 0 && !s)) return set_err(c, "solid count"), LBM_EINVAL;
   if (method < LBM_BB || method > LBM_IBM) return set_err(c, "method"), LBM_EINVAL;
@@ -607,6 +615,7 @@ static lbm_status build_ibm(lbm_ctx *c) {
 }
 
 lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_t n, double dV) {
+  if (c) c->version++;
   if (!c) return LBM_EINVAL;
   if (c->method != LBM_IBM || solid < 0 || solid >= c->nsolid || n < 0 || (n > 0 && !X) || !(dV >= 0.0))
     return set_err(c, "lbm_set_lagrangian needs an IBM solid"), LBM_EINVAL;
@@ -716,6 +725,7 @@ static lbm_status tune_finish(lbm_ctx *c) {
 
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
+  c->version++;
 
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
   for (int64_t k = 0; k < nsteps; k++) {
@@ -857,6 +867,7 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *f) {
   }
   HIPCALL(hipStreamSynchronize(c->stream));
   c->fresh = true;
+  c->version++;
   return LBM_OK;
 }
 
@@ -884,6 +895,7 @@ lbm_status lbm_set_state(lbm_ctx *c, const void *host) {
   }
   HIPCALL(hipStreamSynchronize(c->stream));
   c->fresh = true;
+  c->version++;
   return LBM_OK;
 }
 

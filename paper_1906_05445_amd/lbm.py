@@ -96,11 +96,30 @@ _sig("lbm_profile", _st, [_vp, ctypes.c_int32])
 _sig("lbm_profile_read", _st, [_vp, _d, ctypes.POINTER(_i64)])
 _sig("lbm_autotune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d, _d])
 
+_sig("lbm_batch_table_bytes", ctypes.c_size_t, [ctypes.c_int32])
+_sig("lbm_batch_create", _st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t,
+                               ctypes.POINTER(_vp)])
+_sig("lbm_batch_admit", _st, [_vp, ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64, ctypes.POINTER(_vp)])
+_sig("lbm_batch_release", _st, [_vp, _vp])
+_sig("lbm_batch_step", _st, [_vp, _i64])
+_sig("lbm_batch_sync", _st, [_vp])
+_sig("lbm_batch_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t),
+                             ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i64)])
+_sig("lbm_batch_tune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), _d])
+_sig("lbm_batch_time_sweep", _st, [_vp, _i64, _d])
+_sig("lbm_batch_stream", _vp, [_vp])
+_sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
+_sig("lbm_batch_destroy", _st, [_vp])
+
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
-            "lbm_profile", "lbm_profile_read", "lbm_autotune_info"]
+            "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_batch_table_bytes", "lbm_batch_create",
+            "lbm_batch_admit", "lbm_batch_release", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_info",
+            "lbm_batch_tune_info", "lbm_batch_time_sweep", "lbm_batch_stream", "lbm_batch_last_error",
+            "lbm_batch_destroy"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
 
@@ -153,48 +172,22 @@ def make_solids(solids):
     return arr
 
 
-class Lattice:
-    """One lattice on the current CUDA/HIP device, owning its workspace."""
+class _Context:
+    """Calls on one context handle (readouts as numpy arrays)."""
 
-    def __init__(self, lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
-                 g=(0.0, 0.0, 0.0), g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0,
-                 stream=None, device="cuda"):
-        import torch
-        self._torch = torch
-        self.params, self._rates = make_params(lattice, collision, storage, shape, tau, rates, g, g_fluid_only)
-        self.shape = (self.params.nx, self.params.ny, self.params.nz)
+    handle = None
+
+    def _describe(self, lattice, params):
+        self.params = params
+        self.shape = (params.nx, params.ny, params.nz)
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
         self.Q = 9 if lattice == "D2Q9" else 19
-        self.storage = self.params.storage
-        nbytes = _lib.lbm_workspace_bytes(ctypes.byref(self.params), max_solids, max_links, max_lagrangian)
-        if nbytes == 0:
-            raise LBMError(LBM_EINVAL, "lattice parameters rejected")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream() if stream is None else stream
-        h = _vp()
-        st = _lib.lbm_create(ctypes.byref(self.params), max_solids, max_links, max_lagrangian, _vp(aligned),
-                             nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h))
-        if st != LBM_OK:
-            raise LBMError(st, "lbm_create")
-        self.handle = h
+        self.storage = params.storage
         self.nsolid = 0
 
     def _check(self, st):
         if st != LBM_OK:
             raise LBMError(st, _lib.lbm_last_error(self.handle).decode())
-
-    def close(self):
-        if getattr(self, "handle", None):
-            _lib.lbm_destroy(self.handle)
-            self.handle = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def set_solids(self, solids, method="QUADRATIC", n_iter=5, retraction=0.0):
         arr = make_solids(solids)
@@ -270,6 +263,48 @@ class Lattice:
         self._check(_lib.lbm_node_types(self.handle, _ptr(t, ctypes.c_uint8)))
         return t
 
+    def check(self):
+        st = _lib.lbm_check(self.handle)
+        if st not in (LBM_OK, LBM_EDIVERGED):
+            self._check(st)
+        return st == LBM_OK
+
+
+class Lattice(_Context):
+    """One lattice on the current CUDA/HIP device, owning its workspace."""
+
+    def __init__(self, lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
+                 g=(0.0, 0.0, 0.0), g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0,
+                 stream=None, device="cuda"):
+        import torch
+        self._torch = torch
+        params, self._rates = make_params(lattice, collision, storage, shape, tau, rates, g, g_fluid_only)
+        self._describe(lattice, params)
+        nbytes = _lib.lbm_workspace_bytes(ctypes.byref(self.params), max_solids, max_links, max_lagrangian)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, "lattice parameters rejected")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = _vp()
+        st = _lib.lbm_create(ctypes.byref(self.params), max_solids, max_links, max_lagrangian, _vp(aligned),
+                             nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, "lbm_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def profile(self, enable=True):
         self._check(_lib.lbm_profile(self.handle, int(bool(enable))))
 
@@ -286,8 +321,104 @@ class Lattice:
         self._check(_lib.lbm_autotune_info(self.handle, ctypes.byref(nt), ctypes.byref(a), ctypes.byref(b)))
         return {"nontemporal_stores": nt.value, "sweep_us_plain": a.value, "sweep_us_nontemporal": b.value}
 
-    def check(self):
-        st = _lib.lbm_check(self.handle)
-        if st not in (LBM_OK, LBM_EDIVERGED):
-            self._check(st)
-        return st == LBM_OK
+
+class Member(_Context):
+    """A lattice admitted into a Batch (its workspace lives in the batch pool)."""
+
+    def __init__(self, batch, handle, lattice, params, rates_keep):
+        self.batch = batch
+        self.handle = handle
+        self._rates = rates_keep
+        self._describe(lattice, params)
+
+
+class Batch:
+    """Many lattices of one lattice type and storage advanced together
+    (lbm_batch_*); the pool is a torch tensor owned by this object."""
+
+    def __init__(self, lattice="D3Q19", storage="F32", max_slots=64, pool_bytes=1 << 30, device="cuda"):
+        import torch
+        self._torch = torch
+        self.lattice = lattice
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=device)
+        aligned = (self.pool.data_ptr() + 255) // 256 * 256
+        h = _vp()
+        st = _lib.lbm_batch_create(LATTICES[lattice], STORAGES[storage], int(max_slots), _vp(aligned),
+                                   int(pool_bytes), ctypes.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, "lbm_batch_create")
+        self.handle = h
+        self.members = []
+
+    def _check(self, st):
+        if st != LBM_OK:
+            raise LBMError(st, _lib.lbm_batch_last_error(self.handle).decode())
+
+    @staticmethod
+    def footprint(lattice="D3Q19", collision="MRT", storage="F32", shape=(16, 16, 16), tau=0.8, max_solids=1,
+                  max_links=0, max_lagrangian=0):
+        p, _ = make_params(lattice, collision, storage, shape, tau)
+        return int(_lib.lbm_workspace_bytes(ctypes.byref(p), max_solids, max_links, max_lagrangian))
+
+    def admit(self, collision="MRT", storage="F32", shape=(16, 16, 16), tau=0.8, rates=None, g=(0.0, 0.0, 0.0),
+              g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0):
+        """A new Member, or None when the pool or the slots are full (LBM_EAGAIN)."""
+        params, keep = make_params(self.lattice, collision, storage, shape, tau, rates, g, g_fluid_only)
+        h = _vp()
+        st = _lib.lbm_batch_admit(self.handle, ctypes.byref(params), int(max_solids), int(max_links),
+                                  int(max_lagrangian), ctypes.byref(h))
+        if st == LBM_EAGAIN:
+            return None
+        self._check(st)
+        m = Member(self, h, self.lattice, params, keep)
+        self.members.append(m)
+        return m
+
+    def release(self, m):
+        self._check(_lib.lbm_batch_release(self.handle, m.handle))
+        m.handle = None
+        self.members.remove(m)
+
+    def step(self, n=1):
+        self._check(_lib.lbm_batch_step(self.handle, int(n)))
+
+    def sync(self):
+        self._check(_lib.lbm_batch_sync(self.handle))
+
+    def info(self):
+        n = ctypes.c_int32(0)
+        fr, big = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        cells = _i64(0)
+        self._check(_lib.lbm_batch_info(self.handle, ctypes.byref(n), ctypes.byref(fr), ctypes.byref(big),
+                                        ctypes.byref(cells)))
+        return {"members": n.value, "bytes_free": fr.value, "largest_free": big.value, "cells": cells.value}
+
+    def tune_info(self):
+        nt, order, blocks = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        us = ctypes.c_double(0.0)
+        st = _lib.lbm_batch_tune_info(self.handle, ctypes.byref(nt), ctypes.byref(order), ctypes.byref(blocks),
+                                      ctypes.byref(us))
+        if st == LBM_ESTATE:
+            return None
+        self._check(st)
+        return {"nontemporal_stores": nt.value, "order": order.value, "blocks": blocks.value,
+                "sweep_us": us.value}
+
+    def time_sweep(self, n):
+        us = ctypes.c_double(0.0)
+        self._check(_lib.lbm_batch_time_sweep(self.handle, int(n), ctypes.byref(us)))
+        return us.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lbm_batch_destroy(self.handle)
+            self.handle = None
+            for m in self.members:
+                m.handle = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
