@@ -11,8 +11,10 @@ reduction.  MLUPS counts every lattice cell.
 Also reported (same JSON line): the FP64 and FP16 forms of that workload,
 the direct-forcing IBM form (5 forcing iterations per step), the 256^3 box
 with 64 spheres (working set far beyond the 256 MB Infinity Cache), the
-achievable HBM copy bandwidth, and the FP64 CPU oracle timed on a bounded
-sample of the value workload.
+achievable HBM copy bandwidth, 512 lattices with translating spheres stepped
+as one batch, the request trace served for a bounded window at the trace's
+own rate (saturated) and at a rate below capacity, and the FP64 CPU oracle
+timed on a bounded sample of the value workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -120,6 +122,72 @@ def copy_probe(torch, lbm, nbytes=4 << 30, reps=20, warm=3):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
+def run_batch(torch, lbm, W, steps, warmup, count=512):
+    """512 independent lattices with translating spheres, advanced as one batch."""
+    cases = W.moving_sphere_batch(count)
+    fps = [lbm.Batch.footprint(c.lattice, c.collision, c.storage, c.shape, c.tau, max_solids=1) for c in cases]
+    pool = lbm.lbm_batch_table_bytes(count) + sum((f + 255) // 256 * 256 for f in fps) + (1 << 20)
+    t_setup = time.perf_counter()
+    b = lbm.Batch("D3Q19", "F32", max_slots=count, pool_bytes=pool)
+    members = []
+    for c in cases:
+        m = b.admit(c.collision, c.storage, c.shape, c.tau, g=c.g, max_solids=1)
+        if m is None:
+            raise RuntimeError("batch pool too small")
+        m.set_solids(c.solids, c.method)
+        members.append(m)
+    setup_s = time.perf_counter() - t_setup
+    N = sum(m.N for m in members)
+    b.step(warmup)  # the first steps also tune the sweep's launch shape
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    wall = time.perf_counter() - t0
+    tune = b.tune_info()
+    sweep_us = b.time_sweep(10)
+    ok = all(m.check() for m in members[:: max(1, count // 16)])
+    if not ok:
+        raise RuntimeError("batch: populations diverged")
+    per_cell = 2 * 19 * STORE_BYTES["F32"] + 1
+    achieved = N * per_cell / (sweep_us * 1e-6) / 1e9
+    out = {
+        "lattices": count,
+        "cells": N,
+        "steps": steps,
+        "mlups": N * steps / wall / 1e6,
+        "ms_per_step": wall / steps * 1e3,
+        "setup_s": setup_s,
+        "pool_GB": pool / 1e9,
+        "sweep_us_per_step": sweep_us,
+        "roofline_sweep": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_step": N * per_cell},
+        "tune": tune,
+        "note": "whole step: sweep, bounce-back + force, reclassification, refill and link rebuild of every lattice",
+    }
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_serving(torch, lbm, W, seconds, rate, count, pool_gb, max_slots):
+    """The request trace served for a bounded wall time (see paper_1906_05445_amd/serving.py)."""
+    from paper_1906_05445_amd import serving as S
+
+    trace = W.request_trace(count=count, rate=50.0, seed=5)
+    for e in trace:  # same requests, arrival times rescaled to the requested rate
+        e["arrival"] *= 50.0 / rate
+    reqs = S.requests_from_trace(trace)
+    srv = S.Server(pool_bytes=int(pool_gb * 1e9), max_slots=max_slots, check_every=100, tol=1e-6, step_cap=200000)
+    st = srv.run(reqs, wall_limit=seconds)
+    srv.close()
+    torch.cuda.empty_cache()
+    st.update({"rate_req_per_s": rate, "window_s": seconds, "pool_GB": pool_gb, "max_slots": max_slots,
+               "criterion": "|F(t)-F(t-100)|/|F(t)| < 1e-6, cap 2e5 steps"})
+    return st
+
+
 def cpu_baseline(case, steps):
     """The FP64 oracle (single-threaded C) on a bounded sample of the value workload."""
     from oracle import Oracle
@@ -142,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
+    ap.add_argument("--batch-steps", type=int, default=200, help="steps of the 512-lattice batch (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="wall time of each serving window (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run the copy kernel once over this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -174,6 +244,18 @@ def main():
             print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
                   file=sys.stderr, flush=True)
         extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
+        if args.batch_steps > 0:
+            extras["batch512_moving_f32"] = run_batch(torch, lbm, W, args.batch_steps, 30)
+            bb = extras["batch512_moving_f32"]
+            print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+        if args.serve_seconds > 0:
+            extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 48.0, 32)
+            extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.25, 256, 48.0, 32)
+            for k in ("serving_saturated", "serving_subsaturated"):
+                sv = extras[k]
+                print(f"# {k}: {sv['completed']} solves in {sv['wall_s']:.1f} s, p50 {sv['latency_p50_s']} s, "
+                      f"p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
     if args.copy_calibration > 0:
         copy_probe(torch, lbm, nbytes=args.copy_calibration << 20, reps=1)
     cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps) if args.cpu_steps > 0 else None

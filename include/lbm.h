@@ -278,6 +278,15 @@ lbm_status lbm_batch_tune_info(lbm_batch *b, int32_t *nontemporal, int32_t *orde
  * last lbm_batch_step (LBM_ESTATE otherwise). */
 lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us);
 
+/* Convergence check of every member (serving): for slot k, members[k] is
+ * the member context (NULL for a free slot) and change[k] the largest
+ * relative change of a solid's force over the last `lag` steps,
+ * |F(t-1) - F(t-1-lag)| / |F(t-1)| (Euclidean norms, F the force of step
+ * t-1), or -1 when the member has no solid or fewer than lag + 1 steps.
+ * Both arrays hold max_slots entries.  One launch and one small read-back;
+ * synchronises the batch's stream. */
+lbm_status lbm_batch_force_change(lbm_batch *b, int64_t lag, lbm_ctx **members, double *change);
+
 /* The batch's HIP stream (a hipStream_t). */
 void *lbm_batch_stream(lbm_batch *b);
 

@@ -39,6 +39,7 @@ enum {
   WL_IBM_SHELL,
   WL_IBM_LAG,
   WL_IBM_FT,
+  WL_SOLID,      // one unit per member with solids (convergence check)
   WL_COUNT
 };
 
@@ -83,6 +84,7 @@ struct lbm_batch {
   WorkList *d_wl = nullptr;
   uint32_t *d_start = nullptr;
   int32_t *d_mem = nullptr;
+  double *d_change = nullptr;
   // composition
   bool dirty = true;
   int nlive = 0;
@@ -237,6 +239,7 @@ lbm_status rebuild(lbm_batch *b) {
         add(WL_MACRO, (uint64_t)((c->N + 255) / 256));
       }
     }
+    if (c->nsolid > 0) add(WL_SOLID, 1);
     if (member_ibm(c)) {
       b->any_ibm = true;
       b->max_iter = std::max(b->max_iter, c->n_iter);
@@ -393,7 +396,7 @@ size_t lbm_batch_table_bytes(int32_t max_slots) {
   if (max_slots <= 0) return 0;
   const size_t S = (size_t)max_slots;
   return align256(sizeof(BatchSlot) * S) + 256 + align256(8 * S) + align256(sizeof(WorkList) * WL_COUNT) +
-         align256(4 * WL_COUNT * (S + 1)) + align256(4 * WL_COUNT * S);
+         align256(4 * WL_COUNT * (S + 1)) + align256(4 * WL_COUNT * S) + align256(8 * S);
 }
 
 lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots, void *dev_pool, size_t pool_bytes,
@@ -436,6 +439,8 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
   b->d_start = reinterpret_cast<uint32_t *>(p);
   p += align256(4 * WL_COUNT * (S + 1));
   b->d_mem = reinterpret_cast<int32_t *>(p);
+  p += align256(4 * WL_COUNT * S);
+  b->d_change = reinterpret_cast<double *>(p);
   b->free_[tb] = (pool_bytes - tb) & ~size_t(255);
   if (rebuild(b) != LBM_OK) {
     (void)hipStreamDestroy(b->stream);
@@ -642,6 +647,29 @@ lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us) 
     (void)hipEventDestroy(e.second);
   }
   *sweep_us = 1e3 * tot / (double)nsteps;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_force_change(lbm_batch *b, int64_t lag, lbm_ctx **members, double *change) {
+  if (!b || !members || !change || lag <= 0) return LBM_EINVAL;
+  if (lag >= lbm_history_capacity()) return berr(b, LBM_EINVAL, "lag beyond the force history");
+  for (auto &m : b->mem)
+    if (m.c && m.c->version != m.version) b->dirty = true;
+  if (b->dirty) {
+    const lbm_status st = rebuild(b);
+    if (st != LBM_OK) return st;
+  }
+  const BatchLaunch bl{b->d_slots, b->d_step, b->stream, b->Q, b->storage};
+  launch_force_change(bl, b->wl(WL_SOLID), lag, b->d_change, std::min<uint32_t>(grid_of(b, 1), 1024));
+  BHIP(hipGetLastError());
+  std::vector<double> out((size_t)b->max_slots);
+  BHIP(hipMemcpyAsync(out.data(), b->d_change, sizeof(double) * out.size(), hipMemcpyDeviceToHost, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < b->max_slots; k++) {
+    lbm_ctx *c = b->mem[(size_t)k].c;
+    members[k] = c;
+    change[k] = (c && c->nsolid > 0) ? out[(size_t)k] : -1.0;
+  }
   return LBM_OK;
 }
 

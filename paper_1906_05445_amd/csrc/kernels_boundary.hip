@@ -493,6 +493,54 @@ __global__ __launch_bounds__(kBlock) void k_link_emit_batch(const BatchSlot *__r
   });
 }
 
+// Serving convergence check: per member, the largest relative change of a
+// solid's force over `lag` steps, |F(t-1) - F(t-1-lag)| / |F(t-1)| with t the
+// member's time; -1 while fewer than lag + 1 steps are in its history.
+__global__ __launch_bounds__(64) void k_force_change(const BatchSlot *__restrict__ slots,
+                                                     const WorkList *__restrict__ wl,
+                                                     const int64_t *__restrict__ step, int64_t lag, double *out) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t) {
+    const BatchSlot &sl = slots[m];
+    const int s = (int)threadIdx.x;
+    const int64_t t = sl.t0 + k - 1;
+    const bool ok = lag > 0 && lag < kHistCap && t - lag >= 0;
+    double r = 0.0;
+    if (ok && s < sl.nsolid) {
+      const uint64_t per = (uint64_t)sl.max_solids * 6;
+      const double *a = sl.hist + (uint64_t)(t % kHistCap) * per + (uint64_t)s * 6;
+      const double *b = sl.hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)s * 6;
+      double d2 = 0.0, n2 = 0.0;
+      for (int c = 0; c < 3; c++) {
+        d2 += (a[c] - b[c]) * (a[c] - b[c]);
+        n2 += a[c] * a[c];
+      }
+      r = n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
+    }
+    for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off, 64));
+    for (int s0 = 64; s0 < sl.nsolid; s0 += 64) {  // more than 64 solids: serial tail in lane 0
+      if (threadIdx.x == 0 && ok) {
+        for (int q = s0; q < min(sl.nsolid, s0 + 64); q++) {
+          const uint64_t per = (uint64_t)sl.max_solids * 6;
+          const double *a = sl.hist + (uint64_t)(t % kHistCap) * per + (uint64_t)q * 6;
+          const double *b = sl.hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)q * 6;
+          double d2 = 0.0, n2 = 0.0;
+          for (int c = 0; c < 3; c++) {
+            d2 += (a[c] - b[c]) * (a[c] - b[c]);
+            n2 += a[c] * a[c];
+          }
+          r = fmax(r, n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0));
+        }
+      }
+    }
+    if (threadIdx.x == 0) out[m] = ok ? r : -1.0;
+  });
+}
+
+void launch_force_change(const BatchLaunch &b, const WorkList *wl, int64_t lag, double *out, uint32_t grid) {
+  hipLaunchKernelGGL(k_force_change, dim3(grid), dim3(64), 0, b.stream, b.slots, wl, b.step, lag, out);
+}
+
 void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
 #define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb_batch<QQ, SS>), dim3(grid), dim3(64), 0, b.stream, b.slots, wl, b.step)
   if (b.Q == 9) {

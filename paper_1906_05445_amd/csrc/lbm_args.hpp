@@ -208,6 +208,7 @@ void launch_macros_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid
 void launch_tick(hipStream_t s, int64_t *step);
 void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
+void launch_force_change(const BatchLaunch &b, const WorkList *wl, int64_t lag, double *out, uint32_t grid);
 void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_one, uint32_t grid);
 void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_shell, const WorkList *wl_lag, const WorkList *wl_ft,
                       int max_iter, uint32_t grid);

@@ -108,6 +108,7 @@ _sig("lbm_batch_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER
 _sig("lbm_batch_tune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_time_sweep", _st, [_vp, _i64, _d])
+_sig("lbm_batch_force_change", _st, [_vp, _i64, ctypes.POINTER(_vp), _d])
 _sig("lbm_batch_stream", _vp, [_vp])
 _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_batch_destroy", _st, [_vp])
@@ -118,7 +119,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagr
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
             "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_batch_table_bytes", "lbm_batch_create",
             "lbm_batch_admit", "lbm_batch_release", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_info",
-            "lbm_batch_tune_info", "lbm_batch_time_sweep", "lbm_batch_stream", "lbm_batch_last_error",
+            "lbm_batch_tune_info", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_stream", "lbm_batch_last_error",
             "lbm_batch_destroy"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
@@ -348,6 +349,7 @@ class Batch:
         if st != LBM_OK:
             raise LBMError(st, "lbm_batch_create")
         self.handle = h
+        self.max_slots = int(max_slots)
         self.members = []
 
     def _check(self, st):
@@ -403,6 +405,21 @@ class Batch:
         self._check(st)
         return {"nontemporal_stores": nt.value, "order": order.value, "blocks": blocks.value,
                 "sweep_us": us.value}
+
+    def force_change(self, lag=100):
+        """{Member: relative force change over `lag` steps} (-1: not available yet)."""
+        cap = len(self._slots_buf) if hasattr(self, "_slots_buf") else 0
+        if cap != self.max_slots:
+            self._slots_buf = (_vp * self.max_slots)()
+            self._change_buf = np.empty(self.max_slots)
+        self._check(_lib.lbm_batch_force_change(self.handle, int(lag), self._slots_buf, _ptr(self._change_buf)))
+        by_handle = {m.handle.value: m for m in self.members}
+        out = {}
+        for k in range(self.max_slots):
+            h = self._slots_buf[k]
+            if h and h in by_handle:
+                out[by_handle[h]] = float(self._change_buf[k])
+        return out
 
     def time_sweep(self, n):
         us = ctypes.c_double(0.0)

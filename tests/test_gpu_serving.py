@@ -1,0 +1,50 @@
+"""Serving loop on the GPU: continuous batching of a small request trace.
+
+Bar: every served result (force/torque at the step the request finished) is
+bit for bit the result of the same solve run alone with lbm_step for the same
+number of steps, although requests joined and left the batch at different
+times; converged requests meet the drag-change criterion.
+"""
+import numpy as np
+import pytest
+
+from paper_1906_05445_amd import serving as S
+from paper_1906_05445_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_05445_amd import lbm as L
+
+    return L
+
+
+def test_served_results_match_lone_runs(lbm):
+    trace = W.request_trace(count=7, rate=200.0, seed=7, edge=(24, 36), Re=(1.0, 2.0))
+    reqs = S.requests_from_trace(trace, n_iter=3)
+    fps = [S.footprint(lbm, r.case) for r in reqs]
+    # room for about three of them at once, and at most four slots: the rest queue
+    pool = lbm.lbm_batch_table_bytes(4) + int(3.2 * max(fps))
+    srv = S.Server(pool_bytes=pool, max_slots=4, check_every=100, tol=1e-6, step_cap=4000)
+    st = srv.run(reqs, wall_limit=240)
+    srv.close()
+    assert st["completed"] == len(reqs), st
+    assert st["rejected"] == 0
+    assert any(r.queue_time > 0 for r in reqs if r.admitted is not None)
+    for r in reqs:
+        assert r.steps % 100 == 0 and 0 < r.steps <= 4000
+        if r.converged:
+            assert 0.0 <= r.change < 1e-6
+        c = r.case
+        lone = lbm.Lattice(c.lattice, c.collision, c.storage, c.shape, c.tau, g=c.g, max_solids=1)
+        lone.set_solids(c.solids, c.method, n_iter=3)
+        lone.step(r.steps)
+        ft = lone.force_torque()
+        lone.close()
+        assert np.array_equal(ft.view(np.uint64), r.force.view(np.uint64)), f"request {r.rid}"

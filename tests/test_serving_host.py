@@ -1,0 +1,79 @@
+"""Host logic of the serving loop (no GPU): admission order, percentiles, summary."""
+import numpy as np
+
+from paper_1906_05445_amd import serving as S
+from paper_1906_05445_amd import workloads as W
+
+
+def _req(rid, arrival, size):
+    r = S.Request(rid, arrival, case=None)
+    r.footprint = size
+    return r
+
+
+def test_first_fit_admission_does_not_block_small_requests():
+    free = {"bytes": 100, "slots": 3}
+
+    def try_admit(req):
+        if req.footprint > free["bytes"] or free["slots"] == 0:
+            return None
+        free["bytes"] -= req.footprint
+        free["slots"] -= 1
+        return object()
+
+    adm = S.Admission(try_admit)
+    for rid, size in enumerate([60, 70, 30, 20, 5]):
+        adm.push(_req(rid, 0.1 * rid, size))
+    got = adm.admit_all(now=1.0)
+    # 60 fits, 70 does not, 30 fits, 20 no longer fits (10 left), 5 takes the last slot
+    assert [r.rid for r, _ in got] == [0, 2, 4]
+    assert [r.rid for r in adm.queue] == [1, 3]
+    assert all(r.admitted == 1.0 for r, _ in got)
+    free["bytes"] += 60  # request 0 leaves: 65 bytes, one slot
+    free["slots"] += 1
+    got = adm.admit_all(now=2.0)
+    assert [r.rid for r, _ in got] == [3]  # 70 still does not fit; the next oldest that fits goes
+    assert [r.rid for r in adm.queue] == [1]
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert S.percentile(v, 50) == 50
+    assert S.percentile(v, 99) == 99
+    assert S.percentile(v, 100) == 100
+    assert S.percentile([3.0], 99) == 3.0
+    assert S.percentile([], 50) is None
+    assert S.percentile([5, 1, 3], 50) == 3
+
+
+def test_stats_split_queue_and_service():
+    reqs = []
+    for k in range(4):
+        r = _req(k, float(k), 1)
+        r.admitted = k + 0.5
+        r.finished = k + 2.0 if k < 3 else None
+        r.converged = k < 2
+        r.capped = k == 2
+        r.steps = 100 * (k + 1)
+        reqs.append(r)
+    s = S.stats(reqs, wall=10.0, cell_steps=1e9, in_flight=1)
+    assert s["completed"] == 3 and s["converged"] == 2 and s["capped"] == 1
+    assert s["solves_per_s"] == 0.3
+    assert s["latency_p50_s"] == 2.0 and s["queue_p50_s"] == 0.5 and s["service_p50_s"] == 1.5
+    assert s["mlups"] == 100.0
+
+
+def test_request_trace_is_poisson_and_seeded():
+    a = W.request_trace(count=2000, rate=50.0, seed=5)
+    b = W.request_trace(count=2000, rate=50.0, seed=5)
+    assert [x["arrival"] for x in a] == [x["arrival"] for x in b]
+    t = np.array([x["arrival"] for x in a])
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps > 0)
+    assert abs(gaps.mean() - 1 / 50.0) < 0.1 / 50.0  # mean gap 1/rate within 10%
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.1  # exponential: coefficient of variation 1
+    methods = [x["case"].method for x in a]
+    assert 0.45 < methods.count("IBM") / len(methods) < 0.55
+    for x in a[:50]:
+        c = x["case"]
+        assert 48 <= c.shape[0] <= 160 and c.solids[0]["radius"] == c.shape[0] / 8.0
