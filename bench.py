@@ -145,6 +145,7 @@ def run_batch(torch, lbm, W, steps, warmup, count=512):
     b.sync()
     wall = time.perf_counter() - t0
     tune = b.tune_info()
+    tune["candidates"] = b.tune_table()
     sweep_us = b.time_sweep(10)
     ok = all(m.check() for m in members[:: max(1, count // 16)])
     if not ok:
@@ -210,6 +211,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
+    ap.add_argument("--cases", default="all",
+                    help="comma list of extras: single (the other single-lattice cases), copy, batch, serving")
     ap.add_argument("--batch-steps", type=int, default=200, help="steps of the 512-lattice batch (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="wall time of each serving window (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -231,7 +234,10 @@ def main():
     print(f"# sphere128 F32 IBB: {primary['mlups']:.0f} MLUPS, sweep {primary['sweep_avg_us']:.1f} us, "
           f"{primary['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
     extras = {}
+    want = set()
     if not args.primary_only:
+        want = {"single", "copy", "batch", "serving"} if args.cases == "all" else set(args.cases.split(","))
+    if "single" in want:
         k2 = max(K // 2, 100)
         for key, case in [("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
                           ("sphere128_f16_quadratic", W.sphere_box(storage="F16", method="QUADRATIC")),
@@ -243,19 +249,20 @@ def main():
             extras[key]["steps"] = k
             print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
                   file=sys.stderr, flush=True)
+    if "copy" in want:
         extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
-        if args.batch_steps > 0:
-            extras["batch512_moving_f32"] = run_batch(torch, lbm, W, args.batch_steps, 30)
-            bb = extras["batch512_moving_f32"]
-            print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
-                  file=sys.stderr, flush=True)
-        if args.serve_seconds > 0:
-            extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 48.0, 32)
-            extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.25, 256, 48.0, 32)
-            for k in ("serving_saturated", "serving_subsaturated"):
-                sv = extras[k]
-                print(f"# {k}: {sv['completed']} solves in {sv['wall_s']:.1f} s, p50 {sv['latency_p50_s']} s, "
-                      f"p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
+    if args.batch_steps > 0 and "batch" in want:
+        extras["batch512_moving_f32"] = run_batch(torch, lbm, W, args.batch_steps, 30)
+        bb = extras["batch512_moving_f32"]
+        print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    if args.serve_seconds > 0 and "serving" in want:
+        extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 48.0, 32)
+        extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.25, 256, 48.0, 32)
+        for k in ("serving_saturated", "serving_subsaturated"):
+            sv = extras[k]
+            print(f"# {k}: {sv['completed']} solves in {sv['wall_s']:.1f} s, p50 {sv['latency_p50_s']} s, "
+                  f"p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
     if args.copy_calibration > 0:
         copy_probe(torch, lbm, nbytes=args.copy_calibration << 20, reps=1)
     cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps) if args.cpu_steps > 0 else None

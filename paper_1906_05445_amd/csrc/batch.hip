@@ -35,7 +35,6 @@ enum {
   WL_FT,
   WL_BOX,        // (solid, box chunk) units of members with translating solids
   WL_ONE,        // one unit per member with translating solids
-  WL_MACRO,      // tiles of members with translating solids
   WL_IBM_SHELL,
   WL_IBM_LAG,
   WL_IBM_FT,
@@ -53,17 +52,22 @@ struct Member {
 };
 
 struct SweepCfg {
-  int nt, order, mult;  // store policy, unit order, blocks per compute unit
+  int nt, order, mult;  // store policy, unit order, persistent blocks per compute unit (0: one block per tile)
 };
 
-const SweepCfg kCands[] = {{0, 0, 4}, {0, 0, 8}, {0, 0, 16}, {0, 1, 4}, {0, 1, 8}, {0, 1, 16},
-                           {1, 0, 4}, {1, 0, 8}, {1, 0, 16}, {1, 1, 4}, {1, 1, 8}, {1, 1, 16}};
+const SweepCfg kCands[] = {{0, 0, 4}, {0, 0, 8}, {0, 0, 16}, {0, 1, 4}, {0, 1, 8}, {0, 1, 16}, {0, 0, 0},
+                           {1, 0, 4}, {1, 0, 8}, {1, 0, 16}, {1, 1, 4}, {1, 1, 8}, {1, 1, 16}, {1, 0, 0}};
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// tuned sweep configuration per (lattice, storage, size class), process-wide
-std::map<uint64_t, std::pair<int, double>> g_batch_tune;
+// tuned sweep configuration per (lattice, storage, size class), process-wide:
+// the chosen candidate and the mean time of every candidate (us)
+struct TuneResult {
+  int chosen;
+  double us[kNumCands];
+};
+std::map<uint64_t, TuneResult> g_batch_tune;
 std::mutex g_batch_tune_mutex;
 
 }  // namespace
@@ -93,11 +97,13 @@ struct lbm_batch {
   int max_iter = 0;
   uint64_t tiles = 0;
   // graphs
-  hipGraphExec_t g1 = nullptr, gk = nullptr, glast = nullptr;
+  hipGraphExec_t g1 = nullptr, gk = nullptr;
   uint64_t graph_key = 0;
   // sweep tuning
   int chosen = -1;
   double chosen_us = 0.0;
+  double cand_us[kNumCands] = {0};
+  uint32_t totals[WL_COUNT] = {0};  // units of every work list (host copy)
   uint64_t tune_key = 0;
   int tune_next = 0;
   struct Sample {
@@ -124,7 +130,7 @@ lbm_status berr(lbm_batch *b, lbm_status st, const std::string &msg) {
   } while (0)
 
 void destroy_graphs(lbm_batch *b) {
-  for (hipGraphExec_t *g : {&b->g1, &b->gk, &b->glast})
+  for (hipGraphExec_t *g : {&b->g1, &b->gk})
     if (*g) {
       (void)hipGraphExecDestroy(*g);
       *g = nullptr;
@@ -209,7 +215,6 @@ lbm_status rebuild(lbm_batch *b) {
     const uint32_t tiles = (uint32_t)(c->L.stride / kTile);
     bs.tiles = (int32_t)tiles;
     bs.hist = c->at<double>(c->L.hist);
-    bs.macro = c->at<double>(c->L.macro);
     bs.status = b->d_status + 2 * (size_t)k;
     bs.lag_start = c->at<int64_t>(c->L.misc + 64);
     bs.lag_count = c->at<int64_t>(c->L.misc + 64 + 8 * (size_t)c->L.max_solids);
@@ -218,7 +223,6 @@ lbm_status rebuild(lbm_batch *b) {
     fill_link_args(c, &bs.lk);
     fill_ibm_args(c, &bs.im);
     bs.ft = ft_reduce_args(c, 0);
-    fill_macro_args(c, &bs.mac, 2);
     auto add = [&](int l, uint64_t n) {
       if (n == 0) return;
       units[l].push_back((uint32_t)n);
@@ -236,7 +240,6 @@ lbm_status rebuild(lbm_batch *b) {
         b->any_moving = true;
         add(WL_BOX, (uint64_t)c->max_box_chunks * c->nsolid);
         add(WL_ONE, 1);
-        add(WL_MACRO, (uint64_t)((c->N + 255) / 256));
       }
     }
     if (c->nsolid > 0) add(WL_SOLID, 1);
@@ -262,6 +265,7 @@ lbm_status rebuild(lbm_batch *b) {
     if (run >= (1ull << 32)) return berr(b, LBM_ENOMEM, "too many units in one batched launch");
     st[units[l].size()] = (uint32_t)run;
     wl[l].total = (uint32_t)run;
+    b->totals[l] = (uint32_t)run;
     wl[l].n = (int32_t)units[l].size();
     wl[l].start = b->d_start + (size_t)l * (S + 1);
     wl[l].slot = b->d_mem + (size_t)l * S;
@@ -284,9 +288,8 @@ lbm_status rebuild(lbm_batch *b) {
 
 uint32_t grid_of(const lbm_batch *b, int mult) { return (uint32_t)std::max(1, mult * b->cus); }
 
-// One batched step (enqueue only).  last: also capture the macroscopic fields
-// of members whose solids translate.  e0/e1 (optional) time the sweep launches.
-void enqueue_step(lbm_batch *b, const SweepCfg &cfg, bool last, hipEvent_t e0, hipEvent_t e1) {
+// One batched step (enqueue only); e0/e1 (optional) time the sweep launches.
+void enqueue_step(lbm_batch *b, const SweepCfg &cfg, hipEvent_t e0, hipEvent_t e1) {
   const BatchLaunch bl{b->d_slots, b->d_step, b->stream, b->Q, b->storage};
   if (b->any_ibm) launch_ibm_batch(bl, b->wl(WL_IBM_SHELL), b->wl(WL_IBM_LAG), b->wl(WL_IBM_FT), b->max_iter,
                                    grid_of(b, 4));
@@ -298,15 +301,13 @@ void enqueue_step(lbm_batch *b, const SweepCfg &cfg, bool last, hipEvent_t e0, h
     }
   for (int k = 0; k < 3; k++)
     if (b->coll_mask & (1u << k))
-      launch_sweep_batch(bl, b->wl(WL_SWEEP + k), k, cfg.nt, cfg.order, grid_of(b, cfg.mult),
+      launch_sweep_batch(bl, b->wl(WL_SWEEP + k), k, cfg.nt, cfg.order,
+                         cfg.mult ? grid_of(b, cfg.mult) : std::max<uint32_t>(1, b->totals[WL_SWEEP + k]),
                          k == first ? e0 : nullptr, k == lastc ? e1 : nullptr);
   if (b->any_ibb) {
-    launch_ibb_batch(bl, b->wl(WL_IBB), grid_of(b, 16));
+    launch_ibb_batch(bl, b->wl(WL_IBB), grid_of(b, 32));
     launch_ft_batch(bl, b->wl(WL_FT), std::min<uint32_t>(grid_of(b, 4), 1024));
-    if (b->any_moving) {
-      if (last) launch_macros_batch(bl, b->wl(WL_MACRO), grid_of(b, 8));
-      launch_move_batch(bl, b->wl(WL_BOX), b->wl(WL_ONE), grid_of(b, 8));
-    }
+    if (b->any_moving) launch_move_batch(bl, b->wl(WL_BOX), b->wl(WL_ONE), grid_of(b, 8));
   }
   launch_tick(b->stream, b->d_step);
 }
@@ -326,13 +327,15 @@ uint64_t graph_key_of(const lbm_batch *b) {
   k = k * 2 + (b->any_ibm ? 1 : 0);
   k = k * 64 + (uint64_t)b->max_iter;
   k = k * 64 + (uint64_t)b->chosen;
+  if (b->chosen >= 0 && kCands[b->chosen].mult == 0)  // grid = tiles: re-capture when they change
+    for (int l = WL_SWEEP; l < WL_SWEEP + 3; l++) k = k * 1000003ull + b->totals[l];
   return k;
 }
 
-lbm_status capture(lbm_batch *b, int steps, bool last, hipGraphExec_t *out) {
+lbm_status capture(lbm_batch *b, int steps, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  for (int s = 0; s < steps; s++) enqueue_step(b, kCands[b->chosen], last && s == steps - 1, nullptr, nullptr);
+  for (int s = 0; s < steps; s++) enqueue_step(b, kCands[b->chosen], nullptr, nullptr);
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess) return berr(b, LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -345,9 +348,8 @@ lbm_status ensure_graphs(lbm_batch *b) {
   const uint64_t key = graph_key_of(b);
   if (b->g1 && b->graph_key == key) return LBM_OK;
   destroy_graphs(b);
-  lbm_status st = capture(b, 1, false, &b->g1);
-  if (st == LBM_OK) st = capture(b, kGraphSteps, false, &b->gk);
-  if (st == LBM_OK && b->any_moving) st = capture(b, 1, true, &b->glast);
+  lbm_status st = capture(b, 1, &b->g1);
+  if (st == LBM_OK) st = capture(b, kGraphSteps, &b->gk);
   if (st != LBM_OK) {
     destroy_graphs(b);
     return st;
@@ -374,17 +376,19 @@ lbm_status tune_finish(lbm_batch *b) {
   int best = 0;
   double best_us = 1e300;
   for (int k = 0; k < kNumCands; k++) {
-    if (!cnt[k]) continue;
-    const double us = 1e3 * sum[k] / cnt[k];
-    if (us < best_us) {
-      best_us = us;
+    b->cand_us[k] = cnt[k] ? 1e3 * sum[k] / cnt[k] : -1.0;
+    if (cnt[k] && b->cand_us[k] < best_us) {
+      best_us = b->cand_us[k];
       best = k;
     }
   }
   b->chosen = best;
   b->chosen_us = best_us;
+  TuneResult r;
+  r.chosen = best;
+  for (int k = 0; k < kNumCands; k++) r.us[k] = b->cand_us[k];
   std::lock_guard<std::mutex> g(g_batch_tune_mutex);
-  g_batch_tune[b->tune_key] = {best, best_us};
+  g_batch_tune[b->tune_key] = r;
   return LBM_OK;
 }
 
@@ -521,8 +525,9 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     std::lock_guard<std::mutex> g(g_batch_tune_mutex);
     auto it = g_batch_tune.find(key);
     if (it != g_batch_tune.end()) {
-      b->chosen = it->second.first;
-      b->chosen_us = it->second.second;
+      b->chosen = it->second.chosen;
+      b->chosen_us = it->second.us[b->chosen];
+      for (int k = 0; k < kNumCands; k++) b->cand_us[k] = it->second.us[k];
     }
   }
   int64_t done = 0;
@@ -532,7 +537,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     b->samples.push_back({cand, e0, e1});
-    enqueue_step(b, kCands[cand], done == nsteps - 1, e0, e1);
+    enqueue_step(b, kCands[cand], e0, e1);
     BHIP(hipGetLastError());
     b->tune_next++;
     done++;
@@ -544,10 +549,9 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
   if (done < nsteps) {
     lbm_status st = ensure_graphs(b);
     if (st != LBM_OK) return st;
-    int64_t plain = nsteps - done - (b->any_moving ? 1 : 0);
-    for (; plain >= kGraphSteps; plain -= kGraphSteps) BHIP(hipGraphLaunch(b->gk, b->stream));
-    for (; plain > 0; plain--) BHIP(hipGraphLaunch(b->g1, b->stream));
-    if (b->any_moving) BHIP(hipGraphLaunch(b->glast, b->stream));
+    int64_t left = nsteps - done;
+    for (; left >= kGraphSteps; left -= kGraphSteps) BHIP(hipGraphLaunch(b->gk, b->stream));
+    for (; left > 0; left--) BHIP(hipGraphLaunch(b->g1, b->stream));
   }
   for (auto &m : b->mem) {
     if (!m.c) continue;
@@ -609,9 +613,22 @@ lbm_status lbm_batch_tune_info(lbm_batch *b, int32_t *nontemporal, int32_t *orde
   const SweepCfg &c = kCands[b->chosen];
   if (nontemporal) *nontemporal = c.nt;
   if (order) *order = c.order;
-  if (blocks) *blocks = (int32_t)grid_of(b, c.mult);
+  if (blocks) *blocks = c.mult ? (int32_t)grid_of(b, c.mult) : 0;
   if (sweep_us) *sweep_us = b->chosen_us;
   return LBM_OK;
+}
+
+int32_t lbm_batch_tune_table(lbm_batch *b, int32_t cap, int32_t *nontemporal, int32_t *order, int32_t *blocks,
+                             double *sweep_us) {
+  if (!b) return 0;
+  const int n = std::min<int32_t>(cap, kNumCands);
+  for (int k = 0; k < n; k++) {
+    if (nontemporal) nontemporal[k] = kCands[k].nt;
+    if (order) order[k] = kCands[k].order;
+    if (blocks) blocks[k] = kCands[k].mult ? (int32_t)grid_of(b, kCands[k].mult) : 0;
+    if (sweep_us) sweep_us[k] = b->chosen >= 0 ? b->cand_us[k] : -1.0;
+  }
+  return kNumCands;
 }
 
 lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us) {
@@ -629,7 +646,7 @@ lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us) 
     BHIP(hipEventCreate(&e.second));
   }
   for (int64_t s = 0; s < nsteps; s++)
-    enqueue_step(b, kCands[b->chosen], s == nsteps - 1, ev[(size_t)s].first, ev[(size_t)s].second);
+    enqueue_step(b, kCands[b->chosen], ev[(size_t)s].first, ev[(size_t)s].second);
   BHIP(hipGetLastError());
   for (auto &m : b->mem) {
     if (!m.c) continue;

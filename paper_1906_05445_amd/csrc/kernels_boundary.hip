@@ -28,17 +28,26 @@ __device__ inline uint32_t id_of(int x, int y, int z, const GeoArgs &a) {
 }
 
 // Box of solid s at time t: cell (lx, ly, lz) of the box -> lattice cell.
-__device__ inline void box_origin(const DevSolid &s, const GeoArgs &a, int o[3]) {
+// Also returns the centre at t.
+__device__ inline void box_origin(const DevSolid &s, const GeoArgs &a, int o[3], double c[3]) {
+  solid_centre(s, a.t, a.b, c);
   if (!s.moving) {
     o[0] = s.box0[0];
     o[1] = s.box0[1];
     o[2] = s.box0[2];
     return;
   }
-  double c[3];
-  solid_centre(s, a.t, a.b, c);
   for (int k = 0; k < 3; k++) o[k] = s.full[k] ? 0 : (int)floor(c[k] - s.R) - 2;
 }
+
+// Half-widths of the surface bands: a node changes classification between
+// t and t+1 only within |U| of the surface, and the previous step's changes
+// lie within 2|U| of the surface at t+1; a link (x_f, i) has its solid node
+// x_f - e_i inside, so x_f lies within |e_i| <= sqrt(2) of the surface.
+__device__ inline double move_band(const DevSolid &s) {
+  return 2.0 * sqrt(s.U[0] * s.U[0] + s.U[1] * s.U[1] + s.U[2] * s.U[2]) + 0.5;
+}
+constexpr double kLinkBand = 1.5;
 __device__ inline bool box_cell(const DevSolid &s, const int o[3], uint32_t bi, const GeoArgs &a, int &x, int &y,
                                 int &z) {
   if (bi >= s.box_cells) return false;
@@ -54,7 +63,7 @@ __device__ inline bool box_cell(const DevSolid &s, const int o[3], uint32_t bi, 
 // classification of one cell against all solids (first match wins)
 __device__ inline int classify_cell(const GeoArgs &a, int x, int y, int z) {
   for (int k = 0; k < a.nsolid; k++) {
-    const DevSolid &s = a.solids[k];
+    const DevSolid s = load_uniform(&a.solids[k]);
     double c[3];
     solid_centre(s, a.t, a.b, c);
     if (inside_solid(s, c, x, y, z, a.b)) return k;
@@ -86,11 +95,13 @@ __global__ void k_classify_full(uint8_t *flags, uint16_t *owner, uint16_t *owner
 
 // Moving solids, phase 1 over their boxes: remember the current geometry.
 __device__ inline void classify_keep_body(const LinkArgs &a, uint32_t bx, int s) {
-  const DevSolid &sd = a.g.solids[s];
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
   if (!sd.moving) return;
   int o[3], x, y, z;
-  box_origin(sd, a.g, o);
+  double c[3];
+  box_origin(sd, a.g, o, c);
   if (!box_cell(sd, o, bx * blockDim.x + threadIdx.x, a.g, x, y, z)) return;
+  if (!near_surface(sd, c, x, y, z, a.g.b, move_band(sd))) return;  // unchanged since the last step
   const uint32_t n = id_of(x, y, z, a.g);
   const uint8_t f = a.flags[n];
   a.flags[n] = (f & F_SOLID) ? (f | F_WAS_SOLID) : (uint8_t)(f & ~F_WAS_SOLID);
@@ -98,11 +109,13 @@ __device__ inline void classify_keep_body(const LinkArgs &a, uint32_t bx, int s)
 }
 // Moving solids, phase 2 over their boxes: classify at the new time.
 __device__ inline void classify_box_body(const LinkArgs &a, uint32_t bx, int s) {
-  const DevSolid &sd = a.g.solids[s];
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
   if (!sd.moving) return;
   int o[3], x, y, z;
-  box_origin(sd, a.g, o);
+  double c[3];
+  box_origin(sd, a.g, o, c);
   if (!box_cell(sd, o, bx * blockDim.x + threadIdx.x, a.g, x, y, z)) return;
+  if (!near_surface(sd, c, x, y, z, a.g.b, move_band(sd))) return;  // cannot change this step
   const uint32_t n = id_of(x, y, z, a.g);
   const int k = classify_cell(a.g, x, y, z);
   const uint8_t old = a.flags[n];
@@ -121,12 +134,19 @@ void launch_classify(lbm_ctx *c, int64_t t, bool full);
 // Links of cell n whose solid node belongs to solid s; bit i of the result.
 template <int Q>
 __device__ inline uint32_t link_mask(const LinkArgs &a, int s, int x, int y, int z) {
-  uint32_t m = 0;
+  // all 2(Q-1) loads are independent: issue them together
+  uint8_t f[Q];
+  uint16_t o[Q];
 #pragma unroll
   for (int i = 1; i < Q; i++) {
     const uint32_t nb = id_of(x - Lat<Q>::ex(i), y - Lat<Q>::ey(i), z - Lat<Q>::ez(i), a.g);
-    if ((a.flags[nb] & F_SOLID) && a.owner[nb] == (uint16_t)s) m |= 1u << i;
+    f[i] = a.flags[nb];
+    o[i] = a.owner[nb];
   }
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 1; i < Q; i++)
+    if ((f[i] & F_SOLID) && o[i] == (uint16_t)s) m |= 1u << i;
   return m;
 }
 
@@ -152,7 +172,7 @@ __device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
     cnt++;
   }
   const double drb = cnt ? sum / cnt : 0.0, rb = 1.0 + drb;
-  const DevSolid &sd = a.g.solids[s];
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
   double c[3], r[3], uw[3];
   solid_centre(sd, a.g.t, a.g.b, c);
   lever_arm(sd, c, (double)x, (double)y, (double)z, a.g.b, r);
@@ -169,11 +189,12 @@ __device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
 template <int Q, typename S>
 __device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ double lds[16];
-  const DevSolid &sd = a.g.solids[s];
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
   int o[3], x, y, z;
-  box_origin(sd, a.g, o);
+  double c[3];
+  box_origin(sd, a.g, o, c);
   uint32_t cnt = 0;
-  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z)) {
+  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
     const uint32_t n = id_of(x, y, z, a.g);
     const uint8_t f = a.flags[n];
     if (!(f & F_SOLID)) {
@@ -235,41 +256,56 @@ __device__ inline void link_scan_body(const LinkArgs &a, int nsolid) {
 }
 __global__ void k_link_scan(LinkArgs a, int nsolid) { link_scan_body(a, nsolid); }
 
+// Exclusive prefix sum over the threads of a 256-thread block, in thread order.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds4) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  __syncthreads();  // lds4 free (previous use finished)
+  if (lane == 63) lds4[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int k = 0; k < wv; k++) base += lds4[k];
+  return base + inc - v;
+}
+
 template <int Q>
 __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
-  __shared__ uint32_t pre[kBlock];
-  const DevSolid &sd = a.g.solids[s];
+  __shared__ uint32_t wsum[kBlock / 64];
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
   int o[3], x = 0, y = 0, z = 0;
-  box_origin(sd, a.g, o);
+  double c[3];
+  box_origin(sd, a.g, o, c);
   uint32_t m = 0;
-  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z)) {
+  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
     const uint32_t n = id_of(x, y, z, a.g);
     if (!(a.flags[n] & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
   }
-  // block exclusive scan of the per-thread link counts (fixed order)
-  pre[threadIdx.x] = __popc(m);
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (uint32_t)off ? pre[threadIdx.x - off] : 0u;
-    __syncthreads();
-    pre[threadIdx.x] += v;
-    __syncthreads();
-  }
+  // position of this thread's links: box-chunk offset + links of earlier threads
+  const uint32_t before = block_exclusive_scan((uint32_t)__popc(m), wsum);
   if (!m || bx >= a.max_box_chunks) return;
-  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx] + pre[threadIdx.x] - __popc(m);
+  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx] + before;
   const uint32_t n = id_of(x, y, z, a.g);
-  double c[3];
-  solid_centre(sd, a.g.t, a.g.b, c);
+  // availability of x_ff and x_fff for every link of this cell, loads issued together
+  uint32_t ok1 = 0, ok2 = 0;
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    if (!(m & (1u << i))) continue;
+    const int ex = Lat<Q>::ex(i), ey = Lat<Q>::ey(i), ez = Lat<Q>::ez(i);
+    if (!(a.flags[id_of(x + ex, y + ey, z + ez, a.g)] & F_SOLID)) ok1 |= 1u << i;
+    if (!(a.flags[id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g)] & F_SOLID)) ok2 |= 1u << i;
+  }
+#pragma unroll
   for (int i = 1; i < Q; i++) {
     if (!(m & (1u << i))) continue;
     if (pos < a.max_links) {
       const int ex = Lat<Q>::ex(i), ey = Lat<Q>::ey(i), ez = Lat<Q>::ez(i);
-      const uint32_t ff = id_of(x + ex, y + ey, z + ez, a.g);
-      const uint32_t fff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
-      const uint32_t ffok = (a.flags[ff] & F_SOLID) ? 0u : 1u;
-      const uint32_t fffok = (a.flags[fff] & F_SOLID) ? 0u : 1u;
       a.link_cell[pos] = n;
-      a.link_meta[pos] = (uint32_t)i | (ffok << 5) | (fffok << 6);
+      a.link_meta[pos] = (uint32_t)i | (((ok1 >> i) & 1u) << 5) | (((ok2 >> i) & 1u) << 6);
       a.link_q[pos] = link_fraction(sd, c, x, y, z, ex, ey, ez, a.g.b);
     }
     pos++;
@@ -344,7 +380,7 @@ __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, 
           ez = L::ez(k);
           w = wgt<Q>(k);
         }
-      const DevSolid &sd = a.g.solids[s];
+      const DevSolid sd = load_uniform(&a.g.solids[s]);
       double c[3], r[3], uw[3];
       solid_centre(sd, t, a.g.b, c);
       lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
@@ -397,19 +433,21 @@ __global__ __launch_bounds__(256) void k_ft_reduce(FtReduceArgs r) {
 // batched forms: the same bodies over the members of a work list, each at its
 // own time t = t0 + k and state parity (k: the batch step counter)
 // ----------------------------------------------------------------------------
-__device__ inline int64_t slot_time(const BatchSlot &sl, int64_t k) { return sl.t0 + k; }
-__device__ inline void *slot_post(const BatchSlot &sl, int64_t k) { return sl.P[(sl.cur0 ^ (int)(k & 1)) ^ 1]; }
+__device__ inline int64_t slot_time(const BatchSlot *slots, int m, int64_t k) { return SLOT(m, t0) + k; }
+__device__ inline void *slot_post(const BatchSlot *slots, int m, int64_t k) {
+  return SLOT(m, P[(SLOT(m, cur0) ^ (int)(k & 1)) ^ 1]);
+}
 
 // bounce-back on the post-collision array of this step; unit = (solid, chunk)
 template <int Q, typename S>
 __global__ __launch_bounds__(64) void k_ibb_batch(const BatchSlot *__restrict__ slots, const WorkList *__restrict__ wl,
                                                    const int64_t *__restrict__ step) {
   const int64_t k = *step;
-  batch_units(wl, 1, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    const uint32_t per = (uint32_t)sl.k5_chunks;
+  batch_units(wl, 0, [&](int m, uint32_t u) {
+    const uint32_t per = (uint32_t)SLOT(m, k5_chunks);
     const int s = (int)(u / per);
-    ibb_body<Q, S>(static_cast<S *>(slot_post(sl, k)), sl.ib, slot_time(sl, k), u - (uint32_t)s * per, s);
+    const IbbArgs a = SLOT(m, ib);
+    ibb_body<Q, S>(static_cast<S *>(slot_post(slots, m, k)), a, slot_time(slots, m, k), u - (uint32_t)s * per, s);
   });
 }
 
@@ -418,19 +456,18 @@ __global__ __launch_bounds__(256) void k_ft_batch(const BatchSlot *__restrict__ 
                                                   const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    FtReduceArgs r = sl.ft;
-    r.hist = sl.hist + (uint64_t)(slot_time(sl, k) % kHistCap) * (uint64_t)sl.max_solids * 6;
+    FtReduceArgs r = SLOT(m, ft);
+    r.hist = SLOT(m, hist) + (uint64_t)(slot_time(slots, m, k) % kHistCap) * (uint64_t)SLOT(m, max_solids) * 6;
     ft_reduce_waves(r, u);
   });
 }
 
 // translating solids move to t + 1: keep, classify, count (with refill),
 // scan, emit -- each over the (solid, box chunk) units of the moving members
-__device__ inline LinkArgs move_args(const BatchSlot &sl, int64_t k) {
-  LinkArgs a = sl.lk;
-  a.g.t = slot_time(sl, k) + 1;
-  a.post = slot_post(sl, k);
+__device__ inline LinkArgs move_args(const BatchSlot *slots, int m, int64_t k) {
+  LinkArgs a = SLOT(m, lk);
+  a.g.t = slot_time(slots, m, k) + 1;
+  a.post = slot_post(slots, m, k);
   a.refill = 1;
   return a;
 }
@@ -439,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_keep_batch(const BatchSlot 
                                                                 const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const LinkArgs a = move_args(slots[m], k);
+    const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     classify_keep_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
@@ -449,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *
                                                                const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const LinkArgs a = move_args(slots[m], k);
+    const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
@@ -460,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__
                                                              const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const LinkArgs a = move_args(slots[m], k);
+    const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     link_count_body<Q, S>(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
@@ -469,14 +506,17 @@ __global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__
 __global__ __launch_bounds__(1024) void k_link_scan_batch(const BatchSlot *__restrict__ slots,
                                                           const WorkList *__restrict__ wl) {
   batch_units(wl, 0, [&](int m, uint32_t) {
-    const BatchSlot &sl = slots[m];
-    link_scan_body(sl.lk, sl.nsolid);
+    const LinkArgs a = SLOT(m, lk);
+    const int nsolid = SLOT(m, nsolid);
+    link_scan_body(a, nsolid);
     if (threadIdx.x == 0) {
-      uint32_t bad = sl.lk.misc[1] ? (uint32_t)BS_LINKS_OVERFLOW : 0u;
-      for (int s = 0; s < sl.nsolid; s++)
-        if (sl.lk.sl[s].nchunks > (uint32_t)sl.k5_chunks) bad |= BS_CHUNKS_OVERFLOW;
-      sl.status[0] |= bad;
-      sl.status[1] = sl.lk.misc[0];
+      uint32_t bad = a.misc[1] ? (uint32_t)BS_LINKS_OVERFLOW : 0u;
+      const uint32_t k5 = (uint32_t)SLOT(m, k5_chunks);
+      for (int s = 0; s < nsolid; s++)
+        if (a.sl[s].nchunks > k5) bad |= BS_CHUNKS_OVERFLOW;
+      uint32_t *st = SLOT(m, status);
+      st[0] |= bad;
+      st[1] = a.misc[0];
     }
     __syncthreads();
   });
@@ -487,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_link_emit_batch(const BatchSlot *__r
                                                             const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const LinkArgs a = move_args(slots[m], k);
+    const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     link_emit_body<Q>(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
@@ -501,15 +541,17 @@ __global__ __launch_bounds__(64) void k_force_change(const BatchSlot *__restrict
                                                      const int64_t *__restrict__ step, int64_t lag, double *out) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t) {
-    const BatchSlot &sl = slots[m];
+    const double *hist = SLOT(m, hist);
+    const int nsolid = SLOT(m, nsolid);
+    const int max_solids = SLOT(m, max_solids);
     const int s = (int)threadIdx.x;
-    const int64_t t = sl.t0 + k - 1;
+    const int64_t t = SLOT(m, t0) + k - 1;
     const bool ok = lag > 0 && lag < kHistCap && t - lag >= 0;
     double r = 0.0;
-    if (ok && s < sl.nsolid) {
-      const uint64_t per = (uint64_t)sl.max_solids * 6;
-      const double *a = sl.hist + (uint64_t)(t % kHistCap) * per + (uint64_t)s * 6;
-      const double *b = sl.hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)s * 6;
+    if (ok && s < nsolid) {
+      const uint64_t per = (uint64_t)max_solids * 6;
+      const double *a = hist + (uint64_t)(t % kHistCap) * per + (uint64_t)s * 6;
+      const double *b = hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)s * 6;
       double d2 = 0.0, n2 = 0.0;
       for (int c = 0; c < 3; c++) {
         d2 += (a[c] - b[c]) * (a[c] - b[c]);
@@ -518,12 +560,12 @@ __global__ __launch_bounds__(64) void k_force_change(const BatchSlot *__restrict
       r = n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
     }
     for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off, 64));
-    for (int s0 = 64; s0 < sl.nsolid; s0 += 64) {  // more than 64 solids: serial tail in lane 0
+    for (int s0 = 64; s0 < nsolid; s0 += 64) {  // more than 64 solids: serial tail in lane 0
       if (threadIdx.x == 0 && ok) {
-        for (int q = s0; q < min(sl.nsolid, s0 + 64); q++) {
-          const uint64_t per = (uint64_t)sl.max_solids * 6;
-          const double *a = sl.hist + (uint64_t)(t % kHistCap) * per + (uint64_t)q * 6;
-          const double *b = sl.hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)q * 6;
+        for (int q = s0; q < min(nsolid, s0 + 64); q++) {
+          const uint64_t per = (uint64_t)max_solids * 6;
+          const double *a = hist + (uint64_t)(t % kHistCap) * per + (uint64_t)q * 6;
+          const double *b = hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)q * 6;
           double d2 = 0.0, n2 = 0.0;
           for (int c = 0; c < 3; c++) {
             d2 += (a[c] - b[c]) * (a[c] - b[c]);

@@ -183,26 +183,31 @@ __global__ __launch_bounds__(128) void k_ibm_u0_batch(const BatchSlot *__restric
                                                       const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    IbmArgs a = sl.im;
-    a.t = sl.t0 + k;
-    ibm_u0_body<Q, S>(static_cast<const S *>(sl.P[sl.cur0 ^ (int)(k & 1)]), a, (int64_t)u * 128 + threadIdx.x);
+    IbmArgs a = SLOT(m, im);
+    a.t = SLOT(m, t0) + k;
+    ibm_u0_body<Q, S>(static_cast<const S *>(SLOT(m, P[SLOT(m, cur0) ^ (int)(k & 1)])), a,
+                      (int64_t)u * 128 + threadIdx.x);
   });
 }
 template <typename C>
 __global__ __launch_bounds__(128) void k_ibm_interp_batch(const BatchSlot *__restrict__ slots,
                                                           const WorkList *__restrict__ wl, int it) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    if (it < sl.n_iter) ibm_interp_body<C>(sl.im, it == 0 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+    if (it < SLOT(m, n_iter)) {
+      const IbmArgs a = SLOT(m, im);
+      ibm_interp_body<C>(a, it == 0 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+    }
   });
 }
 template <typename C>
 __global__ __launch_bounds__(128) void k_ibm_spread_batch(const BatchSlot *__restrict__ slots,
                                                           const WorkList *__restrict__ wl, int it) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    if (it < sl.n_iter) ibm_spread_body<C>(sl.im, it == sl.n_iter - 1 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+    const int n_iter = SLOT(m, n_iter);
+    if (it < n_iter) {
+      const IbmArgs a = SLOT(m, im);
+      ibm_spread_body<C>(a, it == n_iter - 1 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+    }
   });
 }
 __global__ __launch_bounds__(256) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
@@ -210,11 +215,10 @@ __global__ __launch_bounds__(256) void k_ibm_ft_batch(const BatchSlot *__restric
                                                       const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const BatchSlot &sl = slots[m];
-    IbmArgs a = sl.im;
-    a.t = sl.t0 + k;
-    double *hist = sl.hist + (uint64_t)(a.t % kHistCap) * (uint64_t)sl.max_solids * 6;
-    ibm_ft_body(a, sl.lag_start, sl.lag_count, hist, (int)u);
+    IbmArgs a = SLOT(m, im);
+    a.t = SLOT(m, t0) + k;
+    double *hist = SLOT(m, hist) + (uint64_t)(a.t % kHistCap) * (uint64_t)SLOT(m, max_solids) * 6;
+    ibm_ft_body(a, SLOT(m, lag_start), SLOT(m, lag_count), hist, (int)u);
   });
 }
 

@@ -162,9 +162,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchSlot *__restr
                                                          const int64_t *__restrict__ step, int order) {
   const int par = (int)(*step & 1);
   batch_units(wl, order, [&](int m, uint32_t blk) {
-    const BatchSlot &sl = slots[m];
-    const int cur = sl.cur0 ^ par;
-    sweep_body<Q, COLL, S, 1, NT>(static_cast<const S *>(sl.P[cur]), static_cast<S *>(sl.P[cur ^ 1]), sl.sw, blk);
+    const int cur = SLOT(m, cur0) ^ par;
+    const SweepArgs a = SLOT(m, sw);
+    sweep_body<Q, COLL, S, 1, NT>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])), a,
+                                  blk);
   });
 }
 
@@ -443,9 +444,13 @@ void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool 
 // ----------------------------------------------------------------------------
 // macroscopic fields
 // ----------------------------------------------------------------------------
-// initial: src holds the shifted pre-collision state, u = j / rho.
-// otherwise: src holds post-collision values of the last collision, whose
-// momentum is j + F, so u = (j + F/2)/rho = (j* - F/2)/rho.
+// src holds populations in the shifted (pull) form, so gathering A_i(x - e_i)
+// gives the populations that arrive at x before a collision.
+// initial (no step since the state was set): u = j / rho.
+// otherwise src is the input array of the last collision, which no later
+// kernel writes (the sweep, bounce-back and refill all write the other
+// array): the gather returns exactly what that collision used, and
+// u = (j + F/2) / rho with the force F of that collision.
 template <int Q, typename S>
 __device__ inline void macros_body(const S *__restrict__ src, double *__restrict__ out, const MacroArgs &m,
                                    uint32_t n) {
@@ -472,7 +477,7 @@ __device__ inline void macros_body(const S *__restrict__ src, double *__restrict
   double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    const uint32_t sn = m.initial ? cell_id(x - L::ex(i), y - L::ey(i), z - L::ez(i), a) : n;
+    const uint32_t sn = cell_id(x - L::ex(i), y - L::ey(i), z - L::ez(i), a);
     const double h = (double)Store<S>::ld(src + pidx<Q>(i, sn));
     drho += h;
     jx += L::ex(i) * h;
@@ -482,7 +487,9 @@ __device__ inline void macros_body(const S *__restrict__ src, double *__restrict
   const double rho = 1.0 + drho;
   double F[3] = {0.0, 0.0, 0.0};
   if (!m.initial) {
-    if (!(fl & F_NOBODY))
+    // a node fluid at the collision gets the body force unless it lies inside
+    // an IBM solid (translating solids are IBB: their flags already moved on)
+    if (m.moved || !(fl & F_NOBODY))
       for (int k = 0; k < 3; k++) F[k] = m.g[k];
     if (fl & F_IBM) {
       using C = typename Store<S>::C;
@@ -491,33 +498,17 @@ __device__ inline void macros_body(const S *__restrict__ src, double *__restrict
     }
   }
   out[n] = rho;
-  out[a.N + n] = (jx - 0.5 * F[0]) / rho;
-  out[2ull * a.N + n] = (jy - 0.5 * F[1]) / rho;
-  out[3ull * a.N + n] = (jz - 0.5 * F[2]) / rho;
+  out[a.N + n] = (jx + 0.5 * F[0]) / rho;
+  out[2ull * a.N + n] = (jy + 0.5 * F[1]) / rho;
+  out[3ull * a.N + n] = (jz + 0.5 * F[2]) / rho;
 }
 template <int Q, typename S>
 __global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, MacroArgs m) {
   macros_body<Q, S>(src, out, m, blockIdx.x * blockDim.x + threadIdx.x);
 }
-// Batched capture of the fields of the collision just done (translating
-// solids, last step of a call): post-collision state P[cur ^ 1].
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void k_macros_batch(const BatchSlot *__restrict__ slots,
-                                                       const WorkList *__restrict__ wl,
-                                                       const int64_t *__restrict__ step) {
-  const int64_t k = *step;
-  batch_units(wl, 0, [&](int s, uint32_t blk) {
-    const BatchSlot &sl = slots[s];
-    MacroArgs m = sl.mac;
-    m.t_geom = sl.t0 + k;
-    const int cur = sl.cur0 ^ (int)(k & 1);
-    macros_body<Q, S>(static_cast<const S *>(sl.P[cur ^ 1]), sl.macro, m, blk * 256 + threadIdx.x);
-  });
-}
 
-// mode 0: before any step (src = shifted pre-collision state); mode 1: after
-// a step, geometry of that step's collision; mode 2: inside a step, right after
-// the collision and before solids move (current geometry).
+// mode 0: no step since the state was set; mode 1: fields of the last
+// collision, in the geometry of that collision.
 void fill_macro_args(lbm_ctx *c, MacroArgs *mp, int mode) {
   MacroArgs &m = *mp;
   m = MacroArgs{};
@@ -526,6 +517,7 @@ void fill_macro_args(lbm_ctx *c, MacroArgs *mp, int mode) {
   const bool prev = mode == 1 && c->any_moving;
   m.owner = c->at<uint16_t>(prev ? c->L.owner1 : c->L.owner0);
   m.solid_bit = prev ? F_WAS_SOLID : F_SOLID;
+  m.moved = prev ? 1 : 0;
   m.solids = c->at<DevSolid>(c->L.solids);
   m.fibm = c->ws + c->L.fibm;
   for (int k = 0; k < 3; k++) m.g[k] = c->p.body_force[k];
@@ -553,20 +545,6 @@ void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {
 #undef LBM_MAC
 }
 
-void launch_macros_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
-#define LBM_MAC(QQ, SS) \
-  hipLaunchKernelGGL((k_macros_batch<QQ, SS>), dim3(grid), dim3(256), 0, b.stream, b.slots, wl, b.step)
-  if (b.Q == 9) {
-    if (b.storage == LBM_F64) LBM_MAC(9, double);
-    else if (b.storage == LBM_F32_DEV) LBM_MAC(9, float);
-    else LBM_MAC(9, _Float16);
-  } else {
-    if (b.storage == LBM_F64) LBM_MAC(19, double);
-    else if (b.storage == LBM_F32_DEV) LBM_MAC(19, float);
-    else LBM_MAC(19, _Float16);
-  }
-#undef LBM_MAC
-}
 
 // ----------------------------------------------------------------------------
 // zero fill, finiteness watchdog, copy probe

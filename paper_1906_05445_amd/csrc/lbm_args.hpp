@@ -101,6 +101,7 @@ struct MacroArgs {
   int64_t t_geom;
   int D;
   int initial;
+  int moved;  // solids translated after the collision: its geometry is the previous one
   int nsolid;
   uint8_t solid_bit;
 };
@@ -120,7 +121,6 @@ struct BatchSlot {
   int32_t tiles;
   int64_t t0;
   double *hist;      // force/torque history ring of the lattice
-  double *macro;     // macroscopic fields captured before translating solids move
   uint32_t *status;  // [0] sticky capacity-overflow flags, [1] link count
   const int64_t *lag_start, *lag_count;
   SweepArgs sw;
@@ -128,7 +128,6 @@ struct BatchSlot {
   LinkArgs lk;
   IbmArgs im;
   FtReduceArgs ft;
-  MacroArgs mac;
 };
 
 // Status bits of a batched lattice.
@@ -144,12 +143,23 @@ struct WorkList {
   const int32_t *slot;
 };
 
+// Load of a block-uniform value from the batch tables through the constant
+// address space: the tables are written only by the host between launches,
+// so the value can come through the scalar cache into scalar registers (only
+// the fields that are used are loaded).  The address must be block-uniform.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+  T v;
+  __builtin_memcpy(&v, (const __attribute__((address_space(4))) T *)p, sizeof(T));
+  return v;
+}
+
 // Member that owns unit `u`: the last k with start[k] <= u.
 __device__ inline int batch_member_of(const uint32_t *start, int n, uint32_t u) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= u) lo = mid;
+    if (load_uniform(start + mid) <= u) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -159,9 +169,10 @@ __device__ inline int batch_member_of(const uint32_t *start, int n, uint32_t u) 
 // contiguous share, order 1 deals the units out round-robin.  f(slot, local
 // unit) is called with the same trip count by every thread of the block.
 template <typename F>
-__device__ inline void batch_units(const WorkList *wl, int order, F f) {
-  const uint32_t total = wl->total;
-  const int n = wl->n;
+__device__ inline void batch_units(const WorkList *wlp, int order, F f) {
+  const WorkList wl = load_uniform(wlp);
+  const uint32_t total = wl.total;
+  const int n = wl.n;
   uint32_t u, end, inc;
   if (order == 0) {
     const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -174,17 +185,20 @@ __device__ inline void batch_units(const WorkList *wl, int order, F f) {
     inc = gridDim.x;
   }
   if (u >= end) return;
-  int k = batch_member_of(wl->start, n, u);
-  uint32_t lo = wl->start[k], hi = wl->start[k + 1];
+  int k = batch_member_of(wl.start, n, u);
+  uint32_t lo = load_uniform(wl.start + k), hi = load_uniform(wl.start + k + 1);
   for (; u < end; u += inc) {
     while (u >= hi) {
       k++;
       lo = hi;
-      hi = wl->start[k + 1];
+      hi = load_uniform(wl.start + k + 1);
     }
-    f(wl->slot[k], u - lo);
+    f(load_uniform(wl.slot + k), u - lo);
   }
 }
+
+// Block-uniform field of member m.
+#define SLOT(m, field) load_uniform(&slots[m].field)
 
 // Host side of a batched launch.
 struct BatchLaunch {
@@ -204,7 +218,6 @@ void fill_ibm_args(lbm_ctx *c, IbmArgs *a);
 // batched launches (grid = persistent blocks)
 void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,
                         hipEvent_t e0, hipEvent_t e1);
-void launch_macros_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_tick(hipStream_t s, int64_t *step);
 void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);

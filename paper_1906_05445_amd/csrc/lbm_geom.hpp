@@ -66,6 +66,20 @@ __device__ inline bool inside_solid(const DevSolid &s, const double c[3], int x,
   return s.inverted ? !in : in;
 }
 
+// Node within distance w of the surface of a sphere or cylinder (planes:
+// always).  Used to skip nodes that can neither change classification nor
+// carry a boundary link; w carries a generous margin, so rounding here never
+// drops a node that the exact tests above would keep.
+__device__ inline bool near_surface(const DevSolid &s, const double c[3], int x, int y, int z, const Box3 &b,
+                                    double w) {
+  if (s.kind == K_PLANE) return true;
+  double d[3];
+  separation(s, c, (double)x, (double)y, (double)z, b, d);
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const double hi = s.R + w, lo = s.R - w;
+  return r2 <= hi * hi && (lo <= 0.0 || r2 >= lo * lo);
+}
+
 // Fraction q in (0, 1] of the segment from fluid node (x,y,z) along e_ibar
 // (towards the solid node) where it crosses the surface of s.
 __device__ inline double link_fraction(const DevSolid &s, const double c[3], int x, int y, int z, int eix,

@@ -37,7 +37,7 @@ struct SolidLinks {
 // Regions carved out of the caller's workspace (byte offsets).
 struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
-      partials, solids, hist, staging, macro, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
+      partials, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
       lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials;

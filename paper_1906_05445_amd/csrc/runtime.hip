@@ -129,7 +129,6 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.solids = take((size_t)max_solids * sizeof(DevSolid));
   l.hist = take((size_t)kHistCap * max_solids * 6 * 8);
   l.staging = take((size_t)4 * N * 8);
-  l.macro = take((size_t)4 * N * 8);
   l.fibm = take((size_t)3 * l.stride * cs);
   l.lag_X = take((size_t)max_lag * 24);
   l.lag_dV = take((size_t)max_lag * 8);
@@ -746,9 +745,6 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       launch_ibb(c, B, c->t);
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
-        // the refill below writes into neighbours' post-collision slots: keep
-        // the macroscopic fields of this collision first (last step of the call)
-        if (k == nsteps - 1) launch_macros(c, B, c->at<double>(c->L.macro), 2);
         launch_classify(c, c->t + 1, false);
         launch_link_count(c, c->t + 1, true, B);
         launch_link_scan(c);
@@ -815,9 +811,8 @@ static lbm_status node_types_at(lbm_ctx *c, uint8_t *node_type, bool last_collis
 lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type) {
   if (!c) return LBM_EINVAL;
   double *stg = c->at<double>(c->L.staging);
-  const bool ibb_moving = c->any_moving && c->method != LBM_IBM && c->nsolid > 0;
-  if (!c->fresh && ibb_moving) stg = c->at<double>(c->L.macro);  // captured inside lbm_step
-  else launch_macros(c, c->state(), stg, c->fresh ? 0 : 1);
+  // after a step the other array still holds the input of the last collision
+  launch_macros(c, c->fresh ? c->state() : c->other(), stg, c->fresh ? 0 : 1);
   HIPCALL(hipGetLastError());
   const size_t N = (size_t)c->N;
   if (rho) HIPCALL(hipMemcpyAsync(rho, stg, N * 8, hipMemcpyDeviceToHost, c->stream));

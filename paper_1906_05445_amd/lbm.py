@@ -108,6 +108,8 @@ _sig("lbm_batch_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER
 _sig("lbm_batch_tune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_time_sweep", _st, [_vp, _i64, _d])
+_sig("lbm_batch_tune_table", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_force_change", _st, [_vp, _i64, ctypes.POINTER(_vp), _d])
 _sig("lbm_batch_stream", _vp, [_vp])
 _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
@@ -119,7 +121,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagr
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
             "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_batch_table_bytes", "lbm_batch_create",
             "lbm_batch_admit", "lbm_batch_release", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_info",
-            "lbm_batch_tune_info", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_stream", "lbm_batch_last_error",
+            "lbm_batch_tune_info", "lbm_batch_tune_table", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_stream", "lbm_batch_last_error",
             "lbm_batch_destroy"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
@@ -420,6 +422,17 @@ class Batch:
             if h and h in by_handle:
                 out[by_handle[h]] = float(self._change_buf[k])
         return out
+
+    def tune_table(self):
+        """Every sweep candidate of the tuner with its measured time (us; -1 before tuning)."""
+        n = _lib.lbm_batch_tune_table(self.handle, 0, None, None, None, None)
+        nt = (ctypes.c_int32 * n)()
+        order = (ctypes.c_int32 * n)()
+        blocks = (ctypes.c_int32 * n)()
+        us = np.zeros(n)
+        _lib.lbm_batch_tune_table(self.handle, n, nt, order, blocks, _ptr(us))
+        return [{"nontemporal_stores": nt[k], "order": order[k], "blocks": blocks[k], "sweep_us": float(us[k])}
+                for k in range(n)]
 
     def time_sweep(self, n):
         us = ctypes.c_double(0.0)
