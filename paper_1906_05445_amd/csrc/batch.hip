@@ -35,7 +35,8 @@ enum {
   WL_FT,
   WL_BOX,        // (solid, box chunk) units of members with translating solids
   WL_ONE,        // one unit per member with translating solids
-  WL_IBM_SHELL,
+  WL_IBM_SHELL,   // 128 shell cells per unit (u0)
+  WL_IBM_SPREAD,  // 16 shell cells per unit (spreading, 16 lanes per cell)
   WL_IBM_LAG,
   WL_IBM_FT,
   WL_SOLID,      // one unit per member with solids (convergence check)
@@ -230,7 +231,7 @@ lbm_status rebuild(lbm_batch *b) {
     };
     const int coll = collision_kind(c);
     b->coll_mask |= 1u << coll;
-    add(WL_SWEEP + coll, tiles);
+    add(WL_SWEEP + coll, (tiles + sweep_cpt_storage(c->store_bytes) - 1) / sweep_cpt_storage(c->store_bytes));
     b->tiles += tiles;
     if (member_ibb(c)) {
       b->any_ibb = true;
@@ -247,7 +248,8 @@ lbm_status rebuild(lbm_batch *b) {
       b->any_ibm = true;
       b->max_iter = std::max(b->max_iter, c->n_iter);
       add(WL_IBM_SHELL, (uint64_t)((c->nshell + 127) / 128));
-      add(WL_IBM_LAG, (uint64_t)((c->nlag + 127) / 128));
+      add(WL_IBM_SPREAD, (uint64_t)((c->nshell + 15) / 16));
+      add(WL_IBM_LAG, (uint64_t)((c->nlag + 3) / 4));  // four points (wavefronts) per block
       add(WL_IBM_FT, (uint64_t)c->nsolid);
     }
   }
@@ -291,7 +293,7 @@ uint32_t grid_of(const lbm_batch *b, int mult) { return (uint32_t)std::max(1, mu
 // One batched step (enqueue only); e0/e1 (optional) time the sweep launches.
 void enqueue_step(lbm_batch *b, const SweepCfg &cfg, hipEvent_t e0, hipEvent_t e1) {
   const BatchLaunch bl{b->d_slots, b->d_step, b->stream, b->Q, b->storage};
-  if (b->any_ibm) launch_ibm_batch(bl, b->wl(WL_IBM_SHELL), b->wl(WL_IBM_LAG), b->wl(WL_IBM_FT), b->max_iter,
+  if (b->any_ibm) launch_ibm_batch(bl, b->wl(WL_IBM_SHELL), b->wl(WL_IBM_SPREAD), b->wl(WL_IBM_LAG), b->wl(WL_IBM_FT), b->max_iter,
                                    grid_of(b, 4));
   int first = -1, lastc = -1;
   for (int k = 0; k < 3; k++)

@@ -27,6 +27,19 @@ __device__ inline uint32_t id_of(int x, int y, int z, const GeoArgs &a) {
          (uint32_t)a.b.nx * ((uint32_t)wrapi(y, a.b.ny) + (uint32_t)a.b.ny * (uint32_t)wrapi(z, a.b.nz));
 }
 
+// Direction i (runtime) of the velocity set.
+template <int Q>
+__device__ inline void dir_of(int i, int &ex, int &ey, int &ez) {
+  ex = ey = ez = 0;
+#pragma unroll
+  for (int k = 1; k < Q; k++)
+    if (k == i) {
+      ex = Lat<Q>::ex(k);
+      ey = Lat<Q>::ey(k);
+      ez = Lat<Q>::ez(k);
+    }
+}
+
 // Box of solid s at time t: cell (lx, ly, lz) of the box -> lattice cell.
 // Also returns the centre at t.
 __device__ inline void box_origin(const DevSolid &s, const GeoArgs &a, int o[3], double c[3]) {
@@ -51,9 +64,8 @@ constexpr double kLinkBand = 1.5;
 __device__ inline bool box_cell(const DevSolid &s, const int o[3], uint32_t bi, const GeoArgs &a, int &x, int &y,
                                 int &z) {
   if (bi >= s.box_cells) return false;
-  const uint32_t ex = (uint32_t)s.ext[0], ey = (uint32_t)s.ext[1];
-  const uint32_t lx = bi % ex, r = bi / ex;
-  const uint32_t ly = r % ey, lz = r / ey;
+  const uint32_t r = fdiv(bi, s.fex), lz = fdiv(bi, s.fexy);
+  const uint32_t lx = bi - r * (uint32_t)s.ext[0], ly = r - lz * (uint32_t)s.ext[1];
   x = wrapi(o[0] + (int)lx, a.b.nx);
   y = wrapi(o[1] + (int)ly, a.b.ny);
   z = wrapi(o[2] + (int)lz, a.b.nz);
@@ -95,6 +107,10 @@ __global__ void k_classify_full(uint8_t *flags, uint16_t *owner, uint16_t *owner
 
 // Moving solids, phase 1 over their boxes: remember the current geometry.
 __device__ inline void classify_keep_body(const LinkArgs &a, uint32_t bx, int s) {
+  if (bx == 0 && s == 0 && threadIdx.x == 0) {  // the refill list of this step starts empty
+    a.misc[3] = 0;
+    a.misc[4] = 0;
+  }
   const DevSolid sd = load_uniform(&a.g.solids[s]);
   if (!sd.moving) return;
   int o[3], x, y, z;
@@ -119,8 +135,15 @@ __device__ inline void classify_box_body(const LinkArgs &a, uint32_t bx, int s) 
   const uint32_t n = id_of(x, y, z, a.g);
   const int k = classify_cell(a.g, x, y, z);
   const uint8_t old = a.flags[n];
-  a.flags[n] = (uint8_t)(flags_for(a.g, k, old & F_IBM) | (old & F_WAS_SOLID));
+  const uint8_t now = (uint8_t)(flags_for(a.g, k, old & F_IBM) | (old & F_WAS_SOLID));
+  a.flags[n] = now;
   a.owner[n] = k < 0 ? 0xFFFF : (uint16_t)k;
+  // uncovered by solid s (the box of its previous owner lists it once): refill
+  if ((now & F_WAS_SOLID) && !(now & F_SOLID) && a.owner_prev[n] == (uint16_t)s) {
+    const uint32_t at = atomicAdd(&a.misc[3], 1u);
+    if (at < a.max_refill) a.refill_list[at] = ((uint64_t)(uint32_t)s << 32) | n;
+    else a.misc[4] = 1u;
+  }
 }
 __global__ void k_classify_keep(LinkArgs a) { classify_keep_body(a, blockIdx.x, blockIdx.y); }
 __global__ void k_classify_box(LinkArgs a) { classify_box_body(a, blockIdx.x, blockIdx.y); }
@@ -153,40 +176,63 @@ __device__ inline uint32_t link_mask(const LinkArgs &a, int s, int x, int y, int
 // Refill of a node uncovered this step (Sec. 3.2): f = f_eq(rho_bar, u_w)
 // with rho_bar the mean density at t of the neighbours that are fluid
 // before and after the move (1 if none); written into the slots the node
-// pulls from, P_i(x - e_i).
+// pulls from, P_i(x - e_i).  One wavefront per node, lane i gathering the
+// density of neighbour x + e_i.  Refills touch disjoint slots (a node's own
+// pull slots belong to other cells than those its neighbours' densities are
+// gathered from), so the list order does not matter.
 template <int Q, typename S>
-__device__ void refill_node(const LinkArgs &a, int s, int x, int y, int z) {
+__device__ void refill_wave(const LinkArgs &a, uint64_t entry) {
   using L = Lat<Q>;
   S *P = static_cast<S *>(a.post);
-  double sum = 0.0;  // of the density deviations rho - 1
-  int cnt = 0;
-  for (int i = 1; i < Q; i++) {
-    const int yx = x + L::ex(i), yy = y + L::ey(i), yzz = z + L::ez(i);
-    const uint32_t m = id_of(yx, yy, yzz, a.g);
-    if (a.flags[m] & (F_SOLID | F_WAS_SOLID)) continue;
-    double r = 0.0;
+  const int s = __builtin_amdgcn_readfirstlane((int)(entry >> 32));
+  const uint32_t n = (uint32_t)entry;
+  int x, y, z;
+  xyz_of(n, a.g, x, y, z);
+  const int lane = (int)(threadIdx.x & 63);
+  double r = 0.0;
+  bool use = false;
+  if (lane >= 1 && lane < Q) {
+    int ex, ey, ez;
+    dir_of<Q>(lane, ex, ey, ez);
+    const int yx = x + ex, yy = y + ey, yzz = z + ez;
+    use = !(a.flags[id_of(yx, yy, yzz, a.g)] & (F_SOLID | F_WAS_SOLID));
+    if (use) {
 #pragma unroll
-    for (int j = 0; j < Q; j++)
-      r += (double)Store<S>::ld(P + pidx<Q>(j, id_of(yx - L::ex(j), yy - L::ey(j), yzz - L::ez(j), a.g)));
-    sum += r;
-    cnt++;
+      for (int j = 0; j < Q; j++)
+        r += (double)Store<S>::ld(P + pidx<Q>(j, id_of(yx - L::ex(j), yy - L::ey(j), yzz - L::ez(j), a.g)));
+    }
   }
+  const int cnt = __popcll(__ballot(use));
+  const double sum = __shfl(wave_sum(use ? r : 0.0), 0, 64);  // density deviations rho - 1
   const double drb = cnt ? sum / cnt : 0.0, rb = 1.0 + drb;
   const DevSolid sd = load_uniform(&a.g.solids[s]);
-  double c[3], r[3], uw[3];
+  double c[3], lv[3], uw[3];
   solid_centre(sd, a.g.t, a.g.b, c);
-  lever_arm(sd, c, (double)x, (double)y, (double)z, a.g.b, r);
-  wall_vel(sd, r, uw);
-  const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+  lever_arm(sd, c, (double)x, (double)y, (double)z, a.g.b, lv);
+  wall_vel(sd, lv, uw);
+  if (lane < Q) {
+    int ex, ey, ez;
+    dir_of<Q>(lane, ex, ey, ez);
+    const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+    const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
+    double w = 0.0;
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const double eu = L::ex(i) * uw[0] + L::ey(i) * uw[1] + L::ez(i) * uw[2];
-    const double heq = wgt<Q>(i) * (drb + rb * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
-    Store<S>::st(P + pidx<Q>(i, id_of(x - L::ex(i), y - L::ey(i), z - L::ez(i), a.g)), (typename Store<S>::C)heq);
+    for (int k = 0; k < Q; k++)
+      if (k == lane) w = wgt<Q>(k);
+    const double heq = w * (drb + rb * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    Store<S>::st(P + pidx<Q>(lane, id_of(x - ex, y - ey, z - ez, a.g)), (typename Store<S>::C)heq);
   }
 }
 
+// Waves of the grid walk the refill list (count in misc[3]).
 template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_refill(LinkArgs a) {
+  const uint32_t cnt = min(a.misc[3], a.max_refill);
+  for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += gridDim.x * 4)
+    refill_wave<Q, S>(a, a.refill_list[e]);
+}
+
+template <int Q>
 __device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ double lds[16];
   const DevSolid sd = load_uniform(&a.g.solids[s]);
@@ -197,17 +243,14 @@ __device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
     const uint32_t n = id_of(x, y, z, a.g);
     const uint8_t f = a.flags[n];
-    if (!(f & F_SOLID)) {
-      if (a.refill && (f & F_WAS_SOLID) && a.owner_prev[n] == (uint16_t)s) refill_node<Q, S>(a, s, x, y, z);
-      cnt = __popc(link_mask<Q>(a, s, x, y, z));
-    }
+    if (!(f & F_SOLID)) cnt = __popc(link_mask<Q>(a, s, x, y, z));
   }
   const double tot = block_sum((double)cnt, lds);
   if (threadIdx.x == 0 && bx < a.max_box_chunks) a.box_counts[(uint64_t)s * a.max_box_chunks + bx] = (uint32_t)tot;
 }
-template <int Q, typename S>
+template <int Q>
 __global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
-  link_count_body<Q, S>(a, blockIdx.x, blockIdx.y);
+  link_count_body<Q>(a, blockIdx.x, blockIdx.y);
 }
 
 // One block: exclusive scan of the per-(solid, box chunk) counts, then the
@@ -256,8 +299,9 @@ __device__ inline void link_scan_body(const LinkArgs &a, int nsolid) {
 }
 __global__ void k_link_scan(LinkArgs a, int nsolid) { link_scan_body(a, nsolid); }
 
-// Exclusive prefix sum over the threads of a 256-thread block, in thread order.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds4) {
+// Exclusive prefix sum over the threads of a 256-thread block, in thread
+// order; *total receives the block sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds4, uint32_t *total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t inc = v;
 #pragma unroll
@@ -268,47 +312,67 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds4) {
   __syncthreads();  // lds4 free (previous use finished)
   if (lane == 63) lds4[wv] = inc;
   __syncthreads();
-  uint32_t base = 0;
-  for (int k = 0; k < wv; k++) base += lds4[k];
+  uint32_t base = 0, all = 0;
+  for (int k = 0; k < kBlock / 64; k++) {
+    if (k < wv) base += lds4[k];
+    all += lds4[k];
+  }
+  *total = all;
   return base + inc - v;
 }
 
+constexpr int kEmitWindow = 1024;  // links of one unit staged in LDS at a time
+
+// Links of one unit (256 box cells): each thread stages its links (cell,
+// direction) in LDS at their place in the unit's order (by cell, then
+// direction), then the whole block computes q and the x_ff / x_fff bits, one
+// link per thread, and writes them.
 template <int Q>
 __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ uint32_t wsum[kBlock / 64];
+  __shared__ uint32_t st_cell[kEmitWindow];
+  __shared__ uint8_t st_dir[kEmitWindow];
   const DevSolid sd = load_uniform(&a.g.solids[s]);
   int o[3], x = 0, y = 0, z = 0;
   double c[3];
   box_origin(sd, a.g, o, c);
-  uint32_t m = 0;
+  uint32_t m = 0, n = 0;
   if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
-    const uint32_t n = id_of(x, y, z, a.g);
+    n = id_of(x, y, z, a.g);
     if (!(a.flags[n] & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
   }
-  // position of this thread's links: box-chunk offset + links of earlier threads
-  const uint32_t before = block_exclusive_scan((uint32_t)__popc(m), wsum);
-  if (!m || bx >= a.max_box_chunks) return;
-  uint64_t pos = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx] + before;
-  const uint32_t n = id_of(x, y, z, a.g);
-  // availability of x_ff and x_fff for every link of this cell, loads issued together
-  uint32_t ok1 = 0, ok2 = 0;
-#pragma unroll
-  for (int i = 1; i < Q; i++) {
-    if (!(m & (1u << i))) continue;
-    const int ex = Lat<Q>::ex(i), ey = Lat<Q>::ey(i), ez = Lat<Q>::ez(i);
-    if (!(a.flags[id_of(x + ex, y + ey, z + ez, a.g)] & F_SOLID)) ok1 |= 1u << i;
-    if (!(a.flags[id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g)] & F_SOLID)) ok2 |= 1u << i;
-  }
-#pragma unroll
-  for (int i = 1; i < Q; i++) {
-    if (!(m & (1u << i))) continue;
-    if (pos < a.max_links) {
-      const int ex = Lat<Q>::ex(i), ey = Lat<Q>::ey(i), ez = Lat<Q>::ez(i);
-      a.link_cell[pos] = n;
-      a.link_meta[pos] = (uint32_t)i | (((ok1 >> i) & 1u) << 5) | (((ok2 >> i) & 1u) << 6);
-      a.link_q[pos] = link_fraction(sd, c, x, y, z, ex, ey, ez, a.g.b);
+  uint32_t total;
+  const uint32_t before = block_exclusive_scan((uint32_t)__popc(m), wsum, &total);
+  if (bx >= a.max_box_chunks) return;  // uniform over the block
+  const uint64_t base = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx];
+  for (uint32_t w0 = 0; w0 < total; w0 += kEmitWindow) {
+    uint32_t k = before, mm = m;
+    while (mm) {
+      const int i = __ffs(mm) - 1;
+      mm &= mm - 1;
+      if (k >= w0 && k < w0 + kEmitWindow) {
+        st_cell[k - w0] = n;
+        st_dir[k - w0] = (uint8_t)i;
+      }
+      k++;
     }
-    pos++;
+    __syncthreads();
+    const uint32_t cnt = min(total - w0, (uint32_t)kEmitWindow);
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+      const uint64_t pos = base + w0 + j;
+      if (pos >= a.max_links) continue;
+      const uint32_t cell = st_cell[j];
+      const int i = st_dir[j];
+      int ex, ey, ez, lx, ly, lz;
+      dir_of<Q>(i, ex, ey, ez);
+      xyz_of(cell, a.g, lx, ly, lz);
+      const uint32_t ok1 = (a.flags[id_of(lx + ex, ly + ey, lz + ez, a.g)] & F_SOLID) ? 0u : 1u;
+      const uint32_t ok2 = (a.flags[id_of(lx + 2 * ex, ly + 2 * ey, lz + 2 * ez, a.g)] & F_SOLID) ? 0u : 1u;
+      a.link_cell[pos] = cell;
+      a.link_meta[pos] = (uint32_t)i | (ok1 << 5) | (ok2 << 6);
+      a.link_q[pos] = link_fraction(sd, c, lx, ly, lz, ex, ey, ez, a.g.b);
+    }
+    __syncthreads();
   }
 }
 template <int Q>
@@ -468,7 +532,6 @@ __device__ inline LinkArgs move_args(const BatchSlot *slots, int m, int64_t k) {
   LinkArgs a = SLOT(m, lk);
   a.g.t = slot_time(slots, m, k) + 1;
   a.post = slot_post(slots, m, k);
-  a.refill = 1;
   return a;
 }
 __global__ __launch_bounds__(kBlock) void k_classify_keep_batch(const BatchSlot *__restrict__ slots,
@@ -491,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *
     classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
 }
-template <int Q, typename S>
+template <int Q>
 __global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__restrict__ slots,
                                                              const WorkList *__restrict__ wl,
                                                              const int64_t *__restrict__ step) {
@@ -499,7 +562,19 @@ __global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__
   batch_units(wl, 0, [&](int m, uint32_t u) {
     const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
-    link_count_body<Q, S>(a, u - (uint32_t)s * a.max_box_chunks, s);
+    link_count_body<Q>(a, u - (uint32_t)s * a.max_box_chunks, s);
+  });
+}
+// refill: one unit (a block of four waves) per member with translating solids
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_refill_batch(const BatchSlot *__restrict__ slots,
+                                                      const WorkList *__restrict__ wl,
+                                                      const int64_t *__restrict__ step) {
+  const int64_t k = *step;
+  batch_units(wl, 0, [&](int m, uint32_t) {
+    const LinkArgs a = move_args(slots, m, k);
+    const uint32_t cnt = min(a.misc[3], a.max_refill);
+    for (uint32_t e = threadIdx.x >> 6; e < cnt; e += 4) refill_wave<Q, S>(a, a.refill_list[e]);
   });
 }
 // one unit per member; also folds the capacity checks into its status words
@@ -511,6 +586,7 @@ __global__ __launch_bounds__(1024) void k_link_scan_batch(const BatchSlot *__res
     link_scan_body(a, nsolid);
     if (threadIdx.x == 0) {
       uint32_t bad = a.misc[1] ? (uint32_t)BS_LINKS_OVERFLOW : 0u;
+      if (a.misc[4]) bad |= BS_REFILL_OVERFLOW;
       const uint32_t k5 = (uint32_t)SLOT(m, k5_chunks);
       for (int s = 0; s < nsolid; s++)
         if (a.sl[s].nchunks > k5) bad |= BS_CHUNKS_OVERFLOW;
@@ -605,17 +681,20 @@ void launch_move_batch(const BatchLaunch &b, const WorkList *box, const WorkList
   const dim3 g(grid), blk(kBlock);
   hipLaunchKernelGGL(k_classify_keep_batch, g, blk, 0, b.stream, b.slots, box, b.step);
   hipLaunchKernelGGL(k_classify_box_batch, g, blk, 0, b.stream, b.slots, box, b.step);
-#define LBM_LC(QQ, SS) hipLaunchKernelGGL((k_link_count_batch<QQ, SS>), g, blk, 0, b.stream, b.slots, box, b.step)
+  const dim3 g1(std::min<uint32_t>(grid, 1024));
+#define LBM_RF(QQ, SS) hipLaunchKernelGGL((k_refill_batch<QQ, SS>), g1, dim3(256), 0, b.stream, b.slots, one, b.step)
   if (b.Q == 9) {
-    if (b.storage == LBM_F64) LBM_LC(9, double);
-    else if (b.storage == LBM_F32_DEV) LBM_LC(9, float);
-    else LBM_LC(9, _Float16);
+    if (b.storage == LBM_F64) LBM_RF(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_RF(9, float);
+    else LBM_RF(9, _Float16);
   } else {
-    if (b.storage == LBM_F64) LBM_LC(19, double);
-    else if (b.storage == LBM_F32_DEV) LBM_LC(19, float);
-    else LBM_LC(19, _Float16);
+    if (b.storage == LBM_F64) LBM_RF(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_RF(19, float);
+    else LBM_RF(19, _Float16);
   }
-#undef LBM_LC
+#undef LBM_RF
+  if (b.Q == 9) hipLaunchKernelGGL(k_link_count_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
+  else hipLaunchKernelGGL(k_link_count_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
   hipLaunchKernelGGL(k_link_scan_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, one);
   if (b.Q == 9) hipLaunchKernelGGL(k_link_emit_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
   else hipLaunchKernelGGL(k_link_emit_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
@@ -654,6 +733,8 @@ static LinkArgs link_args(const lbm_ctx *c, int64_t t) {
   a.max_links = (uint64_t)c->L.max_links;
   a.sl = c->at<SolidLinks>(c->L.solid_links);
   a.misc = c->at<uint32_t>(c->L.misc);
+  a.refill_list = c->at<uint64_t>(c->L.refill);
+  a.max_refill = (uint32_t)c->L.max_refill;
   return a;
 }
 
@@ -686,22 +767,27 @@ void launch_classify(lbm_ctx *c, int64_t t, bool full) {
   hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, a);
 }
 
-void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *post) {
+void launch_refill(lbm_ctx *c, int64_t t, void *post) {
   LinkArgs a = link_args(c, t);
-  a.refill = refill ? 1 : 0;
-  a.post = const_cast<void *>(post);
-  const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
-#define LBM_LC(QQ, SS) hipLaunchKernelGGL((k_link_count<QQ, SS>), grid, dim3(kBlock), 0, c->stream, a)
+  a.post = post;
+#define LBM_RF(QQ, SS) hipLaunchKernelGGL((k_refill<QQ, SS>), dim3(64), dim3(256), 0, c->stream, a)
   if (c->Q == 9) {
-    if (c->p.storage == LBM_F64) LBM_LC(9, double);
-    else if (c->p.storage == LBM_F32_DEV) LBM_LC(9, float);
-    else LBM_LC(9, _Float16);
+    if (c->p.storage == LBM_F64) LBM_RF(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_RF(9, float);
+    else LBM_RF(9, _Float16);
   } else {
-    if (c->p.storage == LBM_F64) LBM_LC(19, double);
-    else if (c->p.storage == LBM_F32_DEV) LBM_LC(19, float);
-    else LBM_LC(19, _Float16);
+    if (c->p.storage == LBM_F64) LBM_RF(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_RF(19, float);
+    else LBM_RF(19, _Float16);
   }
-#undef LBM_LC
+#undef LBM_RF
+}
+
+void launch_link_count(lbm_ctx *c, int64_t t) {
+  LinkArgs a = link_args(c, t);
+  const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
+  if (c->Q == 9) hipLaunchKernelGGL(k_link_count<9>, grid, dim3(kBlock), 0, c->stream, a);
+  else hipLaunchKernelGGL(k_link_count<19>, grid, dim3(kBlock), 0, c->stream, a);
 }
 
 void launch_link_scan(lbm_ctx *c) {

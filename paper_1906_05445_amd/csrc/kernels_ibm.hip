@@ -81,24 +81,36 @@ __device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, in
 }
 
 // Eq. 5 and Eq. 7: interpolate u to the point, F = rho0 (U^d - U~)/dt.
+// One wavefront per point, one stencil cell per lane (4^D cells), summed by
+// a fixed-order wave reduction.
+constexpr int kIbmPointsPerBlock = 4;  // 256-thread blocks
+
+template <typename C>
+__device__ inline C wave_sum_c(C v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 template <typename C>
 __device__ inline void ibm_interp_body(const IbmArgs &a, int first, int64_t l) {
-  if (l >= a.nlag) return;
+  const int slot = (int)(threadIdx.x & 63);
+  const int kz = slot >> 4, ky = (slot >> 2) & 3, kx = slot & 3;
   const C *u = static_cast<const C *>(a.ushell);
-  const double *w = a.wts + l * 12;
-  const uint32_t *ix = a.idx + l * 64;
-  const int nz = a.b.D == 2 ? 1 : 4;
-  C s[3] = {0, 0, 0};
-  for (int kz = 0; kz < nz; kz++)
-    for (int ky = 0; ky < 4; ky++)
-      for (int kx = 0; kx < 4; kx++) {
-        const int slot = kz * 16 + ky * 4 + kx;
-        const C wt = (C)((w[kx] * w[4 + ky]) * w[8 + kz]);
-        const uint32_t si = ix[slot];
-        s[0] += u[si] * wt;
-        s[1] += u[a.nshell + si] * wt;
-        s[2] += u[2 * a.nshell + si] * wt;
-      }
+  C v0 = 0, v1 = 0, v2 = 0;
+  if (l < a.nlag && kz < (a.b.D == 2 ? 1 : 4)) {
+    const double *w = a.wts + l * 12;
+    const C wt = (C)((w[kx] * w[4 + ky]) * w[8 + kz]);
+    const uint32_t si = a.idx[l * 64 + slot];
+    v0 = u[si] * wt;
+    v1 = u[a.nshell + si] * wt;
+    v2 = u[2 * a.nshell + si] * wt;
+  }
+  v0 = wave_sum_c(v0);
+  v1 = wave_sum_c(v1);
+  v2 = wave_sum_c(v2);
+  if (slot != 0 || l >= a.nlag) return;
+  const C s[3] = {v0, v1, v2};
   C *Fk = static_cast<C *>(a.Fk);
   for (int k = 0; k < 3; k++) {
     const C F = (C)a.Ud[l * 3 + k] - s[k];
@@ -107,20 +119,32 @@ __device__ inline void ibm_interp_body(const IbmArgs &a, int first, int64_t l) {
   }
 }
 
-// Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.
+// Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.  Sixteen
+// lanes per shell cell share its (point, slot) list, lane k taking entries
+// k, k+16, ...; the lane partials are then summed in a fixed tree order.
+constexpr int kSpreadLanes = 16;
+constexpr int kSpreadCellsPerBlock = 256 / kSpreadLanes;
+
 template <typename C>
 __device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
-  if (s >= a.nshell) return;
+  const int lane = (int)(threadIdx.x & (kSpreadLanes - 1));
   const C *Fk = static_cast<const C *>(a.Fk);
   C f[3] = {0, 0, 0};
-  for (uint32_t e = a.rowptr[s]; e < a.rowptr[s + 1]; e++) {
-    const uint32_t v = a.ent[e];
-    const uint32_t l = v >> 6, slot = v & 63u;
-    const double *w = a.wts + (uint64_t)l * 12;
-    const C wt = (C)((w[slot & 3u] * w[4 + ((slot >> 2) & 3u)]) * w[8 + (slot >> 4)]);
-    const C dv = (C)a.dV[l];
-    for (int k = 0; k < 3; k++) f[k] += Fk[(uint64_t)l * 3 + k] * wt * dv;
+  if (s < a.nshell) {
+    const uint32_t e1 = a.rowptr[s + 1];
+    for (uint32_t e = a.rowptr[s] + lane; e < e1; e += kSpreadLanes) {
+      const uint32_t v = a.ent[e];
+      const uint32_t l = v >> 6, slot = v & 63u;
+      const double *w = a.wts + (uint64_t)l * 12;
+      const C wt = (C)((w[slot & 3u] * w[4 + ((slot >> 2) & 3u)]) * w[8 + (slot >> 4)]);
+      const C dv = (C)a.dV[l];
+      for (int k = 0; k < 3; k++) f[k] += Fk[(uint64_t)l * 3 + k] * wt * dv;
+    }
   }
+#pragma unroll
+  for (int off = kSpreadLanes / 2; off > 0; off >>= 1)
+    for (int k = 0; k < 3; k++) f[k] += __shfl_down(f[k], off, kSpreadLanes);
+  if (lane != 0 || s >= a.nshell) return;
   C *u = static_cast<C *>(a.ushell);
   C *fs = static_cast<C *>(a.fshell);
   for (int k = 0; k < 3; k++) {
@@ -163,14 +187,14 @@ __global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
   ibm_u0_body<Q, S>(A, a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
 template <typename C>
-__global__ void k_ibm_interp(IbmArgs a, int first) {
-  ibm_interp_body<C>(a, first, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void k_ibm_interp(IbmArgs a, int first) {
+  ibm_interp_body<C>(a, first, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
 template <typename C>
-__global__ void k_ibm_spread(IbmArgs a, int last) {
-  ibm_spread_body<C>(a, last, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void k_ibm_spread(IbmArgs a, int last) {
+  ibm_spread_body<C>(a, last, (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
 }
-__global__ void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
+__global__ __launch_bounds__(1024) void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
   ibm_ft_body(a, start, count, hist, blockIdx.x);
 }
 
@@ -190,27 +214,28 @@ __global__ __launch_bounds__(128) void k_ibm_u0_batch(const BatchSlot *__restric
   });
 }
 template <typename C>
-__global__ __launch_bounds__(128) void k_ibm_interp_batch(const BatchSlot *__restrict__ slots,
+__global__ __launch_bounds__(256) void k_ibm_interp_batch(const BatchSlot *__restrict__ slots,
                                                           const WorkList *__restrict__ wl, int it) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
     if (it < SLOT(m, n_iter)) {
       const IbmArgs a = SLOT(m, im);
-      ibm_interp_body<C>(a, it == 0 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+      ibm_interp_body<C>(a, it == 0 ? 1 : 0, (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6));
     }
   });
 }
 template <typename C>
-__global__ __launch_bounds__(128) void k_ibm_spread_batch(const BatchSlot *__restrict__ slots,
+__global__ __launch_bounds__(256) void k_ibm_spread_batch(const BatchSlot *__restrict__ slots,
                                                           const WorkList *__restrict__ wl, int it) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
     const int n_iter = SLOT(m, n_iter);
     if (it < n_iter) {
       const IbmArgs a = SLOT(m, im);
-      ibm_spread_body<C>(a, it == n_iter - 1 ? 1 : 0, (int64_t)u * 128 + threadIdx.x);
+      ibm_spread_body<C>(a, it == n_iter - 1 ? 1 : 0,
+                         (int64_t)u * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
     }
   });
 }
-__global__ __launch_bounds__(256) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
+__global__ __launch_bounds__(1024) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
                                                       const WorkList *__restrict__ wl,
                                                       const int64_t *__restrict__ step) {
   const int64_t k = *step;
@@ -264,43 +289,45 @@ template <typename S>
 static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t) {
   using C = typename Store<S>::C;
   IbmArgs a = ibm_args(c, t);
-  const dim3 gs((uint32_t)((c->nshell + 127) / 128)), gl((uint32_t)((c->nlag + 127) / 128));
+  const dim3 gs((uint32_t)((c->nshell + 127) / 128)),
+      gl((uint32_t)((c->nlag + kIbmPointsPerBlock - 1) / kIbmPointsPerBlock)),
+      gsp((uint32_t)((c->nshell + kSpreadCellsPerBlock - 1) / kSpreadCellsPerBlock));
   if (c->Q == 9)
     hipLaunchKernelGGL((k_ibm_u0<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
   else
     hipLaunchKernelGGL((k_ibm_u0<19, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
   for (int it = 0; it < c->n_iter; it++) {
-    hipLaunchKernelGGL(k_ibm_interp<C>, gl, dim3(128), 0, c->stream, a, it == 0 ? 1 : 0);
-    hipLaunchKernelGGL(k_ibm_spread<C>, gs, dim3(128), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_ibm_interp<C>, gl, dim3(256), 0, c->stream, a, it == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_ibm_spread<C>, gsp, dim3(256), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
   }
   double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
-  hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(256), 0, c->stream, a,
+  hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(1024), 0, c->stream, a,
                      c->at<int64_t>(c->L.misc + 64), c->at<int64_t>(c->L.misc + 64 + 8 * c->L.max_solids), hist);
 }
 
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a) { *a = ibm_args(c, c->t); }
 
 template <typename S>
-static void ibm_batch_t(const BatchLaunch &b, const WorkList *shell, const WorkList *lag, const WorkList *ft,
-                        int max_iter, uint32_t grid) {
+static void ibm_batch_t(const BatchLaunch &b, const WorkList *shell, const WorkList *spread, const WorkList *lag,
+                        const WorkList *ft, int max_iter, uint32_t grid) {
   using C = typename Store<S>::C;
   if (b.Q == 9)
     hipLaunchKernelGGL((k_ibm_u0_batch<9, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
   else
     hipLaunchKernelGGL((k_ibm_u0_batch<19, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
   for (int it = 0; it < max_iter; it++) {
-    hipLaunchKernelGGL(k_ibm_interp_batch<C>, dim3(grid), dim3(128), 0, b.stream, b.slots, lag, it);
-    hipLaunchKernelGGL(k_ibm_spread_batch<C>, dim3(grid), dim3(128), 0, b.stream, b.slots, shell, it);
+    hipLaunchKernelGGL(k_ibm_interp_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, lag, it);
+    hipLaunchKernelGGL(k_ibm_spread_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, spread, it);
   }
-  hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(256), 0, b.stream, b.slots, ft,
+  hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, ft,
                      b.step);
 }
 
-void launch_ibm_batch(const BatchLaunch &b, const WorkList *shell, const WorkList *lag, const WorkList *ft,
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *shell, const WorkList *spread, const WorkList *lag, const WorkList *ft,
                       int max_iter, uint32_t grid) {
-  if (b.storage == LBM_F64) ibm_batch_t<double>(b, shell, lag, ft, max_iter, grid);
-  else if (b.storage == LBM_F32_DEV) ibm_batch_t<float>(b, shell, lag, ft, max_iter, grid);
-  else ibm_batch_t<_Float16>(b, shell, lag, ft, max_iter, grid);
+  if (b.storage == LBM_F64) ibm_batch_t<double>(b, shell, spread, lag, ft, max_iter, grid);
+  else if (b.storage == LBM_F32_DEV) ibm_batch_t<float>(b, shell, spread, lag, ft, max_iter, grid);
+  else ibm_batch_t<_Float16>(b, shell, spread, lag, ft, max_iter, grid);
 }
 
 void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t) {

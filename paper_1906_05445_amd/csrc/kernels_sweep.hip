@@ -18,18 +18,12 @@ namespace lbm {
 enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
 
 
-template <int Q, int COLL, typename S, int FLAGS, int NT>
-__device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
-                                           uint32_t blk) {
-  using C = typename Store<S>::C;
+// Pull of cell n: population i arrives from x - e_i (raw stored values; the
+// conversion to the compute type happens in sweep_relax, so the loads of
+// several cells can all be in flight together).
+template <int Q, typename S>
+__device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepArgs &a, uint32_t n, S (&r)[Q]) {
   using L = Lat<Q>;
-  const uint32_t n = blk * kBlock + threadIdx.x;
-  if (n >= a.N) return;
-  uint8_t fl = 0;
-  if (FLAGS) {
-    fl = a.flags[n];
-    if (fl & F_SOLID) return;
-  }
   const uint32_t yz = fdiv(n, a.fx);
   const uint32_t x = n - yz * a.nx;
   const uint32_t z = (Q == 9) ? 0u : fdiv(yz, a.fy);
@@ -37,18 +31,26 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   const uint32_t xm = x == 0 ? a.nx - 1 : x - 1, xp = x + 1 == a.nx ? 0 : x + 1;
   const uint32_t ym = y == 0 ? a.ny - 1 : y - 1, yp = y + 1 == a.ny ? 0 : y + 1;
   const uint32_t zm = z == 0 ? a.nz - 1 : z - 1, zp = z + 1 == a.nz ? 0 : z + 1;
-
-  // pull: population i arrives from x - e_i
-  C h[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const uint32_t sx = L::ex(i) > 0 ? xm : (L::ex(i) < 0 ? xp : x);
     const uint32_t sy = L::ey(i) > 0 ? ym : (L::ey(i) < 0 ? yp : y);
     const uint32_t sz = L::ez(i) > 0 ? zm : (L::ez(i) < 0 ? zp : z);
     const uint32_t src = sx + a.nx * (sy + a.ny * sz);
-    h[i] = Store<S>::ld(A + pidx<Q>(i, src));
+    r[i] = A[pidx<Q>(i, src)];
   }
+}
 
+// Relaxation of one cell (Eq. 1 or Eq. 3 with the forcing of Sec. 2.1) and
+// the store of its post-collision values.
+template <int Q, int COLL, typename S, int FLAGS, int NT>
+__device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &a, uint32_t n, uint8_t fl,
+                                            const S (&r)[Q]) {
+  using C = typename Store<S>::C;
+  using L = Lat<Q>;
+  C h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) h[i] = (C)r[i];
   // moments of the deviation: rho = 1 + drho, j = sum h e (sum w e = 0)
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -136,13 +138,42 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
     }
   }
 
-  // one tile per block: the block writes Q contiguous runs of kTile values
+  // the block writes Q contiguous runs of kTile values per tile
   const uint64_t base = pidx<Q>(0, n);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     if (NT) Store<S>::st_nt(B + base + (uint64_t)i * kTile, h[i]);
     else Store<S>::st(B + base + (uint64_t)i * kTile, h[i]);
   }
+}
+
+// One block sweeps sweep_cpt tiles (group blk): every thread pulls its cell
+// of each tile before relaxing any, so that half-precision storage keeps as
+// many bytes in flight per wavefront as single precision.
+template <int Q, int COLL, typename S, int FLAGS, int NT>
+__device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
+                                           uint32_t blk) {
+  constexpr int CPT = sweep_cpt_of<S>();
+  uint32_t n[CPT];
+  uint8_t fl[CPT];
+  bool act[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; c++) {
+    n[c] = (blk * CPT + c) * kBlock + threadIdx.x;
+    act[c] = n[c] < a.N;
+    fl[c] = (FLAGS && act[c]) ? a.flags[n[c]] : (uint8_t)0;
+  }
+  // the loads are not predicated (a branch around them would make the
+  // compiler wait for one cell's loads before issuing the next cell's):
+  // cells past the end load cell N-1, solid nodes load and discard
+  S r[CPT][Q];
+#pragma unroll
+  for (int c = 0; c < CPT; c++) sweep_pull<Q, S>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
+#pragma unroll
+  for (int c = 0; c < CPT; c++) act[c] = act[c] && !(fl[c] & F_SOLID);  // nothing is stored for solid nodes
+#pragma unroll
+  for (int c = 0; c < CPT; c++)
+    if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT>(B, a, n[c], fl[c], r[c]);
 }
 
 template <int Q, int COLL, typename S, int FLAGS, int NT>
@@ -217,7 +248,8 @@ void launch_tick(hipStream_t s, int64_t *step) { hipLaunchKernelGGL(k_tick, dim3
 template <typename S>
 static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags, bool nt,
                            hipEvent_t e0, hipEvent_t e1) {
-  const uint32_t grid = (uint32_t)((c->N + kBlock - 1) / kBlock) + a.rblocks;
+  const uint32_t tiles = (uint32_t)((c->N + kBlock - 1) / kBlock);
+  const uint32_t grid = (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks;
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
   // the events (when given) are attached to the dispatch itself and time the kernel alone

@@ -32,7 +32,8 @@ struct LinkArgs {
   SolidLinks *sl;
   uint32_t *misc;          // [0] total links, [1] overflow flag
   void *post;              // refill: post-collision array of step t-1 -> t
-  int refill;
+  uint64_t *refill_list;   // nodes uncovered this step: (solid << 32) | cell
+  uint32_t max_refill;     // misc[3] counts them, misc[4] flags an overflow
 };
 
 struct IbbArgs {
@@ -131,7 +132,7 @@ struct BatchSlot {
 };
 
 // Status bits of a batched lattice.
-enum { BS_LINKS_OVERFLOW = 1, BS_CHUNKS_OVERFLOW = 2 };
+enum { BS_LINKS_OVERFLOW = 1, BS_CHUNKS_OVERFLOW = 2, BS_REFILL_OVERFLOW = 4 };
 
 // The units (tiles, link chunks, ...) of one batched launch: member k owns
 // units start[k] .. start[k+1]-1 and is lattice slot[k] of the batch.  Kept
@@ -223,7 +224,7 @@ void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_force_change(const BatchLaunch &b, const WorkList *wl, int64_t lag, double *out, uint32_t grid);
 void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_one, uint32_t grid);
-void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_shell, const WorkList *wl_lag, const WorkList *wl_ft,
-                      int max_iter, uint32_t grid);
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_shell, const WorkList *wl_spread,
+                      const WorkList *wl_lag, const WorkList *wl_ft, int max_iter, uint32_t grid);
 
 }  // namespace lbm

@@ -132,6 +132,14 @@ __host__ __device__ constexpr bool odd_row(int k) {
 // that are far apart, which keeps the HBM access pattern dense.
 // ----------------------------------------------------------------------------
 constexpr uint32_t kTile = 256;
+
+// Tiles swept per block (one cell of each per thread): two for half-precision
+// storage, whose loads carry half the bytes, one otherwise.
+template <typename S>
+__host__ __device__ constexpr int sweep_cpt_of() {
+  return sizeof(S) == 2 ? 2 : 1;
+}
+__host__ __device__ constexpr uint32_t sweep_cpt_storage(int storage_bytes) { return storage_bytes == 2 ? 2u : 1u; }
 template <int Q>
 __host__ __device__ inline uint64_t pidx(int i, uint32_t n) {
   return (uint64_t)(n / kTile) * (Q * kTile) + (uint64_t)i * kTile + (n % kTile);
@@ -194,9 +202,17 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t G) {
   return (b & 7u) * G8 + (b >> 3);
 }
 
+// Periodic wrap of a coordinate into [0, n).  Neighbour and box offsets stay
+// within one period, where one compare-and-add suffices; the remainder is
+// taken only outside [-n, 2n).
 __device__ inline int wrapi(int a, int n) {
-  a %= n;
-  return a < 0 ? a + n : a;
+  if (a < 0) a += n;
+  else if (a >= n) a -= n;
+  if ((unsigned)a >= (unsigned)n) {
+    a %= n;
+    if (a < 0) a += n;
+  }
+  return a;
 }
 
 // Block-wide sum of a double (blockDim.x a multiple of 64, <= 1024); fixed order.

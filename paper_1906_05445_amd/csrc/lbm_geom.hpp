@@ -24,6 +24,7 @@ __device__ inline double centre_at(const DevSolid &s, int a, int64_t t, const Bo
   if (!s.moving) return s.c0[a];
   const double L = (double)box_dim(b, a);
   double y = s.c0[a] + (double)t * s.U[a];
+  if (y >= 0.0 && y < L) return y;  // fmod(y, L) is exactly y here; skip the costly call
   y = fmod(y, L);
   if (y < 0.0) y = y + L;
   return y;

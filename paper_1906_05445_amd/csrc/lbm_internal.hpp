@@ -26,6 +26,7 @@ struct DevSolid {
   int32_t ext[3];    // box extent per axis
   int32_t box0[3];   // box origin of a fixed solid
   uint32_t box_cells;
+  FastDiv fex, fexy;  // division by ext[0] and by ext[0] * ext[1]
   double c0[3], R, U[3], W[3];
 };
 
@@ -38,9 +39,9 @@ struct SolidLinks {
 struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
       partials, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
-      lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, misc, total;
+      lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, refill, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
-  int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials;
+  int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials, max_refill;
   int32_t max_solids;
 };
 
@@ -157,7 +158,8 @@ void launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // kernels_boundary.hip
 void launch_classify(lbm_ctx *c, int64_t t, bool full);
-void launch_link_count(lbm_ctx *c, int64_t t, bool refill, const void *Bpost);
+void launch_refill(lbm_ctx *c, int64_t t, void *post);
+void launch_link_count(lbm_ctx *c, int64_t t);
 void launch_link_scan(lbm_ctx *c);
 void launch_link_emit(lbm_ctx *c, int64_t t);
 void launch_ibb(lbm_ctx *c, void *Bpost, int64_t t);

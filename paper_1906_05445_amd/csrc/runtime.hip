@@ -144,6 +144,8 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.shell_ent = take((size_t)max_lag * 64 * 4);
   l.shell_u = take((size_t)3 * l.max_shell * cs);
   l.shell_f = take((size_t)3 * l.max_shell * cs);
+  l.max_refill = std::max<int64_t>(4096, N / 16);
+  l.refill = take((size_t)l.max_refill * 8);
   l.misc = take((size_t)64 + 16 * (size_t)max_solids + 64);
   l.total = o;
   *L = l;
@@ -451,6 +453,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       cells *= (uint64_t)d.ext[a];
     }
     d.box_cells = (uint32_t)cells;
+    d.fex = make_div((uint32_t)d.ext[0]);
+    d.fexy = make_div((uint32_t)d.ext[0] * (uint32_t)d.ext[1]);
     mbc = std::max<int32_t>(mbc, (int32_t)((cells + kBlock - 1) / kBlock));
   }
   // ordinary spheres / cylinders must not overlap
@@ -497,7 +501,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   }
   launch_classify(c, c->t, true);
   if (method != LBM_IBM) {
-    launch_link_count(c, c->t, false, nullptr);
+    launch_link_count(c, c->t);
     launch_link_scan(c);
     launch_link_emit(c, c->t);
     std::vector<SolidLinks> sl((size_t)n);
@@ -746,7 +750,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
         launch_classify(c, c->t + 1, false);
-        launch_link_count(c, c->t + 1, true, B);
+        launch_refill(c, c->t + 1, B);
+        launch_link_count(c, c->t + 1);
         launch_link_scan(c);
         launch_link_emit(c, c->t + 1);
       }
@@ -761,7 +766,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (st != LBM_OK) return st;
   }
   if (ibb && c->any_moving && nsteps > 0) {
-    uint32_t misc[2];
+    uint32_t misc[5];
     std::vector<SolidLinks> sl((size_t)c->nsolid);
     HIPCALL(hipMemcpyAsync(misc, c->ws + c->L.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream));
     HIPCALL(hipMemcpyAsync(sl.data(), c->ws + c->L.solid_links, sizeof(SolidLinks) * c->nsolid,
@@ -769,6 +774,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     HIPCALL(hipStreamSynchronize(c->stream));
     c->nlinks = misc[0];
     if (misc[1]) return set_err(c, "more boundary links than max_links"), LBM_ENOMEM;
+    if (misc[4]) return set_err(c, "more uncovered nodes in one step than the refill list holds"), LBM_ENOMEM;
     for (auto &q : sl)
       if ((int32_t)q.nchunks > c->k5_chunks)
         return set_err(c, "a translating solid outgrew its link headroom"), LBM_ENOMEM;
