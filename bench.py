@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--cases", default="all",
                     help="comma list of extras: single (the other single-lattice cases), copy, batch, serving")
     ap.add_argument("--batch-steps", type=int, default=200, help="steps of the 512-lattice batch (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=30.0, help="wall time of each serving window (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="wall time of each serving window (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run the copy kernel once over this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -257,8 +257,8 @@ def main():
         print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
               file=sys.stderr, flush=True)
     if args.serve_seconds > 0 and "serving" in want:
-        extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 48.0, 32)
-        extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.25, 256, 48.0, 32)
+        extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 32.0, 16)
+        extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.1, 256, 32.0, 16)
         for k in ("serving_saturated", "serving_subsaturated"):
             sv = extras[k]
             print(f"# {k}: {sv['completed']} solves in {sv['wall_s']:.1f} s, p50 {sv['latency_p50_s']} s, "

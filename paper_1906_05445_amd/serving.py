@@ -181,7 +181,9 @@ class Server:
                         log(f"req {req.rid}: {'converged' if done else 'capped'} after {req.steps} steps, "
                             f"latency {req.latency:.3f} s")
         wall = self.clock() - t0
-        return stats(reqs, wall, self.cell_steps, in_flight=len(self.active), queued=len(adm.queue))
+        for m, req in self.active.items():
+            req.steps = m.time
+        return stats(reqs, wall, self.cell_steps, in_flight=list(self.active.values()), queued=len(adm.queue))
 
     def close(self):
         for m in list(self.active):
@@ -190,8 +192,10 @@ class Server:
         self.batch.close()
 
 
-def stats(reqs, wall, cell_steps=0, in_flight=0, queued=0):
+def stats(reqs, wall, cell_steps=0, in_flight=(), queued=0):
+    """Summary of a serving run; in_flight: the requests still running at the end."""
     done = [r for r in reqs if r.finished is not None]
+    running = list(in_flight)
     conv = [r for r in done if r.converged]
     lat = [r.latency for r in done]
     return {
@@ -201,7 +205,10 @@ def stats(reqs, wall, cell_steps=0, in_flight=0, queued=0):
         "converged": len(conv),
         "capped": sum(1 for r in done if r.capped),
         "rejected": sum(1 for r in reqs if r.rejected),
-        "in_flight_at_end": in_flight,
+        "in_flight_at_end": len(running),
+        "in_flight_mean_steps": float(np.mean([r.steps for r in running])) if running else None,
+        "in_flight_median_change": (float(np.median([r.change for r in running if r.change >= 0]))
+                                    if any(r.change >= 0 for r in running) else None),
         "queued_at_end": queued,
         "wall_s": wall,
         "solves_per_s": len(done) / wall if wall > 0 else 0.0,

@@ -56,11 +56,12 @@ def test_stats_split_queue_and_service():
         r.capped = k == 2
         r.steps = 100 * (k + 1)
         reqs.append(r)
-    s = S.stats(reqs, wall=10.0, cell_steps=1e9, in_flight=1)
+    s = S.stats(reqs, wall=10.0, cell_steps=1e9, in_flight=[reqs[3]])
     assert s["completed"] == 3 and s["converged"] == 2 and s["capped"] == 1
     assert s["solves_per_s"] == 0.3
     assert s["latency_p50_s"] == 2.0 and s["queue_p50_s"] == 0.5 and s["service_p50_s"] == 1.5
     assert s["mlups"] == 100.0
+    assert s["in_flight_at_end"] == 1 and s["in_flight_mean_steps"] == 400.0
 
 
 def test_request_trace_is_poisson_and_seeded():
