@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -189,6 +191,56 @@ def run_serving(torch, lbm, W, seconds, rate, count, pool_gb, max_slots):
     return st
 
 
+def run_precision(torch, lbm, W, steps):
+    """Per-sphere drag of the 256^3 64-sphere workload stored in FP32 and FP16, against FP64 storage on the same
+    GPU (the FP64 path matches the FP64 oracle to 1e-12)."""
+    drag = {}
+    for storage in ("F64", "F32", "F16"):
+        case = W.sphere_pack(storage=storage)
+        gpu = lbm.Lattice(case.lattice, case.collision, storage, case.shape, case.tau, g=case.g,
+                          max_solids=len(case.solids))
+        gpu.set_solids(case.solids, case.method)
+        gpu.step(steps)
+        drag[storage] = gpu.force_torque()[:, 0].copy()
+        gpu.close()
+        del gpu
+        torch.cuda.empty_cache()
+    ref = drag["F64"]
+    out = {"steps": steps, "spheres": int(ref.size), "mean_drag_f64": float(ref.mean())}
+    for storage in ("F32", "F16"):
+        rel = abs(drag[storage] - ref) / abs(ref)
+        out[storage] = {"max_rel_drag_err": float(rel.max()), "mean_rel_drag_err": float(rel.mean()),
+                        "rel_err_of_mean_drag": float(abs(drag[storage].mean() - ref.mean()) / abs(ref.mean()))}
+    return out
+
+
+def run_batch_vs_plain(torch, lbm, W, steps, count=8):
+    """Drag of lattices stepped as an FP32 batch against the same lattices stepped alone in FP64."""
+    cases = W.moving_sphere_batch(count, seed=11, edge=(32, 64))
+    fps = [lbm.Batch.footprint(c.lattice, c.collision, "F32", c.shape, c.tau, max_solids=1) for c in cases]
+    b = lbm.Batch("D3Q19", "F32", max_slots=count, pool_bytes=lbm.lbm_batch_table_bytes(count) + sum(fps) + (1 << 24))
+    members = []
+    for c in cases:
+        m = b.admit(c.collision, "F32", c.shape, c.tau, g=c.g, max_solids=1)
+        m.set_solids(c.solids, c.method)
+        members.append(m)
+    b.step(steps)
+    errs = []
+    for c, m in zip(cases, members):
+        ref = lbm.Lattice(c.lattice, c.collision, "F64", c.shape, c.tau, g=c.g, max_solids=1)
+        ref.set_solids(c.solids, c.method)
+        ref.step(steps)
+        f64 = ref.history()[:, 0, :3]
+        f32 = m.history()[:, 0, :3]
+        scale = np.abs(f64).max()
+        errs.append(float(np.abs(f32 - f64).max() / scale))
+        ref.close()
+    b.close()
+    torch.cuda.empty_cache()
+    return {"lattices": count, "steps": steps, "max_rel_force_err": max(errs), "per_lattice": errs,
+            "measure": "max over steps and components of |F_batch,FP32 - F_alone,FP64| / max |F_alone,FP64|"}
+
+
 def cpu_baseline(case, steps):
     """The FP64 oracle (single-threaded C) on a bounded sample of the value workload."""
     from oracle import Oracle
@@ -212,9 +264,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
     ap.add_argument("--cases", default="all",
-                    help="comma list of extras: single (the other single-lattice cases), copy, batch, serving")
+                    help="comma list of extras: single (the other single-lattice cases), copy, batch, precision, serving")
     ap.add_argument("--batch-steps", type=int, default=200, help="steps of the 512-lattice batch (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="wall time of each serving window (0: skip)")
+    ap.add_argument("--precision-steps", type=int, default=2000,
+                    help="steps of the FP32/FP16 vs FP64 drag comparison (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run the copy kernel once over this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -236,14 +290,16 @@ def main():
     extras = {}
     want = set()
     if not args.primary_only:
-        want = {"single", "copy", "batch", "serving"} if args.cases == "all" else set(args.cases.split(","))
+        want = ({"single", "copy", "batch", "precision", "serving"} if args.cases == "all"
+                else set(args.cases.split(",")))
     if "single" in want:
         k2 = max(K // 2, 100)
         for key, case in [("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
                           ("sphere128_f16_quadratic", W.sphere_box(storage="F16", method="QUADRATIC")),
                           ("sphere128_f32_ibm", W.sphere_box(storage="F32", method="IBM")),
                           ("pack256_f32_quadratic", W.sphere_pack(storage="F32")),
-                          ("pack256_f64_quadratic", W.sphere_pack(storage="F64"))]:
+                          ("pack256_f64_quadratic", W.sphere_pack(storage="F64")),
+                          ("pack256_f16_quadratic", W.sphere_pack(storage="F16"))]:
             k = k2 if "256" not in key else max(K // 8, 50)
             extras[key] = run_case(case, k, max(Wm // 4, 20), key, torch, lbm)
             extras[key]["steps"] = k
@@ -256,6 +312,13 @@ def main():
         bb = extras["batch512_moving_f32"]
         print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
               file=sys.stderr, flush=True)
+    if args.precision_steps > 0 and "precision" in want:
+        extras["precision_pack256_vs_f64"] = run_precision(torch, lbm, W, args.precision_steps)
+        extras["batch_f32_vs_plain_f64"] = run_batch_vs_plain(torch, lbm, W, args.precision_steps)
+        pr = extras["precision_pack256_vs_f64"]
+        print(f"# precision: FP32 max drag err {pr['F32']['max_rel_drag_err']:.2e}, FP16 "
+              f"{pr['F16']['max_rel_drag_err']:.2e}; batch FP32 vs FP64 "
+              f"{extras['batch_f32_vs_plain_f64']['max_rel_force_err']:.2e}", file=sys.stderr, flush=True)
     if args.serve_seconds > 0 and "serving" in want:
         extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 32.0, 16)
         extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.1, 256, 32.0, 16)
