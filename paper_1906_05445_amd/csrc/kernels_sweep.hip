@@ -51,14 +51,23 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   C h[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) h[i] = (C)r[i];
-  // moments of the deviation: rho = 1 + drho, j = sum h e (sum w e = 0)
-  C drho = 0, jx = 0, jy = 0, jz = 0;
+  // Directions come in opposite pairs (i, i+1), i odd.  Pair sums and
+  // differences give the moments: rho = 1 + drho, j = sum h e (sum w e = 0).
+  constexpr int NP = (Q - 1) / 2;
+  C Ps[NP], Md[NP];
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    drho += h[i];
-    if (L::ex(i)) jx += L::ex(i) > 0 ? h[i] : -h[i];
-    if (L::ey(i)) jy += L::ey(i) > 0 ? h[i] : -h[i];
-    if (L::ez(i)) jz += L::ez(i) > 0 ? h[i] : -h[i];
+  for (int k = 0; k < NP; k++) {
+    Ps[k] = h[2 * k + 1] + h[2 * k + 2];
+    Md[k] = h[2 * k + 1] - h[2 * k + 2];
+  }
+  C drho = h[0], jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int i = 2 * k + 1;
+    drho += Ps[k];
+    if (L::ex(i)) jx += L::ex(i) > 0 ? Md[k] : -Md[k];
+    if (L::ey(i)) jy += L::ey(i) > 0 ? Md[k] : -Md[k];
+    if (L::ez(i)) jz += L::ez(i) > 0 ? Md[k] : -Md[k];
   }
   const C rho = C(1) + drho;
   C Fx = 0, Fy = 0, Fz = 0;
@@ -78,36 +87,46 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   const C uu = ux * ux + uy * uy + uz * uz;
   const C uF = ux * Fx + uy * Fy + uz * Fz;
 
-  // non-equilibrium part and Guo's forcing term per direction
-  C fneq[Q], Fh[Q];
+  if (COLL == COLL_BGK || COLL == COLL_TRT) {
+    // Eq. 3 with one rate on every even and one on every odd non-conserved
+    // moment (BGK, Eq. 1: both rates 1/tau): M^-1 S M acts as sp on the part
+    // of each pair that is even under e -> -e and as sm on the odd part.
+    // With f_eq and Guo's term split the same way, per pair of direction e:
+    //   even f_eq Se = w (drho - 1.5 rho u.u + 4.5 rho (e.u)^2),  odd Ao = 3 w rho e.u,
+    //   even force FS = w (9 (e.u)(e.F) - 3 u.F),                 odd FA = 3 w e.F.
+    const C sp = COLL == COLL_BGK ? (C)a.omega : (C)a.sp;
+    const C sm = COLL == COLL_BGK ? (C)a.omega : (C)a.sm;
+    const C kp = C(1) - C(0.5) * sp, km = C(1) - C(0.5) * sm;
+    const C base = drho - C(1.5) * rho * uu;
+    const C w0 = (C)wgt<Q>(0);
+    h[0] += -sp * (h[0] - w0 * base) + kp * (w0 * (C(-3) * uF));
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
-    const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
-    const C w = (C)wgt<Q>(i);
-    const C heq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
-    fneq[i] = h[i] - heq;
-    Fh[i] = w * (C(3) * (eF - uF) + C(9) * eu * eF);
-  }
-
-  if (COLL == COLL_BGK) {
-    const C om = (C)a.omega, kf = C(1) - C(0.5) * om;
-#pragma unroll
-    for (int i = 0; i < Q; i++) h[i] += -om * fneq[i] + kf * Fh[i];
-  } else if (COLL == COLL_TRT) {
-    // Eq. 3 with one rate on every even and one on every odd moment: M^-1 S M
-    // acts as sp on the symmetric and sm on the antisymmetric part.
-    const C sp = (C)a.sp, sm = (C)a.sm, kp = C(1) - C(0.5) * sp, km = C(1) - C(0.5) * sm;
-    h[0] += -sp * fneq[0] + kp * Fh[0];
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-      const C p = C(0.5) * (fneq[i] + fneq[i + 1]), m = C(0.5) * (fneq[i] - fneq[i + 1]);
-      const C Fp = C(0.5) * (Fh[i] + Fh[i + 1]), Fm = C(0.5) * (Fh[i] - Fh[i + 1]);
-      const C dp = -sp * p + kp * Fp, dm = -sm * m + km * Fm;
+    for (int k = 0; k < NP; k++) {
+      const int i = 2 * k + 1;
+      const C w = (C)wgt<Q>(i);
+      const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+      const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
+      const C Se = w * (base + C(4.5) * rho * eu * eu);
+      const C Ao = w * (C(3) * rho * eu);
+      const C FS = w * (C(9) * eu * eF - C(3) * uF);
+      const C FA = w * (C(3) * eF);
+      const C dp = -sp * (C(0.5) * Ps[k] - Se) + kp * FS;
+      const C dm = -sm * (C(0.5) * Md[k] - Ao) + km * FA;
       h[i] += dp + dm;
       h[i + 1] += dp - dm;
     }
   } else {
+    // non-equilibrium part and Guo's forcing term per direction
+    C fneq[Q], Fh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+      const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
+      const C w = (C)wgt<Q>(i);
+      const C heq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+      fneq[i] = h[i] - heq;
+      Fh[i] = w * (C(3) * (eF - uF) + C(9) * eu * eF);
+    }
     // general diagonal S: dm_k = -s_k (m - m_eq)_k + (1 - s_k/2) (M F)_k,
     // conserved rows: density 0, momentum F; then h += M^-1 dm.
     C dmn[Q];
