@@ -82,7 +82,7 @@ def _compare(member, ref, tag):
 def test_batch_members_match_alone(lbm, storage):
     """Mixed members (translating and fixed spheres, IBB and IBM, BGK / two-rate /
     general-rate MRT, no solid), 45 steps in uneven calls with readouts between
-    them: tuning steps, then graph replays (one-step, eight-step, last-step)."""
+    them: tuning steps, then graph replays (one-step and eight-step graphs)."""
     specs = _specs()
     calls = [1, 10, 3, 17, 8, 6]
     b = lbm.Batch("D3Q19", storage, max_slots=8, pool_bytes=1 << 30)
@@ -188,4 +188,30 @@ def test_batch_rejects_mismatched_members(lbm):
     assert lbm.lbm_destroy(a.handle) == lbm.LBM_ESTATE
     b.step(3)
     assert a.time == 3 and c.time == 3
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["F16", "F64"])
+def test_batch_d2q9_members_match_alone(lbm, storage):
+    """D2Q9 members (translating and fixed cylinders, IBM circle, BGK and MRT) match their lone runs."""
+    specs = [
+        ("BGK", (61, 47, 1), 0.8, (1e-6, 0.0, 0.0),
+         [W.solid("cylinder", (30.4, 23.7, 0.0), 7.3, velocity=(0.013, -0.008, 0.0))], "LINEAR"),
+        ("MRT", (64, 64, 1), 0.7, (1e-6, 0.0, 0.0), [W.solid("cylinder", (32.4, 31.7, 0.0), 8.3)], "QUADRATIC"),
+        ("MRT", (50, 44, 1), 0.9, (2e-6, 0.0, 0.0), [W.solid("cylinder", (25.2, 21.9, 0.0), 6.1)], "IBM"),
+    ]
+    b = lbm.Batch("D2Q9", storage, max_slots=4, pool_bytes=1 << 27)
+    members = []
+    for coll, shape, tau, g, solids, method in specs:
+        m = b.admit(coll, storage, shape, tau, g=g, max_solids=1)
+        m.set_solids(solids, method, n_iter=3)
+        members.append(m)
+    for n in (7, 40, 13):
+        b.step(n)
+    for k, ((coll, shape, tau, g, solids, method), m) in enumerate(zip(specs, members)):
+        ref = lbm.Lattice("D2Q9", coll, storage, shape, tau, g=g, max_solids=1)
+        ref.set_solids(solids, method, n_iter=3)
+        ref.step(60)
+        _compare(m, ref, f"D2Q9 member {k}")
+        ref.close()
     b.close()
