@@ -266,18 +266,18 @@ lbm_status lbm_batch_info(lbm_batch *b, int32_t *members, size_t *bytes_free, si
                           int64_t *total_cells);
 
 /* Sweep launch shape chosen by the tuner: non-temporal stores (0/1), unit
- * order (0 contiguous share per block, 1 round-robin), persistent blocks
- * (0: one block per tile), and its measured time per step (us, all members).  LBM_ESTATE before the
- * tuner has finished. */
+ * order (0 contiguous share per block, 1 round-robin), persistent blocks, or
+ * 0 with tiles_per_block tiles per block (0 for persistent grids), and its
+ * measured time per step (us, all members).  LBM_ESTATE before the tuner has
+ * finished. */
 lbm_status lbm_batch_tune_info(lbm_batch *b, int32_t *nontemporal, int32_t *order, int32_t *blocks,
-                               double *sweep_us);
+                               int32_t *tiles_per_block, double *sweep_us);
 
-/* The tuner's candidates: fills up to cap entries (store policy, unit order,
- * persistent blocks with 0 meaning one block per tile, mean measured sweep
- * time per step in us or -1 before tuning) and returns the number of
- * candidates. */
+/* The tuner's candidates: fills up to cap entries (fields as in
+ * lbm_batch_tune_info, mean measured sweep time per step in us or -1 before
+ * tuning) and returns the number of candidates. */
 int32_t lbm_batch_tune_table(lbm_batch *b, int32_t cap, int32_t *nontemporal, int32_t *order, int32_t *blocks,
-                             double *sweep_us);
+                             int32_t *tiles_per_block, double *sweep_us);
 
 /* Advance nsteps steps launched one by one (not from the graph) with events
  * on the sweep dispatches; returns the mean sweep time per step (us).  For

@@ -52,12 +52,15 @@ struct Member {
   uint64_t version = 0;
 };
 
+// Sweep launch shape: store policy, unit order, and either a persistent grid
+// of `mult` blocks per compute unit or (mult 0) one block per `tpb` tiles.
 struct SweepCfg {
-  int nt, order, mult;  // store policy, unit order, persistent blocks per compute unit (0: one block per tile)
+  int nt, order, mult, tpb;
 };
 
-const SweepCfg kCands[] = {{0, 0, 4}, {0, 0, 8}, {0, 0, 16}, {0, 1, 4}, {0, 1, 8}, {0, 1, 16}, {0, 0, 0},
-                           {1, 0, 4}, {1, 0, 8}, {1, 0, 16}, {1, 1, 4}, {1, 1, 8}, {1, 1, 16}, {1, 0, 0}};
+const SweepCfg kCands[] = {{0, 0, 4, 0},  {0, 0, 8, 0},  {0, 0, 16, 0}, {0, 1, 4, 0},  {0, 1, 8, 0},  {0, 1, 16, 0},
+                           {0, 0, 0, 1},  {0, 0, 0, 2},  {0, 0, 0, 4},  {1, 0, 4, 0},  {1, 0, 8, 0},  {1, 0, 16, 0},
+                           {1, 1, 4, 0},  {1, 1, 8, 0},  {1, 1, 16, 0}, {1, 0, 0, 1},  {1, 0, 0, 2},  {1, 0, 0, 4}};
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -304,7 +307,8 @@ void enqueue_step(lbm_batch *b, const SweepCfg &cfg, hipEvent_t e0, hipEvent_t e
   for (int k = 0; k < 3; k++)
     if (b->coll_mask & (1u << k))
       launch_sweep_batch(bl, b->wl(WL_SWEEP + k), k, cfg.nt, cfg.order,
-                         cfg.mult ? grid_of(b, cfg.mult) : std::max<uint32_t>(1, b->totals[WL_SWEEP + k]),
+                         cfg.mult ? grid_of(b, cfg.mult)
+                                  : std::max<uint32_t>(1, (b->totals[WL_SWEEP + k] + cfg.tpb - 1) / cfg.tpb),
                          k == first ? e0 : nullptr, k == lastc ? e1 : nullptr);
   if (b->any_ibb) {
     launch_ibb_batch(bl, b->wl(WL_IBB), grid_of(b, 32));
@@ -609,25 +613,27 @@ lbm_status lbm_batch_info(lbm_batch *b, int32_t *members, size_t *bytes_free, si
 }
 
 lbm_status lbm_batch_tune_info(lbm_batch *b, int32_t *nontemporal, int32_t *order, int32_t *blocks,
-                               double *sweep_us) {
+                               int32_t *tiles_per_block, double *sweep_us) {
   if (!b) return LBM_EINVAL;
   if (b->chosen < 0) return berr(b, LBM_ESTATE, "the sweep is not tuned yet");
   const SweepCfg &c = kCands[b->chosen];
   if (nontemporal) *nontemporal = c.nt;
   if (order) *order = c.order;
   if (blocks) *blocks = c.mult ? (int32_t)grid_of(b, c.mult) : 0;
+  if (tiles_per_block) *tiles_per_block = c.tpb;
   if (sweep_us) *sweep_us = b->chosen_us;
   return LBM_OK;
 }
 
 int32_t lbm_batch_tune_table(lbm_batch *b, int32_t cap, int32_t *nontemporal, int32_t *order, int32_t *blocks,
-                             double *sweep_us) {
+                             int32_t *tiles_per_block, double *sweep_us) {
   if (!b) return 0;
   const int n = std::min<int32_t>(cap, kNumCands);
   for (int k = 0; k < n; k++) {
     if (nontemporal) nontemporal[k] = kCands[k].nt;
     if (order) order[k] = kCands[k].order;
     if (blocks) blocks[k] = kCands[k].mult ? (int32_t)grid_of(b, kCands[k].mult) : 0;
+    if (tiles_per_block) tiles_per_block[k] = kCands[k].tpb;
     if (sweep_us) sweep_us[k] = b->chosen >= 0 ? b->cand_us[k] : -1.0;
   }
   return kNumCands;

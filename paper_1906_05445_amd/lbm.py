@@ -106,10 +106,11 @@ _sig("lbm_batch_sync", _st, [_vp])
 _sig("lbm_batch_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t),
                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i64)])
 _sig("lbm_batch_tune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                  ctypes.POINTER(ctypes.c_int32), _d])
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_time_sweep", _st, [_vp, _i64, _d])
 _sig("lbm_batch_tune_table", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _d])
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_force_change", _st, [_vp, _i64, ctypes.POINTER(_vp), _d])
 _sig("lbm_batch_stream", _vp, [_vp])
 _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
@@ -398,15 +399,15 @@ class Batch:
         return {"members": n.value, "bytes_free": fr.value, "largest_free": big.value, "cells": cells.value}
 
     def tune_info(self):
-        nt, order, blocks = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        nt, order, blocks, tpb = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         us = ctypes.c_double(0.0)
         st = _lib.lbm_batch_tune_info(self.handle, ctypes.byref(nt), ctypes.byref(order), ctypes.byref(blocks),
-                                      ctypes.byref(us))
+                                      ctypes.byref(tpb), ctypes.byref(us))
         if st == LBM_ESTATE:
             return None
         self._check(st)
         return {"nontemporal_stores": nt.value, "order": order.value, "blocks": blocks.value,
-                "sweep_us": us.value}
+                "tiles_per_block": tpb.value, "sweep_us": us.value}
 
     def force_change(self, lag=100):
         """{Member: relative force change over `lag` steps} (-1: not available yet)."""
@@ -425,14 +426,15 @@ class Batch:
 
     def tune_table(self):
         """Every sweep candidate of the tuner with its measured time (us; -1 before tuning)."""
-        n = _lib.lbm_batch_tune_table(self.handle, 0, None, None, None, None)
+        n = _lib.lbm_batch_tune_table(self.handle, 0, None, None, None, None, None)
         nt = (ctypes.c_int32 * n)()
         order = (ctypes.c_int32 * n)()
         blocks = (ctypes.c_int32 * n)()
+        tpb = (ctypes.c_int32 * n)()
         us = np.zeros(n)
-        _lib.lbm_batch_tune_table(self.handle, n, nt, order, blocks, _ptr(us))
-        return [{"nontemporal_stores": nt[k], "order": order[k], "blocks": blocks[k], "sweep_us": float(us[k])}
-                for k in range(n)]
+        _lib.lbm_batch_tune_table(self.handle, n, nt, order, blocks, tpb, _ptr(us))
+        return [{"nontemporal_stores": nt[k], "order": order[k], "blocks": blocks[k], "tiles_per_block": tpb[k],
+                 "sweep_us": float(us[k])} for k in range(n)]
 
     def time_sweep(self, n):
         us = ctypes.c_double(0.0)
