@@ -216,7 +216,10 @@ class _Context:
         self._check(_lib.lbm_force_torque(self.handle, _ptr(F), _ptr(T)))
         return np.concatenate([F, T], axis=1)[: self.nsolid]
 
-    def history(self, first=0, count=None):
+    def history(self, first=None, count=None):
+        """Per-step force/torque [count][nsolid][6]; by default every step still in the ring."""
+        if first is None:
+            first = max(0, self.time - int(_lib.lbm_history_capacity()))
         if count is None:
             count = self.time - first
         out = np.zeros((max(count, 1), max(self.nsolid, 1), 6))
