@@ -264,7 +264,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
     ap.add_argument("--cases", default="all",
                     help="comma list of extras: single (the other single-lattice cases), copy, batch, precision, serving")
