@@ -158,30 +158,6 @@ __device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
   }
 }
 
-// Force -sum F_l dV_l and torque -sum (X_l - Y) x F_l dV_l on each solid.
-__device__ inline void ibm_ft_body(const IbmArgs &a, const int64_t *start, const int64_t *count, double *hist, int s) {
-  __shared__ double lds[16];
-  const DevSolid &sd = a.solids[s];
-  double c[3];
-  solid_centre(sd, a.t, a.b, c);
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t l = start[s] + threadIdx.x; l < start[s] + count[s]; l += blockDim.x) {
-    double r[3], F[3];
-    lever_arm(sd, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
-    for (int k = 0; k < 3; k++) F[k] = -a.Fsum[l * 3 + k] * a.dV[l];
-    acc[0] += F[0];
-    acc[1] += F[1];
-    acc[2] += F[2];
-    acc[3] += r[1] * F[2] - r[2] * F[1];
-    acc[4] += r[2] * F[0] - r[0] * F[2];
-    acc[5] += r[0] * F[1] - r[1] * F[0];
-  }
-  for (int k = 0; k < 6; k++) {
-    const double tot = block_sum(acc[k], lds);
-    if (threadIdx.x == 0) hist[(uint64_t)s * 6 + k] = tot;
-  }
-}
-
 template <int Q, typename S>
 __global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
   ibm_u0_body<Q, S>(A, a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
@@ -194,9 +170,7 @@ template <typename C>
 __global__ __launch_bounds__(256) void k_ibm_spread(IbmArgs a, int last) {
   ibm_spread_body<C>(a, last, (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
 }
-__global__ __launch_bounds__(1024) void k_ibm_ft(IbmArgs a, const int64_t *start, const int64_t *count, double *hist) {
-  ibm_ft_body(a, start, count, hist, blockIdx.x);
-}
+__global__ __launch_bounds__(kBlock) void k_ibm_ft(IbmFtArgs f) { ibm_ft_body(f, blockIdx.x); }
 
 // Batched forms over the IBM members of a batch (state P[cur0 ^ (k & 1)] at
 // t = t0 + k); a member takes part in forcing iteration `it` while
@@ -235,15 +209,15 @@ __global__ __launch_bounds__(256) void k_ibm_spread_batch(const BatchSlot *__res
     }
   });
 }
-__global__ __launch_bounds__(1024) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
+__global__ __launch_bounds__(kBlock) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
                                                       const WorkList *__restrict__ wl,
                                                       const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    IbmArgs a = SLOT(m, im);
-    a.t = SLOT(m, t0) + k;
-    double *hist = SLOT(m, hist) + (uint64_t)(a.t % kHistCap) * (uint64_t)SLOT(m, max_solids) * 6;
-    ibm_ft_body(a, SLOT(m, lag_start), SLOT(m, lag_count), hist, (int)u);
+    const int64_t t = SLOT(m, t0) + k;
+    const IbmFtArgs f = ibm_ft_args(SLOT(m, im), t, SLOT(m, lag_start), SLOT(m, lag_count),
+                                    SLOT(m, hist) + (uint64_t)(t % kHistCap) * (uint64_t)SLOT(m, max_solids) * 6);
+    ibm_ft_body(f, (int)u);
   });
 }
 
@@ -286,7 +260,7 @@ void launch_ibm_setup(lbm_ctx *c) {
 }
 
 template <typename S>
-static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t) {
+static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
   using C = typename Store<S>::C;
   IbmArgs a = ibm_args(c, t);
   const dim3 gs((uint32_t)((c->nshell + 127) / 128)),
@@ -300,9 +274,8 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t) {
     hipLaunchKernelGGL(k_ibm_interp<C>, gl, dim3(256), 0, c->stream, a, it == 0 ? 1 : 0);
     hipLaunchKernelGGL(k_ibm_spread<C>, gsp, dim3(256), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
   }
-  double *hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
-  hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(1024), 0, c->stream, a,
-                     c->at<int64_t>(c->L.misc + 64), c->at<int64_t>(c->L.misc + 64 + 8 * c->L.max_solids), hist);
+  if (with_ft)
+    hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t));
 }
 
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a) { *a = ibm_args(c, c->t); }
@@ -319,7 +292,7 @@ static void ibm_batch_t(const BatchLaunch &b, const WorkList *shell, const WorkL
     hipLaunchKernelGGL(k_ibm_interp_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, lag, it);
     hipLaunchKernelGGL(k_ibm_spread_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, spread, it);
   }
-  hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, ft,
+  hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(kBlock), 0, b.stream, b.slots, ft,
                      b.step);
 }
 
@@ -330,11 +303,17 @@ void launch_ibm_batch(const BatchLaunch &b, const WorkList *shell, const WorkLis
   else ibm_batch_t<_Float16>(b, shell, spread, lag, ft, max_iter, grid);
 }
 
-void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t) {
+IbmFtArgs ibm_ft_args_of(lbm_ctx *c, int64_t t) {
+  return ibm_ft_args(ibm_args(c, t), t, c->at<int64_t>(c->L.misc + 64),
+                     c->at<int64_t>(c->L.misc + 64 + 8 * c->L.max_solids),
+                     c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6);
+}
+
+void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
   if (c->nlag <= 0 || c->n_iter <= 0) return;
-  if (c->p.storage == LBM_F64) ibm_step_t<double>(c, A, t);
-  else if (c->p.storage == LBM_F32_DEV) ibm_step_t<float>(c, A, t);
-  else ibm_step_t<_Float16>(c, A, t);
+  if (c->p.storage == LBM_F64) ibm_step_t<double>(c, A, t, with_ft);
+  else if (c->p.storage == LBM_F32_DEV) ibm_step_t<float>(c, A, t, with_ft);
+  else ibm_step_t<_Float16>(c, A, t, with_ft);
 }
 
 }  // namespace lbm

@@ -197,11 +197,17 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
 
 template <int Q, int COLL, typename S, int FLAGS, int NT>
 __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
-  if (blockIdx.x < a.rblocks) {  // dispatched first, finished long before the sweep's tail
+  // leading blocks, dispatched first and finished long before the sweep's tail:
+  // the bounce-back force of the previous step, or the IBM force of this one
+  if (blockIdx.x < a.rblocks) {
     ft_reduce_waves(a.ft, blockIdx.x);
     return;
   }
-  sweep_body<Q, COLL, S, FLAGS, NT>(A, B, a, blockIdx.x - a.rblocks);
+  if (blockIdx.x < a.rblocks + a.iblocks) {
+    ibm_ft_body(a.ift, (int)(blockIdx.x - a.rblocks));
+    return;
+  }
+  sweep_body<Q, COLL, S, FLAGS, NT>(A, B, a, blockIdx.x - a.rblocks - a.iblocks);
 }
 
 // Batched sweep: the tiles of every lattice of a work list in one persistent
@@ -268,7 +274,7 @@ template <typename S>
 static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags, bool nt,
                            hipEvent_t e0, hipEvent_t e1) {
   const uint32_t tiles = (uint32_t)((c->N + kBlock - 1) / kBlock);
-  const uint32_t grid = (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks;
+  const uint32_t grid = (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks + a.iblocks;
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
   // the events (when given) are attached to the dispatch itself and time the kernel alone
@@ -359,12 +365,17 @@ int collision_kind(const lbm_ctx *c, double *sp, double *sm) {
 
 void fill_sweep_args(lbm_ctx *c, SweepArgs *a) { make_sweep_args(c, *a); }
 
-void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t) {
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t,
+                  int64_t ibm_t) {
   SweepArgs a;
   const int coll = make_sweep_args(c, a);
   if (reduce_t >= 0 && c->k5_chunks > 0) {
     a.ft = ft_reduce_args(c, reduce_t);
     a.rblocks = (uint32_t)((c->nsolid + 3) / 4);
+  }
+  if (ibm_t >= 0) {
+    a.ift = ibm_ft_args_of(c, ibm_t);
+    a.iblocks = (uint32_t)c->nsolid;
   }
   const bool flags = c->nsolid > 0;
   const bool ntb = nt != 0;

@@ -46,6 +46,16 @@ struct IbbArgs {
   int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC
 };
 
+// Per-solid IBM force and torque of one step (Sec. 3.1, App. B).
+struct IbmFtArgs {
+  Box3 b;
+  const DevSolid *solids;
+  const double *X, *dV, *Fsum;
+  const int64_t *start, *count;  // points of each solid
+  double *hist;                  // history slot of the step
+  int64_t t;
+};
+
 struct SweepArgs {
   uint32_t N, nx, ny, nz;
   FastDiv fx, fy;
@@ -59,6 +69,8 @@ struct SweepArgs {
   double sB[kMaxQ];      //              (1 - s_k/2) / |M_k|^2
   uint32_t rblocks;      // leading blocks that reduce the previous step's force partials
   FtReduceArgs ft;
+  uint32_t iblocks;      // next blocks: IBM force/torque of this step, one per solid
+  IbmFtArgs ift;
 };
 
 struct IbmArgs {
@@ -83,6 +95,48 @@ struct IbmArgs {
   double g[3];
   int64_t t;
 };
+
+__device__ __host__ inline IbmFtArgs ibm_ft_args(const IbmArgs &a, int64_t t, const int64_t *start,
+                                                 const int64_t *count, double *hist) {
+  IbmFtArgs f;
+  f.b = a.b;
+  f.solids = a.solids;
+  f.X = a.X;
+  f.dV = a.dV;
+  f.Fsum = a.Fsum;
+  f.start = start;
+  f.count = count;
+  f.hist = hist;
+  f.t = t;
+  return f;
+}
+
+// Force -sum F_l dV_l and torque -sum (X_l - Y) x F_l dV_l on solid s; one
+// block of kBlock threads (every caller uses that size, so the summation
+// order, and the result, is the same in the sweep launch and the batched
+// kernel).
+__device__ inline void ibm_ft_body(const IbmFtArgs &a, int s) {
+  __shared__ double lds[16];
+  const DevSolid &sd = a.solids[s];
+  double c[3];
+  solid_centre(sd, a.t, a.b, c);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t l = a.start[s] + threadIdx.x; l < a.start[s] + a.count[s]; l += blockDim.x) {
+    double r[3], F[3];
+    lever_arm(sd, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
+    for (int k = 0; k < 3; k++) F[k] = -a.Fsum[l * 3 + k] * a.dV[l];
+    acc[0] += F[0];
+    acc[1] += F[1];
+    acc[2] += F[2];
+    acc[3] += r[1] * F[2] - r[2] * F[1];
+    acc[4] += r[2] * F[0] - r[0] * F[2];
+    acc[5] += r[0] * F[1] - r[1] * F[0];
+  }
+  for (int k = 0; k < 6; k++) {
+    const double tot = block_sum(acc[k], lds);
+    if (threadIdx.x == 0) a.hist[(uint64_t)s * 6 + k] = tot;
+  }
+}
 
 // Cell indexing of the per-cell helper kernels.
 struct CellArgs {
@@ -215,6 +269,7 @@ void fill_macro_args(lbm_ctx *c, MacroArgs *m, int mode);
 void fill_ibb_args(lbm_ctx *c, IbbArgs *a);
 void fill_link_args(lbm_ctx *c, LinkArgs *a);
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a);
+IbmFtArgs ibm_ft_args_of(lbm_ctx *c, int64_t t);
 
 // batched launches (grid = persistent blocks)
 void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,

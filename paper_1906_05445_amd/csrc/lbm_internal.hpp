@@ -146,9 +146,10 @@ int collision_kind(const lbm_ctx *c, double *sp = nullptr, double *sm = nullptr)
 lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 
 // kernels_sweep.hip
-// reduce_t >= 0: the launch also reduces the force partials of step reduce_t
+// reduce_t >= 0: the launch also reduces the bounce-back force partials of step reduce_t;
+// ibm_t >= 0: it also sums the IBM force/torque of step ibm_t (forcing already done)
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                  int64_t reduce_t = -1);
+                  int64_t reduce_t = -1, int64_t ibm_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
@@ -168,6 +169,6 @@ void launch_ft_reduce(lbm_ctx *c, int64_t t);
 
 // kernels_ibm.hip
 void launch_ibm_setup(lbm_ctx *c);
-void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t);
+void launch_ibm_step(lbm_ctx *c, const void *A, int64_t t, bool with_ft);
 
 }  // namespace lbm

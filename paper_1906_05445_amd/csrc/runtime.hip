@@ -733,7 +733,9 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
-    if (c->method == LBM_IBM && c->nsolid > 0) launch_ibm_step(c, A, c->t);
+    // IBM: forcing iterations now; the solid force of this step is summed in the sweep launch
+    const bool ibm = c->method == LBM_IBM && c->nsolid > 0 && c->nlag > 0 && c->n_iter > 0;
+    if (ibm) launch_ibm_step(c, A, c->t, false);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const int policy = tune_policy(c, &e0, &e1);
     if (!e0 && c->profiling) {
@@ -744,7 +746,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     // the forces of the previous step of this call are reduced inside this sweep
     // launch (translating solids rebuild the link table first, so they reduce at once)
     const bool fused_reduce = ibb && k > 0 && !c->any_moving;
-    launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1);
+    launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm ? c->t : -1);
     if (ibb) {
       launch_ibb(c, B, c->t);
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
