@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "lbm_args.hpp"
+#include "lbm_ibb.hpp"
 
 namespace lbm {
 
@@ -369,7 +370,7 @@ __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
       const uint32_t ok1 = (a.flags[id_of(lx + ex, ly + ey, lz + ez, a.g)] & F_SOLID) ? 0u : 1u;
       const uint32_t ok2 = (a.flags[id_of(lx + 2 * ex, ly + 2 * ey, lz + 2 * ez, a.g)] & F_SOLID) ? 0u : 1u;
       a.link_cell[pos] = cell;
-      a.link_meta[pos] = (uint32_t)i | (ok1 << 5) | (ok2 << 6);
+      a.link_meta[pos] = (uint32_t)i | (ok1 << 5) | (ok2 << 6) | ((uint32_t)s << 8);
       a.link_q[pos] = link_fraction(sd, c, lx, ly, lz, ex, ey, ez, a.g.b);
     }
     __syncthreads();
@@ -384,41 +385,10 @@ __global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
 // interpolated bounce-back + momentum exchange (one thread per link)
 // ----------------------------------------------------------------------------
 
-// Unknown deviation h_i(x_f, t+1) of one link.  hb_*: post-collision h_ibar at
-// x_f, x_ff, x_fff; hs_*: post-collision h_i at x_f, x_ff (= h_i at x_ff,
-// x_fff after streaming).  B: wall term 2 rho0 w_i e_i.u_w / c_s^2.  The
-// coefficients of every scheme sum to one, so the formula holds for the
-// deviations as written for f.
-template <typename C>
-__device__ inline C ibb_value(int method, double q, bool ffok, bool fffok, C hb_f, C hb_ff, C hb_fff, C hs_f,
-                              C hs_ff, C B) {
-  if (method == LBM_IBB_QUADRATIC && ffok && fffok) {
-    if (q < 0.5) {  // Eq. 11a
-      const C c1 = (C)(q * (2.0 * q + 1.0)), c2 = (C)((1.0 + 2.0 * q) * (1.0 - 2.0 * q)),
-              c3 = (C)(q * (1.0 - 2.0 * q));
-      return c1 * hb_f + c2 * hb_ff - c3 * hb_fff + B;
-    }
-    // Eq. 11b
-    const C c1 = (C)(1.0 / (q * (2.0 * q + 1.0))), c2 = (C)((2.0 * q - 1.0) / q),
-            c3 = (C)((2.0 * q - 1.0) / (1.0 + 2.0 * q));
-    return c1 * (hb_f + B) + c2 * hs_f - c3 * hs_ff;
-  }
-  if (method == LBM_IBB_QUADRATIC || method == LBM_IBB_LINEAR) {
-    if (q < 0.5) {
-      if (ffok) return (C)(2.0 * q) * hb_f + (C)(1.0 - 2.0 * q) * hb_ff + B;
-      return hb_f + B;
-    }
-    return (hb_f + B) / (C)(2.0 * q) + (C)((2.0 * q - 1.0) / (2.0 * q)) * hs_f;
-  }
-  return hb_f + B;  // Eq. 10
-}
-
 // One wavefront per chunk of kLinkChunk links of one solid; each wave writes
 // the chunk's force/torque partial (summed per solid in chunk order later).
 template <int Q, typename S>
 __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, uint32_t bx, int s) {
-  using C = typename Store<S>::C;
-  using L = Lat<Q>;
   const SolidLinks sl = a.sl[s];
   const int lane = threadIdx.x;
   const bool active = bx < sl.nchunks && (uint64_t)sl.chunk_base + bx < a.max_partials;
@@ -427,6 +397,7 @@ __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, 
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     // capacity overflow (reported by the host after the step) must not read out of bounds
     if (li < sl.count && (uint64_t)sl.start + li < a.max_links) {
+      using C = typename Store<S>::C;
       const uint64_t l = (uint64_t)sl.start + li;
       const uint32_t n = a.link_cell[l], meta = a.link_meta[l];
       const double q = a.link_q[l];
@@ -434,46 +405,19 @@ __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, 
       const bool ffok = (meta >> 5) & 1u, fffok = (meta >> 6) & 1u;
       int x, y, z;
       xyz_of(n, a.g, x, y, z);
-      int ex = 0, ey = 0, ez = 0;
-      double w = 0.0;
-#pragma unroll
-      for (int k = 1; k < Q; k++)
-        if (k == i) {
-          ex = L::ex(k);
-          ey = L::ey(k);
-          ez = L::ez(k);
-          w = wgt<Q>(k);
-        }
       const DevSolid sd = load_uniform(&a.g.solids[s]);
-      double c[3], r[3], uw[3];
+      double c[3];
       solid_centre(sd, t, a.g.b, c);
-      lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, a.g.b, r);
-      wall_vel(sd, r, uw);
-      const double Bw = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
-      const uint32_t nff = id_of(x + ex, y + ey, z + ez, a.g);
-      const uint32_t nfff = id_of(x + 2 * ex, y + 2 * ey, z + 2 * ez, a.g);
-      const uint32_t nb = id_of(x - ex, y - ey, z - ez, a.g);
+      const LinkGeo g = link_geo<Q>(i, q, sd, c, x, y, z, a.g.b);
+      const LinkCoef<C> k = link_coef<C>(a.method, q, ffok, fffok);
       const C hb_f = Store<S>::ld(P + pidx<Q>(ib, n));
-      const C hb_ff = ffok ? Store<S>::ld(P + pidx<Q>(ib, nff)) : C(0);
-      const C hb_fff = fffok ? Store<S>::ld(P + pidx<Q>(ib, nfff)) : C(0);
+      const C hb_ff = ffok ? Store<S>::ld(P + pidx<Q>(ib, g.nff)) : C(0);
+      const C hb_fff = fffok ? Store<S>::ld(P + pidx<Q>(ib, g.nfff)) : C(0);
       const C hs_f = Store<S>::ld(P + pidx<Q>(i, n));
-      const C hs_ff = ffok ? Store<S>::ld(P + pidx<Q>(i, nff)) : C(0);
-      const C v = ibb_value<C>(a.method, q, ffok, fffok, hb_f, hb_ff, hb_fff, hs_f, hs_ff, (C)Bw);
-      S *dst = P + pidx<Q>(i, nb);
-      Store<S>::st(dst, v);
-      // Eq. 17 in FP64 on the stored values.  With f = w + h the rest-state part
-      // w (e_ibar - u_w) - w (e_i - u_w) is -2 w e_i (u_w cancels).
-      const double hin = (double)Store<S>::ld(dst);
-      const double hout = (double)hb_f;
-      const double e[3] = {(double)ex, (double)ey, (double)ez};
-      double dF[3];
-      for (int k = 0; k < 3; k++) dF[k] = hout * (-e[k] - uw[k]) - hin * (e[k] - uw[k]) - 2.0 * w * e[k];
-      acc[0] = dF[0];
-      acc[1] = dF[1];
-      acc[2] = dF[2];
-      acc[3] = r[1] * dF[2] - r[2] * dF[1];
-      acc[4] = r[2] * dF[0] - r[0] * dF[2];
-      acc[5] = r[0] * dF[1] - r[1] * dF[0];
+      const C hs_ff = ffok ? Store<S>::ld(P + pidx<Q>(i, g.nff)) : C(0);
+      const S v = (S)link_value<C>(k, (C)g.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff);
+      P[pidx<Q>(i, g.nb)] = v;
+      link_ft((double)(C)v, (double)hb_f, g.a, g.b, g.d, g.r, acc);
     }
     for (int k = 0; k < 6; k++) {
       const double tot = wave_sum(acc[k]);
@@ -491,6 +435,93 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
 // lbm_step call; earlier steps are reduced inside the next sweep launch).
 __global__ __launch_bounds__(256) void k_ft_reduce(FtReduceArgs r) {
   ft_reduce_waves(r, blockIdx.x);
+}
+
+// Chunk partials from per-link force terms (the sweep's bounce-back of fixed
+// solids); 256 threads, one chunk unit per wavefront.
+__global__ __launch_bounds__(256) void k_chunk_sum(ChunkSumArgs a) { chunk_sum_waves(a, blockIdx.x); }
+
+// Link lists of fixed solids by sweep segment (64 cells): count the links of
+// every segment (and flag their fluid nodes F_LINK), give each segment with
+// links a range of the cell list, fill the ranges with link indices.  The
+// order inside a range does not matter: every link writes its own direction
+// and its own slots.
+__global__ __launch_bounds__(64) void k_seg_link_count(LinkArgs a, SegLink *seg) {
+  const SolidLinks sl = a.sl[blockIdx.y];
+  const uint32_t li = blockIdx.x * 64 + threadIdx.x;
+  if (li >= sl.count || (uint64_t)sl.start + li >= a.max_links) return;
+  const uint32_t n = a.link_cell[(uint64_t)sl.start + li];
+  atomicAdd(&seg[n >> 6].count, 1u);
+  a.flags[n] = (uint8_t)(a.flags[n] | F_LINK);  // every writer sets the same bit
+}
+__global__ __launch_bounds__(256) void k_seg_link_alloc(SegLink *seg, uint32_t nseg, uint32_t *cursor) {
+  const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t v = s < nseg ? seg[s].count : 0u;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  const uint32_t tot = __shfl(inc, 63, 64);
+  uint32_t base = 0;
+  if (lane == 63 && tot) base = atomicAdd(cursor, tot);
+  base = __shfl(base, 63, 64);
+  if (v) seg[s] = SegLink{base + inc - v, 0u};
+}
+__global__ __launch_bounds__(64) void k_seg_link_fill(LinkArgs a, SegLink *seg, uint32_t *cell_list) {
+  const SolidLinks sl = a.sl[blockIdx.y];
+  const uint32_t li = blockIdx.x * 64 + threadIdx.x;
+  if (li >= sl.count || (uint64_t)sl.start + li >= a.max_links) return;
+  const uint64_t l = (uint64_t)sl.start + li;
+  SegLink *g = &seg[a.link_cell[l] >> 6];
+  const uint64_t pos = (uint64_t)g->first + atomicAdd(&g->count, 1u);
+  if (pos < a.max_links) cell_list[pos] = (uint32_t)l;
+}
+
+// Link table of fixed solids for the sweep, one thread per cell-list entry
+// (sweep-segment order): the link's cells, formula and coefficients
+// (LinkRec at the entry) and the FP64 constants of Eq. 17 ([12][stride]: a,
+// b, d, r at the link index), from the same functions the bounce-back kernel
+// evaluates each step.  Bits 8.. of a link's meta word hold its solid.
+template <int Q, typename S>
+__global__ __launch_bounds__(64) void k_link_table(LinkArgs a, const uint32_t *cell_list, uint32_t nlinks, int method,
+                                                   void *rec_, double *fc, uint64_t stride) {
+  using C = typename Store<S>::C;
+  const uint32_t pos = blockIdx.x * 64 + threadIdx.x;
+  if (pos >= nlinks) return;
+  const uint32_t l = cell_list[pos];
+  if ((uint64_t)l >= stride || (uint64_t)l >= a.max_links) return;
+  const uint32_t n = a.link_cell[l], meta = a.link_meta[l];
+  const double q = a.link_q[l];
+  const int i = (int)(meta & 31u);
+  const int s = (int)(meta >> 8);
+  int x, y, z;
+  xyz_of(n, a.g, x, y, z);
+  const DevSolid sd = a.g.solids[s];
+  double c[3];
+  solid_centre(sd, a.g.t, a.g.b, c);
+  const LinkGeo g = link_geo<Q>(i, q, sd, c, x, y, z, a.g.b);
+  const LinkCoef<C> k = link_coef<C>(method, q, (meta >> 5) & 1u, (meta >> 6) & 1u);
+  LinkRec<C> r{};
+  r.n = n;
+  r.nb = g.nb;
+  r.nff = g.nff;
+  r.nfff = g.nfff;
+  r.kind_dir = (uint32_t)k.kind | ((uint32_t)i << 8);
+  r.l = l;
+  r.k1 = k.k1;
+  r.k2 = k.k2;
+  r.k3 = k.k3;
+  r.B = (C)g.B;
+  static_cast<LinkRec<C> *>(rec_)[pos] = r;
+  for (int j = 0; j < 3; j++) {
+    fc[(uint64_t)j * stride + l] = g.a[j];
+    fc[(uint64_t)(3 + j) * stride + l] = g.b[j];
+    fc[(uint64_t)(6 + j) * stride + l] = g.d[j];
+    fc[(uint64_t)(9 + j) * stride + l] = g.r[j];
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -807,6 +838,7 @@ void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
   IbbArgs a;
   fill_ibb_args(c, &a);
   a.g.t = t;
+  a.partials = partials_of(c, t);
   const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
 #define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(64), 0, c->stream, static_cast<SS *>(P), a)
   if (c->Q == 9) {
@@ -834,7 +866,103 @@ FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t) {
 void launch_ft_reduce(lbm_ctx *c, int64_t t) {
   if (c->k5_chunks <= 0) return;
   FtReduceArgs r = ft_reduce_args(c, t);
+  r.partials = partials_of(c, t);
   hipLaunchKernelGGL(k_ft_reduce, dim3((uint32_t)((c->nsolid + 3) / 4)), dim3(256), 0, c->stream, r);
+}
+
+double *partials_of(lbm_ctx *c, int64_t t) { return c->at<double>((t & 1) ? c->L.partials2 : c->L.partials); }
+
+// Staging region while an lbm_step call applies the bounce-back in the sweep:
+// the link records, the Eq. 17 constants and, per step parity, the stored
+// incoming and outgoing values of every link ([2][stride] compute type).
+static size_t link_rec_bytes(const lbm_ctx *c) { return c->store_bytes == 8 ? sizeof(LinkRec<double>) : sizeof(LinkRec<float>); }
+static size_t link_c_bytes(const lbm_ctx *c) { return c->store_bytes == 8 ? 8 : 4; }
+static size_t link_fc_offset(const lbm_ctx *c) { return c->L.staging + c->link_stride * link_rec_bytes(c); }
+static size_t link_io_offset(const lbm_ctx *c, int64_t t) {
+  return link_fc_offset(c) + c->link_stride * 96 + (size_t)(t & 1) * 2 * c->link_stride * link_c_bytes(c);
+}
+bool link_table_fits(const lbm_ctx *c, uint64_t stride) {
+  const size_t per = link_rec_bytes(c) + 96 + 4 * link_c_bytes(c);
+  return stride * per <= (size_t)4 * c->N * 8;
+}
+
+void *link_io_of(lbm_ctx *c, int64_t t) { return c->ws + link_io_offset(c, t); }
+const void *link_rec_of(lbm_ctx *c) { return c->ws + c->L.staging; }
+
+ChunkSumArgs chunk_sum_args(lbm_ctx *c, int64_t t) {
+  ChunkSumArgs a{};
+  a.io = link_io_of(c, t);
+  a.cbytes = (int)link_c_bytes(c);
+  a.fc = c->at<double>(link_fc_offset(c));
+  a.stride = c->link_stride;
+  a.sl = c->at<SolidLinks>(c->L.solid_links);
+  a.partials = partials_of(c, t);
+  a.max_links = (uint64_t)c->L.max_links;
+  a.max_partials = (uint64_t)c->L.max_partials;
+  a.per = (uint32_t)c->k5_chunks;
+  a.nsolid = c->nsolid;
+  return a;
+}
+
+void launch_link_table(lbm_ctx *c) {
+  if (!c->cell_links) return;
+  const LinkArgs a = link_args(c, c->t);
+  const uint32_t nl = (uint32_t)c->nlinks;
+  const dim3 grid((nl + 63) / 64);
+  const uint32_t *list = c->at<uint32_t>(c->L.cell_list);
+  void *rec = c->ws + c->L.staging;
+  double *fc = c->at<double>(link_fc_offset(c));
+  const uint64_t st = c->link_stride;
+#define LBM_LT(QQ, SS) \
+  hipLaunchKernelGGL((k_link_table<QQ, SS>), grid, dim3(64), 0, c->stream, a, list, nl, c->method, rec, fc, st)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_LT(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_LT(9, float);
+    else LBM_LT(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_LT(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_LT(19, float);
+    else LBM_LT(19, _Float16);
+  }
+#undef LBM_LT
+}
+
+uint32_t chunk_sum_blocks(const lbm_ctx *c) {
+  return (uint32_t)(((int64_t)c->k5_chunks * c->nsolid + 3) / 4);
+}
+
+void launch_chunk_sum(lbm_ctx *c, int64_t t) {
+  if (c->k5_chunks <= 0) return;
+  hipLaunchKernelGGL(k_chunk_sum, dim3(chunk_sum_blocks(c)), dim3(256), 0, c->stream, chunk_sum_args(c, t));
+}
+
+// Builds the cell link table of a context whose solids are all fixed; without
+// it (translating solids, IBM, capacity limits) the bounce-back stays a kernel
+// of its own after every sweep.
+hipError_t build_cell_links(lbm_ctx *c) {
+  c->cell_links = false;
+  c->link_stride = 0;
+  if (c->method == LBM_IBM || c->any_moving || c->nsolid <= 0 || c->nlinks <= 0 || c->k5_chunks <= 0)
+    return hipSuccess;
+  const uint64_t stride = ((uint64_t)c->nlinks + 63) / 64 * 64;
+  // the per-call link table must fit the staging region
+  if (!link_table_fits(c, stride)) return hipSuccess;
+  const uint32_t nseg = (uint32_t)((c->N + 63) / 64);
+  SegLink *seg = c->at<SegLink>(c->L.seg_link);
+  uint32_t *cursor = c->at<uint32_t>(c->L.misc) + 12;
+  hipError_t e = hipMemsetAsync(seg, 0, (size_t)nseg * sizeof(SegLink), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(cursor, 0, 4, c->stream);
+  if (e != hipSuccess) return e;
+  const LinkArgs a = link_args(c, c->t);
+  const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
+  hipLaunchKernelGGL(k_seg_link_count, grid, dim3(64), 0, c->stream, a, seg);
+  hipLaunchKernelGGL(k_seg_link_alloc, dim3((nseg + 255) / 256), dim3(256), 0, c->stream, seg, nseg, cursor);
+  hipLaunchKernelGGL(k_seg_link_fill, grid, dim3(64), 0, c->stream, a, seg, c->at<uint32_t>(c->L.cell_list));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  c->link_stride = stride;
+  c->cell_links = true;
+  return hipSuccess;
 }
 
 }  // namespace lbm

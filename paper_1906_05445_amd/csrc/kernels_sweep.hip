@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 
 #include "lbm_args.hpp"
+#include "lbm_ibb.hpp"
 
 namespace lbm {
 
@@ -166,12 +167,75 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   }
 }
 
+// Boundary links of this wavefront's cells (CPT segments of 64 cells, one
+// cell of each per lane; the link records of segment c are rec[first[c] ..
+// first[c] + cnt[c] - 1]): the lanes take the links one each and evaluate them
+// on the source array; each value goes to the owning lane through LDS (tab,
+// one row of Q-1 directions per cell, and a direction mask) and replaces the
+// pulled value there (the solid-node slot it was pulled from is stale).  It is
+// also written to that slot (read by no other node), and the link's incoming
+// and outgoing values are kept for its force.  first, cnt, total are
+// wavefront-uniform.
+template <int Q, typename S, int CPT>
+__device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la, const uint32_t (&first)[CPT],
+                                            const uint32_t (&cnt)[CPT], uint32_t total, S (&h)[CPT][Q],
+                                            S (*tab)[64 * (Q - 1)], uint32_t (*mask)[64]) {
+  using C = typename Store<S>::C;
+  const int lane = threadIdx.x & 63;
+  const LinkRec<C> *rec = static_cast<const LinkRec<C> *>(la.rec);
+  C *io = static_cast<C *>(la.io);
+  S *dst = const_cast<S *>(A);
+#pragma unroll
+  for (int c = 0; c < CPT; c++) mask[c][lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint32_t b = 0; b < total; b += 64) {
+    const uint32_t j = b + lane;
+    if (j < total) {
+      int c = 0;
+      uint32_t p = first[0] + j;
+      if (CPT == 2 && j >= cnt[0]) {
+        c = 1;
+        p = first[CPT - 1] + (j - cnt[0]);
+      }
+      const LinkRec<C> r = rec[p];
+      const int kind = (int)(r.kind_dir & 255u), i = (int)(r.kind_dir >> 8), ib = opp(i);
+      const C hb_f = Store<S>::ld(A + pidx<Q>(ib, r.n));
+      const C hb_ff = (kind == LK_Q2_NEAR || kind == LK_Q1_NEAR) ? Store<S>::ld(A + pidx<Q>(ib, r.nff)) : C(0);
+      const C hb_fff = kind == LK_Q2_NEAR ? Store<S>::ld(A + pidx<Q>(ib, r.nfff)) : C(0);
+      const C hs_f = (kind == LK_Q2_FAR || kind == LK_Q1_FAR) ? Store<S>::ld(A + pidx<Q>(i, r.n)) : C(0);
+      const C hs_ff = kind == LK_Q2_FAR ? Store<S>::ld(A + pidx<Q>(i, r.nff)) : C(0);
+      const LinkCoef<C> k{kind, r.k1, r.k2, r.k3};
+      const S v = (S)link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff);
+      dst[pidx<Q>(i, r.nb)] = v;
+      io[r.l] = (C)v;
+      io[la.stride + r.l] = hb_f;
+      const uint32_t o = r.n & 63u;
+      tab[c][o * (Q - 1) + (i - 1)] = v;
+      atomicOr(&mask[c][o], 1u << i);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int c = 0; c < CPT; c++) {
+    const uint32_t m = mask[c][lane];
+    if (m) {
+#pragma unroll
+      for (int d = 1; d < Q; d++)
+        if (m & (1u << d)) h[c][d] = tab[c][lane * (Q - 1) + (d - 1)];
+    }
+  }
+}
+
 // One block sweeps sweep_cpt tiles (group blk): every thread pulls its cell
 // of each tile before relaxing any, so that half-precision storage keeps as
 // many bytes in flight per wavefront as single precision.
-template <int Q, int COLL, typename S, int FLAGS, int NT>
+template <int Q, int COLL, typename S, int FLAGS, int NT, int INL>
 __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
-                                           uint32_t blk) {
+                                           const SweepLinkArgs *la, uint32_t blk) {
   constexpr int CPT = sweep_cpt_of<S>();
   uint32_t n[CPT];
   uint8_t fl[CPT];
@@ -190,24 +254,59 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   for (int c = 0; c < CPT; c++) sweep_pull<Q, S>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
 #pragma unroll
   for (int c = 0; c < CPT; c++) act[c] = act[c] && !(fl[c] & F_SOLID);  // nothing is stored for solid nodes
+  if constexpr (INL != 0) {
+    __shared__ S tab[kBlock / 64][CPT][64 * (Q - 1)];
+    __shared__ uint32_t msk[kBlock / 64][CPT][64];
+    const int w = threadIdx.x >> 6;
+    uint32_t first[CPT], cnt[CPT], total = 0;
+#pragma unroll
+    for (int c = 0; c < CPT; c++) {
+      const uint32_t seg = __builtin_amdgcn_readfirstlane((blk * CPT + c) * (kBlock / 64) + (uint32_t)w);
+      SegLink sg{0u, 0u};
+      if (seg < la->nseg) sg = load_uniform(&la->seg_link[seg]);
+      first[c] = sg.first;
+      cnt[c] = sg.count;
+      total += sg.count;
+    }
+    if (total) sweep_links<Q, S, CPT>(A, *la, first, cnt, total, r, tab[w], msk[w]);
+  }
 #pragma unroll
   for (int c = 0; c < CPT; c++)
     if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT>(B, a, n[c], fl[c], r[c]);
 }
 
-template <int Q, int COLL, typename S, int FLAGS, int NT>
-__global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ A, S *__restrict__ B, SweepArgs a) {
+// Waves per SIMD the sweep keeps when it also evaluates boundary links: the
+// occupancy of the plain two-rate sweep, which the link branch must not
+// lower (the general-rate relaxation has no such bound).
+template <typename S, int COLL, int INL>
+constexpr int sweep_min_waves() {
+  return (!INL || COLL == COLL_MRT) ? 1 : (sizeof(S) == 4 ? 8 : (sizeof(S) == 2 ? 5 : 4));
+}
+
+template <int Q, int COLL, typename S, int FLAGS, int NT, int INL>
+__global__ __launch_bounds__(kBlock, (sweep_min_waves<S, COLL, INL>())) void k_sweep(const S *__restrict__ A,
+                                                                             S *__restrict__ B, SweepArgs a,
+                                                                             SweepLinkArgs la) {
   // leading blocks, dispatched first and finished long before the sweep's tail:
-  // the bounce-back force of the previous step, or the IBM force of this one
-  if (blockIdx.x < a.rblocks) {
-    ft_reduce_waves(a.ft, blockIdx.x);
+  // bounce-back force sums of earlier steps, or the IBM force of this one
+  uint32_t blk = blockIdx.x;
+  if (blk < a.rblocks) {
+    ft_reduce_waves(a.ft, blk);
     return;
   }
-  if (blockIdx.x < a.rblocks + a.iblocks) {
-    ibm_ft_body(a.ift, (int)(blockIdx.x - a.rblocks));
+  blk -= a.rblocks;
+  if (INL) {
+    if (blk < la.cblocks) {
+      chunk_sum_waves(la.cs, blk);
+      return;
+    }
+    blk -= la.cblocks;
+  }
+  if (blk < a.iblocks) {
+    ibm_ft_body(a.ift, (int)blk);
     return;
   }
-  sweep_body<Q, COLL, S, FLAGS, NT>(A, B, a, blockIdx.x - a.rblocks - a.iblocks);
+  sweep_body<Q, COLL, S, FLAGS, NT, INL>(A, B, a, &la, blk - a.iblocks);
 }
 
 // Batched sweep: the tiles of every lattice of a work list in one persistent
@@ -220,8 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchSlot *__restr
   batch_units(wl, order, [&](int m, uint32_t blk) {
     const int cur = SLOT(m, cur0) ^ par;
     const SweepArgs a = SLOT(m, sw);
-    sweep_body<Q, COLL, S, 1, NT>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])), a,
-                                  blk);
+    sweep_body<Q, COLL, S, 1, NT, 0>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])),
+                                     a, nullptr, blk);
   });
 }
 
@@ -271,24 +370,29 @@ __global__ void k_tick(int64_t *step) {
 void launch_tick(hipStream_t s, int64_t *step) { hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, step); }
 
 template <typename S>
-static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, int coll, bool flags, bool nt,
-                           hipEvent_t e0, hipEvent_t e1) {
+static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, const SweepLinkArgs &la, int coll,
+                           bool flags, bool nt, bool inl, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t tiles = (uint32_t)((c->N + kBlock - 1) / kBlock);
-  const uint32_t grid = (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks + a.iblocks;
+  const uint32_t grid =
+      (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks + a.iblocks + (inl ? la.cblocks : 0u);
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
   // the events (when given) are attached to the dispatch itself and time the kernel alone
-#define LBM_SWEEP(QQ, CC, FF, NN) \
-  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, As, Bs, a)
-#define LBM_SWEEP2(QQ, CC)                    \
-  do {                                        \
-    if (flags) {                              \
-      if (nt) LBM_SWEEP(QQ, CC, 1, 1);        \
-      else LBM_SWEEP(QQ, CC, 1, 0);           \
-    } else {                                  \
-      if (nt) LBM_SWEEP(QQ, CC, 0, 1);        \
-      else LBM_SWEEP(QQ, CC, 0, 0);           \
-    }                                         \
+#define LBM_SWEEP(QQ, CC, FF, NN, II)                                                                              \
+  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN, II>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, As, Bs, \
+                        a, la)
+#define LBM_SWEEP2(QQ, CC)                     \
+  do {                                         \
+    if (inl) {                                 \
+      if (nt) LBM_SWEEP(QQ, CC, 1, 1, 1);      \
+      else LBM_SWEEP(QQ, CC, 1, 0, 1);         \
+    } else if (flags) {                        \
+      if (nt) LBM_SWEEP(QQ, CC, 1, 1, 0);      \
+      else LBM_SWEEP(QQ, CC, 1, 0, 0);         \
+    } else {                                   \
+      if (nt) LBM_SWEEP(QQ, CC, 0, 1, 0);      \
+      else LBM_SWEEP(QQ, CC, 0, 0, 0);         \
+    }                                          \
   } while (0)
   if (c->Q == 9) {
     if (coll == COLL_BGK) LBM_SWEEP2(9, COLL_BGK);
@@ -366,22 +470,37 @@ int collision_kind(const lbm_ctx *c, double *sp, double *sm) {
 void fill_sweep_args(lbm_ctx *c, SweepArgs *a) { make_sweep_args(c, *a); }
 
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t,
-                  int64_t ibm_t) {
+                  int64_t ibm_t, int64_t link_t, int64_t sum_t) {
   SweepArgs a;
   const int coll = make_sweep_args(c, a);
   if (reduce_t >= 0 && c->k5_chunks > 0) {
     a.ft = ft_reduce_args(c, reduce_t);
+    a.ft.partials = partials_of(c, reduce_t);
     a.rblocks = (uint32_t)((c->nsolid + 3) / 4);
   }
   if (ibm_t >= 0) {
     a.ift = ibm_ft_args_of(c, ibm_t);
     a.iblocks = (uint32_t)c->nsolid;
   }
+  SweepLinkArgs la{};
+  const bool inl = link_t >= 0 && c->cell_links;
+  if (inl) {
+    la.seg_link = c->at<SegLink>(c->L.seg_link);
+    la.cell_list = c->at<uint32_t>(c->L.cell_list);
+    la.nseg = (uint32_t)((c->N + 63) / 64);
+    la.rec = link_rec_of(c);
+    la.io = link_io_of(c, link_t);
+    la.stride = c->link_stride;
+    if (sum_t >= 0) {
+      la.cs = chunk_sum_args(c, sum_t);
+      la.cblocks = chunk_sum_blocks(c);
+    }
+  }
   const bool flags = c->nsolid > 0;
   const bool ntb = nt != 0;
-  if (c->p.storage == LBM_F64) sweep_dispatch<double>(c, A, B, a, coll, flags, ntb, e0, e1);
-  else if (c->p.storage == LBM_F32_DEV) sweep_dispatch<float>(c, A, B, a, coll, flags, ntb, e0, e1);
-  else sweep_dispatch<_Float16>(c, A, B, a, coll, flags, ntb, e0, e1);
+  if (c->p.storage == LBM_F64) sweep_dispatch<double>(c, A, B, a, la, coll, flags, ntb, inl, e0, e1);
+  else if (c->p.storage == LBM_F32_DEV) sweep_dispatch<float>(c, A, B, a, la, coll, flags, ntb, inl, e0, e1);
+  else sweep_dispatch<_Float16>(c, A, B, a, la, coll, flags, ntb, inl, e0, e1);
 }
 
 // ----------------------------------------------------------------------------

@@ -73,6 +73,26 @@ struct SweepArgs {
   IbmFtArgs ift;
 };
 
+// Bounce-back of the previous step applied inside the sweep (fixed solids).
+// The wavefront that sweeps cells 64 s .. 64 s + 63 evaluates the links of
+// those cells (seg_link[s] into cell_list, one link per lane; LinkRec records
+// of the compute type in rec) on the source array, which holds the
+// post-collision values of the previous step.  Each value replaces the pulled
+// value of its direction in the owning lane (through LDS) and is written to
+// the solid-node slot it stands for; the link's incoming and outgoing values
+// (io, [2][stride]) are kept for Eq. 17.  Leading blocks form the chunk
+// partials of the step before.
+struct SweepLinkArgs {
+  const SegLink *seg_link;
+  const uint32_t *cell_list;
+  uint32_t nseg;
+  const void *rec;
+  void *io;
+  uint64_t stride;
+  uint32_t cblocks;
+  ChunkSumArgs cs;
+};
+
 struct IbmArgs {
   Box3 b;
   uint32_t N;

@@ -126,6 +126,7 @@ __device__ inline double link_fraction(const DevSolid &s, const double c[3], int
 // Lever from the centre (shortest image; planes: plain difference).
 __device__ inline void lever_arm(const DevSolid &s, const double c[3], double px, double py, double pz,
                                  const Box3 &b, double r[3]) {
+#pragma clang fp contract(off)
   if (s.kind == K_PLANE) {
     r[0] = px - c[0];
     r[1] = py - c[1];
@@ -139,6 +140,7 @@ __device__ inline void lever_arm(const DevSolid &s, const double c[3], double px
 
 // Rigid-body wall velocity U + Omega x r.
 __device__ inline void wall_vel(const DevSolid &s, const double r[3], double uw[3]) {
+#pragma clang fp contract(off)
   uw[0] = s.U[0] + (s.W[1] * r[2] - s.W[2] * r[1]);
   uw[1] = s.U[1] + (s.W[2] * r[0] - s.W[0] * r[2]);
   uw[2] = s.U[2] + (s.W[0] * r[1] - s.W[1] * r[0]);

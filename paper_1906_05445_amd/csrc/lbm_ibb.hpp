@@ -1,0 +1,186 @@
+// lbm_ibb.hpp -- interpolated bounce-back of one boundary link and its
+// momentum-exchange force/torque terms (Sec. 2.2: Eq. 10, Eq. 11; Eq. 17).
+//
+// A link is evaluated in three parts: its geometry (wall point, lever arm,
+// wall velocity, neighbours), the formula and coefficients that the method,
+// q and the fluid neighbours select, and the arithmetic on the populations.
+// The bounce-back kernel runs all three every step; for fixed solids the
+// first two are tabulated once per lbm_step call and the sweep runs only the
+// third.  Both routes call these same functions, compiled without
+// floating-point contraction, so they produce the same bits.
+#pragma once
+
+#include "lbm_geom.hpp"
+
+namespace lbm {
+
+// Formula of a link: Eq. 11a / 11b (quadratic, x_ff and x_fff fluid), the
+// linear interpolations for q < 1/2 (x_ff fluid) and q >= 1/2, and plain
+// bounce-back (Eq. 10; also the linear scheme for q < 1/2 without x_ff).
+enum { LK_PLAIN = 0, LK_Q2_NEAR = 1, LK_Q2_FAR = 2, LK_Q1_NEAR = 3, LK_Q1_FAR = 4 };
+
+template <typename C>
+struct LinkCoef {
+  int kind;
+  C k1, k2, k3;
+};
+
+template <typename C>
+__device__ inline LinkCoef<C> link_coef(int method, double q, bool ffok, bool fffok) {
+#pragma clang fp contract(off)
+  LinkCoef<C> k{LK_PLAIN, C(0), C(0), C(0)};
+  if (method == LBM_IBB_QUADRATIC && ffok && fffok) {
+    if (q < 0.5) {
+      k.kind = LK_Q2_NEAR;
+      k.k1 = (C)(q * (2.0 * q + 1.0));
+      k.k2 = (C)((1.0 + 2.0 * q) * (1.0 - 2.0 * q));
+      k.k3 = (C)(q * (1.0 - 2.0 * q));
+    } else {
+      k.kind = LK_Q2_FAR;
+      k.k1 = (C)(1.0 / (q * (2.0 * q + 1.0)));
+      k.k2 = (C)((2.0 * q - 1.0) / q);
+      k.k3 = (C)((2.0 * q - 1.0) / (1.0 + 2.0 * q));
+    }
+  } else if (method == LBM_IBB_QUADRATIC || method == LBM_IBB_LINEAR) {
+    if (q < 0.5) {
+      if (ffok) {
+        k.kind = LK_Q1_NEAR;
+        k.k1 = (C)(2.0 * q);
+        k.k2 = (C)(1.0 - 2.0 * q);
+      }
+    } else {
+      k.kind = LK_Q1_FAR;
+      k.k1 = (C)(2.0 * q);
+      k.k2 = (C)((2.0 * q - 1.0) / (2.0 * q));
+    }
+  }
+  return k;
+}
+
+// Unknown deviation h_i(x_f, t+1).  hb_*: post-collision h_ibar at x_f, x_ff,
+// x_fff; hs_*: post-collision h_i at x_f, x_ff (= h_i at x_ff, x_fff after
+// streaming).  B: wall term 2 rho0 w_i e_i.u_w / c_s^2.  The coefficients of
+// every scheme sum to one, so the formulas hold for the deviations as written
+// for f.  Values a formula does not use may be anything.
+template <typename C>
+__device__ inline C link_value(const LinkCoef<C> &k, C B, C hb_f, C hb_ff, C hb_fff, C hs_f, C hs_ff) {
+#pragma clang fp contract(off)
+  switch (k.kind) {
+    case LK_Q2_NEAR: return k.k1 * hb_f + k.k2 * hb_ff - k.k3 * hb_fff + B;  // Eq. 11a
+    case LK_Q2_FAR: return k.k1 * (hb_f + B) + k.k2 * hs_f - k.k3 * hs_ff;   // Eq. 11b
+    case LK_Q1_NEAR: return k.k1 * hb_f + k.k2 * hb_ff + B;
+    case LK_Q1_FAR: return (hb_f + B) / k.k1 + k.k2 * hs_f;
+    default: return hb_f + B;  // Eq. 10
+  }
+}
+
+// Geometry of link (x_f, i) of solid sd with centre c: x_f = cell (x, y, z),
+// direction i, fraction q.  Returns the wall term B (FP64) and the constants
+// of Eq. 17, dF = hout a - hin b - d with a = -e_i - u_w, b = e_i - u_w,
+// d = 2 w_i e_i (the rest-state part w (e_ibar - u_w) - w (e_i - u_w) of
+// f = w + h), and the lever arm r from the centre to the wall point; also the
+// cells x_b = x_f - e_i, x_ff, x_fff.
+struct LinkGeo {
+  double B;
+  double a[3], b[3], d[3], r[3];
+  uint32_t nb, nff, nfff;
+};
+
+template <int Q>
+__device__ inline LinkGeo link_geo(int i, double q, const DevSolid &sd, const double c[3], int x, int y, int z,
+                                   const Box3 &box) {
+#pragma clang fp contract(off)
+  using L = Lat<Q>;
+  int ex = 0, ey = 0, ez = 0;
+  double w = 0.0;
+#pragma unroll
+  for (int k = 1; k < Q; k++)
+    if (k == i) {
+      ex = L::ex(k);
+      ey = L::ey(k);
+      ez = L::ez(k);
+      w = wgt<Q>(k);
+    }
+  LinkGeo g;
+  double uw[3];
+  lever_arm(sd, c, (double)x - q * ex, (double)y - q * ey, (double)z - q * ez, box, g.r);
+  wall_vel(sd, g.r, uw);
+  g.B = 6.0 * w * (ex * uw[0] + ey * uw[1] + ez * uw[2]);
+  const double e[3] = {(double)ex, (double)ey, (double)ez};
+  for (int k = 0; k < 3; k++) {
+    g.a[k] = -e[k] - uw[k];
+    g.b[k] = e[k] - uw[k];
+    g.d[k] = 2.0 * w * e[k];
+  }
+  auto id = [&](int dx, int dy, int dz) {
+    return (uint32_t)wrapi(x + dx, box.nx) +
+           (uint32_t)box.nx * ((uint32_t)wrapi(y + dy, box.ny) + (uint32_t)box.ny * (uint32_t)wrapi(z + dz, box.nz));
+  };
+  g.nb = id(-ex, -ey, -ez);
+  g.nff = id(ex, ey, ez);
+  g.nfff = id(2 * ex, 2 * ey, 2 * ez);
+  return g;
+}
+
+// Eq. 17 force (acc 0..2) and torque about the centre (acc 3..5) of one link
+// from the stored outgoing h_ibar(x_f) and incoming h_i(x_f, t+1), in FP64.
+__device__ inline void link_ft(double hin, double hout, const double a[3], const double b[3], const double d[3],
+                               const double r[3], double acc[6]) {
+#pragma clang fp contract(off)
+  double dF[3];
+  for (int k = 0; k < 3; k++) dF[k] = hout * a[k] - hin * b[k] - d[k];
+  acc[0] = dF[0];
+  acc[1] = dF[1];
+  acc[2] = dF[2];
+  acc[3] = r[1] * dF[2] - r[2] * dF[1];
+  acc[4] = r[2] * dF[0] - r[0] * dF[2];
+  acc[5] = r[0] * dF[1] - r[1] * dF[0];
+}
+
+// Tabulated part of a link of a fixed solid, as the sweep reads it (48 bytes
+// for FP32 and FP16 storage, 64 for FP64), stored in sweep-segment order.
+template <typename C>
+struct LinkRec {
+  C k1, k2, k3, B;
+  uint32_t n, nb, nff, nfff;  // x_f, x_b, x_ff, x_fff
+  uint32_t kind_dir;          // kind | i << 8
+  uint32_t l;                 // link index (order of the force sums)
+  uint32_t pad[2];
+};
+static_assert(sizeof(LinkRec<float>) == 48 && sizeof(LinkRec<double>) == 64, "link record size");
+
+// Chunk partials from tabulated links: the same per-link terms, summed over
+// the same 64 lanes in the same order, as the bounce-back kernel forms from
+// its registers.  Block `blk` (256 threads): chunk units 4*blk .. 4*blk+3,
+// one per wavefront.
+__device__ inline void chunk_sum_waves(const ChunkSumArgs &a, uint32_t blk) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t u = blk * 4 + (threadIdx.x >> 6);
+  const uint32_t s = u / a.per, bx = u - s * a.per;
+  if ((int)s >= a.nsolid) return;
+  const SolidLinks sl = a.sl[s];
+  if (!(bx < sl.nchunks && (uint64_t)sl.chunk_base + bx < a.max_partials)) return;
+  const uint32_t li = bx * kLinkChunk + lane;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // (links are numbered below stride; the test only guards the table bounds)
+  if (li < sl.count && (uint64_t)sl.start + li < a.max_links && (uint64_t)sl.start + li < a.stride) {
+    const uint64_t l = (uint64_t)sl.start + li;
+    double hin, hout;
+    if (a.cbytes == 8) {
+      hin = static_cast<const double *>(a.io)[l];
+      hout = static_cast<const double *>(a.io)[a.stride + l];
+    } else {
+      hin = (double)static_cast<const float *>(a.io)[l];
+      hout = (double)static_cast<const float *>(a.io)[a.stride + l];
+    }
+    double k[12];
+    for (int j = 0; j < 12; j++) k[j] = a.fc[(uint64_t)j * a.stride + l];
+    link_ft(hin, hout, k, k + 3, k + 6, k + 9, acc);
+  }
+  for (int k = 0; k < 6; k++) {
+    const double tot = wave_sum(acc[k]);
+    if (lane == 0) a.partials[(uint64_t)(sl.chunk_base + bx) * 6 + k] = tot;
+  }
+}
+
+}  // namespace lbm

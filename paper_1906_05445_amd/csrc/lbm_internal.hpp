@@ -38,7 +38,7 @@ struct SolidLinks {
 // Regions carved out of the caller's workspace (byte offsets).
 struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
-      partials, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
+      partials, partials2, seg_link, cell_list, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
       lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, refill, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials, max_refill;
@@ -62,6 +62,27 @@ __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
+
+// Links of the 64 cells n = 64 s .. 64 s + 63 (one wavefront of a sweep):
+// entries first .. first + count - 1 of the cell list.
+struct SegLink {
+  uint32_t first, count;
+};
+
+// Chunk partials of the bounce-back force from tabulated links: io holds the
+// stored incoming and outgoing value of every link ([2][stride], compute type
+// of cbytes bytes), fc the FP64 constants of Eq. 17 ([12][stride]).
+struct ChunkSumArgs {
+  const void *io;
+  int cbytes;
+  const double *fc;
+  uint64_t stride;
+  const SolidLinks *sl;
+  double *partials;
+  uint64_t max_links, max_partials;
+  uint32_t per;  // chunk units per solid
+  int nsolid;
+};
 
 // Block `blk` (256 threads) reduces solids 4*blk .. 4*blk+3, one per wavefront.
 __device__ inline void ft_reduce_waves(const FtReduceArgs &r, uint32_t blk) {
@@ -109,6 +130,11 @@ struct lbm_ctx {
   int32_t max_box_chunks;  // per solid, for the link-builder grid
   int32_t k5_chunks;       // grid.x of the bounce-back kernel
   int64_t nlinks;
+  // cell link table of fixed solids built: the sweep can apply the
+  // bounce-back of the previous step itself (per-call link table in the
+  // staging region, link_stride entries per array)
+  bool cell_links;
+  uint64_t link_stride;
   // IBM
   int n_iter;
   double retraction;
@@ -148,8 +174,11 @@ lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 // kernels_sweep.hip
 // reduce_t >= 0: the launch also reduces the bounce-back force partials of step reduce_t;
 // ibm_t >= 0: it also sums the IBM force/torque of step ibm_t (forcing already done)
+// link_t >= 0: the sweep applies the bounce-back of step link_t (= the step
+// whose post-collision values A holds) and stores the per-link force terms of
+// that step; sum_t >= 0: it also forms the chunk partials of step sum_t.
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                  int64_t reduce_t = -1, int64_t ibm_t = -1);
+                  int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
@@ -166,6 +195,18 @@ void launch_link_emit(lbm_ctx *c, int64_t t);
 void launch_ibb(lbm_ctx *c, void *Bpost, int64_t t);
 FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t);
 void launch_ft_reduce(lbm_ctx *c, int64_t t);
+// single contexts alternate two chunk-partial buffers by step parity
+double *partials_of(lbm_ctx *c, int64_t t);
+// per-call link table of fixed solids (staging region) and the per-link
+// values of step t (buffer t & 1)
+bool link_table_fits(const lbm_ctx *c, uint64_t stride);
+void launch_link_table(lbm_ctx *c);
+const void *link_rec_of(lbm_ctx *c);
+void *link_io_of(lbm_ctx *c, int64_t t);
+ChunkSumArgs chunk_sum_args(lbm_ctx *c, int64_t t);
+uint32_t chunk_sum_blocks(const lbm_ctx *c);
+void launch_chunk_sum(lbm_ctx *c, int64_t t);
+hipError_t build_cell_links(lbm_ctx *c);
 
 // kernels_ibm.hip
 void launch_ibm_setup(lbm_ctx *c);

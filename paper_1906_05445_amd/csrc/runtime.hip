@@ -126,6 +126,9 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.box_offsets = take((size_t)max_solids * l.max_box_chunks * 4);
   l.solid_links = take((size_t)max_solids * sizeof(SolidLinks));
   l.partials = take((size_t)l.max_partials * 6 * 8);
+  l.partials2 = take((size_t)l.max_partials * 6 * 8);
+  l.seg_link = take((size_t)((N + 63) / 64) * 8);
+  l.cell_list = take((size_t)max_links * 4);
   l.solids = take((size_t)max_solids * sizeof(DevSolid));
   l.hist = take((size_t)kHistCap * max_solids * 6 * 8);
   l.staging = take((size_t)4 * N * 8);
@@ -489,6 +492,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   if (c->n_iter < 0 || !std::isfinite(c->retraction)) return set_err(c, "IBM options"), LBM_EINVAL;
   c->nlinks = 0;
   c->k5_chunks = 0;
+  c->cell_links = false;
+  c->link_stride = 0;
   c->nlag = 0;
   c->nshell = 0;
   c->lag_user = false;
@@ -516,6 +521,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
     for (auto &q : sl) mx = std::max<int32_t>(mx, (int32_t)q.nchunks);
     // translating solids gain and lose links: leave headroom, checked after each lbm_step
     c->k5_chunks = moving ? 2 * mx + 2 : mx;
+    HIPCALL(build_cell_links(c));
     return LBM_OK;
   }
   const lbm_status st = build_ibm(c);
@@ -731,6 +737,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   c->version++;
 
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
+  const bool inl = ibb && !c->any_moving && c->cell_links;
+  if (inl && nsteps > 1) launch_link_table(c);
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
     // IBM: forcing iterations now; the solid force of this step is summed in the sweep launch
@@ -742,6 +750,18 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       HIPCALL(hipEventCreate(&e0));
       HIPCALL(hipEventCreate(&e1));
       c->prof_events.push_back({e0, e1});
+    }
+    if (inl) {
+      // fixed solids: from the second step of the call on, the sweep applies the
+      // bounce-back of the previous step itself; the force terms of step t - 2
+      // become chunk partials and those of step t - 3 are summed, in its
+      // leading blocks (the last steps are finished after the loop)
+      launch_sweep(c, A, B, policy, e0, e1, k >= 3 ? c->t - 3 : -1, -1, k >= 1 ? c->t - 1 : -1,
+                   k >= 2 ? c->t - 2 : -1);
+      c->cur ^= 1;
+      c->t++;
+      c->fresh = false;
+      continue;
     }
     // the forces of the previous step of this call are reduced inside this sweep
     // launch (translating solids rebuild the link table first, so they reduce at once)
@@ -761,6 +781,18 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     c->cur ^= 1;
     c->t++;
     c->fresh = false;
+  }
+  if (inl && nsteps > 0) {
+    // the last step's bounce-back fills the ghost slots of the state the call
+    // leaves behind; every step of the call has its force summed on return
+    const int64_t T = c->t - 1;
+    if (nsteps >= 3) launch_ft_reduce(c, T - 2);
+    if (nsteps >= 2) {
+      launch_chunk_sum(c, T - 1);
+      launch_ft_reduce(c, T - 1);
+    }
+    launch_ibb(c, c->state(), T);
+    launch_ft_reduce(c, T);
   }
   HIPCALL(hipGetLastError());
   {
