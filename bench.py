@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM roofline (D3Q19 FP32 vs FP64); served solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"F64": 8, "F32": 4, "F16": 2}
+# the timed run records HIP events around every PROFILE_EVERY-th sweep launch
+# (events on every launch add host and dispatch work to each step)
+PROFILE_EVERY = 8
 
 
 def sweep_source_hash():
@@ -67,7 +70,7 @@ def run_case(case, steps, warmup, key, torch, lbm):
     N = gpu.N
     gpu.step(warmup)
     torch.cuda.synchronize()
-    gpu.profile(True)
+    gpu.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gpu.step(steps)
@@ -81,7 +84,12 @@ def run_case(case, steps, warmup, key, torch, lbm):
     tune = gpu.autotune_info()
     wall = t1 - t0
     per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
-    avg_s = sweep_ms / 1e3 / max(launches, 1)
+    timing = f"HIP events around the sweep launches of the timed run (one span per call, or every {PROFILE_EVERY}th)"
+    if launches > 0:
+        avg_s = sweep_ms / 1e3 / launches
+    else:  # a run shorter than the tuner times no sweep: the step average stands in
+        avg_s = wall / steps
+        timing = "no sweep timed (run shorter than the sweep tuner): whole-step average"
     achieved = N * per_cell / avg_s / 1e9
     traffic_bytes = traffic_for(key, N)
     traffic = None if traffic_bytes is None else traffic_bytes / avg_s / 1e9
@@ -93,7 +101,8 @@ def run_case(case, steps, warmup, key, torch, lbm):
         "method": case.method,
         "storage": case.storage,
         "sweep_avg_us": avg_s * 1e6,
-        "sweep_launches": launches,
+        "sweep_launches_timed": launches,
+        "sweep_timing": timing,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": N * per_cell, "traffic_bytes_per_launch": traffic_bytes},
@@ -289,7 +298,8 @@ def main():
     primary_case = W.sphere_box(storage="F32", method="QUADRATIC")
     primary = run_case(primary_case, K, Wm, "sphere128_f32_quadratic", torch, lbm)
     print(f"# sphere128 F32 IBB: {primary['mlups']:.0f} MLUPS, sweep {primary['sweep_avg_us']:.1f} us, "
-          f"{primary['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
+          f"{primary['roofline']['achieved']:.0f} GB/s, policy {primary['autotune'].get('policy')}",
+          file=sys.stderr, flush=True)
     extras = {}
     want = set()
     if not args.primary_only:
@@ -306,7 +316,8 @@ def main():
             k = k2 if "256" not in key else max(K // 8, 50)
             extras[key] = run_case(case, k, max(Wm // 4, 20), key, torch, lbm)
             extras[key]["steps"] = k
-            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
+            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s, "
+                  f"policy {extras[key]['autotune'].get('policy')}",
                   file=sys.stderr, flush=True)
     if "copy" in want:
         extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
@@ -351,6 +362,8 @@ def main():
         "roofline": primary["roofline"],
         "cpu_baseline": cpu,
         "sweep_avg_us": primary["sweep_avg_us"],
+        "sweep_timing": primary["sweep_timing"],
+        "autotune": primary["autotune"],
         "extras": extras,
     }
     print(json.dumps(line))

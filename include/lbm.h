@@ -196,18 +196,32 @@ lbm_status lbm_destroy(lbm_ctx *c);
 const char *lbm_status_string(lbm_status st);
 const char *lbm_last_error(const lbm_ctx *c);
 
-/* Profiling: with enable = 1, lbm_step records a pair of HIP events on the
- * context's stream around every stream-collide launch; lbm_profile_read
- * synchronises the stream, returns the summed duration (ms) and the number
- * of launches recorded since the last read, and clears them. */
-lbm_status lbm_profile(lbm_ctx *c, int32_t enable);
+/* Profiling: with every = k >= 1, lbm_step records HIP events on the
+ * context's stream around its stream-collide launches: when only fixed IBB
+ * solids are present, the launches of steps 2 .. n of a call run back to back
+ * and one pair of events spans all of them; otherwise a pair surrounds every
+ * k-th launch (k = 1: all of them; a larger k keeps the event overhead out of
+ * a timed run).  every = 0 stops recording (every < 0: LBM_EINVAL).
+ * lbm_profile_read synchronises the stream, returns the summed duration (ms)
+ * and the number of launches timed since the last read, and clears them. */
+lbm_status lbm_profile(lbm_ctx *c, int32_t every);
 lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches);
 
 /* Result of the sweep autotuner, which runs on the first lbm_step of a
  * context (or reuses a choice made for an identical lattice in this process):
  * nontemporal = 1 if the sweep writes with non-temporal stores (-1 before
- * tuning), and the measured sweep times of both store policies (us). */
+ * tuning), and the measured sweep times of both store kinds (us). */
 lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain, double *us_nontemporal);
+
+/* The tuner tries four sweep policies, kept per lattice signature:
+ * bit 0 of *policy = non-temporal stores, bit 1 = workgroups take tiles in
+ * an order that gives each of the 8 XCDs (which receive workgroups in turn)
+ * one contiguous range, so neighbouring tiles share an L2.  *policy = -1
+ * before tuning; us[4] (may be NULL) receives, per policy, the time per step
+ * of five consecutive tuning steps in microseconds (the sweeps and any other
+ * kernels of those steps).  lbm_autotune_info above reports the store half
+ * for the chosen tile order. */
+lbm_status lbm_autotune_policy(lbm_ctx *c, int32_t *policy, double *us);
 
 /* Copy `bytes` from src to dst (device pointers) with the library's
  * streaming copy kernel, the bandwidth yardstick for the sweep. */

@@ -289,7 +289,9 @@ __global__ __launch_bounds__(kBlock, (sweep_min_waves<S, COLL, INL>())) void k_s
                                                                              SweepLinkArgs la) {
   // leading blocks, dispatched first and finished long before the sweep's tail:
   // bounce-back force sums of earlier steps, or the IBM force of this one
-  uint32_t blk = blockIdx.x;
+  // policy: XCD-contiguous tile order (workgroups are dealt to the 8 XCDs
+  // round-robin; this gives each XCD's L2 a contiguous range of tiles)
+  uint32_t blk = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   if (blk < a.rblocks) {
     ft_reduce_waves(a.ft, blk);
     return;
@@ -469,10 +471,12 @@ int collision_kind(const lbm_ctx *c, double *sp, double *sm) {
 
 void fill_sweep_args(lbm_ctx *c, SweepArgs *a) { make_sweep_args(c, *a); }
 
-void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t,
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t,
                   int64_t ibm_t, int64_t link_t, int64_t sum_t) {
   SweepArgs a;
   const int coll = make_sweep_args(c, a);
+  const int nt = policy & 1;
+  a.xcd = (uint32_t)((policy >> 1) & 1);
   if (reduce_t >= 0 && c->k5_chunks > 0) {
     a.ft = ft_reduce_args(c, reduce_t);
     a.ft.partials = partials_of(c, reduce_t);

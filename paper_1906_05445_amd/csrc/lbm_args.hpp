@@ -71,6 +71,7 @@ struct SweepArgs {
   FtReduceArgs ft;
   uint32_t iblocks;      // next blocks: IBM force/torque of this step, one per solid
   IbmFtArgs ift;
+  uint32_t xcd;          // 1: blocks take tiles in XCD-contiguous order
 };
 
 // Bounce-back of the previous step applied inside the sweep (fixed solids).

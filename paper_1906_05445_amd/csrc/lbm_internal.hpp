@@ -143,16 +143,24 @@ struct lbm_ctx {
   std::vector<int64_t> lag_start, lag_count;
   std::vector<double> lag_X, lag_dV;
   bool lag_user;
-  bool profiling;
-  int sweep_nt;            // autotuned store policy of the sweep (-1: not tuned yet)
+  int32_t prof_every;       // record events around every prof_every-th sweep (0: off)
+  int64_t prof_count;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;  // read, free for reuse
+  int sweep_policy;        // autotuned sweep policy (bit 0: non-temporal stores, bit 1: XCD-contiguous tiles; -1: not tuned yet)
   struct TuneEvent {
     int policy;
     hipEvent_t e0, e1;
   };
   std::vector<TuneEvent> tune_events;
   uint64_t tuned_key;
-  double tune_us[2];       // measured sweep time of the two store policies
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  double tune_us[4];       // measured sweep time of the four policies
+  int tune_skipped;         // sweeps run before tuning starts
+  int tune_k;               // tuning sweeps run so far
+  struct ProfSpan {
+    hipEvent_t e0, e1;
+    int64_t launches;  // stream-collide launches between the two events
+  };
+  std::vector<ProfSpan> prof_events;
   std::string err;
   // batches
   struct lbm_batch *batch;  // owning batch, or null
@@ -177,7 +185,8 @@ lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 // link_t >= 0: the sweep applies the bounce-back of step link_t (= the step
 // whose post-collision values A holds) and stores the per-link force terms of
 // that step; sum_t >= 0: it also forms the chunk partials of step sum_t.
-void launch_sweep(lbm_ctx *c, const void *A, void *B, int nt, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+// policy: bit 0 non-temporal stores, bit 1 XCD-contiguous tile order
+void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                   int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);

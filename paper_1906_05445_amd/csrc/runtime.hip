@@ -239,6 +239,10 @@ void circle(const double c[3], double R, double z, std::vector<double> &X, doubl
 lbm_status lbm::destroy_ctx(lbm_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto &e : c->prof_events) {
+    (void)hipEventDestroy(e.e0);
+    (void)hipEventDestroy(e.e1);
+  }
+  for (auto &e : c->prof_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
@@ -320,10 +324,11 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->nlag = 0;
   c->nshell = 0;
   c->lag_user = false;
-  c->profiling = false;
-  c->sweep_nt = -1;
+  c->prof_every = 0;
+  c->prof_count = 0;
+  c->sweep_policy = -1;
   c->tuned_key = 0;
-  c->tune_us[0] = c->tune_us[1] = 0.0;
+  for (double &u : c->tune_us) u = 0.0;
   c->fresh = true;
   c->batch = nullptr;
   c->version = 0;
@@ -346,9 +351,23 @@ lbm_status lbm_destroy(lbm_ctx *c) {
   return lbm::destroy_ctx(c);
 }
 
-lbm_status lbm_profile(lbm_ctx *c, int32_t enable) {
-  if (!c) return LBM_EINVAL;
-  c->profiling = enable != 0;
+// A pair of profiling events: from the pool of read ones, else new.
+static hipError_t take_prof_events(lbm_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
+  if (!c->prof_pool.empty()) {
+    *e0 = c->prof_pool.back().first;
+    *e1 = c->prof_pool.back().second;
+    c->prof_pool.pop_back();
+    return hipSuccess;
+  }
+  hipError_t e = hipEventCreate(e0);
+  if (e == hipSuccess) e = hipEventCreate(e1);
+  return e;
+}
+
+lbm_status lbm_profile(lbm_ctx *c, int32_t every) {
+  if (!c || every < 0) return LBM_EINVAL;
+  c->prof_every = every;
+  c->prof_count = 0;
   return LBM_OK;
 }
 
@@ -356,15 +375,16 @@ lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches) {
   if (!c) return LBM_EINVAL;
   HIPCALL(hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  int64_t n = 0;
   for (auto &e : c->prof_events) {
     float ms = 0.0f;
-    HIPCALL(hipEventElapsedTime(&ms, e.first, e.second));
+    HIPCALL(hipEventElapsedTime(&ms, e.e0, e.e1));
     tot += ms;
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    n += e.launches;
+    c->prof_pool.push_back({e.e0, e.e1});  // reused by later recordings
   }
   if (sweep_ms) *sweep_ms = tot;
-  if (launches) *launches = (int64_t)c->prof_events.size();
+  if (launches) *launches = n;
   c->prof_events.clear();
   return LBM_OK;
 }
@@ -669,9 +689,9 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
 // call on and remembered per (lattice, collision, storage, flags, size) for
 // later contexts of this process.  Both policies compute identical values.
 // ----------------------------------------------------------------------------
-static std::map<uint64_t, std::array<double, 3>> g_tune_cache;
+static std::map<uint64_t, std::array<double, 5>> g_tune_cache;  // policy, time of each policy (us)
 static std::mutex g_tune_mutex;
-static constexpr int kTuneReps = 4;
+static constexpr int kTuneReps = 6;
 
 static uint64_t tune_key(const lbm_ctx *c) {
   uint64_t k = (uint64_t)c->N;
@@ -679,11 +699,26 @@ static uint64_t tune_key(const lbm_ctx *c) {
   k = k * 31 + (uint64_t)c->p.collision * 7 + (c->default_rates ? 1 : 0);
   k = k * 31 + (uint64_t)c->p.storage;
   k = k * 31 + (c->nsolid > 0 ? 1 : 0);
+  k = k * 31 + (uint64_t)(c->nsolid > 0 ? c->method : 0) * 2 + (c->cell_links ? 1 : 0);
   return k;
 }
 
-// policy for the next sweep; records tuning events when still tuning
-static int tune_policy(lbm_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
+// Sweep policy tuning.  The first kTuneSkip sweeps of a context use the
+// default policy (the first ones after set-up run faster than the steady
+// state).  Then each of the four policies (store kind x tile order) runs
+// kTuneReps consecutive sweeps; one pair of events spans sweeps 2 .. kTuneReps
+// of the run, so that the first sweep (whose time depends on how the sweep
+// before it left its output) is not counted and the others run back to back,
+// as they do in steady state.
+static constexpr int kPolicies = 4;
+static constexpr int kTuneSkip = 8;
+
+struct TuneStep {
+  int policy;
+  bool start, end;  // record the span's first / last event around this launch
+};
+
+static TuneStep tune_step(lbm_ctx *c) {
   const uint64_t key = tune_key(c);
   if (c->tuned_key != key) {
     for (auto &t : c->tune_events) {
@@ -691,44 +726,50 @@ static int tune_policy(lbm_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
       (void)hipEventDestroy(t.e1);
     }
     c->tune_events.clear();
-    c->sweep_nt = -1;
+    c->sweep_policy = -1;
+    c->tune_skipped = 0;
+    c->tune_k = 0;
     c->tuned_key = key;
     std::lock_guard<std::mutex> g(g_tune_mutex);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->sweep_nt = (int)it->second[0];
-      c->tune_us[0] = it->second[1];
-      c->tune_us[1] = it->second[2];
+      c->sweep_policy = (int)it->second[0];
+      for (int p = 0; p < kPolicies; p++) c->tune_us[p] = it->second[1 + p];
     }
   }
-  if (c->sweep_nt >= 0) return c->sweep_nt;
-  const int k = (int)c->tune_events.size();
-  if (k >= 2 * kTuneReps) return 1;  // decided at the end of this call
-  const int policy = k < kTuneReps ? 0 : 1;
-  if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) return policy;
-  c->tune_events.push_back({policy, *e0, *e1});
-  return policy;
+  if (c->sweep_policy >= 0) return {c->sweep_policy, false, false};
+  if (c->tune_skipped < kTuneSkip) {
+    c->tune_skipped++;
+    return {1, false, false};
+  }
+  const int j = c->tune_k;
+  if (j >= kPolicies * kTuneReps) return {1, false, false};  // decided at the end of this call
+  c->tune_k++;
+  const int r = j % kTuneReps;
+  return {j / kTuneReps, r == 1, r == kTuneReps - 1};
 }
 
 static lbm_status tune_finish(lbm_ctx *c) {
-  if (c->sweep_nt >= 0 || (int)c->tune_events.size() < 2 * kTuneReps) return LBM_OK;
+  if (c->sweep_policy >= 0 || c->tune_k < kPolicies * kTuneReps) return LBM_OK;
   HIPCALL(hipStreamSynchronize(c->stream));
-  double sum[2] = {0.0, 0.0};
-  int cnt[2] = {0, 0};
+  for (int p = 0; p < kPolicies; p++) c->tune_us[p] = 0.0;
   for (auto &t : c->tune_events) {
     float ms = 0.0f;
     HIPCALL(hipEventElapsedTime(&ms, t.e0, t.e1));
-    sum[t.policy] += ms;
-    cnt[t.policy]++;
+    c->tune_us[t.policy] = 1e3 * (double)ms / (kTuneReps - 1);
     (void)hipEventDestroy(t.e0);
     (void)hipEventDestroy(t.e1);
   }
   c->tune_events.clear();
-  c->tune_us[0] = 1e3 * sum[0] / std::max(cnt[0], 1);
-  c->tune_us[1] = 1e3 * sum[1] / std::max(cnt[1], 1);
-  c->sweep_nt = c->tune_us[1] < c->tune_us[0] ? 1 : 0;
+  // the default (non-temporal stores, linear order) is kept unless another
+  // policy is faster by 2 %: short runs flatter plain stores, whose dirty L2
+  // lines cost more in a long run than in the tuning runs
+  int best = 1;
+  for (int p = 0; p < kPolicies; p++)
+    if (p != 1 && c->tune_us[p] > 0.0 && c->tune_us[p] < 0.98 * c->tune_us[best]) best = p;
+  c->sweep_policy = best;
   std::lock_guard<std::mutex> g(g_tune_mutex);
-  g_tune_cache[c->tuned_key] = {(double)c->sweep_nt, c->tune_us[0], c->tune_us[1]};
+  g_tune_cache[c->tuned_key] = {(double)best, c->tune_us[0], c->tune_us[1], c->tune_us[2], c->tune_us[3]};
   return LBM_OK;
 }
 
@@ -739,17 +780,36 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
   const bool inl = ibb && !c->any_moving && c->cell_links;
   if (inl && nsteps > 1) launch_link_table(c);
+  bool span = false;  // a profiling span over the sweeps of this call is open
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
     // IBM: forcing iterations now; the solid force of this step is summed in the sweep launch
     const bool ibm = c->method == LBM_IBM && c->nsolid > 0 && c->nlag > 0 && c->n_iter > 0;
     if (ibm) launch_ibm_step(c, A, c->t, false);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int policy = tune_policy(c, &e0, &e1);
-    if (!e0 && c->profiling) {
-      HIPCALL(hipEventCreate(&e0));
-      HIPCALL(hipEventCreate(&e1));
-      c->prof_events.push_back({e0, e1});
+    const TuneStep ts = tune_step(c);
+    const int policy = ts.policy;
+    if (ts.start) {
+      hipEvent_t t0, t1;
+      HIPCALL(hipEventCreate(&t0));
+      HIPCALL(hipEventCreate(&t1));
+      HIPCALL(hipEventRecord(t0, c->stream));
+      c->tune_events.push_back({policy, t0, t1});
+    }
+    // profiling (once tuned): the sweeps of steps 1 .. n-1 of a call with fixed
+    // solids run back to back and are timed as one span; elsewhere every
+    // prof_every-th sweep launch carries its own events
+    const bool tuned = c->sweep_policy >= 0;
+    if (inl && k == 1 && tuned && c->prof_every > 0) {
+      hipEvent_t s0, s1;
+      HIPCALL(take_prof_events(c, &s0, &s1));
+      HIPCALL(hipEventRecord(s0, c->stream));
+      c->prof_events.push_back({s0, s1, nsteps - 1});
+      span = true;
+    }
+    if (!span && tuned && c->prof_every > 0 && c->prof_count++ % c->prof_every == 0) {
+      HIPCALL(take_prof_events(c, &e0, &e1));
+      c->prof_events.push_back({e0, e1, 1});
     }
     if (inl) {
       // fixed solids: from the second step of the call on, the sweep applies the
@@ -758,6 +818,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       // leading blocks (the last steps are finished after the loop)
       launch_sweep(c, A, B, policy, e0, e1, k >= 3 ? c->t - 3 : -1, -1, k >= 1 ? c->t - 1 : -1,
                    k >= 2 ? c->t - 2 : -1);
+      if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
+      if (span && k == nsteps - 1) HIPCALL(hipEventRecord(c->prof_events.back().e1, c->stream));
       c->cur ^= 1;
       c->t++;
       c->fresh = false;
@@ -767,6 +829,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     // launch (translating solids rebuild the link table first, so they reduce at once)
     const bool fused_reduce = ibb && k > 0 && !c->any_moving;
     launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm ? c->t : -1);
+    if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
     if (ibb) {
       launch_ibb(c, B, c->t);
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
@@ -990,9 +1053,19 @@ lbm_status lbm_check(lbm_ctx *c) {
 
 lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain, double *us_nontemporal) {
   if (!c) return LBM_EINVAL;
-  if (nontemporal) *nontemporal = c->sweep_nt;
-  if (us_plain) *us_plain = c->tune_us[0];
-  if (us_nontemporal) *us_nontemporal = c->tune_us[1];
+  const int p = c->sweep_policy;
+  if (nontemporal) *nontemporal = p < 0 ? -1 : (p & 1);
+  const int order = p < 0 ? 0 : (p & 2);
+  if (us_plain) *us_plain = c->tune_us[order];
+  if (us_nontemporal) *us_nontemporal = c->tune_us[order | 1];
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune_policy(lbm_ctx *c, int32_t *policy, double *us) {
+  if (!c) return LBM_EINVAL;
+  if (policy) *policy = c->sweep_policy;
+  if (us)
+    for (int p = 0; p < 4; p++) us[p] = c->tune_us[p];
   return LBM_OK;
 }
 

@@ -95,6 +95,7 @@ _sig("lbm_copy_probe", _st, [_vp, _vp, ctypes.c_size_t, _vp])
 _sig("lbm_profile", _st, [_vp, ctypes.c_int32])
 _sig("lbm_profile_read", _st, [_vp, _d, ctypes.POINTER(_i64)])
 _sig("lbm_autotune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d, _d])
+_sig("lbm_autotune_policy", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d])
 
 _sig("lbm_batch_table_bytes", ctypes.c_size_t, [ctypes.c_int32])
 _sig("lbm_batch_create", _st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t,
@@ -120,7 +121,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagr
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
-            "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_batch_table_bytes", "lbm_batch_create",
+            "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_autotune_policy", "lbm_batch_table_bytes", "lbm_batch_create",
             "lbm_batch_admit", "lbm_batch_release", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_info",
             "lbm_batch_tune_info", "lbm_batch_tune_table", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_stream", "lbm_batch_last_error",
             "lbm_batch_destroy"]
@@ -312,8 +313,9 @@ class Lattice(_Context):
         except Exception:
             pass
 
-    def profile(self, enable=True):
-        self._check(_lib.lbm_profile(self.handle, int(bool(enable))))
+    def profile(self, enable=True, every=1):
+        """Time every `every`-th stream-collide launch with HIP events (enable=False: stop)."""
+        self._check(_lib.lbm_profile(self.handle, int(every) if enable else 0))
 
     def profile_read(self):
         """(summed stream-collide milliseconds, launches) since the last read."""
@@ -326,7 +328,13 @@ class Lattice(_Context):
         nt = ctypes.c_int32(-1)
         a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
         self._check(_lib.lbm_autotune_info(self.handle, ctypes.byref(nt), ctypes.byref(a), ctypes.byref(b)))
-        return {"nontemporal_stores": nt.value, "sweep_us_plain": a.value, "sweep_us_nontemporal": b.value}
+        pol = ctypes.c_int32(-1)
+        us = (ctypes.c_double * 4)()
+        self._check(_lib.lbm_autotune_policy(self.handle, ctypes.byref(pol), us))
+        names = ["plain_linear", "nontemporal_linear", "plain_xcd", "nontemporal_xcd"]
+        return {"nontemporal_stores": nt.value, "sweep_us_plain": a.value, "sweep_us_nontemporal": b.value,
+                "policy": names[pol.value] if pol.value >= 0 else None,
+                "sweep_us": {names[k]: us[k] for k in range(4)}}
 
 
 class Member(_Context):

@@ -85,3 +85,16 @@ def test_split_calls_match_one_call(lbm, name):
     assert np.all(np.isfinite(one.history()))
     one.close()
     split.close()
+
+
+def test_autotune_reports_policy(lbm):
+    """After the tuning sweeps the context reports its sweep policy and the
+    median time of all four policies; results do not depend on the policy
+    (the split-call cases above tune in their first steps)."""
+    ctx = _make(lbm, CASES["d3q19_bgk_f64_linear"])
+    ctx.step(40)  # tuning: 8 sweeps skipped, then 4 runs of 6
+    info = ctx.autotune_info()
+    assert info["policy"] in ("plain_linear", "nontemporal_linear", "plain_xcd", "nontemporal_xcd")
+    assert all(v > 0.0 for v in info["sweep_us"].values())
+    assert info["nontemporal_stores"] == int(info["policy"].startswith("nontemporal"))
+    ctx.close()
