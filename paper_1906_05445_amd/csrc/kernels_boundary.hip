@@ -8,7 +8,9 @@
 // over it, deterministic.  A link (x_f, i) joins a fluid node x_f to the
 // solid node x_b = x_f - e_i; the bounce-back kernel writes the unknown
 // f_i(x_f, t+1) into slot i of x_b, exactly where the next pull sweep at x_f
-// looks for population i.
+// looks for population i.  For fixed solids the sweep evaluates most steps'
+// links itself, from per-segment link lists and a per-call link table built
+// here (the same link arithmetic, lbm_ibb.hpp).
 #include <algorithm>
 
 #include "lbm_args.hpp"
@@ -905,7 +907,7 @@ ChunkSumArgs chunk_sum_args(lbm_ctx *c, int64_t t) {
 }
 
 void launch_link_table(lbm_ctx *c) {
-  if (!c->cell_links) return;
+  if (!c->link_lists) return;
   const LinkArgs a = link_args(c, c->t);
   const uint32_t nl = (uint32_t)c->nlinks;
   const dim3 grid((nl + 63) / 64);
@@ -936,11 +938,11 @@ void launch_chunk_sum(lbm_ctx *c, int64_t t) {
   hipLaunchKernelGGL(k_chunk_sum, dim3(chunk_sum_blocks(c)), dim3(256), 0, c->stream, chunk_sum_args(c, t));
 }
 
-// Builds the cell link table of a context whose solids are all fixed; without
-// it (translating solids, IBM, capacity limits) the bounce-back stays a kernel
-// of its own after every sweep.
-hipError_t build_cell_links(lbm_ctx *c) {
-  c->cell_links = false;
+// Builds the link lists by sweep segment of a context whose solids are all
+// fixed; without them (translating solids, IBM, capacity limits) the
+// bounce-back stays a kernel of its own after every sweep.
+hipError_t build_link_lists(lbm_ctx *c) {
+  c->link_lists = false;
   c->link_stride = 0;
   if (c->method == LBM_IBM || c->any_moving || c->nsolid <= 0 || c->nlinks <= 0 || c->k5_chunks <= 0)
     return hipSuccess;
@@ -961,7 +963,7 @@ hipError_t build_cell_links(lbm_ctx *c) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   c->link_stride = stride;
-  c->cell_links = true;
+  c->link_lists = true;
   return hipSuccess;
 }
 

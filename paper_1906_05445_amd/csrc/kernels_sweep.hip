@@ -2,11 +2,12 @@
 // helper kernels (state encode/decode, macroscopic fields, watchdog, copy).
 //
 // One thread owns one cell.  It gathers f_i(x, t+1) = f*_i(x - e_i, t) from
-// the source array (pull streaming; the slots of solid nodes that fluid
-// nodes pull from hold the bounce-back values written beforehand), relaxes
-// them (Eq. 1 or Eq. 3 with the second-order body-force term of Sec. 2.1)
-// and writes the post-collision values of its own cell to the destination
-// array.  Storage is the deviation h_i = f_i - w_i (FP64, FP32 or FP16),
+// the source array (pull streaming; where x - e_i is a solid node, the
+// bounce-back value: written into that slot beforehand by the bounce-back
+// kernel, or, for fixed solids, evaluated by the sweep itself from the
+// source array), relaxes them (Eq. 1 or Eq. 3 with the second-order
+// body-force term of Sec. 2.1) and writes the post-collision values of its
+// own cell to the destination array.  Storage is the deviation h_i = f_i - w_i (FP64, FP32 or FP16),
 // arithmetic is FP64 for FP64 storage and FP32 otherwise.  Arrays are SoA,
 // [Q][stride], x fastest, so each of the 2Q streams is coalesced.
 #include <hip/hip_ext.h>
@@ -487,7 +488,7 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0,
     a.iblocks = (uint32_t)c->nsolid;
   }
   SweepLinkArgs la{};
-  const bool inl = link_t >= 0 && c->cell_links;
+  const bool inl = link_t >= 0 && c->link_lists;
   if (inl) {
     la.seg_link = c->at<SegLink>(c->L.seg_link);
     la.cell_list = c->at<uint32_t>(c->L.cell_list);

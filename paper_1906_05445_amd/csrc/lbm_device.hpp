@@ -156,7 +156,7 @@ enum : uint8_t {
   F_NOBODY = 2,    // no body force (inside a solid's volume, fluid-only forcing)
   F_IBM = 4,       // cell of an IBM stencil: read the spread boundary force
   F_WAS_SOLID = 8, // solid in the geometry of the previous step (moving solids)
-  F_LINK = 16,     // fluid node with boundary links (fixed solids; see the cell link table)
+  F_LINK = 16,     // fluid node with boundary links (fixed solids)
 };
 
 // ----------------------------------------------------------------------------

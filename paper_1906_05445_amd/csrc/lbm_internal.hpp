@@ -130,10 +130,10 @@ struct lbm_ctx {
   int32_t max_box_chunks;  // per solid, for the link-builder grid
   int32_t k5_chunks;       // grid.x of the bounce-back kernel
   int64_t nlinks;
-  // cell link table of fixed solids built: the sweep can apply the
-  // bounce-back of the previous step itself (per-call link table in the
+  // link lists of fixed solids by sweep segment built: the sweep can apply
+  // the bounce-back of the previous step itself (per-call link table in the
   // staging region, link_stride entries per array)
-  bool cell_links;
+  bool link_lists;
   uint64_t link_stride;
   // IBM
   int n_iter;
@@ -215,7 +215,7 @@ void *link_io_of(lbm_ctx *c, int64_t t);
 ChunkSumArgs chunk_sum_args(lbm_ctx *c, int64_t t);
 uint32_t chunk_sum_blocks(const lbm_ctx *c);
 void launch_chunk_sum(lbm_ctx *c, int64_t t);
-hipError_t build_cell_links(lbm_ctx *c);
+hipError_t build_link_lists(lbm_ctx *c);
 
 // kernels_ibm.hip
 void launch_ibm_setup(lbm_ctx *c);

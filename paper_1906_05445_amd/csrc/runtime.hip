@@ -512,7 +512,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   if (c->n_iter < 0 || !std::isfinite(c->retraction)) return set_err(c, "IBM options"), LBM_EINVAL;
   c->nlinks = 0;
   c->k5_chunks = 0;
-  c->cell_links = false;
+  c->link_lists = false;
   c->link_stride = 0;
   c->nlag = 0;
   c->nshell = 0;
@@ -541,7 +541,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
     for (auto &q : sl) mx = std::max<int32_t>(mx, (int32_t)q.nchunks);
     // translating solids gain and lose links: leave headroom, checked after each lbm_step
     c->k5_chunks = moving ? 2 * mx + 2 : mx;
-    HIPCALL(build_cell_links(c));
+    HIPCALL(build_link_lists(c));
     return LBM_OK;
   }
   const lbm_status st = build_ibm(c);
@@ -699,7 +699,7 @@ static uint64_t tune_key(const lbm_ctx *c) {
   k = k * 31 + (uint64_t)c->p.collision * 7 + (c->default_rates ? 1 : 0);
   k = k * 31 + (uint64_t)c->p.storage;
   k = k * 31 + (c->nsolid > 0 ? 1 : 0);
-  k = k * 31 + (uint64_t)(c->nsolid > 0 ? c->method : 0) * 2 + (c->cell_links ? 1 : 0);
+  k = k * 31 + (uint64_t)(c->nsolid > 0 ? c->method : 0) * 2 + (c->link_lists ? 1 : 0);
   return k;
 }
 
@@ -778,7 +778,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   c->version++;
 
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
-  const bool inl = ibb && !c->any_moving && c->cell_links;
+  const bool inl = ibb && !c->any_moving && c->link_lists;
   if (inl && nsteps > 1) launch_link_table(c);
   bool span = false;  // a profiling span over the sweeps of this call is open
   for (int64_t k = 0; k < nsteps; k++) {
