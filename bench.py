@@ -314,7 +314,7 @@ def main():
                           ("pack256_f64_quadratic", W.sphere_pack(storage="F64")),
                           ("pack256_f16_quadratic", W.sphere_pack(storage="F16"))]:
             k = k2 if "256" not in key else max(K // 8, 50)
-            extras[key] = run_case(case, k, max(Wm // 4, 20), key, torch, lbm)
+            extras[key] = run_case(case, k, max(Wm // 4, 64), key, torch, lbm)
             extras[key]["steps"] = k
             print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s, "
                   f"policy {extras[key]['autotune'].get('policy')}",

@@ -213,14 +213,15 @@ lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches);
  * tuning), and the measured sweep times of both store kinds (us). */
 lbm_status lbm_autotune_info(lbm_ctx *c, int32_t *nontemporal, double *us_plain, double *us_nontemporal);
 
-/* The tuner tries four sweep policies, kept per lattice signature:
- * bit 0 of *policy = non-temporal stores, bit 1 = workgroups take tiles in
- * an order that gives each of the 8 XCDs (which receive workgroups in turn)
- * one contiguous range, so neighbouring tiles share an L2.  *policy = -1
- * before tuning; us[4] (may be NULL) receives, per policy, the time per step
- * of five consecutive tuning steps in microseconds (the sweeps and any other
- * kernels of those steps).  lbm_autotune_info above reports the store half
- * for the chosen tile order. */
+/* Sweep policy, kept per lattice signature: bit 0 of *policy = non-temporal
+ * stores (always set: the tuner does not change the store kind), bit 1 =
+ * workgroups take tiles in an order that gives each of the 8 XCDs (which
+ * receive workgroups in turn) one contiguous range, so neighbouring tiles
+ * share an L2; the tuner picks the tile order.  *policy = -1 before tuning;
+ * us[4] (may be NULL) receives, per policy, the time per step measured over
+ * back-to-back tuning steps in microseconds (the sweeps and any other kernels
+ * of those steps; 0 for the policies not tried).  lbm_autotune_info above
+ * reports the store half for the chosen tile order. */
 lbm_status lbm_autotune_policy(lbm_ctx *c, int32_t *policy, double *us);
 
 /* Copy `bytes` from src to dst (device pointers) with the library's

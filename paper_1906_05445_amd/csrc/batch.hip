@@ -90,6 +90,7 @@ struct lbm_batch {
   int64_t *d_step = nullptr;
   uint32_t *d_status = nullptr;
   WorkList *d_wl = nullptr;
+  uint16_t *d_bucket = nullptr;  // [WL_COUNT][kWlBuckets]
   uint32_t *d_start = nullptr;
   int32_t *d_mem = nullptr;
   double *d_change = nullptr;
@@ -259,6 +260,7 @@ lbm_status rebuild(lbm_batch *b) {
   std::vector<WorkList> wl(WL_COUNT);
   std::vector<uint32_t> start((size_t)WL_COUNT * (S + 1), 0);
   std::vector<int32_t> slot((size_t)WL_COUNT * S, 0);
+  std::vector<uint16_t> bucket((size_t)WL_COUNT * kWlBuckets, 0);
   for (int l = 0; l < WL_COUNT; l++) {
     uint64_t run = 0;
     uint32_t *st = start.data() + (size_t)l * (S + 1);
@@ -274,6 +276,15 @@ lbm_status rebuild(lbm_batch *b) {
     wl[l].n = (int32_t)units[l].size();
     wl[l].start = b->d_start + (size_t)l * (S + 1);
     wl[l].slot = b->d_mem + (size_t)l * S;
+    wl[l].bucket = b->d_bucket + (size_t)l * kWlBuckets;
+    // owner of the first unit of each bucket (bucket of u: u * kWlBuckets / total)
+    uint16_t *bk = bucket.data() + (size_t)l * kWlBuckets;
+    size_t k = 0;
+    for (uint32_t q = 0; q < kWlBuckets && run > 0; q++) {
+      const uint64_t first = ((uint64_t)q * run + kWlBuckets - 1) / kWlBuckets;
+      while (k + 1 < units[l].size() && st[k + 1] <= first) k++;
+      bk[q] = (uint16_t)k;
+    }
   }
   std::vector<uint32_t> status((size_t)2 * S, 0);
   for (int k = 0; k < S; k++)
@@ -283,6 +294,8 @@ lbm_status rebuild(lbm_batch *b) {
   BHIP(hipMemcpyAsync(b->d_wl, wl.data(), sizeof(WorkList) * WL_COUNT, hipMemcpyHostToDevice, b->stream));
   BHIP(hipMemcpyAsync(b->d_start, start.data(), sizeof(uint32_t) * start.size(), hipMemcpyHostToDevice, b->stream));
   BHIP(hipMemcpyAsync(b->d_mem, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice, b->stream));
+  BHIP(hipMemcpyAsync(b->d_bucket, bucket.data(), sizeof(uint16_t) * bucket.size(), hipMemcpyHostToDevice,
+                      b->stream));
   BHIP(hipMemcpyAsync(b->d_status, status.data(), sizeof(uint32_t) * status.size(), hipMemcpyHostToDevice,
                       b->stream));
   BHIP(hipMemcpyAsync(b->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream));
@@ -406,7 +419,8 @@ size_t lbm_batch_table_bytes(int32_t max_slots) {
   if (max_slots <= 0) return 0;
   const size_t S = (size_t)max_slots;
   return align256(sizeof(BatchSlot) * S) + 256 + align256(8 * S) + align256(sizeof(WorkList) * WL_COUNT) +
-         align256(4 * WL_COUNT * (S + 1)) + align256(4 * WL_COUNT * S) + align256(8 * S);
+         align256(4 * WL_COUNT * (S + 1)) + align256(4 * WL_COUNT * S) + align256(8 * S) +
+         align256(2 * WL_COUNT * (size_t)kWlBuckets);
 }
 
 lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots, void *dev_pool, size_t pool_bytes,
@@ -451,6 +465,8 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
   b->d_mem = reinterpret_cast<int32_t *>(p);
   p += align256(4 * WL_COUNT * S);
   b->d_change = reinterpret_cast<double *>(p);
+  p += align256(8 * S);
+  b->d_bucket = reinterpret_cast<uint16_t *>(p);
   b->free_[tb] = (pool_bytes - tb) & ~size_t(255);
   if (rebuild(b) != LBM_OK) {
     (void)hipStreamDestroy(b->stream);

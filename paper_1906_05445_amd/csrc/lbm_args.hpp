@@ -212,11 +212,16 @@ enum { BS_LINKS_OVERFLOW = 1, BS_CHUNKS_OVERFLOW = 2, BS_REFILL_OVERFLOW = 4 };
 // The units (tiles, link chunks, ...) of one batched launch: member k owns
 // units start[k] .. start[k+1]-1 and is lattice slot[k] of the batch.  Kept
 // in device memory, so a captured launch follows changes of the batch.
+// Units of a batched launch: member j owns units start[j] .. start[j+1]-1
+// and is batch slot slot[j]; bucket[b] is the member that owns the first unit
+// u with u * kWlBuckets / total = b, where a lookup starts.
+constexpr uint32_t kWlBuckets = 1024;
 struct WorkList {
   uint32_t total;
   int32_t n;
   const uint32_t *start;
   const int32_t *slot;
+  const uint16_t *bucket;
 };
 
 // Load of a block-uniform value from the batch tables through the constant
@@ -230,15 +235,13 @@ __device__ __forceinline__ T load_uniform(const T *p) {
   return v;
 }
 
-// Member that owns unit `u`: the last k with start[k] <= u.
-__device__ inline int batch_member_of(const uint32_t *start, int n, uint32_t u) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (load_uniform(start + mid) <= u) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+// Member that owns unit `u` (< total): the last k with start[k] <= u, found
+// from u's bucket (usually zero or one step onwards).
+__device__ inline int batch_member_of(const WorkList &wl, uint32_t u) {
+  const uint32_t b = (uint32_t)(((uint64_t)u * kWlBuckets) / wl.total);
+  int k = load_uniform(wl.bucket + b);
+  while (k + 1 < wl.n && load_uniform(wl.start + k + 1) <= u) k++;
+  return k;
 }
 
 // Persistent walk over the units of a work list: order 0 gives each block a
@@ -248,7 +251,6 @@ template <typename F>
 __device__ inline void batch_units(const WorkList *wlp, int order, F f) {
   const WorkList wl = load_uniform(wlp);
   const uint32_t total = wl.total;
-  const int n = wl.n;
   uint32_t u, end, inc;
   if (order == 0) {
     const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -261,7 +263,7 @@ __device__ inline void batch_units(const WorkList *wlp, int order, F f) {
     inc = gridDim.x;
   }
   if (u >= end) return;
-  int k = batch_member_of(wl.start, n, u);
+  int k = batch_member_of(wl, u);
   uint32_t lo = load_uniform(wl.start + k), hi = load_uniform(wl.start + k + 1);
   for (; u < end; u += inc) {
     while (u >= hi) {

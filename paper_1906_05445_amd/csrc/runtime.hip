@@ -691,7 +691,7 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
 // ----------------------------------------------------------------------------
 static std::map<uint64_t, std::array<double, 5>> g_tune_cache;  // policy, time of each policy (us)
 static std::mutex g_tune_mutex;
-static constexpr int kTuneReps = 6;
+static constexpr int kTuneReps = 12;
 
 static uint64_t tune_key(const lbm_ctx *c) {
   uint64_t k = (uint64_t)c->N;
@@ -703,15 +703,22 @@ static uint64_t tune_key(const lbm_ctx *c) {
   return k;
 }
 
-// Sweep policy tuning.  The first kTuneSkip sweeps of a context use the
+// Sweep policy tuning.  Stores are non-temporal (policy bit 0): tuning runs
+// did not rank plain against non-temporal stores the way long runs do (plain
+// stores won short runs at 128^3 FP32 and lost the long ones), so only the
+// tile order is tuned.  The first kTuneSkip sweeps of a context use the
 // default policy (the first ones after set-up run faster than the steady
-// state).  Then each of the four policies (store kind x tile order) runs
-// kTuneReps consecutive sweeps; one pair of events spans sweeps 2 .. kTuneReps
-// of the run, so that the first sweep (whose time depends on how the sweep
-// before it left its output) is not counted and the others run back to back,
-// as they do in steady state.
+// state).  Then the two candidates run kTuneReps consecutive sweeps each, in
+// the order A B B A, so that a drift of the sweep time over the tuning
+// cancels in each candidate's mean; one pair of events spans sweeps 2 ..
+// kTuneReps of a run, so that the first sweep (whose time depends on how the
+// sweep before it left its output) is not counted and the others run back to
+// back, as they do in steady state.
 static constexpr int kPolicies = 4;
 static constexpr int kTuneSkip = 8;
+static constexpr int kCands[2] = {1, 3};  // non-temporal stores, linear / XCD-contiguous tile order
+static constexpr int kTuneRuns = 4;
+static int tune_run_policy(int r) { return kCands[(r == 0 || r == 3) ? 0 : 1]; }
 
 struct TuneStep {
   int policy;
@@ -743,30 +750,26 @@ static TuneStep tune_step(lbm_ctx *c) {
     return {1, false, false};
   }
   const int j = c->tune_k;
-  if (j >= kPolicies * kTuneReps) return {1, false, false};  // decided at the end of this call
+  if (j >= kTuneRuns * kTuneReps) return {1, false, false};  // decided at the end of this call
   c->tune_k++;
   const int r = j % kTuneReps;
-  return {j / kTuneReps, r == 1, r == kTuneReps - 1};
+  return {tune_run_policy(j / kTuneReps), r == 1, r == kTuneReps - 1};
 }
 
 static lbm_status tune_finish(lbm_ctx *c) {
-  if (c->sweep_policy >= 0 || c->tune_k < kPolicies * kTuneReps) return LBM_OK;
+  if (c->sweep_policy >= 0 || c->tune_k < kTuneRuns * kTuneReps) return LBM_OK;
   HIPCALL(hipStreamSynchronize(c->stream));
   for (int p = 0; p < kPolicies; p++) c->tune_us[p] = 0.0;
-  for (auto &t : c->tune_events) {
+  for (auto &t : c->tune_events) {  // two runs per candidate
     float ms = 0.0f;
     HIPCALL(hipEventElapsedTime(&ms, t.e0, t.e1));
-    c->tune_us[t.policy] = 1e3 * (double)ms / (kTuneReps - 1);
+    c->tune_us[t.policy] += 1e3 * (double)ms / (2 * (kTuneReps - 1));
     (void)hipEventDestroy(t.e0);
     (void)hipEventDestroy(t.e1);
   }
   c->tune_events.clear();
-  // the default (non-temporal stores, linear order) is kept unless another
-  // policy is faster by 2 %: short runs flatter plain stores, whose dirty L2
-  // lines cost more in a long run than in the tuning runs
-  int best = 1;
-  for (int p = 0; p < kPolicies; p++)
-    if (p != 1 && c->tune_us[p] > 0.0 && c->tune_us[p] < 0.98 * c->tune_us[best]) best = p;
+  // the linear order is kept unless the XCD-contiguous one is faster by 1 %
+  const int best = c->tune_us[kCands[1]] < 0.99 * c->tune_us[kCands[0]] ? kCands[1] : kCands[0];
   c->sweep_policy = best;
   std::lock_guard<std::mutex> g(g_tune_mutex);
   g_tune_cache[c->tuned_key] = {(double)best, c->tune_us[0], c->tune_us[1], c->tune_us[2], c->tune_us[3]};
