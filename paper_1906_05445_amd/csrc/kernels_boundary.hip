@@ -242,13 +242,16 @@ __device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   int o[3], x, y, z;
   double c[3];
   box_origin(sd, a.g, o, c);
-  uint32_t cnt = 0;
-  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
+  uint32_t m = 0;
+  const uint32_t bi = bx * kBlock + threadIdx.x;
+  const bool in = box_cell(sd, o, bi, a.g, x, y, z);
+  if (in && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
     const uint32_t n = id_of(x, y, z, a.g);
     const uint8_t f = a.flags[n];
-    if (!(f & F_SOLID)) cnt = __popc(link_mask<Q>(a, s, x, y, z));
+    if (!(f & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
   }
-  const double tot = block_sum((double)cnt, lds);
+  if (a.masks && in) a.masks[sd.mask_off + bi] = m;  // read back by the emit pass
+  const double tot = block_sum((double)__popc(m), lds);
   if (threadIdx.x == 0 && bx < a.max_box_chunks) a.box_counts[(uint64_t)s * a.max_box_chunks + bx] = (uint32_t)tot;
 }
 template <int Q>
@@ -340,7 +343,13 @@ __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
   double c[3];
   box_origin(sd, a.g, o, c);
   uint32_t m = 0, n = 0;
-  if (box_cell(sd, o, bx * kBlock + threadIdx.x, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
+  const uint32_t bi = bx * kBlock + threadIdx.x;
+  if (a.masks) {  // the count pass stored every box cell's mask
+    if (box_cell(sd, o, bi, a.g, x, y, z)) {
+      m = a.masks[sd.mask_off + bi];
+      if (m) n = id_of(x, y, z, a.g);
+    }
+  } else if (box_cell(sd, o, bi, a.g, x, y, z) && near_surface(sd, c, x, y, z, a.g.b, kLinkBand)) {
     n = id_of(x, y, z, a.g);
     if (!(a.flags[n] & F_SOLID)) m = link_mask<Q>(a, s, x, y, z);
   }
@@ -768,6 +777,7 @@ static LinkArgs link_args(const lbm_ctx *c, int64_t t) {
   a.misc = c->at<uint32_t>(c->L.misc);
   a.refill_list = c->at<uint64_t>(c->L.refill);
   a.max_refill = (uint32_t)c->L.max_refill;
+  a.masks = c->mask_cells > 0 ? c->at<uint32_t>(c->L.staging) : nullptr;
   return a;
 }
 

@@ -34,6 +34,8 @@ struct LinkArgs {
   void *post;              // refill: post-collision array of step t-1 -> t
   uint64_t *refill_list;   // nodes uncovered this step: (solid << 32) | cell
   uint32_t max_refill;     // misc[3] counts them, misc[4] flags an overflow
+  uint32_t *masks;         // link mask of every box cell (solid s at solids[s].mask_off), written by
+                           // the count pass, read by the emit pass; null: emit recomputes them
 };
 
 struct IbbArgs {

@@ -27,6 +27,7 @@ struct DevSolid {
   int32_t box0[3];   // box origin of a fixed solid
   uint32_t box_cells;
   FastDiv fex, fexy;  // division by ext[0] and by ext[0] * ext[1]
+  uint64_t mask_off;  // first box cell of this solid in the link-mask buffer
   double c0[3], R, U[3], W[3];
 };
 
@@ -130,6 +131,7 @@ struct lbm_ctx {
   int32_t max_box_chunks;  // per solid, for the link-builder grid
   int32_t k5_chunks;       // grid.x of the bounce-back kernel
   int64_t nlinks;
+  uint64_t mask_cells;     // box cells of all solids, when their link masks fit the staging region (else 0)
   // link lists of fixed solids by sweep segment built: the sweep can apply
   // the bounce-back of the previous step itself (per-call link table in the
   // staging region, link_stride entries per array)

@@ -414,6 +414,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   std::vector<DevSolid> ds((size_t)std::max(n, 1));
   bool moving = false;
   int32_t mbc = 0;
+  uint64_t mask_total = 0;  // box cells of the solids so far (link-mask buffer offsets)
   for (int k = 0; k < n; k++) {
     const lbm_solid &q = s[k];
     DevSolid &d = ds[k];
@@ -476,6 +477,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       cells *= (uint64_t)d.ext[a];
     }
     d.box_cells = (uint32_t)cells;
+    d.mask_off = mask_total;
+    mask_total += cells;
     d.fex = make_div((uint32_t)d.ext[0]);
     d.fexy = make_div((uint32_t)d.ext[0] * (uint32_t)d.ext[1]);
     mbc = std::max<int32_t>(mbc, (int32_t)((cells + kBlock - 1) / kBlock));
@@ -507,6 +510,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->method = method;
   c->any_moving = moving;
   c->max_box_chunks = mbc;
+  // the link masks of the count pass live in the staging region (4 N doubles) while links are built
+  c->mask_cells = mask_total * 4 <= (uint64_t)4 * c->N * 8 ? mask_total : 0;
   c->n_iter = opts ? opts->n_iter : 5;
   c->retraction = opts ? opts->retraction : 0.0;
   if (c->n_iter < 0 || !std::isfinite(c->retraction)) return set_err(c, "IBM options"), LBM_EINVAL;
