@@ -23,7 +23,10 @@ enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
 // Pull of cell n: population i arrives from x - e_i (raw stored values; the
 // conversion to the compute type happens in sweep_relax, so the loads of
 // several cells can all be in flight together).
-template <int Q, typename S>
+// IDX32: the arrays hold fewer than 2^32 values, so offsets are formed in 32
+// bits (a 24-bit multiply-add instead of a 64-bit one per gather; worth it
+// where the sweep is bound by instructions, FP16 storage).
+template <int Q, typename S, int IDX32>
 __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepArgs &a, uint32_t n, S (&r)[Q]) {
   using L = Lat<Q>;
   const uint32_t yz = fdiv(n, a.fx);
@@ -39,13 +42,14 @@ __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepA
     const uint32_t sy = L::ey(i) > 0 ? ym : (L::ey(i) < 0 ? yp : y);
     const uint32_t sz = L::ez(i) > 0 ? zm : (L::ez(i) < 0 ? zp : z);
     const uint32_t src = sx + a.nx * (sy + a.ny * sz);
-    r[i] = A[pidx<Q>(i, src)];
+    if constexpr (IDX32 != 0) r[i] = A[pidx32<Q>(i, src)];
+    else r[i] = A[pidx<Q>(i, src)];
   }
 }
 
 // Relaxation of one cell (Eq. 1 or Eq. 3 with the forcing of Sec. 2.1) and
 // the store of its post-collision values.
-template <int Q, int COLL, typename S, int FLAGS, int NT>
+template <int Q, int COLL, typename S, int FLAGS, int NT, int IDX32>
 __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &a, uint32_t n, uint8_t fl,
                                             const S (&r)[Q]) {
   using C = typename Store<S>::C;
@@ -160,7 +164,9 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   }
 
   // the block writes Q contiguous runs of kTile values per tile
-  const uint64_t base = pidx<Q>(0, n);
+  uint64_t base;
+  if constexpr (IDX32 != 0) base = pidx32<Q>(0, n);
+  else base = pidx<Q>(0, n);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     if (NT) Store<S>::st_nt(B + base + (uint64_t)i * kTile, h[i]);
@@ -234,7 +240,7 @@ __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la,
 // One block sweeps sweep_cpt tiles (group blk): every thread pulls its cell
 // of each tile before relaxing any, so that half-precision storage keeps as
 // many bytes in flight per wavefront as single precision.
-template <int Q, int COLL, typename S, int FLAGS, int NT, int INL>
+template <int Q, int COLL, typename S, int FLAGS, int NT, int INL, int IDX32 = 0>
 __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
                                            const SweepLinkArgs *la, uint32_t blk) {
   constexpr int CPT = sweep_cpt_of<S>();
@@ -252,7 +258,7 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   // cells past the end load cell N-1, solid nodes load and discard
   S r[CPT][Q];
 #pragma unroll
-  for (int c = 0; c < CPT; c++) sweep_pull<Q, S>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
+  for (int c = 0; c < CPT; c++) sweep_pull<Q, S, IDX32>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
 #pragma unroll
   for (int c = 0; c < CPT; c++) act[c] = act[c] && !(fl[c] & F_SOLID);  // nothing is stored for solid nodes
   if constexpr (INL != 0) {
@@ -273,7 +279,7 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   }
 #pragma unroll
   for (int c = 0; c < CPT; c++)
-    if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT>(B, a, n[c], fl[c], r[c]);
+    if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT, IDX32>(B, a, n[c], fl[c], r[c]);
 }
 
 // Waves per SIMD the sweep keeps when it also evaluates boundary links: the
@@ -284,7 +290,7 @@ constexpr int sweep_min_waves() {
   return (!INL || COLL == COLL_MRT) ? 1 : (sizeof(S) == 4 ? 8 : (sizeof(S) == 2 ? 5 : 4));
 }
 
-template <int Q, int COLL, typename S, int FLAGS, int NT, int INL>
+template <int Q, int COLL, typename S, int FLAGS, int NT, int INL, int IDX32>
 __global__ __launch_bounds__(kBlock, (sweep_min_waves<S, COLL, INL>())) void k_sweep(const S *__restrict__ A,
                                                                              S *__restrict__ B, SweepArgs a,
                                                                              SweepLinkArgs la) {
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(kBlock, (sweep_min_waves<S, COLL, INL>())) void k_s
     ibm_ft_body(a.ift, (int)blk);
     return;
   }
-  sweep_body<Q, COLL, S, FLAGS, NT, INL>(A, B, a, &la, blk - a.iblocks);
+  sweep_body<Q, COLL, S, FLAGS, NT, INL, IDX32>(A, B, a, &la, blk - a.iblocks);
 }
 
 // Batched sweep: the tiles of every lattice of a work list in one persistent
@@ -381,9 +387,20 @@ static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
   // the events (when given) are attached to the dispatch itself and time the kernel alone
-#define LBM_SWEEP(QQ, CC, FF, NN, II)                                                                              \
-  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN, II>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, As, Bs, \
-                        a, la)
+  // 32-bit offsets for FP16 storage when Q * stride < 2^32
+  const bool idx32 = sizeof(S) == 2 && (uint64_t)c->Q * c->L.stride < (1ull << 32);
+#define LBM_SWEEP1(QQ, CC, FF, NN, II, XX)                                                                   \
+  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN, II, XX>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, \
+                        As, Bs, a, la)
+#define LBM_SWEEP(QQ, CC, FF, NN, II)               \
+  do {                                              \
+    if constexpr (sizeof(S) == 2) {                 \
+      if (idx32) LBM_SWEEP1(QQ, CC, FF, NN, II, 1); \
+      else LBM_SWEEP1(QQ, CC, FF, NN, II, 0);       \
+    } else {                                        \
+      LBM_SWEEP1(QQ, CC, FF, NN, II, 0);            \
+    }                                               \
+  } while (0)
 #define LBM_SWEEP2(QQ, CC)                     \
   do {                                         \
     if (inl) {                                 \
@@ -408,6 +425,7 @@ static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &
   }
 #undef LBM_SWEEP2
 #undef LBM_SWEEP
+#undef LBM_SWEEP1
 }
 
 // Two-rate test: every even non-conserved row shares one rate, every odd

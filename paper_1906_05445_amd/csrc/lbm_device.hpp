@@ -144,6 +144,12 @@ template <int Q>
 __host__ __device__ inline uint64_t pidx(int i, uint32_t n) {
   return (uint64_t)(n / kTile) * (Q * kTile) + (uint64_t)i * kTile + (n % kTile);
 }
+// The same offset in 32 bits, for arrays of fewer than 2^32 values: one
+// 24-bit multiply-add instead of a 64-bit one.
+template <int Q>
+__device__ inline uint32_t pidx32(int i, uint32_t n) {
+  return __umul24(n >> 8, (uint32_t)(Q * kTile)) + (uint32_t)i * kTile + (n & (kTile - 1));
+}
 __host__ __device__ inline uint64_t pidx_rt(int Q, int i, uint32_t n) {
   return (uint64_t)(n / kTile) * ((uint64_t)Q * kTile) + (uint64_t)i * kTile + (n % kTile);
 }
