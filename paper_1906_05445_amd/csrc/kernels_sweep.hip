@@ -24,8 +24,8 @@ enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
 // conversion to the compute type happens in sweep_relax, so the loads of
 // several cells can all be in flight together).
 // IDX32: the arrays hold fewer than 2^32 values, so offsets are formed in 32
-// bits (a 24-bit multiply-add instead of a 64-bit one per gather; worth it
-// where the sweep is bound by instructions, FP16 storage).
+// bits (a 24-bit multiply-add instead of a 64-bit one per gather: FP16,
+// whose sweep is bound by instructions, gains 2-4 %, FP32 and FP64 under 1 %).
 template <int Q, typename S, int IDX32>
 __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepArgs &a, uint32_t n, S (&r)[Q]) {
   using L = Lat<Q>;
@@ -387,19 +387,15 @@ static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
   // the events (when given) are attached to the dispatch itself and time the kernel alone
-  // 32-bit offsets for FP16 storage when Q * stride < 2^32
-  const bool idx32 = sizeof(S) == 2 && (uint64_t)c->Q * c->L.stride < (1ull << 32);
+  // 32-bit offsets when Q * stride < 2^32
+  const bool idx32 = (uint64_t)c->Q * c->L.stride < (1ull << 32);
 #define LBM_SWEEP1(QQ, CC, FF, NN, II, XX)                                                                   \
   hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, FF, NN, II, XX>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, \
                         As, Bs, a, la)
 #define LBM_SWEEP(QQ, CC, FF, NN, II)               \
   do {                                              \
-    if constexpr (sizeof(S) == 2) {                 \
-      if (idx32) LBM_SWEEP1(QQ, CC, FF, NN, II, 1); \
-      else LBM_SWEEP1(QQ, CC, FF, NN, II, 0);       \
-    } else {                                        \
-      LBM_SWEEP1(QQ, CC, FF, NN, II, 0);            \
-    }                                               \
+    if (idx32) LBM_SWEEP1(QQ, CC, FF, NN, II, 1);   \
+    else LBM_SWEEP1(QQ, CC, FF, NN, II, 0);         \
   } while (0)
 #define LBM_SWEEP2(QQ, CC)                     \
   do {                                         \
