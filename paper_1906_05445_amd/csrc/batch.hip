@@ -36,7 +36,7 @@ enum {
   WL_BOX,        // (solid, box chunk) units of members with translating solids
   WL_ONE,        // one unit per member with translating solids
   WL_IBM_SHELL,   // 128 shell cells per unit (u0)
-  WL_IBM_SPREAD,  // 16 shell cells per unit (spreading, 16 lanes per cell)
+  WL_IBM_SPREAD,  // kSpreadCellsPerBlock shell cells per unit (kSpreadLanes lanes per cell)
   WL_IBM_LAG,
   WL_IBM_FT,
   WL_SOLID,      // one unit per member with solids (convergence check)
@@ -252,7 +252,7 @@ lbm_status rebuild(lbm_batch *b) {
       b->any_ibm = true;
       b->max_iter = std::max(b->max_iter, c->n_iter);
       add(WL_IBM_SHELL, (uint64_t)((c->nshell + 127) / 128));
-      add(WL_IBM_SPREAD, (uint64_t)((c->nshell + 15) / 16));
+      add(WL_IBM_SPREAD, (uint64_t)((c->nshell + kSpreadCellsPerBlock - 1) / kSpreadCellsPerBlock));
       add(WL_IBM_LAG, (uint64_t)((c->nlag + 3) / 4));  // four points (wavefronts) per block
       add(WL_IBM_FT, (uint64_t)c->nsolid);
     }

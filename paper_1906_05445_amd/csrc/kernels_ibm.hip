@@ -8,6 +8,13 @@
 // stencil slot) that cover it sorted by point.  Interpolation is a gather
 // per point; spreading is a gather per shell cell over that list, so no
 // atomics are used and every sum has a fixed order.
+//
+// A step's forcing is a chain of launches, one per phase (u0, then
+// interpolation and spreading per iteration): the phases depend on each other
+// across the whole shell, and a kernel boundary is the cheapest device-wide
+// synchronisation available.  Single contexts and batches run different
+// kernels around the same contraction-free arithmetic, in the same order, so
+// they produce the same bits.
 #include <algorithm>
 
 #include "lbm_args.hpp"
@@ -50,6 +57,7 @@ __global__ void k_ibm_mark(IbmArgs a) {
 // from the shifted state (A_i(x - e_i)); clears the spread force.
 template <int Q, typename S>
 __device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, int64_t s) {
+#pragma clang fp contract(off)
   using C = typename Store<S>::C;
   using L = Lat<Q>;
   if (s >= a.nshell) return;
@@ -92,38 +100,76 @@ __device__ inline C wave_sum_c(C v) {
   return v;
 }
 
+// Delta weight of stencil slot (kx + 4 ky + 16 kz) from the per-axis weights.
+template <typename C>
+__device__ inline C ibm_weight(const double *w, uint32_t slot) {
+#pragma clang fp contract(off)
+  return (C)((w[slot & 3u] * w[4 + ((slot >> 2) & 3u)]) * w[8 + (slot >> 4)]);
+}
+
+// Stencil slot's share of the interpolated velocity (before the wave sum).
+template <typename C>
+__device__ inline void ibm_interp_terms(const C *u, int64_t nshell, uint32_t si, C wt, C v[3]) {
+#pragma clang fp contract(off)
+  v[0] = u[si] * wt;
+  v[1] = u[nshell + si] * wt;
+  v[2] = u[2 * nshell + si] * wt;
+}
+
+// Point force of one iteration, F = U^d - U~ (Eq. 7 with rho0 = dt = 1), and
+// its running sum over the iterations.
+template <typename C>
+__device__ inline C ibm_point_force(C ud, C us, double *sum) {
+#pragma clang fp contract(off)
+  const C F = ud - us;
+  *sum = *sum + (double)F;
+  return F;
+}
+
 template <typename C>
 __device__ inline void ibm_interp_body(const IbmArgs &a, int first, int64_t l) {
   const int slot = (int)(threadIdx.x & 63);
-  const int kz = slot >> 4, ky = (slot >> 2) & 3, kx = slot & 3;
+  const int kz = slot >> 4;
   const C *u = static_cast<const C *>(a.ushell);
-  C v0 = 0, v1 = 0, v2 = 0;
-  if (l < a.nlag && kz < (a.b.D == 2 ? 1 : 4)) {
-    const double *w = a.wts + l * 12;
-    const C wt = (C)((w[kx] * w[4 + ky]) * w[8 + kz]);
-    const uint32_t si = a.idx[l * 64 + slot];
-    v0 = u[si] * wt;
-    v1 = u[a.nshell + si] * wt;
-    v2 = u[2 * a.nshell + si] * wt;
-  }
-  v0 = wave_sum_c(v0);
-  v1 = wave_sum_c(v1);
-  v2 = wave_sum_c(v2);
+  C v[3] = {0, 0, 0};
+  if (l < a.nlag && kz < (a.b.D == 2 ? 1 : 4))
+    ibm_interp_terms<C>(u, a.nshell, a.idx[l * 64 + slot], ibm_weight<C>(a.wts + l * 12, (uint32_t)slot), v);
+  for (int k = 0; k < 3; k++) v[k] = wave_sum_c(v[k]);
   if (slot != 0 || l >= a.nlag) return;
-  const C s[3] = {v0, v1, v2};
   C *Fk = static_cast<C *>(a.Fk);
   for (int k = 0; k < 3; k++) {
-    const C F = (C)a.Ud[l * 3 + k] - s[k];
-    Fk[l * 3 + k] = F;
-    a.Fsum[l * 3 + k] = (first ? 0.0 : a.Fsum[l * 3 + k]) + (double)F;
+    double sum = first ? 0.0 : a.Fsum[l * 3 + k];
+    Fk[l * 3 + k] = ibm_point_force<C>((C)a.Ud[l * 3 + k], v[k], &sum);
+    a.Fsum[l * 3 + k] = sum;
   }
 }
 
-// Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.  Sixteen
-// lanes per shell cell share its (point, slot) list, lane k taking entries
-// k, k+16, ...; the lane partials are then summed in a fixed tree order.
-constexpr int kSpreadLanes = 16;
-constexpr int kSpreadCellsPerBlock = 256 / kSpreadLanes;
+// Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.
+// kSpreadLanes lanes per shell cell share its (point, slot) list, lane k
+// taking entries k, k + kSpreadLanes, ...; the lane partials are then summed
+// in a fixed tree order.
+
+// One (point, slot) entry of a shell cell's list: f += F_l delta dV_l.
+template <typename C>
+__device__ inline void ibm_spread_term(const C *Fk, uint32_t l, C wt, C dv, C f[3]) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; k++) f[k] = f[k] + Fk[(uint64_t)l * 3 + k] * wt * dv;
+}
+
+// Fixed-order sum over the lanes of a shell cell; lane 0 holds it.
+template <typename C>
+__device__ inline void ibm_spread_reduce(C f[3]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int off = kSpreadLanes / 2; off > 0; off >>= 1)
+    for (int k = 0; k < 3; k++) f[k] = f[k] + __shfl_down(f[k], off, kSpreadLanes);
+}
+
+template <typename C>
+__device__ inline C ibm_add(C x, C y) {
+#pragma clang fp contract(off)
+  return x + y;
+}
 
 template <typename C>
 __device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
@@ -134,22 +180,17 @@ __device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
     const uint32_t e1 = a.rowptr[s + 1];
     for (uint32_t e = a.rowptr[s] + lane; e < e1; e += kSpreadLanes) {
       const uint32_t v = a.ent[e];
-      const uint32_t l = v >> 6, slot = v & 63u;
-      const double *w = a.wts + (uint64_t)l * 12;
-      const C wt = (C)((w[slot & 3u] * w[4 + ((slot >> 2) & 3u)]) * w[8 + (slot >> 4)]);
-      const C dv = (C)a.dV[l];
-      for (int k = 0; k < 3; k++) f[k] += Fk[(uint64_t)l * 3 + k] * wt * dv;
+      const uint32_t l = v >> 6;
+      ibm_spread_term<C>(Fk, l, ibm_weight<C>(a.wts + (uint64_t)l * 12, v & 63u), (C)a.dV[l], f);
     }
   }
-#pragma unroll
-  for (int off = kSpreadLanes / 2; off > 0; off >>= 1)
-    for (int k = 0; k < 3; k++) f[k] += __shfl_down(f[k], off, kSpreadLanes);
+  ibm_spread_reduce<C>(f);
   if (lane != 0 || s >= a.nshell) return;
   C *u = static_cast<C *>(a.ushell);
   C *fs = static_cast<C *>(a.fshell);
   for (int k = 0; k < 3; k++) {
-    u[k * a.nshell + s] += f[k];
-    fs[k * a.nshell + s] += f[k];
+    u[k * a.nshell + s] = ibm_add<C>(u[k * a.nshell + s], f[k]);
+    fs[k * a.nshell + s] = ibm_add<C>(fs[k * a.nshell + s], f[k]);
   }
   if (last) {
     C *fb = static_cast<C *>(a.fibm);

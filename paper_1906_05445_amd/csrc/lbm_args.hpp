@@ -96,6 +96,11 @@ struct SweepLinkArgs {
   ChunkSumArgs cs;
 };
 
+// IBM spreading: lanes per shell cell (each takes every kSpreadLanes-th entry
+// of the cell's list) and shell cells per 256-thread block or batch unit.
+constexpr int kSpreadLanes = 16;
+constexpr int kSpreadCellsPerBlock = 256 / kSpreadLanes;
+
 struct IbmArgs {
   Box3 b;
   uint32_t N;
