@@ -29,7 +29,7 @@ _SO = os.path.join(_HERE, "liblbm_oracle.so")
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 COLLISIONS = {"BGK": 0, "MRT": 1}
-METHODS = {"BB": 0, "LINEAR": 1, "QUADRATIC": 2, "IBM": 3}
+METHODS = {"BB": 0, "LINEAR": 1, "QUADRATIC": 2, "IBM": 3, "YU": 4, "ZHAO_YONG": 5}
 KINDS = {"sphere": 0, "cylinder": 1, "plane": 2}
 
 
@@ -98,6 +98,8 @@ def lib():
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 7
         L.orc_ibb_value.restype = ctypes.c_double
+        L.orc_zhao_yong_value.argtypes = [ctypes.c_double] * 4
+        L.orc_zhao_yong_value.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -106,13 +108,18 @@ def _p(a, t=_d):
     return a.ctypes.data_as(t)
 
 
+def zhao_yong_value(q, fi_post, fb_pre, B):
+    """Unknown population of one boundary link by Zhao & Yong's scheme, Eq. 16."""
+    return lib().orc_zhao_yong_value(float(q), float(fi_post), float(fb_pre), float(B))
+
+
 def phi(r: float) -> float:
     """Peskin's 4-point delta factor, Eq. 6."""
     return lib().orc_phi(float(r))
 
 
 def ibb_value(method, q, ff_ok, fff_ok, fb_f, fb_ff, fb_fff, fs_f, fi_ff_new, fi_fff_new, B):
-    """Unknown population of one boundary link (Eq. 10, Eq. 11, linear Bouzidi)."""
+    """Unknown population of one boundary link (Eq. 10, Eq. 11, Eq. 12-14, linear Bouzidi)."""
     return lib().orc_ibb_value(METHODS[method] if isinstance(method, str) else int(method), float(q),
                                int(ff_ok), int(fff_ok), float(fb_f), float(fb_ff), float(fb_fff),
                                float(fs_f), float(fi_ff_new), float(fi_fff_new), float(B))

@@ -21,9 +21,10 @@
  *      second-order (Guo) mesoscopic forcing named in Sec. 2.1;
  *   5. streaming to the neighbour along e_i (periodic box);
  *   6. IBB only: the unknown populations of every boundary link by halfway
- *      bounce-back (Eq. 10), linear Bouzidi, or quadratic Bouzidi (Eq. 11),
- *      then the force and torque on each solid by the Galilean-invariant
- *      momentum exchange method, Eq. 17;
+ *      bounce-back (Eq. 10), linear Bouzidi, quadratic Bouzidi (Eq. 11), Yu's
+ *      unified scheme (Eq. 12-14) or Zhao & Yong's single-node scheme
+ *      (Eq. 16), then the force and torque on each solid by the
+ *      Galilean-invariant momentum exchange method, Eq. 17;
  *   7. moving IBB solids only: advance the solid, reclassify, refill the
  *      newly uncovered nodes and rebuild the boundary links (Sec. 3.2).
  *
@@ -90,7 +91,7 @@ static double weight_of(int D, const int e[3]) {
 /* Solids                                                                    */
 /* ------------------------------------------------------------------------ */
 enum { K_SPHERE = 0, K_CYLINDER = 1, K_PLANE = 2 };
-enum { M_BB = 0, M_LINEAR = 1, M_QUADRATIC = 2, M_IBM = 3 };
+enum { M_BB = 0, M_LINEAR = 1, M_QUADRATIC = 2, M_IBM = 3, M_YU = 4, M_ZHAO_YONG = 5 };
 
 typedef struct {
   int kind, inverted;
@@ -471,13 +472,14 @@ static void lever(const orc *o, const solid_t *s, double px, double py, double p
 /*                         f*_i(x_f, t) and f*_i(x_ff, t)                    */
 /*   B                   : wall term 2 rho0 w_i e_i.u_w / c_s^2 of Eq. 10    */
 /* Halfway bounce-back, Eq. 10.  Quadratic Bouzidi, Eq. 11a (q < 1/2) and    */
-/* Eq. 11b (q >= 1/2).  Linear Bouzidi (named in Sec. 3.3, not printed):     */
+/* Eq. 11b (q >= 1/2).  Yu's unified scheme, Eq. 12-14 (any q).              */
+/* Linear Bouzidi (named in Sec. 3.3, not printed):                         */
 /* the same construction with two-point Lagrange interpolation,             */
 /*   q < 1/2 : 2q f*_ibar(x_f) + (1-2q) f*_ibar(x_ff) + B                    */
 /*   q >= 1/2: [f*_ibar(x_f) + B]/(2q) + (2q-1)/(2q) f*_i(x_f)               */
 /* Where the extra nodes are not fluid (narrow gaps) the scheme degrades:    */
-/* quadratic -> linear -> halfway bounce-back (Sec. 2.2: "Eq. (10) has to be */
-/* used instead").                                                           */
+/* quadratic or Yu -> linear -> halfway bounce-back (Sec. 2.2: Eq. 10 takes  */
+/* over where the interpolation nodes are missing).                          */
 /* ------------------------------------------------------------------------ */
 double orc_ibb_value(int method, double q, int ff_ok, int fff_ok, double fb_f, double fb_ff,
                      double fb_fff, double fi_f, double fi_ff, double fi_fff, double B) {
@@ -488,7 +490,23 @@ double orc_ibb_value(int method, double q, int ff_ok, int fff_ok, double fb_f, d
     return (fb_f + B) / (q * (2.0 * q + 1.0)) + ((2.0 * q - 1.0) / q) * fi_ff -
            ((2.0 * q - 1.0) / (1.0 + 2.0 * q)) * fi_fff;
   }
-  if (method == M_QUADRATIC || method == M_LINEAR) {
+  if (method == M_YU && ff_ok && fff_ok) {
+    /* Yu's three steps, Eq. 12-14, taken in turn:
+     * (12) the population that reaches the wall point after one step starts
+     *      1 - q from x_f towards x_ff; quadratic interpolation there from
+     *      f*_ibar at x_f, x_ff, x_fff;
+     * (13) it bounces back at the wall with the wall term B;
+     * (14) f_i(x_f, t+1) by quadratic interpolation at x_f from the wall
+     *      value (at -q along e_i) and f_i(x_ff), f_i(x_fff) at t+1.
+     * (Eq. 15 merges the three steps; as printed its x_ff coefficient,
+     * 2(1-q)/(1+q), does not follow from Eq. 12-14, which give 2(1-q)/(2+q).) */
+    double fw_in = 0.5 * q * (q + 1.0) * fb_f + (1.0 + q) * (1.0 - q) * fb_ff -
+                   0.5 * q * (1.0 - q) * fb_fff;
+    double fw_out = fw_in + B;
+    return 2.0 / ((1.0 + q) * (2.0 + q)) * fw_out + (2.0 * q / (1.0 + q)) * fi_ff -
+           (q / (2.0 + q)) * fi_fff;
+  }
+  if (method == M_QUADRATIC || method == M_YU || method == M_LINEAR) {
     if (q < 0.5) {
       if (ff_ok) return 2.0 * q * fb_f + (1.0 - 2.0 * q) * fb_ff + B;
       return fb_f + B;
@@ -496,6 +514,14 @@ double orc_ibb_value(int method, double q, int ff_ok, int fff_ok, double fb_f, d
     return (fb_f + B) / (2.0 * q) + ((2.0 * q - 1.0) / (2.0 * q)) * fi_f;
   }
   return fb_f + B;
+}
+
+/* Zhao & Yong's single-node scheme, Eq. 16: the unknown f_i(x_f, t+1) from
+ * the post-collision f*_i(x_f, t) leaving the wall, the pre-collision
+ * f_ibar(x_f, t) heading to it, and the wall term B scaled by 1/(1 + 2q).
+ * Only x_f is read, so there is no fallback for narrow gaps. */
+double orc_zhao_yong_value(double q, double fi_post, double fb_pre, double B) {
+  return (2.0 * q / (1.0 + 2.0 * q)) * fi_post + (1.0 / (1.0 + 2.0 * q)) * fb_pre + B / (1.0 + 2.0 * q);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -932,7 +958,7 @@ static void one_step(orc *o) {
       if (!o->excl[m]) o->fnew[(long)i * N + m] = o->fpost[(long)i * N + n];
     }
   }
-  /* interpolated bounce-back and momentum exchange (Eq. 10, 11, 17) */
+  /* interpolated bounce-back and momentum exchange (Eq. 10, 11, 12-14, 16, 17) */
   acc_t *lacc = (acc_t *)calloc(6 * (o->nsolid > 0 ? o->nsolid : 1), sizeof(acc_t));
   for (long l = 0; l < o->nlink; l++) {
     const link_t *lk = &o->links[l];
@@ -958,8 +984,11 @@ static void one_step(orc *o) {
     double fs_ff = lk->ff_ok ? o->fpost[(long)i * N + ff] : 0.0;      /* f*_i(x_ff)     */
     /* Eq. 11b uses f_i(x_ff, t+1) and f_i(x_fff, t+1); with x_ff, x_fff fluid
      * both are streamed values, f*_i(x_f, t) and f*_i(x_ff, t). */
-    double fnew = orc_ibb_value(o->method, lk->q, lk->ff_ok, lk->fff_ok, fb_f, fb_ff, fb_fff, fs_f,
-                                fs_f, fs_ff, B);
+    double fnew;
+    if (o->method == M_ZHAO_YONG)  /* f_ibar(x_f, t) before the collision: o->f until step 7 */
+      fnew = orc_zhao_yong_value(lk->q, fs_f, o->f[(long)ib * N + n], B);
+    else
+      fnew = orc_ibb_value(o->method, lk->q, lk->ff_ok, lk->fff_ok, fb_f, fb_ff, fb_fff, fs_f, fs_f, fs_ff, B);
     o->fnew[(long)i * N + n] = fnew;
     /* Eq. 17: F dt = sum [f*_ibar (e_ibar - u_w) - f_i(t+1) (e_i - u_w)].  With
      * f = w + h and w_ibar = w_i the rest-state part is w_i (e_ibar - e_i)

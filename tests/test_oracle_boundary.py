@@ -3,6 +3,12 @@
 * IBB formulas (Eq. 10, Eq. 11 and the linear variant): at q = 1/2 every
   scheme reduces bit-exactly to halfway bounce-back; each scheme is Lagrange
   interpolation, so it reproduces polynomials of its degree exactly;
+* Yu's unified scheme (Eq. 12-14): two quadratic interpolations around a
+  bounce at the wall point, so it reproduces a quadratic profile across the
+  wall exactly; the merged form Eq. 15 as printed does not (its weights do
+  not sum to one), the one derived from Eq. 12-14 does;
+* Zhao & Yong's single-node scheme (Eq. 16): weights summing to one, and the
+  pair (f_i, f_ibar) of a fluid moving with the wall is a fixed point;
 * Peskin's 4-point delta (Eq. 6): partition of unity, zero first moment (the
   property App. B relies on), sum of squares 3/8, continuity, phi(0) = 1/2;
 * interpolation (Eq. 5) and spreading (Eq. 8): exact for constant and linear
@@ -81,6 +87,66 @@ def test_narrow_gap_fallbacks():
     q = 0.8
     a = oracle.ibb_value("LINEAR", q, 0, 0, *vals[:3], vals[3], vals[4], vals[5], 1e-4)
     assert abs(a - ((vals[0] + 1e-4) / (2 * q) + (2 * q - 1) / (2 * q) * vals[3])) < 1e-16
+
+
+@pytest.mark.parametrize("k", range(1, 17))
+def test_yu_reproduces_quadratic_profiles(k):
+    """Along the link, s = 0 at x_f, 1 at x_ff, 2 at x_fff, -q at the wall.
+    Post-collision f*_ibar follows a quadratic p(s); the populations leaving the
+    wall follow a quadratic r(s) at t+1, bounced at the wall: r(-q) equals
+    p(1 - q) (the value that reaches the wall in one step) plus the wall term.
+    The scheme must return r(0)."""
+    q = k / 16.0
+    rng = np.random.default_rng(300 + k)
+    for _ in range(20):
+        b0, b1, b2, c1, c2 = rng.standard_normal(5)
+        B = 1e-3 * rng.standard_normal()
+        r = lambda s: b0 + b1 * s + b2 * s * s
+        c0 = r(-q) - B - c1 * (1.0 - q) - c2 * (1.0 - q) ** 2
+        p = lambda s: c0 + c1 * s + c2 * s * s
+        got = oracle.ibb_value("YU", q, 1, 1, p(0), p(1), p(2), 0.0, r(1), r(2), B)
+        assert abs(got - r(0)) < 2e-13 * max(1.0, abs(r(0))), (q, got, r(0))
+
+
+def test_yu_merged_form_coefficient():
+    """Eq. 15 merges Eq. 12-14.  The weights of a consistent scheme sum to one
+    (a uniform field at rest is reproduced); with the x_ff coefficient as printed,
+    2(1-q)/(1+q), they do not, with 2(1-q)/(2+q), which Eq. 12-14 give, they do.
+    The oracle takes the three steps and reproduces uniform fields."""
+    for k in range(1, 17):
+        q = Fraction(k, 16)
+        rest = -(1 - q) * q / ((1 + q) * (2 + q)) + 2 * q / (1 + q) - q / (2 + q) + q / (2 + q)
+        assert rest + 2 * (1 - q) / (2 + q) == 1
+        if q < 1:
+            assert rest + 2 * (1 - q) / (1 + q) != 1
+        c = 0.137
+        got = oracle.ibb_value("YU", float(q), 1, 1, c, c, c, 0.0, c, c, 0.0)
+        assert abs(got - c) < 1e-15
+
+
+def test_yu_narrow_gap_falls_back_to_linear():
+    vals = (0.11, 0.13, 0.17, 0.19, 0.23, 0.29)
+    for q in (0.3, 0.8):
+        for ff, fff in ((1, 0), (0, 0), (0, 1)):
+            assert oracle.ibb_value("YU", q, ff, fff, *vals[:3], vals[3], vals[4], vals[5], 1e-4) == \
+                oracle.ibb_value("LINEAR", q, ff, fff, *vals[:3], vals[3], vals[4], vals[5], 1e-4)
+
+
+def test_zhao_yong_weights_and_moving_wall_fixed_point():
+    rng = np.random.default_rng(33)
+    for _ in range(500):
+        q = rng.uniform(1e-3, 1.0)
+        c = rng.uniform(-0.3, 0.3)
+        # uniform populations, wall at rest: returned unchanged
+        assert abs(oracle.zhao_yong_value(q, c, c, 0.0) - c) < 1e-16
+        # fluid moving with the wall: f_i - f_ibar = 2 w_i e_i.u_w / c_s^2 (the
+        # wall term B of Eq. 10) for the equilibrium, and f_i(t+1) = f_i
+        B = rng.uniform(-1e-2, 1e-2)
+        assert abs(oracle.zhao_yong_value(q, c + B, c, B) - (c + B)) < 1e-16
+    # single node: x_ff and x_fff never enter (the oracle's signature has no slot for them),
+    # and the weight of the outgoing post-collision population grows with q
+    assert oracle.zhao_yong_value(0.25, 1.0, 0.0, 0.0) == pytest.approx(1.0 / 3.0, abs=1e-16)
+    assert oracle.zhao_yong_value(1.0, 1.0, 0.0, 0.0) == pytest.approx(2.0 / 3.0, abs=1e-16)
 
 
 # ----------------------------------------------------------------------------
