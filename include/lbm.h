@@ -69,7 +69,21 @@ typedef enum { LBM_BGK = 0, LBM_MRT = 1 } lbm_collision;
  * the rest state; F64 computes in FP64, F32_DEV and F16_DEV decode to FP32
  * and compute in FP32 (force and torque are always accumulated in FP64). */
 typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2 } lbm_storage;
-typedef enum { LBM_BB = 0, LBM_IBB_LINEAR = 1, LBM_IBB_QUADRATIC = 2, LBM_IBM = 3 } lbm_boundary;
+/* No-slip treatment (Sec. 2.1, 2.2): halfway bounce-back (Eq. 10), linear
+ * Bouzidi (two-point form of Eq. 11), quadratic Bouzidi (Eq. 11), direct-
+ * forcing IBM (Eq. 5-9), Yu's unified scheme (Eq. 12-14; the merged Eq. 15
+ * with its x_ff weight read as 2(1-q)/(2+q), as Eq. 12-14 give), Zhao &
+ * Yong's single-node scheme (Eq. 16).  Quadratic and Yu fall back to linear
+ * where x_ff or x_fff is not fluid, linear (q < 1/2) to Eq. 10 where x_ff is
+ * not; Zhao-Yong reads x_f only. */
+typedef enum {
+  LBM_BB = 0,
+  LBM_IBB_LINEAR = 1,
+  LBM_IBB_QUADRATIC = 2,
+  LBM_IBM = 3,
+  LBM_IBB_YU = 4,
+  LBM_IBB_ZHAO_YONG = 5
+} lbm_boundary;
 typedef enum { LBM_SPHERE = 0, LBM_CYLINDER = 1, LBM_PLANE = 2 } lbm_solid_kind;
 
 typedef struct lbm_ctx lbm_ctx;

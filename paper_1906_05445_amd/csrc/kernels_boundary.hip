@@ -398,8 +398,13 @@ __global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
 
 // One wavefront per chunk of kLinkChunk links of one solid; each wave writes
 // the chunk's force/torque partial (summed per solid in chunk order later).
+// P: post-collision array of step t (receives the ghost values); pre: the
+// array that step's sweep pulled from, where h_ibar(x_f, t) before the
+// collision sits at x_ff (Zhao-Yong only; a fluid value, or the ghost value
+// the previous step left there when x_ff is solid).
 template <int Q, typename S>
-__device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, uint32_t bx, int s) {
+__device__ inline void ibb_body(S *__restrict__ P, const S *__restrict__ pre, const IbbArgs &a, int64_t t,
+                                uint32_t bx, int s) {
   const SolidLinks sl = a.sl[s];
   const int lane = threadIdx.x;
   const bool active = bx < sl.nchunks && (uint64_t)sl.chunk_base + bx < a.max_partials;
@@ -426,7 +431,8 @@ __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, 
       const C hb_fff = fffok ? Store<S>::ld(P + pidx<Q>(ib, g.nfff)) : C(0);
       const C hs_f = Store<S>::ld(P + pidx<Q>(i, n));
       const C hs_ff = ffok ? Store<S>::ld(P + pidx<Q>(i, g.nff)) : C(0);
-      const S v = (S)link_value<C>(k, (C)g.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff);
+      const C hpre = k.kind == LK_ZY ? Store<S>::ld(pre + pidx<Q>(ib, g.nff)) : C(0);
+      const S v = (S)link_value<C>(k, link_wall<C>(k, g.B), hb_f, hb_ff, hb_fff, hs_f, hs_ff, hpre);
       P[pidx<Q>(i, g.nb)] = v;
       link_ft((double)(C)v, (double)hb_f, g.a, g.b, g.d, g.r, acc);
     }
@@ -437,8 +443,8 @@ __device__ inline void ibb_body(S *__restrict__ P, const IbbArgs &a, int64_t t, 
   }
 }
 template <int Q, typename S>
-__global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, IbbArgs a) {
-  ibb_body<Q, S>(P, a, a.g.t, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, const S *__restrict__ pre, IbbArgs a) {
+  ibb_body<Q, S>(P, pre, a, a.g.t, blockIdx.x, blockIdx.y);
 }
 
 // Per-solid force/torque: one wavefront per solid sums that solid's chunk
@@ -525,7 +531,8 @@ __global__ __launch_bounds__(64) void k_link_table(LinkArgs a, const uint32_t *c
   r.k1 = k.k1;
   r.k2 = k.k2;
   r.k3 = k.k3;
-  r.B = (C)g.B;
+  r.k4 = k.k4;
+  r.B = link_wall<C>(k, g.B);
   static_cast<LinkRec<C> *>(rec_)[pos] = r;
   for (int j = 0; j < 3; j++) {
     fc[(uint64_t)j * stride + l] = g.a[j];
@@ -543,6 +550,9 @@ __device__ inline int64_t slot_time(const BatchSlot *slots, int m, int64_t k) { 
 __device__ inline void *slot_post(const BatchSlot *slots, int m, int64_t k) {
   return SLOT(m, P[(SLOT(m, cur0) ^ (int)(k & 1)) ^ 1]);
 }
+__device__ inline const void *slot_pre(const BatchSlot *slots, int m, int64_t k) {
+  return SLOT(m, P[SLOT(m, cur0) ^ (int)(k & 1)]);
+}
 
 // bounce-back on the post-collision array of this step; unit = (solid, chunk)
 template <int Q, typename S>
@@ -553,7 +563,8 @@ __global__ __launch_bounds__(64) void k_ibb_batch(const BatchSlot *__restrict__ 
     const uint32_t per = (uint32_t)SLOT(m, k5_chunks);
     const int s = (int)(u / per);
     const IbbArgs a = SLOT(m, ib);
-    ibb_body<Q, S>(static_cast<S *>(slot_post(slots, m, k)), a, slot_time(slots, m, k), u - (uint32_t)s * per, s);
+    ibb_body<Q, S>(static_cast<S *>(slot_post(slots, m, k)), static_cast<const S *>(slot_pre(slots, m, k)), a,
+                   slot_time(slots, m, k), u - (uint32_t)s * per, s);
   });
 }
 
@@ -845,14 +856,15 @@ void launch_link_emit(lbm_ctx *c, int64_t t) {
   else hipLaunchKernelGGL(k_link_emit<19>, grid, dim3(kBlock), 0, c->stream, a);
 }
 
-void launch_ibb(lbm_ctx *c, void *P, int64_t t) {
+void launch_ibb(lbm_ctx *c, void *P, const void *pre, int64_t t) {
   if (c->k5_chunks <= 0) return;
   IbbArgs a;
   fill_ibb_args(c, &a);
   a.g.t = t;
   a.partials = partials_of(c, t);
   const dim3 grid((uint32_t)c->k5_chunks, (uint32_t)c->nsolid);
-#define LBM_IBB(QQ, SS) hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(64), 0, c->stream, static_cast<SS *>(P), a)
+#define LBM_IBB(QQ, SS) \
+  hipLaunchKernelGGL((k_ibb<QQ, SS>), grid, dim3(64), 0, c->stream, static_cast<SS *>(P), static_cast<const SS *>(pre), a)
   if (c->Q == 9) {
     if (c->p.storage == LBM_F64) LBM_IBB(9, double);
     else if (c->p.storage == LBM_F32_DEV) LBM_IBB(9, float);
@@ -949,12 +961,13 @@ void launch_chunk_sum(lbm_ctx *c, int64_t t) {
 }
 
 // Builds the link lists by sweep segment of a context whose solids are all
-// fixed; without them (translating solids, IBM, capacity limits) the
-// bounce-back stays a kernel of its own after every sweep.
+// fixed; without them (translating solids, IBM, Zhao-Yong, capacity limits)
+// the bounce-back stays a kernel of its own after every sweep.
 hipError_t build_link_lists(lbm_ctx *c) {
   c->link_lists = false;
   c->link_stride = 0;
-  if (c->method == LBM_IBM || c->any_moving || c->nsolid <= 0 || c->nlinks <= 0 || c->k5_chunks <= 0)
+  if (c->method == LBM_IBM || c->method == LBM_IBB_ZHAO_YONG || c->any_moving || c->nsolid <= 0 ||
+      c->nlinks <= 0 || c->k5_chunks <= 0)
     return hipSuccess;
   const uint64_t stride = ((uint64_t)c->nlinks + 63) / 64 * 64;
   // the per-call link table must fit the staging region

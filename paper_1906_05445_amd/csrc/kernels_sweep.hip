@@ -209,12 +209,15 @@ __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la,
       const LinkRec<C> r = rec[p];
       const int kind = (int)(r.kind_dir & 255u), i = (int)(r.kind_dir >> 8), ib = opp(i);
       const C hb_f = Store<S>::ld(A + pidx<Q>(ib, r.n));
-      const C hb_ff = (kind == LK_Q2_NEAR || kind == LK_Q1_NEAR) ? Store<S>::ld(A + pidx<Q>(ib, r.nff)) : C(0);
-      const C hb_fff = kind == LK_Q2_NEAR ? Store<S>::ld(A + pidx<Q>(ib, r.nfff)) : C(0);
-      const C hs_f = (kind == LK_Q2_FAR || kind == LK_Q1_FAR) ? Store<S>::ld(A + pidx<Q>(i, r.n)) : C(0);
-      const C hs_ff = kind == LK_Q2_FAR ? Store<S>::ld(A + pidx<Q>(i, r.nff)) : C(0);
-      const LinkCoef<C> k{kind, r.k1, r.k2, r.k3};
-      const S v = (S)link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff);
+      const C hb_ff =
+          (kind == LK_Q2_NEAR || kind == LK_Q1_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, r.nff)) : C(0);
+      const C hb_fff = (kind == LK_Q2_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, r.nfff)) : C(0);
+      const C hs_f =
+          (kind == LK_Q2_FAR || kind == LK_Q1_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, r.n)) : C(0);
+      const C hs_ff = (kind == LK_Q2_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, r.nff)) : C(0);
+      const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
+      // (no Zhao-Yong links here: the table never holds them)
+      const S v = (S)link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff, C(0));
       dst[pidx<Q>(i, r.nb)] = v;
       io[r.l] = (C)v;
       io[la.stride + r.l] = hb_f;

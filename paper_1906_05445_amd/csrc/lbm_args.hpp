@@ -45,7 +45,7 @@ struct IbbArgs {
   const SolidLinks *sl;
   double *partials;  // [chunk][6]
   uint64_t max_links, max_partials;
-  int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC
+  int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC, LBM_IBB_YU, LBM_IBB_ZHAO_YONG
 };
 
 // Per-solid IBM force and torque of one step (Sec. 3.1, App. B).

@@ -1,12 +1,14 @@
 // lbm_ibb.hpp -- interpolated bounce-back of one boundary link and its
-// momentum-exchange force/torque terms (Sec. 2.2: Eq. 10, Eq. 11; Eq. 17).
+// momentum-exchange force/torque terms (Sec. 2.2: Eq. 10, Eq. 11, Eq. 12-14,
+// Eq. 16; Eq. 17).
 //
 // A link is evaluated in three parts: its geometry (wall point, lever arm,
 // wall velocity, neighbours), the formula and coefficients that the method,
 // q and the fluid neighbours select, and the arithmetic on the populations.
 // The bounce-back kernel runs all three every step; for fixed solids the
 // first two are tabulated once per lbm_step call and the sweep runs only the
-// third.  Both routes call these same functions, compiled without
+// third (except for Zhao-Yong, whose pre-collision input lives in the array
+// the next sweep overwrites: its links stay with the kernel).  Both routes call these same functions, compiled without
 // floating-point contraction, so they produce the same bits.
 #pragma once
 
@@ -14,22 +16,46 @@
 
 namespace lbm {
 
-// Formula of a link: Eq. 11a / 11b (quadratic, x_ff and x_fff fluid), the
-// linear interpolations for q < 1/2 (x_ff fluid) and q >= 1/2, and plain
-// bounce-back (Eq. 10; also the linear scheme for q < 1/2 without x_ff).
-enum { LK_PLAIN = 0, LK_Q2_NEAR = 1, LK_Q2_FAR = 2, LK_Q1_NEAR = 3, LK_Q1_FAR = 4 };
+// Formula of a link: Eq. 11a / 11b (quadratic, x_ff and x_fff fluid), Yu's
+// unified scheme (Eq. 12-14, x_ff and x_fff fluid), the linear interpolations
+// for q < 1/2 (x_ff fluid) and q >= 1/2, plain bounce-back (Eq. 10; also the
+// linear scheme for q < 1/2 without x_ff), and Zhao & Yong's single-node
+// scheme (Eq. 16).
+enum { LK_PLAIN = 0, LK_Q2_NEAR = 1, LK_Q2_FAR = 2, LK_Q1_NEAR = 3, LK_Q1_FAR = 4, LK_YU = 5, LK_ZY = 6 };
 
+// k1..k4 weigh the populations of the formula; kB scales the wall term B of
+// Eq. 10 (1 except for Yu and Zhao-Yong).
 template <typename C>
 struct LinkCoef {
   int kind;
-  C k1, k2, k3;
+  C k1, k2, k3, k4;
+  double kB;
 };
 
 template <typename C>
 __device__ inline LinkCoef<C> link_coef(int method, double q, bool ffok, bool fffok) {
 #pragma clang fp contract(off)
-  LinkCoef<C> k{LK_PLAIN, C(0), C(0), C(0)};
-  if (method == LBM_IBB_QUADRATIC && ffok && fffok) {
+  LinkCoef<C> k{LK_PLAIN, C(0), C(0), C(0), C(0), 1.0};
+  if (method == LBM_IBB_ZHAO_YONG) {
+    // Eq. 16: only x_f is read, whatever its neighbours are
+    k.kind = LK_ZY;
+    k.k1 = (C)(2.0 * q / (1.0 + 2.0 * q));
+    k.k2 = (C)(1.0 / (1.0 + 2.0 * q));
+    k.kB = 1.0 / (1.0 + 2.0 * q);
+  } else if (method == LBM_IBB_YU && ffok && fffok) {
+    // Eq. 12-14 in one formula: interpolate f*_ibar at the point 1 - q from
+    // x_f (weights q(1+q)/2, (1+q)(1-q), -q(1-q)/2), bounce at the wall (+B),
+    // interpolate f_i at x_f from the wall point (-q), x_ff and x_fff (weights
+    // 2/((1+q)(2+q)), 2q/(1+q), -q/(2+q)).  The products give q/(2+q),
+    // 2(1-q)/(2+q), -q(1-q)/((1+q)(2+q)) on f*_ibar; the weight of f_i(x_fff)
+    // is -q/(2+q) as well, so k1 serves both.
+    k.kind = LK_YU;
+    k.k1 = (C)(q / (2.0 + q));
+    k.k2 = (C)(2.0 * (1.0 - q) / (2.0 + q));
+    k.k3 = (C)(q * (1.0 - q) / ((1.0 + q) * (2.0 + q)));
+    k.k4 = (C)(2.0 * q / (1.0 + q));
+    k.kB = 2.0 / ((1.0 + q) * (2.0 + q));
+  } else if (method == LBM_IBB_QUADRATIC && ffok && fffok) {
     if (q < 0.5) {
       k.kind = LK_Q2_NEAR;
       k.k1 = (C)(q * (2.0 * q + 1.0));
@@ -41,7 +67,7 @@ __device__ inline LinkCoef<C> link_coef(int method, double q, bool ffok, bool ff
       k.k2 = (C)((2.0 * q - 1.0) / q);
       k.k3 = (C)((2.0 * q - 1.0) / (1.0 + 2.0 * q));
     }
-  } else if (method == LBM_IBB_QUADRATIC || method == LBM_IBB_LINEAR) {
+  } else if (method == LBM_IBB_QUADRATIC || method == LBM_IBB_YU || method == LBM_IBB_LINEAR) {
     if (q < 0.5) {
       if (ffok) {
         k.kind = LK_Q1_NEAR;
@@ -57,20 +83,31 @@ __device__ inline LinkCoef<C> link_coef(int method, double q, bool ffok, bool ff
   return k;
 }
 
+// The wall term as the formula uses it, kB * B, rounded once to the compute
+// type (for kB = 1 this is B itself).
+template <typename C>
+__device__ inline C link_wall(const LinkCoef<C> &k, double B) {
+#pragma clang fp contract(off)
+  return (C)(k.kB * B);
+}
+
 // Unknown deviation h_i(x_f, t+1).  hb_*: post-collision h_ibar at x_f, x_ff,
 // x_fff; hs_*: post-collision h_i at x_f, x_ff (= h_i at x_ff, x_fff after
-// streaming).  B: wall term 2 rho0 w_i e_i.u_w / c_s^2.  The coefficients of
-// every scheme sum to one, so the formulas hold for the deviations as written
-// for f.  Values a formula does not use may be anything.
+// streaming); hpre: h_ibar(x_f, t) before the collision (Zhao-Yong only).
+// Bw: the wall term from link_wall.  The coefficients of every scheme sum to
+// one, so the formulas hold for the deviations as written for f.  Values a
+// formula does not use may be anything.
 template <typename C>
-__device__ inline C link_value(const LinkCoef<C> &k, C B, C hb_f, C hb_ff, C hb_fff, C hs_f, C hs_ff) {
+__device__ inline C link_value(const LinkCoef<C> &k, C Bw, C hb_f, C hb_ff, C hb_fff, C hs_f, C hs_ff, C hpre) {
 #pragma clang fp contract(off)
   switch (k.kind) {
-    case LK_Q2_NEAR: return k.k1 * hb_f + k.k2 * hb_ff - k.k3 * hb_fff + B;  // Eq. 11a
-    case LK_Q2_FAR: return k.k1 * (hb_f + B) + k.k2 * hs_f - k.k3 * hs_ff;   // Eq. 11b
-    case LK_Q1_NEAR: return k.k1 * hb_f + k.k2 * hb_ff + B;
-    case LK_Q1_FAR: return (hb_f + B) / k.k1 + k.k2 * hs_f;
-    default: return hb_f + B;  // Eq. 10
+    case LK_Q2_NEAR: return k.k1 * hb_f + k.k2 * hb_ff - k.k3 * hb_fff + Bw;  // Eq. 11a
+    case LK_Q2_FAR: return k.k1 * (hb_f + Bw) + k.k2 * hs_f - k.k3 * hs_ff;   // Eq. 11b
+    case LK_Q1_NEAR: return k.k1 * hb_f + k.k2 * hb_ff + Bw;
+    case LK_Q1_FAR: return (hb_f + Bw) / k.k1 + k.k2 * hs_f;
+    case LK_YU: return k.k1 * hb_f + k.k2 * hb_ff - k.k3 * hb_fff + k.k4 * hs_f - k.k1 * hs_ff + Bw;  // Eq. 12-14
+    case LK_ZY: return k.k1 * hs_f + k.k2 * hpre + Bw;  // Eq. 16
+    default: return hb_f + Bw;  // Eq. 10
   }
 }
 
@@ -139,13 +176,14 @@ __device__ inline void link_ft(double hin, double hout, const double a[3], const
 
 // Tabulated part of a link of a fixed solid, as the sweep reads it (48 bytes
 // for FP32 and FP16 storage, 64 for FP64), stored in sweep-segment order.
+// B holds the scaled wall term (link_wall).
 template <typename C>
-struct LinkRec {
+struct alignas(16) LinkRec {
   C k1, k2, k3, B;
   uint32_t n, nb, nff, nfff;  // x_f, x_b, x_ff, x_fff
   uint32_t kind_dir;          // kind | i << 8
   uint32_t l;                 // link index (order of the force sums)
-  uint32_t pad[2];
+  C k4;
 };
 static_assert(sizeof(LinkRec<float>) == 48 && sizeof(LinkRec<double>) == 64, "link record size");
 

@@ -203,7 +203,7 @@ void launch_refill(lbm_ctx *c, int64_t t, void *post);
 void launch_link_count(lbm_ctx *c, int64_t t);
 void launch_link_scan(lbm_ctx *c);
 void launch_link_emit(lbm_ctx *c, int64_t t);
-void launch_ibb(lbm_ctx *c, void *Bpost, int64_t t);
+void launch_ibb(lbm_ctx *c, void *Bpost, const void *pre, int64_t t);
 FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t);
 void launch_ft_reduce(lbm_ctx *c, int64_t t);
 // single contexts alternate two chunk-partial buffers by step parity

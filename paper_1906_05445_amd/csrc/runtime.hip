@@ -410,7 +410,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   if (c) c->version++;
   if (!c) return LBM_EINVAL;
   if (n < 0 || n > c->L.max_solids || (n > 0 && !s)) return set_err(c, "solid count"), LBM_EINVAL;
-  if (method < LBM_BB || method > LBM_IBM) return set_err(c, "method"), LBM_EINVAL;
+  if (method < LBM_BB || method > LBM_IBB_ZHAO_YONG) return set_err(c, "method"), LBM_EINVAL;
   std::vector<DevSolid> ds((size_t)std::max(n, 1));
   bool moving = false;
   int32_t mbc = 0;
@@ -839,7 +839,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm ? c->t : -1);
     if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
     if (ibb) {
-      launch_ibb(c, B, c->t);
+      launch_ibb(c, B, A, c->t);
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
         launch_classify(c, c->t + 1, false);
@@ -862,7 +862,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       launch_chunk_sum(c, T - 1);
       launch_ft_reduce(c, T - 1);
     }
-    launch_ibb(c, c->state(), T);
+    launch_ibb(c, c->state(), c->other(), T);  // (no Zhao-Yong links on this route)
     launch_ft_reduce(c, T);
   }
   HIPCALL(hipGetLastError());

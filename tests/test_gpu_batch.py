@@ -39,6 +39,9 @@ def _specs():
         ("MRT", (26, 24, 22), 0.85, (1e-6, 0.0, 0.0), [], "QUADRATIC", None),
         ("MRT", (30, 28, 26), 0.8, (1.5e-6, 0.0, 0.0), [W.solid("sphere", (15.2, 13.9, 12.8), 4.9)], "QUADRATIC",
          np.array([0, 1.2, 1.4, 0, 1.1, 0, 1.1, 0, 1.1, 1.25, 1.3, 1.25, 1.3, 1.25, 1.25, 1.25, 1.5, 1.5, 1.5])),
+        ("MRT", (34, 31, 28), 0.8, (0.0, 0.0, 0.0),
+         [W.solid("sphere", (16.1, 15.3, 13.6), 5.8, velocity=(-0.015, 0.012, -0.009))], "ZHAO_YONG", None),
+        ("MRT", (29, 33, 27), 0.75, (1e-6, 0.0, 5e-7), [W.solid("sphere", (14.3, 16.2, 13.1), 5.4)], "YU", None),
     ]
 
 
@@ -147,7 +150,8 @@ def test_batch_admission_release_and_late_member(lbm):
     b.close()
 
 
-def test_batch_member_matches_oracle_fp64(lbm):
+@pytest.mark.parametrize("method", ["QUADRATIC", "ZHAO_YONG"])
+def test_batch_member_matches_oracle_fp64(lbm, method):
     """FP64 batch: a translating sphere member against the FP64 oracle (1e-12)."""
     from oracle import Oracle
 
@@ -157,9 +161,9 @@ def test_batch_member_matches_oracle_fp64(lbm):
     other = b.admit("MRT", "F64", (28, 26, 24), 0.8, g=(1e-6, 0.0, 0.0), max_solids=1)
     other.set_solids([W.solid("sphere", (14.0, 13.0, 12.0), 4.5)], "QUADRATIC")
     m = b.admit("MRT", "F64", shape, 0.8, max_solids=1)
-    m.set_solids(solids, "QUADRATIC")
+    m.set_solids(solids, method)
     orc = Oracle("D3Q19", "MRT", shape, 0.8)
-    orc.set_solids(solids, "QUADRATIC")
+    orc.set_solids(solids, method)
     for n in (13, 20, 27):
         b.step(n)
         orc.step(n)

@@ -53,6 +53,15 @@ CASES = {
                                       omega=(0, 0, 0.01 / 20.1))], "QUADRATIC", None),
     "d2q9_bgk_f32_quadratic": ("D2Q9", "BGK", "F32", (61, 47, 1), 0.8, (1e-6, 2e-7, 0.0),
                                [W.solid("cylinder", (30.4, 23.7, 0.0), 7.3)], "QUADRATIC", None),
+    # Yu's scheme (five populations per link) in the sweep and in the kernel, with gaps
+    "d3q19_mrt_f32_yu_gaps": ("D3Q19", "MRT", "F32", (31, 29, 27), 0.7, (2e-6, 0.0, 1e-6),
+                              [W.solid("sphere", (9.5, 10.2, 9.9), 5.5),
+                               W.solid("sphere", (21.6, 10.4, 9.3), 5.2),
+                               W.solid("cylinder", (0.0, 22.3, 16.6), 3.1, axis=(1, 0, 0))],
+                              "YU", None),
+    # Zhao & Yong's scheme stays with the bounce-back kernel after every sweep
+    "d3q19_mrt_f16_zhao_yong": ("D3Q19", "MRT", "F16", (33, 30, 26), 0.9, (1e-5, 0.0, 0.0),
+                                [W.solid("sphere", (16.2, 15.1, 12.8), 6.1)], "ZHAO_YONG", None),
 }
 
 

@@ -176,7 +176,7 @@ def test_periodic_sweep_fp64(lbm, lat, coll, shape, rates_kind):
 # ----------------------------------------------------------------------------
 # interpolated bounce-back
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("method", ["BB", "LINEAR", "QUADRATIC"])
+@pytest.mark.parametrize("method", ["BB", "LINEAR", "QUADRATIC", "YU", "ZHAO_YONG"])
 def test_ibb_sphere_fp64(lbm, method):
     shape = (37, 29, 23)
     g = (3e-6, 1e-6, -5e-7)
@@ -188,12 +188,13 @@ def test_ibb_sphere_fp64(lbm, method):
     _compare_forces(gpu, orc, g, 1e-12)
 
 
-def test_ibb_many_solids_narrow_gaps_fp64(lbm):
+@pytest.mark.parametrize("method", ["QUADRATIC", "YU", "ZHAO_YONG"])
+def test_ibb_many_solids_narrow_gaps_fp64(lbm, method):
     shape = (31, 29, 27)
     g = (2e-6, 0.0, 1e-6)
     solids = [W.solid("sphere", (9.5, 10.2, 9.9), 5.5), W.solid("sphere", (21.6, 10.4, 9.3), 5.2),
               W.solid("cylinder", (0.0, 22.3, 16.6), 3.1, axis=(1, 0, 0))]
-    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.7, g=g, solids=solids, method="QUADRATIC")
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.7, g=g, solids=solids, method=method)
     L = orc.links()
     assert (L["ff_ok"] == 0).sum() > 0 or (L["fff_ok"] == 0).sum() > 0  # fallbacks exercised
     gpu.step(30)
@@ -213,11 +214,12 @@ def test_cylinder_channel_2d_full_run(lbm):
     _compare_forces(gpu, orc, case.g, 1e-12)
 
 
-def test_rotating_wall_couette_fp64(lbm):
+@pytest.mark.parametrize("method", ["QUADRATIC", "YU", "ZHAO_YONG"])
+def test_rotating_wall_couette_fp64(lbm, method):
     n, R1, R2 = 46, 9.3, 20.1
     c = (23.31, 22.83, 0.0)
     solids = [W.solid("cylinder", c, R1), W.solid("cylinder", c, R2, inverted=True, omega=(0, 0, 0.01 / R2))]
-    gpu, orc = _pair(lbm, "D2Q9", "MRT", (n, n, 1), 1.0, solids=solids, method="QUADRATIC",
+    gpu, orc = _pair(lbm, "D2Q9", "MRT", (n, n, 1), 1.0, solids=solids, method=method,
                      rates=np.full(9, 1.0))
     gpu.step(300)
     orc.step(300)
@@ -225,11 +227,12 @@ def test_rotating_wall_couette_fp64(lbm):
     _compare_forces(gpu, orc, (1e-5, 0, 0), 1e-12)
 
 
-def test_translating_sphere_refill_fp64(lbm):
+@pytest.mark.parametrize("method", ["QUADRATIC", "YU", "ZHAO_YONG"])
+def test_translating_sphere_refill_fp64(lbm, method):
     """A sphere crossing grid lines: reclassification, refill, link rebuild each step."""
     shape = (30, 27, 25)
     solids = [W.solid("sphere", (14.2, 13.1, 12.4), 5.3, velocity=(0.07, -0.045, 0.03))]
-    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, solids=solids, method="QUADRATIC")
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, solids=solids, method=method)
     for _ in range(4):
         gpu.step(15)
         orc.step(15)
@@ -286,7 +289,7 @@ def test_library_mesh_matches_generator(lbm):
 # reduced precision against the FP64 oracle
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("storage", ["F32", "F16"])
-@pytest.mark.parametrize("method", ["QUADRATIC", "IBM"])
+@pytest.mark.parametrize("method", ["QUADRATIC", "IBM", "YU", "ZHAO_YONG"])
 def test_reduced_precision(lbm, storage, method):
     shape = (37, 29, 23)
     s = W.solid("sphere", (18.3, 14.1, 11.7), 6.6)
@@ -304,7 +307,8 @@ def test_reduced_precision(lbm, storage, method):
 # ----------------------------------------------------------------------------
 # full-size workload (128^3, the benchmark's launch configuration)
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("storage,method", [("F64", "QUADRATIC"), ("F32", "QUADRATIC"), ("F64", "IBM")])
+@pytest.mark.parametrize("storage,method", [("F64", "QUADRATIC"), ("F32", "QUADRATIC"), ("F64", "IBM"),
+                                            ("F64", "YU"), ("F64", "ZHAO_YONG"), ("F32", "ZHAO_YONG")])
 def test_full_size_sphere_128(lbm, storage, method):
     case = W.sphere_box(storage=storage, method=method)
     gpu, orc = _pair(lbm, case.lattice, case.collision, case.shape, case.tau, g=case.g, storage=storage,
