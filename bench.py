@@ -276,7 +276,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
     ap.add_argument("--cases", default="all",
-                    help="comma list of extras: single (the other single-lattice cases), copy, batch, precision, serving")
+                    help="comma list of extras: single (the other single-lattice cases), schemes (Yu and "
+                         "Zhao-Yong bounce-back; or one of its keys), copy, batch, precision, serving")
     ap.add_argument("--batch-steps", type=int, default=2000, help="steps of the 512-lattice batch (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="wall time of each serving window (0: skip)")
     ap.add_argument("--precision-steps", type=int, default=10000,
@@ -303,7 +304,7 @@ def main():
     extras = {}
     want = set()
     if not args.primary_only:
-        want = ({"single", "copy", "batch", "precision", "serving"} if args.cases == "all"
+        want = ({"single", "schemes", "copy", "batch", "precision", "serving"} if args.cases == "all"
                 else set(args.cases.split(",")))
     if "single" in want:
         k2 = max(K // 2, 100)
@@ -318,6 +319,20 @@ def main():
             extras[key]["steps"] = k
             print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s, "
                   f"policy {extras[key]['autotune'].get('policy')}",
+                  file=sys.stderr, flush=True)
+    # the other two bounce-back schemes the paper compares: Yu's (five populations per link)
+    # and Zhao & Yong's single-node scheme; the 256^3 pack has gaps of 2 lattice units
+    # where the multi-node schemes fall back
+    for key, (ctor, method) in [("sphere128_f32_yu", (W.sphere_box, "YU")),
+                                ("sphere128_f32_zhao_yong", (W.sphere_box, "ZHAO_YONG")),
+                                ("pack256_f32_yu", (W.sphere_pack, "YU")),
+                                ("pack256_f32_zhao_yong", (W.sphere_pack, "ZHAO_YONG"))]:
+        if "schemes" in want or key in want:
+            case = ctor(storage="F32", method=method)
+            k = max(K // 2, 100) if "256" not in key else max(K // 8, 50)
+            extras[key] = run_case(case, k, max(Wm // 4, 64), key, torch, lbm)
+            extras[key]["steps"] = k
+            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
                   file=sys.stderr, flush=True)
     if "copy" in want:
         extras["hbm_copy_GBps"] = copy_probe(torch, lbm)

@@ -961,13 +961,12 @@ void launch_chunk_sum(lbm_ctx *c, int64_t t) {
 }
 
 // Builds the link lists by sweep segment of a context whose solids are all
-// fixed; without them (translating solids, IBM, Zhao-Yong, capacity limits)
-// the bounce-back stays a kernel of its own after every sweep.
+// fixed; without them (translating solids, IBM, capacity limits) the
+// bounce-back stays a kernel of its own after every sweep.
 hipError_t build_link_lists(lbm_ctx *c) {
   c->link_lists = false;
   c->link_stride = 0;
-  if (c->method == LBM_IBM || c->method == LBM_IBB_ZHAO_YONG || c->any_moving || c->nsolid <= 0 ||
-      c->nlinks <= 0 || c->k5_chunks <= 0)
+  if (c->method == LBM_IBM || c->any_moving || c->nsolid <= 0 || c->nlinks <= 0 || c->k5_chunks <= 0)
     return hipSuccess;
   const uint64_t stride = ((uint64_t)c->nlinks + 63) / 64 * 64;
   // the per-call link table must fit the staging region

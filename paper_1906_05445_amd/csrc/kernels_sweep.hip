@@ -48,10 +48,11 @@ __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepA
 }
 
 // Relaxation of one cell (Eq. 1 or Eq. 3 with the forcing of Sec. 2.1) and
-// the store of its post-collision values.
-template <int Q, int COLL, typename S, int FLAGS, int NT, int IDX32>
+// the store of its post-collision values (KEEP: also to keep[0 .. Q-2] for
+// directions 1 .. Q-1, when keep is not null).
+template <int Q, int COLL, typename S, int FLAGS, int NT, int IDX32, bool KEEP = false>
 __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &a, uint32_t n, uint8_t fl,
-                                            const S (&r)[Q]) {
+                                            const S (&r)[Q], S *keep = nullptr) {
   using C = typename Store<S>::C;
   using L = Lat<Q>;
   C h[Q];
@@ -163,6 +164,12 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
     }
   }
 
+  // The relaxation is compiled with contraction allowed; an empty asm makes
+  // every post-collision value opaque, so that what follows (the store, and
+  // in one variant a copy to LDS) cannot change how the compiler fuses the
+  // arithmetic before it: every sweep variant rounds the same way.
+#pragma unroll
+  for (int i = 0; i < Q; i++) asm("" : "+v"(h[i]));
   // the block writes Q contiguous runs of kTile values per tile
   uint64_t base;
   if constexpr (IDX32 != 0) base = pidx32<Q>(0, n);
@@ -171,6 +178,7 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   for (int i = 0; i < Q; i++) {
     if (NT) Store<S>::st_nt(B + base + (uint64_t)i * kTile, h[i]);
     else Store<S>::st(B + base + (uint64_t)i * kTile, h[i]);
+    if (KEEP && i > 0 && keep) keep[i - 1] = (S)h[i];
   }
 }
 
@@ -240,9 +248,54 @@ __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la,
   }
 }
 
+// Zhao-Yong links of this wavefront's cells at the step this sweep computes
+// (Eq. 16 reads x_f only): once the wavefront's cells are relaxed, the lanes
+// take the links one each, read the post-collision h_i(x_f) and h_ibar(x_f)
+// from the cells' LDS rows (tab: Q-1 stored values per cell, as written to B)
+// and h_ibar(x_f) before the collision from A at x_ff (the value the cell
+// pulled; no one writes A during the sweep), and write the unknown into the
+// solid node's slot of B, which the next sweep pulls.  These are the values
+// the bounce-back kernel reads, so both give the same bits.
+template <int Q, typename S, int CPT>
+__device__ __forceinline__ void sweep_links_zy(const S *A, S *B, const SweepLinkArgs &la, const uint32_t (&first)[CPT],
+                                               const uint32_t (&cnt)[CPT], uint32_t total,
+                                               const S (*tab)[64 * (Q - 1)]) {
+  using C = typename Store<S>::C;
+  const int lane = threadIdx.x & 63;
+  const LinkRec<C> *rec = static_cast<const LinkRec<C> *>(la.rec);
+  C *io = static_cast<C *>(la.io);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint32_t b = 0; b < total; b += 64) {
+    const uint32_t j = b + lane;
+    if (j < total) {
+      int c = 0;
+      uint32_t p = first[0] + j;
+      if (CPT == 2 && j >= cnt[0]) {
+        c = 1;
+        p = first[CPT - 1] + (j - cnt[0]);
+      }
+      const LinkRec<C> r = rec[p];
+      const int kind = (int)(r.kind_dir & 255u), i = (int)(r.kind_dir >> 8), ib = opp(i);
+      const uint32_t o = r.n & 63u;
+      const C hs_f = (C)tab[c][o * (Q - 1) + (i - 1)];
+      const C hb_f = (C)tab[c][o * (Q - 1) + (ib - 1)];
+      const C hpre = Store<S>::ld(A + pidx<Q>(ib, r.nff));
+      const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
+      const S v = (S)link_value<C>(k, r.B, hb_f, C(0), C(0), hs_f, C(0), hpre);
+      B[pidx<Q>(i, r.nb)] = v;
+      io[r.l] = (C)v;
+      io[la.stride + r.l] = hb_f;
+    }
+  }
+}
+
 // One block sweeps sweep_cpt tiles (group blk): every thread pulls its cell
 // of each tile before relaxing any, so that half-precision storage keeps as
-// many bytes in flight per wavefront as single precision.
+// many bytes in flight per wavefront as single precision.  INL: 0 no link
+// evaluation, 1 the links of the previous step replace pulled values, 2 the
+// Zhao-Yong links of this step follow the relaxation.
 template <int Q, int COLL, typename S, int FLAGS, int NT, int INL, int IDX32 = 0>
 __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restrict__ B, const SweepArgs &a,
                                            const SweepLinkArgs *la, uint32_t blk) {
@@ -264,11 +317,9 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   for (int c = 0; c < CPT; c++) sweep_pull<Q, S, IDX32>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
 #pragma unroll
   for (int c = 0; c < CPT; c++) act[c] = act[c] && !(fl[c] & F_SOLID);  // nothing is stored for solid nodes
+  uint32_t first[CPT], cnt[CPT], total = 0;
   if constexpr (INL != 0) {
-    __shared__ S tab[kBlock / 64][CPT][64 * (Q - 1)];
-    __shared__ uint32_t msk[kBlock / 64][CPT][64];
     const int w = threadIdx.x >> 6;
-    uint32_t first[CPT], cnt[CPT], total = 0;
 #pragma unroll
     for (int c = 0; c < CPT; c++) {
       const uint32_t seg = __builtin_amdgcn_readfirstlane((blk * CPT + c) * (kBlock / 64) + (uint32_t)w);
@@ -278,11 +329,28 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
       cnt[c] = sg.count;
       total += sg.count;
     }
+  }
+  if constexpr (INL == 1) {
+    __shared__ S tab[kBlock / 64][CPT][64 * (Q - 1)];
+    __shared__ uint32_t msk[kBlock / 64][CPT][64];
+    const int w = threadIdx.x >> 6;
     if (total) sweep_links<Q, S, CPT>(A, *la, first, cnt, total, r, tab[w], msk[w]);
   }
+  if constexpr (INL == 2) {
+    // wavefronts with links keep every cell's stored values in LDS for them
+    __shared__ S ztab[kBlock / 64][CPT][64 * (Q - 1)];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int c = 0; c < CPT; c++)
-    if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT, IDX32>(B, a, n[c], fl[c], r[c]);
+    for (int c = 0; c < CPT; c++)
+      if (act[c])
+        sweep_relax<Q, COLL, S, FLAGS, NT, IDX32, true>(B, a, n[c], fl[c], r[c],
+                                                        total ? &ztab[w][c][lane * (Q - 1)] : nullptr);
+    if (total) sweep_links_zy<Q, S, CPT>(A, B, *la, first, cnt, total, ztab[w]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CPT; c++)
+      if (act[c]) sweep_relax<Q, COLL, S, FLAGS, NT, IDX32>(B, a, n[c], fl[c], r[c]);
+  }
 }
 
 // Waves per SIMD the sweep keeps when it also evaluates boundary links: the
@@ -383,7 +451,7 @@ void launch_tick(hipStream_t s, int64_t *step) { hipLaunchKernelGGL(k_tick, dim3
 
 template <typename S>
 static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, const SweepLinkArgs &la, int coll,
-                           bool flags, bool nt, bool inl, hipEvent_t e0, hipEvent_t e1) {
+                           bool flags, bool nt, int inl, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t tiles = (uint32_t)((c->N + kBlock - 1) / kBlock);
   const uint32_t grid =
       (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks + a.iblocks + (inl ? la.cblocks : 0u);
@@ -402,7 +470,10 @@ static void sweep_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &
   } while (0)
 #define LBM_SWEEP2(QQ, CC)                     \
   do {                                         \
-    if (inl) {                                 \
+    if (inl == 2) {                            \
+      if (nt) LBM_SWEEP(QQ, CC, 1, 1, 2);      \
+      else LBM_SWEEP(QQ, CC, 1, 0, 2);         \
+    } else if (inl) {                          \
       if (nt) LBM_SWEEP(QQ, CC, 1, 1, 1);      \
       else LBM_SWEEP(QQ, CC, 1, 0, 1);         \
     } else if (flags) {                        \
@@ -505,7 +576,9 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0,
     a.iblocks = (uint32_t)c->nsolid;
   }
   SweepLinkArgs la{};
-  const bool inl = link_t >= 0 && c->link_lists;
+  // Zhao-Yong links are evaluated after the relaxation of step link_t itself,
+  // the other schemes' links of step link_t when step link_t + 1 pulls them
+  const int inl = (link_t >= 0 && c->link_lists) ? (c->method == LBM_IBB_ZHAO_YONG ? 2 : 1) : 0;
   if (inl) {
     la.seg_link = c->at<SegLink>(c->L.seg_link);
     la.cell_list = c->at<uint32_t>(c->L.cell_list);

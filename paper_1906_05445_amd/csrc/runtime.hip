@@ -787,7 +787,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
 
   const bool ibb = c->method != LBM_IBM && c->nsolid > 0;
   const bool inl = ibb && !c->any_moving && c->link_lists;
-  if (inl && nsteps > 1) launch_link_table(c);
+  // Zhao-Yong (x_f only) is evaluated by the sweep of its own step, every step of
+  // the call; the other schemes by the sweep of the next step, steps 2..n
+  const bool zy = inl && c->method == LBM_IBB_ZHAO_YONG;
+  if (inl && (nsteps > 1 || (zy && nsteps > 0))) launch_link_table(c);
   bool span = false;  // a profiling span over the sweeps of this call is open
   for (int64_t k = 0; k < nsteps; k++) {
     void *A = c->state(), *B = c->other();
@@ -818,6 +821,17 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (!span && tuned && c->prof_every > 0 && c->prof_count++ % c->prof_every == 0) {
       HIPCALL(take_prof_events(c, &e0, &e1));
       c->prof_events.push_back({e0, e1, 1});
+    }
+    if (zy) {
+      // the sweep evaluates this step's links after relaxing; its leading blocks
+      // form the chunk partials of step t - 1 and the sums of step t - 2
+      launch_sweep(c, A, B, policy, e0, e1, k >= 2 ? c->t - 2 : -1, -1, c->t, k >= 1 ? c->t - 1 : -1);
+      if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
+      if (span && k == nsteps - 1) HIPCALL(hipEventRecord(c->prof_events.back().e1, c->stream));
+      c->cur ^= 1;
+      c->t++;
+      c->fresh = false;
+      continue;
     }
     if (inl) {
       // fixed solids: from the second step of the call on, the sweep applies the
@@ -853,7 +867,13 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     c->t++;
     c->fresh = false;
   }
-  if (inl && nsteps > 0) {
+  if (zy && nsteps > 0) {
+    // the ghost slots are filled; the forces of the last two steps are summed
+    const int64_t T = c->t - 1;
+    if (nsteps >= 2) launch_ft_reduce(c, T - 1);
+    launch_chunk_sum(c, T);
+    launch_ft_reduce(c, T);
+  } else if (inl && nsteps > 0) {
     // the last step's bounce-back fills the ghost slots of the state the call
     // leaves behind; every step of the call has its force summed on return
     const int64_t T = c->t - 1;
@@ -862,7 +882,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       launch_chunk_sum(c, T - 1);
       launch_ft_reduce(c, T - 1);
     }
-    launch_ibb(c, c->state(), c->other(), T);  // (no Zhao-Yong links on this route)
+    launch_ibb(c, c->state(), c->other(), T);
     launch_ft_reduce(c, T);
   }
   HIPCALL(hipGetLastError());

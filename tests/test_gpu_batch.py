@@ -42,6 +42,9 @@ def _specs():
         ("MRT", (34, 31, 28), 0.8, (0.0, 0.0, 0.0),
          [W.solid("sphere", (16.1, 15.3, 13.6), 5.8, velocity=(-0.015, 0.012, -0.009))], "ZHAO_YONG", None),
         ("MRT", (29, 33, 27), 0.75, (1e-6, 0.0, 5e-7), [W.solid("sphere", (14.3, 16.2, 13.1), 5.4)], "YU", None),
+        # fixed: alone, the sweep evaluates these links; in the batch, the bounce-back kernel
+        ("BGK", (31, 27, 30), 0.85, (2e-6, -1e-6, 0.0), [W.solid("sphere", (15.4, 13.2, 14.7), 5.9)], "ZHAO_YONG",
+         None),
     ]
 
 
@@ -88,7 +91,7 @@ def test_batch_members_match_alone(lbm, storage):
     them: tuning steps, then graph replays (one-step and eight-step graphs)."""
     specs = _specs()
     calls = [1, 10, 3, 17, 8, 6]
-    b = lbm.Batch("D3Q19", storage, max_slots=8, pool_bytes=1 << 30)
+    b = lbm.Batch("D3Q19", storage, max_slots=10, pool_bytes=1 << 30)
     members = []
     for spec in specs:
         coll, shape, tau, g, solids, _, rates = spec
