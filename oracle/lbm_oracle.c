@@ -36,7 +36,7 @@
  *
  * The paper does not print the velocity sets, the equilibrium, the MRT
  * matrix, the relaxation rates, the forcing term, the linear Bouzidi formula
- * or the refill rule ("not repeated here", Sec. 2).  The readings used are the
+ * or the refill rule (Sec. 2 defers them to textbooks).  The readings used are the
  * standard ones and are listed where they are used.
  *
  * Pins (see tests/test_oracle_*.py): velocity-set moments, equilibrium and
