@@ -95,6 +95,9 @@ def lib():
         L.orc_spread.argtypes = [ctypes.c_void_p, _d, _d]
         L.orc_phi.argtypes = [ctypes.c_double]
         L.orc_phi.restype = ctypes.c_double
+        L.orc_phi_n.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_phi_n.restype = ctypes.c_double
+        L.orc_set_ibm_delta.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 7
         L.orc_ibb_value.restype = ctypes.c_double
@@ -111,6 +114,11 @@ def _p(a, t=_d):
 def zhao_yong_value(q, fi_post, fb_pre, B):
     """Unknown population of one boundary link by Zhao & Yong's scheme, Eq. 16."""
     return lib().orc_zhao_yong_value(float(q), float(fi_post), float(fb_pre), float(B))
+
+
+def phi_n(points: int, r: float) -> float:
+    """Delta function factor: 4 points (Eq. 6), 3 points (Roma et al.) or 2 points (linear)."""
+    return lib().orc_phi_n(int(points), float(r))
 
 
 def phi(r: float) -> float:
@@ -187,6 +195,11 @@ class Oracle:
 
     def set_ibm_iters(self, n_iter):
         lib().orc_set_ibm_iters(self._h, int(n_iter))
+
+    def set_ibm_delta(self, points):
+        """Delta function of the IBM: 4 (Eq. 6, default), 3 (Roma et al.) or 2 (linear)."""
+        if lib().orc_set_ibm_delta(self._h, int(points)) != 0:
+            raise ValueError(points)
 
     # -- stepping ------------------------------------------------------------
     def step(self, n=1):

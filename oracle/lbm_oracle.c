@@ -16,7 +16,9 @@
  *   2. body force density g on the fluid region (Sec. 3.3 discussion of where
  *      the driving force is applied);
  *   3. IBM only: direct-forcing boundary force by Uhlmann's steps, Eq. 5-9,
- *      with Peskin's 4-point delta, Eq. 6, repeated n_iter times (Sec. 3.1);
+ *      with Peskin's 4-point delta, Eq. 6 (or the 3-point delta of Roma et
+ *      al. or the 2-point linear one, compared in Sec. 3.1), repeated n_iter
+ *      times (Sec. 3.1);
  *   4. collision: lattice BGK, Eq. 1 + Eq. 2, or MRT, Eq. 3, with the
  *      second-order (Guo) mesoscopic forcing named in Sec. 2.1;
  *   5. streaming to the neighbour along e_i (periodic box);
@@ -133,6 +135,7 @@ typedef struct orc {
   link_t *links;
   /* IBM */
   int n_iter;
+  int delta;      /* points of the delta function: 4 (Eq. 6), 3 or 2 */
   long nlag;
   double *X;      /* [nlag][3] */
   double *dV;     /* [nlag] */
@@ -534,8 +537,32 @@ double orc_phi(double r) {
   return 0.125 * (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r));
 }
 
-/* Stencil of a Lagrangian point: 4 nodes per axis, floor(X)-1 .. floor(X)+2
- * (the support |r| < 2 of Eq. 6), with the weight phi(x - X) per axis. */
+/* The other two delta functions of the comparison in Sec. 3.1, which the
+ * paper names but does not print; written from their published definitions.
+ * Three-point (Roma, Peskin & Berger 1999): support |r| < 3/2, the unique
+ * piecewise form with sum_j phi(r - j) = 1, sum_j (r - j) phi(r - j) = 0 and
+ * sum_j phi(r - j)^2 = 1/2 for every r:
+ *   |r| <= 1/2      : (1 + sqrt(1 - 3 r^2)) / 3
+ *   1/2 <= |r| < 3/2: (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6
+ * Two-point: the linear hat 1 - |r| on |r| < 1 (bilinear / trilinear
+ * interpolation). */
+double orc_phi3(double r) {
+  r = fabs(r);
+  if (r >= 1.5) return 0.0;
+  if (r >= 0.5) return (5.0 - 3.0 * r - sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
+  return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+}
+double orc_phi2(double r) {
+  r = fabs(r);
+  return r >= 1.0 ? 0.0 : 1.0 - r;
+}
+double orc_phi_n(int points, double r) {
+  return points == 3 ? orc_phi3(r) : (points == 2 ? orc_phi2(r) : orc_phi(r));
+}
+
+/* Stencil of a Lagrangian point: the w nodes per axis whose distance to X is
+ * below w/2 (the support of the w-point delta; w = 4: floor(X)-1 ..
+ * floor(X)+2), with the weight phi(x - X) per axis. */
 typedef struct {
   long cell[64];
   double wgt[64];
@@ -544,18 +571,19 @@ typedef struct {
 
 static void stencil_of(const orc *o, const double X[3], stencil_t *st) {
   int b[3];
+  const int w = o->delta;
   double wx[4], wy[4], wz[4];
-  for (int a = 0; a < 3; a++) b[a] = (int)floor(X[a]) - 1;
-  for (int k = 0; k < 4; k++) {
-    wx[k] = orc_phi((double)(b[0] + k) - X[0]);
-    wy[k] = orc_phi((double)(b[1] + k) - X[1]);
-    wz[k] = orc_phi((double)(b[2] + k) - X[2]);
+  for (int a = 0; a < 3; a++) b[a] = (int)floor(X[a] - 0.5 * w) + 1;
+  for (int k = 0; k < w; k++) {
+    wx[k] = orc_phi_n(w, (double)(b[0] + k) - X[0]);
+    wy[k] = orc_phi_n(w, (double)(b[1] + k) - X[1]);
+    wz[k] = orc_phi_n(w, (double)(b[2] + k) - X[2]);
   }
   st->n = 0;
-  int kzn = o->D == 2 ? 1 : 4;
+  int kzn = o->D == 2 ? 1 : w;
   for (int kz = 0; kz < kzn; kz++)
-    for (int ky = 0; ky < 4; ky++)
-      for (int kx = 0; kx < 4; kx++) {
+    for (int ky = 0; ky < w; ky++)
+      for (int kx = 0; kx < w; kx++) {
         double wgt = wx[kx] * wy[ky];
         int z = 0;
         if (o->D == 3) {
@@ -699,6 +727,7 @@ orc *orc_create(int lattice, int collision, int nx, int ny, int nz, double tau, 
     for (int i = 0; i < o->Q; i++) o->f[(long)i * o->N + n] = 0.0; /* rest: f = w, rho = 1 */
   }
   o->n_iter = 5;
+  o->delta = 4;
   o->method = M_BB;
   return o;
 }
@@ -784,6 +813,11 @@ int orc_set_lagrangian(orc *o, int sid, const double *X, long n, double dV) {
 
 void orc_clear_lagrangian(orc *o) { o->nlag = 0; }
 void orc_set_ibm_iters(orc *o, int n_iter) { o->n_iter = n_iter; }
+int orc_set_ibm_delta(orc *o, int points) {
+  if (points != 2 && points != 3 && points != 4) return -1;
+  o->delta = points;
+  return 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* one time step                                                             */

@@ -11,6 +11,8 @@
   pair (f_i, f_ibar) of a fluid moving with the wall is a fixed point;
 * Peskin's 4-point delta (Eq. 6): partition of unity, zero first moment (the
   property App. B relies on), sum of squares 3/8, continuity, phi(0) = 1/2;
+  the 3-point delta of Roma et al. (sum of squares 1/2, phi(0) = 2/3) and the
+  2-point linear delta compared in Sec. 3.1: the same moment identities;
 * interpolation (Eq. 5) and spreading (Eq. 8): exact for constant and linear
   fields, conservation of total force and torque, adjointness;
 * node classification, the boundary-link set and q (Fig. 1, Sec. 2.2) checked
@@ -167,20 +169,44 @@ def test_delta_function_moments():
     assert oracle.phi(2.0) == 0.0 and oracle.phi(-2.5) == 0.0
 
 
+@pytest.mark.parametrize("points,support,sum_sq,at0", [(3, 1.5, 0.5, 2.0 / 3.0), (2, 1.0, None, 1.0)])
+def test_narrow_delta_function_moments(points, support, sum_sq, at0):
+    """The 3-point delta (Roma et al.) and the 2-point linear delta: partition of
+    unity and zero first moment for every shift (what interpolation of linear
+    fields and conservation of force and torque need), the 3-point one also a
+    constant sum of squares; continuity; the stated value at 0; the support."""
+    rng = np.random.default_rng(34)
+    js = np.arange(-3, 5)
+    for r in rng.uniform(0.0, 1.0, size=20000):
+        ph = np.array([oracle.phi_n(points, r - j) for j in js])
+        assert abs(ph.sum() - 1.0) < 1e-15
+        assert abs(np.sum((r - js) * ph)) < 1e-15
+        if sum_sq is not None:
+            assert abs(np.sum(ph * ph) - sum_sq) < 1e-15
+        assert np.count_nonzero(ph) <= points
+    assert abs(oracle.phi_n(points, 0.0) - at0) < 1e-16
+    for r0 in (0.5, 1.0, 1.5):
+        assert abs(oracle.phi_n(points, r0 - 1e-12) - oracle.phi_n(points, r0 + 1e-12)) < 1e-11
+    assert oracle.phi_n(points, support) == 0.0 and oracle.phi_n(points, -support - 0.3) == 0.0
+    assert oracle.phi_n(4, 0.3) == oracle.phi(0.3)
+
+
 # ----------------------------------------------------------------------------
 # Interpolation and spreading, Eq. 5 and Eq. 8
 # ----------------------------------------------------------------------------
-def _ibm_oracle(shape=(24, 22, 20), R=5.3, centre=(11.3, 10.7, 9.2)):
+def _ibm_oracle(shape=(24, 22, 20), R=5.3, centre=(11.3, 10.7, 9.2), delta=4):
     o = Oracle("D3Q19", "MRT", shape, 0.8)
     s = W.solid("sphere", centre, R)
     o.set_solids([s], "IBM")
+    o.set_ibm_delta(delta)
     X, dV = W.icosphere(centre, R)
     o.set_lagrangian(0, X, dV)
     return o, X, dV
 
 
-def test_interpolation_exact_for_linear_fields():
-    o, X, dV = _ibm_oracle()
+@pytest.mark.parametrize("delta", [4, 3, 2])
+def test_interpolation_exact_for_linear_fields(delta):
+    o, X, dV = _ibm_oracle(delta=delta)
     nx, ny, nz = o.shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     a = np.array([0.3, -0.2, 0.1])
@@ -192,8 +218,9 @@ def test_interpolation_exact_for_linear_fields():
     assert np.max(np.abs(Ut - want)) < 1e-14
 
 
-def test_spreading_conserves_force_torque_and_is_adjoint():
-    o, X, dV = _ibm_oracle()
+@pytest.mark.parametrize("delta", [4, 3, 2])
+def test_spreading_conserves_force_torque_and_is_adjoint(delta):
+    o, X, dV = _ibm_oracle(delta=delta)
     rng = np.random.default_rng(33)
     F = rng.standard_normal((X.shape[0], 3))
     f = o.spread(F)
