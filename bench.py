@@ -66,7 +66,7 @@ def run_case(case, steps, warmup, key, torch, lbm):
     Q = 19 if case.lattice == "D3Q19" else 9
     gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g,
                       max_solids=max(1, len(case.solids)))
-    gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction)
+    gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction, delta=case.delta)
     N = gpu.N
     gpu.step(warmup)
     torch.cuda.synchronize()
@@ -322,13 +322,18 @@ def main():
                   file=sys.stderr, flush=True)
     # the other two bounce-back schemes the paper compares: Yu's (five populations per link)
     # and Zhao & Yong's single-node scheme; the 256^3 pack has gaps of 2 lattice units
-    # where the multi-node schemes fall back
-    for key, (ctor, method) in [("sphere128_f32_yu", (W.sphere_box, "YU")),
-                                ("sphere128_f32_zhao_yong", (W.sphere_box, "ZHAO_YONG")),
-                                ("pack256_f32_yu", (W.sphere_pack, "YU")),
-                                ("pack256_f32_zhao_yong", (W.sphere_pack, "ZHAO_YONG"))]:
+    # where the multi-node schemes fall back; the IBM with the 3- and 2-point deltas of
+    # the same comparison, each at the retraction the paper finds best for it
+    for key, (ctor, kw) in [("sphere128_f32_yu", (W.sphere_box, {"method": "YU"})),
+                            ("sphere128_f32_zhao_yong", (W.sphere_box, {"method": "ZHAO_YONG"})),
+                            ("pack256_f32_yu", (W.sphere_pack, {"method": "YU"})),
+                            ("pack256_f32_zhao_yong", (W.sphere_pack, {"method": "ZHAO_YONG"})),
+                            ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
+                                                                          "retraction": 0.3})),
+                            ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
+                                                                          "retraction": 0.2}))]:
         if "schemes" in want or key in want:
-            case = ctor(storage="F32", method=method)
+            case = ctor(storage="F32", **kw)
             k = max(K // 2, 100) if "256" not in key else max(K // 8, 50)
             extras[key] = run_case(case, k, max(Wm // 4, 64), key, torch, lbm)
             extras[key]["steps"] = k

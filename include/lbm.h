@@ -129,10 +129,15 @@ typedef struct {
 } lbm_solid;
 
 /* IBM options: n_iter direct-forcing iterations per step (Sec. 3.1 uses 5),
- * retraction R_d of the Lagrangian points towards the solid (Breugem,
- * Sec. 3.1; 0 = Uhlmann). */
+ * delta the regularized delta function of Eq. 5 and Eq. 8 by its width in
+ * lattice nodes: 4 = Peskin's four-point function (Eq. 6; also 0, the
+ * default), 3 = the three-point function of Roma et al., 2 = the two-point
+ * linear one (the three compared in Sec. 3.1), retraction R_d of the
+ * Lagrangian points towards the solid (Breugem, Sec. 3.1; 0 = Uhlmann).
+ * Other delta values give LBM_EINVAL. */
 typedef struct {
   int32_t n_iter;
+  int32_t delta;
   double retraction;
 } lbm_ibm_opts;
 

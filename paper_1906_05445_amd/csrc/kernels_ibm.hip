@@ -1,6 +1,7 @@
 // kernels_ibm.hip -- direct-forcing immersed boundary method (Sec. 2.1,
-// Eq. 5-9) with Peskin's 4-point delta (Eq. 6), iterated n_iter times
-// (Sec. 3.1), and the force/torque on each solid from its Lagrangian forces.
+// Eq. 5-9) with Peskin's 4-point delta (Eq. 6) or the 3- and 2-point deltas
+// compared in Sec. 3.1, iterated n_iter times (Sec. 3.1), and the
+// force/torque on each solid from its Lagrangian forces.
 //
 // Data: the Lagrangian points (FP64 positions, per-axis delta weights, the
 // shell index of each of their 4^D stencil cells), the shell (the sorted
@@ -28,6 +29,24 @@ __device__ inline double phi4(double r) {
   if (r >= 1.0) return 0.125 * (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r));
   return 0.125 * (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r));
 }
+// The other deltas of Sec. 3.1 (not printed there): Roma et al.'s 3-point
+// function, support |r| < 3/2, (1 + sqrt(1 - 3r^2))/3 on |r| <= 1/2 and
+// (5 - 3|r| - sqrt(1 - 3(1 - |r|)^2))/6 beyond; the 2-point hat 1 - |r|.
+// Both vanish outside floor(X) - 1 .. floor(X) + 2, so the 4-node stencil of
+// Eq. 6 holds them with exact zeros at the extra nodes.
+__device__ inline double phi3(double r) {
+  r = fabs(r);
+  if (r >= 1.5) return 0.0;
+  if (r >= 0.5) return (5.0 - 3.0 * r - sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
+  return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+}
+__device__ inline double phi2(double r) {
+  r = fabs(r);
+  return r >= 1.0 ? 0.0 : 1.0 - r;
+}
+__device__ inline double phi_of(int points, double r) {
+  return points == 3 ? phi3(r) : (points == 2 ? phi2(r) : phi4(r));
+}
 
 
 // setup: delta weights and desired velocity U^d = U + Omega x (X - Y)
@@ -36,8 +55,9 @@ __global__ void k_ibm_weights(IbmArgs a) {
   if (l >= a.nlag) return;
   for (int ax = 0; ax < 3; ax++)
     for (int k = 0; k < 4; k++)
-      a.wts[l * 12 + ax * 4 + k] = (ax == 2 && a.b.D == 2) ? (k == 0 ? 1.0 : 0.0)
-                                                           : phi4((double)(a.base[l * 3 + ax] + k) - a.X[l * 3 + ax]);
+      a.wts[l * 12 + ax * 4 + k] =
+          (ax == 2 && a.b.D == 2) ? (k == 0 ? 1.0 : 0.0)
+                                  : phi_of(a.delta, (double)(a.base[l * 3 + ax] + k) - a.X[l * 3 + ax]);
   const DevSolid &s = a.solids[a.sid[l]];
   double c[3], r[3], ud[3];
   solid_centre(s, a.t, a.b, c);
@@ -271,6 +291,7 @@ static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
   a.stride = c->L.stride;
   a.nlag = c->nlag;
   a.nshell = c->nshell;
+  a.delta = c->delta;
   a.X = c->at<double>(c->L.lag_X);
   a.dV = c->at<double>(c->L.lag_dV);
   a.sid = c->at<int32_t>(c->L.lag_sid);

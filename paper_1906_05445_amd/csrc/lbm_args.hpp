@@ -122,6 +122,7 @@ struct IbmArgs {
   const DevSolid *solids;
   double g[3];
   int64_t t;
+  int delta;             // points of the delta function: 4 (Eq. 6), 3 or 2
 };
 
 __device__ __host__ inline IbmFtArgs ibm_ft_args(const IbmArgs &a, int64_t t, const int64_t *start,

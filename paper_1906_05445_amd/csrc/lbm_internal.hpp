@@ -139,6 +139,7 @@ struct lbm_ctx {
   uint64_t link_stride;
   // IBM
   int n_iter;
+  int delta;  // points of the IBM delta function: 4, 3 or 2
   double retraction;
   int64_t nlag;
   int64_t nshell;

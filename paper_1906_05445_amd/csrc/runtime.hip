@@ -320,6 +320,7 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->k5_chunks = 0;
   c->nlinks = 0;
   c->n_iter = 5;
+  c->delta = 4;
   c->retraction = 0.0;
   c->nlag = 0;
   c->nshell = 0;
@@ -513,8 +514,10 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   // the link masks of the count pass live in the staging region (4 N doubles) while links are built
   c->mask_cells = mask_total * 4 <= (uint64_t)4 * c->N * 8 ? mask_total : 0;
   c->n_iter = opts ? opts->n_iter : 5;
+  c->delta = (opts && opts->delta) ? opts->delta : 4;
   c->retraction = opts ? opts->retraction : 0.0;
-  if (c->n_iter < 0 || !std::isfinite(c->retraction)) return set_err(c, "IBM options"), LBM_EINVAL;
+  if (c->n_iter < 0 || !std::isfinite(c->retraction) || c->delta < 2 || c->delta > 4)
+    return set_err(c, "IBM options"), LBM_EINVAL;
   c->nlinks = 0;
   c->k5_chunks = 0;
   c->link_lists = false;

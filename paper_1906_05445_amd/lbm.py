@@ -52,7 +52,7 @@ class lbm_solid(ctypes.Structure):
 
 
 class lbm_ibm_opts(ctypes.Structure):
-    _fields_ = [("n_iter", ctypes.c_int32), ("retraction", ctypes.c_double)]
+    _fields_ = [("n_iter", ctypes.c_int32), ("delta", ctypes.c_int32), ("retraction", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -194,9 +194,9 @@ class _Context:
         if st != LBM_OK:
             raise LBMError(st, _lib.lbm_last_error(self.handle).decode())
 
-    def set_solids(self, solids, method="QUADRATIC", n_iter=5, retraction=0.0):
+    def set_solids(self, solids, method="QUADRATIC", n_iter=5, retraction=0.0, delta=4):
         arr = make_solids(solids)
-        opts = lbm_ibm_opts(int(n_iter), float(retraction))
+        opts = lbm_ibm_opts(int(n_iter), int(delta), float(retraction))
         self._check(_lib.lbm_set_solids(self.handle, arr, len(solids), METHODS[method], ctypes.byref(opts)))
         self.nsolid = len(solids)
 

@@ -142,6 +142,7 @@ class Case:
     ibm_iters: int = 5
     retraction: float = 0.0
     meta: dict = field(default_factory=dict)
+    delta: int = 4
 
 
 def cylinder_channel_2d(n=64, R=8.3, centre=(32.4, 31.7), g=1e-6, tau=0.8, steps=2000, method="LINEAR"):
@@ -151,14 +152,14 @@ def cylinder_channel_2d(n=64, R=8.3, centre=(32.4, 31.7), g=1e-6, tau=0.8, steps
 
 
 def sphere_box(n=128, R=16.2, Re=20.0, tau=0.8, seed=2, method="QUADRATIC", storage="F64", steps=5000,
-               retraction=0.0):
+               retraction=0.0, delta=4):
     """Fixed sphere at a seed-drawn sub-grid offset in a periodic cube, D3Q19 MRT."""
     rng = np.random.default_rng(seed)
     c = np.array([n / 2.0] * 3) + rng.random(3)
     nu = nu_of_tau(tau)
     g, U = stokes_body_force(Re, nu, 2 * R, n ** 3, 4.0 / 3.0 * math.pi * R ** 3)
     return Case(f"sphere_{n}", "D3Q19", "MRT", (n, n, n), tau, (g, 0.0, 0.0), [solid("sphere", c, R)],
-                method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U})
+                method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U}, delta=delta)
 
 
 def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, storage="F64", steps=10000,

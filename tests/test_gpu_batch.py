@@ -222,3 +222,25 @@ def test_batch_d2q9_members_match_alone(lbm, storage):
         _compare(m, ref, f"D2Q9 member {k}")
         ref.close()
     b.close()
+
+
+def test_batch_ibm_delta_members_match_alone(lbm):
+    """IBM members with the 3- and 2-point deltas (Sec. 3.1) next to a 4-point one."""
+    specs = [((29, 27, 25), [W.solid("sphere", (14.2, 13.4, 12.1), 5.1)], 3, 0.3),
+             ((31, 26, 24), [W.solid("sphere", (15.3, 12.6, 11.8), 4.8)], 2, 0.2),
+             ((27, 27, 27), [W.solid("sphere", (13.6, 13.1, 13.9), 5.3)], 4, 0.0)]
+    b = lbm.Batch("D3Q19", "F32", max_slots=4, pool_bytes=1 << 28)
+    members = []
+    for shape, solids, delta, rd in specs:
+        m = b.admit("MRT", "F32", shape, 0.8, g=(2e-6, 0.0, 0.0), max_solids=1)
+        m.set_solids(solids, "IBM", n_iter=3, delta=delta, retraction=rd)
+        members.append(m)
+    for n in (5, 12, 9):
+        b.step(n)
+    for k, ((shape, solids, delta, rd), m) in enumerate(zip(specs, members)):
+        ref = lbm.Lattice("D3Q19", "MRT", "F32", shape, 0.8, g=(2e-6, 0.0, 0.0), max_solids=1)
+        ref.set_solids(solids, "IBM", n_iter=3, delta=delta, retraction=rd)
+        ref.step(26)
+        _compare(m, ref, f"IBM member {k} ({delta}-point delta)")
+        ref.close()
+    b.close()

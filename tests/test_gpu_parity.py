@@ -41,14 +41,15 @@ def _oracle(case_lat, coll, shape, tau, g, rates=None, fluid_only=True):
 
 
 def _pair(lbm, lat, coll, shape, tau, g=(0.0, 0.0, 0.0), storage="F64", rates=None, solids=None,
-          method="QUADRATIC", lag=None, n_iter=5, max_solids=None, fluid_only=True):
+          method="QUADRATIC", lag=None, n_iter=5, max_solids=None, fluid_only=True, delta=4):
     gpu = lbm.Lattice(lat, coll, storage, shape, tau, rates=rates, g=g, g_fluid_only=fluid_only,
                       max_solids=max_solids or max(1, len(solids or [])))
     orc = _oracle(lat, coll, shape, tau, g, rates, fluid_only)
     if solids:
-        gpu.set_solids(solids, method, n_iter=n_iter)
+        gpu.set_solids(solids, method, n_iter=n_iter, delta=delta)
         orc.set_solids(solids, method)
         orc.set_ibm_iters(n_iter)
+        orc.set_ibm_delta(delta)
         if method == "IBM":
             for k, s in enumerate(solids):
                 X, dV = lag[k] if lag else W.lagrangian_mesh(s, lat, shape)
@@ -247,28 +248,39 @@ def test_translating_sphere_refill_fp64(lbm, method):
 # ----------------------------------------------------------------------------
 # immersed boundary
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("retraction", [0.0, 0.4])
-def test_ibm_sphere_fp64(lbm, retraction):
+@pytest.mark.parametrize("delta,retraction", [(4, 0.0), (4, 0.4), (3, 0.3), (2, 0.2), (2, 0.0)])
+def test_ibm_sphere_fp64(lbm, delta, retraction):
+    """Peskin's 4-point delta (Eq. 6) and the 3- and 2-point deltas of Sec. 3.1,
+    each with the retraction the paper finds best for it."""
     shape = (37, 29, 23)
     g = (3e-6, 0.0, 0.0)
     s = W.solid("sphere", (18.3, 14.1, 11.7), 6.6)
     X, dV = W.icosphere(s["centre"], s["radius"] - retraction)
-    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, g=g, solids=[s], method="IBM", lag=[(X, dV)])
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, g=g, solids=[s], method="IBM", lag=[(X, dV)], delta=delta)
     gpu.step(20)
     orc.step(20)
     _compare_fields(gpu, orc)
     _compare_forces(gpu, orc, g, 1e-12)
 
 
-def test_ibm_couette_2d_fp64(lbm):
+@pytest.mark.parametrize("delta", [4, 3, 2])
+def test_ibm_couette_2d_fp64(lbm, delta):
     n, R1 = 40, 8.2
     c = (20.3, 19.6, 0.0)
     s = [W.solid("cylinder", c, R1, omega=(0, 0, 0.002))]
-    gpu, orc = _pair(lbm, "D2Q9", "BGK", (n, n, 1), 0.9, g=(1e-6, 0.0), solids=s, method="IBM", n_iter=3)
+    gpu, orc = _pair(lbm, "D2Q9", "BGK", (n, n, 1), 0.9, g=(1e-6, 0.0), solids=s, method="IBM", n_iter=3,
+                     delta=delta)
     gpu.step(50)
     orc.step(50)
     _compare_fields(gpu, orc)
     _compare_forces(gpu, orc, (1e-6, 0, 0), 1e-12)
+
+
+def test_ibm_delta_option_rejected(lbm):
+    gpu = lbm.Lattice("D3Q19", "MRT", "F64", (16, 16, 16), 0.8)
+    with pytest.raises(lbm.LBMError):
+        gpu.set_solids([W.solid("sphere", (8.1, 7.9, 8.2), 4.0)], "IBM", delta=5)
+    gpu.close()
 
 
 def test_library_mesh_matches_generator(lbm):
