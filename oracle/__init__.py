@@ -98,6 +98,7 @@ def lib():
         L.orc_phi_n.argtypes = [ctypes.c_int, ctypes.c_double]
         L.orc_phi_n.restype = ctypes.c_double
         L.orc_set_ibm_delta.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_strain.argtypes = [ctypes.c_void_p, _d, _d]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 7
         L.orc_ibb_value.restype = ctypes.c_double
@@ -314,6 +315,15 @@ class Oracle:
         out = np.zeros(self.Q)
         lib().orc_collide_node(self._h, _p(fin), _p(F), _p(out))
         return out
+
+    def strain(self):
+        """Strain rate [6][N] (xx, yy, zz, xy, yz, xz) and dissipation rate [N] of the
+        most recent collision, from the non-equilibrium moments (Sec. 3.1, Eq. 19)."""
+        S = np.zeros((6, self.N))
+        eps = np.zeros(self.N)
+        if lib().orc_strain(self._h, _p(S), _p(eps)) != 0:
+            raise RuntimeError("no collision yet")
+        return S, eps
 
     def interpolate(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, self.N)

@@ -128,6 +128,7 @@ typedef struct orc {
   unsigned char *inside;  /* node inside the physical volume of some solid */
   int *owner;             /* solid index of an inside node, -1 otherwise */
   double *rho_out, *u_out; /* macros of the most recent collision */
+  double *strain_out;      /* [6][N] strain rate of the most recent collision (Eq. 19) */
   unsigned char *type_out;
   int nsolid, method;
   solid_t *sol;
@@ -719,6 +720,7 @@ orc *orc_create(int lattice, int collision, int nx, int ny, int nz, double tau, 
   o->owner = (int *)malloc(sizeof(int) * o->N);
   o->rho_out = (double *)malloc(sizeof(double) * o->N);
   o->u_out = (double *)calloc(3 * o->N, sizeof(double));
+  o->strain_out = (double *)calloc(6 * o->N, sizeof(double));
   o->type_out = (unsigned char *)calloc(o->N, 1);
   o->fibm = (double *)calloc(3 * o->N, sizeof(double));
   for (long n = 0; n < o->N; n++) {
@@ -742,6 +744,7 @@ void orc_destroy(orc *o) {
   free(o->owner);
   free(o->rho_out);
   free(o->u_out);
+  free(o->strain_out);
   free(o->type_out);
   free(o->fibm);
   free(o->sol);
@@ -824,6 +827,80 @@ int orc_set_ibm_delta(orc *o, int points) {
 /* ------------------------------------------------------------------------ */
 /* Collision of every fluid node.  h holds f - w; with rho = 1 + drho and
  * f - f_eq = h - h_eq the formulas below are Eq. 1 and Eq. 3 as written. */
+/* Strain rate s_ab = (d_a u_b + d_b u_a)/2 from the non-equilibrium moments
+ * of the populations a collision relaxes (Sec. 3.1, Eq. 19).  hi, heq, Fi:
+ * the deviations, their equilibrium part and Guo's forcing term F_hat of one
+ * node; S: xx, yy, zz, xy, yz, xz.  rho0 = 1, dt = 1.
+ *
+ * D2Q9 is Eq. 19 as printed, in the moment basis its text names (energy
+ * e = 3|e|^2 - 4, normal stress n = e_x^2 - e_y^2, shear c = e_x e_y); psi
+ * is the moment of the forcing term of Eq. 3, (1 - s/2) M F_hat.  For D3Q19
+ * the same first-order Chapman-Enskog balance of every second-order moment
+ * row k (with rate s_k), -(s_k/dt) m_k^(1) + psi_k = (D_0 of the equilibrium
+ * moment)_k = 2 rho0 c_s^2 (row k of s) + (row k of uF + Fu), is solved for
+ * s over the rows |e|^2, 3e_x^2 - |e|^2, e_y^2 - e_z^2, e_x e_y, e_y e_z,
+ * e_x e_z (c_s^2 = 1/3); for D2Q9 it reduces to Eq. 19.  The rates are
+ * those of the same rows of M (R4 order); BGK: all 1/tau. */
+static double rate_of_row(const orc *o, int k) { return o->collision == 0 ? 1.0 / o->tau : o->S[k]; }
+
+static void strain_node(const orc *o, const double *hi, const double *heq, const double *Fi, double S[6]) {
+  for (int a = 0; a < 6; a++) S[a] = 0.0;
+  if (o->D == 2) {
+    const double se = rate_of_row(o, 1), sn = rate_of_row(o, 7), sc = rate_of_row(o, 8);
+    double me = 0.0, mn = 0.0, mc = 0.0, pe = 0.0, pn = 0.0, pc = 0.0;
+    for (int i = 0; i < o->Q; i++) {
+      const double ex = o->e[i][0], ey = o->e[i][1];
+      const double re = 3.0 * (ex * ex + ey * ey) - 4.0, rn = ex * ex - ey * ey, rc = ex * ey;
+      me += re * (hi[i] - heq[i]);
+      mn += rn * (hi[i] - heq[i]);
+      mc += rc * (hi[i] - heq[i]);
+      pe += re * Fi[i];
+      pn += rn * Fi[i];
+      pc += rc * Fi[i];
+    }
+    pe *= 1.0 - 0.5 * se;
+    pn *= 1.0 - 0.5 * sn;
+    pc *= 1.0 - 0.5 * sc;
+    const double fe = (se / (2.0 - se)) * pe, fn = (3.0 * sn / (2.0 - sn)) * pn;
+    S[0] = -se / 4.0 * me - 3.0 * sn / 4.0 * mn - 0.25 * (fe + fn);  /* Eq. 19a */
+    S[1] = -se / 4.0 * me + 3.0 * sn / 4.0 * mn - 0.25 * (fe - fn);  /* Eq. 19b */
+    S[3] = -3.0 * sc / 2.0 * mc - 0.5 * (3.0 * sc / (2.0 - sc)) * pc; /* Eq. 19c */
+    return;
+  }
+  /* D3Q19: rows T, P, W, xy, yz, xz and their rates (R4 row indices 1, 9, 11, 13, 14, 15) */
+  static const int rows[6] = {1, 9, 11, 13, 14, 15};
+  double X[6];
+  for (int k = 0; k < 6; k++) {
+    double m1 = 0.0, psi = 0.0;
+    for (int i = 0; i < o->Q; i++) {
+      const double ex = o->e[i][0], ey = o->e[i][1], ez = o->e[i][2];
+      double r;
+      switch (k) {
+        case 0: r = ex * ex + ey * ey + ez * ez; break;
+        case 1: r = 3.0 * ex * ex - (ex * ex + ey * ey + ez * ez); break;
+        case 2: r = ey * ey - ez * ez; break;
+        case 3: r = ex * ey; break;
+        case 4: r = ey * ez; break;
+        default: r = ex * ez; break;
+      }
+      m1 += r * (hi[i] - heq[i]);
+      psi += r * Fi[i];
+    }
+    const double s = rate_of_row(o, rows[k]);
+    psi *= 1.0 - 0.5 * s;
+    /* 2 c_s^2 = 2/3: row k of s = -(3 s / 2) m1 - (3 / 2) (s / (2 - s)) psi */
+    X[k] = -1.5 * s * m1 - 1.5 * (s / (2.0 - s)) * psi;
+  }
+  /* T = sxx + syy + szz, P = 2 sxx - syy - szz, W = syy - szz */
+  const double sxx = (X[0] + X[1]) / 3.0, rest = (2.0 * X[0] - X[1]) / 3.0;
+  S[0] = sxx;
+  S[1] = 0.5 * (rest + X[2]);
+  S[2] = 0.5 * (rest - X[2]);
+  S[3] = X[3];
+  S[4] = X[4];
+  S[5] = X[5];
+}
+
 static void collide(orc *o, const double *drho, const double *j, const double *Ftot) {
   int Q = o->Q;
   long N = o->N;
@@ -863,6 +940,9 @@ static void collide(orc *o, const double *drho, const double *j, const double *F
     }
     o->rho_out[n] = rho;
     for (int a = 0; a < 3; a++) o->u_out[a * N + n] = u[a];
+    double S[6];
+    strain_node(o, hi, heq, Fi, S);
+    for (int a = 0; a < 6; a++) o->strain_out[a * N + n] = S[a];
   }
 }
 
@@ -878,6 +958,7 @@ static void solid_node_output(orc *o) {
     wall_velocity(s, r, uw);
     o->rho_out[n] = 0.0;
     for (int a = 0; a < 3; a++) o->u_out[a * o->N + n] = uw[a];
+    for (int a = 0; a < 6; a++) o->strain_out[a * o->N + n] = 0.0;
   }
 }
 
@@ -1116,6 +1197,24 @@ void orc_collide_node(const orc *o, const double *fin, const double *F, double *
   double Ft[3] = {F[0], F[1], F[2]};
   collide(&tmp, &drho, j, Ft);
   for (int i = 0; i < o->Q; i++) fout[i] = o->w[i] + hpost[i];
+}
+
+/* Strain rate [6][N] (xx, yy, zz, xy, yz, xz) and dissipation rate
+ * eps = 2 nu s_ab s_ab (Sec. 3.1, nu of Eq. 2) of the most recent collision;
+ * 0 at IBB solid nodes.  -6 before the first step. */
+int orc_strain(const orc *o, double *S, double *eps) {
+  if (!o->stepped) return -6;
+  const double nu = (o->tau - 0.5) / 3.0;
+  for (long n = 0; n < o->N; n++) {
+    double ss = 0.0;
+    for (int a = 0; a < 6; a++) {
+      const double v = o->strain_out[a * o->N + n];
+      if (S) S[a * o->N + n] = v;
+      ss += (a < 3 ? 1.0 : 2.0) * v * v;
+    }
+    if (eps) eps[n] = 2.0 * nu * ss;
+  }
+  return 0;
 }
 
 void orc_macros(const orc *o, double *rho, double *u, unsigned char *type) {

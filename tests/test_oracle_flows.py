@@ -14,7 +14,12 @@
   compares (quadratic Bouzidi, Yu, Zhao & Yong);
 * pipe flow, Eq. 28: steady profile and the transient series; IBB second
   order, IBM first order, and retraction of the Lagrangian points lowering
-  the error and raising the order (Sec. 3.3).
+  the error and raising the order (Sec. 3.3);
+* strain rate from the non-equilibrium moments (Eq. 19): zero for a uniform
+  flow, exact shear in plane Poiseuille flow between halfway walls, second
+  order in Taylor-Green decay with distinct energy and stress rates, and the
+  dissipation rate of circular Couette flow (from Eq. 31) second order with
+  interpolated bounce-back (Sec. 3.1).
 
 The orders the paper states are read from tests/golden/convergence_orders.json
 (each with its citation).
@@ -292,3 +297,96 @@ def test_best_retraction_grows_with_delta_width(entry):
     assert lo - 1e-9 <= best <= hi + 1e-9, (entry["delta_points"], errs)
     # retraction lowers the error for every delta (Sec. 3.1): R_d = 0 is the worst of the sweep
     assert errs[0] == max(errs)
+
+
+# ----------------------------------------------------------------------------
+# strain rate and dissipation, Eq. 19
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_strain_zero_for_uniform_flow(lat):
+    shape = (9, 7, 1 if lat == "D2Q9" else 5)
+    o = Oracle(lat, "MRT", shape, 0.7)
+    f = np.tile(np.asarray(o.feq(1.02, (0.03, -0.02, 0.01 if lat == "D3Q19" else 0.0)))[:, None], (1, o.N))
+    o.set_f(f)
+    o.step(1)
+    S, eps = o.strain()
+    assert np.max(np.abs(S)) < 1e-16 and np.max(eps) < 1e-30
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_strain_exact_in_plane_poiseuille(lat):
+    """Halfway walls (the exact Poiseuille case above): the shear component equals
+    du/dy / 2 of the parabola to rounding (measured 1e-18); the normal components
+    are O(Ma^2) (measured 2.5e-4 of the shear)."""
+    H, tau, U = 16, 0.8, 1e-3
+    ny = H + 2
+    y0, y1 = 0.5, H + 0.5
+    nu = (tau - 0.5) / 3.0
+    g = 8.0 * nu * U / (y1 - y0) ** 2
+    o = Oracle(lat, "MRT", (1, ny, 1 if lat == "D2Q9" else 2), tau, g=(g, 0.0, 0.0))
+    o.set_solids([W.solid("plane", (0, y0, 0), axis=(0, 1, 0)), W.solid("plane", (0, y1, 0), axis=(0, -1, 0))],
+                 "BB")
+    o.step(int(40 * (y1 - y0) ** 2 / (math.pi ** 2 * nu)))
+    S, eps = o.strain()
+    _, _, t = o.macros()
+    fl = t == 0
+    y = np.tile(np.arange(ny, dtype=np.float64), o.N // ny)
+    sxy = g / (4.0 * nu) * (y0 + y1 - 2.0 * y)
+    assert np.max(np.abs(S[3][fl] - sxy[fl])) < 1e-14
+    assert np.max(np.abs(S[[0, 1, 2, 4, 5]][:, fl])) < 1e-3 * np.max(np.abs(sxy))
+    assert np.max(np.abs(eps[fl] - 4.0 * nu * sxy[fl] ** 2)) < 1e-6 * np.max(eps)
+    assert np.all(S[:, ~fl] == 0.0)
+
+
+def _taylor_green_strain_error(N, lat, tau=0.8, U=1e-4):
+    nu = (tau - 0.5) / 3.0
+    k = 2.0 * math.pi / N
+    rates = np.full(9 if lat == "D2Q9" else 19, 1.0 / tau)
+    rates[1] = 1.1  # energy (bulk) rate distinct from the stress rates
+    o = Oracle(lat, "MRT", (N, N, 1), tau, rates=rates)
+    x, y = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    ux = -U * np.cos(k * x) * np.sin(k * y)
+    uy = U * np.sin(k * x) * np.cos(k * y)
+    o.set_f(np.stack([o.feq(1.0, (a, b, 0.0)) for a, b in zip(ux.ravel(), uy.ravel())], axis=1))
+    steps = int(round(N * N / (8.0 * math.pi ** 2 * nu)))
+    o.step(steps)
+    S, _ = o.strain()
+    sxx = (U * k * np.sin(k * x) * np.sin(k * y)).ravel() * math.exp(-2.0 * nu * k * k * (steps - 1))
+    return math.sqrt(np.sum((S[0] - sxx) ** 2 + (S[1] + sxx) ** 2 + S[3] ** 2) / np.sum(2.0 * sxx ** 2))
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_strain_taylor_green_second_order(lat):
+    errs = [_taylor_green_strain_error(N, lat) for N in (16, 32, 64)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 <= p <= 2.2 for p in orders), (errs, orders)  # measured 1.96, 1.99
+
+
+def _couette_dissipation_error(R1, method, tau=1.0, Om2R2=0.01):
+    R2 = 2.0 * R1
+    n = int(2 * R2 + 6)
+    c = (n / 2.0 + 0.31, n / 2.0 - 0.17, 0.0)
+    Om2 = Om2R2 / R2
+    nu = (tau - 0.5) / 3.0
+    o = Oracle("D2Q9", "MRT", (n, n, 1), tau, rates=np.full(9, 1.0 / tau))
+    o.set_solids([W.solid("cylinder", c, R1), W.solid("cylinder", c, R2, inverted=True, omega=(0, 0, Om2))],
+                 method)
+    lam1 = math.pi / (R2 - R1)
+    o.step(int(22.0 / (nu * lam1 * lam1)))
+    _, eps = o.strain()
+    _, _, t = o.macros()
+    x, y = np.meshgrid(np.arange(n) - c[0], np.arange(n) - c[1], indexing="xy")
+    r = np.sqrt(x * x + y * y).ravel()
+    fl = t == 0
+    # Eq. 31 with Omega_1 = 0: u_theta = A/r + B r, s_r_theta = -A/r^2, eps = 2 nu (2 s_r_theta^2)
+    A = -Om2 / (R1 ** -2 - R2 ** -2)
+    eth = 4.0 * nu * A * A / r ** 4
+    return np.sum(np.abs(eps[fl] - eth[fl])) / np.sum(np.abs(eth[fl]))
+
+
+@pytest.mark.parametrize("method", ["QUADRATIC", "YU", "ZHAO_YONG"])
+def test_couette_dissipation_second_order(method):
+    e8, e16 = _couette_dissipation_error(8.0, method), _couette_dissipation_error(16.0, method)
+    p = math.log2(e8 / e16)  # measured 1.87 / 1.89 / 1.88
+    ref, tol = _paper_order("circular_couette_dissipation", method)
+    assert e16 < 2e-2 and abs(p - ref) <= tol, (e8, e16, p)
