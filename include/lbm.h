@@ -188,6 +188,17 @@ int64_t lbm_history_capacity(void);
  * u = j/rho. */
 lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type);
 
+/* Strain rate and dissipation of the most recent collision (Sec. 3.1,
+ * Eq. 19), from the non-equilibrium moments of the populations it relaxed:
+ * S [6][N] = s_xx, s_yy, s_zz, s_xy, s_yz, s_xz with s_ab = (d_a u_b +
+ * d_b u_a)/2, eps [N] = 2 nu s_ab s_ab (nu of Eq. 2); either may be NULL,
+ * not both.  Each second-order moment row k of M (lbm_params) is taken with
+ * its own rate s_k: row k of s = -(3/2) s_k (m_k - m_k^eq) - (3/4) s_k
+ * (row k of u F + F u), rho0 = 1 (for D2Q9 this is Eq. 19).  IBB solid nodes
+ * give 0.  FP64 whatever the storage.  LBM_ESTATE before the first step
+ * after lbm_create / lbm_set_f / lbm_set_state.  Synchronizes the stream. */
+lbm_status lbm_strain(lbm_ctx *c, double *S, double *eps);
+
 /* Populations f_i(x, t) before the next collision, [Q][N] FP64 (solid nodes
  * give 0); lbm_set_f replaces them (time and history are kept). */
 lbm_status lbm_get_f(lbm_ctx *c, double *f);

@@ -783,6 +783,103 @@ __global__ void k_macros(const S *__restrict__ src, double *__restrict__ out, Ma
   macros_body<Q, S>(src, out, m, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Strain rate s_ab and dissipation 2 nu s_ab s_ab of the last collision from
+// its non-equilibrium moments (Sec. 3.1, Eq. 19), in FP64: the same gather,
+// density, velocity and force as macros_body, then Pi_ab = sum e_a e_b
+// (h - h_eq) and Guo's second moment u_a F_b + u_b F_a.  The first-order
+// Chapman-Enskog balance of a second-order row k with rate s_k,
+// -s_k m_k + (1 - s_k/2) psi_k = 2 rho0 c_s^2 (row k of s) + (row k of uF + Fu),
+// with psi_k the row of uF + Fu, gives row k of s = -(3/2) s_k m_k
+// - (3/4) s_k (row k of uF + Fu) (rho0 = 1, c_s^2 = 1/3), solved for s over
+// the trace and the traceless rows.  IBB solid nodes give 0.
+template <int Q, typename S>
+__device__ inline void strain_body(const S *__restrict__ src, double *__restrict__ out, const StrainArgs &sa,
+                                   uint32_t n) {
+  using L = Lat<Q>;
+  const MacroArgs &m = sa.m;
+  const CellArgs &a = m.ca;
+  if (n >= a.N) return;
+  double sv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const uint8_t fl = m.flags ? m.flags[n] : 0;
+  if (!(fl & m.solid_bit)) {
+    int x, y, z;
+    cell_xyz(n, a, x, y, z);
+    double h[Q];
+    double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const uint32_t sn = cell_id(x - L::ex(i), y - L::ey(i), z - L::ez(i), a);
+      h[i] = (double)Store<S>::ld(src + pidx<Q>(i, sn));
+      drho += h[i];
+      jx += L::ex(i) * h[i];
+      jy += L::ey(i) * h[i];
+      jz += L::ez(i) * h[i];
+    }
+    const double rho = 1.0 + drho;
+    double F[3] = {0.0, 0.0, 0.0};
+    if (m.moved || !(fl & F_NOBODY))
+      for (int k = 0; k < 3; k++) F[k] = m.g[k];
+    if (fl & F_IBM) {
+      using C = typename Store<S>::C;
+      const C *fb = reinterpret_cast<const C *>(m.fibm);
+      for (int k = 0; k < m.D; k++) F[k] += (double)fb[k * a.stride + n];
+    }
+    const double u[3] = {(jx + 0.5 * F[0]) / rho, (jy + 0.5 * F[1]) / rho, (jz + 0.5 * F[2]) / rho};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    // Pi^neq: xx, yy, zz, xy, yz, xz
+    double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+      const double eu = ex * u[0] + ey * u[1] + ez * u[2];
+      const double d = h[i] - wgt<Q>(i) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+      P[0] += ex * ex * d;
+      P[1] += ey * ey * d;
+      P[2] += ez * ez * d;
+      P[3] += ex * ey * d;
+      P[4] += ey * ez * d;
+      P[5] += ex * ez * d;
+    }
+    const double G[6] = {2.0 * u[0] * F[0], 2.0 * u[1] * F[1], 2.0 * u[2] * F[2],
+                         u[0] * F[1] + u[1] * F[0], u[1] * F[2] + u[2] * F[1], u[0] * F[2] + u[2] * F[0]};
+    auto row = [&](double s, double mk, double gk) { return -1.5 * s * mk - 0.75 * s * gk; };
+    if (Q == 9) {
+      const double XT = row(sa.s[0], P[0] + P[1], G[0] + G[1]);
+      const double XN = row(sa.s[1], P[0] - P[1], G[0] - G[1]);
+      sv[0] = 0.5 * (XT + XN);
+      sv[1] = 0.5 * (XT - XN);
+      sv[3] = row(sa.s[3], P[3], G[3]);
+    } else {
+      const double XT = row(sa.s[0], P[0] + P[1] + P[2], G[0] + G[1] + G[2]);
+      const double XP = row(sa.s[1], 2.0 * P[0] - P[1] - P[2], 2.0 * G[0] - G[1] - G[2]);
+      const double XW = row(sa.s[2], P[1] - P[2], G[1] - G[2]);
+      const double rest = (2.0 * XT - XP) / 3.0;
+      sv[0] = (XT + XP) / 3.0;
+      sv[1] = 0.5 * (rest + XW);
+      sv[2] = 0.5 * (rest - XW);
+      sv[3] = row(sa.s[3], P[3], G[3]);
+      sv[4] = row(sa.s[4], P[4], G[4]);
+      sv[5] = row(sa.s[5], P[5], G[5]);
+    }
+  }
+  if (sa.part == 0) {
+    const double ss = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2] +
+                      2.0 * (sv[3] * sv[3] + sv[4] * sv[4] + sv[5] * sv[5]);
+    out[n] = sv[0];
+    out[a.N + n] = sv[1];
+    out[2ull * a.N + n] = sv[2];
+    out[3ull * a.N + n] = 2.0 * sa.nu * ss;
+  } else {
+    out[n] = sv[3];
+    out[a.N + n] = sv[4];
+    out[2ull * a.N + n] = sv[5];
+  }
+}
+template <int Q, typename S>
+__global__ void k_strain(const S *__restrict__ src, double *__restrict__ out, StrainArgs sa) {
+  strain_body<Q, S>(src, out, sa, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // mode 0: no step since the state was set; mode 1: fields of the last
 // collision, in the geometry of that collision.
 void fill_macro_args(lbm_ctx *c, MacroArgs *mp, int mode) {
@@ -801,6 +898,30 @@ void fill_macro_args(lbm_ctx *c, MacroArgs *mp, int mode) {
   m.D = c->D;
   m.initial = mode == 0 ? 1 : 0;
   m.nsolid = c->nsolid;
+}
+
+void launch_strain(lbm_ctx *c, const void *src, double *out, int part) {
+  StrainArgs sa{};
+  fill_macro_args(c, &sa.m, 1);
+  sa.part = part;
+  sa.nu = (c->p.tau - 0.5) / 3.0;
+  // rows of the rates in the moment order of lbm.h
+  static const int r19[6] = {1, 9, 11, 13, 14, 15}, r9[6] = {1, 7, 7, 8, 8, 8};
+  for (int k = 0; k < 6; k++)
+    sa.s[k] = c->p.collision == LBM_BGK ? 1.0 / c->p.tau : c->rates[c->Q == 9 ? r9[k] : r19[k]];
+  const uint32_t grid = (uint32_t)((c->N + 255) / 256);
+#define LBM_STR(QQ, SS) \
+  hipLaunchKernelGGL((k_strain<QQ, SS>), dim3(grid), dim3(256), 0, c->stream, static_cast<const SS *>(src), out, sa)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_STR(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_STR(9, float);
+    else LBM_STR(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_STR(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_STR(19, float);
+    else LBM_STR(19, _Float16);
+  }
+#undef LBM_STR
 }
 
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode) {

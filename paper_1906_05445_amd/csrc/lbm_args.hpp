@@ -190,6 +190,17 @@ struct MacroArgs {
   uint8_t solid_bit;
 };
 
+// Strain rate of the last collision (Eq. 19): the rates of the second-order
+// moment rows (trace |e|^2, then 3e_x^2 - |e|^2 and e_y^2 - e_z^2 (D3Q19) or
+// e_x^2 - e_y^2 (D2Q9), then e_x e_y, e_y e_z, e_x e_z), the viscosity of
+// Eq. 2, and which half of the output a launch writes.
+struct StrainArgs {
+  MacroArgs m;
+  double s[6];
+  double nu;
+  int part;  // 0: s_xx, s_yy, s_zz, eps; 1: s_xy, s_yz, s_xz
+};
+
 // One lattice of a batch as the batched kernels see it.  Its time and state
 // parity advance with the batch step counter: at counter value k the lattice
 // is at t = t0 + k and its current state is P[cur0 ^ (k & 1)].

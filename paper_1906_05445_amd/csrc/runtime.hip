@@ -956,6 +956,27 @@ lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type) {
   return LBM_OK;
 }
 
+lbm_status lbm_strain(lbm_ctx *c, double *S, double *eps) {
+  if (!c || (!S && !eps)) return LBM_EINVAL;
+  if (c->fresh) return set_err(c, "lbm_strain needs a step since the populations were set"), LBM_ESTATE;
+  double *stg = c->at<double>(c->L.staging);
+  const size_t N = (size_t)c->N;
+  // the other array still holds the input of the last collision; two passes of
+  // 4 and 3 fields fit the staging region (4 N doubles)
+  launch_strain(c, c->other(), stg, 0);
+  HIPCALL(hipGetLastError());
+  if (S) HIPCALL(hipMemcpyAsync(S, stg, 3 * N * 8, hipMemcpyDeviceToHost, c->stream));
+  if (eps) HIPCALL(hipMemcpyAsync(eps, stg + 3 * N, N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  if (S) {
+    launch_strain(c, c->other(), stg, 1);
+    HIPCALL(hipGetLastError());
+    HIPCALL(hipMemcpyAsync(S + 3 * N, stg, 3 * N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
 // Node types of the current geometry, or of the geometry of the last
 // collision (translating solids move after the collision of each step).
 static lbm_status node_types_at(lbm_ctx *c, uint8_t *node_type, bool last_collision) {

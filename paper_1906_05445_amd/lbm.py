@@ -79,6 +79,7 @@ _sig("lbm_force_torque", _st, [_vp, _d, _d])
 _sig("lbm_force_history", _st, [_vp, _i64, _i64, _d])
 _sig("lbm_history_capacity", _i64, [])
 _sig("lbm_macros", _st, [_vp, _d, _d, ctypes.POINTER(ctypes.c_uint8)])
+_sig("lbm_strain", _st, [_vp, _d, _d])
 _sig("lbm_get_f", _st, [_vp, _d])
 _sig("lbm_set_f", _st, [_vp, _d])
 _sig("lbm_get_state", _st, [_vp, _vp])
@@ -118,7 +119,7 @@ _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_batch_destroy", _st, [_vp])
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
-            "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_get_f",
+            "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_strain", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
             "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_autotune_policy", "lbm_batch_table_bytes", "lbm_batch_create",
@@ -233,6 +234,13 @@ class _Context:
         t = np.empty(self.N, dtype=np.uint8)
         self._check(_lib.lbm_macros(self.handle, _ptr(rho), _ptr(u), _ptr(t, ctypes.c_uint8)))
         return rho, u, t
+
+    def strain(self):
+        """Strain rate [6][N] (xx, yy, zz, xy, yz, xz) and dissipation [N] of the last collision (Eq. 19)."""
+        S = np.empty((6, self.N))
+        eps = np.empty(self.N)
+        self._check(_lib.lbm_strain(self.handle, _ptr(S), _ptr(eps)))
+        return S, eps
 
     def get_f(self):
         f = np.empty((self.Q, self.N))

@@ -337,3 +337,69 @@ def test_full_size_sphere_128(lbm, storage, method):
         _compare_forces(gpu, orc, case.g, 1e-12)
     else:
         _compare_fields(gpu, orc, tol_u=1e-5, tol_rho=1e-6, tol_f=None, rel_l2=True)
+
+
+# ----------------------------------------------------------------------------
+# strain rate and dissipation of the last collision (Eq. 19)
+# ----------------------------------------------------------------------------
+def _compare_strain(gpu, orc, tol):
+    Sg, eg = gpu.strain()
+    So, eo = orc.strain()
+    sc = max(np.max(np.abs(So)), 1e-300)
+    dS = np.max(np.abs(Sg - So)) / sc
+    de = np.max(np.abs(eg - eo)) / max(np.max(eo), 1e-300)
+    assert dS <= tol and de <= 2 * tol, f"strain mismatch {dS:.3e} / dissipation {de:.3e} > {tol}"
+    return dS, de
+
+
+STRAIN_CASES = {
+    "d3q19_mrt_quadratic": ("D3Q19", "MRT", (37, 29, 23), 0.8, (3e-6, 1e-6, -5e-7), None,
+                            [W.solid("sphere", (18.3, 14.1, 11.7), 7.6)], "QUADRATIC"),
+    "d3q19_general_rates_zhao_yong": ("D3Q19", "MRT", (30, 28, 26), 0.8, (1.5e-6, 0.0, 5e-7),
+                                      np.array([0, 1.2, 1.4, 0, 1.1, 0, 1.1, 0, 1.1, 1.25, 1.3, 1.35, 1.3,
+                                                1.45, 1.15, 1.55, 1.5, 1.5, 1.5]),
+                                      [W.solid("sphere", (15.2, 13.9, 12.8), 4.9)], "ZHAO_YONG"),
+    "d2q9_bgk_linear": ("D2Q9", "BGK", (64, 64, 1), 0.8, (1e-5, 0.0, 0.0), None,
+                        [W.solid("cylinder", (32.4, 31.7, 0.0), 8.3)], "LINEAR"),
+    "d2q9_mrt_rates_couette": ("D2Q9", "MRT", (46, 46, 1), 1.0, (0.0, 0.0, 0.0),
+                               np.array([0, 1.1, 1.2, 0, 1.3, 0, 1.3, 1.0, 0.9]),
+                               [W.solid("cylinder", (23.31, 22.83, 0.0), 9.3),
+                                W.solid("cylinder", (23.31, 22.83, 0.0), 20.1, inverted=True,
+                                        omega=(0, 0, 0.01 / 20.1))], "YU"),
+    "d3q19_mrt_ibm": ("D3Q19", "MRT", (37, 29, 23), 0.8, (3e-6, 0.0, 0.0), None,
+                      [W.solid("sphere", (18.3, 14.1, 11.7), 6.6)], "IBM"),
+    "d3q19_translating": ("D3Q19", "MRT", (30, 27, 25), 0.8, (1e-6, 0.0, 0.0), None,
+                          [W.solid("sphere", (14.2, 13.1, 12.4), 5.3, velocity=(0.07, -0.045, 0.03))],
+                          "QUADRATIC"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STRAIN_CASES))
+def test_strain_fp64(lbm, name):
+    """Strain rate and dissipation against the oracle's Eq. 19 (FP64 storage).
+    Both take the same populations (equal to 1e-16 absolute) and differ only by
+    rounding in m - m_eq, whose size is the strain itself: 1e-9 of max|s|."""
+    lat, coll, shape, tau, g, rates, solids, method = STRAIN_CASES[name]
+    gpu, orc = _pair(lbm, lat, coll, shape, tau, g=g, rates=rates, solids=solids, method=method)
+    gpu.step(30)
+    orc.step(30)
+    _compare_strain(gpu, orc, 1e-9)
+    gpu.step(7)
+    orc.step(7)
+    _compare_strain(gpu, orc, 1e-9)
+
+
+def test_strain_reduced_precision_and_state(lbm):
+    shape = (37, 29, 23)
+    s = W.solid("sphere", (18.3, 14.1, 11.7), 6.6)
+    g = (2e-5, 0.0, 0.0)
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, g=g, storage="F32", solids=[s], method="QUADRATIC")
+    with pytest.raises(lbm.LBMError):
+        gpu.strain()  # no collision yet
+    gpu.step(200)
+    orc.step(200)
+    Sg, eg = gpu.strain()
+    So, eo = orc.strain()
+    # FP32 deviation storage: relative L2 of the strain within 1e-3 (measured below 1e-4)
+    assert np.sqrt(np.sum((Sg - So) ** 2) / np.sum(So ** 2)) < 1e-3
+    assert np.sqrt(np.sum((eg - eo) ** 2) / np.sum(eo ** 2)) < 2e-3
