@@ -99,6 +99,8 @@ def lib():
         L.orc_phi_n.restype = ctypes.c_double
         L.orc_set_ibm_delta.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_strain.argtypes = [ctypes.c_void_p, _d, _d]
+        L.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _d]
+        L.orc_solid_state.argtypes = [ctypes.c_void_p, _d]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 7
         L.orc_ibb_value.restype = ctypes.c_double
@@ -314,6 +316,19 @@ class Oracle:
         F = np.ascontiguousarray(list(F) + [0.0] * (3 - len(F)), dtype=np.float64)
         out = np.zeros(self.Q)
         lib().orc_collide_node(self._h, _p(fin), _p(F), _p(out))
+        return out
+
+    def set_free(self, k, density, gravity=(0.0, 0.0, 0.0)):
+        """Make solid k move freely (Eq. 20): density ratio rho_p / rho_f, external acceleration."""
+        g = np.asarray(gravity, dtype=np.float64)
+        st = lib().orc_set_free(self._h, int(k), float(density), _p(g))
+        if st != 0:
+            raise ValueError(st)
+
+    def solid_state(self):
+        """[n][9]: centre, velocity and angular velocity of every solid now."""
+        out = np.zeros((self.nsolid, 9))
+        lib().orc_solid_state(self._h, _p(out))
         return out
 
     def strain(self):

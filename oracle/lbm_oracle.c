@@ -27,8 +27,10 @@
  *      unified scheme (Eq. 12-14) or Zhao & Yong's single-node scheme
  *      (Eq. 16), then the force and torque on each solid by the
  *      Galilean-invariant momentum exchange method, Eq. 17;
- *   7. moving IBB solids only: advance the solid, reclassify, refill the
- *      newly uncovered nodes and rebuild the boundary links (Sec. 3.2).
+ *   7. moving IBB solids only: advance the solid (prescribed translation, or
+ *      free motion by Eq. 20 under the force and torque of step 6), reclassify,
+ *      refill the newly uncovered nodes and rebuild the boundary links
+ *      (Sec. 3.2).
  *
  * Populations are stored as deviations h_i = f_i - w_i from the rest state
  * (rho = 1, u = 0).  Every relation used is linear in f apart from f_eq, and
@@ -104,6 +106,10 @@ typedef struct {
   int sgn;       /* plane normal sign (+1 / -1): the fluid side is sgn*(x-p) > 0 */
   double U[3], W[3];
   int moving;
+  /* free motion (Eq. 20): density ratio rho_p / rho_f, external acceleration
+   * (gravity), volume and moment of inertia of the solid */
+  int free;
+  double rho_p, grav[3], Vp, Ip;
 } solid_t;
 
 typedef struct {
@@ -816,6 +822,40 @@ int orc_set_lagrangian(orc *o, int sid, const double *X, long n, double dV) {
 
 void orc_clear_lagrangian(orc *o) { o->nlag = 0; }
 void orc_set_ibm_iters(orc *o, int n_iter) { o->n_iter = n_iter; }
+
+/* Make solid k free (Eq. 20) with density ratio rho_p / rho_f and external
+ * acceleration g; its velocity and angular velocity start at the values
+ * given to orc_set_solids.  Spheres, and cylinders in D2Q9; not inverted;
+ * interpolated bounce-back only.  -1 invalid, -5 unsupported. */
+int orc_set_free(orc *o, int k, double rho_p, const double *g) {
+  if (k < 0 || k >= o->nsolid || !(rho_p > 0.0)) return -1;
+  solid_t *s = &o->sol[k];
+  if (o->method == M_IBM || s->inverted || s->kind == K_PLANE || (s->kind == K_CYLINDER && o->D != 2)) return -5;
+  s->free = 1;
+  s->moving = 1;
+  s->rho_p = rho_p;
+  for (int a = 0; a < 3; a++) s->grav[a] = g ? g[a] : 0.0;
+  if (o->D == 2) s->grav[2] = 0.0;
+  const double pi = 3.14159265358979323846;
+  if (s->kind == K_SPHERE) {
+    s->Vp = 4.0 / 3.0 * pi * s->R * s->R * s->R;
+    s->Ip = 0.4 * rho_p * s->Vp * s->R * s->R;
+  } else {
+    s->Vp = pi * s->R * s->R;
+    s->Ip = 0.5 * rho_p * s->Vp * s->R * s->R;
+  }
+  return 0;
+}
+
+/* Centre, velocity and angular velocity of every solid now: [n][9]. */
+void orc_solid_state(const orc *o, double *st) {
+  for (int k = 0; k < o->nsolid; k++)
+    for (int a = 0; a < 3; a++) {
+      st[9 * k + a] = o->sol[k].c[a];
+      st[9 * k + 3 + a] = o->sol[k].U[a];
+      st[9 * k + 6 + a] = o->sol[k].W[a];
+    }
+}
 int orc_set_ibm_delta(orc *o, int points) {
   if (points != 2 && points != 3 && points != 4) return -1;
   o->delta = points;
@@ -979,6 +1019,46 @@ static void push_history(orc *o) {
  * after the move (1 if there is none).  Covered nodes are dropped.  The
  * position is recomputed as Y0 + t U (never accumulated) and wrapped to the
  * box. */
+/* Free solid, Eq. 20 with the fluid density rho_f = rho0 = 1 and no
+ * interaction force: explicit in the force and torque F, T of the step just
+ * taken (Eq. 17, on the solid),
+ *   rho_p V_p (v^{n+1} - v^n) = F + (rho_p - 1) V_p g,
+ *   I_p (w^{n+1} - w^n) = T,
+ *   Y^{n+1} = Y^n + (v^n + v^{n+1}) / 2     (dt = 1),
+ * the position wrapped into the box.  With interpolated bounce-back there is
+ * no fluid inside the solid, so none of the inner-fluid terms of Eq. 21-24
+ * enter.  Sphere: V_p = 4 pi R^3 / 3, I_p = 2 rho_p V_p R^2 / 5; cylinder
+ * (D2Q9, per unit depth): V_p = pi R^2, I_p = rho_p V_p R^2 / 2, rotation
+ * about z only. */
+static double wrap_pos(double y, int L) {
+  if (y >= 0.0 && y < (double)L) return y;
+  y = fmod(y, (double)L);
+  if (y < 0.0) y += (double)L;
+  return y;
+}
+
+static void advance_free(orc *o, int k) {
+  solid_t *s = &o->sol[k];
+  const double *F = &o->FT[6 * k], *T = &o->FT[6 * k + 3];
+  const double m = s->rho_p * s->Vp;
+  double vn[3], wn[3];
+  for (int a = 0; a < 3; a++) {
+    vn[a] = s->U[a] + (F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
+    wn[a] = s->W[a] + T[a] / s->Ip;
+  }
+  if (o->D == 2) {
+    vn[2] = 0.0;
+    wn[0] = 0.0;
+    wn[1] = 0.0;
+  }
+  for (int a = 0; a < (o->D == 2 ? 2 : 3); a++)
+    s->c[a] = wrap_pos(s->c[a] + 0.5 * (s->U[a] + vn[a]), dims_of(o, a));
+  for (int a = 0; a < 3; a++) {
+    s->U[a] = vn[a];
+    s->W[a] = wn[a];
+  }
+}
+
 static void move_solids(orc *o) {
   int any = 0;
   for (int k = 0; k < o->nsolid; k++) any |= o->sol[k].moving;
@@ -991,6 +1071,10 @@ static void move_solids(orc *o) {
   for (int k = 0; k < o->nsolid; k++) {
     solid_t *s = &o->sol[k];
     if (!s->moving) continue;
+    if (s->free) {
+      advance_free(o, k);
+      continue;
+    }
     for (int a = 0; a < 3; a++) {
       int L = dims_of(o, a);
       double y = s->c0[a] + (double)(o->t + 1) * s->U[a];
