@@ -117,7 +117,18 @@ typedef struct {
  * into the fluid, `centre` a point of the plane.  inverted = 1 makes the
  * solid the OUTSIDE of the sphere/cylinder (an outer Couette wall, a pipe).
  * Wall velocity u_w(x) = velocity + omega x (x - centre).  A solid with
- * nonzero velocity translates (centre(t) = centre + t*velocity, IBB only). */
+ * nonzero velocity translates (centre(t) = centre + t*velocity, IBB only).
+ * density > 0 makes the solid move freely (Sec. 3.2, Eq. 20 with the fluid
+ * density rho0 = 1 and no interaction force): density is rho_p / rho_f,
+ * gravity the external acceleration; velocity and omega are the initial
+ * values.  After every step t, with the Eq. 17 force F and torque T of that
+ * step: rho_p V_p (v' - v) = F + (rho_p - 1) V_p gravity, I_p (w' - w) = T,
+ * centre' = centre + (v + v')/2 (dt = 1); sphere V_p = 4 pi R^3/3,
+ * I_p = 2 rho_p V_p R^2/5; cylinder (D2Q9 only, per unit depth) V_p = pi R^2,
+ * I_p = rho_p V_p R^2/2, rotation about z.  Free solids need an IBB method,
+ * a sphere or (2D) cylinder that is not inverted, and a context outside any
+ * batch (else LBM_EUNSUPPORTED); a step that would carry one faster than
+ * half a cell per step ends with LBM_EDIVERGED. */
 typedef struct {
   int32_t kind;       /* lbm_solid_kind */
   int32_t inverted;
@@ -126,6 +137,8 @@ typedef struct {
   double axis[3];
   double velocity[3];
   double omega[3];
+  double density;     /* rho_p / rho_f of a free solid; 0 = motion prescribed */
+  double gravity[3];  /* acceleration on a free solid */
 } lbm_solid;
 
 /* IBM options: n_iter direct-forcing iterations per step (Sec. 3.1 uses 5),
@@ -169,6 +182,11 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
 
 /* Advance nsteps time steps (no host synchronisation inside). */
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
+
+/* Centre, velocity and angular velocity of every solid now, state [n][9]
+ * (a free solid's from its integration; others' from their prescribed
+ * motion).  Synchronizes the stream. */
+lbm_status lbm_solid_state(lbm_ctx *c, double *state);
 
 /* Force and torque on every solid in the most recent step, [n][3] each. */
 lbm_status lbm_force_torque(lbm_ctx *c, double *force, double *torque);

@@ -190,6 +190,9 @@ class Oracle:
         self.nsolid = n
         lib().orc_clear_lagrangian(self._h)
         self.nlag = 0
+        for k, s in enumerate(solids):  # free solids (a "density" entry, as the GPU binding reads it)
+            if float(s.get("density", 0.0)) != 0.0:
+                self.set_free(k, s["density"], s.get("gravity", (0.0, 0.0, 0.0)))
 
     def set_lagrangian(self, sid, X, dV):
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)

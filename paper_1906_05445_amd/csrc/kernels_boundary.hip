@@ -447,6 +447,64 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, const S *__restri
   ibb_body<Q, S>(P, pre, a, a.g.t, blockIdx.x, blockIdx.y);
 }
 
+// Free solids (Eq. 20, fluid density rho0 = 1, dt = 1), one thread per solid,
+// after the force/torque of step t is in its history slot: v' = v + (F +
+// (rho_p - 1) V_p g) / (rho_p V_p), w' = w + T / I_p, centre' = centre +
+// (v + v')/2 wrapped into the box; the state of step t is kept in cp, Up, Wp
+// (the geometry of the collision at t, for the macroscopic readout).  Writes
+// with vector stores; kernels launched after it read the new table.  flag:
+// set when a velocity component reaches half a cell per step.
+__global__ void k_free_update(DevSolid *solids, int nsolid, const double *hist, Box3 b, int64_t t, uint32_t *flag) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsolid) return;
+  const DevSolid s = solids[k];
+  if (!s.free) return;
+  const double *F = hist + 6 * k, *T = F + 3;
+  const double m = s.rho_p * s.Vp;
+  double c[3], vn[3], wn[3], cn[3];
+  solid_centre(s, t, b, c);
+  for (int a = 0; a < 3; a++) {
+    vn[a] = s.U[a] + (F[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
+    wn[a] = s.W[a] + T[a] / s.Ip;
+  }
+  if (b.D == 2) {
+    vn[2] = 0.0;
+    wn[0] = 0.0;
+    wn[1] = 0.0;
+  }
+  for (int a = 0; a < 3; a++) {
+    cn[a] = c[a];
+    if (a < b.D) {
+      const double L = (double)box_dim(b, a);
+      double y = c[a] + 0.5 * (s.U[a] + vn[a]);
+      if (!(y >= 0.0 && y < L)) {
+        y = fmod(y, L);
+        if (y < 0.0) y = y + L;
+      }
+      cn[a] = y;
+    }
+    if (fabs(vn[a]) >= 0.5) flag[0] = 1u;
+  }
+  DevSolid &o = solids[k];
+  for (int a = 0; a < 3; a++) {
+    o.cp[a] = c[a];
+    o.Up[a] = s.U[a];
+    o.Wp[a] = s.W[a];
+    o.c0[a] = cn[a];
+    o.U[a] = vn[a];
+    o.W[a] = wn[a];
+  }
+  o.tref = t + 1;
+}
+
+void launch_free_update(lbm_ctx *c, int64_t t) {
+  const FtReduceArgs r = ft_reduce_args(c, t);
+  const Box3 b{c->p.nx, c->p.ny, c->p.nz, c->D};
+  hipLaunchKernelGGL(k_free_update, dim3((uint32_t)((c->nsolid + 63) / 64)), dim3(64), 0, c->stream,
+                     c->at<DevSolid>(c->L.solids), c->nsolid, r.hist, b, t, c->at<uint32_t>(c->L.misc) + 6);
+}
+
 // Per-solid force/torque: one wavefront per solid sums that solid's chunk
 // partials in chunk order into the history slot (used for the last step of an
 // lbm_step call; earlier steps are reduced inside the next sweep launch).

@@ -738,7 +738,16 @@ __device__ inline void macros_body(const S *__restrict__ src, double *__restrict
   const uint8_t fl = m.flags ? m.flags[n] : 0;
   const bool solid = fl & m.solid_bit;
   if (solid && m.owner[n] < m.nsolid) {
-    const DevSolid &s = m.solids[m.owner[n]];
+    DevSolid s = m.solids[m.owner[n]];
+    if (m.moved && s.free) {
+      // a free solid's table already holds the next step; its state at the collision
+      for (int k = 0; k < 3; k++) {
+        s.c0[k] = s.cp[k];
+        s.U[k] = s.Up[k];
+        s.W[k] = s.Wp[k];
+      }
+      s.tref = m.t_geom;
+    }
     Box3 b{(int)a.nx, (int)a.ny, (int)a.nz, m.D};
     double c[3], r[3], uw[3];
     solid_centre(s, m.t_geom, b, c);

@@ -18,12 +18,14 @@ struct Box3 {
 
 __device__ inline int box_dim(const Box3 &b, int a) { return a == 0 ? b.nx : (a == 1 ? b.ny : b.nz); }
 
-// Centre at time t: c0 + t U, wrapped into [0, L) (never accumulated).
+// Centre at time t: c0 + (t - tref) U, wrapped into [0, L).  Prescribed
+// motion has tref = 0 (the centre is never accumulated); a free solid's c0 is
+// its centre at tref.
 __device__ inline double centre_at(const DevSolid &s, int a, int64_t t, const Box3 &b) {
 #pragma clang fp contract(off)
   if (!s.moving) return s.c0[a];
   const double L = (double)box_dim(b, a);
-  double y = s.c0[a] + (double)t * s.U[a];
+  double y = s.c0[a] + (double)(t - s.tref) * s.U[a];
   if (y >= 0.0 && y < L) return y;  // fmod(y, L) is exactly y here; skip the costly call
   y = fmod(y, L);
   if (y < 0.0) y = y + L;

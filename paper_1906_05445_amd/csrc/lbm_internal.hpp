@@ -29,6 +29,13 @@ struct DevSolid {
   FastDiv fex, fexy;  // division by ext[0] and by ext[0] * ext[1]
   uint64_t mask_off;  // first box cell of this solid in the link-mask buffer
   double c0[3], R, U[3], W[3];
+  // free motion (Eq. 20): the centre is c0 at time tref (0 for prescribed
+  // motion), updated after every step; cp, Up, Wp hold the state of the step
+  // before (the geometry of the last collision)
+  int32_t free;
+  int64_t tref;
+  double rho_p, Vp, Ip, grav[3];
+  double cp[3], Up[3], Wp[3];
 };
 
 // Where one solid's links sit in the link arrays, and its chunk partials.
@@ -126,6 +133,7 @@ struct lbm_ctx {
   int method;
   int nsolid;
   bool any_moving;
+  bool any_free;
   std::vector<lbm_solid> solids;
   std::vector<lbm::DevSolid> dsolids;
   int32_t max_box_chunks;  // per solid, for the link-builder grid
@@ -193,6 +201,7 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0 
                   int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
+void launch_free_update(lbm_ctx *c, int64_t t);
 void launch_strain(lbm_ctx *c, const void *src, double *out, int part);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
 void launch_fill_zero(lbm_ctx *c, void *A);

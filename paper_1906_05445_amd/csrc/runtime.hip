@@ -416,6 +416,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   bool moving = false;
   int32_t mbc = 0;
   uint64_t mask_total = 0;  // box cells of the solids so far (link-mask buffer offsets)
+  bool any_free = false;
   for (int k = 0; k < n; k++) {
     const lbm_solid &q = s[k];
     DevSolid &d = ds[k];
@@ -440,6 +441,29 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
     d.ax = ax;
     d.sgn = sg;
     d.moving = (d.U[0] != 0.0 || d.U[1] != 0.0 || d.U[2] != 0.0) ? 1 : 0;
+    if (q.density != 0.0) {
+      // free motion (Eq. 20)
+      if (!(q.density > 0.0) || !std::isfinite(q.density) || !std::isfinite(q.gravity[0]) ||
+          !std::isfinite(q.gravity[1]) || !std::isfinite(q.gravity[2]))
+        return set_err(c, "free solid: density must be positive, gravity finite"), LBM_EINVAL;
+      if (method == LBM_IBM || q.kind == LBM_PLANE || q.inverted || (q.kind == LBM_CYLINDER && c->D != 2) ||
+          c->batch)
+        return set_err(c, "free solids need IBB, a sphere or 2D cylinder, not inverted, outside a batch"),
+               LBM_EUNSUPPORTED;
+      const double pi = 3.14159265358979323846, R = q.radius;
+      d.free = 1;
+      d.moving = 1;
+      d.rho_p = q.density;
+      for (int a = 0; a < 3; a++) d.grav[a] = (c->D == 2 && a == 2) ? 0.0 : q.gravity[a];
+      d.Vp = q.kind == LBM_SPHERE ? 4.0 / 3.0 * pi * R * R * R : pi * R * R;
+      d.Ip = (q.kind == LBM_SPHERE ? 0.4 : 0.5) * q.density * d.Vp * R * R;
+      any_free = true;
+    }
+    for (int a = 0; a < 3; a++) {
+      d.cp[a] = d.c0[a];
+      d.Up[a] = d.U[a];
+      d.Wp[a] = d.W[a];
+    }
     if (d.moving && (method == LBM_IBM || q.kind == LBM_PLANE))
       return set_err(c, "translating solids need IBB and a sphere or cylinder"), LBM_EUNSUPPORTED;
     if (d.moving) {
@@ -510,6 +534,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->nsolid = n;
   c->method = method;
   c->any_moving = moving;
+  c->any_free = any_free;
   c->max_box_chunks = mbc;
   // the link masks of the count pass live in the staging region (4 N doubles) while links are built
   c->mask_cells = mask_total * 4 <= (uint64_t)4 * c->N * 8 ? mask_total : 0;
@@ -527,6 +552,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->lag_user = false;
   HIPCALL(hipMemcpyAsync(c->ws + c->L.solids, ds.data(), sizeof(DevSolid) * ds.size(), hipMemcpyHostToDevice,
                          c->stream));
+  HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 6 * sizeof(uint32_t), 0, sizeof(uint32_t), c->stream));  // free-solid flag
   HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));
   if (n == 0) {
     HIPCALL(hipStreamSynchronize(c->stream));
@@ -859,6 +885,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       launch_ibb(c, B, A, c->t);
       if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
+        if (c->any_free) launch_free_update(c, c->t);
         launch_classify(c, c->t + 1, false);
         launch_refill(c, c->t + 1, B);
         launch_link_count(c, c->t + 1);
@@ -894,7 +921,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (st != LBM_OK) return st;
   }
   if (ibb && c->any_moving && nsteps > 0) {
-    uint32_t misc[5];
+    uint32_t misc[7];
     std::vector<SolidLinks> sl((size_t)c->nsolid);
     HIPCALL(hipMemcpyAsync(misc, c->ws + c->L.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream));
     HIPCALL(hipMemcpyAsync(sl.data(), c->ws + c->L.solid_links, sizeof(SolidLinks) * c->nsolid,
@@ -903,6 +930,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     c->nlinks = misc[0];
     if (misc[1]) return set_err(c, "more boundary links than max_links"), LBM_ENOMEM;
     if (misc[4]) return set_err(c, "more uncovered nodes in one step than the refill list holds"), LBM_ENOMEM;
+    if (misc[6]) return set_err(c, "a free solid reached half a cell per step"), LBM_EDIVERGED;
     for (auto &q : sl)
       if ((int32_t)q.nchunks > c->k5_chunks)
         return set_err(c, "a translating solid outgrew its link headroom"), LBM_ENOMEM;
@@ -953,6 +981,34 @@ lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type) {
   if (u) HIPCALL(hipMemcpyAsync(u, stg + N, 3 * N * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCALL(hipStreamSynchronize(c->stream));
   if (node_type) return node_types_at(c, node_type, !c->fresh && c->any_moving);
+  return LBM_OK;
+}
+
+lbm_status lbm_solid_state(lbm_ctx *c, double *state) {
+  if (!c || (!state && c->nsolid > 0)) return LBM_EINVAL;
+  if (c->nsolid <= 0) return LBM_OK;
+  std::vector<DevSolid> ds((size_t)c->nsolid);
+  HIPCALL(hipMemcpyAsync(ds.data(), c->ws + c->L.solids, sizeof(DevSolid) * ds.size(), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->nsolid; k++) {
+    const DevSolid &d = ds[(size_t)k];
+    for (int a = 0; a < 3; a++) {
+      // the device's centre_at, on the host
+      double y = d.c0[a];
+      if (d.moving && a < c->D) {
+        const double L = (double)dim_of(c, a);
+        y = d.c0[a] + (double)(c->t - d.tref) * d.U[a];
+        if (!(y >= 0.0 && y < L)) {
+          y = std::fmod(y, L);
+          if (y < 0.0) y = y + L;
+        }
+      }
+      state[9 * k + a] = y;
+      state[9 * k + 3 + a] = d.U[a];
+      state[9 * k + 6 + a] = d.W[a];
+    }
+  }
   return LBM_OK;
 }
 

@@ -48,7 +48,7 @@ class lbm_params(ctypes.Structure):
 class lbm_solid(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("inverted", ctypes.c_int32), ("centre", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("axis", ctypes.c_double * 3), ("velocity", ctypes.c_double * 3),
-                ("omega", ctypes.c_double * 3)]
+                ("omega", ctypes.c_double * 3), ("density", ctypes.c_double), ("gravity", ctypes.c_double * 3)]
 
 
 class lbm_ibm_opts(ctypes.Structure):
@@ -80,6 +80,7 @@ _sig("lbm_force_history", _st, [_vp, _i64, _i64, _d])
 _sig("lbm_history_capacity", _i64, [])
 _sig("lbm_macros", _st, [_vp, _d, _d, ctypes.POINTER(ctypes.c_uint8)])
 _sig("lbm_strain", _st, [_vp, _d, _d])
+_sig("lbm_solid_state", _st, [_vp, _d])
 _sig("lbm_get_f", _st, [_vp, _d])
 _sig("lbm_set_f", _st, [_vp, _d])
 _sig("lbm_get_state", _st, [_vp, _vp])
@@ -119,7 +120,7 @@ _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_batch_destroy", _st, [_vp])
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
-            "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_strain", "lbm_get_f",
+            "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_strain", "lbm_solid_state", "lbm_get_f",
             "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
             "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_autotune_policy", "lbm_batch_table_bytes", "lbm_batch_create",
@@ -169,11 +170,14 @@ def make_solids(solids):
         ax = list(s.get("axis", (0, 0, 1))) + [0.0] * 3
         v = list(s.get("velocity", (0, 0, 0))) + [0.0] * 3
         w = list(s.get("omega", (0, 0, 0))) + [0.0] * 3
+        gr = list(s.get("gravity", (0, 0, 0))) + [0.0] * 3
         for a in range(3):
             arr[k].centre[a] = float(c[a])
             arr[k].axis[a] = float(ax[a])
             arr[k].velocity[a] = float(v[a])
             arr[k].omega[a] = float(w[a])
+            arr[k].gravity[a] = float(gr[a])
+        arr[k].density = float(s.get("density", 0.0))
         arr[k].radius = float(s.get("radius", 0.0))
     return arr
 
@@ -234,6 +238,12 @@ class _Context:
         t = np.empty(self.N, dtype=np.uint8)
         self._check(_lib.lbm_macros(self.handle, _ptr(rho), _ptr(u), _ptr(t, ctypes.c_uint8)))
         return rho, u, t
+
+    def solid_state(self):
+        """[n][9]: centre, velocity and angular velocity of every solid now."""
+        out = np.zeros((max(self.nsolid, 1), 9))
+        self._check(_lib.lbm_solid_state(self.handle, _ptr(out)))
+        return out[: self.nsolid]
 
     def strain(self):
         """Strain rate [6][N] (xx, yy, zz, xy, yz, xz) and dissipation [N] of the last collision (Eq. 19)."""

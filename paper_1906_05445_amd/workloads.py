@@ -23,12 +23,14 @@ PHI = (1.0 + math.sqrt(5.0)) / 2.0
 
 
 def solid(kind="sphere", centre=(0.0, 0.0, 0.0), radius=1.0, axis=(0.0, 0.0, 1.0), inverted=False,
-          velocity=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0)):
-    """Solid description understood by both the GPU binding and the oracle."""
+          velocity=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0), density=0.0, gravity=(0.0, 0.0, 0.0)):
+    """Solid description understood by both the GPU binding and the oracle.  density > 0: a free solid
+    with that density ratio to the fluid and external acceleration gravity (velocity, omega: initial)."""
     c = list(map(float, centre)) + [0.0] * (3 - len(centre))
     return {"kind": kind, "inverted": bool(inverted), "centre": tuple(c[:3]), "radius": float(radius),
             "axis": tuple(map(float, axis)), "velocity": tuple(map(float, velocity)),
-            "omega": tuple(map(float, omega))}
+            "omega": tuple(map(float, omega)), "density": float(density),
+            "gravity": tuple(map(float, gravity))}
 
 
 # --------------------------------------------------------------------------

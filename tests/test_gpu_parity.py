@@ -403,3 +403,87 @@ def test_strain_reduced_precision_and_state(lbm):
     # FP32 deviation storage: relative L2 of the strain within 1e-3 (measured below 1e-4)
     assert np.sqrt(np.sum((Sg - So) ** 2) / np.sum(So ** 2)) < 1e-3
     assert np.sqrt(np.sum((eg - eo) ** 2) / np.sum(eo ** 2)) < 2e-3
+
+
+# ----------------------------------------------------------------------------
+# freely moving solids (Eq. 20 with the Eq. 17 force and torque)
+# ----------------------------------------------------------------------------
+def _compare_state(gpu, orc, tol):
+    sg, so = gpu.solid_state(), orc.solid_state()
+    assert sg.shape == so.shape
+    dc = np.max(np.abs(sg[:, :3] - so[:, :3]))
+    dv = np.max(np.abs(sg[:, 3:] - so[:, 3:])) / max(np.max(np.abs(so[:, 3:])), 1e-300)
+    assert dc <= tol and dv <= tol, f"solid state mismatch: centre {dc:.3e}, velocities {dv:.3e}"
+
+
+@pytest.mark.parametrize("method", ["QUADRATIC", "ZHAO_YONG"])
+def test_free_sphere_fp64(lbm, method):
+    """A sphere twice as dense as the fluid falling under gravity across grid lines, in a flow driven by
+    a body force, stepped in uneven calls.  The solid's force is summed in another order on the GPU
+    (chunk partials) than in the oracle, so its trajectory agrees to rounding: links and node types
+    exactly, q and the state to 1e-12."""
+    shape = (30, 27, 25)
+    s = W.solid("sphere", (14.2, 13.1, 12.4), 5.3, density=2.0, gravity=(0.0, -1.5e-4, 8e-5),
+                velocity=(0.004, 0.0, -0.002), omega=(0.0, 0.001, 0.0))
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, g=(2e-6, 0.0, 1e-6), solids=[s], method=method)
+    for n in (1, 24, 35):
+        gpu.step(n)
+        orc.step(n)
+        _compare_fields(gpu, orc, tol_f=1e-12)
+        _compare_state(gpu, orc, 1e-12)
+    Lg, Lo = gpu.links(), orc.links()
+    for k in ("cell", "dir", "sid"):
+        assert np.array_equal(Lg[k], Lo[k]), k
+    assert np.max(np.abs(Lg["q"] - Lo["q"])) <= 1e-12
+    _compare_forces(gpu, orc, (2e-6, 0.0, 1e-6), 1e-12)
+    assert gpu.solid_state()[0, 4] < 0.0  # it falls along gravity
+
+
+def test_free_cylinder_spins_up_fp64(lbm):
+    """Free inner cylinder of a circular Couette cell (D2Q9): the rotation of the outer wall drags it
+    round (the oracle's pin: it reaches the wall's angular velocity)."""
+    n, R1, R2 = 40, 6.0, 14.0
+    c = (n / 2.0 + 0.31, n / 2.0 - 0.17, 0.0)
+    solids = [W.solid("cylinder", c, R1, density=1.0),
+              W.solid("cylinder", c, R2, inverted=True, omega=(0, 0, 0.01 / R2))]
+    gpu, orc = _pair(lbm, "D2Q9", "MRT", (n, n, 1), 1.0, solids=solids, method="QUADRATIC", rates=np.full(9, 1.0))
+    gpu.step(400)
+    orc.step(400)
+    _compare_fields(gpu, orc, tol_f=1e-12)
+    _compare_state(gpu, orc, 1e-12)
+    assert gpu.solid_state()[0, 8] > 0.0
+
+
+def test_free_sphere_fp32(lbm):
+    shape = (30, 27, 25)
+    s = W.solid("sphere", (14.2, 13.1, 12.4), 5.3, density=1.5, gravity=(0.0, -1e-4, 0.0))
+    gpu, orc = _pair(lbm, "D3Q19", "MRT", shape, 0.8, g=(2e-5, 0.0, 0.0), storage="F32", solids=[s],
+                     method="QUADRATIC")
+    gpu.step(150)
+    orc.step(150)
+    rg, ug, tg = gpu.macros()
+    ro, uo, to = orc.macros()
+    assert np.array_equal(tg, to)
+    fl = tg != 1
+    # fluid: the reduced-precision bar; solid nodes report the wall velocity of a solid whose own
+    # velocity follows the FP32 forces (1e-4 below)
+    assert np.sqrt(np.sum((ug[:, fl] - uo[:, fl]) ** 2) / np.sum(uo[:, fl] ** 2)) <= 2e-5
+    assert np.max(np.abs(ug[:, ~fl] - uo[:, ~fl])) <= 1e-4 * np.max(np.abs(uo[:, ~fl]))
+    sg, so = gpu.solid_state()[0], orc.solid_state()[0]
+    assert np.max(np.abs(sg[3:6] - so[3:6])) <= 1e-4 * np.max(np.abs(so[3:6]))
+    assert np.max(np.abs(sg[:3] - so[:3])) <= 1e-6
+
+
+def test_free_solid_rejections(lbm):
+    free = W.solid("sphere", (8.2, 7.9, 8.1), 3.5, density=1.5)
+    g = lbm.Lattice("D3Q19", "MRT", "F64", (16, 16, 16), 0.8)
+    with pytest.raises(lbm.LBMError):
+        g.set_solids([free], "IBM")
+    with pytest.raises(lbm.LBMError):
+        g.set_solids([W.solid("sphere", (8.2, 7.9, 8.1), 6.5, inverted=True, density=1.5)], "QUADRATIC")
+    g.close()
+    b = lbm.Batch("D3Q19", "F64", max_slots=1, pool_bytes=1 << 26)
+    m = b.admit("MRT", "F64", (16, 16, 16), 0.8)
+    with pytest.raises(lbm.LBMError):
+        m.set_solids([free], "QUADRATIC")
+    b.close()
