@@ -268,20 +268,29 @@ __device__ inline void link_scan_body(const LinkArgs &a, int nsolid) {
   const uint32_t b0 = threadIdx.x * per, b1 = min(total, b0 + per);
   uint32_t s = 0;
   for (uint32_t k = b0; k < b1; k++) s += a.box_counts[k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (uint32_t k = 0; k < blockDim.x; k++) {
-      const uint32_t v = part[k];
-      part[k] = run;
-      run += v;
-    }
-    a.misc[0] = run;
-    a.misc[1] = run > a.max_links ? 1u : 0u;
+  // exclusive scan of the per-thread sums over the block (integer: any order
+  // gives the same offsets): inclusive within each wavefront, then the
+  // wavefront totals
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += v;
   }
+  if (lane == 63) part[wv] = inc;
   __syncthreads();
-  uint32_t run = part[threadIdx.x];
+  uint32_t base = 0, all = 0;
+  for (int k = 0; k < nw; k++) {
+    const uint32_t v = part[k];
+    if (k < wv) base += v;
+    all += v;
+  }
+  if (threadIdx.x == 0) {
+    a.misc[0] = all;
+    a.misc[1] = all > a.max_links ? 1u : 0u;
+  }
+  uint32_t run = base + inc - s;
   for (uint32_t k = b0; k < b1; k++) {
     const uint32_t v = a.box_counts[k];
     a.box_offsets[k] = run;
@@ -447,26 +456,24 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, const S *__restri
   ibb_body<Q, S>(P, pre, a, a.g.t, blockIdx.x, blockIdx.y);
 }
 
-// Free solids (Eq. 20, fluid density rho0 = 1, dt = 1), one thread per solid,
-// after the force/torque of step t is in its history slot: v' = v + (F +
-// (rho_p - 1) V_p g) / (rho_p V_p), w' = w + T / I_p, centre' = centre +
-// (v + v')/2 wrapped into the box; the state of step t is kept in cp, Up, Wp
-// (the geometry of the collision at t, for the macroscopic readout).  Writes
-// with vector stores; kernels launched after it read the new table.  flag:
-// set when a velocity component reaches half a cell per step.
-__global__ void k_free_update(DevSolid *solids, int nsolid, const double *hist, Box3 b, int64_t t, uint32_t *flag) {
+// Free solid k (Eq. 20, fluid density rho0 = 1, dt = 1) after the force and
+// torque FT of step t are known: v' = v + (F + (rho_p - 1) V_p g) /
+// (rho_p V_p), w' = w + T / I_p, centre' = centre + (v + v')/2 wrapped into
+// the box; the state of step t is kept in cp, Up, Wp (the geometry of the
+// collision at t, for the macroscopic readout).  Vector stores; kernels
+// launched after it read the new table.  flag: set when a velocity component
+// reaches half a cell per step.
+__device__ inline void free_update_one(DevSolid *solids, int k, const double FT[6], const Box3 &b, int64_t t,
+                                       uint32_t *flag) {
 #pragma clang fp contract(off)
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nsolid) return;
   const DevSolid s = solids[k];
   if (!s.free) return;
-  const double *F = hist + 6 * k, *T = F + 3;
   const double m = s.rho_p * s.Vp;
   double c[3], vn[3], wn[3], cn[3];
   solid_centre(s, t, b, c);
   for (int a = 0; a < 3; a++) {
-    vn[a] = s.U[a] + (F[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
-    wn[a] = s.W[a] + T[a] / s.Ip;
+    vn[a] = s.U[a] + (FT[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
+    wn[a] = s.W[a] + FT[3 + a] / s.Ip;
   }
   if (b.D == 2) {
     vn[2] = 0.0;
@@ -498,11 +505,16 @@ __global__ void k_free_update(DevSolid *solids, int nsolid, const double *hist, 
   o.tref = t + 1;
 }
 
-void launch_free_update(lbm_ctx *c, int64_t t) {
-  const FtReduceArgs r = ft_reduce_args(c, t);
-  const Box3 b{c->p.nx, c->p.ny, c->p.nz, c->D};
-  hipLaunchKernelGGL(k_free_update, dim3((uint32_t)((c->nsolid + 63) / 64)), dim3(64), 0, c->stream,
-                     c->at<DevSolid>(c->L.solids), c->nsolid, r.hist, b, t, c->at<uint32_t>(c->L.misc) + 6);
+// Force/torque of step t per solid (as k_ft_reduce) and, by the lane that
+// wrote them, the free motion of that solid from the same values.
+__global__ __launch_bounds__(256) void k_ft_reduce_free(FtReduceArgs r, DevSolid *solids, Box3 b, int64_t t,
+                                                        uint32_t *flag) {
+  ft_reduce_waves(r, blockIdx.x);
+  const int s = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if ((threadIdx.x & 63) != 0 || s >= r.nsolid) return;
+  double FT[6];
+  for (int k = 0; k < 6; k++) FT[k] = r.hist[(uint64_t)s * 6 + k];  // this thread's own stores
+  free_update_one(solids, s, FT, b, t, flag);
 }
 
 // Per-solid force/torque: one wavefront per solid sums that solid's chunk
@@ -950,6 +962,16 @@ void launch_ft_reduce(lbm_ctx *c, int64_t t) {
   FtReduceArgs r = ft_reduce_args(c, t);
   r.partials = partials_of(c, t);
   hipLaunchKernelGGL(k_ft_reduce, dim3((uint32_t)((c->nsolid + 3) / 4)), dim3(256), 0, c->stream, r);
+}
+
+// Free solids: the force reduction of step t and the motion update in one launch
+// (a solid without links gets zero force and moves under its weight alone).
+void launch_ft_reduce_free(lbm_ctx *c, int64_t t) {
+  FtReduceArgs r = ft_reduce_args(c, t);
+  r.partials = partials_of(c, t);
+  const Box3 b{c->p.nx, c->p.ny, c->p.nz, c->D};
+  hipLaunchKernelGGL(k_ft_reduce_free, dim3((uint32_t)((c->nsolid + 3) / 4)), dim3(256), 0, c->stream, r,
+                     c->at<DevSolid>(c->L.solids), b, t, c->at<uint32_t>(c->L.misc) + 6);
 }
 
 double *partials_of(lbm_ctx *c, int64_t t) { return c->at<double>((t & 1) ? c->L.partials2 : c->L.partials); }

@@ -883,9 +883,9 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
     if (ibb) {
       launch_ibb(c, B, A, c->t);
-      if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
+      if (c->any_free) launch_ft_reduce_free(c, c->t);  // force of step t, then the motion to t+1
+      else if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
-        if (c->any_free) launch_free_update(c, c->t);
         launch_classify(c, c->t + 1, false);
         launch_refill(c, c->t + 1, B);
         launch_link_count(c, c->t + 1);

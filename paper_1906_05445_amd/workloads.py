@@ -164,6 +164,21 @@ def sphere_box(n=128, R=16.2, Re=20.0, tau=0.8, seed=2, method="QUADRATIC", stor
                 method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U}, delta=delta)
 
 
+def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, storage="F32", steps=5000):
+    """A free sphere settling under gravity in a periodic cube (the density ratio of the paper's
+    sedimentation case, Sec. 3.2), quadratic IBB.  Gravity from the Stokes estimate of a settling speed
+    U_set; the fluid carries the opposite body force, so that no net force drives the box."""
+    rng = np.random.default_rng(seed)
+    c = np.array([n / 2.0] * 3) + rng.random(3)
+    nu = nu_of_tau(tau)
+    Vp = 4.0 / 3.0 * math.pi * R ** 3
+    gz = -6.0 * math.pi * nu * R * U_set / ((density - 1.0) * Vp)
+    g_fluid = -(density - 1.0) * Vp * gz / (n ** 3 - Vp)
+    return Case(f"settle_{n}", "D3Q19", "MRT", (n, n, n), tau, (0.0, 0.0, g_fluid),
+                [solid("sphere", c, R, density=density, gravity=(0.0, 0.0, gz))], "QUADRATIC", steps, storage,
+                meta={"U_set": U_set, "density": density})
+
+
 def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, storage="F64", steps=10000,
                 method="QUADRATIC"):
     """Random sequential addition of non-overlapping spheres (periodic gap >= gap)."""
