@@ -259,6 +259,23 @@ __global__ __launch_bounds__(kBlock) void k_link_count(LinkArgs a) {
   link_count_body<Q>(a, blockIdx.x, blockIdx.y);
 }
 
+// Refill and link count of a single context in one launch: both read only the
+// finished classification (the refill writes populations, the count flags and
+// owners it does not touch).  Blocks 0 .. kRefillBlocks-1 walk the refill list,
+// the others are the count pass's (box chunk, solid) units.
+constexpr uint32_t kRefillBlocks = 64;
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_refill_count(LinkArgs a) {
+  if (blockIdx.x < kRefillBlocks) {
+    const uint32_t cnt = min(a.misc[3], a.max_refill);
+    for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += kRefillBlocks * 4)
+      refill_wave<Q, S>(a, a.refill_list[e]);
+    return;
+  }
+  const uint32_t u = blockIdx.x - kRefillBlocks, per = a.max_box_chunks;
+  link_count_body<Q>(a, u % per, (int)(u / per));
+}
+
 // One block: exclusive scan of the per-(solid, box chunk) counts, then the
 // per-solid link ranges and chunk bases of the bounce-back kernel.
 __device__ inline void link_scan_body(const LinkArgs &a, int nsolid) {
@@ -905,6 +922,23 @@ void launch_refill(lbm_ctx *c, int64_t t, void *post) {
     else LBM_RF(19, _Float16);
   }
 #undef LBM_RF
+}
+
+void launch_refill_count(lbm_ctx *c, int64_t t, void *post) {
+  LinkArgs a = link_args(c, t);
+  a.post = post;
+  const dim3 grid(kRefillBlocks + (uint32_t)c->max_box_chunks * (uint32_t)c->nsolid);
+#define LBM_RC(QQ, SS) hipLaunchKernelGGL((k_refill_count<QQ, SS>), grid, dim3(kBlock), 0, c->stream, a)
+  if (c->Q == 9) {
+    if (c->p.storage == LBM_F64) LBM_RC(9, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_RC(9, float);
+    else LBM_RC(9, _Float16);
+  } else {
+    if (c->p.storage == LBM_F64) LBM_RC(19, double);
+    else if (c->p.storage == LBM_F32_DEV) LBM_RC(19, float);
+    else LBM_RC(19, _Float16);
+  }
+#undef LBM_RC
 }
 
 void launch_link_count(lbm_ctx *c, int64_t t) {

@@ -201,6 +201,7 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0 
                   int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
+void launch_refill_count(lbm_ctx *c, int64_t t, void *post);
 void launch_ft_reduce_free(lbm_ctx *c, int64_t t);
 void launch_strain(lbm_ctx *c, const void *src, double *out, int part);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);

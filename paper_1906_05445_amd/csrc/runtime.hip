@@ -887,8 +887,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       else if (k == nsteps - 1 || c->any_moving) launch_ft_reduce(c, c->t);
       if (c->any_moving) {
         launch_classify(c, c->t + 1, false);
-        launch_refill(c, c->t + 1, B);
-        launch_link_count(c, c->t + 1);
+        launch_refill_count(c, c->t + 1, B);
         launch_link_scan(c);
         launch_link_emit(c, c->t + 1);
       }
