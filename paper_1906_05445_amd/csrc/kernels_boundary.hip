@@ -109,11 +109,10 @@ __global__ void k_classify_full(uint8_t *flags, uint16_t *owner, uint16_t *owner
 }
 
 // Moving solids, phase 1 over their boxes: remember the current geometry.
+// (The refill list of a step starts empty: the link emit pass of the step
+// before, the last reader of its count misc[3], clears it.  The overflow flag
+// misc[4] stays set until lbm_set_solids.)
 __device__ inline void classify_keep_body(const LinkArgs &a, uint32_t bx, int s) {
-  if (bx == 0 && s == 0 && threadIdx.x == 0) {  // the refill list of this step starts empty
-    a.misc[3] = 0;
-    a.misc[4] = 0;
-  }
   const DevSolid sd = load_uniform(&a.g.solids[s]);
   if (!sd.moving) return;
   int o[3], x, y, z;
@@ -150,6 +149,12 @@ __device__ inline void classify_box_body(const LinkArgs &a, uint32_t bx, int s) 
 }
 __global__ void k_classify_keep(LinkArgs a) { classify_keep_body(a, blockIdx.x, blockIdx.y); }
 __global__ void k_classify_box(LinkArgs a) { classify_box_body(a, blockIdx.x, blockIdx.y); }
+// One solid: no other solid's box can meet this one's, so each box cell is one
+// thread's in both phases, which then run back to back in that thread.
+__global__ void k_classify_one(LinkArgs a) {
+  classify_keep_body(a, blockIdx.x, 0);
+  classify_box_body(a, blockIdx.x, 0);
+}
 
 void launch_classify(lbm_ctx *c, int64_t t, bool full);
 
@@ -361,6 +366,7 @@ constexpr int kEmitWindow = 1024;  // links of one unit staged in LDS at a time
 // link per thread, and writes them.
 template <int Q>
 __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
+  if (bx == 0 && s == 0 && threadIdx.x == 0) a.misc[3] = 0;  // the next step's refill list starts empty
   __shared__ uint32_t wsum[kBlock / 64];
   __shared__ uint32_t st_cell[kEmitWindow];
   __shared__ uint8_t st_dir[kEmitWindow];
@@ -903,6 +909,10 @@ void launch_classify(lbm_ctx *c, int64_t t, bool full) {
     return;
   }
   LinkArgs a = link_args(c, t);
+  if (c->nsolid == 1) {
+    hipLaunchKernelGGL(k_classify_one, dim3((uint32_t)c->max_box_chunks), dim3(kBlock), 0, c->stream, a);
+    return;
+  }
   const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
   hipLaunchKernelGGL(k_classify_keep, grid, dim3(kBlock), 0, c->stream, a);
   hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, a);

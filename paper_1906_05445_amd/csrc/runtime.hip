@@ -552,7 +552,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->lag_user = false;
   HIPCALL(hipMemcpyAsync(c->ws + c->L.solids, ds.data(), sizeof(DevSolid) * ds.size(), hipMemcpyHostToDevice,
                          c->stream));
-  HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 6 * sizeof(uint32_t), 0, sizeof(uint32_t), c->stream));  // free-solid flag
+  // the refill count and overflow flag (misc[3], misc[4]) and the free-solid flag (misc[6])
+  HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 3 * sizeof(uint32_t), 0, 4 * sizeof(uint32_t), c->stream));
   HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));
   if (n == 0) {
     HIPCALL(hipStreamSynchronize(c->stream));
