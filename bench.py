@@ -11,10 +11,13 @@ reduction.  MLUPS counts every lattice cell.
 Also reported (same JSON line): the FP64 and FP16 forms of that workload,
 the direct-forcing IBM form (5 forcing iterations per step), the 256^3 box
 with 64 spheres (working set far beyond the 256 MB Infinity Cache), the
-achievable HBM copy bandwidth, 512 lattices with translating spheres stepped
-as one batch, the request trace served for a bounded window at the trace's
-own rate (saturated) and at a rate below capacity, and the FP64 CPU oracle
-timed on a bounded sample of the value workload.
+other bounce-back schemes (Yu's, Zhao & Yong's single-node one) on both
+boxes, the IBM with the 3- and 2-point delta functions, a free sphere
+settling under gravity (its link set rebuilt every step), the achievable HBM
+copy bandwidth, 512 lattices with translating spheres stepped as one batch,
+the request trace served for a bounded window at the trace's own rate
+(saturated) and at a rate below capacity, and the FP64 CPU oracle timed on a
+bounded sample of the value workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -331,7 +334,8 @@ def main():
                             ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
                                                                           "retraction": 0.3})),
                             ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
-                                                                          "retraction": 0.2}))]:
+                                                                          "retraction": 0.2})),
+                            ("settle128_f32_free", (W.settling_sphere, {}))]:
         if "schemes" in want or key in want:
             case = ctor(storage="F32", **kw)
             k = max(K // 2, 100) if "256" not in key else max(K // 8, 50)
