@@ -364,10 +364,26 @@ constexpr int kEmitWindow = 1024;  // links of one unit staged in LDS at a time
 // direction) in LDS at their place in the unit's order (by cell, then
 // direction), then the whole block computes q and the x_ff / x_fff bits, one
 // link per thread, and writes them.
-template <int Q>
+// Sum over the threads of a 256-thread block (every thread gets it).
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t *lds4) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) lds4[wv] = v;
+  __syncthreads();
+  uint32_t all = 0;
+  for (int k = 0; k < kBlock / 64; k++) all += lds4[k];
+  return all;
+}
+
+// ONE: a context with a single solid, whose link offsets need no scan pass:
+// each block sums the counts of the box chunks before its own, and block 0
+// also writes the solid's link range and the total (what the scan writes).
+template <int Q, bool ONE = false>
 __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
   if (bx == 0 && s == 0 && threadIdx.x == 0) a.misc[3] = 0;  // the next step's refill list starts empty
   __shared__ uint32_t wsum[kBlock / 64];
+  __shared__ uint32_t wsum2[kBlock / 64];
   __shared__ uint32_t st_cell[kEmitWindow];
   __shared__ uint8_t st_dir[kEmitWindow];
   const DevSolid sd = load_uniform(&a.g.solids[s]);
@@ -388,7 +404,26 @@ __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
   uint32_t total;
   const uint32_t before = block_exclusive_scan((uint32_t)__popc(m), wsum, &total);
   if (bx >= a.max_box_chunks) return;  // uniform over the block
-  const uint64_t base = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx];
+  uint64_t base;
+  if constexpr (ONE) {
+    const uint32_t lim = bx == 0 ? a.max_box_chunks : bx;
+    uint32_t v = 0;
+    for (uint32_t k = threadIdx.x; k < lim; k += kBlock) v += a.box_counts[k];
+    const uint32_t sum = block_sum_u32(v, wsum2);
+    base = bx == 0 ? 0 : sum;
+    if (bx == 0 && threadIdx.x == 0) {
+      SolidLinks L;
+      L.start = 0;
+      L.count = sum;
+      L.chunk_base = 0;
+      L.nchunks = (sum + kLinkChunk - 1) / kLinkChunk;
+      a.sl[0] = L;
+      a.misc[0] = sum;
+      a.misc[1] = sum > a.max_links ? 1u : 0u;
+    }
+  } else {
+    base = a.box_offsets[(uint64_t)s * a.max_box_chunks + bx];
+  }
   for (uint32_t w0 = 0; w0 < total; w0 += kEmitWindow) {
     uint32_t k = before, mm = m;
     while (mm) {
@@ -422,6 +457,10 @@ __device__ inline void link_emit_body(const LinkArgs &a, uint32_t bx, int s) {
 template <int Q>
 __global__ __launch_bounds__(kBlock) void k_link_emit(LinkArgs a) {
   link_emit_body<Q>(a, blockIdx.x, blockIdx.y);
+}
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_link_emit_one(LinkArgs a) {
+  link_emit_body<Q, true>(a, blockIdx.x, 0);
 }
 
 // ----------------------------------------------------------------------------
@@ -965,6 +1004,12 @@ void launch_link_scan(lbm_ctx *c) {
 
 void launch_link_emit(lbm_ctx *c, int64_t t) {
   LinkArgs a = link_args(c, t);
+  if (c->nsolid == 1) {  // offsets formed in the emit pass itself (no scan launch)
+    const dim3 g1((uint32_t)c->max_box_chunks);
+    if (c->Q == 9) hipLaunchKernelGGL(k_link_emit_one<9>, g1, dim3(kBlock), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_link_emit_one<19>, g1, dim3(kBlock), 0, c->stream, a);
+    return;
+  }
   const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
   if (c->Q == 9) hipLaunchKernelGGL(k_link_emit<9>, grid, dim3(kBlock), 0, c->stream, a);
   else hipLaunchKernelGGL(k_link_emit<19>, grid, dim3(kBlock), 0, c->stream, a);

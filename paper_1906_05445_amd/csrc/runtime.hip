@@ -889,7 +889,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       if (c->any_moving) {
         launch_classify(c, c->t + 1, false);
         launch_refill_count(c, c->t + 1, B);
-        launch_link_scan(c);
+        if (c->nsolid != 1) launch_link_scan(c);
         launch_link_emit(c, c->t + 1);
       }
     }
