@@ -103,7 +103,10 @@ def _compare_forces(gpu, orc, g, tol):
 # bit-exact pieces
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("storage", ["F64", "F32", "F16"])
-@pytest.mark.parametrize("lat,shape", [("D2Q9", (67, 45, 1)), ("D3Q19", (37, 29, 23))])
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (67, 45, 1)), ("D3Q19", (37, 29, 23)),
+                                       # widths that are multiples of 64 (a wavefront is one row); the
+                                       # last tile of 64 x 5 x 3 ends with a wavefront past the end
+                                       ("D2Q9", (128, 3, 1)), ("D3Q19", (64, 5, 3)), ("D3Q19", (192, 2, 2))])
 def test_streaming_permutation_bit_exact(lbm, lat, shape, storage):
     Q = 9 if lat == "D2Q9" else 19
     gpu = lbm.Lattice(lat, "MRT", storage, shape, 0.8, rates=np.zeros(Q))
