@@ -232,14 +232,6 @@ __device__ void refill_wave(const LinkArgs &a, uint64_t entry) {
   }
 }
 
-// Waves of the grid walk the refill list (count in misc[3]).
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void k_refill(LinkArgs a) {
-  const uint32_t cnt = min(a.misc[3], a.max_refill);
-  for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += gridDim.x * 4)
-    refill_wave<Q, S>(a, a.refill_list[e]);
-}
-
 template <int Q>
 __device__ inline void link_count_body(const LinkArgs &a, uint32_t bx, int s) {
   __shared__ double lds[16];
@@ -955,22 +947,6 @@ void launch_classify(lbm_ctx *c, int64_t t, bool full) {
   const dim3 grid((uint32_t)c->max_box_chunks, (uint32_t)c->nsolid);
   hipLaunchKernelGGL(k_classify_keep, grid, dim3(kBlock), 0, c->stream, a);
   hipLaunchKernelGGL(k_classify_box, grid, dim3(kBlock), 0, c->stream, a);
-}
-
-void launch_refill(lbm_ctx *c, int64_t t, void *post) {
-  LinkArgs a = link_args(c, t);
-  a.post = post;
-#define LBM_RF(QQ, SS) hipLaunchKernelGGL((k_refill<QQ, SS>), dim3(64), dim3(256), 0, c->stream, a)
-  if (c->Q == 9) {
-    if (c->p.storage == LBM_F64) LBM_RF(9, double);
-    else if (c->p.storage == LBM_F32_DEV) LBM_RF(9, float);
-    else LBM_RF(9, _Float16);
-  } else {
-    if (c->p.storage == LBM_F64) LBM_RF(19, double);
-    else if (c->p.storage == LBM_F32_DEV) LBM_RF(19, float);
-    else LBM_RF(19, _Float16);
-  }
-#undef LBM_RF
 }
 
 void launch_refill_count(lbm_ctx *c, int64_t t, void *post) {

@@ -211,7 +211,6 @@ void launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // kernels_boundary.hip
 void launch_classify(lbm_ctx *c, int64_t t, bool full);
-void launch_refill(lbm_ctx *c, int64_t t, void *post);
 void launch_link_count(lbm_ctx *c, int64_t t);
 void launch_link_scan(lbm_ctx *c);
 void launch_link_emit(lbm_ctx *c, int64_t t);
