@@ -86,6 +86,18 @@ def run_case(case, steps, warmup, key, torch, lbm):
     F = gpu.force_torque()
     tune = gpu.autotune_info()
     wall = t1 - t0
+    # readouts after the timed run: fluid cells, and the Reynolds number at its end
+    # (superficial velocity = mean fluid velocity times the fluid fraction, over the
+    # sphere diameter and the viscosity) against the one its body force was set for
+    _, u, types = gpu.macros()
+    fluid = types != 1
+    nfluid = int(fluid.sum())
+    re_at_end = None
+    if case.meta.get("Re") is not None and case.solids:
+        nu = (case.tau - 0.5) / 3.0
+        gdir = int(np.argmax(np.abs(case.g)))
+        u_sup = float(u[gdir][fluid].sum()) / N
+        re_at_end = u_sup * 2.0 * case.solids[0]["radius"] / nu
     per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
     timing = f"HIP events around the sweep launches of the timed run (one span per call, or every {PROFILE_EVERY}th)"
     if launches > 0:
@@ -98,8 +110,12 @@ def run_case(case, steps, warmup, key, torch, lbm):
     traffic = None if traffic_bytes is None else traffic_bytes / avg_s / 1e9
     out = {
         "mlups": N * steps / wall / 1e6,
+        "mflups_fluid": nfluid * steps / wall / 1e6,
         "ms_per_step": wall / steps * 1e3,
         "cells": N,
+        "fluid_cells": nfluid,
+        "re_target": case.meta.get("Re"),
+        "re_at_end": re_at_end,
         "solids": len(case.solids),
         "method": case.method,
         "storage": case.storage,
@@ -385,6 +401,10 @@ def main():
                    "cells": primary["cells"], "parallelism": "single GPU"},
         "roofline": primary["roofline"],
         "cpu_baseline": cpu,
+        "flow": {"re_target": primary["re_target"], "re_at_end": primary["re_at_end"],
+                 "note": "the body force is a Stokes estimate for re_target; from rest, the mean flow of "
+                         "the periodic box relaxes over about L^2/(3 nu) (5e4 steps at 128^3, tau 0.8), "
+                         "so a run of a few thousand steps ends in its start-up transient"},
         "sweep_avg_us": primary["sweep_avg_us"],
         "sweep_timing": primary["sweep_timing"],
         "autotune": primary["autotune"],
