@@ -305,7 +305,7 @@ def main():
                     help="also run the copy kernel once over this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU (a lattice is not split across GPUs here); --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
