@@ -1,7 +1,8 @@
 """Full-size workloads in the launch configuration bench.py times, through the C ABI.
 
 * 256^3 box with 64 spheres (gaps down to 2 lattice units, 296k boundary links), FP64 storage,
-  quadratic interpolated bounce-back: node classification, link set and q bit-exact against the FP64
+  quadratic and single-node (Zhao-Yong) interpolated bounce-back: node classification, link set and q
+  bit-exact against the FP64
   oracle, fields (max|du|/max|u|, max|drho|) and per-sphere force/torque at 1e-12 after two steps
   (the oracle needs about half a minute per step at this size).
 * 512 lattices with translating spheres stepped as one FP32 batch (the batching workload, about
@@ -28,10 +29,11 @@ def lbm():
 
 
 @pytest.mark.timeout(600)
-def test_pack256_fp64_against_oracle(lbm):
+@pytest.mark.parametrize("method", ["QUADRATIC", "ZHAO_YONG"])
+def test_pack256_fp64_against_oracle(lbm, method):
     from oracle import Oracle
 
-    case = W.sphere_pack(storage="F64")
+    case = W.sphere_pack(storage="F64", method=method)
     print(f"pack256: {case.shape}, {len(case.solids)} spheres", flush=True)
     gpu = lbm.Lattice(case.lattice, case.collision, "F64", case.shape, case.tau, g=case.g,
                       max_solids=len(case.solids))

@@ -339,6 +339,7 @@ def test_full_size_sphere_128(lbm, storage, method):
     if storage == "F64":
         _compare_fields(gpu, orc)
         _compare_forces(gpu, orc, case.g, 1e-12)
+        _compare_strain(gpu, orc, 1e-9)  # Eq. 19 readout at full size
     else:
         _compare_fields(gpu, orc, tol_u=1e-5, tol_rho=1e-6, tol_f=None, rel_l2=True)
 
