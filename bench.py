@@ -400,6 +400,11 @@ def main():
                                "body force, quadratic IBB + momentum-exchange force, FP32 deviation storage",
                    "cells": primary["cells"], "parallelism": "single GPU"},
         "roofline": primary["roofline"],
+        "mflups_fluid": primary["mflups_fluid"],
+        "sweep_vs_copy": (None if "hbm_copy_GBps" not in extras else
+                          {"copy_GBps": extras["hbm_copy_GBps"],
+                           "frac": primary["roofline"]["achieved"] / extras["hbm_copy_GBps"],
+                           "note": "sweep algorithmic GB/s over the copy kernel's measured GB/s"}),
         "cpu_baseline": cpu,
         "flow": {"re_target": primary["re_target"], "re_at_end": primary["re_at_end"],
                  "note": "the body force is a Stokes estimate for re_target; from rest, the mean flow of "
