@@ -30,7 +30,10 @@
  *   7. moving IBB solids only: advance the solid (prescribed translation, or
  *      free motion by Eq. 20 under the force and torque of step 6), reclassify,
  *      refill the newly uncovered nodes and rebuild the boundary links
- *      (Sec. 3.2).
+ *      (Sec. 3.2).  Moving IBM solids: advance the solid (prescribed
+ *      translation, or free motion by Feng & Michaelides's discretisation,
+ *      Eq. 23, under the force and torque of step 3) and carry its Lagrangian
+ *      points with it.
  *
  * Populations are stored as deviations h_i = f_i - w_i from the rest state
  * (rho = 1, u = 0).  Every relation used is linear in f apart from f_eq, and
@@ -50,7 +53,9 @@
  * with halfway bounce-back, second-order IBB convergence, steady Couette
  * (App. A, Eq. 31) and its torque, pipe flow (Eq. 28), delta-function moment
  * identities (App. B), interpolation/spreading invariants, link
- * classification and q by exact arithmetic on tiny grids.
+ * classification and q by exact arithmetic on tiny grids; free IBM solids by
+ * the closed-form solution of the Eq. 23 recurrence without fluid force and
+ * by the exact balance of fluid plus solid momentum (tests/test_oracle_free_ibm.py).
  *
  * PARITY UNPINNED (no closed form or independent reference exists): the
  * coupling reading of the IBM (which velocity is interpolated, force factor 1,
@@ -110,6 +115,10 @@ typedef struct {
    * (gravity), volume and moment of inertia of the solid */
   int free;
   double rho_p, grav[3], Vp, Ip;
+  /* IBM: displacement of the solid since its Lagrangian points were placed
+   * (unwrapped; the points move rigidly with it), and the velocities of the
+   * step before (Eq. 23 reads v^{n-1}, w^{n-1}) */
+  double disp[3], Up[3], Wp[3];
 } solid_t;
 
 typedef struct {
@@ -603,11 +612,22 @@ static void stencil_of(const orc *o, const double X[3], stencil_t *st) {
       }
 }
 
+/* Position of Lagrangian point l now: where it was placed, moved with its
+ * solid (rigid translation; the points of a sphere or cylinder keep their
+ * orientation, which the shape does not see). */
+static void lag_pos(const orc *o, long l, double X[3]) {
+  const solid_t *s = &o->sol[o->lag_sid[l]];
+  for (int a = 0; a < 3; a++) X[a] = o->X[3 * l + a] + s->disp[a];
+  if (o->D == 2) X[2] = 0.0;
+}
+
 /* Eq. 5: U(X_l) = sum_x u(x) delta_h(x - X_l) h^3, with h = 1. */
 static void interpolate(const orc *o, const double *u, double *Ut) {
   for (long l = 0; l < o->nlag; l++) {
     stencil_t st;
-    stencil_of(o, &o->X[3 * l], &st);
+    double X[3];
+    lag_pos(o, l, X);
+    stencil_of(o, X, &st);
     double s[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < st.n; k++)
       for (int a = 0; a < 3; a++) s[a] += u[a * o->N + st.cell[k]] * st.wgt[k];
@@ -619,7 +639,9 @@ static void interpolate(const orc *o, const double *u, double *Ut) {
 static void spread(const orc *o, const double *F, double *f) {
   for (long l = 0; l < o->nlag; l++) {
     stencil_t st;
-    stencil_of(o, &o->X[3 * l], &st);
+    double X[3];
+    lag_pos(o, l, X);
+    stencil_of(o, X, &st);
     for (int k = 0; k < st.n; k++)
       for (int a = 0; a < 3; a++) f[a * o->N + st.cell[k]] += F[3 * l + a] * st.wgt[k] * o->dV[l];
   }
@@ -651,8 +673,9 @@ static void ibm_force(orc *o, const double *rho, const double *j, const double *
     interpolate(o, u, Ut);
     for (long l = 0; l < o->nlag; l++) {
       const solid_t *s = &o->sol[o->lag_sid[l]];
-      double r[3], Ud[3];
-      lever(o, s, o->X[3 * l], o->X[3 * l + 1], o->X[3 * l + 2], r);
+      double r[3], Ud[3], X[3];
+      lag_pos(o, l, X);
+      lever(o, s, X[0], X[1], X[2], r);
       wall_velocity(s, r, Ud);
       for (int a = 0; a < 3; a++) Fk[3 * l + a] = Ud[a] - Ut[3 * l + a];
       if (o->D == 2) Fk[3 * l + 2] = 0.0;
@@ -669,8 +692,9 @@ static void ibm_force(orc *o, const double *rho, const double *j, const double *
   for (long l = 0; l < o->nlag; l++) {
     int k = o->lag_sid[l];
     const solid_t *s = &o->sol[k];
-    double r[3], F[3];
-    lever(o, s, o->X[3 * l], o->X[3 * l + 1], o->X[3 * l + 2], r);
+    double r[3], F[3], X[3];
+    lag_pos(o, l, X);
+    lever(o, s, X[0], X[1], X[2], r);
     for (int a = 0; a < 3; a++) F[a] = -o->Flag[3 * l + a] * o->dV[l];
     acc_add(&acc[6 * k + 0], F[0]);
     acc_add(&acc[6 * k + 1], F[1]);
@@ -792,8 +816,13 @@ int orc_set_solids(orc *o, int n, const int *kind, const int *inverted, const do
       for (int a = 0; a < o->D; a++)
         if (!(s->c0[a] >= 0.0 && s->c0[a] < (double)dims_of(o, a)) && !(s->kind == K_CYLINDER && a == s->ax))
           return -1;
+    for (int a = 0; a < 3; a++) {
+      s->disp[a] = 0.0;
+      s->Up[a] = s->U[a];
+      s->Wp[a] = s->W[a];
+    }
     s->moving = (s->U[0] != 0.0 || s->U[1] != 0.0 || s->U[2] != 0.0);
-    if (s->moving && (method == M_IBM || s->kind == K_PLANE)) return -5;
+    if (s->moving && (s->kind == K_PLANE || (method == M_IBM && s->inverted))) return -5;
   }
   free(o->FT);
   o->FT = (double *)calloc(6 * (n > 0 ? n : 1), sizeof(double));
@@ -823,14 +852,15 @@ int orc_set_lagrangian(orc *o, int sid, const double *X, long n, double dV) {
 void orc_clear_lagrangian(orc *o) { o->nlag = 0; }
 void orc_set_ibm_iters(orc *o, int n_iter) { o->n_iter = n_iter; }
 
-/* Make solid k free (Eq. 20) with density ratio rho_p / rho_f and external
- * acceleration g; its velocity and angular velocity start at the values
- * given to orc_set_solids.  Spheres, and cylinders in D2Q9; not inverted;
- * interpolated bounce-back only.  -1 invalid, -5 unsupported. */
+/* Make solid k free (Eq. 20 with bounce-back, Eq. 23 with the IBM) with
+ * density ratio rho_p / rho_f and external acceleration g; its velocity and
+ * angular velocity start at the values given to orc_set_solids, and so do
+ * those of the step before.  Spheres, and cylinders in D2Q9; not inverted.
+ * -1 invalid, -5 unsupported. */
 int orc_set_free(orc *o, int k, double rho_p, const double *g) {
   if (k < 0 || k >= o->nsolid || !(rho_p > 0.0)) return -1;
   solid_t *s = &o->sol[k];
-  if (o->method == M_IBM || s->inverted || s->kind == K_PLANE || (s->kind == K_CYLINDER && o->D != 2)) return -5;
+  if (s->inverted || s->kind == K_PLANE || (s->kind == K_CYLINDER && o->D != 2)) return -5;
   s->free = 1;
   s->moving = 1;
   s->rho_p = rho_p;
@@ -1037,23 +1067,39 @@ static double wrap_pos(double y, int L) {
   return y;
 }
 
+/* With the IBM the fluid fills the solid, and the update is Feng &
+ * Michaelides's discretisation, Eq. 23, with rho_f = 1 and dt = 1:
+ *   rho_p V_p (v^{n+1} - v^n) = V_p (v^n - v^{n-1}) + F + (rho_p - 1) V_p g,
+ *   I_p (w^{n+1} - w^n) = (I_p / rho_p) (w^n - w^{n-1}) + T,
+ * F, T being the IBM force and torque of the step (-sum F_l dV_l and
+ * -sum (X_l - Y) x F_l dV_l); the position as above.  At the first step
+ * v^{n-1} = v^n (the solid moved steadily before). */
 static void advance_free(orc *o, int k) {
   solid_t *s = &o->sol[k];
   const double *F = &o->FT[6 * k], *T = &o->FT[6 * k + 3];
   const double m = s->rho_p * s->Vp;
   double vn[3], wn[3];
   for (int a = 0; a < 3; a++) {
-    vn[a] = s->U[a] + (F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
-    wn[a] = s->W[a] + T[a] / s->Ip;
+    if (o->method == M_IBM) {
+      vn[a] = s->U[a] + (s->Vp * (s->U[a] - s->Up[a]) + F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
+      wn[a] = s->W[a] + (s->Ip / s->rho_p * (s->W[a] - s->Wp[a]) + T[a]) / s->Ip;
+    } else {
+      vn[a] = s->U[a] + (F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
+      wn[a] = s->W[a] + T[a] / s->Ip;
+    }
   }
   if (o->D == 2) {
     vn[2] = 0.0;
     wn[0] = 0.0;
     wn[1] = 0.0;
   }
-  for (int a = 0; a < (o->D == 2 ? 2 : 3); a++)
+  for (int a = 0; a < (o->D == 2 ? 2 : 3); a++) {
     s->c[a] = wrap_pos(s->c[a] + 0.5 * (s->U[a] + vn[a]), dims_of(o, a));
+    s->disp[a] = s->disp[a] + 0.5 * (s->U[a] + vn[a]);
+  }
   for (int a = 0; a < 3; a++) {
+    s->Up[a] = s->U[a];
+    s->Wp[a] = s->W[a];
     s->U[a] = vn[a];
     s->W[a] = wn[a];
   }
@@ -1081,6 +1127,7 @@ static void move_solids(orc *o) {
       y = fmod(y, (double)L);
       if (y < 0.0) y += (double)L;
       s->c[a] = y;
+      s->disp[a] = (double)(o->t + 1) * s->U[a];
     }
   }
   classify(o);

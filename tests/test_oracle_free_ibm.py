@@ -1,0 +1,111 @@
+"""Pins of the oracle's moving IBM solids: prescribed translation, and free motion by Feng &
+Michaelides's discretisation (Eq. 23) under the IBM force and torque.
+
+The paper's sedimentation reference data is not available, so the pins are what the discretisation
+and the mathematics fix:
+* with no Lagrangian points (no fluid force) the update is a linear recurrence whose solution has a
+  closed form, v^n = v^0 + g (n - r (1 - r^n) / (1 - r)) with r = rho_f / rho_p, and a constant
+  angular velocity;
+* without gravity and body force, the fluid momentum plus rho_p V_p v^n - rho_f V_p v^{n-1} is
+  conserved exactly: the spread force gives the fluid what Eq. 23 takes from the solid, and the
+  rho_f V_p (v^n - v^{n-1}) term is the change of the last step's inner-fluid momentum;
+* the Lagrangian points travel with a translating solid: after it has moved by more than its
+  diameter, its boundary force is centred on its new position and the fluid there moves with it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1906_05445_amd import workloads as W
+
+
+def _momentum(o):
+    e = np.asarray(o.lattice_tables()[0], dtype=np.float64)  # (Q, 3) velocity set
+    f = o.get_f()  # (Q, N)
+    return e.T @ f.sum(axis=1)
+
+
+@pytest.mark.parametrize("rho_p", [1.6, 1.03, 8.0])
+def test_feng_michaelides_recurrence_closed_form(rho_p):
+    g = np.array([1e-5, -2e-5, 4e-6])
+    U0 = np.array([0.01, 0.0, -0.004])
+    W0 = np.array([0.0, 2e-4, 1e-4])
+    c0 = np.array([12.3, 11.8, 12.6])
+    o = Oracle("D3Q19", "MRT", (24, 24, 24), 0.8)
+    o.set_solids([W.solid("sphere", c0, 4.0, velocity=U0, omega=W0, density=rho_p, gravity=g)], "IBM")
+    n = 40
+    o.step(n)
+    st = o.solid_state()[0]
+    r = 1.0 / rho_p
+    v = U0 + g * (n - r * (1.0 - r ** n) / (1.0 - r))
+    np.testing.assert_allclose(st[3:6], v, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(st[6:9], W0, rtol=0, atol=0)
+    # trapezoid positions: Y^n - Y^0 = sum over the steps of (v^k + v^{k+1}) / 2
+    vk = [U0 + g * (k - r * (1.0 - r ** k) / (1.0 - r)) for k in range(n + 1)]
+    disp = sum(0.5 * (vk[k] + vk[k + 1]) for k in range(n))
+    np.testing.assert_allclose(st[0:3], np.mod(c0 + disp, 24.0), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_free_ibm_momentum_invariant(lattice):
+    if lattice == "D2Q9":
+        shape, c, R = (40, 36, 1), (19.4, 17.7, 0.0), 5.0
+        s = W.solid("cylinder", c, R, velocity=(0.02, 0.01, 0.0), omega=(0.0, 0.0, 0.002), density=1.5)
+        X, dV = W.circle(c, R)
+        Vp = math.pi * R * R
+    else:
+        shape, c, R = (24, 22, 20), (11.6, 10.7, 9.9), 4.0
+        s = W.solid("sphere", c, R, velocity=(0.02, 0.0, -0.01), omega=(0.001, 0.0, 0.002), density=1.5)
+        X, dV = W.icosphere(c, R)
+        Vp = 4.0 / 3.0 * math.pi * R ** 3
+    o = Oracle(lattice, "MRT", shape, 0.8)
+    o.set_solids([s], "IBM")
+    o.set_lagrangian(0, X, dV)
+    rho_p = 1.5
+    prev = o.solid_state()[0][3:6].copy()
+
+    def invariant(v, vprev):
+        return _momentum(o) + rho_p * Vp * v - Vp * vprev
+
+    I0 = invariant(prev, prev)
+    worst = 0.0
+    for k in range(120):
+        o.step(1)
+        v = o.solid_state()[0][3:6].copy()
+        if k % 20 == 19:
+            worst = max(worst, float(np.abs(invariant(v, prev) - I0).max()))
+        prev = v
+    # the solid did exchange momentum with the fluid (the pin is not vacuous)
+    assert abs(_momentum(o)).max() > 0.05 * rho_p * Vp * 0.01
+    assert worst < 1e-12 * rho_p * Vp * 0.02
+
+
+def test_translating_ibm_points_move_with_the_solid():
+    shape, c, R, U = (64, 40, 1), (12.3, 19.6, 0.0), 5.0, 0.04
+    o = Oracle("D2Q9", "MRT", shape, 0.8)
+    o.set_solids([W.solid("cylinder", c, R, velocity=(U, 0.0, 0.0))], "IBM")
+    X, dV = W.circle(c, R)
+    o.set_lagrangian(0, X, dV)
+    T = 300  # 12 cells, more than the diameter
+    o.step(T)
+    st = o.solid_state()[0]
+    np.testing.assert_allclose(st[0], c[0] + T * U, rtol=0, atol=1e-12)
+    # the boundary force of the last step (points at c + (T - 1) U) sits on the solid there: its
+    # centroid, weighted by |f|, is on the axis of motion and within a cell and a half of that
+    # centre (behind it by about half a cell, the drag making the front and rear forces unequal),
+    # where points left at their start would put it 12 cells back
+    f = o.ibm_force_field().reshape(3, shape[1], shape[0])
+    mag = np.sqrt((f ** 2).sum(axis=0))
+    assert mag.sum() > 0.0
+    y, x = np.mgrid[0:shape[1], 0:shape[0]].astype(np.float64)
+    ctr = np.array(c[:2]) + np.array([(T - 1) * U, 0.0])
+    dx = (x - ctr[0] + shape[0] / 2) % shape[0] - shape[0] / 2
+    dy = (y - ctr[1] + shape[1] / 2) % shape[1] - shape[1] / 2
+    assert abs((dx * mag).sum() / mag.sum()) < 1.5
+    assert abs((dy * mag).sum() / mag.sum()) < 0.1
+    # and the fluid at the centre moves with the solid
+    _, u, _ = o.macros()
+    u = u.reshape(3, shape[1], shape[0])
+    assert u[0, int(round(st[1])), int(round(st[0]))] > 0.85 * U
