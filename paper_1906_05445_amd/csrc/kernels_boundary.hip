@@ -526,17 +526,26 @@ __device__ inline void free_update_one(DevSolid *solids, int k, const double FT[
   double c[3], vn[3], wn[3], cn[3];
   solid_centre(s, t, b, c);
   for (int a = 0; a < 3; a++) {
-    vn[a] = s.U[a] + (FT[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
-    wn[a] = s.W[a] + FT[3 + a] / s.Ip;
+    if (s.fm) {
+      // Eq. 23 (rho_f = 1, dt = 1): the inner fluid's inertia from the velocities of the step before
+      vn[a] = s.U[a] + (s.Vp * (s.U[a] - s.Up[a]) + FT[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
+      wn[a] = s.W[a] + (s.Ip / s.rho_p * (s.W[a] - s.Wp[a]) + FT[3 + a]) / s.Ip;
+    } else {
+      vn[a] = s.U[a] + (FT[a] + (s.rho_p - 1.0) * s.Vp * s.grav[a]) / m;
+      wn[a] = s.W[a] + FT[3 + a] / s.Ip;
+    }
   }
   if (b.D == 2) {
     vn[2] = 0.0;
     wn[0] = 0.0;
     wn[1] = 0.0;
   }
+  double dn[3];
   for (int a = 0; a < 3; a++) {
     cn[a] = c[a];
+    dn[a] = s.dsp[a];
     if (a < b.D) {
+      dn[a] = s.dsp[a] + 0.5 * (s.U[a] + vn[a]);
       const double L = (double)box_dim(b, a);
       double y = c[a] + 0.5 * (s.U[a] + vn[a]);
       if (!(y >= 0.0 && y < L)) {
@@ -555,8 +564,24 @@ __device__ inline void free_update_one(DevSolid *solids, int k, const double FT[
     o.c0[a] = cn[a];
     o.U[a] = vn[a];
     o.W[a] = wn[a];
+    o.dsp[a] = dn[a];
   }
   o.tref = t + 1;
+}
+
+// IBM force/torque of step t of a free IBM solid (one block per solid) and,
+// by the thread that wrote them, its motion to t + 1 by Eq. 23.
+__global__ __launch_bounds__(kBlock) void k_ibm_ft_free(IbmFtArgs f, DevSolid *solids, uint32_t *flag) {
+  ibm_ft_body(f, (int)blockIdx.x);
+  if (threadIdx.x != 0) return;
+  double FT[6];
+  for (int k = 0; k < 6; k++) FT[k] = f.hist[(uint64_t)blockIdx.x * 6 + k];
+  free_update_one(solids, (int)blockIdx.x, FT, f.b, f.t, flag);
+}
+
+void launch_ibm_ft_free(lbm_ctx *c, int64_t t) {
+  hipLaunchKernelGGL(k_ibm_ft_free, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t),
+                     c->at<DevSolid>(c->L.solids), c->at<uint32_t>(c->L.misc) + 6);
 }
 
 // Force/torque of step t per solid (as k_ft_reduce) and, by the lane that

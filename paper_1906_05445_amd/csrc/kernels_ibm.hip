@@ -76,12 +76,10 @@ __global__ void k_ibm_mark(IbmArgs a) {
 // u0 = (j + g/2)/rho at every shell cell from the populations f(t), gathered
 // from the shifted state (A_i(x - e_i)); clears the spread force.
 template <int Q, typename S>
-__device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, int64_t s) {
+__device__ inline void ibm_u0_at(const S *__restrict__ A, const IbmArgs &a, int64_t s, uint32_t n) {
 #pragma clang fp contract(off)
   using C = typename Store<S>::C;
   using L = Lat<Q>;
-  if (s >= a.nshell) return;
-  const uint32_t n = a.shell_cell[s];
   const uint32_t yz = fdiv(n, a.fx);
   const int x = (int)(n - yz * (uint32_t)a.b.nx);
   const int z = (int)fdiv(yz, a.fy);
@@ -106,6 +104,11 @@ __device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, in
     u[k * a.nshell + s] = (j[k] + C(0.5) * (body ? (C)a.g[k] : C(0))) / rho;
     f[k * a.nshell + s] = C(0);
   }
+}
+template <int Q, typename S>
+__device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, int64_t s) {
+  if (s >= a.nshell) return;
+  ibm_u0_at<Q, S>(A, a, s, a.shell_cell[s]);
 }
 
 // Eq. 5 and Eq. 7: interpolate u to the point, F = rho0 (U^d - U~)/dt.
@@ -219,6 +222,138 @@ __device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
   }
 }
 
+// ---- one moving solid ------------------------------------------------------
+// The points move rigidly with the solid: X_l(t) = X_l(placed) + d(t).  With
+// d = n + delta (n whole cells, delta in [0, 1) per axis), the 4-node stencil
+// of a point, floor(X - 1) .. floor(X) + 2, lies inside the 5-node box
+// floor(X_placed) - 1 + n .. + 4 whatever delta is.  The shell is the union of
+// these boxes where the points were placed, built once with its transpose;
+// at step t it is moved by n, and the box nodes outside a point's stencil
+// take exact zeros from the delta function.
+constexpr int kMvBox = 5;
+
+// Cell of shell cell s under the whole-cell shift sh[0..2].
+__device__ inline uint32_t mv_cell(const IbmArgs &a, int64_t s, const int32_t *sh) {
+  const uint32_t n = a.shell_cell[s];
+  const uint32_t yz = fdiv(n, a.fx);
+  const int x = (int)(n - yz * (uint32_t)a.b.nx);
+  const int z = (int)fdiv(yz, a.fy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)a.b.ny);
+  return (uint32_t)wrapi(x + sh[0], a.b.nx) +
+         (uint32_t)a.b.nx * ((uint32_t)wrapi(y + sh[1], a.b.ny) + (uint32_t)a.b.ny * (uint32_t)wrapi(z + sh[2], a.b.nz));
+}
+
+// Per point: box weights for the displacement d(t), U^d, the lever arm; the
+// shift of step t.
+__global__ void k_ibm_move(IbmArgs a) {
+#pragma clang fp contract(off)
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= a.nlag) return;
+  const DevSolid &s = a.solids[a.sid[l]];
+  double d[3], del[3], X[3], c[3], r[3], ud[3];
+  int n[3];
+  solid_disp(s, a.t, d);
+  for (int ax = 0; ax < 3; ax++) {
+    const bool on = ax < a.b.D;
+    n[ax] = on ? (int)floor(d[ax]) : 0;
+    del[ax] = on ? d[ax] - (double)n[ax] : 0.0;
+    X[ax] = on ? a.X[l * 3 + ax] + d[ax] : a.X[l * 3 + ax];
+  }
+  double *w = a.wts + l * 24;
+  for (int ax = 0; ax < 3; ax++)
+    for (int k = 0; k < kMvBox; k++)
+      w[ax * kMvBox + k] = (ax == 2 && a.b.D == 2)
+                               ? (k == 0 ? 1.0 : 0.0)
+                               : phi_of(a.delta, (double)(a.base[l * 3 + ax] + k) - (a.X[l * 3 + ax] + del[ax]));
+  solid_centre(s, a.t, a.b, c);
+  lever_arm(s, c, X[0], X[1], X[2], a.b, r);
+  wall_vel(s, r, ud);
+  if (a.b.D == 2) ud[2] = 0.0;
+  for (int k = 0; k < 3; k++) {
+    a.Ud[l * 3 + k] = ud[k];
+    w[16 + k] = r[k];
+  }
+  if (l == 0)
+    for (int k = 0; k < 3; k++) a.shift[4 * (int)(a.t & 1) + k] = n[k];
+}
+
+// u0 on the shell moved to step t; the boundary force and the F_IBM flag of
+// the shell of step t - 1 are cleared (the spreading of this step sets them
+// on the new cells).
+template <int Q, typename S>
+__global__ void k_ibm_u0_mv(const S *__restrict__ A, IbmArgs a) {
+  using C = typename Store<S>::C;
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.nshell) return;
+  const int cur = (int)(a.t & 1);
+  const uint32_t old = mv_cell(a, s, a.shift + 4 * (cur ^ 1));
+  a.flags[old] = (uint8_t)(a.flags[old] & ~F_IBM);
+  C *fb = static_cast<C *>(a.fibm);
+  for (int k = 0; k < 3; k++) fb[k * a.stride + old] = C(0);
+  ibm_u0_at<Q, S>(A, a, s, mv_cell(a, s, a.shift + 4 * cur));
+}
+
+template <typename C>
+__device__ inline C mv_weight(const double *w, uint32_t slot) {
+#pragma clang fp contract(off)
+  return (C)((w[slot % 5u] * w[5 + (slot / 5u) % 5u]) * w[10 + slot / 25u]);
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_ibm_interp_mv(IbmArgs a, int first) {
+  const int64_t l = (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  const int nsl = a.b.D == 2 ? kMvBox * kMvBox : kMvBox * kMvBox * kMvBox;
+  const C *u = static_cast<const C *>(a.ushell);
+  C v[3] = {0, 0, 0};
+  for (int p = 0; p < 2; p++) {
+    const int slot = lane + 64 * p;
+    if (l < a.nlag && slot < nsl) {
+      C t[3];
+      ibm_interp_terms<C>(u, a.nshell, a.idx[l * 128 + slot], mv_weight<C>(a.wts + l * 24, (uint32_t)slot), t);
+      for (int k = 0; k < 3; k++) v[k] = ibm_add<C>(v[k], t[k]);
+    }
+  }
+  for (int k = 0; k < 3; k++) v[k] = wave_sum_c(v[k]);
+  if (lane != 0 || l >= a.nlag) return;
+  C *Fk = static_cast<C *>(a.Fk);
+  for (int k = 0; k < 3; k++) {
+    double sum = first ? 0.0 : a.Fsum[l * 3 + k];
+    Fk[l * 3 + k] = ibm_point_force<C>((C)a.Ud[l * 3 + k], v[k], &sum);
+    a.Fsum[l * 3 + k] = sum;
+  }
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_ibm_spread_mv(IbmArgs a, int last) {
+  const int64_t s = (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes);
+  const int lane = (int)(threadIdx.x & (kSpreadLanes - 1));
+  const C *Fk = static_cast<const C *>(a.Fk);
+  C f[3] = {0, 0, 0};
+  if (s < a.nshell) {
+    const uint32_t e1 = a.rowptr[s + 1];
+    for (uint32_t e = a.rowptr[s] + lane; e < e1; e += kSpreadLanes) {
+      const uint32_t v = a.ent[e];
+      const uint32_t l = v >> 7;
+      ibm_spread_term<C>(Fk, l, mv_weight<C>(a.wts + (uint64_t)l * 24, v & 127u), (C)a.dV[l], f);
+    }
+  }
+  ibm_spread_reduce<C>(f);
+  if (lane != 0 || s >= a.nshell) return;
+  C *u = static_cast<C *>(a.ushell);
+  C *fs = static_cast<C *>(a.fshell);
+  for (int k = 0; k < 3; k++) {
+    u[k * a.nshell + s] = ibm_add<C>(u[k * a.nshell + s], f[k]);
+    fs[k * a.nshell + s] = ibm_add<C>(fs[k * a.nshell + s], f[k]);
+  }
+  if (last) {
+    C *fb = static_cast<C *>(a.fibm);
+    const uint32_t n = mv_cell(a, s, a.shift + 4 * (int)(a.t & 1));
+    for (int k = 0; k < 3; k++) fb[k * a.stride + n] = fs[k * a.nshell + s];
+    a.flags[n] = (uint8_t)(a.flags[n] | F_IBM);
+  }
+}
+
 template <int Q, typename S>
 __global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
   ibm_u0_body<Q, S>(A, a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
@@ -311,13 +446,18 @@ static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
   a.solids = c->at<DevSolid>(c->L.solids);
   for (int k = 0; k < 3; k++) a.g[k] = c->p.body_force[k];
   a.t = t;
+  a.mv = c->ibm_moving ? 1 : 0;
+  a.shift = c->at<int32_t>(c->L.misc + 64 + 16 * (size_t)c->L.max_solids);
   return a;
 }
 
 void launch_ibm_setup(lbm_ctx *c) {
   if (c->nlag <= 0) return;
   IbmArgs a = ibm_args(c, c->t);
-  hipLaunchKernelGGL(k_ibm_weights, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+  if (c->ibm_moving)
+    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(k_ibm_weights, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
   hipLaunchKernelGGL(k_ibm_mark, dim3((uint32_t)((c->nshell + 255) / 256)), dim3(256), 0, c->stream, a);
 }
 
@@ -328,6 +468,21 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
   const dim3 gs((uint32_t)((c->nshell + 127) / 128)),
       gl((uint32_t)((c->nlag + kIbmPointsPerBlock - 1) / kIbmPointsPerBlock)),
       gsp((uint32_t)((c->nshell + kSpreadCellsPerBlock - 1) / kSpreadCellsPerBlock));
+  if (c->ibm_moving) {
+    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+    if (c->Q == 9)
+      hipLaunchKernelGGL((k_ibm_u0_mv<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
+    else
+      hipLaunchKernelGGL((k_ibm_u0_mv<19, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
+    for (int it = 0; it < c->n_iter; it++) {
+      hipLaunchKernelGGL(k_ibm_interp_mv<C>, gl, dim3(256), 0, c->stream, a, it == 0 ? 1 : 0);
+      hipLaunchKernelGGL(k_ibm_spread_mv<C>, gsp, dim3(256), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
+    }
+    if (c->ibm_free) launch_ibm_ft_free(c, t);  // force of step t, then the motion to t + 1 (Eq. 23)
+    else if (with_ft)
+      hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t));
+    return;
+  }
   if (c->Q == 9)
     hipLaunchKernelGGL((k_ibm_u0<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
   else

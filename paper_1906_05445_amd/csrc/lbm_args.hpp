@@ -52,6 +52,8 @@ struct IbbArgs {
 struct IbmFtArgs {
   Box3 b;
   const DevSolid *solids;
+  int mv;              // moving solid: lever arms from wts (see IbmArgs)
+  const double *wts;
   const double *X, *dV, *Fsum;
   const int64_t *start, *count;  // points of each solid
   double *hist;                  // history slot of the step
@@ -123,6 +125,12 @@ struct IbmArgs {
   double g[3];
   int64_t t;
   int delta;             // points of the delta function: 4 (Eq. 6), 3 or 2
+  // moving solid: 5-node boxes (idx [nlag][128], ent = point << 7 | slot,
+  // wts [nlag][24] = 3 x 5 weights, pad, lever arm at 16..18); shell cells
+  // are where they were at placement, moved by the whole-cell shift, kept
+  // for the step t in shift[4 (t & 1) + axis]
+  int mv;
+  int32_t *shift;
 };
 
 __device__ __host__ inline IbmFtArgs ibm_ft_args(const IbmArgs &a, int64_t t, const int64_t *start,
@@ -130,6 +138,8 @@ __device__ __host__ inline IbmFtArgs ibm_ft_args(const IbmArgs &a, int64_t t, co
   IbmFtArgs f;
   f.b = a.b;
   f.solids = a.solids;
+  f.mv = a.mv;
+  f.wts = a.wts;
   f.X = a.X;
   f.dV = a.dV;
   f.Fsum = a.Fsum;
@@ -152,7 +162,10 @@ __device__ inline void ibm_ft_body(const IbmFtArgs &a, int s) {
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int64_t l = a.start[s] + threadIdx.x; l < a.start[s] + a.count[s]; l += blockDim.x) {
     double r[3], F[3];
-    lever_arm(sd, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
+    if (a.mv)
+      for (int k = 0; k < 3; k++) r[k] = a.wts[l * 24 + 16 + k];
+    else
+      lever_arm(sd, c, a.X[l * 3], a.X[l * 3 + 1], a.X[l * 3 + 2], a.b, r);
     for (int k = 0; k < 3; k++) F[k] = -a.Fsum[l * 3 + k] * a.dV[l];
     acc[0] += F[0];
     acc[1] += F[1];
@@ -312,6 +325,7 @@ void fill_ibb_args(lbm_ctx *c, IbbArgs *a);
 void fill_link_args(lbm_ctx *c, LinkArgs *a);
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a);
 IbmFtArgs ibm_ft_args_of(lbm_ctx *c, int64_t t);
+void launch_ibm_ft_free(lbm_ctx *c, int64_t t);
 
 // batched launches (grid = persistent blocks)
 void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,

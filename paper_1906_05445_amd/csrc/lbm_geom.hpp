@@ -148,6 +148,13 @@ __device__ inline void wall_vel(const DevSolid &s, const double r[3], double uw[
   uw[2] = s.U[2] + (s.W[0] * r[1] - s.W[1] * r[0]);
 }
 
+// Displacement of solid s at time t since its Lagrangian points were placed
+// (prescribed motion at any t, free motion at t = tref).
+__device__ inline void solid_disp(const DevSolid &s, int64_t t, double d[3]) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; a++) d[a] = s.moving ? s.dsp[a] + (double)(t - s.tref) * s.U[a] : s.dsp[a];
+}
+
 __device__ inline void solid_centre(const DevSolid &s, int64_t t, const Box3 &b, double c[3]) {
   c[0] = centre_at(s, 0, t, b);
   c[1] = centre_at(s, 1, t, b);

@@ -36,6 +36,11 @@ struct DevSolid {
   int64_t tref;
   double rho_p, Vp, Ip, grav[3];
   double cp[3], Up[3], Wp[3];
+  // IBM: displacement of the solid at time tref since its Lagrangian points
+  // were placed (unwrapped; the points move rigidly with it), and free motion
+  // by Eq. 23 (fluid inside the solid) instead of Eq. 20
+  double dsp[3];
+  int32_t fm;
 };
 
 // Where one solid's links sit in the link arrays, and its chunk partials.
@@ -132,8 +137,11 @@ struct lbm_ctx {
   // solids
   int method;
   int nsolid;
-  bool any_moving;
+  bool any_moving;  // IBB solids that translate or move freely
   bool any_free;
+  bool ibm_moving;  // the IBM solid translates or moves freely (one solid)
+  bool ibm_free;
+  int64_t solids_t;  // t at lbm_set_solids
   std::vector<lbm_solid> solids;
   std::vector<lbm::DevSolid> dsolids;
   int32_t max_box_chunks;  // per solid, for the link-builder grid

@@ -316,6 +316,10 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   c->method = LBM_BB;
   c->nsolid = 0;
   c->any_moving = false;
+  c->any_free = false;
+  c->ibm_moving = false;
+  c->ibm_free = false;
+  c->solids_t = 0;
   c->max_box_chunks = 0;
   c->k5_chunks = 0;
   c->nlinks = 0;
@@ -446,10 +450,10 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       if (!(q.density > 0.0) || !std::isfinite(q.density) || !std::isfinite(q.gravity[0]) ||
           !std::isfinite(q.gravity[1]) || !std::isfinite(q.gravity[2]))
         return set_err(c, "free solid: density must be positive, gravity finite"), LBM_EINVAL;
-      if (method == LBM_IBM || q.kind == LBM_PLANE || q.inverted || (q.kind == LBM_CYLINDER && c->D != 2) ||
-          c->batch)
-        return set_err(c, "free solids need IBB, a sphere or 2D cylinder, not inverted, outside a batch"),
+      if (q.kind == LBM_PLANE || q.inverted || (q.kind == LBM_CYLINDER && c->D != 2) || c->batch)
+        return set_err(c, "free solids need a sphere or 2D cylinder, not inverted, outside a batch"),
                LBM_EUNSUPPORTED;
+      d.fm = method == LBM_IBM ? 1 : 0;  // Eq. 23 with the fluid inside the solid, else Eq. 20
       const double pi = 3.14159265358979323846, R = q.radius;
       d.free = 1;
       d.moving = 1;
@@ -464,8 +468,16 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       d.Up[a] = d.U[a];
       d.Wp[a] = d.W[a];
     }
-    if (d.moving && (method == LBM_IBM || q.kind == LBM_PLANE))
-      return set_err(c, "translating solids need IBB and a sphere or cylinder"), LBM_EUNSUPPORTED;
+    if (d.moving && q.kind == LBM_PLANE)
+      return set_err(c, "translating solids need a sphere or cylinder"), LBM_EUNSUPPORTED;
+    if (d.moving && method == LBM_IBM) {
+      const bool g = c->p.body_force[0] != 0.0 || c->p.body_force[1] != 0.0 || c->p.body_force[2] != 0.0;
+      if (n != 1 || q.inverted || (q.kind == LBM_CYLINDER && c->D != 2) || c->batch ||
+          (g && c->p.body_force_fluid_only))
+        return set_err(c, "a moving IBM solid: the only solid, a sphere or 2D cylinder, not inverted, outside a "
+                          "batch, with no fluid-only body force"),
+               LBM_EUNSUPPORTED;
+    }
     if (d.moving) {
       for (int a = 0; a < 3; a++)
         if (std::fabs(d.U[a]) >= 1.0) return set_err(c, "solid speed must be below one cell per step"), LBM_EINVAL;
@@ -533,8 +545,11 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->dsolids = ds;
   c->nsolid = n;
   c->method = method;
-  c->any_moving = moving;
-  c->any_free = any_free;
+  c->any_moving = moving && method != LBM_IBM;
+  c->any_free = any_free && method != LBM_IBM;
+  c->ibm_moving = moving && method == LBM_IBM;
+  c->ibm_free = any_free && method == LBM_IBM;
+  c->solids_t = c->t;
   c->max_box_chunks = mbc;
   // the link masks of the count pass live in the staging region (4 N doubles) while links are built
   c->mask_cells = mask_total * 4 <= (uint64_t)4 * c->N * 8 ? mask_total : 0;
@@ -554,6 +569,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
                          c->stream));
   // the refill count and overflow flag (misc[3], misc[4]) and the free-solid flag (misc[6])
   HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 3 * sizeof(uint32_t), 0, 4 * sizeof(uint32_t), c->stream));
+  // the whole-cell shifts of a moving IBM shell (both slots: no shift yet)
+  HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 64 + 16 * (size_t)c->L.max_solids, 0, 8 * sizeof(int32_t), c->stream));
   HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));
   if (n == 0) {
     HIPCALL(hipStreamSynchronize(c->stream));
@@ -611,25 +628,31 @@ static lbm_status build_ibm(lbm_ctx *c) {
   }
   const int64_t nl = (int64_t)(c->lag_X.size() / 3);
   if (nl > c->L.max_lag) return set_err(c, "more Lagrangian points than max_lagrangian"), LBM_ENOMEM;
+  // a moving solid keeps a 5-node box per axis per point (125 slots in a
+  // 128-entry row), twice the fixed stencil's room: half the point capacity
+  const bool mv = c->ibm_moving;
+  if (mv && 2 * nl > c->L.max_lag)
+    return set_err(c, "a moving IBM solid holds at most max_lagrangian / 2 points"), LBM_ENOMEM;
+  const int bw = mv ? 5 : 4, row = mv ? 128 : 64, sbits = mv ? 7 : 6;
   std::vector<int32_t> sid((size_t)std::max<int64_t>(nl, 1)), base((size_t)std::max<int64_t>(3 * nl, 3));
   for (int k = 0; k < c->nsolid; k++)
     for (int64_t l = c->lag_start[k]; l < c->lag_start[k] + c->lag_count[k]; l++) sid[l] = k;
-  const int nzs = c->D == 2 ? 1 : 4;
-  std::vector<uint32_t> cellof((size_t)std::max<int64_t>(nl * 64, 1), 0);
+  const int nzs = c->D == 2 ? 1 : bw;
+  std::vector<uint32_t> cellof((size_t)std::max<int64_t>(nl * row, 1), 0);
   std::vector<uint32_t> all;
-  all.reserve((size_t)nl * 64);
+  all.reserve((size_t)nl * row);
   for (int64_t l = 0; l < nl; l++) {
     int b[3];
     for (int a = 0; a < 3; a++) b[a] = (a < c->D) ? (int)std::floor(c->lag_X[3 * l + a]) - 1 : 0;
     for (int a = 0; a < 3; a++) base[3 * l + a] = b[a];
     for (int kz = 0; kz < nzs; kz++)
-      for (int ky = 0; ky < 4; ky++)
-        for (int kx = 0; kx < 4; kx++) {
+      for (int ky = 0; ky < bw; ky++)
+        for (int kx = 0; kx < bw; kx++) {
           auto w = [](int v, int L) { return ((v % L) + L) % L; };
           const uint32_t cell = (uint32_t)w(b[0] + kx, c->p.nx) +
                                 (uint32_t)c->p.nx * ((uint32_t)w(b[1] + ky, c->p.ny) +
                                                      (uint32_t)c->p.ny * (uint32_t)w(b[2] + kz, c->p.nz));
-          cellof[(size_t)l * 64 + kz * 16 + ky * 4 + kx] = cell;
+          cellof[(size_t)l * row + (kz * bw + ky) * bw + kx] = cell;
           all.push_back(cell);
         }
   }
@@ -637,24 +660,22 @@ static lbm_status build_ibm(lbm_ctx *c) {
   all.erase(std::unique(all.begin(), all.end()), all.end());
   const int64_t ns = (int64_t)all.size();
   if (ns > c->L.max_shell) return set_err(c, "IBM shell larger than its capacity"), LBM_ENOMEM;
-  std::vector<uint32_t> idx((size_t)std::max<int64_t>(nl * 64, 1), 0), rowcnt((size_t)ns + 1, 0);
+  const int nslot = bw * bw * nzs;
+  std::vector<uint32_t> idx((size_t)std::max<int64_t>(nl * row, 1), 0), rowcnt((size_t)ns + 1, 0);
   for (int64_t l = 0; l < nl; l++)
-    for (int slot = 0; slot < 64; slot++) {
-      const int kz = slot >> 4;
-      if (kz >= nzs) continue;
-      const uint32_t cell = cellof[(size_t)l * 64 + slot];
+    for (int slot = 0; slot < nslot; slot++) {
+      const uint32_t cell = cellof[(size_t)l * row + slot];
       const uint32_t si = (uint32_t)(std::lower_bound(all.begin(), all.end(), cell) - all.begin());
-      idx[(size_t)l * 64 + slot] = si;
+      idx[(size_t)l * row + slot] = si;
       rowcnt[si + 1]++;
     }
   std::vector<uint32_t> rowptr((size_t)ns + 1, 0);
   for (int64_t s = 0; s < ns; s++) rowptr[s + 1] = rowptr[s] + rowcnt[s + 1];
   std::vector<uint32_t> ent((size_t)std::max<uint32_t>(rowptr[ns], 1)), fill(rowptr.begin(), rowptr.end() - 1);
   for (int64_t l = 0; l < nl; l++)  // points in order, so each row is sorted by point
-    for (int slot = 0; slot < 64; slot++) {
-      if ((slot >> 4) >= nzs) continue;
-      const uint32_t si = idx[(size_t)l * 64 + slot];
-      ent[fill[si]++] = (uint32_t)(l << 6) | (uint32_t)slot;
+    for (int slot = 0; slot < nslot; slot++) {
+      const uint32_t si = idx[(size_t)l * row + slot];
+      ent[fill[si]++] = (uint32_t)(l << sbits) | (uint32_t)slot;
     }
   c->nlag = nl;
   c->nshell = ns;
@@ -665,7 +686,7 @@ static lbm_status build_ibm(lbm_ctx *c) {
   HIPCALL(up(c->L.lag_dV, c->lag_dV.data(), sizeof(double) * nl));
   HIPCALL(up(c->L.lag_sid, sid.data(), sizeof(int32_t) * nl));
   HIPCALL(up(c->L.lag_base, base.data(), sizeof(int32_t) * 3 * nl));
-  HIPCALL(up(c->L.lag_idx, idx.data(), sizeof(uint32_t) * 64 * nl));
+  HIPCALL(up(c->L.lag_idx, idx.data(), sizeof(uint32_t) * row * nl));
   HIPCALL(up(c->L.shell_cell, all.data(), sizeof(uint32_t) * ns));
   HIPCALL(up(c->L.shell_rowptr, rowptr.data(), sizeof(uint32_t) * (ns + 1)));
   HIPCALL(up(c->L.shell_ent, ent.data(), sizeof(uint32_t) * rowptr[ns]));
@@ -683,6 +704,8 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
   if (!c) return LBM_EINVAL;
   if (c->method != LBM_IBM || solid < 0 || solid >= c->nsolid || n < 0 || (n > 0 && !X) || !(dV >= 0.0))
     return set_err(c, "lbm_set_lagrangian needs an IBM solid"), LBM_EINVAL;
+  if (c->ibm_moving && c->t != c->solids_t)
+    return set_err(c, "the points of a moving IBM solid are set before it moves"), LBM_EINVAL;
   // rebuild the per-solid point lists with this solid replaced
   std::vector<double> NX, NdV;
   std::vector<int64_t> st(c->nsolid), ct(c->nsolid);
@@ -880,7 +903,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     // the forces of the previous step of this call are reduced inside this sweep
     // launch (translating solids rebuild the link table first, so they reduce at once)
     const bool fused_reduce = ibb && k > 0 && !c->any_moving;
-    launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm ? c->t : -1);
+    launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm && !c->ibm_free ? c->t : -1);
     if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
     if (ibb) {
       launch_ibb(c, B, A, c->t);
@@ -919,6 +942,13 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   {
     const lbm_status st = tune_finish(c);
     if (st != LBM_OK) return st;
+  }
+  if (c->ibm_free && nsteps > 0) {
+    uint32_t flag = 0;
+    HIPCALL(hipMemcpyAsync(&flag, c->ws + c->L.misc + 6 * sizeof(uint32_t), sizeof(flag), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIPCALL(hipStreamSynchronize(c->stream));
+    if (flag) return set_err(c, "a free solid reached half a cell per step"), LBM_EDIVERGED;
   }
   if (ibb && c->any_moving && nsteps > 0) {
     uint32_t misc[7];

@@ -43,7 +43,8 @@ def test_invalid_lattice_parameters(lbm):
     ([W.solid("sphere", (8.1, 7.9, 8.2), 8.5)], "QUADRATIC", "EINVAL"),             # wider than the box
     ([W.solid("sphere", (18.0, 7.9, 8.2), 3.0)], "QUADRATIC", "EINVAL"),            # centre outside
     ([W.solid("sphere", (8.1, 7.9, 8.2), 3.0, velocity=(1.2, 0.0, 0.0))], "QUADRATIC", "EINVAL"),  # speed
-    ([W.solid("sphere", (8.1, 7.9, 8.2), 3.0, velocity=(0.1, 0.0, 0.0))], "IBM", "EUNSUPPORTED"),
+    ([W.solid("sphere", (8.1, 7.9, 8.2), 3.0, inverted=True, velocity=(0.1, 0.0, 0.0))], "IBM",
+     "EUNSUPPORTED"),                                                                # moving inverted IBM
     ([W.solid("plane", (0.0, 4.3, 0.0), axis=(0, 1, 0), velocity=(0.01, 0.0, 0.0))], "QUADRATIC",
      "EUNSUPPORTED"),
     ([W.solid("sphere", (8.1, 7.9, 8.2), 3.0, density=-1.0)], "QUADRATIC", "EINVAL"),
