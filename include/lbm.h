@@ -117,18 +117,30 @@ typedef struct {
  * into the fluid, `centre` a point of the plane.  inverted = 1 makes the
  * solid the OUTSIDE of the sphere/cylinder (an outer Couette wall, a pipe).
  * Wall velocity u_w(x) = velocity + omega x (x - centre).  A solid with
- * nonzero velocity translates (centre(t) = centre + t*velocity, IBB only).
- * density > 0 makes the solid move freely (Sec. 3.2, Eq. 20 with the fluid
- * density rho0 = 1 and no interaction force): density is rho_p / rho_f,
- * gravity the external acceleration; velocity and omega are the initial
- * values.  After every step t, with the Eq. 17 force F and torque T of that
- * step: rho_p V_p (v' - v) = F + (rho_p - 1) V_p gravity, I_p (w' - w) = T,
+ * nonzero velocity translates (centre(t) = centre + t*velocity).
+ * density > 0 makes the solid move freely (Sec. 3.2, fluid density rho0 = 1,
+ * no interaction force): density is rho_p / rho_f, gravity the external
+ * acceleration; velocity and omega are the initial values (and those of the
+ * step before the first).  After every step t, with the force F and torque T
+ * of that step on the solid:
+ *   IBB (Eq. 20, F and T by Eq. 17): rho_p V_p (v' - v) = F + (rho_p - 1)
+ *   V_p gravity, I_p (w' - w) = T;
+ *   IBM (Eq. 23, Feng & Michaelides, F = -sum F_l dV_l, T = -sum (X_l - Y)
+ *   x F_l dV_l): rho_p V_p (v' - v) = V_p (v - v_prev) + F + (rho_p - 1) V_p
+ *   gravity, I_p (w' - w) = (I_p / rho_p) (w - w_prev) + T;
  * centre' = centre + (v + v')/2 (dt = 1); sphere V_p = 4 pi R^3/3,
  * I_p = 2 rho_p V_p R^2/5; cylinder (D2Q9 only, per unit depth) V_p = pi R^2,
- * I_p = rho_p V_p R^2/2, rotation about z.  Free solids need an IBB method,
- * a sphere or (2D) cylinder that is not inverted, and a context outside any
- * batch (else LBM_EUNSUPPORTED); a step that would carry one faster than
- * half a cell per step ends with LBM_EDIVERGED. */
+ * I_p = rho_p V_p R^2/2, rotation about z.  The Eq. 23 update is explicit:
+ * at small radii and density ratios near one it can oscillate with growing
+ * amplitude (a sphere of radius 4 at rho_p = 1.5 does; radius 7, or rho_p = 3,
+ * does not).  Free solids need a sphere or (2D) cylinder that is not inverted
+ * and a context outside any batch (else LBM_EUNSUPPORTED); a step that would
+ * carry one faster than half a cell per step ends with LBM_EDIVERGED.  A
+ * moving (translating or free) IBM solid must moreover be the only solid,
+ * with no fluid-only body force (body_force zero or body_force_fluid_only 0);
+ * its Lagrangian points move rigidly with it (their orientation is kept),
+ * and it uses twice the point capacity of a fixed one (at most
+ * max_lagrangian / 2 points). */
 typedef struct {
   int32_t kind;       /* lbm_solid_kind */
   int32_t inverted;
@@ -177,7 +189,9 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
 lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts);
 
 /* IBM only: replace the Lagrangian points of one solid with X [n][3]
- * (FP64, lattice units), each with control volume dV. */
+ * (FP64, lattice units), each with control volume dV.  The points of a moving
+ * solid are given where the solid was placed by lbm_set_solids, before any
+ * step (else LBM_EINVAL). */
 lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_t n, double dV);
 
 /* Advance nsteps time steps (no host synchronisation inside). */
