@@ -68,7 +68,7 @@ def traffic_for(key, cells):
 def run_case(case, steps, warmup, key, torch, lbm):
     Q = 19 if case.lattice == "D3Q19" else 9
     gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g,
-                      max_solids=max(1, len(case.solids)))
+                      g_fluid_only=case.g_fluid_only, max_solids=max(1, len(case.solids)))
     gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction, delta=case.delta)
     N = gpu.N
     gpu.step(warmup)
@@ -128,6 +128,9 @@ def run_case(case, steps, warmup, key, torch, lbm):
         "drag_x": float(F[0, 0]),
         "autotune": tune,
     }
+    if case.meta.get("U_set") is not None:  # free solid: its vertical velocity at the end vs the Stokes target
+        out["settling_velocity_at_end"] = float(gpu.solid_state()[0, 2 + 3])
+        out["settling_velocity_stokes"] = -case.meta["U_set"]
     gpu.close()
     del gpu
     torch.cuda.empty_cache()
@@ -351,7 +354,8 @@ def main():
                                                                           "retraction": 0.3})),
                             ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
                                                                           "retraction": 0.2})),
-                            ("settle128_f32_free", (W.settling_sphere, {}))]:
+                            ("settle128_f32_free", (W.settling_sphere, {})),
+                            ("settle128_f32_free_ibm", (W.settling_sphere, {"method": "IBM"}))]:
         if "schemes" in want or key in want:
             case = ctor(storage="F32", **kw)
             k = max(K // 2, 100) if "256" not in key else max(K // 8, 50)

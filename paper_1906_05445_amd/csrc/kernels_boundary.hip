@@ -569,9 +569,11 @@ __device__ inline void free_update_one(DevSolid *solids, int k, const double FT[
   o.tref = t + 1;
 }
 
-// IBM force/torque of step t of a free IBM solid (one block per solid) and,
-// by the thread that wrote them, its motion to t + 1 by Eq. 23.
-__global__ __launch_bounds__(kBlock) void k_ibm_ft_free(IbmFtArgs f, DevSolid *solids, uint32_t *flag) {
+// IBM force/torque of step t of a free IBM solid (one block of 1024 threads
+// per solid: the sum is latency-bound) and, by the thread that wrote them,
+// its motion to t + 1 by Eq. 23.
+constexpr int kFtFreeBlock = 1024;
+__global__ __launch_bounds__(kFtFreeBlock) void k_ibm_ft_free(IbmFtArgs f, DevSolid *solids, uint32_t *flag) {
   ibm_ft_body(f, (int)blockIdx.x);
   if (threadIdx.x != 0) return;
   double FT[6];
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_ibm_ft_free(IbmFtArgs f, DevSolid *s
 }
 
 void launch_ibm_ft_free(lbm_ctx *c, int64_t t) {
-  hipLaunchKernelGGL(k_ibm_ft_free, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t),
+  hipLaunchKernelGGL(k_ibm_ft_free, dim3((uint32_t)c->nsolid), dim3(kFtFreeBlock), 0, c->stream, ibm_ft_args_of(c, t),
                      c->at<DevSolid>(c->L.solids), c->at<uint32_t>(c->L.misc) + 6);
 }
 

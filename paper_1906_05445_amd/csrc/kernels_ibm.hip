@@ -243,28 +243,37 @@ __device__ inline uint32_t mv_cell(const IbmArgs &a, int64_t s, const int32_t *s
          (uint32_t)a.b.nx * ((uint32_t)wrapi(y + sh[1], a.b.ny) + (uint32_t)a.b.ny * (uint32_t)wrapi(z + sh[2], a.b.nz));
 }
 
-// Per point: box weights for the displacement d(t), U^d, the lever arm; the
+// Per point, 16 threads: the 15 box weights for the displacement d(t), one
+// each; the last thread the position, lever arm and U^d, and (point 0) the
 // shift of step t.
-__global__ void k_ibm_move(IbmArgs a) {
+constexpr int kMoveLanes = 16;
+__global__ __launch_bounds__(256) void k_ibm_move(IbmArgs a) {
 #pragma clang fp contract(off)
-  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t l = g / kMoveLanes;
+  const int j = (int)(g % kMoveLanes);
   if (l >= a.nlag) return;
   const DevSolid &s = a.solids[a.sid[l]];
-  double d[3], del[3], X[3], c[3], r[3], ud[3];
-  int n[3];
+  double d[3];
   solid_disp(s, a.t, d);
+  if (j < 3 * kMvBox) {
+    const int ax = j / kMvBox, k = j % kMvBox;
+    double w = k == 0 ? 1.0 : 0.0;  // the z axis of D2Q9
+    if (ax < a.b.D) {
+      const double del = d[ax] - floor(d[ax]);
+      w = phi_of(a.delta, (double)(a.base[l * 3 + ax] + k) - (a.X[l * 3 + ax] + del));
+    }
+    a.wts[l * 24 + j] = w;
+    return;
+  }
+  double X[3], c[3], r[3], ud[3];
+  int n[3];
   for (int ax = 0; ax < 3; ax++) {
     const bool on = ax < a.b.D;
     n[ax] = on ? (int)floor(d[ax]) : 0;
-    del[ax] = on ? d[ax] - (double)n[ax] : 0.0;
     X[ax] = on ? a.X[l * 3 + ax] + d[ax] : a.X[l * 3 + ax];
   }
   double *w = a.wts + l * 24;
-  for (int ax = 0; ax < 3; ax++)
-    for (int k = 0; k < kMvBox; k++)
-      w[ax * kMvBox + k] = (ax == 2 && a.b.D == 2)
-                               ? (k == 0 ? 1.0 : 0.0)
-                               : phi_of(a.delta, (double)(a.base[l * 3 + ax] + k) - (a.X[l * 3 + ax] + del[ax]));
   solid_centre(s, a.t, a.b, c);
   lever_arm(s, c, X[0], X[1], X[2], a.b, r);
   wall_vel(s, r, ud);
@@ -455,7 +464,7 @@ void launch_ibm_setup(lbm_ctx *c) {
   if (c->nlag <= 0) return;
   IbmArgs a = ibm_args(c, c->t);
   if (c->ibm_moving)
-    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag * kMoveLanes + 255) / 256)), dim3(256), 0, c->stream, a);
   else
     hipLaunchKernelGGL(k_ibm_weights, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
   hipLaunchKernelGGL(k_ibm_mark, dim3((uint32_t)((c->nshell + 255) / 256)), dim3(256), 0, c->stream, a);
@@ -469,7 +478,7 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
       gl((uint32_t)((c->nlag + kIbmPointsPerBlock - 1) / kIbmPointsPerBlock)),
       gsp((uint32_t)((c->nshell + kSpreadCellsPerBlock - 1) / kSpreadCellsPerBlock));
   if (c->ibm_moving) {
-    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag * kMoveLanes + 255) / 256)), dim3(256), 0, c->stream, a);
     if (c->Q == 9)
       hipLaunchKernelGGL((k_ibm_u0_mv<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
     else

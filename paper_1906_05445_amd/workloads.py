@@ -145,6 +145,7 @@ class Case:
     retraction: float = 0.0
     meta: dict = field(default_factory=dict)
     delta: int = 4
+    g_fluid_only: bool = True
 
 
 def cylinder_channel_2d(n=64, R=8.3, centre=(32.4, 31.7), g=1e-6, tau=0.8, steps=2000, method="LINEAR"):
@@ -164,19 +165,23 @@ def sphere_box(n=128, R=16.2, Re=20.0, tau=0.8, seed=2, method="QUADRATIC", stor
                 method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U}, delta=delta)
 
 
-def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, storage="F32", steps=5000):
+def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, storage="F32", steps=5000,
+                    method="QUADRATIC"):
     """A free sphere settling under gravity in a periodic cube (the density ratio of the paper's
-    sedimentation case, Sec. 3.2), quadratic IBB.  Gravity from the Stokes estimate of a settling speed
-    U_set; the fluid carries the opposite body force, so that no net force drives the box."""
+    sedimentation case, Sec. 3.2), quadratic IBB (Eq. 20) or the IBM (Eq. 23).  Gravity from the Stokes
+    estimate of a settling speed U_set; the fluid carries the opposite body force, so that no net force
+    drives the box: on the fluid outside the sphere with IBB, on every cell with the IBM (whose fluid
+    fills the sphere)."""
     rng = np.random.default_rng(seed)
     c = np.array([n / 2.0] * 3) + rng.random(3)
     nu = nu_of_tau(tau)
     Vp = 4.0 / 3.0 * math.pi * R ** 3
     gz = -6.0 * math.pi * nu * R * U_set / ((density - 1.0) * Vp)
-    g_fluid = -(density - 1.0) * Vp * gz / (n ** 3 - Vp)
+    ibm = method == "IBM"
+    g_fluid = -(density - 1.0) * Vp * gz / (n ** 3 - (0.0 if ibm else Vp))
     return Case(f"settle_{n}", "D3Q19", "MRT", (n, n, n), tau, (0.0, 0.0, g_fluid),
-                [solid("sphere", c, R, density=density, gravity=(0.0, 0.0, gz))], "QUADRATIC", steps, storage,
-                meta={"U_set": U_set, "density": density})
+                [solid("sphere", c, R, density=density, gravity=(0.0, 0.0, gz))], method, steps, storage,
+                meta={"U_set": U_set, "density": density}, g_fluid_only=not ibm)
 
 
 def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, storage="F64", steps=10000,
