@@ -517,10 +517,9 @@ __global__ __launch_bounds__(64) void k_ibb(S *__restrict__ P, const S *__restri
 // collision at t, for the macroscopic readout).  Vector stores; kernels
 // launched after it read the new table.  flag: set when a velocity component
 // reaches half a cell per step.
-__device__ inline void free_update_one(DevSolid *solids, int k, const double FT[6], const Box3 &b, int64_t t,
-                                       uint32_t *flag) {
+__device__ inline void free_update_with(const DevSolid &s, DevSolid *solids, int k, const double FT[6],
+                                        const Box3 &b, int64_t t, uint32_t *flag) {
 #pragma clang fp contract(off)
-  const DevSolid s = solids[k];
   if (!s.free) return;
   const double m = s.rho_p * s.Vp;
   double c[3], vn[3], wn[3], cn[3];
@@ -568,17 +567,63 @@ __device__ inline void free_update_one(DevSolid *solids, int k, const double FT[
   }
   o.tref = t + 1;
 }
+__device__ inline void free_update_one(DevSolid *solids, int k, const double FT[6], const Box3 &b, int64_t t,
+                                       uint32_t *flag) {
+  const DevSolid s = solids[k];
+  free_update_with(s, solids, k, FT, b, t, flag);
+}
 
 // IBM force/torque of step t of a free IBM solid (one block of 1024 threads
 // per solid: the sum is latency-bound) and, by the thread that wrote them,
 // its motion to t + 1 by Eq. 23.
 constexpr int kFtFreeBlock = 1024;
+// The solid's record is copied to LDS while the points are summed, the six
+// sums share one pass of wave shuffles, and the totals reach the updating
+// thread through LDS.
 __global__ __launch_bounds__(kFtFreeBlock) void k_ibm_ft_free(IbmFtArgs f, DevSolid *solids, uint32_t *flag) {
-  ibm_ft_body(f, (int)blockIdx.x);
+#pragma clang fp contract(off)
+  static_assert(sizeof(DevSolid) % 8 == 0 && sizeof(DevSolid) / 8 <= kFtFreeBlock, "solid record copy");
+  __shared__ DevSolid sd;
+  __shared__ double part[kFtFreeBlock / 64][6];
+  __shared__ double tot[6];
+  const int s = (int)blockIdx.x;
+  if (threadIdx.x < sizeof(DevSolid) / 8)
+    reinterpret_cast<uint64_t *>(&sd)[threadIdx.x] = reinterpret_cast<const uint64_t *>(solids + s)[threadIdx.x];
+  double c[3] = {0.0, 0.0, 0.0};
+  if (!f.mv) solid_centre(solids[s], f.t, f.b, c);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t l0 = f.start[s], l1 = l0 + f.count[s];
+  for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+    double r[3], F[3];
+    if (f.mv)
+      for (int k = 0; k < 3; k++) r[k] = f.wts[l * 24 + 16 + k];
+    else
+      lever_arm(solids[s], c, f.X[l * 3], f.X[l * 3 + 1], f.X[l * 3 + 2], f.b, r);
+    for (int k = 0; k < 3; k++) F[k] = -f.Fsum[l * 3 + k] * f.dV[l];
+    acc[0] += F[0];
+    acc[1] += F[1];
+    acc[2] += F[2];
+    acc[3] += r[1] * F[2] - r[2] * F[1];
+    acc[4] += r[2] * F[0] - r[0] * F[2];
+    acc[5] += r[0] * F[1] - r[1] * F[0];
+  }
+  for (int k = 0; k < 6; k++)
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 6; k++) part[wv][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) v += part[w][threadIdx.x];
+    tot[threadIdx.x] = v;
+    f.hist[(uint64_t)s * 6 + threadIdx.x] = v;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   double FT[6];
-  for (int k = 0; k < 6; k++) FT[k] = f.hist[(uint64_t)blockIdx.x * 6 + k];
-  free_update_one(solids, (int)blockIdx.x, FT, f.b, f.t, flag);
+  for (int k = 0; k < 6; k++) FT[k] = tot[k];
+  free_update_with(sd, solids, s, FT, f.b, f.t, flag);
 }
 
 void launch_ibm_ft_free(lbm_ctx *c, int64_t t) {
