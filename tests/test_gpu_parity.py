@@ -481,9 +481,9 @@ def test_free_sphere_fp32(lbm):
 
 def test_free_solid_rejections(lbm):
     free = W.solid("sphere", (8.2, 7.9, 8.1), 3.5, density=1.5)
-    g = lbm.Lattice("D3Q19", "MRT", "F64", (16, 16, 16), 0.8)
-    with pytest.raises(lbm.LBMError):
-        g.set_solids([free], "IBM")
+    g = lbm.Lattice("D3Q19", "MRT", "F64", (16, 16, 16), 0.8, max_solids=2)
+    with pytest.raises(lbm.LBMError):  # a moving IBM solid must be the only solid
+        g.set_solids([free, W.solid("sphere", (2.1, 2.2, 2.3), 1.5)], "IBM")
     with pytest.raises(lbm.LBMError):
         g.set_solids([W.solid("sphere", (8.2, 7.9, 8.1), 6.5, inverted=True, density=1.5)], "QUADRATIC")
     g.close()
@@ -491,4 +491,6 @@ def test_free_solid_rejections(lbm):
     m = b.admit("MRT", "F64", (16, 16, 16), 0.8)
     with pytest.raises(lbm.LBMError):
         m.set_solids([free], "QUADRATIC")
+    with pytest.raises(lbm.LBMError):
+        m.set_solids([free], "IBM")
     b.close()
