@@ -98,6 +98,10 @@ def lib():
         L.orc_phi_n.argtypes = [ctypes.c_int, ctypes.c_double]
         L.orc_phi_n.restype = ctypes.c_double
         L.orc_set_ibm_delta.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_ibm_inner.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_kempe_volume.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_kempe_volume.restype = ctypes.c_double
+        L.orc_kempe_inner.argtypes = [ctypes.c_void_p, ctypes.c_int, _d]
         L.orc_strain.argtypes = [ctypes.c_void_p, _d, _d]
         L.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _d]
         L.orc_solid_state.argtypes = [ctypes.c_void_p, _d]
@@ -201,6 +205,19 @@ class Oracle:
 
     def set_ibm_iters(self, n_iter):
         lib().orc_set_ibm_iters(self._h, int(n_iter))
+
+    def set_ibm_inner(self, mode):
+        """Inner-fluid treatment of free IBM solids: "FENG" (Eq. 23) or "KEMPE" (Eq. 24-26)."""
+        if lib().orc_set_ibm_inner(self._h, {"FENG": 0, "KEMPE": 1}[mode]) != 0:
+            raise ValueError("inner-fluid mode")
+
+    def kempe_volume(self, k):
+        return lib().orc_kempe_volume(self._h, int(k))
+
+    def kempe_inner(self, k):
+        out = np.zeros(6)
+        lib().orc_kempe_inner(self._h, int(k), _p(out))
+        return out
 
     def set_ibm_delta(self, points):
         """Delta function of the IBM: 4 (Eq. 6, default), 3 (Roma et al.) or 2 (linear)."""

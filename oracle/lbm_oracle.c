@@ -119,6 +119,10 @@ typedef struct {
    * (unwrapped; the points move rigidly with it), and the velocities of the
    * step before (Eq. 23 reads v^{n-1}, w^{n-1}) */
   double disp[3], Up[3], Wp[3];
+  /* Kempe's inner-fluid integrals (Eq. 24-26) of the last step and of the
+   * step before: sum alpha u and sum alpha r x u; kfirst: no step yet */
+  double Ik[6], Ikp[6];
+  int kfirst;
 } solid_t;
 
 typedef struct {
@@ -151,6 +155,7 @@ typedef struct orc {
   link_t *links;
   /* IBM */
   int n_iter;
+  int inner;      /* free IBM solids: 0 Feng & Michaelides (Eq. 23), 1 Kempe (Eq. 24-26) */
   int delta;      /* points of the delta function: 4 (Eq. 6), 3 or 2 */
   long nlag;
   double *X;      /* [nlag][3] */
@@ -821,6 +826,8 @@ int orc_set_solids(orc *o, int n, const int *kind, const int *inverted, const do
       s->Up[a] = s->U[a];
       s->Wp[a] = s->W[a];
     }
+    for (int a = 0; a < 6; a++) s->Ik[a] = s->Ikp[a] = 0.0;
+    s->kfirst = 1;
     s->moving = (s->U[0] != 0.0 || s->U[1] != 0.0 || s->U[2] != 0.0);
     if (s->moving && (s->kind == K_PLANE || (method == M_IBM && s->inverted))) return -5;
   }
@@ -885,6 +892,62 @@ void orc_solid_state(const orc *o, double *st) {
       st[9 * k + 3 + a] = o->sol[k].U[a];
       st[9 * k + 6 + a] = o->sol[k].W[a];
     }
+}
+int orc_set_ibm_inner(orc *o, int mode) {
+  if (mode != 0 && mode != 1) return -1;
+  o->inner = mode;
+  return 0;
+}
+/* Eq. 25 with the signed distance of Eq. 26 (a = b = c = R): the solid
+ * fraction of the grid cell centred on node (x, y, z), from phi at its 8
+ * corners x +- 1/2 (4 in 2D); phi < 0 inside. */
+static double kempe_alpha(const orc *o, const solid_t *s, int x, int y, int z) {
+  double num = 0.0, den = 0.0;
+  const int nz = o->D == 2 ? 1 : 2;
+  for (int kz = 0; kz < nz; kz++)
+    for (int ky = 0; ky < 2; ky++)
+      for (int kx = 0; kx < 2; kx++) {
+        double r[3];
+        lever(o, s, (double)x + kx - 0.5, (double)y + ky - 0.5, o->D == 2 ? 0.0 : (double)z + kz - 0.5, r);
+        const double phi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) / s->R - 1.0;
+        if (phi < 0.0) num += -phi;
+        den += fabs(phi);
+      }
+  return den > 0.0 ? num / den : 0.0;
+}
+/* Kempe's integrals over solid k of the velocity u of the collision just
+ * taken (Eq. 24, h = 1): I = sum alpha u, L = sum alpha (x - Y) x u. */
+static void kempe_integrals(const orc *o, const solid_t *s, double out[6]) {
+  for (int a = 0; a < 6; a++) out[a] = 0.0;
+  for (long n = 0; n < o->N; n++) {
+    int x, y, z;
+    coords_of(o, n, &x, &y, &z);
+    const double al = kempe_alpha(o, s, x, y, z);
+    if (al == 0.0) continue;
+    double r[3], u[3];
+    lever(o, s, (double)x, (double)y, (double)z, r);
+    for (int a = 0; a < 3; a++) u[a] = o->u_out[a * o->N + n];
+    out[0] += al * u[0];
+    out[1] += al * u[1];
+    out[2] += al * u[2];
+    out[3] += al * (r[1] * u[2] - r[2] * u[1]);
+    out[4] += al * (r[2] * u[0] - r[0] * u[2]);
+    out[5] += al * (r[0] * u[1] - r[1] * u[0]);
+  }
+}
+/* Sum of alpha over the box (the level-set volume of solid k) and the last
+ * step's Kempe integrals of solid k. */
+double orc_kempe_volume(const orc *o, int k) {
+  double v = 0.0;
+  for (long n = 0; n < o->N; n++) {
+    int x, y, z;
+    coords_of(o, n, &x, &y, &z);
+    v += kempe_alpha(o, &o->sol[k], x, y, z);
+  }
+  return v;
+}
+void orc_kempe_inner(const orc *o, int k, double out[6]) {
+  for (int a = 0; a < 6; a++) out[a] = o->sol[k].Ik[a];
 }
 int orc_set_ibm_delta(orc *o, int points) {
   if (points != 2 && points != 3 && points != 4) return -1;
@@ -1073,14 +1136,23 @@ static double wrap_pos(double y, int L) {
  *   I_p (w^{n+1} - w^n) = (I_p / rho_p) (w^n - w^{n-1}) + T,
  * F, T being the IBM force and torque of the step (-sum F_l dV_l and
  * -sum (X_l - Y) x F_l dV_l); the position as above.  At the first step
- * v^{n-1} = v^n (the solid moved steadily before). */
+ * v^{n-1} = v^n (the solid moved steadily before).  With Kempe's treatment
+ * (Eq. 24-26, orc_set_ibm_inner(o, 1)) the inner-fluid terms are the change
+ * over the step of I = sum alpha u and L = sum alpha r x u (u of the
+ * collision, h = 1):
+ *   rho_p V_p (v^{n+1} - v^n) = (I^n - I^{n-1}) + F + (rho_p - 1) V_p g,
+ *   I_p (w^{n+1} - w^n) = (L^n - L^{n-1}) + T,
+ * with I^{-1} = I^0 at the first step. */
 static void advance_free(orc *o, int k) {
   solid_t *s = &o->sol[k];
   const double *F = &o->FT[6 * k], *T = &o->FT[6 * k + 3];
   const double m = s->rho_p * s->Vp;
   double vn[3], wn[3];
   for (int a = 0; a < 3; a++) {
-    if (o->method == M_IBM) {
+    if (o->method == M_IBM && o->inner == 1) {
+      vn[a] = s->U[a] + ((s->Ik[a] - s->Ikp[a]) + F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
+      wn[a] = s->W[a] + ((s->Ik[3 + a] - s->Ikp[3 + a]) + T[a]) / s->Ip;
+    } else if (o->method == M_IBM) {
       vn[a] = s->U[a] + (s->Vp * (s->U[a] - s->Up[a]) + F[a] + (s->rho_p - 1.0) * s->Vp * s->grav[a]) / m;
       wn[a] = s->W[a] + (s->Ip / s->rho_p * (s->W[a] - s->Wp[a]) + T[a]) / s->Ip;
     } else {
@@ -1103,6 +1175,7 @@ static void advance_free(orc *o, int k) {
     s->U[a] = vn[a];
     s->W[a] = wn[a];
   }
+  for (int a = 0; a < 6; a++) s->Ikp[a] = s->Ik[a];
 }
 
 static void move_solids(orc *o) {
@@ -1194,6 +1267,16 @@ static void one_step(orc *o) {
   }
   collide(o, drho, j, Ft);
   solid_node_output(o);
+  if (o->method == M_IBM && o->inner == 1)
+    for (int k = 0; k < o->nsolid; k++) {
+      solid_t *s = &o->sol[k];
+      if (!s->free) continue;
+      kempe_integrals(o, s, s->Ik);
+      if (s->kfirst) {  /* the solid moved steadily before: no change of its inner momentum yet */
+        for (int a = 0; a < 6; a++) s->Ikp[a] = s->Ik[a];
+        s->kfirst = 0;
+      }
+    }
   /* streaming (push) */
   for (long n = 0; n < N; n++) {
     if (o->excl[n]) continue;
