@@ -142,3 +142,12 @@ def test_moving_ibm_rules(lbm):
     g.step(3)
     assert g.check()
     g.close()
+
+
+def test_free_ibm_fp16(lbm):
+    """FP16 deviation storage against the FP64 oracle, with the FP16 bars of the fixed-solid parity tests:
+    velocities within 2e-2 of max|u|, force and torque within 5e-2 of their scale; solid state within 1e-4
+    absolute (velocities of order 5e-3, centres of order 20)."""
+    s = W.solid("sphere", (14.6, 15.3, 20.8), 6.0, density=2.0, gravity=(0.0, 0.0, -3e-4))
+    gpu, orc = _run_pair(lbm, "D3Q19", (30, 31, 36), s, 100, storage="F16", chunks=(100,))
+    _compare(gpu, orc, tol_f=None, tol_u=2e-2, tol_F=5e-2, tol_s=1e-4)
