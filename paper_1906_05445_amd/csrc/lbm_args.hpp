@@ -325,7 +325,6 @@ void fill_ibb_args(lbm_ctx *c, IbbArgs *a);
 void fill_link_args(lbm_ctx *c, LinkArgs *a);
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a);
 IbmFtArgs ibm_ft_args_of(lbm_ctx *c, int64_t t);
-void launch_ibm_ft_free(lbm_ctx *c, int64_t t);
 
 // batched launches (grid = persistent blocks)
 void launch_sweep_batch(const BatchLaunch &b, const WorkList *wl, int coll, int nt, int order, uint32_t grid,

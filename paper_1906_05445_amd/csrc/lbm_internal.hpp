@@ -211,6 +211,7 @@ void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool r
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
 void launch_refill_count(lbm_ctx *c, int64_t t, void *post);
 void launch_ft_reduce_free(lbm_ctx *c, int64_t t);
+void launch_ibm_ft_free(lbm_ctx *c, int64_t t);
 void launch_strain(lbm_ctx *c, const void *src, double *out, int part);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
 void launch_fill_zero(lbm_ctx *c, void *A);

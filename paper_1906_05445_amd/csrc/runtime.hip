@@ -558,6 +558,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->retraction = opts ? opts->retraction : 0.0;
   if (c->n_iter < 0 || !std::isfinite(c->retraction) || c->delta < 2 || c->delta > 4)
     return set_err(c, "IBM options"), LBM_EINVAL;
+  if (c->ibm_moving && c->n_iter == 0) return set_err(c, "a moving IBM solid needs forcing iterations"), LBM_EINVAL;
   c->nlinks = 0;
   c->k5_chunks = 0;
   c->link_lists = false;
@@ -850,6 +851,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     // IBM: forcing iterations now; the solid force of this step is summed in the sweep launch
     const bool ibm = c->method == LBM_IBM && c->nsolid > 0 && c->nlag > 0 && c->n_iter > 0;
     if (ibm) launch_ibm_step(c, A, c->t, false);
+    else if (c->ibm_free) launch_ibm_ft_free(c, c->t);  // no points: no fluid force, the motion by Eq. 23 still
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const TuneStep ts = tune_step(c);
     const int policy = ts.policy;

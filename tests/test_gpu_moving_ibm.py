@@ -151,3 +151,25 @@ def test_free_ibm_fp16(lbm):
     s = W.solid("sphere", (14.6, 15.3, 20.8), 6.0, density=2.0, gravity=(0.0, 0.0, -3e-4))
     gpu, orc = _run_pair(lbm, "D3Q19", (30, 31, 36), s, 100, storage="F16", chunks=(100,))
     _compare(gpu, orc, tol_f=None, tol_u=2e-2, tol_F=5e-2, tol_s=1e-4)
+
+
+def test_free_ibm_without_points(lbm):
+    """A free IBM solid with no Lagrangian points feels no fluid force: its motion is the Eq. 23 recurrence
+    alone (whose closed form pins the oracle), and the fluid stays at rest."""
+    from oracle import Oracle
+
+    s = W.solid("sphere", (12.3, 11.8, 12.6), 4.0, velocity=(0.01, 0.0, -0.004), omega=(0.0, 2e-4, 1e-4),
+                density=1.6, gravity=(1e-5, -2e-5, 4e-6))
+    gpu = lbm.Lattice("D3Q19", "MRT", "F64", (24, 24, 24), 0.8)
+    orc = Oracle("D3Q19", "MRT", (24, 24, 24), 0.8)
+    gpu.set_solids([s], "IBM")
+    gpu.set_lagrangian(0, np.zeros((0, 3)), 1.0)
+    orc.set_solids([s], "IBM")
+    for n in (1, 12, 27):
+        gpu.step(n)
+    orc.step(40)
+    assert np.max(np.abs(gpu.solid_state() - orc.solid_state())) <= 1e-14
+    assert np.max(np.abs(gpu.get_f() - orc.get_f())) == 0.0
+    with pytest.raises(lbm.LBMError) as e:  # no forcing iterations for a moving IBM solid
+        gpu.set_solids([s], "IBM", n_iter=0)
+    assert e.value.status == lbm.LBM_EINVAL
