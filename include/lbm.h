@@ -137,7 +137,8 @@ typedef struct {
  * and a context outside any batch (else LBM_EUNSUPPORTED); a step that would
  * carry one faster than half a cell per step ends with LBM_EDIVERGED.  A
  * moving (translating or free) IBM solid must moreover be the only solid,
- * with no fluid-only body force (body_force zero or body_force_fluid_only 0);
+ * with no fluid-only body force (body_force zero or body_force_fluid_only 0)
+ * and at least one forcing iteration (else LBM_EINVAL);
  * its Lagrangian points move rigidly with it (their orientation is kept),
  * and it uses twice the point capacity of a fixed one (at most
  * max_lagrangian / 2 points). */
