@@ -35,7 +35,7 @@ KINDS = {"sphere": 0, "cylinder": 1, "plane": 2}
 
 def build() -> str:
     """Compile the oracle into ``oracle/liblbm_oracle.so``."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
            "-o", _SO, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     return _SO
@@ -103,6 +103,9 @@ def lib():
         L.orc_kempe_volume.restype = ctypes.c_double
         L.orc_kempe_inner.argtypes = [ctypes.c_void_p, ctypes.c_int, _d]
         L.orc_strain.argtypes = [ctypes.c_void_p, _d, _d]
+        L.orc_set_form.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_form.argtypes = [ctypes.c_void_p]
+        L.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _d]
         L.orc_solid_state.argtypes = [ctypes.c_void_p, _d]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
@@ -147,10 +150,16 @@ def _axis_index(axis):
 
 
 class Oracle:
-    """One periodic lattice stepped by the FP64 oracle."""
+    """One periodic lattice stepped by the FP64 oracle.
+
+    form: "f" stores the populations themselves, the equations as written
+    (the default); "h" stores their deviations from the rest state, the same
+    step with three decades less rounding (the two are pinned against each
+    other in tests/test_oracle_forms.py).  threads: threads of the per-cell
+    loops (results do not depend on it)."""
 
     def __init__(self, lattice="D3Q19", collision="MRT", shape=(16, 16, 16), tau=0.8, rates=None,
-                 g=(0.0, 0.0, 0.0), g_fluid_only=True):
+                 g=(0.0, 0.0, 0.0), g_fluid_only=True, form="f", threads=1):
         nx, ny, nz = (tuple(shape) + (1,))[:3] if len(shape) == 2 else tuple(shape)
         self.shape = (nx, ny, nz)
         self.lattice = lattice
@@ -164,6 +173,11 @@ class Oracle:
         if not h:
             raise ValueError("oracle rejected the lattice parameters")
         self._h = ctypes.c_void_p(h)
+        if form not in ("f", "h"):
+            raise ValueError(form)
+        self.form = form
+        lib().orc_set_form(self._h, 1 if form == "f" else 0)
+        lib().orc_set_threads(self._h, int(threads))
         self.N = nx * ny * nz
         self.nsolid = 0
         self.nlag = 0
@@ -242,8 +256,11 @@ class Oracle:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.N)
         lib().orc_set_f(self._h, _p(f))
 
+    def set_threads(self, n):
+        lib().orc_set_threads(self._h, int(n))
+
     def get_h(self):
-        """Stored deviations h = f - w (exact, no conversion)."""
+        """Deviations h = f - w (exact in the "h" form)."""
         out = np.empty((self.Q, self.N), dtype=np.float64)
         lib().orc_get_h(self._h, _p(out))
         return out

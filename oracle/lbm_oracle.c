@@ -35,11 +35,23 @@
  *      Eq. 23, under the force and torque of step 3) and carry its Lagrangian
  *      points with it.
  *
- * Populations are stored as deviations h_i = f_i - w_i from the rest state
- * (rho = 1, u = 0).  Every relation used is linear in f apart from f_eq, and
- * all bounce-back weights sum to one, so the step is the same computation
- * written for h (f - f_eq = h - h_eq); it only keeps the stored numbers
- * small, which lowers the oracle's own rounding by about three decades.
+ * Two representations of the same step (orc_set_form):
+ *   - literal (the default): the populations f_i themselves, the equilibrium
+ *     f_eq(rho, u), rho = sum f_i, and the momentum exchange of Eq. 17 summed
+ *     term by term with plain additions, as the equations are written;
+ *   - deviation: h_i = f_i - w_i from the rest state (rho = 1, u = 0).  Every
+ *     relation used is linear in f apart from f_eq, and all bounce-back
+ *     weights sum to one, so the step is the same computation written for h
+ *     (f - f_eq = h - h_eq, and the rest-state part of each Eq. 17 term,
+ *     w_i (e_ibar - e_i), is added in closed form); Eq. 17 is summed with
+ *     compensated additions.  This keeps the stored numbers small, which
+ *     lowers the rounding by about three decades.
+ * tests/test_oracle_forms.py pins the two against each other within the
+ * literal form's measured rounding, for every boundary scheme and the IBM.
+ *
+ * Threads (orc_set_threads, default 1) split only the per-cell loops
+ * (moments, collision, streaming, classification), whose results do not
+ * depend on the split; every sum across cells keeps its serial order.
  *
  * The paper does not print the velocity sets, the equilibrium, the MRT
  * matrix, the relaxation rates, the forcing term, the linear Bouzidi formula
@@ -169,6 +181,8 @@ typedef struct orc {
   long hist_len, hist_cap;
   long t;
   int stepped;
+  int literal;   /* 1: f stores f_i; 0: f stores h_i = f_i - w_i */
+  int nthreads;  /* threads of the per-cell loops */
 } orc;
 
 static void solid_node_output(struct orc *o);
@@ -382,6 +396,7 @@ static int in_solid(const orc *o, const solid_t *s, int x, int y, int z) {
 }
 
 static void classify(orc *o) {
+#pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < o->N; n++) {
     int x, y, z;
     coords_of(o, n, &x, &y, &z);
@@ -758,10 +773,12 @@ orc *orc_create(int lattice, int collision, int nx, int ny, int nz, double tau, 
   o->strain_out = (double *)calloc(6 * o->N, sizeof(double));
   o->type_out = (unsigned char *)calloc(o->N, 1);
   o->fibm = (double *)calloc(3 * o->N, sizeof(double));
+  o->literal = 1;
+  o->nthreads = 1;
   for (long n = 0; n < o->N; n++) {
     o->owner[n] = -1;
     o->rho_out[n] = 1.0;
-    for (int i = 0; i < o->Q; i++) o->f[(long)i * o->N + n] = 0.0; /* rest: f = w, rho = 1 */
+    for (int i = 0; i < o->Q; i++) o->f[(long)i * o->N + n] = o->w[i]; /* rest: f = w, rho = 1 */
   }
   o->n_iter = 5;
   o->delta = 4;
@@ -1034,17 +1051,23 @@ static void strain_node(const orc *o, const double *hi, const double *heq, const
   S[5] = X[5];
 }
 
-static void collide(orc *o, const double *drho, const double *j, const double *Ftot) {
+/* Collision of every fluid node (Eq. 1 or Eq. 3 with the forcing of Sec.
+ * 2.1), from the moments rho (and drho = rho - 1) and j of the stored
+ * populations; hi and heq below are f and f_eq in the literal form, h and
+ * h_eq = f_eq - w in the deviation form. */
+static void collide(orc *o, const double *rhoa, const double *drho, const double *j, const double *Ftot) {
   int Q = o->Q;
   long N = o->N;
+#pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++) {
     if (o->excl[n]) continue;
     double hi[QMAX], heq[QMAX], Fi[QMAX], u[3], F[3];
-    double rho = 1.0 + drho[n];
+    double rho = rhoa[n];
     for (int i = 0; i < Q; i++) hi[i] = o->f[(long)i * N + n];
     for (int a = 0; a < 3; a++) F[a] = Ftot[a * N + n];
     for (int a = 0; a < 3; a++) u[a] = (j[a * N + n] + 0.5 * F[a]) / rho;
-    heq_all(o, drho[n], u, heq);
+    if (o->literal) feq_all(o, rho, u, heq);
+    else heq_all(o, drho[n], u, heq);
     guo_all(o, u, F, Fi);
     if (o->collision == 0) {
       /* Eq. 1 with F_i = (1 - 1/(2 tau)) F_hat_i */
@@ -1218,7 +1241,9 @@ static void move_solids(orc *o) {
       rs += r;
       cnt++;
     }
-    double drb = cnt ? rs / cnt : 0.0; /* mean density minus 1 */
+    /* mean density of those neighbours (literal form; the deviation form
+     * sums h, the mean density minus 1); rho0 = 1 when there is none */
+    double drb = cnt ? rs / cnt : (o->literal ? 1.0 : 0.0);
     /* the solid that covered the node at t; its wall velocity at t+1 */
     int sid = old_owner[n];
     double uw[3] = {0.0, 0.0, 0.0}, feq[QMAX];
@@ -1227,7 +1252,8 @@ static void move_solids(orc *o) {
       lever(o, &o->sol[sid], (double)x, (double)y, (double)z, r);
       wall_velocity(&o->sol[sid], r, uw);
     }
-    heq_all(o, drb, uw, feq);
+    if (o->literal) feq_all(o, drb, uw, feq);
+    else heq_all(o, drb, uw, feq);
     for (int i = 0; i < o->Q; i++) o->f[(long)i * N + n] = feq[i];
   }
   free(old);
@@ -1242,6 +1268,10 @@ static void one_step(orc *o) {
   double *rho = (double *)malloc(sizeof(double) * N);
   double *j = (double *)calloc(3 * N, sizeof(double));
   double *Ft = (double *)calloc(3 * N, sizeof(double));
+  /* density and momentum (sums over i of f_i and f_i e_i; the deviation
+   * form sums h_i, whose density sum is rho - 1 and whose momentum sum is j,
+   * since sum w_i = 1 and sum w_i e_i = 0) */
+#pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++) {
     double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     if (!o->excl[n])
@@ -1252,8 +1282,13 @@ static void one_step(orc *o) {
         jy += v * o->e[i][1];
         jz += v * o->e[i][2];
       }
-    drho[n] = r;
-    rho[n] = 1.0 + r;
+    if (o->literal) {
+      rho[n] = o->excl[n] ? 1.0 : r;
+      drho[n] = rho[n] - 1.0;
+    } else {
+      drho[n] = r;
+      rho[n] = 1.0 + r;
+    }
     j[n] = jx;
     j[N + n] = jy;
     j[2 * N + n] = jz;
@@ -1265,7 +1300,7 @@ static void one_step(orc *o) {
     ibm_force(o, rho, j, Ft);
     for (long n = 0; n < 3 * N; n++) Ft[n] += o->fibm[n];
   }
-  collide(o, drho, j, Ft);
+  collide(o, rho, drho, j, Ft);
   solid_node_output(o);
   if (o->method == M_IBM && o->inner == 1)
     for (int k = 0; k < o->nsolid; k++) {
@@ -1277,7 +1312,8 @@ static void one_step(orc *o) {
         s->kfirst = 0;
       }
     }
-  /* streaming (push) */
+  /* streaming (push); every target slot (i, x + e_i) has one source */
+#pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++) {
     if (o->excl[n]) continue;
     int x, y, z;
@@ -1289,6 +1325,7 @@ static void one_step(orc *o) {
   }
   /* interpolated bounce-back and momentum exchange (Eq. 10, 11, 12-14, 16, 17) */
   acc_t *lacc = (acc_t *)calloc(6 * (o->nsolid > 0 ? o->nsolid : 1), sizeof(acc_t));
+  double *plain = (double *)calloc(6 * (o->nsolid > 0 ? o->nsolid : 1), sizeof(double));
   for (long l = 0; l < o->nlink; l++) {
     const link_t *lk = &o->links[l];
     int i = lk->dir, ib = o->opp[i];
@@ -1319,24 +1356,35 @@ static void one_step(orc *o) {
     else
       fnew = orc_ibb_value(o->method, lk->q, lk->ff_ok, lk->fff_ok, fb_f, fb_ff, fb_fff, fs_f, fs_f, fs_ff, B);
     o->fnew[(long)i * N + n] = fnew;
-    /* Eq. 17: F dt = sum [f*_ibar (e_ibar - u_w) - f_i(t+1) (e_i - u_w)].  With
-     * f = w + h and w_ibar = w_i the rest-state part is w_i (e_ibar - e_i)
-     * = -2 w_i e_i, the wall velocity cancelling out of it. */
+    /* Eq. 17: F dt = sum [f*_ibar (e_ibar - u_w) - f_i(t+1) (e_i - u_w)].  In
+     * the deviation form f = w + h, and with w_ibar = w_i the rest-state part
+     * is w_i (e_ibar - e_i) = -2 w_i e_i, the wall velocity cancelling out of
+     * it. */
     double dF[3];
-    for (int a = 0; a < 3; a++)
-      dF[a] = fb_f * ((double)o->e[ib][a] - uw[a]) - fnew * ((double)o->e[i][a] - uw[a]) -
-              2.0 * o->w[i] * (double)o->e[i][a];
-    acc_t *A = &lacc[6 * lk->sid];
-    acc_add(&A[0], dF[0]);
-    acc_add(&A[1], dF[1]);
-    acc_add(&A[2], dF[2]);
-    acc_add(&A[3], r[1] * dF[2] - r[2] * dF[1]);
-    acc_add(&A[4], r[2] * dF[0] - r[0] * dF[2]);
-    acc_add(&A[5], r[0] * dF[1] - r[1] * dF[0]);
+    for (int a = 0; a < 3; a++) {
+      dF[a] = fb_f * ((double)o->e[ib][a] - uw[a]) - fnew * ((double)o->e[i][a] - uw[a]);
+      if (!o->literal) dF[a] -= 2.0 * o->w[i] * (double)o->e[i][a];
+    }
+    const double dT[3] = {r[1] * dF[2] - r[2] * dF[1], r[2] * dF[0] - r[0] * dF[2], r[0] * dF[1] - r[1] * dF[0]};
+    if (o->literal) {
+      double *P = &plain[6 * lk->sid];
+      for (int a = 0; a < 3; a++) {
+        P[a] += dF[a];
+        P[3 + a] += dT[a];
+      }
+    } else {
+      acc_t *A = &lacc[6 * lk->sid];
+      for (int a = 0; a < 3; a++) {
+        acc_add(&A[a], dF[a]);
+        acc_add(&A[3 + a], dT[a]);
+      }
+    }
   }
   if (o->nlink > 0)
-    for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = acc_get(&lacc[k]);
+    for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = o->literal ? plain[k] : acc_get(&lacc[k]);
   free(lacc);
+  free(plain);
+#pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++)
     if (!o->excl[n])
       for (int i = 0; i < Q; i++) o->f[(long)i * N + n] = o->fnew[(long)i * N + n];
@@ -1361,17 +1409,38 @@ int orc_step(orc *o, long nsteps) {
 long orc_cells(const orc *o) { return o->N; }
 int orc_q(const orc *o) { return o->Q; }
 long orc_time(const orc *o) { return o->t; }
+/* offset between the stored value and f_i: 0 (literal) or w_i (deviation) */
+static double stored_base(const orc *o, int i) { return o->literal ? 0.0 : o->w[i]; }
 void orc_get_f(const orc *o, double *f) {
   for (int i = 0; i < o->Q; i++)
-    for (long n = 0; n < o->N; n++) f[(long)i * o->N + n] = o->w[i] + o->f[(long)i * o->N + n];
+    for (long n = 0; n < o->N; n++) f[(long)i * o->N + n] = stored_base(o, i) + o->f[(long)i * o->N + n];
 }
 void orc_set_f(orc *o, const double *f) {
   for (int i = 0; i < o->Q; i++)
-    for (long n = 0; n < o->N; n++) o->f[(long)i * o->N + n] = f[(long)i * o->N + n] - o->w[i];
+    for (long n = 0; n < o->N; n++) o->f[(long)i * o->N + n] = f[(long)i * o->N + n] - stored_base(o, i);
 }
-/* the stored deviations h = f - w */
-void orc_get_h(const orc *o, double *h) { memcpy(h, o->f, sizeof(double) * o->Q * o->N); }
-void orc_set_h(orc *o, const double *h) { memcpy(o->f, h, sizeof(double) * o->Q * o->N); }
+/* the deviations h = f - w */
+void orc_get_h(const orc *o, double *h) {
+  for (int i = 0; i < o->Q; i++)
+    for (long n = 0; n < o->N; n++)
+      h[(long)i * o->N + n] = o->literal ? o->f[(long)i * o->N + n] - o->w[i] : o->f[(long)i * o->N + n];
+}
+void orc_set_h(orc *o, const double *h) {
+  for (int i = 0; i < o->Q; i++)
+    for (long n = 0; n < o->N; n++)
+      o->f[(long)i * o->N + n] = o->literal ? h[(long)i * o->N + n] + o->w[i] : h[(long)i * o->N + n];
+}
+/* Representation of the stored populations: literal = 1 stores f_i, 0 the
+ * deviation h_i = f_i - w_i; the current state is converted. */
+void orc_set_form(orc *o, int literal) {
+  literal = literal ? 1 : 0;
+  if (literal == o->literal) return;
+  for (int i = 0; i < o->Q; i++)
+    for (long n = 0; n < o->N; n++) o->f[(long)i * o->N + n] += literal ? o->w[i] : -o->w[i];
+  o->literal = literal;
+}
+int orc_form(const orc *o) { return o->literal; }
+void orc_set_threads(orc *o, int n) { o->nthreads = n > 0 ? n : 1; }
 void orc_get_rates(const orc *o, double *S) { memcpy(S, o->S, sizeof(double) * o->Q); }
 void orc_get_mrt(const orc *o, double *M, double *Minv) {
   for (int r = 0; r < o->Q; r++)
@@ -1394,12 +1463,15 @@ void orc_forcing(const orc *o, const double *u, const double *F, double *Fi) { g
 void orc_collide_node(const orc *o, const double *fin, const double *F, double *fout) {
   double hin[QMAX], drho = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < o->Q; i++) {
-    hin[i] = fin[i] - o->w[i];
+    hin[i] = fin[i] - stored_base(o, i);
     drho += hin[i];
     for (int a = 0; a < 3; a++) j[a] += hin[i] * o->e[i][a];
   }
+  double rho = o->literal ? drho : 1.0 + drho;
+  if (o->literal) drho = rho - 1.0;
   orc tmp = *o;
   tmp.N = 1;
+  tmp.nthreads = 1;
   double hpost[QMAX];
   unsigned char ex = 0;
   double rho_o, u_o[3];
@@ -1409,8 +1481,8 @@ void orc_collide_node(const orc *o, const double *fin, const double *F, double *
   tmp.rho_out = &rho_o;
   tmp.u_out = u_o;
   double Ft[3] = {F[0], F[1], F[2]};
-  collide(&tmp, &drho, j, Ft);
-  for (int i = 0; i < o->Q; i++) fout[i] = o->w[i] + hpost[i];
+  collide(&tmp, &rho, &drho, j, Ft);
+  for (int i = 0; i < o->Q; i++) fout[i] = stored_base(o, i) + hpost[i];
 }
 
 /* Strain rate [6][N] (xx, yy, zz, xy, yz, xz) and dissipation rate
@@ -1440,9 +1512,10 @@ void orc_macros(const orc *o, double *rho, double *u, unsigned char *type) {
         r += v;
         for (int a = 0; a < 3; a++) jj[a] += v * o->e[i][a];
       }
-      if (rho) rho[n] = o->excl[n] ? o->rho_out[n] : 1.0 + r;
+      const double rr = o->literal ? r : 1.0 + r;
+      if (rho) rho[n] = o->excl[n] ? o->rho_out[n] : rr;
       if (u)
-        for (int a = 0; a < 3; a++) u[a * o->N + n] = o->excl[n] ? o->u_out[a * o->N + n] : jj[a] / (1.0 + r);
+        for (int a = 0; a < 3; a++) u[a * o->N + n] = o->excl[n] ? o->u_out[a * o->N + n] : jj[a] / rr;
     }
   } else {
     if (rho) memcpy(rho, o->rho_out, sizeof(double) * o->N);

@@ -158,34 +158,42 @@ def test_mrt_single_rate_equals_bgk(lat):
 
 
 @pytest.mark.parametrize("lat", LATTICES)
-def test_no_relaxation_step_is_exact_streaming(lat):
-    """With S = 0 and g = 0 a step is a pure periodic shift of each population."""
+@pytest.mark.parametrize("form", ["f", "h"])
+def test_no_relaxation_step_is_exact_streaming(lat, form):
+    """With S = 0 and g = 0 a step is a pure periodic shift of each stored
+    population (f in the literal form, h = f - w in the deviation form)."""
     Q = 9 if lat == "D2Q9" else 19
     shape = (7, 5, 1) if lat == "D2Q9" else (7, 5, 4)
-    o = Oracle(lat, "MRT", shape, 0.8, rates=np.zeros(Q))
+    o = Oracle(lat, "MRT", shape, 0.8, rates=np.zeros(Q), form=form)
     e, w, _ = o.lattice_tables()
     rng = np.random.default_rng(15)
     h0 = w[:, None] * 0.1 * rng.uniform(-1, 1, size=(Q, o.N))
-    o.set_h(h0)
+    x0 = w[:, None] + h0 if form == "f" else h0
+    (o.set_f if form == "f" else o.set_h)(x0)
     o.step(3)
     nx, ny, nz = shape
-    ref = h0.reshape(Q, nz, ny, nx).copy()
+    ref = x0.reshape(Q, nz, ny, nx).copy()
     for i in range(Q):
         ref[i] = np.roll(ref[i], shift=(3 * e[i][2], 3 * e[i][1], 3 * e[i][0]), axis=(0, 1, 2))
-    assert np.array_equal(o.get_h(), ref.reshape(Q, -1))
+    got = o.get_f() if form == "f" else o.get_h()
+    assert np.array_equal(got, ref.reshape(Q, -1))
 
 
-def test_no_relaxation_with_halfway_walls_is_a_permutation():
-    """S = 0, g = 0, u_w = 0 and halfway walls: streaming plus exact reversal."""
+@pytest.mark.parametrize("form", ["f", "h"])
+def test_no_relaxation_with_halfway_walls_is_a_permutation(form):
+    """S = 0, g = 0, u_w = 0 and halfway walls: streaming plus exact reversal
+    of the stored populations, in either form."""
     Q = 9
     nx, ny = 5, 8
-    o = Oracle("D2Q9", "MRT", (nx, ny, 1), 0.8, rates=np.zeros(Q))
+    o = Oracle("D2Q9", "MRT", (nx, ny, 1), 0.8, rates=np.zeros(Q), form=form)
     o.set_solids([{"kind": "plane", "centre": (0, 0.5, 0), "axis": (0, 1, 0)},
                   {"kind": "plane", "centre": (0, ny - 1.5, 0), "axis": (0, -1, 0)}], "QUADRATIC")
     e, w, opp = o.lattice_tables()
     rng = np.random.default_rng(16)
     f0 = w[:, None] * 0.1 * rng.uniform(-1, 1, size=(Q, o.N))  # deviations h = f - w
-    o.set_h(f0)
+    if form == "f":
+        f0 = w[:, None] + f0
+    (o.set_f if form == "f" else o.set_h)(f0)
     o.step(1)
     fluid = lambda y: 1 <= y <= ny - 2
     ref = np.zeros_like(f0)
@@ -200,6 +208,6 @@ def test_no_relaxation_with_halfway_walls_is_a_permutation():
                     ref[i, n] = f0[i, sx + nx * sy]
                 else:
                     ref[i, n] = f0[opp[i], n]
-    got = o.get_h()
+    got = o.get_f() if form == "f" else o.get_h()
     mask = np.array([fluid(n // nx) for n in range(o.N)])
     assert np.array_equal(got[:, mask], ref[:, mask])
