@@ -1,25 +1,27 @@
 #!/usr/bin/env python
 """Benchmark of the lattice Boltzmann hot path on one MI355X.
 
-Workload (the value line): D3Q19 MRT, FP32 deviation storage, 128^3 periodic
-box, one fixed sphere of radius 16.2 at a seed-drawn sub-grid offset, body
-force for Re = 20, quadratic interpolated bounce-back with momentum-exchange
-force and torque every step.  A step is the whole per-step path: the fused
-stream-collide sweep, the bounce-back/force kernel and the per-solid force
-reduction.  MLUPS counts every lattice cell.
+Workload of the value line (the precision configuration, the largest single
+lattice): D3Q19 MRT, FP32 deviation storage, 256^3 periodic box, 64 fixed
+spheres of radius 8 at seed-drawn positions (random sequential addition,
+gaps >= 2), body force for Re = 10, quadratic interpolated bounce-back with
+the momentum-exchange force and torque of every sphere at every step.  A step
+is the whole per-step path: the fused stream-collide sweep that also applies
+the bounce-back of the links and the per-sphere force reduction.  MLUPS counts
+every lattice cell.  The same workload in FP64 and FP16 deviation storage is
+summarised in the line as well.
 
-Also reported (same JSON line): the FP64 and FP16 forms of that workload,
-the direct-forcing IBM form (5 forcing iterations per step), the 256^3 box
-with 64 spheres (working set far beyond the 256 MB Infinity Cache), the
-other bounce-back schemes (Yu's, Zhao & Yong's single-node one) on both
-boxes, the IBM with the 3- and 2-point delta functions, a free sphere
-settling under gravity (its link set rebuilt every step), the achievable HBM
-copy bandwidth, 512 lattices with translating spheres stepped as one batch,
-the request trace served for a bounded window at the trace's own rate
-(saturated) and at a rate below capacity, and the FP64 CPU oracle timed on a
-bounded sample of the value workload.
+The last stdout line is one compact JSON object (the contract).  Every other
+measurement goes to stderr (one "# key: ..." line each) and, in full, to the
+JSON file --extras-out: the 128^3 one-sphere workload (FP32 / FP64 / FP16,
+quadratic IBB and the direct-forcing IBM), the other bounce-back schemes, the
+IBM with the 3- and 2-point deltas, a general-rate MRT run, free spheres
+settling under gravity, the HBM copy yardstick, 512 lattices with translating
+spheres as one batch, the FP32/FP16 drag error against FP64 storage, the
+request trace served at saturation and below it, and the FP64 CPU oracle on a
+bounded sample of the value workload (one thread and all cores).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras all|none|k1,k2]
 """
 from __future__ import annotations
 
@@ -38,9 +40,16 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM roofline (D3Q19 FP32 vs FP64); served solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"F64": 8, "F32": 4, "F16": 2}
-# the timed run records HIP events around every PROFILE_EVERY-th sweep launch
-# (events on every launch add host and dispatch work to each step)
+# the sweep tuner of a new lattice takes 8 + 4 x 12 steps; warm-up always runs past it
+TUNER_STEPS = 64
+# extra runs record HIP events around every PROFILE_EVERY-th sweep launch where the
+# sweeps of a call are not back to back (events on every launch add work to each step)
 PROFILE_EVERY = 8
+ALL_EXTRAS = ("single", "schemes", "copy", "batch", "precision", "serving", "cpu")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def sweep_source_hash():
@@ -49,10 +58,9 @@ def sweep_source_hash():
 
 
 def traffic_for(key, cells):
-    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (calibrated on a copy kernel), if they were taken on the
-    current sweep source; otherwise None.  The roofline's "traffic" is these
-    bytes over the same average launch duration as "achieved"."""
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs (scaled by the same counters on a copy kernel), if they were taken on the
+    current sweep source; otherwise None."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
@@ -65,53 +73,58 @@ def traffic_for(key, cells):
     return ent["bytes_per_launch"]
 
 
-def run_case(case, steps, warmup, key, torch, lbm):
+def run_case(case, steps, warmup, key, torch, lbm, rates=None):
+    """Warm up past the sweep tuner, then time exactly `steps` steps in one lbm_step
+    call: HIP events on the lattice's stream around the call (whole-step time), the
+    host clock around it (synchronised on both sides), and the library's events
+    around the sweep launches (sweep-kernel time)."""
     Q = 19 if case.lattice == "D3Q19" else 9
-    gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g,
+    gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g, rates=rates,
                       g_fluid_only=case.g_fluid_only, max_solids=max(1, len(case.solids)))
     gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction, delta=case.delta)
     N = gpu.N
-    gpu.step(warmup)
+    w = max(warmup, TUNER_STEPS)
+    gpu.step(w)
+    while gpu.autotune_info()["policy"] is None:  # a tuner that needs longer
+        gpu.step(TUNER_STEPS)
+        w += TUNER_STEPS
     torch.cuda.synchronize()
     gpu.profile(True, every=PROFILE_EVERY)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record(gpu.stream)
     gpu.step(steps)
+    e1.record(gpu.stream)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
+    step_s = e0.elapsed_time(e1) / 1e3 / steps
     sweep_ms, launches = gpu.profile_read()
     gpu.profile(False)
     if not gpu.check():
         raise RuntimeError(f"{key}: populations diverged")
     F = gpu.force_torque()
     tune = gpu.autotune_info()
-    wall = t1 - t0
-    # readouts after the timed run: fluid cells, and the Reynolds number at its end
-    # (superficial velocity = mean fluid velocity times the fluid fraction, over the
-    # sphere diameter and the viscosity) against the one its body force was set for
     _, u, types = gpu.macros()
     fluid = types != 1
     nfluid = int(fluid.sum())
     re_at_end = None
     if case.meta.get("Re") is not None and case.solids:
+        # superficial velocity (mean fluid velocity x fluid fraction) over the diameter and viscosity
         nu = (case.tau - 0.5) / 3.0
         gdir = int(np.argmax(np.abs(case.g)))
-        u_sup = float(u[gdir][fluid].sum()) / N
-        re_at_end = u_sup * 2.0 * case.solids[0]["radius"] / nu
+        re_at_end = float(u[gdir][fluid].sum()) / N * 2.0 * case.solids[0]["radius"] / nu
     per_cell = 2 * Q * STORE_BYTES[case.storage] + 1  # pull Q, push Q, one flag byte
-    timing = f"HIP events around the sweep launches of the timed run (one span per call, or every {PROFILE_EVERY}th)"
-    if launches > 0:
-        avg_s = sweep_ms / 1e3 / launches
-    else:  # a run shorter than the tuner times no sweep: the step average stands in
-        avg_s = wall / steps
-        timing = "no sweep timed (run shorter than the sweep tuner): whole-step average"
-    achieved = N * per_cell / avg_s / 1e9
+    achieved = N * per_cell / step_s / 1e9
+    sweep_s = sweep_ms / 1e3 / launches if launches > 0 else None
     traffic_bytes = traffic_for(key, N)
-    traffic = None if traffic_bytes is None else traffic_bytes / avg_s / 1e9
     out = {
         "mlups": N * steps / wall / 1e6,
         "mflups_fluid": nfluid * steps / wall / 1e6,
         "ms_per_step": wall / steps * 1e3,
+        "event_ms_per_step": step_s * 1e3,
+        "steps": steps,
+        "warmup": w,
         "cells": N,
         "fluid_cells": nfluid,
         "re_target": case.meta.get("Re"),
@@ -119,14 +132,16 @@ def run_case(case, steps, warmup, key, torch, lbm):
         "solids": len(case.solids),
         "method": case.method,
         "storage": case.storage,
-        "sweep_avg_us": avg_s * 1e6,
-        "sweep_launches_timed": launches,
-        "sweep_timing": timing,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": N * per_cell, "traffic_bytes_per_launch": traffic_bytes},
-        "drag_x": float(F[0, 0]),
-        "autotune": tune,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic_bytes is None or sweep_s is None else traffic_bytes / sweep_s / 1e9,
+                     "basis": f"{per_cell} B/cell x {N} cells per step over the whole-step time (HIP events "
+                              f"around the {steps} timed steps)"},
+        "sweep_kernel": None if sweep_s is None else {
+            "avg_us": sweep_s * 1e6, "launches_timed": launches,
+            "achieved_GBps": N * per_cell / sweep_s / 1e9, "frac": N * per_cell / sweep_s / 1e9 / HBM_PEAK_GBS},
+        "drag_x_solid0": float(F[0, 0]) if len(F) else None,
+        "autotune_policy": tune.get("policy"),
     }
     if case.meta.get("U_set") is not None:  # free solid: its vertical velocity at the end vs the Stokes target
         out["settling_velocity_at_end"] = float(gpu.solid_state()[0, 2 + 3])
@@ -178,24 +193,16 @@ def run_batch(torch, lbm, W, steps, warmup, count=512):
     b.sync()
     wall = time.perf_counter() - t0
     tune = b.tune_info()
-    tune["candidates"] = b.tune_table()
     sweep_us = b.time_sweep(10)
-    ok = all(m.check() for m in members[:: max(1, count // 16)])
-    if not ok:
+    if not all(m.check() for m in members[:: max(1, count // 16)]):
         raise RuntimeError("batch: populations diverged")
     per_cell = 2 * 19 * STORE_BYTES["F32"] + 1
-    achieved = N * per_cell / (sweep_us * 1e-6) / 1e9
     out = {
-        "lattices": count,
-        "cells": N,
-        "steps": steps,
-        "mlups": N * steps / wall / 1e6,
-        "ms_per_step": wall / steps * 1e3,
-        "setup_s": setup_s,
-        "pool_GB": pool / 1e9,
+        "lattices": count, "cells": N, "steps": steps, "mlups": N * steps / wall / 1e6,
+        "ms_per_step": wall / steps * 1e3, "setup_s": setup_s, "pool_GB": pool / 1e9,
+        "step_frac": N * per_cell / (wall / steps) / 1e9 / HBM_PEAK_GBS,
         "sweep_us_per_step": sweep_us,
-        "roofline_sweep": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_step": N * per_cell},
+        "sweep_frac": N * per_cell / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
         "tune": tune,
         "note": "whole step: sweep, bounce-back + force, reclassification, refill and link rebuild of every lattice",
     }
@@ -205,26 +212,34 @@ def run_batch(torch, lbm, W, steps, warmup, count=512):
     return out
 
 
-def run_serving(torch, lbm, W, seconds, rate, count, pool_gb, max_slots):
-    """The request trace served for a bounded wall time (see paper_1906_05445_amd/serving.py)."""
+def run_serving(torch, lbm, W, rate, seconds, min_completed, count=256, pool_gb=32.0, max_slots=16,
+                step_cap=200000):
+    """The request trace served until min_completed requests have finished or `seconds`
+    have passed (see paper_1906_05445_amd/serving.py)."""
     from paper_1906_05445_amd import serving as S
 
     trace = W.request_trace(count=count, rate=50.0, seed=5)
     for e in trace:  # same requests, arrival times rescaled to the requested rate
         e["arrival"] *= 50.0 / rate
     reqs = S.requests_from_trace(trace)
-    srv = S.Server(pool_bytes=int(pool_gb * 1e9), max_slots=max_slots, check_every=100, tol=1e-6, step_cap=200000)
-    st = srv.run(reqs, wall_limit=seconds)
+    srv = S.Server(pool_bytes=int(pool_gb * 1e9), max_slots=max_slots, check_every=100, tol=1e-6,
+                   step_cap=step_cap)
+    st = srv.run(reqs, wall_limit=seconds, stop_after=min_completed, log=lambda m: log(f"#   {m}"))
     srv.close()
     torch.cuda.empty_cache()
-    st.update({"rate_req_per_s": rate, "window_s": seconds, "pool_GB": pool_gb, "max_slots": max_slots,
-               "criterion": "|F(t)-F(t-100)|/|F(t)| < 1e-6, cap 2e5 steps"})
+    done = [r for r in reqs if r.finished is not None]
+    st.update({"rate_req_per_s": rate, "window_limit_s": seconds, "stop_after": min_completed, "pool_GB": pool_gb,
+               "max_slots": max_slots, "criterion": f"|F(t)-F(t-100)|/|F(t)| < 1e-6, cap {step_cap} steps",
+               "start": "uniform flow at the periodic-array estimate of the mean velocity",
+               "per_request": [{"edge": r.case.shape[0], "Re": round(r.case.meta["Re"], 2), "method": r.case.method,
+                                "steps": r.steps, "converged": r.converged, "latency_s": round(r.latency, 3)}
+                               for r in done]})
     return st
 
 
 def run_precision(torch, lbm, W, steps):
-    """Per-sphere drag of the 256^3 64-sphere workload stored in FP32 and FP16, against FP64 storage on the same
-    GPU (the FP64 path matches the FP64 oracle to 1e-12)."""
+    """Per-sphere drag of the 256^3 64-sphere workload stored in FP32 and FP16, against FP64
+    storage on the same GPU (the FP64 path matches the FP64 oracle to 1e-12)."""
     drag = {}
     for storage in ("F64", "F32", "F16"):
         case = W.sphere_pack(storage=storage)
@@ -264,8 +279,7 @@ def run_batch_vs_plain(torch, lbm, W, steps, count=8):
         ref.step(steps)
         f64 = ref.history()[:, 0, :3]
         f32 = m.history()[:, 0, :3]
-        scale = np.abs(f64).max()
-        errs.append(float(np.abs(f32 - f64).max() / scale))
+        errs.append(float(np.abs(f32 - f64).max() / np.abs(f64).max()))
         ref.close()
     b.close()
     torch.cuda.empty_cache()
@@ -275,40 +289,63 @@ def run_batch_vs_plain(torch, lbm, W, steps, count=8):
                        "|F_batch,FP32 - F_alone,FP64| / max |F_alone,FP64|"}
 
 
-def cpu_baseline(case, steps):
-    """The FP64 oracle (single-threaded C) on a bounded sample of the value workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, steps1, stepsN, threads):
+    """The FP64 oracle (plain C, literal form, OpenMP over its per-cell loops) on a
+    bounded sample of the value workload: steps1 steps on one thread, then stepsN
+    steps on `threads` threads, from the same state."""
     from oracle import Oracle
 
-    o = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g)
-    o.set_solids(case.solids, case.method)
     t0 = time.perf_counter()
-    o.step(steps)
-    wall = time.perf_counter() - t0
+    o = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g, threads=threads)
+    o.set_solids(case.solids, case.method)
+    setup = time.perf_counter() - t0
     N = case.shape[0] * case.shape[1] * case.shape[2]
-    return {"value": N * steps / wall / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the 128^3 one-sphere workload (quadratic IBB), FP64, one host thread",
-            "seconds": wall}
+    o.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(steps1)
+    w1 = time.perf_counter() - t0
+    o.set_threads(threads)
+    t0 = time.perf_counter()
+    o.step(stepsN)
+    wN = time.perf_counter() - t0
+    del o
+    return {"value": N * stepsN / wN / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{stepsN} steps of the value workload (256^3, 64 spheres, quadratic IBB, FP64) on "
+                      f"{threads} threads; {steps1} steps on one thread",
+            "value_1thread": N * steps1 / w1 / 1e6, "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "seconds": w1 + wN, "setup_s": setup}
+
+
+def compact(d, keys):
+    return {k: (round(d[k], 4) if isinstance(d.get(k), float) else d.get(k)) for k in keys}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=10)
-    ap.add_argument("--primary-only", action="store_true", help="measure only the value workload")
-    ap.add_argument("--cases", default="all",
-                    help="comma list of extras: single (the other single-lattice cases), schemes (Yu and "
-                         "Zhao-Yong bounce-back; or one of its keys), copy, batch, precision, serving")
-    ap.add_argument("--batch-steps", type=int, default=2000, help="steps of the 512-lattice batch (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=60.0, help="wall time of each serving window (0: skip)")
-    ap.add_argument("--precision-steps", type=int, default=10000,
-                    help="steps of the FP32/FP16 vs FP64 drag comparison (0: skip)")
-    ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="also run the copy kernel once over this many MiB (counter calibration)")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--extras", default="all", help="all, none, or a comma list of " + ",".join(ALL_EXTRAS))
+    ap.add_argument("--extras-out", default=os.path.join("gpurun_out", "bench_extras.json"))
+    ap.add_argument("--batch-steps", type=int, default=500, help="steps of the 512-lattice batch")
+    ap.add_argument("--precision-steps", type=int, default=10000, help="steps of the FP32/FP16 vs FP64 comparison")
+    ap.add_argument("--serve-seconds", type=float, default=180.0, help="limit of the saturated serving window")
+    ap.add_argument("--serve-min", type=int, default=32, help="completions that end the saturated window")
+    ap.add_argument("--cpu-steps", default="1,3", help="oracle sample: steps on one thread, steps on all threads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU (a lattice is not split across GPUs here); --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU: a lattice is not split across GPUs here, so "
+                                   "--gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -318,108 +355,128 @@ def main():
 
     torch.cuda.set_device(0)
     K, Wm = args.steps, args.warmup
-    primary_case = W.sphere_box(storage="F32", method="QUADRATIC")
-    primary = run_case(primary_case, K, Wm, "sphere128_f32_quadratic", torch, lbm)
-    print(f"# sphere128 F32 IBB: {primary['mlups']:.0f} MLUPS, sweep {primary['sweep_avg_us']:.1f} us, "
-          f"{primary['roofline']['achieved']:.0f} GB/s, policy {primary['autotune'].get('policy')}",
-          file=sys.stderr, flush=True)
+    want = set(ALL_EXTRAS) if args.extras == "all" else (set() if args.extras == "none" else
+                                                          set(args.extras.split(",")))
     extras = {}
-    want = set()
-    if not args.primary_only:
-        want = ({"single", "schemes", "copy", "batch", "precision", "serving"} if args.cases == "all"
-                else set(args.cases.split(",")))
+
+    def extra(key, value, summary):
+        extras[key] = value
+        log(f"# {key}: {summary}")
+
+    # ---- the value workload, FP32, and its FP64 / FP16 forms
+    prim = run_case(W.sphere_pack(storage="F32"), K, Wm, "pack256_f32_quadratic", torch, lbm)
+    log(f"# pack256 F32: {prim['mlups']:.0f} MLUPS, step {prim['event_ms_per_step'] * 1e3:.1f} us, "
+        f"{prim['roofline']['achieved']:.0f} GB/s ({prim['roofline']['frac']:.3f}), policy {prim['autotune_policy']}")
+    forms = {}
+    for st in ("F64", "F16"):
+        r = run_case(W.sphere_pack(storage=st), K, Wm, f"pack256_{st.lower()}_quadratic", torch, lbm)
+        forms[st] = r
+        log(f"# pack256 {st}: {r['mlups']:.0f} MLUPS, {r['roofline']['achieved']:.0f} GB/s "
+            f"({r['roofline']['frac']:.3f})")
+
+    # ---- everything else: stderr + the extras file
+    k2 = max(K, 100)
     if "single" in want:
-        k2 = max(K // 2, 100)
-        for key, case in [("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
+        for key, case in [("sphere128_f32_quadratic", W.sphere_box(storage="F32", method="QUADRATIC")),
+                          ("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
                           ("sphere128_f16_quadratic", W.sphere_box(storage="F16", method="QUADRATIC")),
                           ("sphere128_f32_ibm", W.sphere_box(storage="F32", method="IBM")),
-                          ("pack256_f32_quadratic", W.sphere_pack(storage="F32")),
-                          ("pack256_f64_quadratic", W.sphere_pack(storage="F64")),
-                          ("pack256_f16_quadratic", W.sphere_pack(storage="F16"))]:
-            k = k2 if "256" not in key else max(K // 8, 50)
-            extras[key] = run_case(case, k, max(Wm // 4, 64), key, torch, lbm)
-            extras[key]["steps"] = k
-            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s, "
-                  f"policy {extras[key]['autotune'].get('policy')}",
-                  file=sys.stderr, flush=True)
-    # the other two bounce-back schemes the paper compares: Yu's (five populations per link)
-    # and Zhao & Yong's single-node scheme; the 256^3 pack has gaps of 2 lattice units
-    # where the multi-node schemes fall back; the IBM with the 3- and 2-point deltas of
-    # the same comparison, each at the retraction the paper finds best for it
-    for key, (ctor, kw) in [("sphere128_f32_yu", (W.sphere_box, {"method": "YU"})),
-                            ("sphere128_f32_zhao_yong", (W.sphere_box, {"method": "ZHAO_YONG"})),
-                            ("pack256_f32_yu", (W.sphere_pack, {"method": "YU"})),
-                            ("pack256_f32_zhao_yong", (W.sphere_pack, {"method": "ZHAO_YONG"})),
-                            ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
-                                                                          "retraction": 0.3})),
-                            ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
-                                                                          "retraction": 0.2})),
-                            ("settle128_f32_free", (W.settling_sphere, {})),
-                            ("settle128_f32_free_ibm", (W.settling_sphere, {"method": "IBM"}))]:
-        if "schemes" in want or key in want:
-            case = ctor(storage="F32", **kw)
-            k = max(K // 2, 100) if "256" not in key else max(K // 8, 50)
-            extras[key] = run_case(case, k, max(Wm // 4, 64), key, torch, lbm)
-            extras[key]["steps"] = k
-            print(f"# {key}: {extras[key]['mlups']:.0f} MLUPS, {extras[key]['roofline']['achieved']:.0f} GB/s",
-                  file=sys.stderr, flush=True)
+                          ("sphere128_f64_ibm", W.sphere_box(storage="F64", method="IBM"))]:
+            r = run_case(case, k2, Wm, key, torch, lbm)
+            extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+        # general relaxation rates (every MRT row its own rate): the sparse-M relaxation
+        rates = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, 1.0 / 0.8, 1.4, 1.0 / 0.8, 1.4, 1.0 / 0.8,
+                 1.0 / 0.8, 1.0 / 0.8, 1.98, 1.98, 1.98]
+        r = run_case(W.sphere_box(storage="F32", method="QUADRATIC"), k2, Wm, "sphere128_f32_mrt_rates", torch, lbm,
+                     rates=rates)
+        extra("sphere128_f32_mrt_general_rates", r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+    if "schemes" in want:
+        for key, (ctor, kw) in [("sphere128_f32_yu", (W.sphere_box, {"method": "YU"})),
+                                ("sphere128_f32_zhao_yong", (W.sphere_box, {"method": "ZHAO_YONG"})),
+                                ("pack256_f32_yu", (W.sphere_pack, {"method": "YU"})),
+                                ("pack256_f32_zhao_yong", (W.sphere_pack, {"method": "ZHAO_YONG"})),
+                                ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
+                                                                              "retraction": 0.3})),
+                                ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
+                                                                              "retraction": 0.2})),
+                                ("settle128_f32_free", (W.settling_sphere, {})),
+                                ("settle128_f32_free_ibm", (W.settling_sphere, {"method": "IBM"}))]:
+            r = run_case(ctor(storage="F32", **kw), k2, Wm, key, torch, lbm)
+            extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
     if "copy" in want:
-        extras["hbm_copy_GBps"] = copy_probe(torch, lbm)
-    if args.batch_steps > 0 and "batch" in want:
-        extras["batch512_moving_f32"] = run_batch(torch, lbm, W, args.batch_steps, 40)  # tuning: 36 steps
-        bb = extras["batch512_moving_f32"]
-        print(f"# batch512: {bb['mlups']:.0f} MLUPS, sweep {bb['roofline_sweep']['achieved']:.0f} GB/s",
-              file=sys.stderr, flush=True)
-    if args.precision_steps > 0 and "precision" in want:
-        extras["precision_pack256_vs_f64"] = run_precision(torch, lbm, W, args.precision_steps)
-        extras["batch_f32_vs_plain_f64"] = run_batch_vs_plain(torch, lbm, W, args.precision_steps)
-        pr = extras["precision_pack256_vs_f64"]
-        print(f"# precision: FP32 max drag err {pr['F32']['max_rel_drag_err']:.2e}, FP16 "
-              f"{pr['F16']['max_rel_drag_err']:.2e}; batch FP32 vs FP64 "
-              f"{extras['batch_f32_vs_plain_f64']['max_rel_force_err']:.2e}", file=sys.stderr, flush=True)
-    if args.serve_seconds > 0 and "serving" in want:
-        extras["serving_saturated"] = run_serving(torch, lbm, W, args.serve_seconds, 50.0, 256, 32.0, 16)
-        extras["serving_subsaturated"] = run_serving(torch, lbm, W, args.serve_seconds, 0.1, 256, 32.0, 16)
-        for k in ("serving_saturated", "serving_subsaturated"):
-            sv = extras[k]
-            print(f"# {k}: {sv['completed']} solves in {sv['wall_s']:.1f} s, p50 {sv['latency_p50_s']} s, "
-                  f"p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
-    if args.copy_calibration > 0:
-        copy_probe(torch, lbm, nbytes=args.copy_calibration << 20, reps=1)
-    cpu = cpu_baseline(W.sphere_box(storage="F64", method="QUADRATIC"), args.cpu_steps) if args.cpu_steps > 0 else None
+        c = copy_probe(torch, lbm)
+        extra("hbm_copy_GBps", c, f"{c:.0f} GB/s")
+    if "batch" in want and args.batch_steps > 0:
+        bb = run_batch(torch, lbm, W, args.batch_steps, 40)  # tuning: 36 steps
+        extra("batch512_moving_f32", bb, f"{bb['mlups']:.0f} MLUPS, step frac {bb['step_frac']:.3f}, "
+                                         f"sweep frac {bb['sweep_frac']:.3f}")
+    if "precision" in want and args.precision_steps > 0:
+        pr = run_precision(torch, lbm, W, args.precision_steps)
+        extra("precision_pack256_vs_f64", pr, f"FP32 max drag err {pr['F32']['max_rel_drag_err']:.2e}, "
+                                              f"FP16 {pr['F16']['max_rel_drag_err']:.2e}")
+        bp = run_batch_vs_plain(torch, lbm, W, args.precision_steps)
+        extra("batch_f32_vs_plain_f64", bp, f"max rel force err {bp['max_rel_force_err']:.2e}")
+    serving = None
+    if "serving" in want and args.serve_seconds > 0:
+        sat = run_serving(torch, lbm, W, 50.0, args.serve_seconds, args.serve_min)
+        extra("serving_saturated", sat, f"{sat['completed']} done ({sat['converged']} converged) in "
+                                        f"{sat['wall_s']:.1f} s, p50 {sat['latency_p50_s']} s, p99 {sat['latency_p99_s']} s")
+        # below capacity: arrivals at half the measured saturated completion rate
+        rate = max(0.5 * sat["solves_per_s"], 0.02)
+        sub = run_serving(torch, lbm, W, rate, 60.0, None)
+        extra("serving_subsaturated", sub, f"{sub['completed']} done at {rate:.3f} req/s, p50 "
+                                           f"{sub['latency_p50_s']} s, p99 {sub['latency_p99_s']} s")
+        serving = {"n": sat["latency_n"], "converged": sat["converged"], "capped": sat["capped"],
+                   "p50_s": sat["latency_p50_s"], "p99_s": sat["latency_p99_s"],
+                   "solves_per_s": round(sat["solves_per_s"], 4), "offered_req_per_s": 50.0,
+                   "sub_rate_req_per_s": round(rate, 4), "sub_n": sub["latency_n"], "sub_p50_s": sub["latency_p50_s"],
+                   "sub_p99_s": sub["latency_p99_s"]}
+    cpu = None
+    if "cpu" in want:
+        s1, sN = (int(x) for x in args.cpu_steps.split(","))
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(W.sphere_pack(storage="F64"), s1, sN, threads)
+        extras["cpu_baseline"] = cpu
+        log(f"# cpu_baseline: {cpu['value']:.2f} MLUPS on {threads} threads, {cpu['value_1thread']:.2f} on one")
+    if args.extras_out:
+        d = os.path.dirname(args.extras_out)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.extras_out, "w") as fh:
+            json.dump({"primary": prim, "f64": forms["F64"], "f16": forms["F16"], "extras": extras}, fh, indent=1)
+
+    rf = prim["roofline"]
     line = {
         "metric": METRIC,
-        "value": primary["mlups"],
+        "value": prim["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": K,
-        "warmup": Wm,
-        "ms_per_step": primary["ms_per_step"],
+        "warmup": prim["warmup"],
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sphere128: D3Q19 MRT, 128^3 periodic, one sphere R=16.2 (seed 2), Re=20 "
-                               "body force, quadratic IBB + momentum-exchange force, FP32 deviation storage",
-                   "cells": primary["cells"], "parallelism": "single GPU"},
-        "roofline": primary["roofline"],
-        "mflups_fluid": primary["mflups_fluid"],
-        "sweep_vs_copy": (None if "hbm_copy_GBps" not in extras else
-                          {"copy_GBps": extras["hbm_copy_GBps"],
-                           "frac": primary["roofline"]["achieved"] / extras["hbm_copy_GBps"],
-                           "note": "sweep algorithmic GB/s over the copy kernel's measured GB/s"}),
-        "cpu_baseline": cpu,
-        "flow": {"re_target": primary["re_target"], "re_at_end": primary["re_at_end"],
-                 "note": "the body force is a Stokes estimate for re_target; from rest, the mean flow of "
-                         "the periodic box relaxes over about L^2/(3 nu) (5e4 steps at 128^3, tau 0.8), "
-                         "so a run of a few thousand steps ends in its start-up transient"},
-        "sweep_avg_us": primary["sweep_avg_us"],
-        "sweep_timing": primary["sweep_timing"],
-        "autotune": primary["autotune"],
-        "extras": extras,
+        "config": {"workload": "pack256: D3Q19 MRT 256^3 periodic, 64 fixed spheres R=8 (seed 3, gaps>=2), Re=10 "
+                               "body force, quadratic IBB + Eq.17 force/torque, FP32 deviation storage",
+                   "cells": prim["cells"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(rf["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(rf["frac"], 4), "traffic": None if rf["traffic"] is None else round(rf["traffic"], 1),
+                     "basis": "153 B/cell/step over HIP-event whole-step time",
+                     "sweep_kernel_frac": None if prim["sweep_kernel"] is None else
+                     round(prim["sweep_kernel"]["frac"], 4)},
+        "f64": {"mlups": round(forms["F64"]["mlups"], 1), "frac": round(forms["F64"]["roofline"]["frac"], 4)},
+        "f16": {"mlups": round(forms["F16"]["mlups"], 1), "frac": round(forms["F16"]["roofline"]["frac"], 4)},
+        "serving": serving,
+        "cpu_baseline": None if cpu is None else {
+            "value": round(cpu["value"], 3), "unit": "MLUPS", "cores": cpu["cores"], "kind": "oracle",
+            "sample": cpu["sample"], "value_1thread": round(cpu["value_1thread"], 3), "cpu": cpu["cpu"],
+            "nproc": cpu["nproc"]},
+        "extras_file": args.extras_out or None,
     }
-    print(json.dumps(line))
+    print(json.dumps(line, separators=(",", ":")))
 
 
 if __name__ == "__main__":

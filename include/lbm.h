@@ -168,34 +168,49 @@ typedef struct {
 } lbm_ibm_opts;
 
 /* Bytes of device workspace for one context.  max_links bounds the number of
- * IBB boundary links, max_lagrangian the number of IBM points; 0 selects a
- * bound computed from the lattice size. */
+ * IBB boundary links (Sec. 2.2: one per fluid node and direction whose
+ * neighbour across the wall is a solid node), max_lagrangian the number of
+ * IBM points (Sec. 2.1, Eq. 5-9); 0 selects a bound computed from the
+ * lattice size.  Returns 0 for invalid parameters. */
 size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_links,
                            int64_t max_lagrangian);
 
-/* Create a context inside dev_workspace (device memory, >= ws_bytes, caller
- * owned, 256-byte aligned) for work on hip_stream (a hipStream_t, may be
- * NULL for the default stream).  The populations start at rest (f = w).
- * Errors: LBM_EINVAL, LBM_ENOMEM (ws_bytes too small), LBM_EDEVICE. */
+/* Create a context for the lattice Boltzmann equation of Sec. 2 (BGK, Eq. 1
+ * with the viscosity of Eq. 2, or MRT, Eq. 3, with the forcing of Sec. 2.1)
+ * inside dev_workspace (device memory, >= ws_bytes, caller owned, 256-byte
+ * aligned, kept until lbm_destroy) for work on hip_stream (a hipStream_t,
+ * caller owned; NULL for the default stream).  The populations start at
+ * rest (f = w).  Errors: LBM_EINVAL (tau <= 1/2, dimensions, rates),
+ * LBM_ENOMEM (ws_bytes too small), LBM_EDEVICE. */
 lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
                       void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 /* Set the solids and the no-slip method (replaces any previous set).
- * IBB: classifies nodes (inside iff squared distance <= R^2, shortest
- * periodic image), builds the boundary links, computes q.  IBM: generates
+ * IBB (Sec. 2.2, Fig. 1): classifies nodes (inside iff squared distance
+ * <= R^2, shortest periodic image), builds the boundary links and the wall
+ * fraction q = |x_f - x_w| / |x_f - x_b| of each.  IBM (Sec. 2.1): generates
  * the Lagrangian mesh of each solid (geodesic sphere of about one point per
- * unit area; circles / rings of spacing about 1), unless points are given
- * afterwards with lbm_set_lagrangian.  opts may be NULL (5 iterations, no
- * retraction).  Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EUNSUPPORTED. */
+ * unit area; circles / rings of spacing about 1; Sec. 3.1 places the points
+ * R_d inside the surface), unless points are given afterwards with
+ * lbm_set_lagrangian.  opts may be NULL (5 iterations, no retraction).
+ * Errors: LBM_EINVAL and LBM_EUNSUPPORTED leave the context as it was;
+ * after LBM_ENOMEM (too many links or points) the context has no solids. */
 lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts);
 
-/* IBM only: replace the Lagrangian points of one solid with X [n][3]
- * (FP64, lattice units), each with control volume dV.  The points of a moving
- * solid are given where the solid was placed by lbm_set_solids, before any
- * step (else LBM_EINVAL). */
+/* IBM only: replace the Lagrangian points X_l of one solid (Eq. 5, 8) with
+ * X [n][3] (FP64, lattice units), each with control volume dV (Delta V_l of
+ * Eq. 8).  The points of a moving solid are given where the solid was placed
+ * by lbm_set_solids, before any step (else LBM_EINVAL). */
 lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_t n, double dV);
 
-/* Advance nsteps time steps (no host synchronisation inside). */
+/* Advance nsteps time steps t -> t+1 (no host synchronisation inside): IBM
+ * forcing (Eq. 5-9, n_iter times, Sec. 3.1), then streaming and collision
+ * (Eq. 1 or Eq. 3 with the body force of Sec. 2.1), then for IBB the unknown
+ * populations of every boundary link (Eq. 10, 11, 12-14 or 16) and the
+ * force and torque of Eq. 17.  Moving IBB solids are reclassified, their
+ * uncovered nodes refilled and their links rebuilt (Sec. 3.2).  Errors:
+ * LBM_ENOMEM (a moving solid outgrew a capacity), LBM_EDIVERGED (a free
+ * solid reached half a cell per step), LBM_EDEVICE. */
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
 
 /* Centre, velocity and angular velocity of every solid now, state [n][9]
@@ -203,18 +218,25 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
  * motion).  Synchronizes the stream. */
 lbm_status lbm_solid_state(lbm_ctx *c, double *state);
 
-/* Force and torque on every solid in the most recent step, [n][3] each. */
+/* Force and torque on every solid in the most recent step, [n][3] each:
+ * IBB by the Galilean-invariant momentum exchange of Eq. 17 (lever arm from
+ * the solid centre to the wall point x_w = x_f - q e_i of each link); IBM
+ * -sum F_l dV_l and -sum (X_l - Y) x F_l dV_l (Sec. 3.1, App. B).  FP64.
+ * Synchronizes the stream. */
 lbm_status lbm_force_torque(lbm_ctx *c, double *force, double *torque);
 
-/* Per-step force and torque, ft [count][nsolid][6] = (Fx Fy Fz Tx Ty Tz),
- * for steps first .. first+count-1 (step k is the update k -> k+1).  The
- * library keeps the last lbm_history_capacity() steps; older ones give
- * LBM_EINVAL. */
+/* Per-step force and torque (as lbm_force_torque: Eq. 17, or the IBM sums of
+ * Sec. 3.1), ft [count][nsolid][6] = (Fx Fy Fz Tx Ty Tz), for steps first ..
+ * first+count-1 (step k is the update k -> k+1).  The library keeps the last
+ * lbm_history_capacity() steps; older ones give LBM_EINVAL.  Synchronizes
+ * the stream. */
 lbm_status lbm_force_history(lbm_ctx *c, int64_t first, int64_t count, double *ft);
 int64_t lbm_history_capacity(void);
 
-/* Macroscopic fields of the most recent collision: rho [N], u [3][N] with
- * u = (j + F/2)/rho; IBB solid nodes report rho = 0 and the wall velocity.
+/* Macroscopic fields of the most recent collision: rho [N] = sum_i f_i and
+ * u [3][N] = (j + F/2)/rho with j = sum_i f_i e_i and F the total force
+ * density of that collision (the second-order forcing of Sec. 2.1 uses this
+ * velocity); IBB solid nodes report rho = 0 and the wall velocity of Eq. 10.
  * node_type [N] (may be NULL), in the geometry of that collision: 0 fluid,
  * 1 IBB solid node, 2 fluid inside an IBM solid.  Before the first step (or
  * after lbm_set_f / lbm_set_state): the fields of the current populations,
@@ -232,18 +254,30 @@ lbm_status lbm_macros(lbm_ctx *c, double *rho, double *u, uint8_t *node_type);
  * after lbm_create / lbm_set_f / lbm_set_state.  Synchronizes the stream. */
 lbm_status lbm_strain(lbm_ctx *c, double *S, double *eps);
 
-/* Populations f_i(x, t) before the next collision, [Q][N] FP64 (solid nodes
- * give 0); lbm_set_f replaces them (time and history are kept). */
+/* Populations f_i(x, t) of Eq. 1 / Eq. 3 before the next collision, [Q][N]
+ * FP64 (solid nodes give 0); lbm_set_f replaces them (time and history are
+ * kept).  Both synchronize the stream. */
 lbm_status lbm_get_f(lbm_ctx *c, double *f);
 lbm_status lbm_set_f(lbm_ctx *c, const double *f);
+
+/* Set every population to the equilibrium f_eq(rho, u) of a uniform flow
+ * (the second-order polynomial equilibrium of Eq. 1 and Eq. 3, c_s^2 = 1/3),
+ * u [3] (u[2] ignored for D2Q9); the same start as from rest, with a mean
+ * flow.  Time and history are kept.  Errors: LBM_EINVAL (rho <= 0,
+ * non-finite values).  Synchronizes the stream. */
+lbm_status lbm_set_equilibrium(lbm_ctx *c, double rho, const double *u);
 
 /* Raw deviations f_i - w_i before the next collision, [Q][N] in the storage
  * format (double, float or IEEE half), bit for bit. */
 lbm_status lbm_get_state(lbm_ctx *c, void *host);
 lbm_status lbm_set_state(lbm_ctx *c, const void *host);
 
-/* Boundary links in canonical order (by cell, then direction): cell, dir,
- * solid, q.  Pass NULL arrays to get the count only. */
+/* Boundary links of Sec. 2.2 in canonical order (by fluid cell x_f, then
+ * direction i, the population f_i(x_f) that bounce-back supplies): cell,
+ * dir, solid, q = |x_f - x_w| / |x_f - x_b| in (0, 1] (FP64, Fig. 1).  Pass
+ * NULL arrays to get the count only; otherwise *count holds the capacity of
+ * the arrays on entry (LBM_EINVAL if smaller than the link count) and the
+ * count on return.  Synchronizes the stream. */
 lbm_status lbm_link_list(lbm_ctx *c, int64_t *count, uint32_t *cell, uint8_t *dir, int32_t *solid, double *q);
 
 /* Node classification [N]: 0 fluid, 1 IBB solid node, 2 inside an IBM solid. */
@@ -255,7 +289,11 @@ int64_t lbm_time(const lbm_ctx *c);
 /* Scan the current populations for NaN/Inf: LBM_OK or LBM_EDIVERGED. */
 lbm_status lbm_check(lbm_ctx *c);
 
+/* Release the host side of a context (not a step of the method); the
+ * workspace stays the caller's.  Members of a batch are released with
+ * lbm_batch_release instead (LBM_ESTATE here). */
 lbm_status lbm_destroy(lbm_ctx *c);
+/* Name of a status code, and the detail text of a context's last error. */
 const char *lbm_status_string(lbm_status st);
 const char *lbm_last_error(const lbm_ctx *c);
 
@@ -302,8 +340,8 @@ lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_st
  * until lbm_batch_destroy).  The first lbm_batch_table_bytes(max_slots)
  * bytes hold the batch's tables; members are contexts whose workspaces are
  * carved from the rest.  All members share one lattice and one storage
- * format, and all batch work runs on a stream the batch creates
- * (lbm_batch_stream).  Each step is one launch per stage over the units of
+ * format, and all batch work runs on one stream (lbm_batch_stream): the
+ * caller's, or one the batch creates when the caller passes none.  Each step is one launch per stage over the units of
  * all members, replayed from a captured HIP graph; the first steps of a new
  * total size tune the sweep's launch shape and store policy.
  * A batch and its members must not be used by two host threads at once.
@@ -313,12 +351,19 @@ lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_st
 size_t lbm_batch_table_bytes(int32_t max_slots);
 
 /* Create a batch of up to max_slots members in dev_pool.  lattice is an
- * lbm_lattice and storage an lbm_storage shared by every member.
- * Errors: LBM_EINVAL, LBM_ENOMEM (pool smaller than the tables), LBM_EDEVICE. */
+ * lbm_lattice and storage an lbm_storage shared by every member (each member
+ * a lattice of Sec. 2 with its own solids, stepped as lbm_step defines).
+ * hip_stream (a hipStream_t, caller owned, kept until lbm_batch_destroy) is
+ * the stream of every batch and member call; it must not be the legacy null
+ * stream, because the batched steps are captured as HIP graphs on it.  NULL:
+ * the batch creates a non-blocking stream of its own (default priority) and
+ * destroys it with the batch.  Errors: LBM_EINVAL, LBM_ENOMEM (pool smaller
+ * than the tables), LBM_EDEVICE. */
 lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots, void *dev_pool, size_t pool_bytes,
-                            lbm_batch **out);
+                            void *hip_stream, lbm_batch **out);
 
-/* Admit a member: a context as from lbm_create (same parameters) whose
+/* Admit a member (a lattice of Sec. 2, as lbm_create defines it): a context
+ * with the same parameters as lbm_create whose
  * workspace of lbm_workspace_bytes(p, ...) bytes is taken from the pool.
  * It is configured and read with the ordinary context calls (lbm_set_solids,
  * lbm_force_torque, lbm_macros, ...) and may even be stepped alone with
@@ -327,10 +372,15 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
 lbm_status lbm_batch_admit(lbm_batch *b, const lbm_params *p, int32_t max_solids, int64_t max_links,
                            int64_t max_lagrangian, lbm_ctx **out);
 
-/* Release a member: its context is destroyed and its pool range returned. */
+/* Release a member: its context is destroyed and its pool range returned
+ * (its results, the Eq. 17 or Sec. 3.1 force history and the fields, are
+ * read before, with the context calls). */
 lbm_status lbm_batch_release(lbm_batch *b, lbm_ctx *c);
 
-/* Advance every member by nsteps steps.  Returns after enqueueing, except
+/* Advance every member by nsteps steps, each step exactly the one lbm_step
+ * takes (Sec. 2: forcing, Eq. 5-9; stream and collide, Eq. 1 / Eq. 3;
+ * bounce-back, Eq. 10-16, and Eq. 17; Sec. 3.2 rebuild of moving solids),
+ * one launch per stage over all members.  Returns after enqueueing, except
  * when a member has translating solids: then the stream is synchronised and
  * the members' link capacities are checked (LBM_ENOMEM when exceeded, with
  * the member's lbm_last_error naming the capacity). */
@@ -371,6 +421,14 @@ lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us);
  * Both arrays hold max_slots entries.  One launch and one small read-back;
  * synchronises the batch's stream. */
 lbm_status lbm_batch_force_change(lbm_batch *b, int64_t lag, lbm_ctx **members, double *change);
+
+/* Members whose drag has converged (serving): after lbm_batch_force_change
+ * with the same lag, the members whose change is >= 0 and < tol, in slot
+ * order; up to cap of them go to converged, *n gets how many there are.
+ * The change is the relative change of the Eq. 17 (IBB) or Sec. 3.1 (IBM)
+ * force over lag steps.  Synchronises the batch's stream.  Errors:
+ * LBM_EINVAL (tol <= 0, lag <= 0 or beyond the history). */
+lbm_status lbm_batch_poll(lbm_batch *b, int64_t lag, double tol, lbm_ctx **converged, int32_t cap, int32_t *n);
 
 /* The batch's HIP stream (a hipStream_t). */
 void *lbm_batch_stream(lbm_batch *b);

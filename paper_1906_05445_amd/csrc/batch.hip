@@ -79,6 +79,7 @@ std::mutex g_batch_tune_mutex;
 struct lbm_batch {
   int lattice = 0, storage = 0, Q = 19;
   hipStream_t stream = nullptr;
+  bool own_stream = false;  // created by lbm_batch_create (the caller passed none)
   char *pool = nullptr;
   size_t pool_bytes = 0, table_bytes = 0;
   int32_t max_slots = 0;
@@ -424,7 +425,7 @@ size_t lbm_batch_table_bytes(int32_t max_slots) {
 }
 
 lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots, void *dev_pool, size_t pool_bytes,
-                            lbm_batch **out) {
+                            void *hip_stream, lbm_batch **out) {
   if (!out) return LBM_EINVAL;
   *out = nullptr;
   if ((lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || storage < LBM_F64 || storage > LBM_F16_DEV) return LBM_EINVAL;
@@ -445,10 +446,16 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
     b->cus = cus;
-  // a stream of its own (default priority): graphs cannot be captured on the null stream
-  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
-    delete b;
-    return LBM_EDEVICE;
+  // the caller's stream, else one of the batch's own (default priority); the
+  // steps are captured as graphs, which the null stream cannot hold
+  if (hip_stream) {
+    b->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return LBM_EDEVICE;
+    }
+    b->own_stream = true;
   }
   char *p = b->pool;
   const size_t S = (size_t)max_slots;
@@ -469,7 +476,7 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
   b->d_bucket = reinterpret_cast<uint16_t *>(p);
   b->free_[tb] = (pool_bytes - tb) & ~size_t(255);
   if (rebuild(b) != LBM_OK) {
-    (void)hipStreamDestroy(b->stream);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return LBM_EDEVICE;
   }
@@ -714,6 +721,22 @@ lbm_status lbm_batch_force_change(lbm_batch *b, int64_t lag, lbm_ctx **members, 
   return LBM_OK;
 }
 
+lbm_status lbm_batch_poll(lbm_batch *b, int64_t lag, double tol, lbm_ctx **converged, int32_t cap, int32_t *n) {
+  if (!b || !n || !(tol > 0.0) || cap < 0 || (cap > 0 && !converged)) return LBM_EINVAL;
+  std::vector<lbm_ctx *> members((size_t)b->max_slots);
+  std::vector<double> change((size_t)b->max_slots);
+  const lbm_status st = lbm_batch_force_change(b, lag, members.data(), change.data());
+  if (st != LBM_OK) return st;
+  int32_t k = 0;
+  for (int s = 0; s < b->max_slots; s++)
+    if (members[(size_t)s] && change[(size_t)s] >= 0.0 && change[(size_t)s] < tol) {
+      if (k < cap) converged[k] = members[(size_t)s];
+      k++;
+    }
+  *n = k;
+  return LBM_OK;
+}
+
 void *lbm_batch_stream(lbm_batch *b) { return b ? (void *)b->stream : nullptr; }
 
 const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : "null batch"; }
@@ -729,7 +752,7 @@ lbm_status lbm_batch_destroy(lbm_batch *b) {
     }
   destroy_graphs(b);
   drop_samples(b);
-  (void)hipStreamDestroy(b->stream);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return LBM_OK;
 }

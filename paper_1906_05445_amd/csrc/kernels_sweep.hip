@@ -964,6 +964,32 @@ void launch_fill_zero(lbm_ctx *c, void *A) {
   hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, c->stream, static_cast<uint4 *>(A), bytes / 16);
 }
 
+// Every slot of direction i (every cell, solid nodes and tile padding
+// included) set to the stored deviation v[i]: a uniform state, whose pull
+// gives the same populations at every cell.
+template <typename S>
+__global__ void k_fill_uniform(S *__restrict__ A, uint64_t count, uint32_t Q, DirVals v) {
+  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = (uint32_t)((k / kTile) % Q);
+    A[k] = (S)v.v[i];
+  }
+}
+
+void launch_fill_uniform(lbm_ctx *c, void *A, const double *h) {
+  const uint64_t count = (uint64_t)c->Q * c->L.stride;
+  DirVals v;
+  for (int i = 0; i < kMaxQ; i++) v.v[i] = i < c->Q ? h[i] : 0.0;
+  if (c->store_bytes == 8)
+    hipLaunchKernelGGL(k_fill_uniform<double>, dim3(2048), dim3(256), 0, c->stream, static_cast<double *>(A), count,
+                       (uint32_t)c->Q, v);
+  else if (c->store_bytes == 4)
+    hipLaunchKernelGGL(k_fill_uniform<float>, dim3(2048), dim3(256), 0, c->stream, static_cast<float *>(A), count,
+                       (uint32_t)c->Q, v);
+  else
+    hipLaunchKernelGGL(k_fill_uniform<_Float16>, dim3(2048), dim3(256), 0, c->stream, static_cast<_Float16 *>(A),
+                       count, (uint32_t)c->Q, v);
+}
+
 template <typename S>
 __global__ void k_finite(const S *__restrict__ A, uint64_t count, uint32_t *flag) {
   using C = typename Store<S>::C;

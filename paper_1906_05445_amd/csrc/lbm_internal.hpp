@@ -215,6 +215,11 @@ void launch_ibm_ft_free(lbm_ctx *c, int64_t t);
 void launch_strain(lbm_ctx *c, const void *src, double *out, int part);
 void launch_macros(lbm_ctx *c, const void *src, double *out, int mode);
 void launch_fill_zero(lbm_ctx *c, void *A);
+struct DirVals {
+  double v[kMaxQ];
+};
+// every slot of direction i of A set to h[i] (a uniform state)
+void launch_fill_uniform(lbm_ctx *c, void *A, const double *h);
 int launch_check_finite(lbm_ctx *c, const void *A, uint32_t *flag);
 void launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 

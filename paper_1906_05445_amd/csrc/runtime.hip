@@ -23,6 +23,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+
 int csize_of(int storage) { return storage == LBM_F64 ? 8 : 4; }
 int ssize_of(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32_DEV ? 4 : 2); }
 
@@ -282,19 +283,22 @@ size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_
   return L.total;
 }
 
-lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
-                      void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
-  if (!out) return LBM_EINVAL;
-  *out = nullptr;
-  Layout L;
-  if (!make_layout(p, max_solids, max_links, max_lagrangian, &L)) return LBM_EINVAL;
+// Parameters checked and the workspace layout of a context.
+static lbm_status check_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                               Layout *L) {
+  if (!p || !make_layout(p, max_solids, max_links, max_lagrangian, L)) return LBM_EINVAL;
   if (p->collision == LBM_MRT && p->rates)
     for (int k = 0; k < qof(p->lattice); k++)
       if (!std::isfinite(p->rates[k]) || p->rates[k] < 0.0 || p->rates[k] >= 2.0) return LBM_EINVAL;
-  if (!dev_workspace || ws_bytes < L.total) return LBM_ENOMEM;
-  if (((uintptr_t)dev_workspace & 255) != 0) return LBM_EINVAL;
-  lbm_ctx *c = new (std::nothrow) lbm_ctx();
-  if (!c) return LBM_ENOMEM;
+  return LBM_OK;
+}
+
+// A new context in the host storage `c` over the device workspace ws: the
+// rest state, cleared flags and no owner (every byte of the workspace that is
+// read before it is written is set here, so a reused workspace carries
+// nothing over).
+static lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const Layout &L, void *dev_workspace, size_t ws_bytes,
+                           void *hip_stream) {
   c->p = *p;
   c->p.rates = nullptr;
   c->Q = qof(p->lattice);
@@ -342,13 +346,29 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner0, 0xFF, (size_t)c->N * 2, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner1, 0xFF, (size_t)c->N * 2, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) {
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  Layout L;
+  const lbm_status st = check_create(p, max_solids, max_links, max_lagrangian, &L);
+  if (st != LBM_OK) return st;
+  if (!dev_workspace || ws_bytes < L.total) return LBM_ENOMEM;
+  if (((uintptr_t)dev_workspace & 255) != 0) return LBM_EINVAL;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  if (init_ctx(c, p, L, dev_workspace, ws_bytes, hip_stream) != LBM_OK) {
     delete c;
     return LBM_EDEVICE;
   }
   *out = c;
   return LBM_OK;
 }
+
+
 
 lbm_status lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_EINVAL;
@@ -395,6 +415,7 @@ lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches) {
 }
 
 static lbm_status build_ibm(lbm_ctx *c);
+static lbm_status clear_solids(lbm_ctx *c, lbm_status st);
 
 static bool coord_axis(const double a[3], int *ax, int *sg) {
   int k = -1, cnt = 0;
@@ -541,6 +562,14 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       if (c->D == 3 && s[k].kind == LBM_CYLINDER && ds[k].ax != 2)
         return set_err(c, "IBM cylinders lie along z"), LBM_EUNSUPPORTED;
     }
+  // the IBM options are checked before anything is written: a rejected call
+  // leaves the context exactly as it was
+  const int n_iter = opts ? opts->n_iter : 5;
+  const int delta = (opts && opts->delta) ? opts->delta : 4;
+  const double retraction = opts ? opts->retraction : 0.0;
+  if (n_iter < 0 || !std::isfinite(retraction) || delta < 2 || delta > 4) return set_err(c, "IBM options"), LBM_EINVAL;
+  if (moving && method == LBM_IBM && n_iter == 0)
+    return set_err(c, "a moving IBM solid needs forcing iterations"), LBM_EINVAL;
   c->solids.assign(s, s + n);
   c->dsolids = ds;
   c->nsolid = n;
@@ -553,12 +582,9 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->max_box_chunks = mbc;
   // the link masks of the count pass live in the staging region (4 N doubles) while links are built
   c->mask_cells = mask_total * 4 <= (uint64_t)4 * c->N * 8 ? mask_total : 0;
-  c->n_iter = opts ? opts->n_iter : 5;
-  c->delta = (opts && opts->delta) ? opts->delta : 4;
-  c->retraction = opts ? opts->retraction : 0.0;
-  if (c->n_iter < 0 || !std::isfinite(c->retraction) || c->delta < 2 || c->delta > 4)
-    return set_err(c, "IBM options"), LBM_EINVAL;
-  if (c->ibm_moving && c->n_iter == 0) return set_err(c, "a moving IBM solid needs forcing iterations"), LBM_EINVAL;
+  c->n_iter = n_iter;
+  c->delta = delta;
+  c->retraction = retraction;
   c->nlinks = 0;
   c->k5_chunks = 0;
   c->link_lists = false;
@@ -588,7 +614,10 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
                            c->stream));
     HIPCALL(hipMemcpyAsync(misc, c->ws + c->L.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream));
     HIPCALL(hipStreamSynchronize(c->stream));
-    if (misc[1]) return set_err(c, "more boundary links than max_links"), LBM_ENOMEM;
+    if (misc[1]) {
+      set_err(c, "more boundary links than max_links");
+      return clear_solids(c, LBM_ENOMEM);
+    }
     c->nlinks = misc[0];
     int32_t mx = 0;
     for (auto &q : sl) mx = std::max<int32_t>(mx, (int32_t)q.nchunks);
@@ -599,6 +628,25 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   }
   const lbm_status st = build_ibm(c);
   HIPCALL(hipStreamSynchronize(c->stream));
+  return st == LBM_OK ? st : clear_solids(c, st);
+}
+
+// After a failure past the point where lbm_set_solids starts writing the
+// context: no solid is left, so lbm_step is a plain periodic sweep (the node
+// flags were cleared before the geometry was built and are cleared again).
+static lbm_status clear_solids(lbm_ctx *c, lbm_status st) {
+  c->solids.clear();
+  c->nsolid = 0;
+  c->nlinks = 0;
+  c->k5_chunks = 0;
+  c->link_lists = false;
+  c->nlag = 0;
+  c->nshell = 0;
+  c->any_moving = c->any_free = c->ibm_moving = c->ibm_free = false;
+  c->lag_user = false;
+  if (hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return LBM_EDEVICE;
   return st;
 }
 
@@ -1103,6 +1151,42 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *f) {
     HIPCALL(hipMemcpyAsync(stg, f + (size_t)i * c->N, (size_t)c->N * 8, hipMemcpyHostToDevice, c->stream));
     launch_encode_shift(c, i, stg, c->state(), false);
   }
+  HIPCALL(hipStreamSynchronize(c->stream));
+  c->fresh = true;
+  c->version++;
+  return LBM_OK;
+}
+
+// Direction i of the velocity set (ABI order) and its weight.
+static void lattice_dir(int Q, int i, int e[3], double *w) {
+  if (Q == 9) {
+    e[0] = Lat<9>::ex(i), e[1] = Lat<9>::ey(i), e[2] = 0;
+    *w = wgt<9>(i);
+  } else {
+    e[0] = Lat<19>::ex(i), e[1] = Lat<19>::ey(i), e[2] = Lat<19>::ez(i);
+    *w = wgt<19>(i);
+  }
+}
+
+lbm_status lbm_set_equilibrium(lbm_ctx *c, double rho, const double *u) {
+  if (!c || !u || !(rho > 0.0) || !std::isfinite(rho)) return LBM_EINVAL;
+  double uu = 0.0;
+  for (int a = 0; a < c->D; a++) {
+    if (!std::isfinite(u[a])) return LBM_EINVAL;
+    uu += u[a] * u[a];
+  }
+  // f_eq_i - w_i = w_i [(rho - 1) + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)], rest state rho = 1, u = 0
+  double h[kMaxQ];
+  for (int i = 0; i < c->Q; i++) {
+    int e[3];
+    double w;
+    lattice_dir(c->Q, i, e, &w);
+    double eu = 0.0;
+    for (int a = 0; a < c->D; a++) eu += e[a] * u[a];
+    h[i] = w * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+  }
+  launch_fill_uniform(c, c->state(), h);
+  HIPCALL(hipGetLastError());
   HIPCALL(hipStreamSynchronize(c->stream));
   c->fresh = true;
   c->version++;

@@ -83,6 +83,7 @@ _sig("lbm_strain", _st, [_vp, _d, _d])
 _sig("lbm_solid_state", _st, [_vp, _d])
 _sig("lbm_get_f", _st, [_vp, _d])
 _sig("lbm_set_f", _st, [_vp, _d])
+_sig("lbm_set_equilibrium", _st, [_vp, ctypes.c_double, _d])
 _sig("lbm_get_state", _st, [_vp, _vp])
 _sig("lbm_set_state", _st, [_vp, _vp])
 _sig("lbm_link_list", _st, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_uint32),
@@ -100,7 +101,7 @@ _sig("lbm_autotune_info", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d, _d])
 _sig("lbm_autotune_policy", _st, [_vp, ctypes.POINTER(ctypes.c_int32), _d])
 
 _sig("lbm_batch_table_bytes", ctypes.c_size_t, [ctypes.c_int32])
-_sig("lbm_batch_create", _st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t,
+_sig("lbm_batch_create", _st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
                                ctypes.POINTER(_vp)])
 _sig("lbm_batch_admit", _st, [_vp, ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64, ctypes.POINTER(_vp)])
 _sig("lbm_batch_release", _st, [_vp, _vp])
@@ -115,17 +116,19 @@ _sig("lbm_batch_tune_table", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTE
                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32), _d])
 _sig("lbm_batch_force_change", _st, [_vp, _i64, ctypes.POINTER(_vp), _d])
+_sig("lbm_batch_poll", _st, [_vp, _i64, ctypes.c_double, ctypes.POINTER(_vp), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32)])
 _sig("lbm_batch_stream", _vp, [_vp])
 _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_batch_destroy", _st, [_vp])
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_strain", "lbm_solid_state", "lbm_get_f",
-            "lbm_set_f", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
+            "lbm_set_f", "lbm_set_equilibrium", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
             "lbm_profile", "lbm_profile_read", "lbm_autotune_info", "lbm_autotune_policy", "lbm_batch_table_bytes", "lbm_batch_create",
             "lbm_batch_admit", "lbm_batch_release", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_info",
-            "lbm_batch_tune_info", "lbm_batch_tune_table", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_stream", "lbm_batch_last_error",
+            "lbm_batch_tune_info", "lbm_batch_tune_table", "lbm_batch_time_sweep", "lbm_batch_force_change", "lbm_batch_poll", "lbm_batch_stream", "lbm_batch_last_error",
             "lbm_batch_destroy"]
 globals().update({n: getattr(_lib, n) for n in EXPORTED})
 
@@ -261,6 +264,11 @@ class _Context:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.N)
         self._check(_lib.lbm_set_f(self.handle, _ptr(f)))
 
+    def set_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
+        """Uniform flow f = f_eq(rho, u) everywhere (lbm_set_equilibrium)."""
+        uu = np.ascontiguousarray((list(u) + [0.0, 0.0, 0.0])[:3], dtype=np.float64)
+        self._check(_lib.lbm_set_equilibrium(self.handle, float(rho), _ptr(uu)))
+
     def get_state(self):
         out = np.empty((self.Q, self.N), dtype=STORAGE_DTYPES[self.storage])
         self._check(_lib.lbm_get_state(self.handle, out.ctypes.data_as(_vp)))
@@ -369,15 +377,19 @@ class Batch:
     """Many lattices of one lattice type and storage advanced together
     (lbm_batch_*); the pool is a torch tensor owned by this object."""
 
-    def __init__(self, lattice="D3Q19", storage="F32", max_slots=64, pool_bytes=1 << 30, device="cuda"):
+    def __init__(self, lattice="D3Q19", storage="F32", max_slots=64, pool_bytes=1 << 30, device="cuda",
+                 stream=None):
         import torch
         self._torch = torch
         self.lattice = lattice
         self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=device)
         aligned = (self.pool.data_ptr() + 255) // 256 * 256
+        # the caller's stream (a torch stream of default priority unless one is given):
+        # batched steps are captured as graphs on it, so it is never the null stream
+        self.stream = torch.cuda.Stream() if stream is None else stream
         h = _vp()
         st = _lib.lbm_batch_create(LATTICES[lattice], STORAGES[storage], int(max_slots), _vp(aligned),
-                                   int(pool_bytes), ctypes.byref(h))
+                                   int(pool_bytes), _vp(self.stream.cuda_stream), ctypes.byref(h))
         if st != LBM_OK:
             raise LBMError(st, "lbm_batch_create")
         self.handle = h
@@ -452,6 +464,14 @@ class Batch:
             if h and h in by_handle:
                 out[by_handle[h]] = float(self._change_buf[k])
         return out
+
+    def poll(self, lag=100, tol=1e-6):
+        """Members whose relative force change over `lag` steps is below tol (lbm_batch_poll)."""
+        buf = (_vp * self.max_slots)()
+        n = ctypes.c_int32(0)
+        self._check(_lib.lbm_batch_poll(self.handle, int(lag), float(tol), buf, self.max_slots, ctypes.byref(n)))
+        by_handle = {m.handle.value: m for m in self.members}
+        return [by_handle[buf[k]] for k in range(min(n.value, self.max_slots)) if buf[k] in by_handle]
 
     def tune_table(self):
         """Every sweep candidate of the tuner with its measured time (us; -1 before tuning)."""

@@ -61,6 +61,15 @@ def footprint(lbm, case, max_links=0, max_lagrangian=0) -> int:
                                max_lagrangian=max_lagrangian)
 
 
+def initial_velocity(case):
+    """Uniform start velocity of a solve (meta["U_init"] along its body force), or None (from rest)."""
+    U0 = case.meta.get("U_init")
+    gn = np.asarray(case.g, dtype=np.float64)
+    if not U0 or not np.any(gn):
+        return None
+    return tuple(U0 * gn / np.linalg.norm(gn))
+
+
 def percentile(values, q):
     """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence; None if empty."""
     v = sorted(values)
@@ -102,7 +111,7 @@ class Server:
     """A batch of resident lattices serving a request trace."""
 
     def __init__(self, pool_bytes: int, max_slots: int = 128, storage: str = "F32", check_every: int = 100,
-                 tol: float = 1e-6, step_cap: int = 200000, clock=time.perf_counter):
+                 tol: float = 1e-6, step_cap: int = 200000, clock=time.perf_counter, warm_start: bool = True):
         from . import lbm
 
         self.lbm = lbm
@@ -113,6 +122,9 @@ class Server:
         self.tol = float(tol)
         self.step_cap = int(step_cap)
         self.clock = clock
+        # start each solve from the uniform flow its case estimates (meta["U_init"], along the
+        # body force) instead of from rest: the same steady state, a shorter transient
+        self.warm_start = bool(warm_start)
         self.active = {}  # Member -> Request
         self.cell_steps = 0
 
@@ -126,6 +138,9 @@ class Server:
         if m is None:
             return None
         m.set_solids(c.solids, c.method, n_iter=req.n_iter)
+        u0 = initial_velocity(c) if self.warm_start else None
+        if u0 is not None:
+            m.set_equilibrium(1.0, u0)
         return m
 
     def _finish(self, m, req, now):
@@ -135,9 +150,11 @@ class Server:
         self.batch.release(m)
         del self.active[m]
 
-    def run(self, requests: Iterable[Request], wall_limit: Optional[float] = None, log=None):
-        """Serve the requests (sorted by arrival) until all are done or wall_limit
-        seconds have passed; returns the summary dict of ``stats``."""
+    def run(self, requests: Iterable[Request], wall_limit: Optional[float] = None, log=None,
+            stop_after: Optional[int] = None):
+        """Serve the requests (sorted by arrival) until all are done, wall_limit
+        seconds have passed or stop_after requests have completed; returns the
+        summary dict of ``stats``."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             r.footprint = footprint(self.lbm, r.case)
@@ -145,14 +162,21 @@ class Server:
         adm = Admission(self._try_admit)
         t0 = self.clock()
         now = 0.0
+        next_note = 20.0
         while True:
             now = self.clock() - t0
+            if log and now >= next_note:  # a status line from the loop every 20 s
+                log(f"serving: {now:.0f} s, {sum(1 for r in reqs if r.finished is not None)} done, "
+                    f"{len(self.active)} running, {len(adm.queue)} queued")
+                next_note += 20.0
             while pending and pending[0].arrival <= now:
                 adm.push(pending.popleft())
             for req, m in adm.admit_all(now):
                 self.active[m] = req
             adm.queue = deque(r for r in adm.queue if not r.rejected)
             if wall_limit is not None and now >= wall_limit:
+                break
+            if stop_after is not None and sum(1 for r in reqs if r.finished is not None) >= stop_after:
                 break
             if not self.active:
                 if not pending and not adm.queue:
@@ -212,6 +236,7 @@ def stats(reqs, wall, cell_steps=0, in_flight=(), queued=0):
         "queued_at_end": queued,
         "wall_s": wall,
         "solves_per_s": len(done) / wall if wall > 0 else 0.0,
+        "latency_n": len(lat),
         "latency_p50_s": percentile(lat, 50),
         "latency_p99_s": percentile(lat, 99),
         "queue_p50_s": percentile([r.queue_time for r in done], 50),

@@ -50,3 +50,31 @@ def test_workspace_sizing_and_validation_without_gpu():
     bad2, _ = lbm.make_params("D2Q9", "BGK", "F64", (16, 16, 2), 0.8)
     assert lbm.lbm_workspace_bytes(ctypes.byref(bad2), 1, 0, 0) == 0
     assert lbm.lbm_status_string(-4) == b"non-finite populations"
+
+
+# the calls of the boundary that carry a step or a result of the method: each
+# declaration's comment names the passage of the paper that defines it
+CITED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
+         "lbm_force_torque", "lbm_force_history", "lbm_macros", "lbm_strain", "lbm_link_list",
+         "lbm_get_f", "lbm_set_equilibrium", "lbm_batch_create", "lbm_batch_admit", "lbm_batch_step",
+         "lbm_batch_poll", "lbm_batch_release"]
+
+
+def _comment_before(src, name):
+    """The comment block that documents `name`: the last /* ... */ before its
+    declaration, with only declarations (no other comment) in between."""
+    m = re.search(r"\b" + name + r"\s*\(", src)
+    assert m, name
+    head = src[: m.start()]
+    end = head.rfind("*/")
+    start = head.rfind("/*", 0, end)
+    assert end > 0 and start >= 0, name
+    between = head[end + 2:]
+    assert "/*" not in between, name
+    return head[start:end]
+
+
+def test_declarations_cite_the_paper():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    missing = [n for n in CITED if not re.search(r"(Eq\.|Sec\.|Fig\.|App\.)\s*\d", _comment_before(src, n))]
+    assert not missing, missing

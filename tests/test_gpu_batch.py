@@ -165,7 +165,7 @@ def test_batch_member_matches_oracle_fp64(lbm, method):
     other.set_solids([W.solid("sphere", (14.0, 13.0, 12.0), 4.5)], "QUADRATIC")
     m = b.admit("MRT", "F64", shape, 0.8, max_solids=1)
     m.set_solids(solids, method)
-    orc = Oracle("D3Q19", "MRT", shape, 0.8)
+    orc = Oracle("D3Q19", "MRT", shape, 0.8, form="h")
     orc.set_solids(solids, method)
     for n in (13, 20, 27):
         b.step(n)

@@ -28,6 +28,7 @@ def lbm():
 def _oracle(*a, **k):
     from oracle import Oracle
 
+    k.setdefault("form", "h")
     return Oracle(*a, **k)
 
 

@@ -9,6 +9,8 @@
   1.7e8 cells): sampled members (the smallest, the largest and the median lattice) are bit for bit
   their lone runs after the batch's tuning steps.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -38,7 +40,8 @@ def test_pack256_fp64_against_oracle(lbm, method):
     gpu = lbm.Lattice(case.lattice, case.collision, "F64", case.shape, case.tau, g=case.g,
                       max_solids=len(case.solids))
     gpu.set_solids(case.solids, case.method)
-    orc = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g)
+    orc = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g, form="h",
+                 threads=min(16, os.cpu_count() or 1))
     orc.set_solids(case.solids, case.method)
     Lg, Lo = gpu.links(), orc.links()
     assert len(Lg["cell"]) == len(Lo["cell"]) > 250000

@@ -6,9 +6,10 @@ The solids cross several cell faces during each run, so the shell of stencil cel
 (and the force of the old cells cleared) more than once.  Density ratios are chosen where the
 explicit Eq. 23 update is stable at these small radii: with R = 4 and rho_p = 1.5 the rotation of
 a sphere oscillates with growing amplitude (the diffuse IBM shell adds inertia beyond the solid's
-volume that the inner-fluid term does not hold), while R = 7, or rho_p = 3 at R = 4, is stable.  Bars: FP64 storage, populations
-max|df| <= 1e-13 and velocities max|du| / max|u| <= 1e-11 over all cells, force and torque
-relative to their scale <= 1e-11 (torque scale: the larger of max|T| and the force scale
+volume that the inner-fluid term does not hold), while R = 7, or rho_p = 3 at R = 4, is stable.  The oracle
+runs in its deviation form (pinned against the literal one in tests/test_oracle_forms.py).  Bars: FP64
+storage, populations max|df| <= 1e-13 and velocities max|du| / max|u| <= 1e-12 over all cells (measured
+about 1e-15), force and torque relative to their scale <= 1e-12 (torque scale: the larger of max|T| and the force scale
 times the box edge, as a solid that does not spin has a torque of rounding size), solid centre, velocity and angular velocity <= 1e-12 (absolute;
 centres of order 10, velocities of order 1e-2); FP32 storage, the bounds stated in the test.
 """
@@ -38,7 +39,7 @@ def _run_pair(lbm, lat, shape, solid, steps, storage="F64", g=(0.0, 0.0, 0.0), f
     from oracle import Oracle
 
     gpu = lbm.Lattice(lat, "MRT", storage, shape, tau, g=g, g_fluid_only=fluid_only)
-    orc = Oracle(lat, "MRT", shape, tau, g=g, g_fluid_only=fluid_only)
+    orc = Oracle(lat, "MRT", shape, tau, g=g, g_fluid_only=fluid_only, form="h")
     gpu.set_solids([solid], "IBM", n_iter=n_iter, delta=delta)
     orc.set_solids([solid], "IBM")
     orc.set_ibm_iters(n_iter)
@@ -56,7 +57,7 @@ def _run_pair(lbm, lat, shape, solid, steps, storage="F64", g=(0.0, 0.0, 0.0), f
     return gpu, orc
 
 
-def _compare(gpu, orc, tol_f=1e-13, tol_u=1e-11, tol_F=1e-11, tol_s=1e-12):
+def _compare(gpu, orc, tol_f=1e-13, tol_u=1e-12, tol_F=1e-12, tol_s=1e-12):
     df = np.max(np.abs(gpu.get_f() - orc.get_f()))
     _, ug, _ = gpu.macros()
     _, uo, _ = orc.macros()
@@ -161,7 +162,7 @@ def test_free_ibm_without_points(lbm):
     s = W.solid("sphere", (12.3, 11.8, 12.6), 4.0, velocity=(0.01, 0.0, -0.004), omega=(0.0, 2e-4, 1e-4),
                 density=1.6, gravity=(1e-5, -2e-5, 4e-6))
     gpu = lbm.Lattice("D3Q19", "MRT", "F64", (24, 24, 24), 0.8)
-    orc = Oracle("D3Q19", "MRT", (24, 24, 24), 0.8)
+    orc = Oracle("D3Q19", "MRT", (24, 24, 24), 0.8, form="h")
     gpu.set_solids([s], "IBM")
     gpu.set_lagrangian(0, np.zeros((0, 3)), 1.0)
     orc.set_solids([s], "IBM")

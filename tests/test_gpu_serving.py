@@ -2,7 +2,7 @@
 
 Bar: every served result (force/torque at the step the request finished) is
 bit for bit the result of the same solve run alone with lbm_step for the same
-number of steps, although requests joined and left the batch at different
+number of steps from the same uniform start (lbm_set_equilibrium), although requests joined and left the batch at different
 times; converged requests meet the drag-change criterion.
 """
 import numpy as np
@@ -44,6 +44,9 @@ def test_served_results_match_lone_runs(lbm):
         c = r.case
         lone = lbm.Lattice(c.lattice, c.collision, c.storage, c.shape, c.tau, g=c.g, max_solids=1)
         lone.set_solids(c.solids, c.method, n_iter=3)
+        u0 = S.initial_velocity(c)  # the server's warm start
+        if u0 is not None:
+            lone.set_equilibrium(1.0, u0)
         lone.step(r.steps)
         ft = lone.force_torque()
         lone.close()
