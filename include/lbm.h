@@ -185,6 +185,24 @@ size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_
 lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
                       void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid it): lbm_create without a
+ * workspace argument.  The workspace is a file-scope device array of
+ * lbm_noalloc_capacity() bytes (64 MiB) that the library holds on every
+ * device it runs on until the process ends; the call allocates nothing,
+ * device or host.  Everything else is lbm_create's: the same parameters, the
+ * same layout (lbm_workspace_bytes must not exceed the capacity: about
+ * 240 bytes per cell with the default capacities, e.g. 64^3 in FP32), the
+ * same calls on the context afterwards, lbm_destroy to release it.  One such
+ * context at a time per device: the array keeps the last context's contents
+ * and is cleared by the next lbm_create_noalloc; a second one while the
+ * first lives gives LBM_ESTATE, and two host threads using the array of one
+ * device at once would race.  Errors: LBM_EINVAL as lbm_create, LBM_ENOMEM
+ * (the lattice does not fit the array), LBM_ESTATE, LBM_EDEVICE. */
+lbm_status lbm_create_noalloc(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                              void *hip_stream, lbm_ctx **out);
+size_t lbm_noalloc_capacity(void);
+
 /* Set the solids and the no-slip method (replaces any previous set).
  * IBB (Sec. 2.2, Fig. 1): classifies nodes (inside iff squared distance
  * <= R^2, shortest periodic image), builds the boundary links and the wall

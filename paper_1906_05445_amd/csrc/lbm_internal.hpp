@@ -184,6 +184,9 @@ struct lbm_ctx {
   // batches
   struct lbm_batch *batch;  // owning batch, or null
   uint64_t version;         // bumped by every call that changes the state or the geometry
+  // lbm_create_noalloc: the device whose static scratch array holds the workspace
+  // (the host struct then lives in static storage too); -1 otherwise
+  int noalloc_dev;
   // helpers
   void *state() const { return ws + (cur == 0 ? L.A : L.B); }
   void *other() const { return ws + (cur == 0 ? L.B : L.A); }

@@ -23,6 +23,8 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// bytes of the static workspace array behind lbm_create_noalloc
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
 
 int csize_of(int storage) { return storage == LBM_F64 ? 8 : 4; }
 int ssize_of(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32_DEV ? 4 : 2); }
@@ -237,6 +239,33 @@ void circle(const double c[3], double R, double z, std::vector<double> &X, doubl
 // ----------------------------------------------------------------------------
 // C ABI
 // ----------------------------------------------------------------------------
+// ----------------------------------------------------------------------------
+// lbm_create_noalloc: the workspace of one context per device in a file-scope
+// device array.  In host code `scratch` names a host-side stand-in, not device
+// memory; its device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// used.  The host struct of the context lives in static storage, so the call
+// allocates nothing on the device or the host.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mutex;
+char *g_scratch_ptr[kNoAllocDevices];  // device address of `scratch` per device (null: not taken yet)
+bool g_noalloc_busy[kNoAllocDevices];  // a context lives in that device's array
+alignas(lbm_ctx) unsigned char g_noalloc_ctx[kNoAllocDevices][sizeof(lbm_ctx)];
+}  // namespace
+
+// Releases the static slot of a context made by lbm_create_noalloc (the host
+// struct is destroyed in place).
+static void release_noalloc(lbm_ctx *c) {
+  const int dev = c->noalloc_dev;
+  c->~lbm_ctx();
+  std::lock_guard<std::mutex> g(g_noalloc_mutex);
+  g_noalloc_busy[dev] = false;
+}
+
 lbm_status lbm::destroy_ctx(lbm_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto &e : c->prof_events) {
@@ -251,7 +280,8 @@ lbm_status lbm::destroy_ctx(lbm_ctx *c) {
     (void)hipEventDestroy(t.e0);
     (void)hipEventDestroy(t.e1);
   }
-  delete c;
+  if (c->noalloc_dev >= 0) release_noalloc(c);
+  else delete c;
   return LBM_OK;
 }
 
@@ -283,7 +313,8 @@ size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_
   return L.total;
 }
 
-// Parameters checked and the workspace layout of a context.
+// Parameters checked and the workspace layout of a context (lbm_create and
+// lbm_create_noalloc).
 static lbm_status check_create(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
                                Layout *L) {
   if (!p || !make_layout(p, max_solids, max_links, max_lagrangian, L)) return LBM_EINVAL;
@@ -341,6 +372,7 @@ static lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const Layout &L, voi
   c->fresh = true;
   c->batch = nullptr;
   c->version = 0;
+  c->noalloc_dev = -1;
   // rest state, cleared flags and ownership
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner0, 0xFF, (size_t)c->N * 2, c->stream);
@@ -368,6 +400,35 @@ lbm_status lbm_create(const lbm_params *p, int32_t max_solids, int64_t max_links
   return LBM_OK;
 }
 
+lbm_status lbm_create_noalloc(const lbm_params *p, int32_t max_solids, int64_t max_links, int64_t max_lagrangian,
+                              void *hip_stream, lbm_ctx **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  Layout L;
+  const lbm_status st = check_create(p, max_solids, max_links, max_lagrangian, &L);
+  if (st != LBM_OK) return st;
+  if (L.total > kNoAllocBytes) return LBM_ENOMEM;  // the lattice does not fit the static array
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return LBM_EDEVICE;
+  std::lock_guard<std::mutex> g(g_noalloc_mutex);
+  if (g_noalloc_busy[dev]) return LBM_ESTATE;  // one context per device shares the array
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EDEVICE;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  lbm_ctx *c = new (g_noalloc_ctx[dev]) lbm_ctx();
+  if (init_ctx(c, p, L, g_scratch_ptr[dev], kNoAllocBytes, hip_stream) != LBM_OK) {
+    c->~lbm_ctx();
+    return LBM_EDEVICE;
+  }
+  c->noalloc_dev = dev;
+  g_noalloc_busy[dev] = true;
+  *out = c;
+  return LBM_OK;
+}
+
+size_t lbm_noalloc_capacity(void) { return kNoAllocBytes; }
 
 
 lbm_status lbm_destroy(lbm_ctx *c) {

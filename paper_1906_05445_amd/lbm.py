@@ -71,6 +71,8 @@ def _sig(name, res, args):
 _sig("lbm_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64])
 _sig("lbm_create", _st, [ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64, _vp, ctypes.c_size_t, _vp,
                          ctypes.POINTER(_vp)])
+_sig("lbm_create_noalloc", _st, [ctypes.POINTER(lbm_params), ctypes.c_int32, _i64, _i64, _vp, ctypes.POINTER(_vp)])
+_sig("lbm_noalloc_capacity", ctypes.c_size_t, [])
 _sig("lbm_set_solids", _st, [_vp, ctypes.POINTER(lbm_solid), ctypes.c_int32, ctypes.c_int32,
                              ctypes.POINTER(lbm_ibm_opts)])
 _sig("lbm_set_lagrangian", _st, [_vp, ctypes.c_int32, _d, _i64, ctypes.c_double])
@@ -122,7 +124,7 @@ _sig("lbm_batch_stream", _vp, [_vp])
 _sig("lbm_batch_last_error", ctypes.c_char_p, [_vp])
 _sig("lbm_batch_destroy", _st, [_vp])
 
-EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
+EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_create_noalloc", "lbm_noalloc_capacity", "lbm_set_solids", "lbm_set_lagrangian", "lbm_step",
             "lbm_force_torque", "lbm_force_history", "lbm_history_capacity", "lbm_macros", "lbm_strain", "lbm_solid_state", "lbm_get_f",
             "lbm_set_f", "lbm_set_equilibrium", "lbm_get_state", "lbm_set_state", "lbm_link_list", "lbm_node_types", "lbm_time",
             "lbm_check", "lbm_destroy", "lbm_status_string", "lbm_last_error", "lbm_copy_probe",
@@ -361,6 +363,36 @@ class Lattice(_Context):
         return {"nontemporal_stores": nt.value, "sweep_us_plain": a.value, "sweep_us_nontemporal": b.value,
                 "policy": names[pol.value] if pol.value >= 0 else None,
                 "sweep_us": {names[k]: us[k] for k in range(4)}}
+
+
+class StaticLattice(_Context):
+    """One lattice whose workspace is the library's static device array
+    (lbm_create_noalloc): no device memory is allocated for it.  One per
+    device at a time."""
+
+    def __init__(self, lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
+                 g=(0.0, 0.0, 0.0), g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0, stream=None):
+        import torch
+        params, self._rates = make_params(lattice, collision, storage, shape, tau, rates, g, g_fluid_only)
+        self._describe(lattice, params)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = _vp()
+        st = _lib.lbm_create_noalloc(ctypes.byref(self.params), max_solids, max_links, max_lagrangian,
+                                     _vp(self.stream.cuda_stream), ctypes.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, "lbm_create_noalloc")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Member(_Context):
