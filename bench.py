@@ -212,8 +212,7 @@ def run_batch(torch, lbm, W, steps, warmup, count=512):
     return out
 
 
-def run_serving(torch, lbm, W, rate, seconds, min_completed, count=256, pool_gb=32.0, max_slots=16,
-                step_cap=200000):
+def run_serving(torch, lbm, W, rate, seconds, min_completed, step_cap, count=256, pool_gb=32.0, max_slots=16):
     """The request trace served until min_completed requests have finished or `seconds`
     have passed (see paper_1906_05445_amd/serving.py)."""
     from paper_1906_05445_amd import serving as S
@@ -339,8 +338,10 @@ def main():
     ap.add_argument("--extras-out", default=os.path.join("gpurun_out", "bench_extras.json"))
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the 512-lattice batch")
     ap.add_argument("--precision-steps", type=int, default=10000, help="steps of the FP32/FP16 vs FP64 comparison")
-    ap.add_argument("--serve-seconds", type=float, default=180.0, help="limit of the saturated serving window")
+    ap.add_argument("--serve-seconds", type=float, default=240.0, help="limit of the saturated serving window")
     ap.add_argument("--serve-min", type=int, default=32, help="completions that end the saturated window")
+    ap.add_argument("--serve-cap", type=int, default=30000,
+                    help="step cap of a solve (a capped solve is reported as capped, with its drag at the cap)")
     ap.add_argument("--cpu-steps", default="1,3", help="oracle sample: steps on one thread, steps on all threads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -357,6 +358,9 @@ def main():
     K, Wm = args.steps, args.warmup
     want = set(ALL_EXTRAS) if args.extras == "all" else (set() if args.extras == "none" else
                                                           set(args.extras.split(",")))
+
+    def wanted(group, key):  # a whole group, or one case by its key
+        return group in want or key in want
     extras = {}
 
     def extra(key, value, summary):
@@ -376,33 +380,35 @@ def main():
 
     # ---- everything else: stderr + the extras file
     k2 = max(K, 100)
-    if "single" in want:
-        for key, case in [("sphere128_f32_quadratic", W.sphere_box(storage="F32", method="QUADRATIC")),
-                          ("sphere128_f64_quadratic", W.sphere_box(storage="F64", method="QUADRATIC")),
-                          ("sphere128_f16_quadratic", W.sphere_box(storage="F16", method="QUADRATIC")),
-                          ("sphere128_f32_ibm", W.sphere_box(storage="F32", method="IBM")),
-                          ("sphere128_f64_ibm", W.sphere_box(storage="F64", method="IBM"))]:
-            r = run_case(case, k2, Wm, key, torch, lbm)
+    for key, (ctor, kw) in [("sphere128_f32_quadratic", (W.sphere_box, {"storage": "F32"})),
+                            ("sphere128_f64_quadratic", (W.sphere_box, {"storage": "F64"})),
+                            ("sphere128_f16_quadratic", (W.sphere_box, {"storage": "F16"})),
+                            ("sphere128_f32_ibm", (W.sphere_box, {"storage": "F32", "method": "IBM"})),
+                            ("sphere128_f64_ibm", (W.sphere_box, {"storage": "F64", "method": "IBM"}))]:
+        if wanted("single", key):
+            r = run_case(ctor(**kw), k2, Wm, key, torch, lbm)
             extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+    if wanted("single", "sphere128_f32_mrt_general_rates"):
         # general relaxation rates (every MRT row its own rate): the sparse-M relaxation
         rates = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, 1.0 / 0.8, 1.4, 1.0 / 0.8, 1.4, 1.0 / 0.8,
                  1.0 / 0.8, 1.0 / 0.8, 1.98, 1.98, 1.98]
         r = run_case(W.sphere_box(storage="F32", method="QUADRATIC"), k2, Wm, "sphere128_f32_mrt_rates", torch, lbm,
                      rates=rates)
         extra("sphere128_f32_mrt_general_rates", r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
-    if "schemes" in want:
-        for key, (ctor, kw) in [("sphere128_f32_yu", (W.sphere_box, {"method": "YU"})),
-                                ("sphere128_f32_zhao_yong", (W.sphere_box, {"method": "ZHAO_YONG"})),
-                                ("pack256_f32_yu", (W.sphere_pack, {"method": "YU"})),
-                                ("pack256_f32_zhao_yong", (W.sphere_pack, {"method": "ZHAO_YONG"})),
-                                ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
-                                                                              "retraction": 0.3})),
-                                ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
-                                                                              "retraction": 0.2})),
-                                ("settle128_f32_free", (W.settling_sphere, {})),
-                                ("settle128_f32_free_ibm", (W.settling_sphere, {"method": "IBM"}))]:
-            r = run_case(ctor(storage="F32", **kw), k2, Wm, key, torch, lbm)
-            extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+    for key, (ctor, kw) in [("sphere128_f32_yu", (W.sphere_box, {"method": "YU"})),
+                            ("sphere128_f32_zhao_yong", (W.sphere_box, {"method": "ZHAO_YONG"})),
+                            ("pack256_f32_yu", (W.sphere_pack, {"method": "YU"})),
+                            ("pack256_f32_zhao_yong", (W.sphere_pack, {"method": "ZHAO_YONG"})),
+                            ("sphere128_f32_ibm_delta3", (W.sphere_box, {"method": "IBM", "delta": 3,
+                                                                          "retraction": 0.3})),
+                            ("sphere128_f32_ibm_delta2", (W.sphere_box, {"method": "IBM", "delta": 2,
+                                                                          "retraction": 0.2})),
+                            ("settle128_f32_free", (W.settling_sphere, {})),
+                            ("settle128_f32_free_ibm", (W.settling_sphere, {"method": "IBM"}))]:
+        if not wanted("schemes", key):
+            continue
+        r = run_case(ctor(storage="F32", **kw), k2, Wm, key, torch, lbm)
+        extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
     if "copy" in want:
         c = copy_probe(torch, lbm)
         extra("hbm_copy_GBps", c, f"{c:.0f} GB/s")
@@ -418,15 +424,16 @@ def main():
         extra("batch_f32_vs_plain_f64", bp, f"max rel force err {bp['max_rel_force_err']:.2e}")
     serving = None
     if "serving" in want and args.serve_seconds > 0:
-        sat = run_serving(torch, lbm, W, 50.0, args.serve_seconds, args.serve_min)
+        sat = run_serving(torch, lbm, W, 50.0, args.serve_seconds, args.serve_min, args.serve_cap)
         extra("serving_saturated", sat, f"{sat['completed']} done ({sat['converged']} converged) in "
                                         f"{sat['wall_s']:.1f} s, p50 {sat['latency_p50_s']} s, p99 {sat['latency_p99_s']} s")
         # below capacity: arrivals at half the measured saturated completion rate
         rate = max(0.5 * sat["solves_per_s"], 0.02)
-        sub = run_serving(torch, lbm, W, rate, 60.0, None)
+        sub = run_serving(torch, lbm, W, rate, 60.0, None, args.serve_cap)
         extra("serving_subsaturated", sub, f"{sub['completed']} done at {rate:.3f} req/s, p50 "
                                            f"{sub['latency_p50_s']} s, p99 {sub['latency_p99_s']} s")
         serving = {"n": sat["latency_n"], "converged": sat["converged"], "capped": sat["capped"],
+                   "step_cap": args.serve_cap,
                    "p50_s": sat["latency_p50_s"], "p99_s": sat["latency_p99_s"],
                    "solves_per_s": round(sat["solves_per_s"], 4), "offered_req_per_s": 50.0,
                    "sub_rate_req_per_s": round(rate, 4), "sub_n": sub["latency_n"], "sub_p50_s": sub["latency_p50_s"],

@@ -35,7 +35,6 @@ enum {
   WL_FT,
   WL_BOX,        // (solid, box chunk) units of members with translating solids
   WL_ONE,        // one unit per member with translating solids
-  WL_IBM_SHELL,   // 128 shell cells per unit (u0)
   WL_IBM_SPREAD,  // kSpreadCellsPerBlock shell cells per unit (kSpreadLanes lanes per cell)
   WL_IBM_LAG,
   WL_IBM_FT,
@@ -252,7 +251,6 @@ lbm_status rebuild(lbm_batch *b) {
     if (member_ibm(c)) {
       b->any_ibm = true;
       b->max_iter = std::max(b->max_iter, c->n_iter);
-      add(WL_IBM_SHELL, (uint64_t)((c->nshell + 127) / 128));
       add(WL_IBM_SPREAD, (uint64_t)((c->nshell + kSpreadCellsPerBlock - 1) / kSpreadCellsPerBlock));
       add(WL_IBM_LAG, (uint64_t)((c->nlag + 3) / 4));  // four points (wavefronts) per block
       add(WL_IBM_FT, (uint64_t)c->nsolid);
@@ -310,8 +308,8 @@ uint32_t grid_of(const lbm_batch *b, int mult) { return (uint32_t)std::max(1, mu
 // One batched step (enqueue only); e0/e1 (optional) time the sweep launches.
 void enqueue_step(lbm_batch *b, const SweepCfg &cfg, hipEvent_t e0, hipEvent_t e1) {
   const BatchLaunch bl{b->d_slots, b->d_step, b->stream, b->Q, b->storage};
-  if (b->any_ibm) launch_ibm_batch(bl, b->wl(WL_IBM_SHELL), b->wl(WL_IBM_SPREAD), b->wl(WL_IBM_LAG), b->wl(WL_IBM_FT), b->max_iter,
-                                   grid_of(b, 4));
+  if (b->any_ibm)
+    launch_ibm_batch(bl, b->wl(WL_IBM_SPREAD), b->wl(WL_IBM_LAG), b->wl(WL_IBM_FT), b->max_iter, grid_of(b, 4));
   int first = -1, lastc = -1;
   for (int k = 0; k < 3; k++)
     if (b->coll_mask & (1u << k)) {

@@ -73,10 +73,11 @@ __global__ void k_ibm_mark(IbmArgs a) {
   a.flags[n] = (uint8_t)(a.flags[n] | F_IBM);
 }
 
-// u0 = (j + g/2)/rho at every shell cell from the populations f(t), gathered
-// from the shifted state (A_i(x - e_i)); clears the spread force.
+// u0 = (j + g/2)/rho at cell n from the populations f(t), gathered from the
+// shifted state (A_i(x - e_i)); the body force only where it acts.
 template <int Q, typename S>
-__device__ inline void ibm_u0_at(const S *__restrict__ A, const IbmArgs &a, int64_t s, uint32_t n) {
+__device__ inline void ibm_u0_cell(const S *__restrict__ A, const IbmArgs &a, uint32_t n,
+                                   typename Store<S>::C (&u)[3]) {
 #pragma clang fp contract(off)
   using C = typename Store<S>::C;
   using L = Lat<Q>;
@@ -98,17 +99,21 @@ __device__ inline void ibm_u0_at(const S *__restrict__ A, const IbmArgs &a, int6
   }
   const C rho = C(1) + drho;
   const bool body = !(a.flags[n] & F_NOBODY);
+  for (int k = 0; k < 3; k++) u[k] = (j[k] + C(0.5) * (body ? (C)a.g[k] : C(0))) / rho;
+}
+
+// u0 at shell cell s (cell n) into the shell's velocity; clears its spread force.
+template <int Q, typename S>
+__device__ inline void ibm_u0_at(const S *__restrict__ A, const IbmArgs &a, int64_t s, uint32_t n) {
+  using C = typename Store<S>::C;
+  C v[3];
+  ibm_u0_cell<Q, S>(A, a, n, v);
   C *u = static_cast<C *>(a.ushell);
   C *f = static_cast<C *>(a.fshell);
   for (int k = 0; k < 3; k++) {
-    u[k * a.nshell + s] = (j[k] + C(0.5) * (body ? (C)a.g[k] : C(0))) / rho;
+    u[k * a.nshell + s] = v[k];
     f[k * a.nshell + s] = C(0);
   }
-}
-template <int Q, typename S>
-__device__ inline void ibm_u0_body(const S *__restrict__ A, const IbmArgs &a, int64_t s) {
-  if (s >= a.nshell) return;
-  ibm_u0_at<Q, S>(A, a, s, a.shell_cell[s]);
 }
 
 // Eq. 5 and Eq. 7: interpolate u to the point, F = rho0 (U^d - U~)/dt.
@@ -139,6 +144,22 @@ __device__ inline void ibm_interp_terms(const C *u, int64_t nshell, uint32_t si,
   v[2] = u[2 * nshell + si] * wt;
 }
 
+// The same share from the velocity values themselves.
+template <typename C>
+__device__ inline void ibm_interp_values(const C (&u)[3], C wt, C v[3]) {
+#pragma clang fp contract(off)
+  v[0] = u[0] * wt;
+  v[1] = u[1] * wt;
+  v[2] = u[2] * wt;
+}
+
+// One entry of a row of the point coupling: acc += A_lm F_m.
+template <typename C>
+__device__ inline void ibm_couple_term(C A, const C (&Fm)[3], C acc[3]) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; k++) acc[k] = acc[k] + A * Fm[k];
+}
+
 // Point force of one iteration, F = U^d - U~ (Eq. 7 with rho0 = dt = 1), and
 // its running sum over the iterations.
 template <typename C>
@@ -147,24 +168,6 @@ __device__ inline C ibm_point_force(C ud, C us, double *sum) {
   const C F = ud - us;
   *sum = *sum + (double)F;
   return F;
-}
-
-template <typename C>
-__device__ inline void ibm_interp_body(const IbmArgs &a, int first, int64_t l) {
-  const int slot = (int)(threadIdx.x & 63);
-  const int kz = slot >> 4;
-  const C *u = static_cast<const C *>(a.ushell);
-  C v[3] = {0, 0, 0};
-  if (l < a.nlag && kz < (a.b.D == 2 ? 1 : 4))
-    ibm_interp_terms<C>(u, a.nshell, a.idx[l * 64 + slot], ibm_weight<C>(a.wts + l * 12, (uint32_t)slot), v);
-  for (int k = 0; k < 3; k++) v[k] = wave_sum_c(v[k]);
-  if (slot != 0 || l >= a.nlag) return;
-  C *Fk = static_cast<C *>(a.Fk);
-  for (int k = 0; k < 3; k++) {
-    double sum = first ? 0.0 : a.Fsum[l * 3 + k];
-    Fk[l * 3 + k] = ibm_point_force<C>((C)a.Ud[l * 3 + k], v[k], &sum);
-    a.Fsum[l * 3 + k] = sum;
-  }
 }
 
 // Eq. 8 and Eq. 9: f(x) = sum_l F_l delta dV_l, u += f dt / rho0.
@@ -177,6 +180,13 @@ template <typename C>
 __device__ inline void ibm_spread_term(const C *Fk, uint32_t l, C wt, C dv, C f[3]) {
 #pragma clang fp contract(off)
   for (int k = 0; k < 3; k++) f[k] = f[k] + Fk[(uint64_t)l * 3 + k] * wt * dv;
+}
+
+// The same with the summed point force (FP64) of all iterations.
+template <typename C>
+__device__ inline void ibm_spread_sum_term(const double *Fs, C wt, C dv, C f[3]) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; k++) f[k] = f[k] + (C)Fs[k] * wt * dv;
 }
 
 // Fixed-order sum over the lanes of a shell cell; lane 0 holds it.
@@ -194,32 +204,141 @@ __device__ inline C ibm_add(C x, C y) {
   return x + y;
 }
 
+// ---- fixed solids: the forcing iterations in point space -------------------
+// With fixed points, interpolating u^k = u^(k-1) + f^k (Eq. 9) after spreading
+// f^k = sum_m F^k_m delta(x - X_m) dV_m (Eq. 8) gives, by linearity,
+//   U~^(k+1)_l = U~^k_l + sum_m A_lm F^k_m,
+//   A_lm = dV_m sum_x delta(x - X_l) delta(x - X_m),
+// so after one interpolation of u0 (Eq. 5) the n_iter iterations of Eq. 7
+// run on the points, and the summed force is spread once.  The delta
+// function is a product over the axes, and so is the sum over the shared
+// stencil cells: A_lm = dV_m prod_a S_a with S_a = sum over the node pairs
+// (k, k') of the two stencils that fall on the same node (periodically) of
+// w_l[a][k] w_m[a][k'].
+
+// Eq. 5 at the first iteration: u0 at the point's 4^D stencil cells (one
+// lane each, pulled from the state as ibm_u0_cell does) times the delta
+// weight, wave-summed; then Eq. 7, F = U^d - U~, the first term of the sum.
+template <int Q, typename S>
+__device__ inline void ibm_interp0_body(const S *__restrict__ A, const IbmArgs &a, int64_t l) {
+  using C = typename Store<S>::C;
+  const int slot = (int)(threadIdx.x & 63);
+  const int kz = slot >> 4;
+  const bool pt = l < a.nlag;
+  // the point's operands, fetched before the sums that come later need them
+  double ud[3] = {0.0, 0.0, 0.0};
+  if (pt && slot == 0)
+    for (int k = 0; k < 3; k++) ud[k] = a.Ud[l * 3 + k];
+  C v[3] = {0, 0, 0};
+  if (pt && kz < (a.b.D == 2 ? 1 : 4)) {
+    C u[3];
+    ibm_u0_cell<Q, S>(A, a, a.idx[l * 64 + slot], u);  // the slot's cell
+    ibm_interp_values<C>(u, ibm_weight<C>(a.wts + l * 12, (uint32_t)slot), v);
+  }
+  for (int k = 0; k < 3; k++) v[k] = wave_sum_c(v[k]);
+  if (slot != 0 || !pt) return;
+  IbmF4<C> F;
+  C *Ut = static_cast<C *>(a.Ut);
+  C f[3];
+  for (int k = 0; k < 3; k++) {
+    double sum = 0.0;
+    Ut[l * 3 + k] = v[k];
+    f[k] = ibm_point_force<C>((C)ud[k], v[k], &sum);
+    a.Fsum[l * 3 + k] = sum;
+  }
+  F.x = f[0], F.y = f[1], F.z = f[2], F.w = C(0);
+  static_cast<IbmF4<C> *>(a.Fk)[l] = F;
+}
+
+// Iteration it >= 1: U~ += A F (the forces of iteration it - 1, buffer
+// (it - 1) & 1), then F = U^d - U~ into buffer it & 1 and the running sum.
+// One wavefront per point, one row entry per lane (rows padded to a fixed
+// width with zeros), a fixed-order wave sum.
 template <typename C>
-__device__ inline void ibm_spread_body(const IbmArgs &a, int last, int64_t s) {
+__device__ inline void ibm_iter_body(const IbmArgs &a, int it, int64_t l) {
+  const int lane = (int)(threadIdx.x & 63);
+  const IbmF4<C> *Fp = static_cast<const IbmF4<C> *>(((it - 1) & 1) ? a.Fk2 : a.Fk);
+  IbmF4<C> *Fc = static_cast<IbmF4<C> *>((it & 1) ? a.Fk2 : a.Fk);
+  const IbmEntry<C> *row = static_cast<const IbmEntry<C> *>(a.nrow);
+  const bool pt = l < a.nlag;
+  C ut[3] = {0, 0, 0};
+  double ud[3] = {0.0, 0.0, 0.0}, fs[3] = {0.0, 0.0, 0.0};
+  if (pt && lane == 0) {
+    const C *Ut = static_cast<const C *>(a.Ut);
+    for (int k = 0; k < 3; k++) {
+      ut[k] = Ut[l * 3 + k];
+      ud[k] = a.Ud[l * 3 + k];
+      fs[k] = a.Fsum[l * 3 + k];
+    }
+  }
+  C acc[3] = {0, 0, 0};
+  if (pt)
+    for (int j = lane; j < a.nw; j += 64) {
+      const IbmEntry<C> e = row[l * a.nw + j];
+      const IbmF4<C> F = Fp[e.col];
+      const C Fm[3] = {F.x, F.y, F.z};
+      ibm_couple_term<C>(e.val, Fm, acc);
+    }
+  for (int k = 0; k < 3; k++) acc[k] = wave_sum_c(acc[k]);
+  if (lane != 0 || !pt) return;
+  C *Ut = static_cast<C *>(a.Ut);
+  C f[3];
+  for (int k = 0; k < 3; k++) {
+    const C us = ibm_add<C>(ut[k], acc[k]);
+    Ut[l * 3 + k] = us;
+    f[k] = ibm_point_force<C>((C)ud[k], us, &fs[k]);
+    a.Fsum[l * 3 + k] = fs[k];
+  }
+  IbmF4<C> F;
+  F.x = f[0], F.y = f[1], F.z = f[2], F.w = C(0);
+  Fc[l] = F;
+}
+
+// Setup: the values of row l of A (one wavefront per point, one entry per
+// lane; the padding keeps value 0).
+template <typename C>
+__device__ inline void ibm_amat_body(const IbmArgs &a, int64_t l) {
+#pragma clang fp contract(off)
+  const int lane = (int)(threadIdx.x & 63);
+  if (l >= a.nlag) return;
+  const int Ls[3] = {a.b.nx, a.b.ny, a.b.nz};
+  IbmEntry<C> *row = static_cast<IbmEntry<C> *>(a.nrow) + l * a.nw;
+  for (int j = lane; j < (int)a.nptr[l]; j += 64) {
+    const uint32_t m = row[j].col;
+    double A = a.dV[m];
+    for (int ax = 0; ax < 3; ax++) {
+      double S = 0.0;
+      const int bl = a.base[l * 3 + ax], bm = a.base[(int64_t)m * 3 + ax];
+      for (int k = 0; k < 4; k++)
+        for (int k2 = 0; k2 < 4; k2++)
+          if (wrapi(bl + k - bm - k2, Ls[ax]) == 0) S = S + a.wts[l * 12 + ax * 4 + k] * a.wts[(int64_t)m * 12 + ax * 4 + k2];
+      A = A * S;
+    }
+    row[j].val = (C)A;
+  }
+}
+
+// Eq. 8 once, with the summed force: f(x) = sum_l (sum_k F^k_l) delta dV_l
+// over the shell cell's (point, slot) list, into the force field the sweep
+// reads (kSpreadLanes lanes per cell, fixed-order lane sum).
+template <typename C>
+__device__ inline void ibm_spread_sum_body(const IbmArgs &a, int64_t s) {
   const int lane = (int)(threadIdx.x & (kSpreadLanes - 1));
-  const C *Fk = static_cast<const C *>(a.Fk);
   C f[3] = {0, 0, 0};
   if (s < a.nshell) {
     const uint32_t e1 = a.rowptr[s + 1];
     for (uint32_t e = a.rowptr[s] + lane; e < e1; e += kSpreadLanes) {
       const uint32_t v = a.ent[e];
       const uint32_t l = v >> 6;
-      ibm_spread_term<C>(Fk, l, ibm_weight<C>(a.wts + (uint64_t)l * 12, v & 63u), (C)a.dV[l], f);
+      ibm_spread_sum_term<C>(a.Fsum + (uint64_t)l * 3, ibm_weight<C>(a.wts + (uint64_t)l * 12, v & 63u), (C)a.dV[l],
+                             f);
     }
   }
   ibm_spread_reduce<C>(f);
   if (lane != 0 || s >= a.nshell) return;
-  C *u = static_cast<C *>(a.ushell);
-  C *fs = static_cast<C *>(a.fshell);
-  for (int k = 0; k < 3; k++) {
-    u[k * a.nshell + s] = ibm_add<C>(u[k * a.nshell + s], f[k]);
-    fs[k * a.nshell + s] = ibm_add<C>(fs[k * a.nshell + s], f[k]);
-  }
-  if (last) {
-    C *fb = static_cast<C *>(a.fibm);
-    const uint32_t n = a.shell_cell[s];
-    for (int k = 0; k < 3; k++) fb[k * a.stride + n] = fs[k * a.nshell + s];
-  }
+  C *fb = static_cast<C *>(a.fibm);
+  const uint32_t n = a.shell_cell[s];
+  for (int k = 0; k < 3; k++) fb[k * a.stride + n] = f[k];
 }
 
 // ---- one moving solid ------------------------------------------------------
@@ -364,16 +483,20 @@ __global__ __launch_bounds__(256) void k_ibm_spread_mv(IbmArgs a, int last) {
 }
 
 template <int Q, typename S>
-__global__ void k_ibm_u0(const S *__restrict__ A, IbmArgs a) {
-  ibm_u0_body<Q, S>(A, a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void k_ibm_interp0(const S *__restrict__ A, IbmArgs a) {
+  ibm_interp0_body<Q, S>(A, a, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
 template <typename C>
-__global__ __launch_bounds__(256) void k_ibm_interp(IbmArgs a, int first) {
-  ibm_interp_body<C>(a, first, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
+__global__ __launch_bounds__(256) void k_ibm_iter(IbmArgs a, int it) {
+  ibm_iter_body<C>(a, it, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
 template <typename C>
-__global__ __launch_bounds__(256) void k_ibm_spread(IbmArgs a, int last) {
-  ibm_spread_body<C>(a, last, (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
+__global__ __launch_bounds__(256) void k_ibm_spread_sum(IbmArgs a) {
+  ibm_spread_sum_body<C>(a, (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
+}
+template <typename C>
+__global__ __launch_bounds__(256) void k_ibm_amat(IbmArgs a) {
+  ibm_amat_body<C>(a, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
 __global__ __launch_bounds__(kBlock) void k_ibm_ft(IbmFtArgs f) { ibm_ft_body(f, blockIdx.x); }
 
@@ -381,37 +504,33 @@ __global__ __launch_bounds__(kBlock) void k_ibm_ft(IbmFtArgs f) { ibm_ft_body(f,
 // t = t0 + k); a member takes part in forcing iteration `it` while
 // it < n_iter.  Units: 128 shell cells or points; one solid for the force.
 template <int Q, typename S>
-__global__ __launch_bounds__(128) void k_ibm_u0_batch(const BatchSlot *__restrict__ slots,
-                                                      const WorkList *__restrict__ wl,
-                                                      const int64_t *__restrict__ step) {
+__global__ __launch_bounds__(256) void k_ibm_interp0_batch(const BatchSlot *__restrict__ slots,
+                                                           const WorkList *__restrict__ wl,
+                                                           const int64_t *__restrict__ step) {
   const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t u) {
     IbmArgs a = SLOT(m, im);
     a.t = SLOT(m, t0) + k;
-    ibm_u0_body<Q, S>(static_cast<const S *>(SLOT(m, P[SLOT(m, cur0) ^ (int)(k & 1)])), a,
-                      (int64_t)u * 128 + threadIdx.x);
+    ibm_interp0_body<Q, S>(static_cast<const S *>(SLOT(m, P[SLOT(m, cur0) ^ (int)(k & 1)])), a,
+                           (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6));
   });
 }
 template <typename C>
-__global__ __launch_bounds__(256) void k_ibm_interp_batch(const BatchSlot *__restrict__ slots,
-                                                          const WorkList *__restrict__ wl, int it) {
+__global__ __launch_bounds__(256) void k_ibm_iter_batch(const BatchSlot *__restrict__ slots,
+                                                        const WorkList *__restrict__ wl, int it) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
     if (it < SLOT(m, n_iter)) {
       const IbmArgs a = SLOT(m, im);
-      ibm_interp_body<C>(a, it == 0 ? 1 : 0, (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6));
+      ibm_iter_body<C>(a, it, (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6));
     }
   });
 }
 template <typename C>
-__global__ __launch_bounds__(256) void k_ibm_spread_batch(const BatchSlot *__restrict__ slots,
-                                                          const WorkList *__restrict__ wl, int it) {
+__global__ __launch_bounds__(256) void k_ibm_spread_sum_batch(const BatchSlot *__restrict__ slots,
+                                                              const WorkList *__restrict__ wl) {
   batch_units(wl, 0, [&](int m, uint32_t u) {
-    const int n_iter = SLOT(m, n_iter);
-    if (it < n_iter) {
-      const IbmArgs a = SLOT(m, im);
-      ibm_spread_body<C>(a, it == n_iter - 1 ? 1 : 0,
-                         (int64_t)u * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
-    }
+    const IbmArgs a = SLOT(m, im);
+    ibm_spread_sum_body<C>(a, (int64_t)u * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
   });
 }
 __global__ __launch_bounds__(kBlock) void k_ibm_ft_batch(const BatchSlot *__restrict__ slots,
@@ -457,6 +576,11 @@ static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
   a.t = t;
   a.mv = c->ibm_moving ? 1 : 0;
   a.shift = c->at<int32_t>(c->L.misc + 64 + 16 * (size_t)c->L.max_solids);
+  a.nptr = c->at<uint32_t>(c->L.lag_nptr);
+  a.nrow = c->ws + c->L.lag_nrow;
+  a.nw = c->ibm_nw;
+  a.Ut = c->ws + c->L.lag_Ut;
+  a.Fk2 = c->ws + c->L.lag_Fk2;
   return a;
 }
 
@@ -465,8 +589,12 @@ void launch_ibm_setup(lbm_ctx *c) {
   IbmArgs a = ibm_args(c, c->t);
   if (c->ibm_moving)
     hipLaunchKernelGGL(k_ibm_move, dim3((uint32_t)((c->nlag * kMoveLanes + 255) / 256)), dim3(256), 0, c->stream, a);
-  else
+  else {
     hipLaunchKernelGGL(k_ibm_weights, dim3((uint32_t)((c->nlag + 127) / 128)), dim3(128), 0, c->stream, a);
+    const dim3 g((uint32_t)((c->nlag + kIbmPointsPerBlock - 1) / kIbmPointsPerBlock));
+    if (c->p.storage == LBM_F64) hipLaunchKernelGGL(k_ibm_amat<double>, g, dim3(256), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_ibm_amat<float>, g, dim3(256), 0, c->stream, a);
+  }
   hipLaunchKernelGGL(k_ibm_mark, dim3((uint32_t)((c->nshell + 255) / 256)), dim3(256), 0, c->stream, a);
 }
 
@@ -492,14 +620,14 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
       hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t));
     return;
   }
+  // fixed solids: u0 and the first interpolation, n_iter - 1 point-space
+  // iterations, one spreading of the summed force
   if (c->Q == 9)
-    hipLaunchKernelGGL((k_ibm_u0<9, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
+    hipLaunchKernelGGL((k_ibm_interp0<9, S>), gl, dim3(256), 0, c->stream, static_cast<const S *>(A), a);
   else
-    hipLaunchKernelGGL((k_ibm_u0<19, S>), gs, dim3(128), 0, c->stream, static_cast<const S *>(A), a);
-  for (int it = 0; it < c->n_iter; it++) {
-    hipLaunchKernelGGL(k_ibm_interp<C>, gl, dim3(256), 0, c->stream, a, it == 0 ? 1 : 0);
-    hipLaunchKernelGGL(k_ibm_spread<C>, gsp, dim3(256), 0, c->stream, a, it == c->n_iter - 1 ? 1 : 0);
-  }
+    hipLaunchKernelGGL((k_ibm_interp0<19, S>), gl, dim3(256), 0, c->stream, static_cast<const S *>(A), a);
+  for (int it = 1; it < c->n_iter; it++) hipLaunchKernelGGL(k_ibm_iter<C>, gl, dim3(256), 0, c->stream, a, it);
+  hipLaunchKernelGGL(k_ibm_spread_sum<C>, gsp, dim3(256), 0, c->stream, a);
   if (with_ft)
     hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t));
 }
@@ -507,26 +635,25 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
 void fill_ibm_args(lbm_ctx *c, IbmArgs *a) { *a = ibm_args(c, c->t); }
 
 template <typename S>
-static void ibm_batch_t(const BatchLaunch &b, const WorkList *shell, const WorkList *spread, const WorkList *lag,
-                        const WorkList *ft, int max_iter, uint32_t grid) {
+static void ibm_batch_t(const BatchLaunch &b, const WorkList *spread, const WorkList *lag, const WorkList *ft,
+                        int max_iter, uint32_t grid) {
   using C = typename Store<S>::C;
   if (b.Q == 9)
-    hipLaunchKernelGGL((k_ibm_u0_batch<9, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
+    hipLaunchKernelGGL((k_ibm_interp0_batch<9, S>), dim3(grid), dim3(256), 0, b.stream, b.slots, lag, b.step);
   else
-    hipLaunchKernelGGL((k_ibm_u0_batch<19, S>), dim3(grid), dim3(128), 0, b.stream, b.slots, shell, b.step);
-  for (int it = 0; it < max_iter; it++) {
-    hipLaunchKernelGGL(k_ibm_interp_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, lag, it);
-    hipLaunchKernelGGL(k_ibm_spread_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, spread, it);
-  }
+    hipLaunchKernelGGL((k_ibm_interp0_batch<19, S>), dim3(grid), dim3(256), 0, b.stream, b.slots, lag, b.step);
+  for (int it = 1; it < max_iter; it++)
+    hipLaunchKernelGGL(k_ibm_iter_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, lag, it);
+  hipLaunchKernelGGL(k_ibm_spread_sum_batch<C>, dim3(grid), dim3(256), 0, b.stream, b.slots, spread);
   hipLaunchKernelGGL(k_ibm_ft_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(kBlock), 0, b.stream, b.slots, ft,
                      b.step);
 }
 
-void launch_ibm_batch(const BatchLaunch &b, const WorkList *shell, const WorkList *spread, const WorkList *lag, const WorkList *ft,
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *spread, const WorkList *lag, const WorkList *ft,
                       int max_iter, uint32_t grid) {
-  if (b.storage == LBM_F64) ibm_batch_t<double>(b, shell, spread, lag, ft, max_iter, grid);
-  else if (b.storage == LBM_F32_DEV) ibm_batch_t<float>(b, shell, spread, lag, ft, max_iter, grid);
-  else ibm_batch_t<_Float16>(b, shell, spread, lag, ft, max_iter, grid);
+  if (b.storage == LBM_F64) ibm_batch_t<double>(b, spread, lag, ft, max_iter, grid);
+  else if (b.storage == LBM_F32_DEV) ibm_batch_t<float>(b, spread, lag, ft, max_iter, grid);
+  else ibm_batch_t<_Float16>(b, spread, lag, ft, max_iter, grid);
 }
 
 IbmFtArgs ibm_ft_args_of(lbm_ctx *c, int64_t t) {

@@ -12,6 +12,8 @@
 // [Q][stride], x fastest, so each of the 2Q streams is coalesced.
 #include <hip/hip_ext.h>
 
+#include <utility>
+
 #include "lbm_args.hpp"
 #include "lbm_ibb.hpp"
 
@@ -45,6 +47,45 @@ __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepA
     if constexpr (IDX32 != 0) r[i] = A[pidx32<Q>(i, src)];
     else r[i] = A[pidx<Q>(i, src)];
   }
+}
+
+// Row K of M times v, over the nonzero entries in ascending i.
+template <int Q, int K, typename C, int... I>
+__device__ __forceinline__ C mrt_row_dot(const C (&v)[Q], std::integer_sequence<int, I...>) {
+  C s = C(0);
+  ((s = (mrow<Q>(K, I) != 0) ? s + C(mrow<Q>(K, I)) * v[I] : s), ...);
+  return s;
+}
+// Column I of M^T times dm (the back transform of one direction), ascending k.
+template <int Q, int I, typename C, int... K>
+__device__ __forceinline__ C mrt_col_dot(const C (&dm)[Q], std::integer_sequence<int, K...>) {
+  C s = C(0);
+  ((s = (mrow<Q>(K, I) != 0) ? s + C(mrow<Q>(K, I)) * dm[K] : s), ...);
+  return s;
+}
+// dm of one row: conserved rows carry the force (momentum) or nothing
+// (density); the others relax with their own rate, scaled by 1/|M_k|^2.
+template <int Q, int K, typename C>
+__device__ __forceinline__ C mrt_row(const C (&fneq)[Q], const C (&Fh)[Q], const SweepArgs &a, C Fx, C Fy, C Fz) {
+  if constexpr (conserved<Q>(K)) {
+    const C invn = C(1.0 / mnorm<Q>(K));
+    return K == 0 ? C(0) : (K == 3 ? Fx : (K == 5 ? Fy : Fz)) * invn;
+  } else {
+    const auto seq = std::make_integer_sequence<int, Q>{};
+    const C mn = mrt_row_dot<Q, K, C>(fneq, seq);
+    const C mf = mrt_row_dot<Q, K, C>(Fh, seq);
+    return (C)a.sA[K] * mn + (C)a.sB[K] * mf;
+  }
+}
+template <int Q, typename C, int... K>
+__device__ __forceinline__ void mrt_rows(const C (&fneq)[Q], const C (&Fh)[Q], const SweepArgs &a, C Fx, C Fy, C Fz,
+                                         C (&dmn)[Q], std::integer_sequence<int, K...>) {
+  ((dmn[K] = mrt_row<Q, K, C>(fneq, Fh, a, Fx, Fy, Fz)), ...);
+}
+template <int Q, typename C, int... I>
+__device__ __forceinline__ void mrt_cols(const C (&dmn)[Q], C (&h)[Q], std::integer_sequence<int, I...>) {
+  const auto seq = std::make_integer_sequence<int, Q>{};
+  ((h[I] += mrt_col_dot<Q, I, C>(dmn, seq)), ...);
 }
 
 // Relaxation of one cell (Eq. 1 or Eq. 3 with the forcing of Sec. 2.1) and
@@ -135,33 +176,12 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
       Fh[i] = w * (C(3) * (eF - uF) + C(9) * eu * eF);
     }
     // general diagonal S: dm_k = -s_k (m - m_eq)_k + (1 - s_k/2) (M F)_k,
-    // conserved rows: density 0, momentum F; then h += M^-1 dm.
+    // conserved rows: density 0, momentum F; then h += M^-1 dm.  The sparse
+    // integer products are expanded at compile time (mrt_rows, mrt_cols):
+    // only the nonzero entries of M become multiply-adds.
     C dmn[Q];
-#pragma unroll
-    for (int k = 0; k < Q; k++) {
-      if (conserved<Q>(k)) {
-        const C invn = C(1.0 / mnorm<Q>(k));
-        dmn[k] = k == 0 ? C(0) : (k == 3 ? Fx : (k == 5 ? Fy : Fz)) * invn;
-      } else {
-        C mn = 0, mf = 0;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-          if (mrow<Q>(k, i) != 0) {
-            mn += C(mrow<Q>(k, i)) * fneq[i];
-            mf += C(mrow<Q>(k, i)) * Fh[i];
-          }
-        }
-        dmn[k] = (C)a.sA[k] * mn + (C)a.sB[k] * mf;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      C s = 0;
-#pragma unroll
-      for (int k = 0; k < Q; k++)
-        if (mrow<Q>(k, i) != 0) s += C(mrow<Q>(k, i)) * dmn[k];
-      h[i] += s;
-    }
+    mrt_rows<Q, C>(fneq, Fh, a, Fx, Fy, Fz, dmn, std::make_integer_sequence<int, Q>{});
+    mrt_cols<Q, C>(dmn, h, std::make_integer_sequence<int, Q>{});
   }
 
   // The relaxation is compiled with contraction allowed; an empty asm makes

@@ -131,6 +131,36 @@ struct IbmArgs {
   // for the step t in shift[4 (t & 1) + axis]
   int mv;
   int32_t *shift;
+  // fixed solids, forcing iterations in point space: row l of the point
+  // coupling A is nrow[l * nw .. l * nw + nw - 1] (IbmEntry of the compute
+  // type; nptr[l] of them are the row, the rest padding with value 0 and
+  // column l); the interpolated velocity U~ [nlag][3]; the force of an
+  // iteration in Fk / Fk2 as [nlag] x 4 (x, y, z, 0) of the compute type; idx
+  // holds the cell (not the shell index) of each stencil slot
+  const uint32_t *nptr;
+  void *nrow;
+  int nw;
+  void *Ut;
+  void *Fk2;
+};
+
+// One entry of a row of the point coupling: column (a point) and value.
+template <typename C>
+struct IbmEntry;
+template <>
+struct alignas(8) IbmEntry<float> {
+  uint32_t col;
+  float val;
+};
+template <>
+struct alignas(16) IbmEntry<double> {
+  uint32_t col, pad;
+  double val;
+};
+// A point force of one iteration, padded to four components (one vector load).
+template <typename C>
+struct alignas(4 * sizeof(C)) IbmF4 {
+  C x, y, z, w;
 };
 
 __device__ __host__ inline IbmFtArgs ibm_ft_args(const IbmArgs &a, int64_t t, const int64_t *start,
@@ -334,7 +364,7 @@ void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_force_change(const BatchLaunch &b, const WorkList *wl, int64_t lag, double *out, uint32_t grid);
 void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_one, uint32_t grid);
-void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_shell, const WorkList *wl_spread,
-                      const WorkList *wl_lag, const WorkList *wl_ft, int max_iter, uint32_t grid);
+void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_spread, const WorkList *wl_lag, const WorkList *wl_ft,
+                      int max_iter, uint32_t grid);
 
 }  // namespace lbm

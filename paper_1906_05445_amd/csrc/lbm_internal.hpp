@@ -18,6 +18,7 @@ constexpr int kMaxQ = 19;
 constexpr int kHistCap = 8192;  // steps of force/torque history kept on the device
 constexpr int kBlock = 256;     // threads per block for per-cell kernels
 constexpr int kLinkChunk = 64;  // links per wavefront of the bounce-back kernel
+constexpr int kIbmNbr = 128;    // point-coupling entries per Lagrangian point of capacity
 
 // Solid as the kernels see it.
 struct DevSolid {
@@ -52,7 +53,8 @@ struct SolidLinks {
 struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
       partials, partials2, seg_link, cell_list, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
-      lag_Fk, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f, refill, misc, total;
+      lag_Fk, lag_Fk2, lag_Ut, lag_nptr, lag_nrow, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f,
+      refill, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials, max_refill;
   int32_t max_solids;
@@ -159,6 +161,7 @@ struct lbm_ctx {
   double retraction;
   int64_t nlag;
   int64_t nshell;
+  int ibm_nw;  // width of a row of the point coupling (64 or 128; fixed IBM solids)
   std::vector<int64_t> lag_start, lag_count;
   std::vector<double> lag_X, lag_dV;
   bool lag_user;

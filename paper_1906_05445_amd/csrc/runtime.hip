@@ -144,7 +144,11 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.lag_w = take((size_t)max_lag * 96);
   l.lag_idx = take((size_t)max_lag * 256);
   l.lag_Fsum = take((size_t)max_lag * 24);
-  l.lag_Fk = take((size_t)max_lag * 3 * cs);
+  l.lag_Fk = take((size_t)max_lag * 4 * cs);
+  l.lag_Fk2 = take((size_t)max_lag * 4 * cs);
+  l.lag_Ut = take((size_t)max_lag * 3 * cs);
+  l.lag_nptr = take((size_t)max_lag * 4);
+  l.lag_nrow = take((size_t)max_lag * kIbmNbr * (cs == 8 ? 16 : 8));
   l.shell_cell = take((size_t)l.max_shell * 4);
   l.shell_rowptr = take((size_t)(l.max_shell + 1) * 4);
   l.shell_ent = take((size_t)max_lag * 64 * 4);
@@ -363,6 +367,7 @@ static lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const Layout &L, voi
   c->retraction = 0.0;
   c->nlag = 0;
   c->nshell = 0;
+  c->ibm_nw = 64;
   c->lag_user = false;
   c->prof_every = 0;
   c->prof_count = 0;
@@ -787,6 +792,48 @@ static lbm_status build_ibm(lbm_ctx *c) {
       const uint32_t si = idx[(size_t)l * row + slot];
       ent[fill[si]++] = (uint32_t)(l << sbits) | (uint32_t)slot;
     }
+  // fixed solids: the point coupling of the forcing iterations (Eq. 5 after
+  // Eq. 8-9), A_lm = dV_m sum_x delta(x - X_l) delta(x - X_m): nonzero where
+  // the stencils of l and m share a cell; each row lists those m in order,
+  // padded to a fixed width (the values are formed on the device from the
+  // delta weights); the stencil slots hold cells, not shell indices
+  std::vector<uint32_t> rlen;
+  std::vector<unsigned char> rows;
+  int nw = 64;
+  if (!mv) {
+    rlen.assign((size_t)std::max<int64_t>(nl, 1), 0);
+    std::vector<std::vector<uint32_t>> lists((size_t)nl);
+    std::vector<int64_t> seen((size_t)std::max<int64_t>(nl, 1), -1);
+    for (int64_t l = 0; l < nl; l++) {
+      std::vector<uint32_t> &rowl = lists[(size_t)l];
+      for (int slot = 0; slot < nslot; slot++) {
+        const uint32_t si = idx[(size_t)l * row + slot];
+        for (uint32_t e = rowptr[si]; e < rowptr[si + 1]; e++) {
+          const uint32_t m = ent[e] >> sbits;
+          if (seen[m] != l) {
+            seen[m] = l;
+            rowl.push_back(m);
+          }
+        }
+      }
+      std::sort(rowl.begin(), rowl.end());
+      rlen[(size_t)l] = (uint32_t)rowl.size();
+      if (rowl.size() > (size_t)kIbmNbr)
+        return set_err(c, "a Lagrangian point couples to more than 128 others (points too close together)"),
+               LBM_ENOMEM;
+      if (rowl.size() > 64) nw = 128;
+    }
+    const size_t es = csize_of(c->p.storage) == 8 ? 16 : 8;
+    rows.assign((size_t)std::max<int64_t>(nl, 1) * nw * es, 0);
+    for (int64_t l = 0; l < nl; l++)
+      for (int j = 0; j < nw; j++) {  // padding: column l, value 0
+        const uint32_t m = j < (int)rlen[(size_t)l] ? lists[(size_t)l][(size_t)j] : (uint32_t)l;
+        std::memcpy(rows.data() + ((size_t)l * nw + j) * es, &m, 4);
+      }
+    for (int64_t l = 0; l < nl; l++)
+      for (int slot = 0; slot < nslot; slot++) idx[(size_t)l * row + slot] = cellof[(size_t)l * row + slot];
+  }
+  c->ibm_nw = nw;
   c->nlag = nl;
   c->nshell = ns;
   auto up = [&](size_t off, const void *src, size_t bytes) {
@@ -800,6 +847,10 @@ static lbm_status build_ibm(lbm_ctx *c) {
   HIPCALL(up(c->L.shell_cell, all.data(), sizeof(uint32_t) * ns));
   HIPCALL(up(c->L.shell_rowptr, rowptr.data(), sizeof(uint32_t) * (ns + 1)));
   HIPCALL(up(c->L.shell_ent, ent.data(), sizeof(uint32_t) * rowptr[ns]));
+  if (!mv) {
+    HIPCALL(up(c->L.lag_nptr, rlen.data(), sizeof(uint32_t) * nl));
+    HIPCALL(up(c->L.lag_nrow, rows.data(), (size_t)nl * nw * (csize_of(c->p.storage) == 8 ? 16 : 8)));
+  }
   HIPCALL(up(c->L.misc + 64, c->lag_start.data(), sizeof(int64_t) * c->nsolid));
   HIPCALL(up(c->L.misc + 64 + 8 * (size_t)c->L.max_solids, c->lag_count.data(), sizeof(int64_t) * c->nsolid));
   HIPCALL(hipMemsetAsync(c->ws + c->L.fibm, 0, (size_t)3 * c->L.stride * csize_of(c->p.storage), c->stream));

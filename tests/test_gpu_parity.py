@@ -4,7 +4,8 @@ The oracle runs in both of its forms (tests/paired.py): the deviation form
 h = f - w at the bars below, and the literal form (the populations f as the
 equations write them, plain sums) at the same bars plus its own measured
 rounding (tests/test_oracle_forms.py): velocity + 2e-15 absolute, density and
-populations at least 5e-13 and 2e-13, force at least 1e-11 F_scale + 1e-12.
+populations at least 5e-13 and 2e-13, force at least 1e-11 F_scale + 1e-15
+per force term (link or point).
 
 Bars (stated per check):
 * bit-exact: streaming permutation (no relaxation), node classification,
@@ -24,7 +25,7 @@ import os
 import numpy as np
 import pytest
 
-from paired import LITERAL_FLOOR
+from paired import LITERAL_FLOOR, force_terms
 from paper_1906_05445_amd import workloads as W
 
 ORACLE_THREADS = min(16, os.cpu_count() or 1)
@@ -109,7 +110,8 @@ def _compare_fields_one(gpu, orc, tol_u, tol_rho, tol_f, rel_l2, floor_u=0.0):
 def _compare_forces(gpu, orc, g, tol):
     lit = getattr(orc, "lit", None)
     if lit is not None:  # the literal form: plain Eq. 17 sums, rounding floor measured
-        _compare_forces_one(gpu, lit, g, max(tol, LITERAL_FLOOR["F_rel"]), LITERAL_FLOOR["F_abs"])
+        _compare_forces_one(gpu, lit, g, max(tol, LITERAL_FLOOR["F_rel"]),
+                            LITERAL_FLOOR["F_abs_per_term"] * force_terms(orc))
     return _compare_forces_one(gpu, orc, g, tol)
 
 
