@@ -106,6 +106,7 @@ def lib():
         L.orc_set_form.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_form.argtypes = [ctypes.c_void_p]
         L.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_boundaries.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _d]
         L.orc_solid_state.argtypes = [ctypes.c_void_p, _d]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
@@ -258,6 +259,15 @@ class Oracle:
 
     def set_threads(self, n):
         lib().orc_set_threads(self._h, int(n))
+
+    BCS = {"periodic": 0, "slip": 1, "open": 2}
+
+    def set_boundaries(self, x="periodic", y="periodic", z="periodic", inflow=0.0):
+        """Domain boundaries of Sec. 3.4 per axis: "periodic", "slip" (stress-free planes
+        halfway outside the first and last layers) or, on x only, "open" (velocity inlet
+        `inflow` before x = 0, convective outflow at the last layer)."""
+        if lib().orc_set_boundaries(self._h, self.BCS[x], self.BCS[y], self.BCS[z], float(inflow)) != 0:
+            raise ValueError((x, y, z))
 
     def get_h(self):
         """Deviations h = f - w (exact in the "h" form)."""

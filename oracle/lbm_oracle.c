@@ -183,7 +183,17 @@ typedef struct orc {
   int stepped;
   int literal;   /* 1: f stores f_i; 0: f stores h_i = f_i - w_i */
   int nthreads;  /* threads of the per-cell loops */
+  /* domain boundaries per axis (Sec. 3.4): BC_PERIODIC, BC_SLIP (stress-free
+   * planes halfway outside the first and last node layers) or, on x only,
+   * BC_OPEN (velocity inlet halfway before x = 0, convective outflow at the
+   * last layer); Uin the inflow velocity; mir[a][i] the direction i with its
+   * axis-a component reversed */
+  int bc[3];
+  double Uin;
+  int mir[3][QMAX];
 } orc;
+
+enum { BC_PERIODIC = 0, BC_SLIP = 1, BC_OPEN = 2 };
 
 static void solid_node_output(struct orc *o);
 
@@ -374,9 +384,10 @@ static void default_rates(orc *o) {
 /* sgn*(x - p) <= 0.                                                         */
 /* ------------------------------------------------------------------------ */
 static void sep(const orc *o, const solid_t *s, double px, double py, double pz, double d[3]) {
-  d[0] = min_image(px - s->c[0], o->nx);
-  d[1] = min_image(py - s->c[1], o->ny);
-  d[2] = o->D == 2 ? 0.0 : min_image(pz - s->c[2], o->nz);
+  /* shortest periodic image along periodic axes; the plain difference along bounded ones */
+  d[0] = o->bc[0] == BC_PERIODIC ? min_image(px - s->c[0], o->nx) : px - s->c[0];
+  d[1] = o->bc[1] == BC_PERIODIC ? min_image(py - s->c[1], o->ny) : py - s->c[1];
+  d[2] = o->D == 2 ? 0.0 : (o->bc[2] == BC_PERIODIC ? min_image(pz - s->c[2], o->nz) : pz - s->c[2]);
   if (s->kind == K_CYLINDER) d[s->ax] = 0.0;
 }
 static int in_solid(const orc *o, const solid_t *s, int x, int y, int z) {
@@ -775,6 +786,16 @@ orc *orc_create(int lattice, int collision, int nx, int ny, int nz, double tau, 
   o->fibm = (double *)calloc(3 * o->N, sizeof(double));
   o->literal = 1;
   o->nthreads = 1;
+  for (int a = 0; a < 3; a++) {
+    o->bc[a] = BC_PERIODIC;
+    for (int i = 0; i < o->Q; i++)
+      for (int k = 0; k < o->Q; k++) {
+        int same = 1;
+        for (int b = 0; b < 3; b++) same &= o->e[k][b] == (b == a ? -o->e[i][b] : o->e[i][b]);
+        if (same) o->mir[a][i] = k;
+      }
+  }
+  o->Uin = 0.0;
   for (long n = 0; n < o->N; n++) {
     o->owner[n] = -1;
     o->rho_out[n] = 1.0;
@@ -1312,15 +1333,41 @@ static void one_step(orc *o) {
         s->kfirst = 0;
       }
     }
-  /* streaming (push); every target slot (i, x + e_i) has one source */
+  /* streaming (push); every target slot (i, x + e_i) has one source.  At the
+   * domain boundaries of Sec. 3.4 (bounded axes only):
+   *  - velocity inlet, a plane halfway before x = 0: a population that would
+   *    leave through it returns to its node reversed, with the wall term of
+   *    Eq. 10 for the inflow velocity (u_w = (Uin, 0, 0), rho0 = 1);
+   *  - outflow past the last x layer: the population leaves the domain (the
+   *    ones entering there are set by the convective condition below);
+   *  - stress-free planes halfway outside the first and last layers of y or z
+   *    (or x): specular reflection, the normal component reversed and the
+   *    population kept in its layer (zero normal velocity, zero normal
+   *    derivative of the tangential velocity). */
+  const int nb[3] = {o->nx, o->ny, o->nz};
 #pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++) {
     if (o->excl[n]) continue;
     int x, y, z;
     coords_of(o, n, &x, &y, &z);
+    const int c0[3] = {x, y, z};
     for (int i = 0; i < Q; i++) {
-      long m = cell_of(o, x + o->e[i][0], y + o->e[i][1], z + o->e[i][2]);
-      if (!o->excl[m]) o->fnew[(long)i * N + m] = o->fpost[(long)i * N + n];
+      int t[3], j = i;
+      for (int a = 0; a < 3; a++) t[a] = c0[a] + o->e[i][a];
+      if (o->bc[0] == BC_OPEN && t[0] < 0) {
+        const int ib = o->opp[i];
+        const double eu = (double)o->e[ib][0] * o->Uin;
+        o->fnew[(long)ib * N + n] = o->fpost[(long)i * N + n] + 6.0 * o->w[ib] * eu; /* 2 rho0 w e.u_w / c_s^2 */
+        continue;
+      }
+      if (o->bc[0] == BC_OPEN && t[0] >= o->nx) continue;
+      for (int a = 0; a < 3; a++)
+        if (o->bc[a] == BC_SLIP && (t[a] < 0 || t[a] >= nb[a])) {
+          t[a] = c0[a];
+          j = o->mir[a][j];
+        }
+      const long m = cell_of(o, t[0], t[1], t[2]);
+      if (!o->excl[m]) o->fnew[(long)j * N + m] = o->fpost[(long)i * N + n];
     }
   }
   /* interpolated bounce-back and momentum exchange (Eq. 10, 11, 12-14, 16, 17) */
@@ -1384,6 +1431,24 @@ static void one_step(orc *o) {
     for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = o->literal ? plain[k] : acc_get(&lacc[k]);
   free(lacc);
   free(plain);
+  /* convective outflow (Sec. 3.4): d(rho0 u)/dt + U_o d(rho0 u)/dx = 0 taken
+   * for the populations that enter the last layer from outside, first-order
+   * implicit in time and upwind in x:
+   *   f_i(N, t+1) = [f_i(N, t) + U_o f_i(N-1, t+1)] / (1 + U_o),
+   * U_o the streamwise velocity of the collision at (N, y, z) (not below 0) */
+  if (o->bc[0] == BC_OPEN) {
+    const int X = o->nx - 1;
+    for (int z = 0; z < o->nz; z++)
+      for (int y = 0; y < o->ny; y++) {
+        const long n = cell_of(o, X, y, z), m = cell_of(o, X - 1, y, z);
+        if (o->excl[n]) continue;
+        double Uo = o->u_out[n];
+        if (Uo < 0.0) Uo = 0.0;
+        for (int i = 0; i < Q; i++)
+          if (o->e[i][0] < 0)
+            o->fnew[(long)i * N + n] = (o->f[(long)i * N + n] + Uo * o->fnew[(long)i * N + m]) / (1.0 + Uo);
+      }
+  }
 #pragma omp parallel for num_threads(o->nthreads) schedule(static)
   for (long n = 0; n < N; n++)
     if (!o->excl[n])
@@ -1441,6 +1506,21 @@ void orc_set_form(orc *o, int literal) {
 }
 int orc_form(const orc *o) { return o->literal; }
 void orc_set_threads(orc *o, int n) { o->nthreads = n > 0 ? n : 1; }
+/* Domain boundaries (Sec. 3.4): per axis 0 periodic, 1 stress-free planes,
+ * 2 (x only) velocity inlet Uin before x = 0 and convective outflow at the
+ * last layer.  D2Q9 keeps z periodic.  Returns -1 for an invalid set. */
+int orc_set_boundaries(orc *o, int bcx, int bcy, int bcz, double Uin) {
+  const int b[3] = {bcx, bcy, bcz};
+  for (int a = 0; a < 3; a++) {
+    if (b[a] < BC_PERIODIC || b[a] > BC_OPEN) return -1;
+    if (b[a] == BC_OPEN && a != 0) return -1;
+  }
+  if (o->D == 2 && bcz != BC_PERIODIC) return -1;
+  if (bcx == BC_OPEN && o->nx < 2) return -1;
+  for (int a = 0; a < 3; a++) o->bc[a] = b[a];
+  o->Uin = Uin;
+  return 0;
+}
 void orc_get_rates(const orc *o, double *S) { memcpy(S, o->S, sizeof(double) * o->Q); }
 void orc_get_mrt(const orc *o, double *M, double *Minv) {
   for (int r = 0; r < o->Q; r++)
