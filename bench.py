@@ -52,9 +52,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+SWEEP_SOURCES = ("sweep_core.hpp", "kernels_sweep.hip", "lbm_ibb.hpp", "lbm_device.hpp", "lbm_args.hpp")
+
+
 def sweep_source_hash():
-    src = os.path.join(ROOT, "paper_1906_05445_amd", "csrc", "kernels_sweep.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the sweep kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1906_05445_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(key, cells):

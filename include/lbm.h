@@ -85,6 +85,22 @@ typedef enum {
   LBM_IBB_ZHAO_YONG = 5
 } lbm_boundary;
 typedef enum { LBM_SPHERE = 0, LBM_CYLINDER = 1, LBM_PLANE = 2 } lbm_solid_kind;
+/* Domain boundary of one axis (Sec. 3.4: the sphere in an open domain has a
+ * uniform inflow, stress-free sides and a convective outflow).
+ *   PERIODIC : the default.
+ *   SLIP     : stress-free planes halfway outside the first and last node
+ *              layers: a population that would cross one has its normal
+ *              component reversed and stays in its layer (zero normal
+ *              velocity, zero normal derivative of the tangential ones).
+ *   OPEN     : x only.  Velocity inlet halfway before x = 0: a population
+ *              that would leave there returns reversed with the wall term of
+ *              Eq. 10 for u_w = (inflow, 0, 0) and rho0 = 1.  Convective
+ *              outflow at the last layer x = nx - 1: a population entering it
+ *              from outside is f_i(t+1) = [f_i(t) + U_o f_i(nx-2, t+1)] /
+ *              (1 + U_o), U_o = max(u_x of that node's last collision, 0)
+ *              (the condition d f/dt + U_o d f/dx = 0, implicit in time,
+ *              upwind in x). */
+typedef enum { LBM_PERIODIC = 0, LBM_SLIP = 1, LBM_OPEN = 2 } lbm_domain;
 
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
@@ -99,16 +115,24 @@ typedef struct lbm_batch lbm_batch;
  *   body_force        : force density g added on the fluid region.
  *   body_force_fluid_only : 1 = g acts only on nodes outside every solid's
  *           volume (the setting Sec. 3.3 finds more accurate for IBM);
- *           0 = everywhere (IBB solid nodes never carry fluid). */
+ *           0 = everywhere (IBB solid nodes never carry fluid).
+ *   boundary : lbm_domain per axis (zero: periodic).  OPEN is allowed on x
+ *           only and needs nx >= 8; D2Q9 keeps z periodic.  A lattice with a
+ *           bounded axis takes fixed solids only, each at least 4 nodes clear
+ *           of every bounded face (lbm_set_solids), and is not admitted to a
+ *           batch.
+ *   inflow : inflow velocity U_in of an OPEN x axis (|U_in| < 0.3). */
 typedef struct {
   int32_t lattice;    /* lbm_lattice */
   int32_t collision;  /* lbm_collision */
   int32_t storage;    /* lbm_storage */
-  int32_t nx, ny, nz; /* all axes periodic; nz == 1 for D2Q9 */
+  int32_t nx, ny, nz; /* nz == 1 for D2Q9 */
   double tau;
   const double *rates;
   double body_force[3];
   int32_t body_force_fluid_only;
+  int32_t boundary[3]; /* lbm_domain per axis */
+  double inflow;
 } lbm_params;
 
 /* A rigid solid.  Sphere: centre, radius (in 2D a circle).  Cylinder: axis
@@ -211,6 +235,10 @@ size_t lbm_noalloc_capacity(void);
  * unit area; circles / rings of spacing about 1; Sec. 3.1 places the points
  * R_d inside the surface), unless points are given afterwards with
  * lbm_set_lagrangian.  opts may be NULL (5 iterations, no retraction).
+ * On a lattice with a bounded axis (lbm_params.boundary) the solids are
+ * fixed (velocity and rotation zero, no free motion: else LBM_EUNSUPPORTED)
+ * and each keeps 4 nodes between its surface and every bounded face:
+ * centre +- (radius + 4) within [0, n - 1] on that axis (else LBM_EINVAL).
  * Errors: LBM_EINVAL and LBM_EUNSUPPORTED leave the context as it was;
  * after LBM_ENOMEM (too many links or points) the context has no solids. */
 lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t method, const lbm_ibm_opts *opts);
@@ -286,7 +314,10 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *f);
 lbm_status lbm_set_equilibrium(lbm_ctx *c, double rho, const double *u);
 
 /* Raw deviations f_i - w_i before the next collision, [Q][N] in the storage
- * format (double, float or IEEE half), bit for bit. */
+ * format (double, float or IEEE half), bit for bit.  With an OPEN x axis the
+ * populations entering at the inlet are given without the inlet term of
+ * Eq. 10 (6 w_i e_ix U_in), which the next collision adds: the raw state is
+ * what is stored, so that a restore is exact. */
 lbm_status lbm_get_state(lbm_ctx *c, void *host);
 lbm_status lbm_set_state(lbm_ctx *c, const void *host);
 

@@ -490,6 +490,8 @@ lbm_status lbm_batch_admit(lbm_batch *b, const lbm_params *p, int32_t max_solids
     return berr(b, LBM_EINVAL, "lattice and storage must match the batch");
   const size_t need = lbm_workspace_bytes(p, max_solids, max_links, max_lagrangian);
   if (!need) return berr(b, LBM_EINVAL, "invalid lattice parameters");
+  if (p->boundary[0] != BND_PERIODIC || p->boundary[1] != BND_PERIODIC || p->boundary[2] != BND_PERIODIC)
+    return berr(b, LBM_EUNSUPPORTED, "batches take periodic lattices");
   int slot = -1;
   for (int k = 0; k < b->max_slots; k++)
     if (!b->mem[(size_t)k].c) {

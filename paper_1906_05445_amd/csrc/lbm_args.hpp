@@ -76,6 +76,9 @@ struct SweepArgs {
   uint32_t iblocks;      // next blocks: IBM force/torque of this step, one per solid
   IbmFtArgs ift;
   uint32_t xcd;          // 1: blocks take tiles in XCD-contiguous order
+  int32_t bc[3];         // domain boundaries per axis (BND_*), bounded-domain sweeps only
+  double uin;            // inflow velocity of an open x axis
+  void *uo;              // [ny nz] compute type: u_x of the last x layer's collisions (open x)
 };
 
 // Bounce-back of the previous step applied inside the sweep (fixed solids).
@@ -215,6 +218,9 @@ struct CellArgs {
   uint32_t N, nx, ny, nz;
   FastDiv fx, fy;
   uint64_t stride;
+  int32_t bnd;     // some axis is not periodic: gathers follow bnd_src
+  int32_t bc[3];   // domain boundaries per axis (BND_*)
+  double uin;      // inflow velocity of an open x axis
 };
 
 // Macroscopic-field kernel arguments.
@@ -350,6 +356,9 @@ struct BatchLaunch {
 
 // argument blocks of a context (host)
 void fill_sweep_args(lbm_ctx *c, SweepArgs *a);
+// kernels_sweep_bnd.hip: the sweep on a domain with bounded axes
+void launch_sweep_bnd(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, const SweepLinkArgs &la, int coll,
+                      int inl, hipEvent_t e0, hipEvent_t e1);
 void fill_macro_args(lbm_ctx *c, MacroArgs *m, int mode);
 void fill_ibb_args(lbm_ctx *c, IbbArgs *a);
 void fill_link_args(lbm_ctx *c, LinkArgs *a);

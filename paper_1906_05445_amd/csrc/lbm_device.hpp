@@ -155,6 +155,80 @@ __host__ __device__ inline uint64_t pidx_rt(int Q, int i, uint32_t n) {
 }
 
 // ----------------------------------------------------------------------------
+// domain boundaries (Sec. 3.4)
+// ----------------------------------------------------------------------------
+// Per axis: periodic; stress-free planes halfway outside the first and last
+// node layers (specular reflection: the normal component of a population
+// that would cross one is reversed and it stays in its layer); or, on x only,
+// a velocity inlet halfway before x = 0 (bounce-back with the inflow velocity
+// as wall velocity, the form of Eq. 10) and a convective outflow at the last
+// layer.
+enum : int32_t { BND_PERIODIC = 0, BND_SLIP = 1, BND_OPEN = 2 };
+
+// Direction i with its components on the axes of mask m (bit a: axis a) reversed.
+template <int Q>
+__host__ __device__ constexpr int dir_flip(int i, int m) {
+  const int ex = (m & 1) ? -Lat<Q>::ex(i) : Lat<Q>::ex(i);
+  const int ey = (m & 2) ? -Lat<Q>::ey(i) : Lat<Q>::ey(i);
+  const int ez = (m & 4) ? -Lat<Q>::ez(i) : Lat<Q>::ez(i);
+  for (int k = 0; k < Q; k++)
+    if (Lat<Q>::ex(k) == ex && Lat<Q>::ey(k) == ey && Lat<Q>::ez(k) == ez) return k;
+  return i;
+}
+
+// Where the population of direction e = (ex, ey, ez) that arrives at node
+// (x, y, z) is kept in the pull form (the stored array holds each node's
+// post-collision values in its own slots).  Inside the domain, and across a
+// periodic axis: node x - e, same direction.  Across a stress-free plane:
+// the node's own layer on that axis, the direction mirrored on it (flip).
+// Before the inlet or past the outlet (open): the node's own slot of the
+// reverse direction -- at the inlet the reflected post-collision value, to
+// which the inlet term 6 w_i e_ix U_in is added; at the outlet the value the
+// convective outflow condition set there after the previous sweep (the
+// reverse direction leaves the domain, so no node pulls that slot).
+struct BndSrc {
+  uint32_t cell;
+  int flip;
+  bool open, inlet;
+};
+__device__ __forceinline__ BndSrc bnd_src(int ex, int ey, int ez, int x, int y, int z, int nx, int ny, int nz,
+                                          const int32_t *bc) {
+  const bool ox = ex != 0 && bc[0] != BND_PERIODIC && (ex > 0 ? x == 0 : x == nx - 1);
+  const bool oy = ey != 0 && bc[1] != BND_PERIODIC && (ey > 0 ? y == 0 : y == ny - 1);
+  const bool oz = ez != 0 && bc[2] != BND_PERIODIC && (ez > 0 ? z == 0 : z == nz - 1);
+  BndSrc s;
+  s.open = ox && bc[0] == BND_OPEN;
+  s.inlet = s.open && ex > 0;
+  if (s.open) {
+    s.cell = (uint32_t)x + (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
+    s.flip = 0;
+    return s;
+  }
+  int sx = ox ? x : x - ex, sy = oy ? y : y - ey, sz = oz ? z : z - ez;
+  sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+  sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+  sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+  s.cell = (uint32_t)sx + (uint32_t)nx * ((uint32_t)sy + (uint32_t)ny * (uint32_t)sz);
+  s.flip = (ox ? 1 : 0) | (oy ? 2 : 0) | (oz ? 4 : 0);
+  return s;
+}
+// Slot direction of bnd_src for direction i of a compile-time lattice (i a
+// constant after unrolling: every candidate folds to a constant).
+template <int Q>
+__device__ __forceinline__ int bnd_dir(int i, const BndSrc &s) {
+  if (s.open) return opp(i);
+  const int f = s.flip;
+  return f == 0 ? i
+       : f == 1 ? dir_flip<Q>(i, 1)
+       : f == 2 ? dir_flip<Q>(i, 2)
+       : f == 3 ? dir_flip<Q>(i, 3)
+       : f == 4 ? dir_flip<Q>(i, 4)
+       : f == 5 ? dir_flip<Q>(i, 5)
+       : f == 6 ? dir_flip<Q>(i, 6)
+                : dir_flip<Q>(i, 7);
+}
+
+// ----------------------------------------------------------------------------
 // node flags
 // ----------------------------------------------------------------------------
 enum : uint8_t {

@@ -12,6 +12,8 @@
 // floating-point contraction, so they produce the same bits.
 #pragma once
 
+#include <cstddef>
+
 #include "lbm_geom.hpp"
 
 namespace lbm {
@@ -177,15 +179,23 @@ __device__ inline void link_ft(double hin, double hout, const double a[3], const
 // Tabulated part of a link of a fixed solid, as the sweep reads it (48 bytes
 // for FP32 and FP16 storage, 64 for FP64), stored in sweep-segment order.
 // B holds the scaled wall term (link_wall).
+// The four words that address the link's loads (n, nff, nfff, kind_dir) come
+// first after the coefficients, 16-byte aligned, so that the sweep can fetch
+// them in one load before its own pulls (LinkRec::head).
 template <typename C>
 struct alignas(16) LinkRec {
   C k1, k2, k3, B;
-  uint32_t n, nb, nff, nfff;  // x_f, x_b, x_ff, x_fff
-  uint32_t kind_dir;          // kind | i << 8
-  uint32_t l;                 // link index (order of the force sums)
+  uint32_t n, nff, nfff;  // x_f, x_ff, x_fff
+  uint32_t kind_dir;      // kind | i << 8
+  uint32_t nb;            // x_b
+  uint32_t l;             // link index (order of the force sums)
   C k4;
+  __device__ static uint4 head(const LinkRec *r) { return *reinterpret_cast<const uint4 *>(&r->n); }
 };
 static_assert(sizeof(LinkRec<float>) == 48 && sizeof(LinkRec<double>) == 64, "link record size");
+static_assert(offsetof(LinkRec<float>, n) % 16 == 0 && offsetof(LinkRec<double>, n) % 16 == 0 &&
+                  offsetof(LinkRec<float>, kind_dir) == offsetof(LinkRec<float>, n) + 12,
+              "link record head");
 
 // Chunk partials from tabulated links: the same per-link terms, summed over
 // the same 64 lanes in the same order, as the bounce-back kernel forms from

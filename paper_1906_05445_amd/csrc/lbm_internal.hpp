@@ -54,7 +54,7 @@ struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
       partials, partials2, seg_link, cell_list, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
       lag_Fk, lag_Fk2, lag_Ut, lag_nptr, lag_nrow, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f,
-      refill, misc, total;
+      refill, uo, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials, max_refill;
   int32_t max_solids;
@@ -201,6 +201,11 @@ struct lbm_ctx {
 
 namespace lbm {
 
+// some axis is not periodic (lbm_params.boundary)
+inline bool bounded(const lbm_ctx *c) {
+  return c->p.boundary[0] != BND_PERIODIC || c->p.boundary[1] != BND_PERIODIC || c->p.boundary[2] != BND_PERIODIC;
+}
+
 int collision_kind(const lbm_ctx *c, double *sp = nullptr, double *sm = nullptr);
 lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 
@@ -214,6 +219,10 @@ lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                   int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
+// kernels_sweep_bnd.hip: bounded domains (lbm_params.boundary)
+void launch_outflow(lbm_ctx *c, const void *A, void *B);
+void launch_transfer_bnd(lbm_ctx *c, int dir, const double *f, void *A, bool encode, bool raw);
+void launch_bnd_uniform(lbm_ctx *c, void *A, const double *h);
 void launch_decode_gather(lbm_ctx *c, int dir, const void *A, double *dst, bool raw);
 void launch_refill_count(lbm_ctx *c, int64_t t, void *post);
 void launch_ft_reduce_free(lbm_ctx *c, int64_t t);

@@ -72,6 +72,14 @@ bool valid_params(const lbm_params *p) {
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
   for (int k = 0; k < 3; k++)
     if (!std::isfinite(p->body_force[k])) return false;
+  // domain boundaries (Sec. 3.4): OPEN on x only, D2Q9 keeps z periodic
+  for (int k = 0; k < 3; k++) {
+    if (p->boundary[k] < BND_PERIODIC || p->boundary[k] > BND_OPEN) return false;
+    if (p->boundary[k] == BND_OPEN && k != 0) return false;
+  }
+  if (p->lattice == LBM_D2Q9 && p->boundary[2] != BND_PERIODIC) return false;
+  if (p->boundary[0] == BND_OPEN && p->nx < 8) return false;
+  if (!std::isfinite(p->inflow) || std::fabs(p->inflow) >= 0.3) return false;
   return true;
 }
 
@@ -156,6 +164,7 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.shell_f = take((size_t)3 * l.max_shell * cs);
   l.max_refill = std::max<int64_t>(4096, N / 16);
   l.refill = take((size_t)l.max_refill * 8);
+  l.uo = take(p->boundary[0] == BND_OPEN ? (size_t)p->ny * p->nz * cs : 0);
   l.misc = take((size_t)64 + 16 * (size_t)max_solids + 64);
   l.total = o;
   *L = l;
@@ -382,6 +391,12 @@ static lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const Layout &L, voi
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner0, 0xFF, (size_t)c->N * 2, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.owner1, 0xFF, (size_t)c->N * 2, c->stream);
+  if (e == hipSuccess && bounded(c)) {
+    // the rest state f = w: the inlet slots hold its values less the inlet term
+    const double zero[kMaxQ] = {};
+    launch_bnd_uniform(c, c->state(), zero);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
@@ -554,6 +569,19 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
       d.cp[a] = d.c0[a];
       d.Up[a] = d.U[a];
       d.Wp[a] = d.W[a];
+    }
+    if (bounded(c)) {
+      // fixed spheres and cylinders along periodic axes, clear of the bounded faces
+      if (d.moving || d.free || q.kind == LBM_PLANE || q.inverted ||
+          (q.kind == LBM_CYLINDER && c->p.boundary[ax] != BND_PERIODIC))
+        return set_err(c, "a bounded domain takes fixed spheres and cylinders along periodic axes"),
+               LBM_EUNSUPPORTED;
+      const int nn[3] = {c->p.nx, c->p.ny, c->p.nz};
+      for (int a = 0; a < c->D; a++) {
+        if (c->p.boundary[a] == BND_PERIODIC || (q.kind == LBM_CYLINDER && a == ax)) continue;
+        if (!(q.centre[a] - q.radius - 4.0 >= 0.0 && q.centre[a] + q.radius + 4.0 <= nn[a] - 1.0))
+          return set_err(c, "a solid must stay 4 nodes clear of the bounded faces"), LBM_EINVAL;
+      }
     }
     if (d.moving && q.kind == LBM_PLANE)
       return set_err(c, "translating solids need a sphere or cylinder"), LBM_EUNSUPPORTED;
@@ -888,6 +916,14 @@ lbm_status lbm_set_lagrangian(lbm_ctx *c, int32_t solid, const double *X, int64_
   }
   for (double v : NX)
     if (!std::isfinite(v)) return set_err(c, "non-finite Lagrangian point"), LBM_EINVAL;
+  if (bounded(c)) {
+    // the delta kernel's support (two nodes either side) stays off the bounded faces
+    const int nn[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int64_t l = 0; l < n; l++)
+      for (int a = 0; a < c->D; a++)
+        if (c->p.boundary[a] != BND_PERIODIC && !(X[3 * l + a] >= 3.0 && X[3 * l + a] <= nn[a] - 4.0))
+          return set_err(c, "a Lagrangian point must stay 3 nodes clear of the bounded faces"), LBM_EINVAL;
+  }
   c->lag_X = NX;
   c->lag_dV = NdV;
   c->lag_start = st;
@@ -1004,6 +1040,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   // Zhao-Yong (x_f only) is evaluated by the sweep of its own step, every step of
   // the call; the other schemes by the sweep of the next step, steps 2..n
   const bool zy = inl && c->method == LBM_IBB_ZHAO_YONG;
+  // convective outflow (Sec. 3.4) after each sweep
+  const bool open_x = c->p.boundary[0] == BND_OPEN;
   if (inl && (nsteps > 1 || (zy && nsteps > 0))) launch_link_table(c);
   bool span = false;  // a profiling span over the sweeps of this call is open
   for (int64_t k = 0; k < nsteps; k++) {
@@ -1041,6 +1079,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       // the sweep evaluates this step's links after relaxing; its leading blocks
       // form the chunk partials of step t - 1 and the sums of step t - 2
       launch_sweep(c, A, B, policy, e0, e1, k >= 2 ? c->t - 2 : -1, -1, c->t, k >= 1 ? c->t - 1 : -1);
+      if (open_x) launch_outflow(c, A, B);
       if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
       if (span && k == nsteps - 1) HIPCALL(hipEventRecord(c->prof_events.back().e1, c->stream));
       c->cur ^= 1;
@@ -1055,6 +1094,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       // leading blocks (the last steps are finished after the loop)
       launch_sweep(c, A, B, policy, e0, e1, k >= 3 ? c->t - 3 : -1, -1, k >= 1 ? c->t - 1 : -1,
                    k >= 2 ? c->t - 2 : -1);
+      if (open_x) launch_outflow(c, A, B);
       if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
       if (span && k == nsteps - 1) HIPCALL(hipEventRecord(c->prof_events.back().e1, c->stream));
       c->cur ^= 1;
@@ -1066,6 +1106,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     // launch (translating solids rebuild the link table first, so they reduce at once)
     const bool fused_reduce = ibb && k > 0 && !c->any_moving;
     launch_sweep(c, A, B, policy, e0, e1, fused_reduce ? c->t - 1 : -1, ibm && !c->ibm_free ? c->t : -1);
+    if (open_x) launch_outflow(c, A, B);
     if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
     if (ibb) {
       launch_ibb(c, B, A, c->t);
@@ -1298,6 +1339,7 @@ lbm_status lbm_set_equilibrium(lbm_ctx *c, double rho, const double *u) {
     h[i] = w * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
   }
   launch_fill_uniform(c, c->state(), h);
+  if (bounded(c)) launch_bnd_uniform(c, c->state(), h);
   HIPCALL(hipGetLastError());
   HIPCALL(hipStreamSynchronize(c->stream));
   c->fresh = true;

@@ -78,3 +78,25 @@ def test_declarations_cite_the_paper():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
     missing = [n for n in CITED if not re.search(r"(Eq\.|Sec\.|Fig\.|App\.)\s*\d", _comment_before(src, n))]
     assert not missing, missing
+
+
+def test_domain_boundaries_validate():
+    """Domain boundaries (Sec. 3.4): open on x only, D2Q9 keeps z periodic, an
+    open x axis needs nx >= 8 and |inflow| < 0.3; the outlet plane's buffer is
+    part of the workspace."""
+    from paper_1906_05445_amd import lbm
+
+    def nbytes(lat, shape, bnd, inflow=0.0):
+        p, _ = lbm.make_params(lat, "MRT", "F32", shape, 0.8, boundary=bnd, inflow=inflow)
+        return lbm._lib.lbm_workspace_bytes(ctypes.byref(p), 1, 0, 0)
+
+    per = nbytes("D3Q19", (32, 24, 20), ("periodic", "periodic", "periodic"))
+    assert per > 0
+    assert nbytes("D3Q19", (32, 24, 20), ("slip", "slip", "slip")) == per
+    assert nbytes("D3Q19", (32, 24, 20), ("open", "slip", "slip"), 0.05) >= per + 24 * 20 * 4
+    assert nbytes("D3Q19", (32, 24, 20), ("periodic", "open", "periodic")) == 0
+    assert nbytes("D3Q19", (32, 24, 20), ("periodic", "periodic", "open")) == 0
+    assert nbytes("D3Q19", (7, 24, 20), ("open", "slip", "slip")) == 0
+    assert nbytes("D3Q19", (32, 24, 20), ("open", "slip", "slip"), 0.3) == 0
+    assert nbytes("D2Q9", (32, 24, 1), ("open", "slip", "periodic"), 0.05) > 0
+    assert nbytes("D2Q9", (32, 24, 1), ("open", "slip", "slip")) == 0
