@@ -45,7 +45,7 @@ TUNER_STEPS = 64
 # extra runs record HIP events around every PROFILE_EVERY-th sweep launch where the
 # sweeps of a call are not back to back (events on every launch add work to each step)
 PROFILE_EVERY = 8
-ALL_EXTRAS = ("single", "schemes", "copy", "batch", "precision", "serving", "cpu")
+ALL_EXTRAS = ("single", "schemes", "open", "copy", "batch", "precision", "serving", "cpu")
 
 
 def log(msg):
@@ -86,8 +86,11 @@ def run_case(case, steps, warmup, key, torch, lbm, rates=None):
     around the sweep launches (sweep-kernel time)."""
     Q = 19 if case.lattice == "D3Q19" else 9
     gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, g=case.g, rates=rates,
-                      g_fluid_only=case.g_fluid_only, max_solids=max(1, len(case.solids)))
+                      g_fluid_only=case.g_fluid_only, max_solids=max(1, len(case.solids)),
+                      boundary=case.boundary, inflow=case.inflow)
     gpu.set_solids(case.solids, case.method, n_iter=case.ibm_iters, retraction=case.retraction, delta=case.delta)
+    if case.inflow:
+        gpu.set_equilibrium(1.0, (case.inflow, 0.0, 0.0))
     N = gpu.N
     w = max(warmup, TUNER_STEPS)
     gpu.step(w)
@@ -115,7 +118,7 @@ def run_case(case, steps, warmup, key, torch, lbm, rates=None):
     fluid = types != 1
     nfluid = int(fluid.sum())
     re_at_end = None
-    if case.meta.get("Re") is not None and case.solids:
+    if case.meta.get("Re") is not None and case.solids and not case.inflow:
         # superficial velocity (mean fluid velocity x fluid fraction) over the diameter and viscosity
         nu = (case.tau - 0.5) / 3.0
         gdir = int(np.argmax(np.abs(case.g)))
@@ -174,6 +177,44 @@ def copy_probe(torch, lbm, nbytes=4 << 30, reps=20, warm=3):
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def run_open_sphere(torch, lbm, W, steps, chunk=1000, **kw):
+    """The sphere of Sec. 3.4 (uniform inflow, stress-free sides, convective outflow) from a uniform
+    stream: whole-step throughput, and the drag coefficient at the end with its change over the last
+    chunk, beside the standard correlation (a sanity reference)."""
+    case = W.open_sphere(**kw)
+    gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, max_solids=1,
+                      boundary=case.boundary, inflow=case.inflow)
+    gpu.set_solids(case.solids, case.method)
+    gpu.set_equilibrium(1.0, (case.inflow, 0.0, 0.0))
+    gpu.step(TUNER_STEPS)
+    torch.cuda.synchronize()
+    nu = (case.tau - 0.5) / 3.0
+    Re = case.meta["Re"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cd = []
+    ms = 0.0
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        e0.record(gpu.stream)
+        gpu.step(k)
+        e1.record(gpu.stream)
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += k
+        cd.append(W.drag_coefficient(float(gpu.force_torque()[0, 0]), Re, nu))
+    ok = gpu.check()
+    gpu.close()
+    N = case.shape[0] * case.shape[1] * case.shape[2]
+    ref = W.schiller_naumann(Re)
+    return {"workload": case.name, "shape": list(case.shape), "D": case.meta["D"], "Re": Re, "U_in": case.inflow,
+            "tau": case.tau, "method": case.method, "storage": case.storage, "steps": done,
+            "mlups": N * done / (ms / 1e3) / 1e6, "finite": bool(ok),
+            "C_D": cd[-1], "C_D_rel_change_last_chunk": abs(cd[-1] - cd[-2]) / abs(cd[-1]) if len(cd) > 1 else None,
+            "C_D_history_per_chunk": [round(x, 5) for x in cd], "chunk": chunk,
+            "C_D_schiller_naumann": ref, "rel_diff_to_correlation": cd[-1] / ref - 1.0}
 
 
 def run_batch(torch, lbm, W, steps, warmup, count=512):
@@ -344,10 +385,11 @@ def main():
     ap.add_argument("--extras-out", default=os.path.join("gpurun_out", "bench_extras.json"))
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the 512-lattice batch")
     ap.add_argument("--precision-steps", type=int, default=10000, help="steps of the FP32/FP16 vs FP64 comparison")
-    ap.add_argument("--serve-seconds", type=float, default=240.0, help="limit of the saturated serving window")
+    ap.add_argument("--serve-seconds", type=float, default=200.0, help="limit of the saturated serving window")
     ap.add_argument("--serve-min", type=int, default=32, help="completions that end the saturated window")
-    ap.add_argument("--serve-cap", type=int, default=30000,
+    ap.add_argument("--serve-cap", type=int, default=60000,
                     help="step cap of a solve (a capped solve is reported as capped, with its drag at the cap)")
+    ap.add_argument("--open-steps", type=int, default=20000, help="steps of the open-domain sphere (Sec. 3.4)")
     ap.add_argument("--cpu-steps", default="1,3", help="oracle sample: steps on one thread, steps on all threads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -415,6 +457,16 @@ def main():
             continue
         r = run_case(ctor(storage="F32", **kw), k2, Wm, key, torch, lbm)
         extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+    if "open" in want and args.open_steps > 0:
+        # Sec. 3.4's sphere, D = 16 (Zhao-Yong's sufficient resolution is about 14 at Re_p = 20)
+        op = run_open_sphere(torch, lbm, W, args.open_steps)
+        extra("open_sphere_re20_f32_zhao_yong", op,
+              f"{op['mlups']:.0f} MLUPS, C_D {op['C_D']:.4f} (change {op['C_D_rel_change_last_chunk']:.1e} over the "
+              f"last {op['chunk']} steps; Schiller-Naumann {op['C_D_schiller_naumann']:.4f})")
+        key = "open_sphere_f32_quadratic"
+        if wanted("open", key):
+            r = run_case(W.open_sphere(method="QUADRATIC"), k2, Wm, key, torch, lbm)
+            extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
     if "copy" in want:
         c = copy_probe(torch, lbm)
         extra("hbm_copy_GBps", c, f"{c:.0f} GB/s")

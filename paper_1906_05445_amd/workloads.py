@@ -166,6 +166,8 @@ class Case:
     meta: dict = field(default_factory=dict)
     delta: int = 4
     g_fluid_only: bool = True
+    boundary: tuple = ("periodic", "periodic", "periodic")
+    inflow: float = 0.0
 
 
 def cylinder_channel_2d(n=64, R=8.3, centre=(32.4, 31.7), g=1e-6, tau=0.8, steps=2000, method="LINEAR"):
@@ -202,6 +204,30 @@ def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, st
     return Case(f"settle_{n}", "D3Q19", "MRT", (n, n, n), tau, (0.0, 0.0, g_fluid),
                 [solid("sphere", c, R, density=density, gravity=(0.0, 0.0, gz))], method, steps, storage,
                 meta={"U_set": U_set, "density": density}, g_fluid_only=not ibm)
+
+
+def open_sphere(D=16.0, Re=20.0, U=0.05, method="ZHAO_YONG", storage="F32", steps=20000, seed=6):
+    """The sphere of Sec. 3.4: diameter D fixed at (6D, 6D, 6D) (plus a seed-drawn sub-node offset) in a
+    24D x 12D x 12D box, uniform inflow U at x = 0, stress-free sides, convective outflow; nu from
+    Re_p = U D / nu.  D3Q19 MRT."""
+    rng = np.random.default_rng(seed)
+    n = (int(round(24 * D)), int(round(12 * D)), int(round(12 * D)))
+    c = np.array([6 * D, 6 * D, 6 * D]) + 0.5 * rng.random(3)
+    nu = U * D / Re
+    return Case(f"open_sphere_D{D:g}_Re{Re:g}", "D3Q19", "MRT", n, tau_of_nu(nu), (0.0, 0.0, 0.0),
+                [solid("sphere", c, D / 2.0)], method, steps, storage, meta={"Re": Re, "U_ref": U, "D": D},
+                boundary=("open", "slip", "slip"), inflow=U)
+
+
+def drag_coefficient(F, Re, nu):
+    """C_D = 8 F_D / (rho_f Re_p^2 pi nu^2) (Sec. 3.4), rho_f = 1."""
+    return 8.0 * F / (Re * Re * math.pi * nu * nu)
+
+
+def schiller_naumann(Re):
+    """Standard drag correlation of a sphere, C_D = 24/Re (1 + 0.15 Re^0.687) (Re < 800): a sanity
+    reference, not the paper's data."""
+    return 24.0 / Re * (1.0 + 0.15 * Re ** 0.687)
 
 
 def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, storage="F64", steps=10000,
