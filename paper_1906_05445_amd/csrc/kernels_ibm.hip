@@ -294,6 +294,33 @@ __device__ inline void ibm_iter_body(const IbmArgs &a, int it, int64_t l) {
   Fc[l] = F;
 }
 
+// The iterations in one pass: with F^(k+1) = F^k - A F^k (Eq. 7 after the
+// point-space update), the summed force is sum_{k < n_iter} (I - A)^k F^0 =
+// P F^0, and P, a polynomial in A, is formed once per set of fixed points
+// (host, FP64).  Row l of P (nptr[l] entries, fixed row stride nw) times the
+// first iteration's forces, one wavefront per point, the lane products summed
+// in FP64 in a fixed order.
+template <typename C>
+__device__ inline void ibm_psum_body(const IbmArgs &a, int64_t l) {
+#pragma clang fp contract(off)
+  const int lane = (int)(threadIdx.x & 63);
+  if (l >= a.nlag) return;
+  const IbmF4<C> *F0 = static_cast<const IbmF4<C> *>(a.Fk);
+  const IbmEntry<C> *row = static_cast<const IbmEntry<C> *>(a.nrow) + l * a.nw;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int len = (int)a.nptr[l];
+  for (int j = lane; j < len; j += 64) {
+    const IbmEntry<C> e = row[j];
+    const IbmF4<C> F = F0[e.col];
+    acc[0] = acc[0] + (double)(e.val * F.x);
+    acc[1] = acc[1] + (double)(e.val * F.y);
+    acc[2] = acc[2] + (double)(e.val * F.z);
+  }
+  for (int k = 0; k < 3; k++) acc[k] = wave_sum(acc[k]);
+  if (lane == 0)
+    for (int k = 0; k < 3; k++) a.Fsum[l * 3 + k] = acc[k];
+}
+
 // Setup: the values of row l of A (one wavefront per point, one entry per
 // lane; the padding keeps value 0).
 template <typename C>
@@ -495,6 +522,10 @@ __global__ __launch_bounds__(256) void k_ibm_spread_sum(IbmArgs a) {
   ibm_spread_sum_body<C>(a, (int64_t)blockIdx.x * kSpreadCellsPerBlock + (threadIdx.x / kSpreadLanes));
 }
 template <typename C>
+__global__ __launch_bounds__(256) void k_ibm_psum(IbmArgs a) {
+  ibm_psum_body<C>(a, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
+}
+template <typename C>
 __global__ __launch_bounds__(256) void k_ibm_amat(IbmArgs a) {
   ibm_amat_body<C>(a, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
@@ -521,7 +552,9 @@ __global__ __launch_bounds__(256) void k_ibm_iter_batch(const BatchSlot *__restr
   batch_units(wl, 0, [&](int m, uint32_t u) {
     if (it < SLOT(m, n_iter)) {
       const IbmArgs a = SLOT(m, im);
-      ibm_iter_body<C>(a, it, (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6));
+      const int64_t l = (int64_t)u * kIbmPointsPerBlock + (threadIdx.x >> 6);
+      if (!a.poly) ibm_iter_body<C>(a, it, l);
+      else if (it == 1) ibm_psum_body<C>(a, l);  // all iterations in one product
     }
   });
 }
@@ -579,6 +612,7 @@ static IbmArgs ibm_args(lbm_ctx *c, int64_t t) {
   a.nptr = c->at<uint32_t>(c->L.lag_nptr);
   a.nrow = c->ws + c->L.lag_nrow;
   a.nw = c->ibm_nw;
+  a.poly = c->ibm_poly ? 1 : 0;
   a.Ut = c->ws + c->L.lag_Ut;
   a.Fk2 = c->ws + c->L.lag_Fk2;
   return a;
@@ -626,7 +660,10 @@ static void ibm_step_t(lbm_ctx *c, const void *A, int64_t t, bool with_ft) {
     hipLaunchKernelGGL((k_ibm_interp0<9, S>), gl, dim3(256), 0, c->stream, static_cast<const S *>(A), a);
   else
     hipLaunchKernelGGL((k_ibm_interp0<19, S>), gl, dim3(256), 0, c->stream, static_cast<const S *>(A), a);
-  for (int it = 1; it < c->n_iter; it++) hipLaunchKernelGGL(k_ibm_iter<C>, gl, dim3(256), 0, c->stream, a, it);
+  if (c->ibm_poly) {
+    if (c->n_iter > 1) hipLaunchKernelGGL(k_ibm_psum<C>, gl, dim3(256), 0, c->stream, a);
+  } else
+    for (int it = 1; it < c->n_iter; it++) hipLaunchKernelGGL(k_ibm_iter<C>, gl, dim3(256), 0, c->stream, a, it);
   hipLaunchKernelGGL(k_ibm_spread_sum<C>, gsp, dim3(256), 0, c->stream, a);
   if (with_ft)
     hipLaunchKernelGGL(k_ibm_ft, dim3((uint32_t)c->nsolid), dim3(kBlock), 0, c->stream, ibm_ft_args_of(c, t));

@@ -143,6 +143,7 @@ struct IbmArgs {
   const uint32_t *nptr;
   void *nrow;
   int nw;
+  int poly;  // the rows hold P (one product replaces the iterations), else A
   void *Ut;
   void *Fk2;
 };

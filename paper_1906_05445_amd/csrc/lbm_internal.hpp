@@ -161,7 +161,10 @@ struct lbm_ctx {
   double retraction;
   int64_t nlag;
   int64_t nshell;
-  int ibm_nw;  // width of a row of the point coupling (64 or 128; fixed IBM solids)
+  int ibm_nw;  // row stride of the point coupling (fixed IBM solids)
+  // the rows hold P = sum_{k < n_iter} (I - A)^k instead of A: the iterations
+  // run as one product (single contexts whose P fits the row capacity)
+  bool ibm_poly = false;
   std::vector<int64_t> lag_start, lag_count;
   std::vector<double> lag_X, lag_dV;
   bool lag_user;

@@ -496,6 +496,7 @@ lbm_status lbm_profile_read(lbm_ctx *c, double *sweep_ms, int64_t *launches) {
 }
 
 static lbm_status build_ibm(lbm_ctx *c);
+static lbm_status ibm_polynomial(lbm_ctx *c, const std::vector<uint32_t> &rlen);
 static lbm_status clear_solids(lbm_ctx *c, lbm_status st);
 
 static bool coord_axis(const double a[3], int *ax, int *sg) {
@@ -685,6 +686,7 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
   c->link_stride = 0;
   c->nlag = 0;
   c->nshell = 0;
+  c->ibm_poly = false;
   c->lag_user = false;
   HIPCALL(hipMemcpyAsync(c->ws + c->L.solids, ds.data(), sizeof(DevSolid) * ds.size(), hipMemcpyHostToDevice,
                          c->stream));
@@ -737,6 +739,7 @@ static lbm_status clear_solids(lbm_ctx *c, lbm_status st) {
   c->nlag = 0;
   c->nshell = 0;
   c->any_moving = c->any_free = c->ibm_moving = c->ibm_free = false;
+  c->ibm_poly = false;
   c->lag_user = false;
   if (hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
@@ -885,6 +888,130 @@ static lbm_status build_ibm(lbm_ctx *c) {
   launch_ibm_setup(c);
   // the host vectors must outlive the copies
   HIPCALL(hipStreamSynchronize(c->stream));
+  c->ibm_poly = false;
+  if (!mv && c->n_iter > 1) return ibm_polynomial(c, rlen);
+  return LBM_OK;
+}
+
+// Fixed points: replace the rows of A (formed on the device
+// from the delta weights) with those of P = sum_{k < n_iter} B^k, B = I - A,
+// built in FP64 (row by row, each product B^k = B^(k-1) B through a dense
+// accumulator), so that one product P F^0 gives the summed force of all
+// iterations.  Kept as A (the iterations run one by one) when P's widest row
+// does not fit the row capacity.
+static lbm_status ibm_polynomial(lbm_ctx *c, const std::vector<uint32_t> &rlen) {
+  const int64_t nl = c->nlag;
+  const bool f64 = csize_of(c->p.storage) == 8;
+  const size_t es = f64 ? 16 : 8;
+  const int nw = c->ibm_nw;
+  std::vector<unsigned char> raw((size_t)nl * nw * es);
+  HIPCALL(hipMemcpyAsync(raw.data(), c->ws + c->L.lag_nrow, raw.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));
+  // A in CSR (entry: column at byte 0, value at byte 8 (FP64) or 4 (FP32))
+  std::vector<int64_t> ap((size_t)nl + 1, 0);
+  for (int64_t l = 0; l < nl; l++) ap[(size_t)l + 1] = ap[(size_t)l] + rlen[(size_t)l];
+  std::vector<uint32_t> acol((size_t)ap[(size_t)nl]);
+  std::vector<double> aval((size_t)ap[(size_t)nl]);
+  for (int64_t l = 0; l < nl; l++)
+    for (uint32_t j = 0; j < rlen[(size_t)l]; j++) {
+      const unsigned char *e = raw.data() + ((size_t)l * nw + j) * es;
+      uint32_t col;
+      std::memcpy(&col, e, 4);
+      double v;
+      if (f64) std::memcpy(&v, e + 8, 8);
+      else {
+        float f;
+        std::memcpy(&f, e + 4, 4);
+        v = (double)f;
+      }
+      acol[(size_t)(ap[(size_t)l] + j)] = col;
+      aval[(size_t)(ap[(size_t)l] + j)] = v;
+    }
+  // row l of P: t = e_l; p = e_l; n_iter - 1 times t = t B, p += t
+  std::vector<std::vector<std::pair<uint32_t, double>>> prow((size_t)nl);
+  std::vector<double> t((size_t)nl, 0.0), tn((size_t)nl, 0.0), pacc((size_t)nl, 0.0);
+  std::vector<char> in_t((size_t)nl, 0), in_tn((size_t)nl, 0), in_p((size_t)nl, 0);
+  std::vector<uint32_t> lt, ltn, lp;
+  size_t widest = 0;
+  for (int64_t l = 0; l < nl; l++) {
+    lt.assign(1, (uint32_t)l);
+    lp.assign(1, (uint32_t)l);
+    t[(size_t)l] = 1.0;
+    in_t[(size_t)l] = 1;
+    pacc[(size_t)l] = 1.0;
+    in_p[(size_t)l] = 1;
+    for (int k = 1; k < c->n_iter; k++) {
+      ltn.clear();
+      for (uint32_t m : lt) {
+        const double tm = t[m];
+        // (t B)_j = t_j - sum_m t_m A_mj
+        if (!in_tn[m]) {
+          in_tn[m] = 1;
+          ltn.push_back(m);
+        }
+        tn[m] += tm;
+        for (int64_t q = ap[m]; q < ap[(size_t)m + 1]; q++) {
+          const uint32_t j = acol[(size_t)q];
+          if (!in_tn[j]) {
+            in_tn[j] = 1;
+            ltn.push_back(j);
+          }
+          tn[j] -= tm * aval[(size_t)q];
+        }
+      }
+      for (uint32_t m : lt) {
+        t[m] = 0.0;
+        in_t[m] = 0;
+      }
+      lt.swap(ltn);
+      for (uint32_t j : lt) {
+        t[j] = tn[j];
+        tn[j] = 0.0;
+        in_tn[j] = 0;
+        in_t[j] = 1;
+        if (!in_p[j]) {
+          in_p[j] = 1;
+          lp.push_back(j);
+        }
+        pacc[j] += t[j];
+      }
+    }
+    std::sort(lp.begin(), lp.end());
+    auto &row = prow[(size_t)l];
+    row.reserve(lp.size());
+    for (uint32_t j : lp) {
+      row.emplace_back(j, pacc[j]);
+      pacc[j] = 0.0;
+      in_p[j] = 0;
+    }
+    for (uint32_t m : lt) {
+      t[m] = 0.0;
+      in_t[m] = 0;
+    }
+    widest = std::max(widest, row.size());
+  }
+  const int64_t pw = (int64_t)((widest + 63) / 64 * 64);
+  if (nl * pw > c->L.max_lag * (int64_t)kIbmNbr) return LBM_OK;  // the iterations stay
+  std::vector<unsigned char> out((size_t)nl * pw * es, 0);
+  std::vector<uint32_t> plen((size_t)nl);
+  for (int64_t l = 0; l < nl; l++) {
+    const auto &row = prow[(size_t)l];
+    plen[(size_t)l] = (uint32_t)row.size();
+    for (size_t j = 0; j < row.size(); j++) {
+      unsigned char *e = out.data() + ((size_t)l * pw + j) * es;
+      std::memcpy(e, &row[j].first, 4);
+      if (f64) std::memcpy(e + 8, &row[j].second, 8);
+      else {
+        const float f = (float)row[j].second;
+        std::memcpy(e + 4, &f, 4);
+      }
+    }
+  }
+  HIPCALL(hipMemcpyAsync(c->ws + c->L.lag_nrow, out.data(), out.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCALL(hipMemcpyAsync(c->ws + c->L.lag_nptr, plen.data(), plen.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCALL(hipStreamSynchronize(c->stream));  // the host vectors end here
+  c->ibm_nw = (int)pw;
+  c->ibm_poly = true;
   return LBM_OK;
 }
 

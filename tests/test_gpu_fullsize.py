@@ -1,10 +1,10 @@
 """Full-size workloads in the launch configuration bench.py times, through the C ABI.
 
 * 256^3 box with 64 spheres (gaps down to 2 lattice units, 296k boundary links), FP64 storage,
-  quadratic and single-node (Zhao-Yong) interpolated bounce-back: node classification, link set and q
-  bit-exact against the FP64
-  oracle, fields (max|du|/max|u|, max|drho|) and per-sphere force/torque at 1e-12 after two steps
-  (the oracle needs about half a minute per step at this size).
+  quadratic and single-node (Zhao-Yong) interpolated bounce-back, and FP32 storage with quadratic
+  bounce-back (the bench line's configuration): node classification, link set and q bit-exact against
+  the FP64 oracle, fields (max|du|/max|u|, max|drho|) and per-sphere force/torque after two steps at
+  1e-12 (FP64) or the FP32 bars (the oracle needs about half a minute per step at this size).
 * 512 lattices with translating spheres stepped as one FP32 batch (the batching workload, about
   1.7e8 cells): sampled members (the smallest, the largest and the median lattice) are bit for bit
   their lone runs after the batch's tuning steps.
@@ -30,14 +30,20 @@ def lbm():
     return L
 
 
+# FP32 storage (the configuration of the bench line): the FP32 bars of the periodic parity tests,
+# relative 2e-5 in velocity and 1e-4 in force, density 1e-6 absolute
+BARS = {"F64": {"u": 1e-12, "rho": 1e-12, "F": 1e-12}, "F32": {"u": 2e-5, "rho": 1e-6, "F": 1e-4}}
+
+
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("method", ["QUADRATIC", "ZHAO_YONG"])
-def test_pack256_fp64_against_oracle(lbm, method):
+@pytest.mark.parametrize("method,storage", [("QUADRATIC", "F64"), ("ZHAO_YONG", "F64"), ("QUADRATIC", "F32")])
+def test_pack256_against_oracle(lbm, method, storage):
     from oracle import Oracle
 
-    case = W.sphere_pack(storage="F64", method=method)
-    print(f"pack256: {case.shape}, {len(case.solids)} spheres", flush=True)
-    gpu = lbm.Lattice(case.lattice, case.collision, "F64", case.shape, case.tau, g=case.g,
+    case = W.sphere_pack(storage=storage, method=method)
+    bar = BARS[storage]
+    print(f"pack256: {case.shape}, {len(case.solids)} spheres, {storage}", flush=True)
+    gpu = lbm.Lattice(case.lattice, case.collision, storage, case.shape, case.tau, g=case.g,
                       max_solids=len(case.solids))
     gpu.set_solids(case.solids, case.method)
     orc = Oracle(case.lattice, case.collision, case.shape, case.tau, g=case.g, form="h",
@@ -58,12 +64,12 @@ def test_pack256_fp64_against_oracle(lbm, method):
     fl = tg != 1
     du = np.max(np.abs(ug[:, fl] - uo[:, fl])) / np.max(np.abs(uo[:, fl]))
     drho = np.max(np.abs(rg[fl] - ro[fl]))
-    assert du <= 1e-12 and drho <= 1e-12, (du, drho)
+    assert du <= bar["u"] and drho <= bar["rho"], (du, drho)
     hg, ho = gpu.history(), orc.history()
     scale = max(np.max(np.abs(ho[-1, :, :3])), np.linalg.norm(case.g) * np.sum(fl))
-    assert np.max(np.abs(hg[:, :, :3] - ho[:, :, :3])) / scale <= 1e-12
+    assert np.max(np.abs(hg[:, :, :3] - ho[:, :, :3])) / scale <= bar["F"]
     tscale = scale * max(case.shape)
-    assert np.max(np.abs(hg[:, :, 3:] - ho[:, :, 3:])) / tscale <= 1e-12
+    assert np.max(np.abs(hg[:, :, 3:] - ho[:, :, 3:])) / tscale <= bar["F"]
     gpu.close()
 
 
