@@ -278,8 +278,13 @@ def run_serving(torch, lbm, W, rate, seconds, min_completed, step_cap, count=256
                "max_slots": max_slots, "criterion": f"|F(t)-F(t-100)|/|F(t)| < 1e-6, cap {step_cap} steps",
                "start": "uniform flow at the periodic-array estimate of the mean velocity",
                "per_request": [{"edge": r.case.shape[0], "Re": round(r.case.meta["Re"], 2), "method": r.case.method,
-                                "steps": r.steps, "converged": r.converged, "latency_s": round(r.latency, 3)}
+                                "steps": r.steps, "converged": r.converged, "latency_s": round(r.latency, 3),
+                                "last_change": float(r.change) if r.change >= 0 else None}
                                for r in done]})
+    # how far the capped solves were from the criterion when they stopped
+    ch = sorted(float(r.change) for r in done if not r.converged and r.change >= 0)
+    st["capped_last_change_p50"] = ch[len(ch) // 2] if ch else None
+    st["capped_last_change_max"] = ch[-1] if ch else None
     return st
 
 
@@ -491,7 +496,7 @@ def main():
         extra("serving_subsaturated", sub, f"{sub['completed']} done at {rate:.3f} req/s, p50 "
                                            f"{sub['latency_p50_s']} s, p99 {sub['latency_p99_s']} s")
         serving = {"n": sat["latency_n"], "converged": sat["converged"], "capped": sat["capped"],
-                   "step_cap": args.serve_cap,
+                   "step_cap": args.serve_cap, "capped_change_p50": sat["capped_last_change_p50"],
                    "p50_s": sat["latency_p50_s"], "p99_s": sat["latency_p99_s"],
                    "solves_per_s": round(sat["solves_per_s"], 4), "offered_req_per_s": 50.0,
                    "sub_rate_req_per_s": round(rate, 4), "sub_n": sub["latency_n"], "sub_p50_s": sub["latency_p50_s"],
