@@ -66,9 +66,14 @@ typedef int32_t lbm_status;
 typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
 typedef enum { LBM_BGK = 0, LBM_MRT = 1 } lbm_collision;
 /* Storage of the populations.  All formats hold the deviation f_i - w_i from
- * the rest state; F64 computes in FP64, F32_DEV and F16_DEV decode to FP32
- * and compute in FP32 (force and torque are always accumulated in FP64). */
-typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2 } lbm_storage;
+ * the rest state; F64 computes in FP64, F32_DEV and the FP16 formats decode
+ * to FP32 and compute in FP32 (force and torque are always accumulated in
+ * FP64).  F16_DEV rounds to nearest on store; F16_SR (IEEE half too) rounds
+ * stochastically: up with the probability of the fraction dropped, so that
+ * changes smaller than half a unit in the last place survive on average (a
+ * slowly developing flow stored to nearest lags behind); the dither is a
+ * hash of slot and time step, so runs repeat bit for bit. */
+typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2, LBM_F16_SR = 3 } lbm_storage;
 /* No-slip treatment (Sec. 2.1, 2.2): halfway bounce-back (Eq. 10), linear
  * Bouzidi (two-point form of Eq. 11), quadratic Bouzidi (Eq. 11), direct-
  * forcing IBM (Eq. 5-9), Yu's unified scheme (Eq. 12-14; the merged Eq. 15

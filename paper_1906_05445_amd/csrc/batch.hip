@@ -426,7 +426,7 @@ lbm_status lbm_batch_create(int32_t lattice, int32_t storage, int32_t max_slots,
                             void *hip_stream, lbm_batch **out) {
   if (!out) return LBM_EINVAL;
   *out = nullptr;
-  if ((lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || storage < LBM_F64 || storage > LBM_F16_DEV) return LBM_EINVAL;
+  if ((lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || storage < LBM_F64 || storage > LBM_F16_SR) return LBM_EINVAL;
   if (max_slots <= 0 || max_slots > 65536 || !dev_pool || ((uintptr_t)dev_pool & 255)) return LBM_EINVAL;
   const size_t tb = lbm_batch_table_bytes(max_slots);
   if (pool_bytes < tb + 256) return LBM_ENOMEM;

@@ -495,7 +495,8 @@ __device__ inline void ibb_body(S *__restrict__ P, const S *__restrict__ pre, co
       const C hs_f = Store<S>::ld(P + pidx<Q>(i, n));
       const C hs_ff = ffok ? Store<S>::ld(P + pidx<Q>(i, g.nff)) : C(0);
       const C hpre = k.kind == LK_ZY ? Store<S>::ld(pre + pidx<Q>(ib, g.nff)) : C(0);
-      const S v = (S)link_value<C>(k, link_wall<C>(k, g.B), hb_f, hb_ff, hb_fff, hs_f, hs_ff, hpre);
+      const S v = store_value<S, C>(link_value<C>(k, link_wall<C>(k, g.B), hb_f, hb_ff, hb_fff, hs_f, hs_ff, hpre),
+                                    a.sr != 0, a.sr ? hash32((g.nb * 32u + (uint32_t)i) ^ sr_seed(t)) >> 19 : 0u);
       P[pidx<Q>(i, g.nb)] = v;
       link_ft((double)(C)v, (double)hb_f, g.a, g.b, g.d, g.r, acc);
     }
@@ -1000,6 +1001,7 @@ void fill_ibb_args(lbm_ctx *c, IbbArgs *ap) {
   a.sl = c->at<SolidLinks>(c->L.solid_links);
   a.partials = c->at<double>(c->L.partials);
   a.method = c->method;
+  a.sr = c->p.storage == LBM_F16_SR ? 1 : 0;
   a.max_links = (uint64_t)c->L.max_links;
   a.max_partials = (uint64_t)c->L.max_partials;
 }

@@ -16,7 +16,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchSlot *__restr
   const int par = (int)(*step & 1);
   batch_units(wl, order, [&](int m, uint32_t blk) {
     const int cur = SLOT(m, cur0) ^ par;
-    const SweepArgs a = SLOT(m, sw);
+    SweepArgs a = SLOT(m, sw);
+    a.seed = sr_seed(SLOT(m, t0) + *step);
     sweep_body<Q, COLL, S, 1, NT, 0>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])),
                                      a, nullptr, blk);
   });
@@ -158,6 +159,8 @@ static int make_sweep_args(lbm_ctx *c, SweepArgs &a) {
   for (int k = 0; k < 3; k++) a.bc[k] = c->p.boundary[k];
   a.uin = c->p.inflow;
   a.uo = c->p.boundary[0] == BND_OPEN ? c->ws + c->L.uo : nullptr;
+  a.sr = c->p.storage == LBM_F16_SR ? 1u : 0u;
+  a.seed = sr_seed(c->t);
   int coll;
   if (c->p.collision == LBM_BGK) {
     coll = COLL_BGK;
@@ -207,6 +210,8 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0,
     la.rec = link_rec_of(c);
     la.io = link_io_of(c, link_t);
     la.stride = c->link_stride;
+    la.sr = a.sr;
+    la.lseed = sr_seed(link_t);
     if (sum_t >= 0) {
       la.cs = chunk_sum_args(c, sum_t);
       la.cblocks = chunk_sum_blocks(c);

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void k_outflow(const S *__restrict__ A, S *__r
     const C old = Store<S>::ld(A + pidx32<Q>(opp(i), n));
     const BndSrc s = bnd_src(L::ex(i), L::ey(i), L::ez(i), x - 1, y, z, (int)a.nx, (int)a.ny, (int)a.nz, a.bc);
     const C up = Store<S>::ld(B + pidx32<Q>(bnd_dir<Q>(i, s), s.cell));
-    Store<S>::st(B + pidx32<Q>(opp(i), n), (old + U * up) / (C(1) + U));
+    B[pidx32<Q>(opp(i), n)] = store_value<S, C>((old + U * up) / (C(1) + U), a.sr != 0,
+                                                a.sr ? hash32((n * 32u + (uint32_t)opp(i)) ^ a.seed) >> 19 : 0u);
   }
 }
 

@@ -46,6 +46,7 @@ struct IbbArgs {
   double *partials;  // [chunk][6]
   uint64_t max_links, max_partials;
   int method;        // LBM_BB, LBM_IBB_LINEAR, LBM_IBB_QUADRATIC, LBM_IBB_YU, LBM_IBB_ZHAO_YONG
+  int sr;            // FP16 stochastic rounding of the link values (seed from the step)
 };
 
 // Per-solid IBM force and torque of one step (Sec. 3.1, App. B).
@@ -76,6 +77,8 @@ struct SweepArgs {
   uint32_t iblocks;      // next blocks: IBM force/torque of this step, one per solid
   IbmFtArgs ift;
   uint32_t xcd;          // 1: blocks take tiles in XCD-contiguous order
+  uint32_t sr;           // FP16 storage with stochastic rounding
+  uint32_t seed;         // sr_seed of the step the sweep computes
   int32_t bc[3];         // domain boundaries per axis (BND_*), bounded-domain sweeps only
   double uin;            // inflow velocity of an open x axis
   void *uo;              // [ny nz] compute type: u_x of the last x layer's collisions (open x)
@@ -99,6 +102,7 @@ struct SweepLinkArgs {
   uint64_t stride;
   uint32_t cblocks;
   ChunkSumArgs cs;
+  uint32_t sr, lseed;  // FP16 stochastic rounding of the link values; sr_seed of the links' step
 };
 
 // IBM spreading: lanes per shell cell (each takes every kSpreadLanes-th entry

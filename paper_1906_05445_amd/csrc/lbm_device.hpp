@@ -267,6 +267,49 @@ struct Store<_Float16> {
 };
 
 // ----------------------------------------------------------------------------
+// FP16 storage with stochastic rounding (LBM_F16_SR)
+// ----------------------------------------------------------------------------
+// Round-to-nearest loses every change smaller than half a unit in the last
+// place of the stored value: in a slowly developing flow the per-step
+// increments of the populations fall below it and the flow lags.  Stochastic
+// rounding rounds up with probability equal to the dropped fraction, so the
+// stored value is unbiased.  The dither is a deterministic hash of the slot
+// and the time step, so runs repeat bit for bit.
+//
+// Integer hash: two multiply-xorshift rounds (Wellons's "lowbias32").
+__host__ __device__ inline uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+// Per-step seed of the dither.
+__host__ __device__ inline uint32_t sr_seed(int64_t t) { return hash32((uint32_t)t * 0x9e3779b9U + 0x632be5abU); }
+// 13 dither bits of direction i from a cell's hash h (h times an odd constant
+// is uniform when h is; its top bits are taken).
+__device__ inline uint32_t sr_bits(uint32_t h, int i) { return (h * (0x9e3779b1U * (2U * (uint32_t)i + 1U))) >> 19; }
+// v rounded to FP16 stochastically with dither r (13 bits, the bits FP16
+// drops from an FP32 mantissa), in FP16's normal range; nearest elsewhere.
+__device__ inline _Float16 f16_round_sr(float v, uint32_t r) {
+  const uint32_t b = __float_as_uint(v), mag = b & 0x7fffffffU;
+  if (mag < 0x38800000U || mag >= 0x477fe000U) return (_Float16)v;
+  return (_Float16)__uint_as_float((b + r) & 0xffffe000U);  // exact in FP16
+}
+// Storage value of a computed population: stochastic for FP16 when sr is
+// set (dither r), the plain conversion otherwise.
+template <typename S, typename C>
+__device__ inline S store_value(C v, bool sr, uint32_t r) {
+  if constexpr (sizeof(S) == 2) {
+    if (sr) return f16_round_sr((float)v, r);
+  }
+  (void)sr;
+  (void)r;
+  return (S)v;
+}
+
+// ----------------------------------------------------------------------------
 // integer helpers
 // ----------------------------------------------------------------------------
 // Division by a runtime constant d for n < 2^31: q = (umulhi(n, m) + n) >> s.

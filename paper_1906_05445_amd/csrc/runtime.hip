@@ -64,7 +64,7 @@ bool valid_params(const lbm_params *p) {
   if (!p) return false;
   if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return false;
   if (p->collision != LBM_BGK && p->collision != LBM_MRT) return false;
-  if (p->storage < LBM_F64 || p->storage > LBM_F16_DEV) return false;
+  if (p->storage < LBM_F64 || p->storage > LBM_F16_SR) return false;
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return false;
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return false;
   const double N = (double)p->nx * p->ny * p->nz;

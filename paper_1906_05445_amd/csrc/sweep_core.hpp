@@ -232,11 +232,18 @@ __device__ __forceinline__ void sweep_relax(S *__restrict__ B, const SweepArgs &
   uint64_t base;
   if constexpr (IDX32 != 0) base = pidx32<Q>(0, n);
   else base = pidx<Q>(0, n);
+  bool sr = false;
+  uint32_t hsr = 0;
+  if constexpr (sizeof(S) == 2) {
+    sr = a.sr != 0;
+    if (sr) hsr = hash32(n ^ a.seed);
+  }
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    if (NT) Store<S>::st_nt(B + base + (uint64_t)i * kTile, h[i]);
-    else Store<S>::st(B + base + (uint64_t)i * kTile, h[i]);
-    if (KEEP && i > 0 && keep) keep[i - 1] = (S)h[i];
+    const S sv = store_value<S, C>(h[i], sr, sr ? sr_bits(hsr, i) : 0u);
+    if (NT) __builtin_nontemporal_store(sv, B + base + (uint64_t)i * kTile);
+    else B[base + (uint64_t)i * kTile] = sv;
+    if (KEEP && i > 0 && keep) keep[i - 1] = sv;
   }
 }
 
@@ -296,7 +303,8 @@ __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la,
       const LinkRec<C> &r = rec[p];
       const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
       // (no Zhao-Yong links here: the table never holds them)
-      const S v = (S)link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff, C(0));
+      const S v = store_value<S, C>(link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff, C(0)), la.sr != 0,
+                                    la.sr ? hash32((r.nb * 32u + (uint32_t)i) ^ la.lseed) >> 19 : 0u);
       dst[pidx<Q>(i, r.nb)] = v;
       io[r.l] = (C)v;
       io[la.stride + r.l] = hb_f;
@@ -350,7 +358,8 @@ __device__ __forceinline__ void sweep_links_zy(const S *A, S *B, const SweepLink
       const C hb_f = (C)tab[c][o * (Q - 1) + (ib - 1)];
       const C hpre = Store<S>::ld(A + pidx<Q>(ib, r.nff));
       const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
-      const S v = (S)link_value<C>(k, r.B, hb_f, C(0), C(0), hs_f, C(0), hpre);
+      const S v = store_value<S, C>(link_value<C>(k, r.B, hb_f, C(0), C(0), hs_f, C(0), hpre), la.sr != 0,
+                                    la.sr ? hash32((r.nb * 32u + (uint32_t)i) ^ la.lseed) >> 19 : 0u);
       B[pidx<Q>(i, r.nb)] = v;
       io[r.l] = (C)v;
       io[la.stride + r.l] = hb_f;

@@ -32,10 +32,10 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_EUNSUPPORTED, LB
     0, -1, -2, -3, -4, -5, -6, -7
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 COLLISIONS = {"BGK": 0, "MRT": 1}
-STORAGES = {"F64": 0, "F32": 1, "F16": 2}
+STORAGES = {"F64": 0, "F32": 1, "F16": 2, "F16_SR": 3}
 METHODS = {"BB": 0, "LINEAR": 1, "QUADRATIC": 2, "IBM": 3, "YU": 4, "ZHAO_YONG": 5}
 KINDS = {"sphere": 0, "cylinder": 1, "plane": 2}
-STORAGE_DTYPES = {0: np.float64, 1: np.float32, 2: np.float16}
+STORAGE_DTYPES = {0: np.float64, 1: np.float32, 2: np.float16, 3: np.float16}
 
 
 class lbm_params(ctypes.Structure):

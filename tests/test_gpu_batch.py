@@ -198,7 +198,7 @@ def test_batch_rejects_mismatched_members(lbm):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["F16", "F64"])
+@pytest.mark.parametrize("storage", ["F16", "F16_SR", "F64"])
 def test_batch_d2q9_members_match_alone(lbm, storage):
     """D2Q9 members (translating and fixed cylinders, IBM circle, BGK and MRT) match their lone runs."""
     specs = [

@@ -62,6 +62,12 @@ CASES = {
     # Zhao & Yong's scheme stays with the bounce-back kernel after every sweep
     "d3q19_mrt_f16_zhao_yong": ("D3Q19", "MRT", "F16", (33, 30, 26), 0.9, (1e-5, 0.0, 0.0),
                                 [W.solid("sphere", (16.2, 15.1, 12.8), 6.1)], "ZHAO_YONG", None),
+    # FP16 with stochastic rounding: the link values of the sweep and of the bounce-back kernel take the
+    # same dither (slot and step), so splitting calls changes nothing
+    "d3q19_mrt_f16sr_quadratic": ("D3Q19", "MRT", "F16_SR", (33, 30, 26), 0.9, (1e-5, 0.0, 0.0),
+                                  [W.solid("sphere", (16.2, 15.1, 12.8), 6.1)], "QUADRATIC", None),
+    "d3q19_mrt_f16sr_zhao_yong": ("D3Q19", "MRT", "F16_SR", (33, 30, 26), 0.9, (1e-5, 0.0, 0.0),
+                                  [W.solid("sphere", (16.2, 15.1, 12.8), 6.1)], "ZHAO_YONG", None),
 }
 
 

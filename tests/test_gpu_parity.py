@@ -32,7 +32,7 @@ ORACLE_THREADS = min(16, os.cpu_count() or 1)
 
 pytestmark = pytest.mark.gpu
 
-REDUCED = {"F32": {"u": 2e-5, "F": 1e-4}, "F16": {"u": 2e-2, "F": 5e-2}}
+REDUCED = {"F32": {"u": 2e-5, "F": 1e-4}, "F16": {"u": 2e-2, "F": 5e-2}, "F16_SR": {"u": 2e-2, "F": 5e-2}}
 
 
 @pytest.fixture(scope="module")
@@ -132,7 +132,7 @@ def _compare_forces_one(gpu, orc, g, tol, floor=0.0):
 # ----------------------------------------------------------------------------
 # bit-exact pieces
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("storage", ["F64", "F32", "F16"])
+@pytest.mark.parametrize("storage", ["F64", "F32", "F16", "F16_SR"])
 @pytest.mark.parametrize("lat,shape", [("D2Q9", (67, 45, 1)), ("D3Q19", (37, 29, 23)),
                                        # widths that are multiples of 64 (a wavefront is one row); the
                                        # last tile of 64 x 5 x 3 ends with a wavefront past the end
@@ -333,7 +333,7 @@ def test_library_mesh_matches_generator(lbm):
 # ----------------------------------------------------------------------------
 # reduced precision against the FP64 oracle
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("storage", ["F32", "F16"])
+@pytest.mark.parametrize("storage", ["F32", "F16", "F16_SR"])
 @pytest.mark.parametrize("method", ["QUADRATIC", "IBM", "YU", "ZHAO_YONG"])
 def test_reduced_precision(lbm, storage, method):
     shape = (37, 29, 23)
