@@ -2,12 +2,14 @@
 oracle to 1e-12, tests/test_gpu_parity.py).
 
 Bars here, after 600 steps of reduced versions of the workloads (per-sphere relative drag error):
-FP32 deviation storage 1e-4, FP16 deviation storage 2e-2; lattices stepped as an FP32 batch against the
-same lattices stepped alone with FP64 storage: force error 1e-5 of the largest FP64 force.
+FP32 deviation storage 1e-4, FP16 deviation storage 2e-2 (round to nearest and stochastic rounding);
+lattices stepped as an FP32 batch against the same lattices stepped alone with FP64 storage: force
+error 1e-5 of the largest FP64 force.
 The errors grow with the length of the run; bench.py reports them on the full workloads (256^3 with
-64 spheres and 8 moving-sphere lattices, 10000 steps): FP32 6.4e-5, FP16 4.3e-2 (a systematic drift of
-the mean drag, FP16 rounding of the deviations being 2^-11 relative), batched FP32 vs plain FP64
-1.8e-4, against stated full-length tolerances of 2e-4, 1e-1 and 5e-4.
+64 spheres and 8 moving-sphere lattices, 10000 steps): FP32 6.4e-5; FP16 to nearest 4.3e-2 (a
+systematic lag of the mean flow: per-step increments below half an FP16 unit are rounded away); FP16
+with stochastic rounding 3.2e-4; batched FP32 vs plain FP64 1.8e-4; against stated full-length
+tolerances of 2e-4, 1e-1, 2e-3 and 5e-4.
 """
 import numpy as np
 import pytest
