@@ -126,7 +126,15 @@ typedef struct lbm_batch lbm_batch;
  *           bounded axis takes fixed solids only, each at least 4 nodes clear
  *           of every bounded face (lbm_set_solids), and is not admitted to a
  *           batch.
- *   inflow : inflow velocity U_in of an OPEN x axis (|U_in| < 0.3). */
+ *   inflow : inflow velocity U_in of an OPEN x axis (|U_in| < 0.3).
+ *   cover_momentum : 1 = moving bounce-back solids exchange momentum with
+ *           the nodes they cover and uncover (Sec. 3.2 needs the refill but
+ *           gives no such term; this reading is an option): a node covered
+ *           in a step gives the solid its momentum sum_i f_i e_i, a node
+ *           uncovered (refilled with f_eq(rho_bar, u_w)) takes rho_bar u_w
+ *           from it, with the torques about the solid's centre; the sums
+ *           (fixed point, order-free) join the force and torque of the next
+ *           step, which free solids move with.  0 = off (default). */
 typedef struct {
   int32_t lattice;    /* lbm_lattice */
   int32_t collision;  /* lbm_collision */
@@ -138,6 +146,7 @@ typedef struct {
   int32_t body_force_fluid_only;
   int32_t boundary[3]; /* lbm_domain per axis */
   double inflow;
+  int32_t cover_momentum;
 } lbm_params;
 
 /* A rigid solid.  Sphere: centre, radius (in 2D a circle).  Cylinder: axis

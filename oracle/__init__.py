@@ -107,6 +107,7 @@ def lib():
         L.orc_form.argtypes = [ctypes.c_void_p]
         L.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_set_boundaries.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_set_cover.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _d]
         L.orc_solid_state.argtypes = [ctypes.c_void_p, _d]
         L.orc_ibb_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + \
@@ -259,6 +260,12 @@ class Oracle:
 
     def set_threads(self, n):
         lib().orc_set_threads(self._h, int(n))
+
+    def set_cover(self, on=True):
+        """Covering / uncovering momentum of moving bounce-back solids: a node the
+        solid covers gives its momentum to the solid, a node it uncovers (refilled at
+        the wall velocity) takes its momentum from it; added to the next step's force."""
+        lib().orc_set_cover(self._h, int(bool(on)))
 
     BCS = {"periodic": 0, "slip": 1, "open": 2}
 

@@ -191,6 +191,11 @@ typedef struct orc {
   int bc[3];
   double Uin;
   int mir[3][QMAX];
+  /* covering / uncovering momentum of moving IBB solids (R38): on or off, and
+   * per solid the force and torque [6] of the last move, added to the force
+   * of the next step */
+  int cover;
+  double *cu;
 } orc;
 
 enum { BC_PERIODIC = 0, BC_SLIP = 1, BC_OPEN = 2 };
@@ -827,6 +832,7 @@ void orc_destroy(orc *o) {
   free(o->lag_sid);
   free(o->Flag);
   free(o->FT);
+  free(o->cu);
   free(o->hist);
   free(o);
 }
@@ -871,6 +877,8 @@ int orc_set_solids(orc *o, int n, const int *kind, const int *inverted, const do
   }
   free(o->FT);
   o->FT = (double *)calloc(6 * (n > 0 ? n : 1), sizeof(double));
+  free(o->cu);
+  o->cu = (double *)calloc(6 * (n > 0 ? n : 1), sizeof(double));
   o->hist_len = 0;
   classify(o);
   build_links(o);
@@ -1248,6 +1256,25 @@ static void move_solids(orc *o) {
     }
   }
   classify(o);
+  /* covering (R38): a node fluid at t and solid at t+1 takes its momentum,
+   * sum_i f_i e_i of the populations that streamed into it, into the solid
+   * that now holds it (torque about that solid's centre at t+1) */
+  if (o->cover)
+    for (long n = 0; n < N; n++) {
+      if (old[n] || !o->excl[n] || o->owner[n] < 0) continue;
+      int x, y, z;
+      coords_of(o, n, &x, &y, &z);
+      double m[3] = {0.0, 0.0, 0.0}, r[3];
+      for (int i = 0; i < o->Q; i++)
+        for (int a = 0; a < 3; a++) m[a] += o->f[(long)i * N + n] * o->e[i][a];
+      const int sid = o->owner[n];
+      lever(o, &o->sol[sid], (double)x, (double)y, (double)z, r);
+      double *cu = &o->cu[6 * sid];
+      for (int a = 0; a < 3; a++) cu[a] += m[a];
+      cu[3] += r[1] * m[2] - r[2] * m[1];
+      cu[4] += r[2] * m[0] - r[0] * m[2];
+      cu[5] += r[0] * m[1] - r[1] * m[0];
+    }
   for (long n = 0; n < N; n++) {
     if (!(old[n] && !o->excl[n])) continue;
     int x, y, z;
@@ -1276,6 +1303,19 @@ static void move_solids(orc *o) {
     if (o->literal) feq_all(o, drb, uw, feq);
     else heq_all(o, drb, uw, feq);
     for (int i = 0; i < o->Q; i++) o->f[(long)i * N + n] = feq[i];
+    /* uncovering (R38): the refilled node's momentum rho_bar u_w comes out of
+     * the solid that left it */
+    if (o->cover && sid >= 0) {
+      const double rb = o->literal ? drb : 1.0 + drb;
+      double r[3], m[3];
+      lever(o, &o->sol[sid], (double)x, (double)y, (double)z, r);
+      for (int a = 0; a < 3; a++) m[a] = rb * uw[a];
+      double *cu = &o->cu[6 * sid];
+      for (int a = 0; a < 3; a++) cu[a] -= m[a];
+      cu[3] -= r[1] * m[2] - r[2] * m[1];
+      cu[4] -= r[2] * m[0] - r[0] * m[2];
+      cu[5] -= r[0] * m[1] - r[1] * m[0];
+    }
   }
   free(old);
   free(old_owner);
@@ -1431,6 +1471,13 @@ static void one_step(orc *o) {
     for (int k = 0; k < 6 * o->nsolid; k++) o->FT[k] = o->literal ? plain[k] : acc_get(&lacc[k]);
   free(lacc);
   free(plain);
+  /* the momentum the last move of the solids took from and gave to the fluid
+   * (nodes covered and uncovered), part of this step's force and torque */
+  if (o->cover && o->cu)
+    for (int k = 0; k < 6 * o->nsolid; k++) {
+      o->FT[k] += o->cu[k];
+      o->cu[k] = 0.0;
+    }
   /* convective outflow (Sec. 3.4): d(rho0 u)/dt + U_o d(rho0 u)/dx = 0 taken
    * for the populations that enter the last layer from outside, first-order
    * implicit in time and upwind in x:
@@ -1509,6 +1556,8 @@ void orc_set_threads(orc *o, int n) { o->nthreads = n > 0 ? n : 1; }
 /* Domain boundaries (Sec. 3.4): per axis 0 periodic, 1 stress-free planes,
  * 2 (x only) velocity inlet Uin before x = 0 and convective outflow at the
  * last layer.  D2Q9 keeps z periodic.  Returns -1 for an invalid set. */
+/* Covering / uncovering momentum of moving IBB solids (R38) on (1) or off. */
+void orc_set_cover(orc *o, int on) { o->cover = on ? 1 : 0; }
 int orc_set_boundaries(orc *o, int bcx, int bcy, int bcz, double Uin) {
   const int b[3] = {bcx, bcy, bcz};
   for (int a = 0; a < 3; a++) {

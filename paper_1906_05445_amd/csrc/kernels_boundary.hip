@@ -146,6 +146,12 @@ __device__ inline void classify_box_body(const LinkArgs &a, uint32_t bx, int s) 
     if (at < a.max_refill) a.refill_list[at] = ((uint64_t)(uint32_t)s << 32) | n;
     else a.misc[4] = 1u;
   }
+  // covered by solid s (its box lists it once): its momentum goes to s
+  if (a.cu && !(now & F_WAS_SOLID) && (now & F_SOLID) && k == s) {
+    const uint32_t at = atomicAdd(&a.misc[3], 1u);
+    if (at < a.max_refill) a.refill_list[at] = (1ull << 63) | ((uint64_t)(uint32_t)s << 32) | n;
+    else a.misc[4] = 1u;
+  }
 }
 __global__ void k_classify_keep(LinkArgs a) { classify_keep_body(a, blockIdx.x, blockIdx.y); }
 __global__ void k_classify_box(LinkArgs a) { classify_box_body(a, blockIdx.x, blockIdx.y); }
@@ -188,12 +194,54 @@ __device__ inline uint32_t link_mask(const LinkArgs &a, int s, int x, int y, int
 // density of neighbour x + e_i.  Refills touch disjoint slots (a node's own
 // pull slots belong to other cells than those its neighbours' densities are
 // gathered from), so the list order does not matter.
+// Fixed-point add of a solid's covering / uncovering force m and torque r x m
+// (sign -1: taken from the solid).
+__device__ inline void cu_add(unsigned long long *cu, int s, const double m[3], const double r[3], double sign) {
+  const double v[6] = {m[0], m[1], m[2], r[1] * m[2] - r[2] * m[1], r[2] * m[0] - r[0] * m[2],
+                       r[0] * m[1] - r[1] * m[0]};
+  for (int k = 0; k < 6; k++)
+    atomicAdd(cu + (uint64_t)s * 6 + k, (unsigned long long)__double2ll_rn(sign * v[k] * cu_scale(k)));
+}
+
+// A node the solid covered this step (list entry with bit 63): its momentum,
+// sum_i f_i e_i of the populations that streamed into it (pulled from the
+// post-collision array, ghost values included), goes to the solid, with the
+// torque about the solid's centre at t+1.  One wavefront, lane i pulling f_i.
+template <int Q, typename S>
+__device__ void cover_wave(const LinkArgs &a, int s, uint32_t n) {
+  using L = Lat<Q>;
+  const S *P = static_cast<const S *>(a.post);
+  int x, y, z;
+  xyz_of(n, a.g, x, y, z);
+  const int lane = (int)(threadIdx.x & 63);
+  double m[3] = {0.0, 0.0, 0.0};
+  if (lane < Q) {
+    int ex, ey, ez;
+    dir_of<Q>(lane, ex, ey, ez);
+    const double h = (double)Store<S>::ld(P + pidx<Q>(lane, id_of(x - ex, y - ey, z - ez, a.g)));
+    m[0] = ex * h;  // sum_i h_i e_i = sum_i f_i e_i (sum_i w_i e_i = 0)
+    m[1] = ey * h;
+    m[2] = ez * h;
+  }
+  for (int k = 0; k < 3; k++) m[k] = __shfl(wave_sum(m[k]), 0, 64);
+  if (lane != 0) return;
+  const DevSolid sd = load_uniform(&a.g.solids[s]);
+  double c[3], r[3];
+  solid_centre(sd, a.g.t, a.g.b, c);
+  lever_arm(sd, c, (double)x, (double)y, (double)z, a.g.b, r);
+  cu_add(a.cu, s, m, r, 1.0);
+}
+
 template <int Q, typename S>
 __device__ void refill_wave(const LinkArgs &a, uint64_t entry) {
   using L = Lat<Q>;
   S *P = static_cast<S *>(a.post);
-  const int s = __builtin_amdgcn_readfirstlane((int)(entry >> 32));
+  const int s = __builtin_amdgcn_readfirstlane((int)((entry >> 32) & 0x7fffffffull));
   const uint32_t n = (uint32_t)entry;
+  if (entry >> 63) {
+    cover_wave<Q, S>(a, s, n);
+    return;
+  }
   int x, y, z;
   xyz_of(n, a.g, x, y, z);
   const int lane = (int)(threadIdx.x & 63);
@@ -229,6 +277,11 @@ __device__ void refill_wave(const LinkArgs &a, uint64_t entry) {
       if (k == lane) w = wgt<Q>(k);
     const double heq = w * (drb + rb * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     Store<S>::st(P + pidx<Q>(lane, id_of(x - ex, y - ey, z - ez, a.g)), (typename Store<S>::C)heq);
+  }
+  // uncovering: the refilled momentum rho_bar u_w comes out of the solid
+  if (a.cu && lane == 0) {
+    const double m[3] = {rb * uw[0], rb * uw[1], rb * uw[2]};
+    cu_add(a.cu, s, m, lv, -1.0);
   }
 }
 
@@ -986,6 +1039,7 @@ static LinkArgs link_args(const lbm_ctx *c, int64_t t) {
   a.refill_list = c->at<uint64_t>(c->L.refill);
   a.max_refill = (uint32_t)c->L.max_refill;
   a.masks = c->mask_cells > 0 ? c->at<uint32_t>(c->L.staging) : nullptr;
+  a.cu = c->p.cover_momentum ? c->at<unsigned long long>(c->L.cu) : nullptr;
   return a;
 }
 
@@ -1093,6 +1147,7 @@ FtReduceArgs ft_reduce_args(lbm_ctx *c, int64_t t) {
   r.hist = c->at<double>(c->L.hist) + (uint64_t)(t % kHistCap) * c->L.max_solids * 6;
   r.nsolid = c->nsolid;
   r.max_partials = (uint64_t)c->L.max_partials;
+  r.cu = (c->p.cover_momentum && c->any_moving) ? c->at<unsigned long long>(c->L.cu) : nullptr;
   return r;
 }
 

@@ -309,13 +309,22 @@ __device__ inline void ibm_psum_body(const IbmArgs &a, int64_t l) {
   const IbmEntry<C> *row = static_cast<const IbmEntry<C> *>(a.nrow) + l * a.nw;
   double acc[3] = {0.0, 0.0, 0.0};
   const int len = (int)a.nptr[l];
-  for (int j = lane; j < len; j += 64) {
-    const IbmEntry<C> e = row[j];
-    const IbmF4<C> F = F0[e.col];
+  auto add = [&](const IbmEntry<C> &e, const IbmF4<C> &F) {
     acc[0] = acc[0] + (double)(e.val * F.x);
     acc[1] = acc[1] + (double)(e.val * F.y);
     acc[2] = acc[2] + (double)(e.val * F.z);
+  };
+  int j = lane;
+  // four entries per lane at a time: their loads, then their gathers, are in flight together
+  for (; j + 192 < len; j += 256) {
+    const IbmEntry<C> e0 = row[j], e1 = row[j + 64], e2 = row[j + 128], e3 = row[j + 192];
+    const IbmF4<C> F0v = F0[e0.col], F1v = F0[e1.col], F2v = F0[e2.col], F3v = F0[e3.col];
+    add(e0, F0v);
+    add(e1, F1v);
+    add(e2, F2v);
+    add(e3, F3v);
   }
+  for (; j < len; j += 64) add(row[j], F0[row[j].col]);
   for (int k = 0; k < 3; k++) acc[k] = wave_sum(acc[k]);
   if (lane == 0)
     for (int k = 0; k < 3; k++) a.Fsum[l * 3 + k] = acc[k];

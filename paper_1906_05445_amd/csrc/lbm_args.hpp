@@ -32,7 +32,9 @@ struct LinkArgs {
   SolidLinks *sl;
   uint32_t *misc;          // [0] total links, [1] overflow flag
   void *post;              // refill: post-collision array of step t-1 -> t
-  uint64_t *refill_list;   // nodes uncovered this step: (solid << 32) | cell
+  uint64_t *refill_list;   // nodes uncovered this step: (solid << 32) | cell; with cu also the
+                           // nodes covered, marked by bit 63
+  unsigned long long *cu;  // covering / uncovering momentum [solid][6] in fixed point (cu_scale), or null
   uint32_t max_refill;     // misc[3] counts them, misc[4] flags an overflow
   uint32_t *masks;         // link mask of every box cell (solid s at solids[s].mask_off), written by
                            // the count pass, read by the emit pass; null: emit recomputes them

@@ -54,7 +54,7 @@ struct Layout {
   size_t A, B, flags, owner0, owner1, link_cell, link_meta, link_q, box_counts, box_offsets, solid_links,
       partials, partials2, seg_link, cell_list, solids, hist, staging, fibm, lag_X, lag_dV, lag_sid, lag_Ud, lag_base, lag_w, lag_idx, lag_Fsum,
       lag_Fk, lag_Fk2, lag_Ut, lag_nptr, lag_nrow, shell_cell, shell_rowptr, shell_ent, shell_u, shell_f,
-      refill, uo, misc, total;
+      refill, uo, cu, misc, total;
   size_t stride;  // N rounded up to whole tiles; populations take Q * stride values
   int64_t max_links, max_lag, max_shell, max_box_chunks, max_partials, max_refill;
   int32_t max_solids;
@@ -69,7 +69,13 @@ struct FtReduceArgs {
   double *hist;
   int nsolid;
   uint64_t max_partials;
+  unsigned long long *cu;  // covering / uncovering momentum of the last move (added, then cleared), or null
 };
+
+// Covering / uncovering momentum (moving bounce-back solids) is summed in
+// fixed point, so that the sum does not depend on the order the nodes come
+// in: 2^56 per unit of force (|sum| < 128), 2^50 per unit of torque.
+__host__ __device__ inline double cu_scale(int k) { return k < 3 ? 72057594037927936.0 : 1125899906842624.0; }
 
 // Wave-wide sum of a double (64 lanes, fixed order); lane 0 holds the result.
 __device__ inline double wave_sum(double v) {
@@ -112,8 +118,15 @@ __device__ inline void ft_reduce_waves(const FtReduceArgs &r, uint32_t blk) {
     for (int k = 0; k < 6; k++) v[k] += r.partials[at * 6 + k];
   }
   for (int k = 0; k < 6; k++) {
-    const double tot = wave_sum(v[k]);
-    if (lane == 0) r.hist[(uint64_t)s * 6 + k] = tot;
+    double tot = wave_sum(v[k]);
+    if (lane == 0) {
+      if (r.cu) {
+        unsigned long long *q = r.cu + (uint64_t)s * 6 + k;
+        tot = tot + (double)(long long)*q / cu_scale(k);
+        *q = 0ull;
+      }
+      r.hist[(uint64_t)s * 6 + k] = tot;
+    }
   }
 }
 

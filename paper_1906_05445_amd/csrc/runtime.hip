@@ -80,6 +80,7 @@ bool valid_params(const lbm_params *p) {
   if (p->lattice == LBM_D2Q9 && p->boundary[2] != BND_PERIODIC) return false;
   if (p->boundary[0] == BND_OPEN && p->nx < 8) return false;
   if (!std::isfinite(p->inflow) || std::fabs(p->inflow) >= 0.3) return false;
+  if (p->cover_momentum != 0 && p->cover_momentum != 1) return false;
   return true;
 }
 
@@ -165,6 +166,7 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.max_refill = std::max<int64_t>(4096, N / 16);
   l.refill = take((size_t)l.max_refill * 8);
   l.uo = take(p->boundary[0] == BND_OPEN ? (size_t)p->ny * p->nz * cs : 0);
+  l.cu = take((size_t)max_solids * 6 * 8);
   l.misc = take((size_t)64 + 16 * (size_t)max_solids + 64);
   l.total = o;
   *L = l;
@@ -692,6 +694,8 @@ lbm_status lbm_set_solids(lbm_ctx *c, const lbm_solid *s, int32_t n, int32_t met
                          c->stream));
   // the refill count and overflow flag (misc[3], misc[4]) and the free-solid flag (misc[6])
   HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 3 * sizeof(uint32_t), 0, 4 * sizeof(uint32_t), c->stream));
+  // no covering / uncovering momentum carried over from the previous solids
+  HIPCALL(hipMemsetAsync(c->ws + c->L.cu, 0, (size_t)c->L.max_solids * 6 * 8, c->stream));
   // the whole-cell shifts of a moving IBM shell (both slots: no shift yet)
   HIPCALL(hipMemsetAsync(c->ws + c->L.misc + 64 + 16 * (size_t)c->L.max_solids, 0, 8 * sizeof(int32_t), c->stream));
   HIPCALL(hipMemsetAsync(c->ws + c->L.flags, 0, (size_t)c->N, c->stream));

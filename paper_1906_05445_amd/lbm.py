@@ -43,7 +43,7 @@ class lbm_params(ctypes.Structure):
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("rates", ctypes.POINTER(ctypes.c_double)),
                 ("body_force", ctypes.c_double * 3), ("body_force_fluid_only", ctypes.c_int32),
-                ("boundary", ctypes.c_int32 * 3), ("inflow", ctypes.c_double)]
+                ("boundary", ctypes.c_int32 * 3), ("inflow", ctypes.c_double), ("cover_momentum", ctypes.c_int32)]
 
 
 class lbm_solid(ctypes.Structure):
@@ -151,7 +151,8 @@ DOMAINS = {"periodic": 0, "slip": 1, "open": 2}
 
 
 def make_params(lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
-                g=(0.0, 0.0, 0.0), g_fluid_only=True, boundary=("periodic", "periodic", "periodic"), inflow=0.0):
+                g=(0.0, 0.0, 0.0), g_fluid_only=True, boundary=("periodic", "periodic", "periodic"), inflow=0.0,
+                cover_momentum=False):
     """boundary: per axis "periodic", "slip" (stress-free planes) or, on x, "open"
     (velocity inlet `inflow` at x = 0, convective outflow at the last layer): Sec. 3.4."""
     p = lbm_params()
@@ -173,6 +174,7 @@ def make_params(lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 
     for k in range(3):
         p.boundary[k] = DOMAINS[bnd[k]]
     p.inflow = float(inflow)
+    p.cover_momentum = int(bool(cover_momentum))
     return p, keep
 
 
@@ -321,11 +323,12 @@ class Lattice(_Context):
 
     def __init__(self, lattice="D3Q19", collision="MRT", storage="F64", shape=(16, 16, 16), tau=0.8, rates=None,
                  g=(0.0, 0.0, 0.0), g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0,
-                 stream=None, device="cuda", boundary=("periodic", "periodic", "periodic"), inflow=0.0):
+                 stream=None, device="cuda", boundary=("periodic", "periodic", "periodic"), inflow=0.0,
+                 cover_momentum=False):
         import torch
         self._torch = torch
         params, self._rates = make_params(lattice, collision, storage, shape, tau, rates, g, g_fluid_only,
-                                          boundary, inflow)
+                                          boundary, inflow, cover_momentum)
         self._describe(lattice, params)
         nbytes = _lib.lbm_workspace_bytes(ctypes.byref(self.params), max_solids, max_links, max_lagrangian)
         if nbytes == 0:
@@ -451,10 +454,10 @@ class Batch:
 
     def admit(self, collision="MRT", storage="F32", shape=(16, 16, 16), tau=0.8, rates=None, g=(0.0, 0.0, 0.0),
               g_fluid_only=True, max_solids=1, max_links=0, max_lagrangian=0,
-              boundary=("periodic", "periodic", "periodic"), inflow=0.0):
+              boundary=("periodic", "periodic", "periodic"), inflow=0.0, cover_momentum=False):
         """A new Member, or None when the pool or the slots are full (LBM_EAGAIN)."""
         params, keep = make_params(self.lattice, collision, storage, shape, tau, rates, g, g_fluid_only,
-                                   boundary, inflow)
+                                   boundary, inflow, cover_momentum)
         h = _vp()
         st = _lib.lbm_batch_admit(self.handle, ctypes.byref(params), int(max_solids), int(max_links),
                                   int(max_lagrangian), ctypes.byref(h))

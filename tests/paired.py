@@ -24,7 +24,7 @@ def force_terms(orc):
 
 
 _MUTATORS = {"set_solids", "set_lagrangian", "set_ibm_iters", "set_ibm_delta", "set_ibm_inner", "step", "set_f",
-             "set_h", "set_free", "set_threads", "set_boundaries"}
+             "set_h", "set_free", "set_threads", "set_boundaries", "set_cover"}
 
 
 class PairedOracle:

@@ -143,3 +143,53 @@ def test_single_point_direct_forcing_recurrence(lat, delta, n_iter, form):
     _, u, _ = o.macros()
     expect = U0[:, None] + 0.5 * (g[:, None] + fib) / rho0
     assert np.max(np.abs(u - expect)) <= 1e-15
+
+
+@pytest.mark.parametrize("form", ["f", "h"])
+def test_comoving_cover_momentum(form):
+    """Covering and uncovering momentum (R38) in the co-moving state.  Every
+    fluid node holds f_eq(1, U), whose momentum is U, and a node the solid
+    uncovers is refilled with f_eq(1, U) as well; Eq. 17 sums to zero force.
+    So the force and torque a step reports with the correction, less those of
+    the same run without it, are U times (nodes covered - nodes uncovered) by
+    the move before it and the sum of r x U over them (r from the solid's
+    centre after that move, shortest periodic image): counts taken from the
+    node flags, the lever arms from the prescribed motion."""
+    U = np.array([0.045, -0.03, 0.025])
+    c0 = np.array([10.3, 8.6, 7.9])
+    L = np.array(SHAPE, dtype=float)
+    s = W.solid("sphere", tuple(c0), 4.6, velocity=tuple(U))
+    o = Oracle("D3Q19", "MRT", SHAPE, 0.8, form=form)
+    o.set_solids([s], "QUADRATIC")
+    o.set_cover(True)
+    _uniform(o, U)
+    x, y, z = np.meshgrid(*(np.arange(n) for n in SHAPE), indexing="ij")
+    pos = np.stack([a.transpose(2, 1, 0).ravel() for a in (x, y, z)], axis=1)  # cell n = x + nx (y + ny z)
+    expect, moved = [], 0
+    ex0, _, _ = o.node_flags()
+    for t in range(40):
+        o.step(1)
+        ex1, _, _ = o.node_flags()
+        cov, unc = (ex0 == 0) & (ex1 != 0), (ex0 != 0) & (ex1 == 0)
+        moved += int(cov.sum() + unc.sum())
+        Y = np.mod(c0 + (t + 1) * U, L)
+        r = pos - Y
+        r -= L * np.round(r / L)
+        F = U * (cov.sum() - unc.sum())
+        T = np.cross(r[cov], U).sum(axis=0) - np.cross(r[unc], U).sum(axis=0)
+        expect.append(np.concatenate([F, T]))
+        ex0 = ex1
+    # off: the same run (the fluid does not depend on the setting) reports Eq. 17 alone, zero force
+    o2 = Oracle("D3Q19", "MRT", SHAPE, 0.8, form=form)
+    o2.set_solids([s], "QUADRATIC")
+    _uniform(o2, U)
+    o2.step(40)
+    H0 = o2.history()
+    assert np.max(np.abs(H0[:, 0, :3])) <= 1e-13
+    H = o.history()
+    assert moved > 50  # the solid covers and uncovers nodes on most steps
+    got = H[1:, 0, :] - H0[1:, 0, :]  # the force of step t + 1 carries the move of step t
+    want = np.array(expect[:-1])
+    assert np.max(np.abs(got[:, :3] - want[:, :3])) <= 1e-13
+    assert np.max(np.abs(got[:, 3:] - want[:, 3:])) <= 1e-12
+    assert np.array_equal(H[0], H0[0])  # nothing moved before the first step
