@@ -123,3 +123,41 @@ def test_degenerate_periodic_boxes(lbm, lat, shape):
     assert np.max(np.abs(ug - uo)) <= 1e-12 * max(np.max(np.abs(uo)), 1e-300)
     assert np.max(np.abs(rg - ro)) <= 1e-12
     gpu.close()
+
+
+def test_rejected_set_solids_leaves_the_context_unchanged(lbm):
+    """An IBM set-up, then a call rejected on its options (a moving sphere with a 5-point delta): the
+    context steps on bit for bit as one that never saw the rejected call."""
+    shape, g = (26, 22, 20), (2e-6, 0.0, 0.0)
+    fixed = [W.solid("sphere", (12.3, 10.6, 9.2), 4.7)]
+    a = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_lagrangian=600)
+    b = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_lagrangian=600)
+    for c in (a, b):
+        c.set_solids(fixed, "IBM", n_iter=3)
+        c.step(5)
+    with pytest.raises(lbm.LBMError) as e:
+        a.set_solids([W.solid("sphere", (12.3, 10.6, 9.2), 4.7, velocity=(0.01, 0.0, 0.0))], "IBM", delta=5)
+    assert e.value.status == lbm.LBM_EINVAL
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.get_state().view(np.uint64), b.get_state().view(np.uint64))
+    assert np.array_equal(a.history().view(np.uint64), b.history().view(np.uint64))
+    a.close()
+    b.close()
+
+
+def test_failed_set_solids_leaves_a_plain_lattice(lbm):
+    """A set-up that fails late (more links than max_links): the context has no solids, and steps as a
+    lattice that never had any."""
+    shape, g = (24, 24, 24), (1e-6, 0.0, 0.0)
+    a = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_links=200)
+    b = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_links=200)
+    with pytest.raises(lbm.LBMError) as e:
+        a.set_solids([W.solid("sphere", (12.2, 11.8, 12.1), 6.0)], "QUADRATIC")
+    assert e.value.status == lbm.LBM_ENOMEM
+    a.step(12)
+    b.step(12)
+    assert np.array_equal(a.get_state().view(np.uint64), b.get_state().view(np.uint64))
+    assert np.all(a.node_types() != 1)
+    a.close()
+    b.close()
