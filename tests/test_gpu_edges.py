@@ -130,8 +130,9 @@ def test_rejected_set_solids_leaves_the_context_unchanged(lbm):
     context steps on bit for bit as one that never saw the rejected call."""
     shape, g = (26, 22, 20), (2e-6, 0.0, 0.0)
     fixed = [W.solid("sphere", (12.3, 10.6, 9.2), 4.7)]
-    a = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_lagrangian=600)
-    b = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, max_lagrangian=600)
+    # body force on every node: a moving IBM sphere is allowed, so the 5-point delta is what is rejected
+    a = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, g_fluid_only=False, max_lagrangian=600)
+    b = lbm.Lattice("D3Q19", "MRT", "F64", shape, 0.8, g=g, g_fluid_only=False, max_lagrangian=600)
     for c in (a, b):
         c.set_solids(fixed, "IBM", n_iter=3)
         c.step(5)
