@@ -139,7 +139,7 @@ typedef struct {
   int32_t lattice;    /* lbm_lattice */
   int32_t collision;  /* lbm_collision */
   int32_t storage;    /* lbm_storage */
-  int32_t nx, ny, nz; /* nz == 1 for D2Q9 */
+  int32_t nx, ny, nz; /* nz == 1 for D2Q9; fewer than 2^31 cells */
   double tau;
   const double *rates;
   double body_force[3];

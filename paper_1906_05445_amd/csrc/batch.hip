@@ -492,6 +492,9 @@ lbm_status lbm_batch_admit(lbm_batch *b, const lbm_params *p, int32_t max_solids
   if (!need) return berr(b, LBM_EINVAL, "invalid lattice parameters");
   if (p->boundary[0] != BND_PERIODIC || p->boundary[1] != BND_PERIODIC || p->boundary[2] != BND_PERIODIC)
     return berr(b, LBM_EUNSUPPORTED, "batches take periodic lattices");
+  // the batched sweep forms offsets in 32 bits
+  if ((double)p->nx * p->ny * p->nz * (p->lattice == LBM_D2Q9 ? 9 : 19) >= 2147483648.0)
+    return berr(b, LBM_EINVAL, "a batch member holds fewer than 2^31 values per population array");
   int slot = -1;
   for (int k = 0; k < b->max_slots; k++)
     if (!b->mem[(size_t)k].c) {

@@ -18,7 +18,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchSlot *__restr
     const int cur = SLOT(m, cur0) ^ par;
     SweepArgs a = SLOT(m, sw);
     a.seed = sr_seed(SLOT(m, t0) + *step);
-    sweep_body<Q, COLL, S, 1, NT, 0>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])),
+    // (a member holds fewer than 2^31 values per array: 32-bit offsets)
+    sweep_body<Q, COLL, S, 1, NT, 0, 1>(static_cast<const S *>(SLOT(m, P[cur])), static_cast<S *>(SLOT(m, P[cur ^ 1])),
                                      a, nullptr, blk);
   });
 }

@@ -16,9 +16,9 @@
 
 namespace lbm {
 
-// Bounded domains always take the flag variant (solids or not) and 32-bit
-// offsets (N Q < 2^31 is required of every lattice), and always store with
-// non-temporal hints: the tuner's choice of store hint does not apply.
+// Bounded domains always take the flag variant (solids or not), and always
+// store with non-temporal hints: the tuner's choice of store hint does not
+// apply.  Offsets are 32-bit when the arrays hold fewer than 2^32 values.
 template <typename S>
 static void sweep_bnd_dispatch(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, const SweepLinkArgs &la,
                                int coll, int inl, hipEvent_t e0, hipEvent_t e1) {
@@ -27,9 +27,15 @@ static void sweep_bnd_dispatch(lbm_ctx *c, const void *A, void *B, const SweepAr
       (tiles + sweep_cpt_of<S>() - 1) / sweep_cpt_of<S>() + a.rblocks + a.iblocks + (inl ? la.cblocks : 0u);
   const S *As = static_cast<const S *>(A);
   S *Bs = static_cast<S *>(B);
-#define LBM_SWEEP_BND(QQ, CC, II)                                                                              \
-  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, 1, 1, II, 1, 1>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, 0, \
-                        As, Bs, a, la)
+  const bool idx32 = (uint64_t)c->Q * c->L.stride < (1ull << 32);
+#define LBM_SWEEP_BND1(QQ, CC, II, XX)                                                                         \
+  hipExtLaunchKernelGGL((k_sweep<QQ, CC, S, 1, 1, II, XX, 1>), dim3(grid), dim3(kBlock), 0, c->stream, e0, e1, \
+                        0, As, Bs, a, la)
+#define LBM_SWEEP_BND(QQ, CC, II)                \
+  do {                                           \
+    if (idx32) LBM_SWEEP_BND1(QQ, CC, II, 1);    \
+    else LBM_SWEEP_BND1(QQ, CC, II, 0);          \
+  } while (0)
 #define LBM_SWEEP_BND2(QQ, CC)                 \
   do {                                         \
     if (inl == 2) LBM_SWEEP_BND(QQ, CC, 2);    \
@@ -47,6 +53,7 @@ static void sweep_bnd_dispatch(lbm_ctx *c, const void *A, void *B, const SweepAr
   }
 #undef LBM_SWEEP_BND2
 #undef LBM_SWEEP_BND
+#undef LBM_SWEEP_BND1
 }
 
 void launch_sweep_bnd(lbm_ctx *c, const void *A, void *B, const SweepArgs &a, const SweepLinkArgs &la, int coll,
@@ -83,10 +90,10 @@ __global__ __launch_bounds__(256) void k_outflow(const S *__restrict__ A, S *__r
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     if (L::ex(i) >= 0) continue;
-    const C old = Store<S>::ld(A + pidx32<Q>(opp(i), n));
+    const C old = Store<S>::ld(A + pidx<Q>(opp(i), n));
     const BndSrc s = bnd_src(L::ex(i), L::ey(i), L::ez(i), x - 1, y, z, (int)a.nx, (int)a.ny, (int)a.nz, a.bc);
-    const C up = Store<S>::ld(B + pidx32<Q>(bnd_dir<Q>(i, s), s.cell));
-    B[pidx32<Q>(opp(i), n)] = store_value<S, C>((old + U * up) / (C(1) + U), a.sr != 0,
+    const C up = Store<S>::ld(B + pidx<Q>(bnd_dir<Q>(i, s), s.cell));
+    B[pidx<Q>(opp(i), n)] = store_value<S, C>((old + U * up) / (C(1) + U), a.sr != 0,
                                                 a.sr ? hash32((n * 32u + (uint32_t)opp(i)) ^ a.seed) >> 19 : 0u);
   }
 }

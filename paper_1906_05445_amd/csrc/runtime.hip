@@ -67,8 +67,10 @@ bool valid_params(const lbm_params *p) {
   if (p->storage < LBM_F64 || p->storage > LBM_F16_SR) return false;
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return false;
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return false;
+  // cell indices are 32-bit (and sums of two of them stay below 2^32); offsets
+  // into the population arrays are 64-bit where Q * cells reaches 2^32
   const double N = (double)p->nx * p->ny * p->nz;
-  if (N * qof(p->lattice) >= 2147483647.0) return false;  // 32-bit in-lattice offsets
+  if (N >= 2147483648.0) return false;
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
   for (int k = 0; k < 3; k++)
     if (!std::isfinite(p->body_force[k])) return false;

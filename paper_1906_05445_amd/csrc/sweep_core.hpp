@@ -53,7 +53,7 @@ __device__ __forceinline__ void sweep_pull(const S *__restrict__ A, const SweepA
 // Pull of cell n on a bounded domain: each direction from where bnd_src
 // keeps it.  Returns the mask of directions that take the inlet term; uo_at
 // is the cell's index in the outlet plane (y + ny z), or ~0u.
-template <int Q, typename S>
+template <int Q, typename S, int IDX32>
 __device__ __forceinline__ uint32_t sweep_pull_bnd(const S *__restrict__ A, const SweepArgs &a, uint32_t n,
                                                    S (&r)[Q], uint32_t &uo_at) {
   using L = Lat<Q>;
@@ -65,7 +65,8 @@ __device__ __forceinline__ uint32_t sweep_pull_bnd(const S *__restrict__ A, cons
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const BndSrc s = bnd_src(L::ex(i), L::ey(i), L::ez(i), x, y, z, (int)a.nx, (int)a.ny, (int)a.nz, a.bc);
-    r[i] = A[pidx32<Q>(bnd_dir<Q>(i, s), s.cell)];
+    if constexpr (IDX32 != 0) r[i] = A[pidx32<Q>(bnd_dir<Q>(i, s), s.cell)];
+    else r[i] = A[pidx<Q>(bnd_dir<Q>(i, s), s.cell)];
     if (s.inlet) inl |= 1u << i;
   }
   uo_at = (a.bc[0] == BND_OPEN && x == (int)a.nx - 1) ? yz : ~0u;
@@ -416,7 +417,7 @@ __device__ __forceinline__ void sweep_body(const S *__restrict__ A, S *__restric
   uint32_t inm[CPT], uo_at[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; c++) {
-    if constexpr (BND != 0) inm[c] = sweep_pull_bnd<Q, S>(A, a, act[c] ? n[c] : a.N - 1, r[c], uo_at[c]);
+    if constexpr (BND != 0) inm[c] = sweep_pull_bnd<Q, S, IDX32>(A, a, act[c] ? n[c] : a.N - 1, r[c], uo_at[c]);
     else {
       sweep_pull<Q, S, IDX32>(A, a, act[c] ? n[c] : a.N - 1, r[c]);
       inm[c] = 0u;

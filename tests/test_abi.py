@@ -100,3 +100,16 @@ def test_domain_boundaries_validate():
     assert nbytes("D3Q19", (32, 24, 20), ("open", "slip", "slip"), 0.3) == 0
     assert nbytes("D2Q9", (32, 24, 1), ("open", "slip", "periodic"), 0.05) > 0
     assert nbytes("D2Q9", (32, 24, 1), ("open", "slip", "slip")) == 0
+
+
+def test_lattice_size_limit():
+    """Up to 2^31 - 1 cells (32-bit cell indices); population offsets are 64-bit, so the arrays may hold
+    more than 2^31 values."""
+    from paper_1906_05445_amd import lbm
+
+    def nbytes(shape):
+        p, _ = lbm.make_params("D3Q19", "MRT", "F32", shape, 0.8)
+        return lbm._lib.lbm_workspace_bytes(ctypes.byref(p), 1, 4096, 1024)
+
+    assert nbytes((1152, 576, 576)) > 0          # 3.8e8 cells, 7.3e9 values per array
+    assert nbytes((2048, 1024, 1024)) == 0       # 2^31 cells
