@@ -179,13 +179,14 @@ def copy_probe(torch, lbm, nbytes=4 << 30, reps=20, warm=3):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def run_open_sphere(torch, lbm, W, steps, chunk=1000, **kw):
+def run_open_sphere(torch, lbm, W, steps, chunk=1000, tol=None, **kw):
     """The sphere of Sec. 3.4 (uniform inflow, stress-free sides, convective outflow) from a uniform
     stream: whole-step throughput, and the drag coefficient at the end with its change over the last
-    chunk, beside the standard correlation (a sanity reference)."""
+    chunk, beside the standard correlation (a sanity reference).  tol: stop once C_D changes by less
+    than tol (relative) over a chunk, else after `steps`."""
     case = W.open_sphere(**kw)
     gpu = lbm.Lattice(case.lattice, case.collision, case.storage, case.shape, case.tau, max_solids=1,
-                      boundary=case.boundary, inflow=case.inflow)
+                      max_links=4_000_000, max_lagrangian=1024, boundary=case.boundary, inflow=case.inflow)
     gpu.set_solids(case.solids, case.method)
     gpu.set_equilibrium(1.0, (case.inflow, 0.0, 0.0))
     gpu.step(TUNER_STEPS)
@@ -205,6 +206,10 @@ def run_open_sphere(torch, lbm, W, steps, chunk=1000, **kw):
         ms += e0.elapsed_time(e1)
         done += k
         cd.append(W.drag_coefficient(float(gpu.force_torque()[0, 0]), Re, nu))
+        if len(cd) % 5 == 0:
+            log(f"#   {case.name}: {done} steps, C_D {cd[-1]:.5f}")
+        if tol is not None and len(cd) > 1 and abs(cd[-1] - cd[-2]) <= tol * abs(cd[-1]):
+            break
     ok = gpu.check()
     gpu.close()
     N = case.shape[0] * case.shape[1] * case.shape[2]
@@ -474,6 +479,19 @@ def main():
         if wanted("open", key):
             r = run_case(W.open_sphere(method="QUADRATIC"), k2, Wm, key, torch, lbm)
             extra(key, r, f"{r['mlups']:.0f} MLUPS, step frac {r['roofline']['frac']:.3f}")
+    if "open_resolution" in want:
+        # Sec. 3.4's resolution question for Zhao-Yong at Re_p = 20: D = 16, 32 and 48 (the paper's largest:
+        # 1152 x 576 x 576, 3.8e8 cells) at the viscosity of the D = 16 case (the paper keeps nu fixed), each
+        # run until C_D changes by less than 1e-5 over 1000 steps
+        res = {}
+        for D, cap in ((16, 30000), (32, 50000), (48, 60000)):
+            r = run_open_sphere(torch, lbm, W, cap, tol=1e-5, D=float(D), nu=0.04)
+            res[f"D{D}"] = r
+            log(f"# open sphere D = {D}: C_D {r['C_D']:.5f} after {r['steps']} steps, {r['mlups']:.0f} MLUPS")
+        hi = res["D48"]["C_D"]
+        extra("open_sphere_resolution_re20_zhao_yong",
+              {"runs": res, "rel_diff_to_D48": {k: v["C_D"] / hi - 1.0 for k, v in res.items()}},
+              ", ".join(f"{k}: {v['C_D'] / hi - 1.0:+.4f}" for k, v in res.items()) + " relative to D48")
     if "copy" in want:
         c = copy_probe(torch, lbm)
         extra("hbm_copy_GBps", c, f"{c:.0f} GB/s")

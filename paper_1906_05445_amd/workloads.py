@@ -206,14 +206,17 @@ def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, st
                 meta={"U_set": U_set, "density": density}, g_fluid_only=not ibm)
 
 
-def open_sphere(D=16.0, Re=20.0, U=0.05, method="ZHAO_YONG", storage="F32", steps=20000, seed=6):
+def open_sphere(D=16.0, Re=20.0, U=0.05, method="ZHAO_YONG", storage="F32", steps=20000, seed=6, nu=None):
     """The sphere of Sec. 3.4: diameter D fixed at (6D, 6D, 6D) (plus a seed-drawn sub-node offset) in a
     24D x 12D x 12D box, uniform inflow U at x = 0, stress-free sides, convective outflow; nu from
-    Re_p = U D / nu.  D3Q19 MRT."""
+    Re_p = U D / nu, or, given nu (the paper keeps nu fixed as it refines), U from it.  D3Q19 MRT."""
     rng = np.random.default_rng(seed)
     n = (int(round(24 * D)), int(round(12 * D)), int(round(12 * D)))
     c = np.array([6 * D, 6 * D, 6 * D]) + 0.5 * rng.random(3)
-    nu = U * D / Re
+    if nu is None:
+        nu = U * D / Re
+    else:
+        U = Re * nu / D
     return Case(f"open_sphere_D{D:g}_Re{Re:g}", "D3Q19", "MRT", n, tau_of_nu(nu), (0.0, 0.0, 0.0),
                 [solid("sphere", c, D / 2.0)], method, steps, storage, meta={"Re": Re, "U_ref": U, "D": D},
                 boundary=("open", "slip", "slip"), inflow=U)
