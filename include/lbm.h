@@ -209,7 +209,15 @@ typedef struct {
  * IBB boundary links (Sec. 2.2: one per fluid node and direction whose
  * neighbour across the wall is a solid node), max_lagrangian the number of
  * IBM points (Sec. 2.1, Eq. 5-9); 0 selects a bound computed from the
- * lattice size.  Returns 0 for invalid parameters. */
+ * lattice size (N / 2 links, max(1024, N / 64) points).  The IBM shell
+ * (the cells within the points' delta supports) may hold min(N, 16 x the
+ * point capacity) cells: a mesh of about one point per unit area needs 4 to
+ * 8 per point, and a sparser one may give LBM_ENOMEM from lbm_set_solids.
+ * A negative
+ * max_lagrangian reserves no IBM space at all (no points, shell or spread
+ * force field: 3 N force values fewer), for contexts that never take IBM
+ * solids; lbm_set_solids with LBM_IBM and lbm_set_lagrangian then give
+ * LBM_ENOMEM.  Returns 0 for invalid parameters. */
 size_t lbm_workspace_bytes(const lbm_params *p, int32_t max_solids, int64_t max_links,
                            int64_t max_lagrangian);
 

@@ -35,6 +35,7 @@ enum {
   WL_FT,
   WL_BOX,        // (solid, box chunk) units of members with translating solids
   WL_ONE,        // one unit per member with translating solids
+  WL_BOX_MULTI,  // the WL_BOX units of those members that hold several solids
   WL_IBM_SPREAD,  // kSpreadCellsPerBlock shell cells per unit (kSpreadLanes lanes per cell)
   WL_IBM_LAG,
   WL_IBM_FT,
@@ -98,7 +99,7 @@ struct lbm_batch {
   bool dirty = true;
   int nlive = 0;
   uint32_t coll_mask = 0;
-  bool any_ibb = false, any_moving = false, any_ibm = false;
+  bool any_ibb = false, any_moving = false, any_multi = false, any_ibm = false;
   int max_iter = 0;
   uint64_t tiles = 0;
   // graphs
@@ -197,7 +198,7 @@ lbm_status rebuild(lbm_batch *b) {
   std::vector<std::vector<int32_t>> who(WL_COUNT);
   b->nlive = 0;
   b->coll_mask = 0;
-  b->any_ibb = b->any_moving = b->any_ibm = false;
+  b->any_ibb = b->any_moving = b->any_multi = b->any_ibm = false;
   b->max_iter = 0;
   b->tiles = 0;
   for (int k = 0; k < S; k++) {
@@ -245,6 +246,10 @@ lbm_status rebuild(lbm_batch *b) {
         b->any_moving = true;
         add(WL_BOX, (uint64_t)c->max_box_chunks * c->nsolid);
         add(WL_ONE, 1);
+        if (c->nsolid > 1) {
+          b->any_multi = true;
+          add(WL_BOX_MULTI, (uint64_t)c->max_box_chunks * c->nsolid);
+        }
       }
     }
     if (c->nsolid > 0) add(WL_SOLID, 1);
@@ -325,7 +330,8 @@ void enqueue_step(lbm_batch *b, const SweepCfg &cfg, hipEvent_t e0, hipEvent_t e
   if (b->any_ibb) {
     launch_ibb_batch(bl, b->wl(WL_IBB), grid_of(b, 32));
     launch_ft_batch(bl, b->wl(WL_FT), std::min<uint32_t>(grid_of(b, 4), 1024));
-    if (b->any_moving) launch_move_batch(bl, b->wl(WL_BOX), b->wl(WL_ONE), grid_of(b, 8));
+    if (b->any_moving)
+      launch_move_batch(bl, b->wl(WL_BOX), b->wl(WL_BOX_MULTI), b->wl(WL_ONE), b->any_multi, grid_of(b, 8));
   }
   launch_tick(b->stream, b->d_step);
 }
@@ -342,6 +348,7 @@ uint64_t graph_key_of(const lbm_batch *b) {
   k = k * 8 + b->coll_mask;
   k = k * 2 + (b->any_ibb ? 1 : 0);
   k = k * 2 + (b->any_moving ? 1 : 0);
+  k = k * 2 + (b->any_multi ? 1 : 0);
   k = k * 2 + (b->any_ibm ? 1 : 0);
   k = k * 64 + (uint64_t)b->max_iter;
   k = k * 64 + (uint64_t)b->chosen;

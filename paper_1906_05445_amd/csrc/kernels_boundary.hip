@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void k_ft_batch(const BatchSlot *__restrict__ 
   });
 }
 
-// translating solids move to t + 1: keep, classify, count (with refill),
+// translating solids move to t + 1: keep and classify, refill with count,
 // scan, emit -- each over the (solid, box chunk) units of the moving members
 __device__ inline LinkArgs move_args(const BatchSlot *slots, int m, int64_t k) {
   LinkArgs a = SLOT(m, lk);
@@ -837,6 +837,9 @@ __device__ inline LinkArgs move_args(const BatchSlot *slots, int m, int64_t k) {
   a.post = slot_post(slots, m, k);
   return a;
 }
+// (a member with one solid classifies in the same pass: no other box can meet
+// its box, so each box cell is one thread's in both phases; members with
+// several solids classify in k_classify_box_batch, over their own work list)
 __global__ __launch_bounds__(kBlock) void k_classify_keep_batch(const BatchSlot *__restrict__ slots,
                                                                 const WorkList *__restrict__ wl,
                                                                 const int64_t *__restrict__ step) {
@@ -844,7 +847,9 @@ __global__ __launch_bounds__(kBlock) void k_classify_keep_batch(const BatchSlot 
   batch_units(wl, 0, [&](int m, uint32_t u) {
     const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
-    classify_keep_body(a, u - (uint32_t)s * a.max_box_chunks, s);
+    const uint32_t bx = u - (uint32_t)s * a.max_box_chunks;
+    classify_keep_body(a, bx, s);
+    if (SLOT(m, nsolid) == 1) classify_box_body(a, bx, s);
   });
 }
 __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *__restrict__ slots,
@@ -857,27 +862,30 @@ __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *
     classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
 }
-template <int Q>
-__global__ __launch_bounds__(kBlock) void k_link_count_batch(const BatchSlot *__restrict__ slots,
-                                                             const WorkList *__restrict__ wl,
-                                                             const int64_t *__restrict__ step) {
+// Refill and link count in one launch (both read only the finished
+// classification; the refill writes populations, the count flags and owners
+// it does not touch): blocks 0 .. kRefillBatchBlocks-1 walk the members with
+// translating solids, one block of four waves per member refilling its list,
+// the others the (solid, box chunk) units of the count.
+constexpr uint32_t kRefillBatchBlocks = 256;
+template <int Q, typename S>
+__global__ __launch_bounds__(kBlock) void k_refill_count_batch(const BatchSlot *__restrict__ slots,
+                                                               const WorkList *__restrict__ one,
+                                                               const WorkList *__restrict__ box,
+                                                               const int64_t *__restrict__ step) {
   const int64_t k = *step;
-  batch_units(wl, 0, [&](int m, uint32_t u) {
+  if (blockIdx.x < kRefillBatchBlocks) {
+    batch_units_in(one, 0, blockIdx.x, kRefillBatchBlocks, [&](int m, uint32_t) {
+      const LinkArgs a = move_args(slots, m, k);
+      const uint32_t cnt = min(a.misc[3], a.max_refill);
+      for (uint32_t e = threadIdx.x >> 6; e < cnt; e += kBlock / 64) refill_wave<Q, S>(a, a.refill_list[e]);
+    });
+    return;
+  }
+  batch_units_in(box, 0, blockIdx.x - kRefillBatchBlocks, gridDim.x - kRefillBatchBlocks, [&](int m, uint32_t u) {
     const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     link_count_body<Q>(a, u - (uint32_t)s * a.max_box_chunks, s);
-  });
-}
-// refill: one unit (a block of four waves) per member with translating solids
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void k_refill_batch(const BatchSlot *__restrict__ slots,
-                                                      const WorkList *__restrict__ wl,
-                                                      const int64_t *__restrict__ step) {
-  const int64_t k = *step;
-  batch_units(wl, 0, [&](int m, uint32_t) {
-    const LinkArgs a = move_args(slots, m, k);
-    const uint32_t cnt = min(a.misc[3], a.max_refill);
-    for (uint32_t e = threadIdx.x >> 6; e < cnt; e += 4) refill_wave<Q, S>(a, a.refill_list[e]);
   });
 }
 // one unit per member; also folds the capacity checks into its status words
@@ -980,24 +988,24 @@ void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
   hipLaunchKernelGGL(k_ft_batch, dim3(grid), dim3(256), 0, b.stream, b.slots, wl, b.step);
 }
 
-void launch_move_batch(const BatchLaunch &b, const WorkList *box, const WorkList *one, uint32_t grid) {
+void launch_move_batch(const BatchLaunch &b, const WorkList *box, const WorkList *boxm, const WorkList *one,
+                       bool any_multi, uint32_t grid) {
   const dim3 g(grid), blk(kBlock);
   hipLaunchKernelGGL(k_classify_keep_batch, g, blk, 0, b.stream, b.slots, box, b.step);
-  hipLaunchKernelGGL(k_classify_box_batch, g, blk, 0, b.stream, b.slots, box, b.step);
-  const dim3 g1(std::min<uint32_t>(grid, 1024));
-#define LBM_RF(QQ, SS) hipLaunchKernelGGL((k_refill_batch<QQ, SS>), g1, dim3(256), 0, b.stream, b.slots, one, b.step)
+  if (any_multi) hipLaunchKernelGGL(k_classify_box_batch, g, blk, 0, b.stream, b.slots, boxm, b.step);
+  const dim3 g1(kRefillBatchBlocks + grid);
+#define LBM_RC(QQ, SS) \
+  hipLaunchKernelGGL((k_refill_count_batch<QQ, SS>), g1, blk, 0, b.stream, b.slots, one, box, b.step)
   if (b.Q == 9) {
-    if (b.storage == LBM_F64) LBM_RF(9, double);
-    else if (b.storage == LBM_F32_DEV) LBM_RF(9, float);
-    else LBM_RF(9, _Float16);
+    if (b.storage == LBM_F64) LBM_RC(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_RC(9, float);
+    else LBM_RC(9, _Float16);
   } else {
-    if (b.storage == LBM_F64) LBM_RF(19, double);
-    else if (b.storage == LBM_F32_DEV) LBM_RF(19, float);
-    else LBM_RF(19, _Float16);
+    if (b.storage == LBM_F64) LBM_RC(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_RC(19, float);
+    else LBM_RC(19, _Float16);
   }
-#undef LBM_RF
-  if (b.Q == 9) hipLaunchKernelGGL(k_link_count_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
-  else hipLaunchKernelGGL(k_link_count_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
+#undef LBM_RC
   hipLaunchKernelGGL(k_link_scan_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, one);
   if (b.Q == 9) hipLaunchKernelGGL(k_link_emit_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
   else hipLaunchKernelGGL(k_link_emit_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);

@@ -319,23 +319,24 @@ __device__ inline int batch_member_of(const WorkList &wl, uint32_t u) {
   return k;
 }
 
-// Persistent walk over the units of a work list: order 0 gives each block a
-// contiguous share, order 1 deals the units out round-robin.  f(slot, local
-// unit) is called with the same trip count by every thread of the block.
+// Persistent walk over the units of a work list by blocks blk of nblk: order 0
+// gives each block a contiguous share, order 1 deals the units out
+// round-robin.  f(slot, local unit) is called with the same trip count by
+// every thread of the block.
 template <typename F>
-__device__ inline void batch_units(const WorkList *wlp, int order, F f) {
+__device__ inline void batch_units_in(const WorkList *wlp, int order, uint32_t blk, uint32_t nblk, F f) {
   const WorkList wl = load_uniform(wlp);
   const uint32_t total = wl.total;
   uint32_t u, end, inc;
   if (order == 0) {
-    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
-    u = blockIdx.x * per;
+    const uint32_t per = (total + nblk - 1) / nblk;
+    u = blk * per;
     end = min(total, u + per);
     inc = 1;
   } else {
-    u = blockIdx.x;
+    u = blk;
     end = total;
-    inc = gridDim.x;
+    inc = nblk;
   }
   if (u >= end) return;
   int k = batch_member_of(wl, u);
@@ -348,6 +349,11 @@ __device__ inline void batch_units(const WorkList *wlp, int order, F f) {
     }
     f(load_uniform(wl.slot + k), u - lo);
   }
+}
+// ... by all blocks of the grid
+template <typename F>
+__device__ inline void batch_units(const WorkList *wlp, int order, F f) {
+  batch_units_in(wlp, order, blockIdx.x, gridDim.x, f);
 }
 
 // Block-uniform field of member m.
@@ -379,7 +385,8 @@ void launch_tick(hipStream_t s, int64_t *step);
 void launch_ibb_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid);
 void launch_force_change(const BatchLaunch &b, const WorkList *wl, int64_t lag, double *out, uint32_t grid);
-void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_one, uint32_t grid);
+void launch_move_batch(const BatchLaunch &b, const WorkList *wl_box, const WorkList *wl_box_multi,
+                       const WorkList *wl_one, bool any_multi, uint32_t grid);
 void launch_ibm_batch(const BatchLaunch &b, const WorkList *wl_spread, const WorkList *wl_lag, const WorkList *wl_ft,
                       int max_iter, uint32_t grid);
 

@@ -111,14 +111,16 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   if (max_solids <= 0) max_solids = 1;
   if (max_solids > 65534) return false;
   if (max_links <= 0) max_links = std::max<int64_t>(65536, N / 2);
-  if (max_lag < 0) return false;
-  if (max_lag == 0) max_lag = std::max<int64_t>(1024, N / 64);
+  if (max_lag < 0) max_lag = 0;  // no IBM space
+  else if (max_lag == 0) max_lag = std::max<int64_t>(1024, N / 64);
   if (max_links >= (1ll << 32) || max_lag >= (1ll << 26)) return false;
   Layout l{};
   l.stride = (size_t)((N + kTile - 1) / kTile * kTile);  // whole tiles
   l.max_links = max_links;
   l.max_lag = max_lag;
-  l.max_shell = std::min<int64_t>(N, 64 * max_lag);
+  // cells in the points' delta supports: 16 per point of capacity (a mesh of
+  // about one point per unit area, Sec. 2.1, takes 4 to 8)
+  l.max_shell = std::min<int64_t>(N, 16 * max_lag);
   l.max_box_chunks = (N + kBlock - 1) / kBlock;
   l.max_partials = (max_links + kLinkChunk - 1) / kLinkChunk + max_solids;
   l.max_solids = max_solids;
@@ -146,7 +148,7 @@ bool make_layout(const lbm_params *p, int32_t max_solids, int64_t max_links, int
   l.solids = take((size_t)max_solids * sizeof(DevSolid));
   l.hist = take((size_t)kHistCap * max_solids * 6 * 8);
   l.staging = take((size_t)4 * N * 8);
-  l.fibm = take((size_t)3 * l.stride * cs);
+  l.fibm = take(max_lag > 0 ? (size_t)3 * l.stride * cs : 0);
   l.lag_X = take((size_t)max_lag * 24);
   l.lag_dV = take((size_t)max_lag * 8);
   l.lag_sid = take((size_t)max_lag * 4);

@@ -3,7 +3,8 @@
 Requests (a lattice, its solids and its boundary method) arrive over time.  A
 request is admitted as soon as the batch has a free slot and a free pool
 range of the request's footprint (``lbm_workspace_bytes``: populations, flags,
-links, Lagrangian data, history); its lattice then stays resident and is
+links, Lagrangian data, history, with link and point capacities sized to the
+request's solids); its lattice then stays resident and is
 advanced together with every other admitted lattice by the batch (continuous
 batching: members join and leave between check intervals while the others
 keep running).  Every ``check_every`` steps one device launch measures, per
@@ -16,6 +17,7 @@ Latency is split into queueing (arrival -> admission) and service (admission
 from __future__ import annotations
 
 import dataclasses
+import math
 import time
 from collections import deque
 from typing import Callable, Iterable, List, Optional
@@ -54,9 +56,35 @@ class Request:
         return None if self.finished is None or self.admitted is None else self.finished - self.admitted
 
 
-def footprint(lbm, case, max_links=0, max_lagrangian=0) -> int:
+def capacities(case):
+    """(max_links, max_lagrangian) that a request's solids need, or 0 for the
+    library's bound from the lattice size where no bound is known here.
+
+    A bounce-back sphere of radius R (D3Q19) has, for each direction e_i, one
+    link on every lattice line along e_i that holds a solid node (the first
+    fluid node past the solid run: the sphere is convex), so at most as many
+    as such lines pass within R of the centre.  Those lines cross the plane
+    normal to e_i in a 2-D lattice of |e_i| points per unit area whose
+    Voronoi cells lie within rho_i of their point (rho = sqrt(2)/2 for the
+    6 axis directions, sqrt(3/2)/2 for the 12 diagonal ones), which bounds
+    their number by |e_i| pi (R + rho_i)^2.  Such a request reserves no IBM
+    space (-1).  IBM requests keep the library's bounds: the point capacity
+    also sizes the table of the summed direct-forcing iterations, which a
+    tighter capacity could leave out (the iterations would then run one by
+    one)."""
+    if case.lattice != "D3Q19" or case.method == "IBM" or \
+            any(s["kind"] != "sphere" or s["inverted"] for s in case.solids):
+        return 0, 0
+    ra, rd = math.sqrt(2.0) / 2.0, math.sqrt(1.5) / 2.0
+    links = sum(6.0 * math.pi * (s["radius"] + ra) ** 2 + 12.0 * math.sqrt(2.0) * math.pi * (s["radius"] + rd) ** 2
+                for s in case.solids)
+    return int(links) + 64, -1
+
+
+def footprint(lbm, case, storage=None) -> int:
     """Device bytes a request takes in the pool (its context workspace)."""
-    return lbm.Batch.footprint(case.lattice, case.collision, case.storage, case.shape, case.tau,
+    max_links, max_lagrangian = capacities(case)
+    return lbm.Batch.footprint(case.lattice, case.collision, storage or case.storage, case.shape, case.tau,
                                max_solids=max(1, len(case.solids)), max_links=max_links,
                                max_lagrangian=max_lagrangian)
 
@@ -133,8 +161,10 @@ class Server:
         if req.footprint > self.pool_bytes:
             req.rejected = True
             return None
+        max_links, max_lagrangian = capacities(c)
         m = self.batch.admit(c.collision, self.storage, c.shape, c.tau, g=c.g,
-                             max_solids=max(1, len(c.solids)))
+                             max_solids=max(1, len(c.solids)), max_links=max_links,
+                             max_lagrangian=max_lagrangian)
         if m is None:
             return None
         m.set_solids(c.solids, c.method, n_iter=req.n_iter)
@@ -157,7 +187,7 @@ class Server:
         summary dict of ``stats``."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
-            r.footprint = footprint(self.lbm, r.case)
+            r.footprint = footprint(self.lbm, r.case, self.storage)
         pending = deque(reqs)
         adm = Admission(self._try_admit)
         t0 = self.clock()

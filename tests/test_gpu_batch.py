@@ -45,6 +45,10 @@ def _specs():
         # fixed: alone, the sweep evaluates these links; in the batch, the bounce-back kernel
         ("BGK", (31, 27, 30), 0.85, (2e-6, -1e-6, 0.0), [W.solid("sphere", (15.4, 13.2, 14.7), 5.9)], "ZHAO_YONG",
          None),
+        # two translating spheres whose boxes overlap (the two classification phases run apart)
+        ("MRT", (44, 30, 28), 0.8, (1e-6, 0.0, 0.0),
+         [W.solid("sphere", (14.6, 15.2, 13.7), 4.6, velocity=(0.014, 0.006, -0.004)),
+          W.solid("sphere", (27.9, 14.1, 14.3), 4.3, velocity=(-0.011, 0.008, 0.005))], "QUADRATIC", None),
     ]
 
 
@@ -91,7 +95,7 @@ def test_batch_members_match_alone(lbm, storage):
     them: tuning steps, then graph replays (one-step and eight-step graphs)."""
     specs = _specs()
     calls = [1, 10, 3, 17, 8, 6]
-    b = lbm.Batch("D3Q19", storage, max_slots=10, pool_bytes=1 << 30)
+    b = lbm.Batch("D3Q19", storage, max_slots=12, pool_bytes=1 << 30)
     members = []
     for spec in specs:
         coll, shape, tau, g, solids, _, rates = spec

@@ -78,3 +78,42 @@ def test_request_trace_is_poisson_and_seeded():
     for x in a[:50]:
         c = x["case"]
         assert 48 <= c.shape[0] <= 160 and c.solids[0]["radius"] == c.shape[0] / 8.0
+
+
+def test_link_capacity_bound_holds_for_bounce_back_spheres():
+    """The link capacity a bounce-back request reserves bounds the links the
+    oracle's builder finds (Sec. 2.2), over radii and sub-cell centre offsets;
+    IBM requests keep the library's bounds."""
+    import oracle
+
+    rng = np.random.default_rng(11)
+    for R in (2.6, 4.0, 5.5, 8.0, 11.3, 16.2):
+        L = int(2 * R + 10)
+        for _ in range(2):
+            c = tuple(L / 2.0 + rng.random(3))
+            case = W.Case("cap", "D3Q19", "MRT", (L, L, L), 0.8, (1e-6, 0.0, 0.0), [W.solid("sphere", c, R)],
+                          "QUADRATIC", 0, "F32")
+            max_links, max_lag = S.capacities(case)
+            assert max_lag == -1
+            o = oracle.Oracle("D3Q19", "MRT", (L, L, L), 0.8)
+            o.set_solids(case.solids, "QUADRATIC")
+            n = len(o.links()["cell"])
+            assert 0 < n <= max_links, (R, n, max_links)
+    ibm = W.Case("cap", "D3Q19", "MRT", (40, 40, 40), 0.8, (1e-6, 0.0, 0.0), [W.solid("sphere", (20, 20, 20), 5.0)],
+                 "IBM", 0, "F32")
+    assert S.capacities(ibm) == (0, 0)
+
+
+def test_workspace_without_ibm_space_is_smaller():
+    """max_lagrangian < 0 drops the IBM arrays (points, shell, spread force
+    field): at least 3 N force values less than the default capacity."""
+    import ctypes
+    from paper_1906_05445_amd import lbm
+
+    p, _ = lbm.make_params("D3Q19", "MRT", "F32", (64, 64, 64), 0.8)
+    N = 64 ** 3
+    full = lbm.lbm_workspace_bytes(ctypes.byref(p), 1, 0, 0)
+    none = lbm.lbm_workspace_bytes(ctypes.byref(p), 1, 0, -1)
+    assert 0 < none and full - none >= 3 * N * 4
+    # populations stay the bulk: two arrays of 19 values per cell
+    assert none > 2 * 19 * N * 4
