@@ -472,9 +472,11 @@ def main():
     if "open" in want and args.open_steps > 0:
         # Sec. 3.4's sphere, D = 16 (Zhao-Yong's sufficient resolution is about 14 at Re_p = 20)
         op = run_open_sphere(torch, lbm, W, args.open_steps)
+        ch = op["C_D_rel_change_last_chunk"]
         extra("open_sphere_re20_f32_zhao_yong", op,
-              f"{op['mlups']:.0f} MLUPS, C_D {op['C_D']:.4f} (change {op['C_D_rel_change_last_chunk']:.1e} over the "
-              f"last {op['chunk']} steps; Schiller-Naumann {op['C_D_schiller_naumann']:.4f})")
+              f"{op['mlups']:.0f} MLUPS, C_D {op['C_D']:.4f} (change "
+              f"{'n/a' if ch is None else format(ch, '.1e')} over the last {op['chunk']} steps; "
+              f"Schiller-Naumann {op['C_D_schiller_naumann']:.4f})")
         key = "open_sphere_f32_quadratic"
         if wanted("open", key):
             r = run_case(W.open_sphere(method="QUADRATIC"), k2, Wm, key, torch, lbm)

@@ -518,9 +518,12 @@ __global__ __launch_bounds__(256) void k_ibm_spread_mv(IbmArgs a, int last) {
   }
 }
 
+// (consecutive points, which lie close together on the mesh, go to one XCD:
+// their stencils' populations then come once into that XCD's L2)
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void k_ibm_interp0(const S *__restrict__ A, IbmArgs a) {
-  ibm_interp0_body<Q, S>(A, a, (int64_t)blockIdx.x * kIbmPointsPerBlock + (threadIdx.x >> 6));
+  ibm_interp0_body<Q, S>(A, a,
+                         (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kIbmPointsPerBlock + (threadIdx.x >> 6));
 }
 template <typename C>
 __global__ __launch_bounds__(256) void k_ibm_iter(IbmArgs a, int it) {
