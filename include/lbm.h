@@ -488,7 +488,9 @@ lbm_status lbm_batch_time_sweep(lbm_batch *b, int64_t nsteps, double *sweep_us);
  * the member context (NULL for a free slot) and change[k] the largest
  * relative change of a solid's force over the last `lag` steps,
  * |F(t-1) - F(t-1-lag)| / |F(t-1)| (Euclidean norms, F the force of step
- * t-1), or -1 when the member has no solid or fewer than lag + 1 steps.
+ * t-1), NaN when one of those forces is not finite (the member diverged:
+ * its populations went non-finite; the other members are not affected), or
+ * -1 when the member has no solid or fewer than lag + 1 steps.
  * Both arrays hold max_slots entries.  One launch and one small read-back;
  * synchronises the batch's stream. */
 lbm_status lbm_batch_force_change(lbm_batch *b, int64_t lag, lbm_ctx **members, double *change);

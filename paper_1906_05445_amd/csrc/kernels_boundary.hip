@@ -920,9 +920,26 @@ __global__ __launch_bounds__(kBlock) void k_link_emit_batch(const BatchSlot *__r
   });
 }
 
+// Relative change |a - b| / |a| of a solid's force (3 values each): 0 for two
+// zero forces, infinity from zero to non-zero, NaN when either is not finite
+// (a diverged member).
+__device__ inline double force_rel_change(const double *a, const double *b) {
+  double d2 = 0.0, n2 = 0.0, m2 = 0.0;
+  for (int c = 0; c < 3; c++) {
+    d2 += (a[c] - b[c]) * (a[c] - b[c]);
+    n2 += a[c] * a[c];
+    m2 += b[c] * b[c];
+  }
+  if (!isfinite(n2) || !isfinite(m2) || !isfinite(d2)) return __builtin_nan("");
+  return n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
+}
+// max that keeps a NaN
+__device__ inline double max_keep_nan(double x, double y) { return (x != x || y != y) ? __builtin_nan("") : fmax(x, y); }
+
 // Serving convergence check: per member, the largest relative change of a
 // solid's force over `lag` steps, |F(t-1) - F(t-1-lag)| / |F(t-1)| with t the
-// member's time; -1 while fewer than lag + 1 steps are in its history.
+// member's time (NaN if a force is not finite); -1 while fewer than lag + 1
+// steps are in its history.
 __global__ __launch_bounds__(64) void k_force_change(const BatchSlot *__restrict__ slots,
                                                      const WorkList *__restrict__ wl,
                                                      const int64_t *__restrict__ step, int64_t lag, double *out) {
@@ -939,26 +956,16 @@ __global__ __launch_bounds__(64) void k_force_change(const BatchSlot *__restrict
       const uint64_t per = (uint64_t)max_solids * 6;
       const double *a = hist + (uint64_t)(t % kHistCap) * per + (uint64_t)s * 6;
       const double *b = hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)s * 6;
-      double d2 = 0.0, n2 = 0.0;
-      for (int c = 0; c < 3; c++) {
-        d2 += (a[c] - b[c]) * (a[c] - b[c]);
-        n2 += a[c] * a[c];
-      }
-      r = n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
+      r = force_rel_change(a, b);
     }
-    for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off, 64));
+    for (int off = 32; off > 0; off >>= 1) r = max_keep_nan(r, __shfl_down(r, off, 64));
     for (int s0 = 64; s0 < nsolid; s0 += 64) {  // more than 64 solids: serial tail in lane 0
       if (threadIdx.x == 0 && ok) {
         for (int q = s0; q < min(nsolid, s0 + 64); q++) {
           const uint64_t per = (uint64_t)max_solids * 6;
           const double *a = hist + (uint64_t)(t % kHistCap) * per + (uint64_t)q * 6;
           const double *b = hist + (uint64_t)((t - lag) % kHistCap) * per + (uint64_t)q * 6;
-          double d2 = 0.0, n2 = 0.0;
-          for (int c = 0; c < 3; c++) {
-            d2 += (a[c] - b[c]) * (a[c] - b[c]);
-            n2 += a[c] * a[c];
-          }
-          r = fmax(r, n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0));
+          r = max_keep_nan(r, force_rel_change(a, b));
         }
       }
     }

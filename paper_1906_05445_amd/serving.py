@@ -39,6 +39,7 @@ class Request:
     steps: int = 0
     converged: bool = False
     capped: bool = False
+    diverged: bool = False
     rejected: bool = False
     force: Optional[np.ndarray] = None  # [nsolid, 6] at the last step
     change: float = -1.0
@@ -96,6 +97,20 @@ def initial_velocity(case):
     if not U0 or not np.any(gn):
         return None
     return tuple(U0 * gn / np.linalg.norm(gn))
+
+
+def outcome(change, time, step_cap, tol, nsolid):
+    """What a check does with a running request: "converged" (relative force
+    change below tol), "diverged" (the change is not a number: the member's
+    force, hence its populations, went non-finite), "capped" (step cap
+    reached, or no solid to converge), or None (keep running)."""
+    if change != change:  # NaN
+        return "diverged"
+    if 0.0 <= change < tol:
+        return "converged"
+    if time >= step_cap or not nsolid:
+        return "capped"
+    return None
 
 
 def percentile(values, q):
@@ -226,14 +241,14 @@ class Server:
             for m, req in list(self.active.items()):
                 ch = change.get(m, -1.0)
                 req.change = ch
-                done = 0.0 <= ch < self.tol
-                if done or m.time >= self.step_cap or not m.nsolid:
-                    req.converged = done
-                    req.capped = not done
+                end = outcome(ch, m.time, self.step_cap, self.tol, m.nsolid)
+                if end is not None:
+                    req.converged = end == "converged"
+                    req.capped = end == "capped"
+                    req.diverged = end == "diverged"
                     self._finish(m, req, now)
                     if log:
-                        log(f"req {req.rid}: {'converged' if done else 'capped'} after {req.steps} steps, "
-                            f"latency {req.latency:.3f} s")
+                        log(f"req {req.rid}: {end} after {req.steps} steps, latency {req.latency:.3f} s")
         wall = self.clock() - t0
         for m, req in self.active.items():
             req.steps = m.time
@@ -258,6 +273,7 @@ def stats(reqs, wall, cell_steps=0, in_flight=(), queued=0):
         "completed": len(done),
         "converged": len(conv),
         "capped": sum(1 for r in done if r.capped),
+        "diverged": sum(1 for r in done if r.diverged),
         "rejected": sum(1 for r in reqs if r.rejected),
         "in_flight_at_end": len(running),
         "in_flight_mean_steps": float(np.mean([r.steps for r in running])) if running else None,

@@ -248,3 +248,39 @@ def test_batch_ibm_delta_members_match_alone(lbm):
         _compare(m, ref, f"IBM member {k} ({delta}-point delta)")
         ref.close()
     b.close()
+
+
+def test_batch_member_with_non_finite_state_is_isolated(lbm):
+    """A member whose populations take a NaN mid-run: the batch steps on, the other
+    members match their lone runs bit for bit, the member's own check reports the
+    divergence and its force change is NaN (the serving loop ends such a request),
+    and after its release the batch goes on as before."""
+    specs = [_specs()[1], _specs()[0], _specs()[4]]  # fixed sphere (takes the NaN), translating sphere, no solid
+    b = lbm.Batch("D3Q19", "F32", max_slots=4, pool_bytes=1 << 28)
+    ms = []
+    for spec in specs:
+        coll, shape, tau, g, solids, _, rates = spec
+        m = b.admit(coll, "F32", shape, tau, rates=rates, g=g, max_solids=max(1, len(solids)))
+        _configure(m, spec)
+        ms.append(m)
+    b.step(6)
+    h = ms[0].get_state().copy()
+    h[3, 1234] = np.nan
+    ms[0].set_state(h)
+    b.step(30)
+    assert not ms[0].check()
+    assert ms[1].check() and ms[2].check()
+    ch = b.force_change(10)
+    assert np.isnan(ch[ms[0]])
+    assert np.isfinite(ch[ms[1]]) and ch[ms[1]] >= 0.0
+    assert ms[0] not in b.poll(10, tol=1e30)
+    refs = [_alone(lbm, "F32", specs[k], [36]) for k in (1, 2)]
+    for k, ref in zip((1, 2), refs):
+        _compare(ms[k], ref, f"member {k} beside a diverged one")
+    b.release(ms[0])
+    b.step(4)
+    for k, ref in zip((1, 2), refs):
+        ref.step(4)
+        _compare(ms[k], ref, f"member {k} after the diverged one left")
+        ref.close()
+    b.close()

@@ -51,3 +51,37 @@ def test_served_results_match_lone_runs(lbm):
         ft = lone.force_torque()
         lone.close()
         assert np.array_equal(ft.view(np.uint64), r.force.view(np.uint64)), f"request {r.rid}"
+
+
+def test_diverging_request_ends_without_disturbing_the_others(lbm):
+    """A request whose flow blows up (tau just above 1/2, a body force of 0.05 per
+    step: the oracle grows by about 1e41 every 25 steps) ends as diverged at the
+    first check that has a force change (step 200: the change over 100 steps
+    needs 101 steps of history); the requests served beside it match their lone
+    runs bit for bit."""
+    import dataclasses
+
+    trace = W.request_trace(count=3, rate=200.0, seed=7, edge=(24, 36), Re=(1.0, 2.0))
+    reqs = S.requests_from_trace(trace, n_iter=3)
+    bad = dataclasses.replace(reqs[0].case, name="blowup", tau=0.5001, g=(0.05, 0.0, 0.0), method="QUADRATIC",
+                              meta={})
+    reqs.insert(1, S.Request(99, reqs[0].arrival, bad, n_iter=3))
+    srv = S.Server(pool_bytes=1 << 30, max_slots=4, check_every=100, tol=1e-6, step_cap=4000)
+    st = srv.run(reqs, wall_limit=240)
+    srv.close()
+    assert st["completed"] == len(reqs) and st["diverged"] == 1, st
+    assert reqs[1].diverged and reqs[1].steps == 200
+    for r in reqs:
+        if r.rid == 99:
+            continue
+        assert not r.diverged
+        c = r.case
+        lone = lbm.Lattice(c.lattice, c.collision, c.storage, c.shape, c.tau, g=c.g, max_solids=1)
+        lone.set_solids(c.solids, c.method, n_iter=3)
+        u0 = S.initial_velocity(c)
+        if u0 is not None:
+            lone.set_equilibrium(1.0, u0)
+        lone.step(r.steps)
+        ft = lone.force_torque()
+        lone.close()
+        assert np.array_equal(ft.view(np.uint64), r.force.view(np.uint64)), f"request {r.rid}"

@@ -117,3 +117,19 @@ def test_workspace_without_ibm_space_is_smaller():
     assert 0 < none and full - none >= 3 * N * 4
     # populations stay the bulk: two arrays of 19 values per cell
     assert none > 2 * 19 * N * 4
+
+
+def test_check_outcome_of_a_running_request():
+    nan = float("nan")
+    # (change, time, cap, tol, nsolid) -> outcome
+    assert S.outcome(5e-7, 300, 1000, 1e-6, 1) == "converged"
+    assert S.outcome(0.0, 300, 1000, 1e-6, 1) == "converged"
+    assert S.outcome(2e-6, 300, 1000, 1e-6, 1) is None
+    assert S.outcome(-1.0, 100, 1000, 1e-6, 1) is None  # not enough history yet
+    assert S.outcome(2e-6, 1000, 1000, 1e-6, 1) == "capped"
+    assert S.outcome(-1.0, 100, 1000, 1e-6, 0) == "capped"  # nothing to converge
+    assert S.outcome(nan, 100, 1000, 1e-6, 1) == "diverged"
+    assert S.outcome(nan, 1000, 1000, 1e-6, 1) == "diverged"
+    assert S.outcome(float("inf"), 300, 1000, 1e-6, 1) is None  # zero to non-zero force: keep running
+    st = S.stats([], 1.0)
+    assert st["diverged"] == 0
