@@ -162,3 +162,24 @@ def test_failed_set_solids_leaves_a_plain_lattice(lbm):
     assert np.all(a.node_types() != 1)
     a.close()
     b.close()
+
+
+def test_context_without_ibm_space(lbm):
+    """max_lagrangian < 0 reserves no IBM space: bounce-back solids step bit for bit as in a
+    context with the default capacities, and an IBM set-up is refused (LBM_ENOMEM) without
+    touching the context."""
+    shape, g = (28, 26, 24), (1e-6, 0.0, 0.0)
+    s = [W.solid("sphere", (13.6, 12.2, 11.9), 5.1)]
+    a = lbm.Lattice("D3Q19", "MRT", "F32", shape, 0.8, g=g, max_lagrangian=-1)
+    b = lbm.Lattice("D3Q19", "MRT", "F32", shape, 0.8, g=g)
+    assert a.workspace.numel() < b.workspace.numel()
+    with pytest.raises(lbm.LBMError) as e:
+        a.set_solids(s, "IBM")
+    assert e.value.status == lbm.LBM_ENOMEM
+    for c in (a, b):
+        c.set_solids(s, "QUADRATIC")
+        c.step(40)
+    assert np.array_equal(a.get_state().view(np.uint32), b.get_state().view(np.uint32))
+    assert np.array_equal(a.history().view(np.uint64), b.history().view(np.uint64))
+    a.close()
+    b.close()
