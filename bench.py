@@ -48,8 +48,12 @@ PROFILE_EVERY = 8
 ALL_EXTRAS = ("single", "schemes", "open", "copy", "batch", "precision", "serving", "cpu")
 
 
+T_START = time.perf_counter()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    """A progress line on stderr, with the seconds since the start of the run."""
+    print(f"{msg}  [{time.perf_counter() - T_START:.0f} s]", file=sys.stderr, flush=True)
 
 
 SWEEP_SOURCES = ("sweep_core.hpp", "kernels_sweep.hip", "lbm_ibb.hpp", "lbm_device.hpp", "lbm_args.hpp")
