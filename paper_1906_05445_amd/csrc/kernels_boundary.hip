@@ -829,8 +829,9 @@ __global__ __launch_bounds__(256) void k_ft_batch(const BatchSlot *__restrict__ 
   });
 }
 
-// translating solids move to t + 1: keep and classify, refill with count,
-// scan, emit -- each over the (solid, box chunk) units of the moving members
+// translating solids move to t + 1: keep and classify, count, scan with
+// refill, emit -- over the (solid, box chunk) units of the moving members, or
+// one unit per member
 __device__ inline LinkArgs move_args(const BatchSlot *slots, int m, int64_t k) {
   LinkArgs a = SLOT(m, lk);
   a.g.t = slot_time(slots, m, k) + 1;
@@ -862,37 +863,30 @@ __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *
     classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
 }
-// Refill and link count in one launch (both read only the finished
-// classification; the refill writes populations, the count flags and owners
-// it does not touch): blocks 0 .. kRefillBatchBlocks-1 walk the members with
-// translating solids, one block of four waves per member refilling its list,
-// the others the (solid, box chunk) units of the count.
-constexpr uint32_t kRefillBatchBlocks = 256;
-template <int Q, typename S>
-__global__ __launch_bounds__(kBlock) void k_refill_count_batch(const BatchSlot *__restrict__ slots,
-                                                               const WorkList *__restrict__ one,
-                                                               const WorkList *__restrict__ box,
-                                                               const int64_t *__restrict__ step) {
+template <int Q>
+__global__ __launch_bounds__(kBlock, 8) void k_link_count_batch(const BatchSlot *__restrict__ slots,
+                                                             const WorkList *__restrict__ wl,
+                                                             const int64_t *__restrict__ step) {
   const int64_t k = *step;
-  if (blockIdx.x < kRefillBatchBlocks) {
-    batch_units_in(one, 0, blockIdx.x, kRefillBatchBlocks, [&](int m, uint32_t) {
-      const LinkArgs a = move_args(slots, m, k);
-      const uint32_t cnt = min(a.misc[3], a.max_refill);
-      for (uint32_t e = threadIdx.x >> 6; e < cnt; e += kBlock / 64) refill_wave<Q, S>(a, a.refill_list[e]);
-    });
-    return;
-  }
-  batch_units_in(box, 0, blockIdx.x - kRefillBatchBlocks, gridDim.x - kRefillBatchBlocks, [&](int m, uint32_t u) {
+  batch_units(wl, 0, [&](int m, uint32_t u) {
     const LinkArgs a = move_args(slots, m, k);
     const int s = (int)(u / a.max_box_chunks);
     link_count_body<Q>(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
 }
-// one unit per member; also folds the capacity checks into its status words
-__global__ __launch_bounds__(1024) void k_link_scan_batch(const BatchSlot *__restrict__ slots,
-                                                          const WorkList *__restrict__ wl) {
+// One unit per member: the link scan, which also folds the capacity checks
+// into the member's status words, then the refill of the nodes its solids
+// uncovered, the block's 16 wavefronts walking the refill list.  The refill
+// reads only the finished classification and writes populations, which
+// neither the scan nor the count and emit passes touch; it rides here rather
+// than in the count pass, whose occupancy its registers would lower.
+template <int Q, typename S>
+__global__ __launch_bounds__(1024) void k_scan_refill_batch(const BatchSlot *__restrict__ slots,
+                                                            const WorkList *__restrict__ wl,
+                                                            const int64_t *__restrict__ step) {
+  const int64_t k = *step;
   batch_units(wl, 0, [&](int m, uint32_t) {
-    const LinkArgs a = SLOT(m, lk);
+    const LinkArgs a = move_args(slots, m, k);
     const int nsolid = SLOT(m, nsolid);
     link_scan_body(a, nsolid);
     if (threadIdx.x == 0) {
@@ -905,11 +899,13 @@ __global__ __launch_bounds__(1024) void k_link_scan_batch(const BatchSlot *__res
       st[0] |= bad;
       st[1] = a.misc[0];
     }
+    const uint32_t cnt = min(a.misc[3], a.max_refill);
+    for (uint32_t e = threadIdx.x >> 6; e < cnt; e += blockDim.x >> 6) refill_wave<Q, S>(a, a.refill_list[e]);
     __syncthreads();
   });
 }
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_link_emit_batch(const BatchSlot *__restrict__ slots,
+__global__ __launch_bounds__(kBlock, 5) void k_link_emit_batch(const BatchSlot *__restrict__ slots,
                                                             const WorkList *__restrict__ wl,
                                                             const int64_t *__restrict__ step) {
   const int64_t k = *step;
@@ -997,23 +993,23 @@ void launch_ft_batch(const BatchLaunch &b, const WorkList *wl, uint32_t grid) {
 
 void launch_move_batch(const BatchLaunch &b, const WorkList *box, const WorkList *boxm, const WorkList *one,
                        bool any_multi, uint32_t grid) {
-  const dim3 g(grid), blk(kBlock);
+  const dim3 g(grid), blk(kBlock), g1(std::min<uint32_t>(grid, 1024));
   hipLaunchKernelGGL(k_classify_keep_batch, g, blk, 0, b.stream, b.slots, box, b.step);
   if (any_multi) hipLaunchKernelGGL(k_classify_box_batch, g, blk, 0, b.stream, b.slots, boxm, b.step);
-  const dim3 g1(kRefillBatchBlocks + grid);
-#define LBM_RC(QQ, SS) \
-  hipLaunchKernelGGL((k_refill_count_batch<QQ, SS>), g1, blk, 0, b.stream, b.slots, one, box, b.step)
+  if (b.Q == 9) hipLaunchKernelGGL(k_link_count_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
+  else hipLaunchKernelGGL(k_link_count_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
+#define LBM_SR(QQ, SS) \
+  hipLaunchKernelGGL((k_scan_refill_batch<QQ, SS>), g1, dim3(1024), 0, b.stream, b.slots, one, b.step)
   if (b.Q == 9) {
-    if (b.storage == LBM_F64) LBM_RC(9, double);
-    else if (b.storage == LBM_F32_DEV) LBM_RC(9, float);
-    else LBM_RC(9, _Float16);
+    if (b.storage == LBM_F64) LBM_SR(9, double);
+    else if (b.storage == LBM_F32_DEV) LBM_SR(9, float);
+    else LBM_SR(9, _Float16);
   } else {
-    if (b.storage == LBM_F64) LBM_RC(19, double);
-    else if (b.storage == LBM_F32_DEV) LBM_RC(19, float);
-    else LBM_RC(19, _Float16);
+    if (b.storage == LBM_F64) LBM_SR(19, double);
+    else if (b.storage == LBM_F32_DEV) LBM_SR(19, float);
+    else LBM_SR(19, _Float16);
   }
-#undef LBM_RC
-  hipLaunchKernelGGL(k_link_scan_batch, dim3(std::min<uint32_t>(grid, 1024)), dim3(1024), 0, b.stream, b.slots, one);
+#undef LBM_SR
   if (b.Q == 9) hipLaunchKernelGGL(k_link_emit_batch<9>, g, blk, 0, b.stream, b.slots, box, b.step);
   else hipLaunchKernelGGL(k_link_emit_batch<19>, g, blk, 0, b.stream, b.slots, box, b.step);
 }
