@@ -706,7 +706,10 @@ __global__ __launch_bounds__(256) void k_ft_reduce(FtReduceArgs r) {
 
 // Chunk partials from per-link force terms (the sweep's bounce-back of fixed
 // solids); 256 threads, one chunk unit per wavefront.
-__global__ __launch_bounds__(256) void k_chunk_sum(ChunkSumArgs a) { chunk_sum_waves(a, blockIdx.x); }
+template <int Q>
+__global__ __launch_bounds__(256) void k_chunk_sum(ChunkSumArgs a) {
+  chunk_sum_waves<Q>(a, blockIdx.x);
+}
 
 // Link lists of fixed solids by sweep segment (64 cells): count the links of
 // every segment (and flag their fluid nodes F_LINK), give each segment with
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(64) void k_seg_link_fill(LinkArgs a, SegLink *seg, 
 // evaluates each step.  Bits 8.. of a link's meta word hold its solid.
 template <int Q, typename S>
 __global__ __launch_bounds__(64) void k_link_table(LinkArgs a, const uint32_t *cell_list, uint32_t nlinks, int method,
-                                                   void *rec_, double *fc, uint64_t stride) {
+                                                   void *rec_, uint64_t stride) {
   using C = typename Store<S>::C;
   const uint32_t pos = blockIdx.x * 64 + threadIdx.x;
   if (pos >= nlinks) return;
@@ -784,12 +787,6 @@ __global__ __launch_bounds__(64) void k_link_table(LinkArgs a, const uint32_t *c
   r.k4 = k.k4;
   r.B = link_wall<C>(k, g.B);
   static_cast<LinkRec<C> *>(rec_)[pos] = r;
-  for (int j = 0; j < 3; j++) {
-    fc[(uint64_t)j * stride + l] = g.a[j];
-    fc[(uint64_t)(3 + j) * stride + l] = g.b[j];
-    fc[(uint64_t)(6 + j) * stride + l] = g.d[j];
-    fc[(uint64_t)(9 + j) * stride + l] = g.r[j];
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1182,16 +1179,15 @@ void launch_ft_reduce_free(lbm_ctx *c, int64_t t) {
 double *partials_of(lbm_ctx *c, int64_t t) { return c->at<double>((t & 1) ? c->L.partials2 : c->L.partials); }
 
 // Staging region while an lbm_step call applies the bounce-back in the sweep:
-// the link records, the Eq. 17 constants and, per step parity, the stored
-// incoming and outgoing values of every link ([2][stride] compute type).
+// the link records and, per step parity, the stored incoming and outgoing
+// values of every link ([2][stride] compute type).
 static size_t link_rec_bytes(const lbm_ctx *c) { return c->store_bytes == 8 ? sizeof(LinkRec<double>) : sizeof(LinkRec<float>); }
 static size_t link_c_bytes(const lbm_ctx *c) { return c->store_bytes == 8 ? 8 : 4; }
-static size_t link_fc_offset(const lbm_ctx *c) { return c->L.staging + c->link_stride * link_rec_bytes(c); }
 static size_t link_io_offset(const lbm_ctx *c, int64_t t) {
-  return link_fc_offset(c) + c->link_stride * 96 + (size_t)(t & 1) * 2 * c->link_stride * link_c_bytes(c);
+  return c->L.staging + c->link_stride * link_rec_bytes(c) + (size_t)(t & 1) * 2 * c->link_stride * link_c_bytes(c);
 }
 bool link_table_fits(const lbm_ctx *c, uint64_t stride) {
-  const size_t per = link_rec_bytes(c) + 96 + 4 * link_c_bytes(c);
+  const size_t per = link_rec_bytes(c) + 4 * link_c_bytes(c);
   return stride * per <= (size_t)4 * c->N * 8;
 }
 
@@ -1202,7 +1198,16 @@ ChunkSumArgs chunk_sum_args(lbm_ctx *c, int64_t t) {
   ChunkSumArgs a{};
   a.io = link_io_of(c, t);
   a.cbytes = (int)link_c_bytes(c);
-  a.fc = c->at<double>(link_fc_offset(c));
+  a.lcell = c->at<uint32_t>(c->L.link_cell);
+  a.lmeta = c->at<uint32_t>(c->L.link_meta);
+  a.lq = c->at<double>(c->L.link_q);
+  a.solids = c->at<DevSolid>(c->L.solids);
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.D = c->D;
+  a.fx = c->fx;
+  a.fy = c->fy;
   a.stride = c->link_stride;
   a.sl = c->at<SolidLinks>(c->L.solid_links);
   a.partials = partials_of(c, t);
@@ -1220,10 +1225,9 @@ void launch_link_table(lbm_ctx *c) {
   const dim3 grid((nl + 63) / 64);
   const uint32_t *list = c->at<uint32_t>(c->L.cell_list);
   void *rec = c->ws + c->L.staging;
-  double *fc = c->at<double>(link_fc_offset(c));
   const uint64_t st = c->link_stride;
 #define LBM_LT(QQ, SS) \
-  hipLaunchKernelGGL((k_link_table<QQ, SS>), grid, dim3(64), 0, c->stream, a, list, nl, c->method, rec, fc, st)
+  hipLaunchKernelGGL((k_link_table<QQ, SS>), grid, dim3(64), 0, c->stream, a, list, nl, c->method, rec, st)
   if (c->Q == 9) {
     if (c->p.storage == LBM_F64) LBM_LT(9, double);
     else if (c->p.storage == LBM_F32_DEV) LBM_LT(9, float);
@@ -1242,7 +1246,10 @@ uint32_t chunk_sum_blocks(const lbm_ctx *c) {
 
 void launch_chunk_sum(lbm_ctx *c, int64_t t) {
   if (c->k5_chunks <= 0) return;
-  hipLaunchKernelGGL(k_chunk_sum, dim3(chunk_sum_blocks(c)), dim3(256), 0, c->stream, chunk_sum_args(c, t));
+  if (c->Q == 9)
+    hipLaunchKernelGGL(k_chunk_sum<9>, dim3(chunk_sum_blocks(c)), dim3(256), 0, c->stream, chunk_sum_args(c, t));
+  else
+    hipLaunchKernelGGL(k_chunk_sum<19>, dim3(chunk_sum_blocks(c)), dim3(256), 0, c->stream, chunk_sum_args(c, t));
 }
 
 // Builds the link lists by sweep segment of a context whose solids are all

@@ -197,10 +197,12 @@ static_assert(offsetof(LinkRec<float>, n) % 16 == 0 && offsetof(LinkRec<double>,
                   offsetof(LinkRec<float>, kind_dir) == offsetof(LinkRec<float>, n) + 12,
               "link record head");
 
-// Chunk partials from tabulated links: the same per-link terms, summed over
-// the same 64 lanes in the same order, as the bounce-back kernel forms from
-// its registers.  Block `blk` (256 threads): chunk units 4*blk .. 4*blk+3,
-// one per wavefront.
+// Chunk partials of links evaluated in the sweep: the same per-link terms,
+// summed over the same 64 lanes in the same order, as the bounce-back kernel
+// forms from its registers (the link's geometry formed again from its cell,
+// direction and q, exactly as when its record was tabulated).  Block `blk`
+// (256 threads): chunk units 4*blk .. 4*blk+3, one per wavefront.
+template <int Q>
 __device__ inline void chunk_sum_waves(const ChunkSumArgs &a, uint32_t blk) {
   const int lane = threadIdx.x & 63;
   const uint32_t u = blk * 4 + (threadIdx.x >> 6);
@@ -221,9 +223,17 @@ __device__ inline void chunk_sum_waves(const ChunkSumArgs &a, uint32_t blk) {
       hin = (double)static_cast<const float *>(a.io)[l];
       hout = (double)static_cast<const float *>(a.io)[a.stride + l];
     }
-    double k[12];
-    for (int j = 0; j < 12; j++) k[j] = a.fc[(uint64_t)j * a.stride + l];
-    link_ft(hin, hout, k, k + 3, k + 6, k + 9, acc);
+    const uint32_t n = a.lcell[l], meta = a.lmeta[l];
+    const double q = a.lq[l];
+    const uint32_t yz = fdiv(n, a.fx);
+    const int x = (int)(n - yz * (uint32_t)a.nx), z = (int)fdiv(yz, a.fy);
+    const int y = (int)(yz - (uint32_t)z * (uint32_t)a.ny);
+    const Box3 box{a.nx, a.ny, a.nz, a.D};
+    const DevSolid sd = a.solids[s];
+    double c[3];
+    solid_centre(sd, 0, box, c);  // a fixed solid: its centre at any time
+    const LinkGeo g = link_geo<Q>((int)(meta & 31u), q, sd, c, x, y, z, box);
+    link_ft(hin, hout, g.a, g.b, g.d, g.r, acc);
   }
   for (int k = 0; k < 6; k++) {
     const double tot = wave_sum(acc[k]);

@@ -96,7 +96,13 @@ struct SegLink {
 struct ChunkSumArgs {
   const void *io;
   int cbytes;
-  const double *fc;
+  // the links (cell, direction | solid << 8, q) and the geometry their Eq. 17
+  // terms are formed from (fixed solids)
+  const uint32_t *lcell, *lmeta;
+  const double *lq;
+  const DevSolid *solids;
+  int32_t nx, ny, nz, D;
+  FastDiv fx, fy;
   uint64_t stride;
   const SolidLinks *sl;
   double *partials;

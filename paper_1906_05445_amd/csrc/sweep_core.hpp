@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kBlock, (sweep_min_waves<S, COLL, INL>())) void k_s
   blk -= a.rblocks;
   if (INL) {
     if (blk < la.cblocks) {
-      chunk_sum_waves(la.cs, blk);
+      chunk_sum_waves<Q>(la.cs, blk);
       return;
     }
     blk -= la.cblocks;
