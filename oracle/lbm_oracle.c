@@ -70,11 +70,14 @@
  * by the exact balance of fluid plus solid momentum (tests/test_oracle_free_ibm.py).
  *
  * PARITY UNPINNED (no closed form or independent reference exists): the
- * coupling reading of the IBM (which velocity is interpolated, force factor 1,
- * Sec. 2.1 last paragraph), the default MRT rates beyond what exact Poiseuille
- * pins, and the refill rule for newly uncovered nodes of a moving IBB solid.
- * These are checked only against the GPU library (same reading on both sides)
- * and by convergence order.
+ * default MRT rates beyond what exact Poiseuille pins, and of the refill rule
+ * for newly uncovered nodes of a moving IBB solid the choice of the density
+ * (the mean over the neighbours that stay fluid; the co-moving uniform flow
+ * fixes it only where the density is uniform).  These are checked only
+ * against the GPU library (same reading on both sides) and by convergence
+ * order.  (The IBM coupling reading -- which velocity is interpolated, force
+ * factor 1, Sec. 2.1 -- is pinned by the one-point closed form of
+ * tests/test_oracle_comoving.py.)
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
  *        -o liblbm_oracle.so lbm_oracle.c -lm
