@@ -287,9 +287,16 @@ __host__ __device__ inline uint32_t hash32(uint32_t x) {
 }
 // Per-step seed of the dither.
 __host__ __device__ inline uint32_t sr_seed(int64_t t) { return hash32((uint32_t)t * 0x9e3779b9U + 0x632be5abU); }
-// 13 dither bits of direction i from a cell's hash h (h times an odd constant
-// is uniform when h is; its top bits are taken).
-__device__ inline uint32_t sr_bits(uint32_t h, int i) { return (h * (0x9e3779b1U * (2U * (uint32_t)i + 1U))) >> 19; }
+// 13 dither bits of direction i from a cell's hash h: the top bits of the low
+// word of (h >> 8) times an odd 24-bit constant of that direction in
+// [2^23, 2^24).  The product spans about 2^47, so its low word wraps some 2^15
+// times and its top 13 bits are uniform to about 2^-15 when h is.  Both
+// factors are below 2^24, so the compiler takes the full-rate 24-bit multiply
+// (v_mul_u32_u24), where a 32-bit one takes four times as long.
+__device__ inline uint32_t sr_bits(uint32_t h, int i) {
+  const uint32_t k = ((0x9e3779U * (2U * (uint32_t)i + 1U)) & 0x7fffffU) | 0x800001U;
+  return ((h >> 8) * k) >> 19;
+}
 // v rounded to FP16 stochastically with dither r (13 bits, the bits FP16
 // drops from an FP32 mantissa), in FP16's normal range; nearest elsewhere.
 __device__ inline _Float16 f16_round_sr(float v, uint32_t r) {
