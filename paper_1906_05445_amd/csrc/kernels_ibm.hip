@@ -314,17 +314,23 @@ __device__ inline void ibm_psum_body(const IbmArgs &a, int64_t l) {
     acc[1] = acc[1] + (double)(e.val * F.y);
     acc[2] = acc[2] + (double)(e.val * F.z);
   };
-  int j = lane;
-  // four entries per lane at a time: their loads, then their gathers, are in flight together
-  for (; j + 192 < len; j += 256) {
-    const IbmEntry<C> e0 = row[j], e1 = row[j + 64], e2 = row[j + 128], e3 = row[j + 192];
-    const IbmF4<C> F0v = F0[e0.col], F1v = F0[e1.col], F2v = F0[e2.col], F3v = F0[e3.col];
-    add(e0, F0v);
-    add(e1, F1v);
-    add(e2, F2v);
-    add(e3, F3v);
+  // twelve entries per lane at a time (a row of up to 768 entries in one
+  // pass): their loads, then their gathers, are in flight together, and the
+  // sums take them in the order of the row
+  constexpr int U = 12;
+  for (int j = lane; j < len; j += 64 * U) {
+    IbmEntry<C> e[U];
+    IbmF4<C> F[U];
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (j + 64 * k < len) e[k] = row[j + 64 * k];
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (j + 64 * k < len) F[k] = F0[e[k].col];
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (j + 64 * k < len) add(e[k], F[k]);
   }
-  for (; j < len; j += 64) add(row[j], F0[row[j].col]);
   for (int k = 0; k < 3; k++) acc[k] = wave_sum(acc[k]);
   if (lane == 0)
     for (int k = 0; k < 3; k++) a.Fsum[l * 3 + k] = acc[k];
