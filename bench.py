@@ -398,7 +398,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--extras", default="all", help="all, none, or a comma list of " + ",".join(ALL_EXTRAS))
-    ap.add_argument("--extras-out", default=os.path.join("gpurun_out", "bench_extras.json"))
+    ap.add_argument("--extras-out", default=os.path.join("bench_out", "bench_extras.json"))
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the 512-lattice batch")
     ap.add_argument("--precision-steps", type=int, default=10000, help="steps of the FP32/FP16 vs FP64 comparison")
     ap.add_argument("--serve-seconds", type=float, default=200.0, help="limit of the saturated serving window")
@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--cpu-steps", default="1,3", help="oracle sample: steps on one thread, steps on all threads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: a lattice is not split across GPUs here, so "
+        print(json.dumps({"error": "bench.py measures one GPU (a lattice is not split across GPUs), so "
                                    "--gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
