@@ -860,6 +860,8 @@ __global__ __launch_bounds__(kBlock) void k_classify_box_batch(const BatchSlot *
     classify_box_body(a, u - (uint32_t)s * a.max_box_chunks, s);
   });
 }
+// (the box units are latency-bound chains of loads; at most 64 registers, no
+// spills, let 8 waves per SIMD overlap them)
 template <int Q>
 __global__ __launch_bounds__(kBlock, 8) void k_link_count_batch(const BatchSlot *__restrict__ slots,
                                                              const WorkList *__restrict__ wl,
@@ -901,6 +903,7 @@ __global__ __launch_bounds__(1024) void k_scan_refill_batch(const BatchSlot *__r
     __syncthreads();
   });
 }
+// (5 waves per SIMD is the most its registers allow without spills)
 template <int Q>
 __global__ __launch_bounds__(kBlock, 5) void k_link_emit_batch(const BatchSlot *__restrict__ slots,
                                                             const WorkList *__restrict__ wl,
