@@ -186,7 +186,7 @@ int collision_kind(const lbm_ctx *c, double *sp, double *sm) {
 void fill_sweep_args(lbm_ctx *c, SweepArgs *a) { make_sweep_args(c, *a); }
 
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0, hipEvent_t e1, int64_t reduce_t,
-                  int64_t ibm_t, int64_t link_t, int64_t sum_t) {
+                  int64_t ibm_t, int64_t link_t, int64_t sum_t, bool ghost) {
   SweepArgs a;
   const int coll = make_sweep_args(c, a);
   const int nt = policy & 1;
@@ -213,6 +213,7 @@ void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0,
     la.stride = c->link_stride;
     la.sr = a.sr;
     la.lseed = sr_seed(link_t);
+    la.ghost = ghost ? 1u : 0u;
     if (sum_t >= 0) {
       la.cs = chunk_sum_args(c, sum_t);
       la.cblocks = chunk_sum_blocks(c);

@@ -105,6 +105,7 @@ struct SweepLinkArgs {
   uint32_t cblocks;
   ChunkSumArgs cs;
   uint32_t sr, lseed;  // FP16 stochastic rounding of the link values; sr_seed of the links' step
+  uint32_t ghost;      // links evaluated from A also store their values in A's solid-node slots
 };
 
 // IBM spreading: lanes per shell cell (each takes every kSpreadLanes-th entry

@@ -237,9 +237,13 @@ lbm_status destroy_ctx(lbm_ctx *c);  // frees the host side of a context
 // link_t >= 0: the sweep applies the bounce-back of step link_t (= the step
 // whose post-collision values A holds) and stores the per-link force terms of
 // that step; sum_t >= 0: it also forms the chunk partials of step sum_t.
+// ghost (with link_t >= 0): the link values also go to the solid nodes' slots
+// of A, which only a readout of A after the call (lbm_macros, lbm_strain)
+// pulls, so the last sweep of a call stores them and the others need not.
 // policy: bit 0 non-temporal stores, bit 1 XCD-contiguous tile order
 void launch_sweep(lbm_ctx *c, const void *A, void *B, int policy, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                  int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1);
+                  int64_t reduce_t = -1, int64_t ibm_t = -1, int64_t link_t = -1, int64_t sum_t = -1,
+                  bool ghost = true);
 void launch_encode_shift(lbm_ctx *c, int dir, const double *src, void *A, bool raw);
 // kernels_sweep_bnd.hip: bounded domains (lbm_params.boundary)
 void launch_outflow(lbm_ctx *c, const void *A, void *B);

@@ -1228,7 +1228,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
       // become chunk partials and those of step t - 3 are summed, in its
       // leading blocks (the last steps are finished after the loop)
       launch_sweep(c, A, B, policy, e0, e1, k >= 3 ? c->t - 3 : -1, -1, k >= 1 ? c->t - 1 : -1,
-                   k >= 2 ? c->t - 2 : -1);
+                   k >= 2 ? c->t - 2 : -1, k == nsteps - 1);
       if (open_x) launch_outflow(c, A, B);
       if (ts.end) HIPCALL(hipEventRecord(c->tune_events.back().e1, c->stream));
       if (span && k == nsteps - 1) HIPCALL(hipEventRecord(c->prof_events.back().e1, c->stream));

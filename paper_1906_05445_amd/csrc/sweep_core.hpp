@@ -260,18 +260,49 @@ __device__ __forceinline__ uint32_t link_pos(const uint32_t (&first)[CPT], const
   return first[0] + j;
 }
 
+// One link of sweep_links: lane link at record p, addressing words hd,
+// segment c.  The populations are gathered first and the rest of the record
+// is read after them, so that no wait separates the gathers from the pulls.
+template <int Q, typename S, int CPT>
+__device__ __forceinline__ void sweep_link_one(const S *A, const SweepLinkArgs &la, uint32_t p, uint4 hd, int c,
+                                               S (*tab)[64 * (Q - 1)], uint32_t (*mask)[64]) {
+  using C = typename Store<S>::C;
+  const LinkRec<C> *rec = static_cast<const LinkRec<C> *>(la.rec);
+  C *io = static_cast<C *>(la.io);
+  S *dst = const_cast<S *>(A);
+  const uint32_t rn = hd.x, rnff = hd.y, rnfff = hd.z;
+  const int kind = (int)(hd.w & 255u), i = (int)(hd.w >> 8), ib = opp(i);
+  const C hb_f = Store<S>::ld(A + pidx<Q>(ib, rn));
+  const C hb_ff =
+      (kind == LK_Q2_NEAR || kind == LK_Q1_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, rnff)) : C(0);
+  const C hb_fff = (kind == LK_Q2_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, rnfff)) : C(0);
+  const C hs_f = (kind == LK_Q2_FAR || kind == LK_Q1_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, rn)) : C(0);
+  const C hs_ff = (kind == LK_Q2_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, rnff)) : C(0);
+  const LinkRec<C> &r = rec[p];
+  const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
+  // (no Zhao-Yong links here: the table never holds them)
+  const S v = store_value<S, C>(link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff, C(0)), la.sr != 0,
+                                la.sr ? hash32((r.nb * 32u + (uint32_t)i) ^ la.lseed) >> 19 : 0u);
+  if (la.ghost) dst[pidx<Q>(i, r.nb)] = v;
+  io[r.l] = (C)v;
+  io[la.stride + r.l] = hb_f;
+  const uint32_t o = rn & 63u;
+  tab[c][o * (Q - 1) + (i - 1)] = v;
+  atomicOr(&mask[c][o], 1u << i);
+}
+
 // Boundary links of this wavefront's cells (CPT segments of 64 cells, one
 // cell of each per lane; the link records of segment c are rec[first[c] ..
 // first[c] + cnt[c] - 1]): the lanes take the links one each and evaluate them
 // on the source array; each value goes to the owning lane through LDS (tab,
 // one row of Q-1 directions per cell, and a direction mask) and replaces the
-// pulled value there (the solid-node slot it was pulled from is stale).  It is
-// also written to that slot (read by no other node), and the link's incoming
-// and outgoing values are kept for its force.  first, cnt, total are
-// wavefront-uniform.  head0: the addressing words of the lane's first link,
-// fetched before the cells' pulls were issued (loads complete in order, so a
-// record read after the pulls would hold the link loads back until every pull
-// had arrived).
+// pulled value there (the solid-node slot it was pulled from is stale).  With
+// la.ghost it is also written to that slot (read by no other node in this
+// sweep), and the link's incoming and outgoing values are kept for its force.
+// first, cnt, total are wavefront-uniform.  head0: the addressing words of the
+// lane's first link, fetched before the cells' pulls were issued (loads
+// complete in order, so a record read after the pulls would hold the link
+// loads back until every pull had arrived).
 template <int Q, typename S, int CPT>
 __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la, const uint32_t (&first)[CPT],
                                             const uint32_t (&cnt)[CPT], uint32_t total, uint4 head0,
@@ -279,39 +310,25 @@ __device__ __forceinline__ void sweep_links(const S *A, const SweepLinkArgs &la,
   using C = typename Store<S>::C;
   const int lane = threadIdx.x & 63;
   const LinkRec<C> *rec = static_cast<const LinkRec<C> *>(la.rec);
-  C *io = static_cast<C *>(la.io);
-  S *dst = const_cast<S *>(A);
 #pragma unroll
   for (int c = 0; c < CPT; c++) mask[c][lane] = 0u;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (uint32_t b = 0; b < total; b += 64) {
+  // the first 64 links from the addressing words fetched before the pulls (a
+  // branch joining them with a later load would make the compiler wait for
+  // every pull before the first gather); further ones, rare, one load each
+  if ((uint32_t)lane < total) {
+    int c;
+    const uint32_t p = link_pos<C, CPT>(first, cnt, (uint32_t)lane, c);
+    sweep_link_one<Q, S, CPT>(A, la, p, head0, c, tab, mask);
+  }
+  for (uint32_t b = 64; b < total; b += 64) {
     const uint32_t j = b + lane;
     if (j < total) {
       int c;
       const uint32_t p = link_pos<C, CPT>(first, cnt, j, c);
-      const uint4 hd = b == 0 ? head0 : LinkRec<C>::head(rec + p);
-      const uint32_t rn = hd.x, rnff = hd.y, rnfff = hd.z;
-      const int kind = (int)(hd.w & 255u), i = (int)(hd.w >> 8), ib = opp(i);
-      const C hb_f = Store<S>::ld(A + pidx<Q>(ib, rn));
-      const C hb_ff =
-          (kind == LK_Q2_NEAR || kind == LK_Q1_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, rnff)) : C(0);
-      const C hb_fff = (kind == LK_Q2_NEAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(ib, rnfff)) : C(0);
-      const C hs_f =
-          (kind == LK_Q2_FAR || kind == LK_Q1_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, rn)) : C(0);
-      const C hs_ff = (kind == LK_Q2_FAR || kind == LK_YU) ? Store<S>::ld(A + pidx<Q>(i, rnff)) : C(0);
-      const LinkRec<C> &r = rec[p];
-      const LinkCoef<C> k{kind, r.k1, r.k2, r.k3, r.k4, 1.0};
-      // (no Zhao-Yong links here: the table never holds them)
-      const S v = store_value<S, C>(link_value<C>(k, r.B, hb_f, hb_ff, hb_fff, hs_f, hs_ff, C(0)), la.sr != 0,
-                                    la.sr ? hash32((r.nb * 32u + (uint32_t)i) ^ la.lseed) >> 19 : 0u);
-      dst[pidx<Q>(i, r.nb)] = v;
-      io[r.l] = (C)v;
-      io[la.stride + r.l] = hb_f;
-      const uint32_t o = rn & 63u;
-      tab[c][o * (Q - 1) + (i - 1)] = v;
-      atomicOr(&mask[c][o], 1u << i);
+      sweep_link_one<Q, S, CPT>(A, la, p, LinkRec<C>::head(rec + p), c, tab, mask);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
