@@ -129,6 +129,21 @@ def stokes_body_force(Re, nu, D, box_cells, solid_volume, n_spheres=1):
     return 3.0 * math.pi * nu * D * U * n_spheres / (box_cells - solid_volume), U
 
 
+def _array_drag_factor(c):
+    # K(c) of Sangani & Acrivos (1982), simple cubic array at solid fraction c
+    return 1.0 / (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c ** 2 + 3.9799 * c ** (8.0 / 3.0)
+                  - 3.0734 * c ** (10.0 / 3.0))
+
+
+def array_body_force(Re, nu, D, box_cells, solid_volume):
+    """Body force density under which the periodic-array estimate below gives the mean velocity
+    U = Re nu / D: g = 3 pi nu D U K(c) (1 + 0.15 Re^0.687) / (box - V_s).  Returns (g, U)."""
+    U = Re * nu / D
+    c = solid_volume / box_cells
+    return 3.0 * math.pi * nu * D * U * _array_drag_factor(c) * (1.0 + 0.15 * Re ** 0.687) / (
+        box_cells - solid_volume), U
+
+
 def periodic_array_velocity(g, nu, D, box_cells, solid_volume):
     """Estimate of the mean fluid velocity that a body force g drives through a
     simple cubic array of spheres (one sphere of diameter D per periodic box):
@@ -139,9 +154,7 @@ def periodic_array_velocity(g, nu, D, box_cells, solid_volume):
     for the inertia at Re = U D / nu.  An initial condition only (a warm
     start for solves run to a steady drag): the flow then relaxes to the
     method's own steady state."""
-    c = solid_volume / box_cells
-    K = 1.0 / (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c ** 2 + 3.9799 * c ** (8.0 / 3.0)
-               - 3.0734 * c ** (10.0 / 3.0))
+    K = _array_drag_factor(solid_volume / box_cells)
     total = g * (box_cells - solid_volume)
     U = total / (3.0 * math.pi * nu * D * K)
     for _ in range(50):  # fixed point on the inertial factor (a contraction for these Re)
@@ -177,14 +190,21 @@ def cylinder_channel_2d(n=64, R=8.3, centre=(32.4, 31.7), g=1e-6, tau=0.8, steps
 
 
 def sphere_box(n=128, R=16.2, Re=20.0, tau=0.8, seed=2, method="QUADRATIC", storage="F64", steps=5000,
-               retraction=0.0, delta=4):
-    """Fixed sphere at a seed-drawn sub-grid offset in a periodic cube, D3Q19 MRT."""
+               retraction=0.0, delta=4, drive="stokes"):
+    """Fixed sphere at a seed-drawn sub-grid offset in a periodic cube, D3Q19 MRT.  Body force: the
+    Stokes drag of one sphere at Re (drive="stokes"; the steady flow of the array is slower), or the
+    periodic-array estimate that gives Re at steady state (drive="array").  meta["U_init"]: the
+    periodic-array estimate of the mean velocity under that force (a warm start)."""
     rng = np.random.default_rng(seed)
     c = np.array([n / 2.0] * 3) + rng.random(3)
     nu = nu_of_tau(tau)
-    g, U = stokes_body_force(Re, nu, 2 * R, n ** 3, 4.0 / 3.0 * math.pi * R ** 3)
+    Vs = 4.0 / 3.0 * math.pi * R ** 3
+    force = array_body_force if drive == "array" else stokes_body_force
+    g, U = force(Re, nu, 2 * R, n ** 3, Vs)
+    U0 = periodic_array_velocity(g, nu, 2 * R, n ** 3, Vs)
     return Case(f"sphere_{n}", "D3Q19", "MRT", (n, n, n), tau, (g, 0.0, 0.0), [solid("sphere", c, R)],
-                method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U}, delta=delta)
+                method, steps, storage, retraction=retraction, meta={"Re": Re, "U_ref": U, "U_init": U0},
+                delta=delta)
 
 
 def settling_sphere(n=128, R=16.2, density=1.03, U_set=0.01, tau=0.8, seed=2, storage="F32", steps=5000,
@@ -234,8 +254,10 @@ def schiller_naumann(Re):
 
 
 def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, storage="F64", steps=10000,
-                method="QUADRATIC"):
-    """Random sequential addition of non-overlapping spheres (periodic gap >= gap)."""
+                method="QUADRATIC", drive="stokes"):
+    """Random sequential addition of non-overlapping spheres (periodic gap >= gap).  Body force as in
+    sphere_box (drive), each sphere taken with its share of the box; meta["U_init"]: the periodic-array
+    estimate of the mean velocity under it."""
     rng = np.random.default_rng(seed)
     cs = []
     dmin = 2 * R + gap
@@ -251,9 +273,15 @@ def sphere_pack(n=256, count=64, R=8.0, gap=2.0, Re=10.0, tau=0.8, seed=3, stora
         if ok:
             cs.append(c)
     nu = nu_of_tau(tau)
-    g, U = stokes_body_force(Re, nu, 2 * R, n ** 3, count * 4.0 / 3.0 * math.pi * R ** 3, n_spheres=count)
+    Vs = 4.0 / 3.0 * math.pi * R ** 3
+    if drive == "array":
+        g, U = array_body_force(Re, nu, 2 * R, n ** 3 / count, Vs)
+    else:
+        g, U = stokes_body_force(Re, nu, 2 * R, n ** 3, count * Vs, n_spheres=count)
+    U0 = periodic_array_velocity(g, nu, 2 * R, n ** 3 / count, Vs)
     return Case(f"pack_{n}_{count}", "D3Q19", "MRT", (n, n, n), tau, (g, 0.0, 0.0),
-                [solid("sphere", c, R) for c in cs], method, steps, storage, meta={"Re": Re, "U_ref": U})
+                [solid("sphere", c, R) for c in cs], method, steps, storage,
+                meta={"Re": Re, "U_ref": U, "U_init": U0})
 
 
 def moving_sphere_batch(count=512, seed=4, edge=(32, 96), radius=(4.0, 16.0), speed=(0.005, 0.02),
