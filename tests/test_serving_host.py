@@ -133,3 +133,20 @@ def test_check_outcome_of_a_running_request():
     assert S.outcome(float("inf"), 300, 1000, 1e-6, 1) is None  # zero to non-zero force: keep running
     st = S.stats([], 1.0)
     assert st["diverged"] == 0
+
+
+def test_array_body_force_inverts_the_periodic_array_estimate():
+    """The benchmark's body force for a target Re is the force under which the periodic-array
+    estimate (the serving warm start) gives U = Re nu / D; a lone sphere's Stokes force is smaller,
+    since the array factor K(c) and the inertia factor both exceed one."""
+    nu = W.nu_of_tau(0.8)
+    for Re, D, box, n in ((20.0, 32.4, 128 ** 3, 1), (10.0, 16.0, 256 ** 3, 64), (1.0, 12.0, 48 ** 3, 1)):
+        Vs = np.pi / 6.0 * D ** 3
+        g, U = W.array_body_force(Re, nu, D, box / n, Vs)
+        assert U == Re * nu / D
+        assert abs(W.periodic_array_velocity(g, nu, D, box / n, Vs) - U) <= 1e-12 * U
+        g_stokes, _ = W.stokes_body_force(Re, nu, D, box, n * Vs, n_spheres=n)
+        assert g > g_stokes
+    case = W.sphere_pack(drive="array")
+    assert abs(case.meta["U_init"] - case.meta["U_ref"]) <= 1e-12 * case.meta["U_ref"]
+    assert W.sphere_box().g[0] < W.sphere_box(drive="array").g[0]
